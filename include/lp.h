@@ -1,0 +1,183 @@
+/*
+ * lp.h -- C ABI of the MI355X local-parallel finite element library.
+ *
+ * The library advances the two-grid local parallel scheme for the transient
+ * triple-porosity / Navier-Stokes model (Algorithm 3 of Cao, Li, Chen, Du,
+ * "A Local Parallel Finite Element Method for Super-Hydrophobic Proppants in a
+ * Hydraulic Fracturing System Based on a 2D/3D Transient Triple-Porosity
+ * Navier-Stokes Model", Section 5) on one AMD Instinct MI355X (gfx950):
+ *
+ *   lp_setup        -> domain, nested meshes T_H / T_h, partition {D_j} -> {Omega_j}
+ *                      and parameters (Section 2, Section 4 setting, Algorithm 3 Step 2)
+ *   lp_coarse_step  -> Algorithm 3 Step 1: one decoupled backward-Euler step on T_H
+ *                      (three porous SPD solves + Navier-Stokes by Newton), FP64
+ *   lp_local_step   -> Algorithm 3 Steps 3-4: local fine corrections on every
+ *                      Omega_j (three porous solves, one Oseen solve) and the
+ *                      partition-of-unity correction of the fine solution
+ *   lp_get_solution -> copy one field out (merged fine, coarse, or one e_j)
+ *
+ * Conventions shared by every call
+ *   - 2D only in this version (dim = 2).  Porous region (0,1)^2 below the
+ *     conduit (0,1)x(1,2); interface Gamma at y = 1 (Example 1, Section 6).
+ *   - Each region is an N x N grid of square cells split into the triangles
+ *     {(i,j),(i+1,j),(i+1,j+1)} and {(i,j),(i+1,j+1),(i,j+1)}.  P2 nodes are
+ *     the half-step lattice (a,b), 0 <= a,b <= 2N, index a + (2N+1) b (the
+ *     conduit's vertical index counts up from Gamma); P1 nodes are the
+ *     vertices, index i + (N+1) j.
+ *   - Vectors crossing the ABI are FP64.  Velocity is component-blocked:
+ *     all u_x values, then all u_y values.
+ *   - Every device operation is ordered on the HIP stream passed in (a
+ *     hipStream_t cast to void*, NULL = default stream).  Only a copy to host
+ *     memory synchronises that stream.
+ *   - Errors: every call returns an lp_status; on failure lp_last_error()
+ *     returns a thread-local message.  No C++ exception crosses the ABI.
+ *   - Ownership: input structs and arrays are copied by lp_setup; the caller
+ *     may free them afterwards.  The context owns its device memory (taken
+ *     from the optional allocator, else hipMalloc) until lp_destroy.
+ */
+#ifndef LP_H
+#define LP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lp_ctx lp_ctx;
+
+typedef enum {
+    LP_OK = 0,
+    LP_ERR_ARG = 1,          /* invalid argument (sizes, partition, NULL pointer) */
+    LP_ERR_STATE = 2,        /* call out of order: setup -> (coarse_step -> local_step)* */
+    LP_ERR_ALLOC = 3,        /* device or host allocation failed */
+    LP_ERR_DEVICE = 4,       /* a HIP runtime call failed */
+    LP_ERR_NOCONV = 5,       /* a solve or refinement did not reach its tolerance;
+                                the best iterate is kept and stats.flags is set */
+    LP_ERR_UNSUPPORTED = 6   /* valid request this build does not implement */
+} lp_status;
+
+/* fields (the paper's u_c, p, p_F, p_f, p_m) */
+enum { LP_U = 0, LP_P = 1, LP_PF = 2, LP_PFMI = 3, LP_PM = 4 };
+/* levels of lp_get_solution */
+enum { LP_MERGED_FINE = 0, LP_COARSE = 1, LP_LOCAL = 2 };
+/* arithmetic of the local solves */
+enum { LP_FP64 = 0, LP_MIXED = 1 };
+/* manufactured problems */
+enum { LP_MMS_EX1_2D = 0 };
+
+/* Nested meshes (Section 4: T_h is a uniform refinement of T_H).
+ *   n_coarse = 1/H cells per unit length, refine = H/h (integer >= 1). */
+typedef struct {
+    int32_t dim;             /* 2 */
+    int32_t n_coarse;
+    int32_t refine;
+} lp_mesh;
+
+/* Partition of each region (Algorithm 3 Step 2).
+ *   nsub[0], nsub[1]: cores per region along x and y (both regions alike).
+ *   overlap: enlargement of each core D_j in fine cells; Omega_j is clipped
+ *            to its region and never crosses Gamma.
+ *   cuts: NULL for uniform cuts k*N/nsub, else 2*(nsub[0]+1) + 2*(nsub[1]+1)
+ *         integers in fine cells, in the order porous-x, porous-y, conduit-x,
+ *         conduit-y; each list starts at 0, ends at N and is increasing.
+ * Subdomain ids: porous first (x fastest, then y), then conduit. */
+typedef struct {
+    int32_t nsub[2];
+    int32_t overlap;
+    const int32_t *cuts;
+} lp_partition;
+
+/* Model parameters (Section 2) and the time step.  Index 0,1,2 = F, f, m. */
+typedef struct {
+    double phi[3], C[3], k[3];
+    double mu_tilde, sigma, sigma_star, rho, alpha, eta, nu;
+    double dt;
+} lp_params;
+
+typedef struct {
+    int32_t problem;         /* LP_MMS_EX1_2D */
+    int32_t precision;       /* LP_FP64 (FP64 factorisation and solves) or
+                                LP_MIXED (FP32 factorisation and solves, FP64
+                                residuals, iterative refinement) */
+    int32_t convection;      /* 1: Navier-Stokes (default); 0: Stokes (drops b_N) */
+    int32_t max_ir;          /* refinement sweeps cap (>= 1) */
+    double ir_tol;           /* stop when ||b - A x|| <= ir_tol ||b|| per system */
+    int32_t max_newton;      /* coarse Newton iterations cap */
+    double newton_tol;       /* stop when ||delta|| <= newton_tol ||x|| */
+} lp_options;
+
+/* Optional device allocator (e.g. a framework's caching allocator). */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *user);
+    void (*free)(void *ptr, void *user);
+    void *user;
+} lp_allocator;
+
+typedef struct {
+    int64_t step;            /* completed local steps */
+    int64_t n_porous, n_conduit;      /* subdomains */
+    int64_t local_dofs;      /* unknowns solved per local step (all systems) */
+    int64_t max_bw;          /* largest half-bandwidth of a local system */
+    int32_t newton_its;      /* Newton iterations of the last coarse step */
+    int32_t ir_sweeps;       /* refinement sweeps of the last local step (max over systems) */
+    double ir_relres;        /* largest final relative residual of the last local step */
+    int32_t flags;           /* bit 0: refinement did not converge; bit 1: Newton did not converge;
+                                bit 2: zero or non-finite pivot */
+    int32_t reserved;
+} lp_stats;
+
+/* Build meshes, partition, reference data and device buffers; interpolate the
+ * initial data (t = 0) on both grids and set e_j^0 = I_h x_0 - Pi_h x_H^0 on each
+ * Omega_j (zero on artificial faces); factor the constant local porous
+ * matrices.  Synchronises `stream` before returning.
+ * Errors: LP_ERR_ARG (dim != 2, n_coarse < 1, refine < 1, overlap < 0, bad cuts,
+ * non-positive dt or parameters), LP_ERR_ALLOC, LP_ERR_DEVICE. */
+lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_params *prm,
+                   const lp_options *opt, const lp_allocator *alloc, void *stream,
+                   lp_ctx **out);
+
+/* Algorithm 3 Step 1 for t_n -> t_{n+1} on T_H (FP64).  LP_ERR_STATE if the
+ * previous coarse step has not been followed by lp_local_step. */
+lp_status lp_coarse_step(lp_ctx *ctx, void *stream);
+
+/* Algorithm 3 Steps 3-4 for t_{n+1}: prolongation, local right-hand sides,
+ * local solves, merge, and e_j^n <- e_j^{n+1}.  LP_ERR_STATE unless a coarse
+ * step is pending. */
+lp_status lp_local_step(lp_ctx *ctx, void *stream);
+
+/* Length (in doubles) of a field at a level.  sub is the subdomain id for
+ * LP_LOCAL (its local lattice, Dirichlet nodes included), ignored otherwise. */
+lp_status lp_get_size(lp_ctx *ctx, int32_t field, int32_t level, int32_t sub, int64_t *len);
+
+/* Copy a field into `out` (len doubles; host memory, or device memory when
+ * out_is_device != 0).  A host copy synchronises `stream`. */
+lp_status lp_get_solution(lp_ctx *ctx, int32_t field, int32_t level, int32_t sub,
+                          double *out, int64_t len, int32_t out_is_device, void *stream);
+
+lp_status lp_get_stats(lp_ctx *ctx, lp_stats *out);
+
+/* Host-only partition queries (no device needed), for bit-exact index parity.
+ *   which = 0: subdomain table, 9 int64 per subdomain:
+ *              region, x0, x1, y0, y1 (Omega box), dx0, dx1, dy0, dy1 (core D)
+ *   which = 1: P2 node class of subdomain `sub`, local lattice order:
+ *              0 free, 1 physical Dirichlet, 2 artificial (zero)
+ *   which = 2: P1 vertex class of subdomain `sub` (0 free, 2 artificial)
+ *   which = 3: band-system unknown of each local P2 node of `sub`
+ *              (porous: scalar index; conduit: index of u_x, u_y follows), -1 if fixed
+ *   which = 4: band-system unknown of each local P1 vertex of conduit `sub`, -1 if fixed
+ *   which = 5: per subdomain: number of unknowns and half-bandwidth (2 int64 each)
+ * `needed` receives the required length; nothing is written if len is short. */
+lp_status lp_plan_query(const lp_mesh *mesh, const lp_partition *part, int32_t which,
+                        int32_t sub, int64_t *out, int64_t len, int64_t *needed);
+
+void lp_destroy(lp_ctx *ctx);
+
+const char *lp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LP_H */

@@ -1,0 +1,715 @@
+// C-ABI layer: context lifetime, device buffers, and the per-step launch
+// sequences of Algorithm 3 (Step 1 on T_H, Steps 3-4 on the subdomains).
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "lp_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+lp_status fail(lp_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIPCHK(expr)                                                                           \
+    do {                                                                                       \
+        hipError_t _e = (expr);                                                                \
+        if (_e != hipSuccess)                                                                  \
+            return fail(LP_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e));     \
+    } while (0)
+
+}  // namespace
+
+struct lp_ctx {
+    lp::Plan P;
+    lp::Coef co{};
+    lp::RefData ref{};
+    lp_params prm{};
+    lp_options opt{};
+    lp_allocator alloc{};
+    bool has_alloc = false;
+    std::vector<void *> owned;
+    int64_t n = 0;                 // completed local steps
+    bool coarse_pending = false;
+    int ccur = 0;                  // coarse buffers holding t_n
+    int ecur = 0;                  // correction buffers holding e^n
+    bool mixed = false;
+
+    // sizes
+    long long nf2 = 0, nf1 = 0, nc2 = 0, nc1 = 0;
+
+    // tables and descriptors
+    lp::SysDesc *d_por = nullptr, *d_ose = nullptr, *d_cpor = nullptr, *d_cns = nullptr;
+    int8_t *d_cls2 = nullptr, *d_cls1 = nullptr;
+    int32_t *d_dof2 = nullptr, *d_dof1 = nullptr;
+    lp::BandSys *d_lu_por = nullptr, *d_lu_ose = nullptr, *d_lu_cpor = nullptr, *d_lu_cns = nullptr;
+    lp::BandSys *d_sv_por = nullptr, *d_sv_ose = nullptr, *d_sv_cpor = nullptr, *d_sv_cns = nullptr;
+    int32_t *d_own[2][2][4] = {};  // [region][axis][own2_lo, own2_n, own1_lo, own1_n]
+
+    // manufactured data on both grids
+    double *ex_f[6] = {}, *ex_c[6] = {};
+    double *ld_f[5][3] = {}, *ld_c[5][3] = {};
+
+    // coarse states (two time levels)
+    double *cP[2] = {}, *cU[2] = {}, *cp[2] = {};
+    double *nwt_e = nullptr, *nwt_e1 = nullptr;
+    int *d_done = nullptr, *d_its = nullptr, *d_flags = nullptr;
+
+    // prolonged coarse fields on the fine lattices
+    double *pro_P1 = nullptr, *pro_P0 = nullptr, *pro_U1 = nullptr, *pro_U0 = nullptr, *pro_p1 = nullptr;
+
+    // local corrections (two time levels) and merged output
+    double *e2[2] = {}, *e1[2] = {};
+    double *m_P = nullptr, *m_U = nullptr, *m_p = nullptr;
+
+    // linear algebra storage
+    void *band_por = nullptr, *band_ose = nullptr;        // float (mixed) or double
+    double *band_cpor = nullptr, *band_cns = nullptr;
+    double *b_por = nullptr, *x_por = nullptr, *r_por = nullptr;
+    double *b_ose = nullptr, *x_ose = nullptr, *r_ose = nullptr;
+    void *y_por = nullptr, *y_ose = nullptr;
+    double *b_cp = nullptr, *x_cp = nullptr, *r_cp = nullptr, *y_cp = nullptr;
+    double *b_cn = nullptr, *x_cn = nullptr, *r_cn = nullptr, *y_cn = nullptr;
+    int *conv_por = nullptr, *conv_ose = nullptr, *conv_cp = nullptr, *conv_cn = nullptr;
+    double *rel_por = nullptr, *rel_ose = nullptr, *rel_cp = nullptr, *rel_cn = nullptr;
+    int *sw_por = nullptr, *sw_ose = nullptr, *sw_cp = nullptr, *sw_cn = nullptr;
+
+    int maxbw_por = 0, maxbw_ose = 0;
+
+    ~lp_ctx() {
+        for (void *p : owned) {
+            if (has_alloc) alloc.free(p, alloc.user);
+            else (void)hipFree(p);
+        }
+    }
+
+    template <typename T>
+    lp_status dalloc(T **p, long long count) {
+        size_t bytes = (size_t)(count > 0 ? count : 1) * sizeof(T);
+        void *q = nullptr;
+        if (has_alloc) q = alloc.alloc(bytes, alloc.user);
+        else if (hipMalloc(&q, bytes) != hipSuccess) q = nullptr;
+        if (!q) return fail(LP_ERR_ALLOC, "device allocation of " + std::to_string(bytes) + " bytes failed");
+        owned.push_back(q);
+        *p = (T *)q;
+        return LP_OK;
+    }
+
+    template <typename T>
+    lp_status upload(T **p, const std::vector<T> &v, hipStream_t st) {
+        lp_status s = dalloc(p, (long long)v.size());
+        if (s != LP_OK) return s;
+        if (!v.empty()) HIPCHK(hipMemcpyAsync(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+        return LP_OK;
+    }
+};
+
+namespace {
+
+#define TRY(expr)                        \
+    do {                                 \
+        lp_status _s = (expr);           \
+        if (_s != LP_OK) return _s;      \
+    } while (0)
+
+std::vector<lp::BandSys> lu_list(const std::vector<lp::SysDesc> &v, int nmat) {
+    std::vector<lp::BandSys> out;
+    for (const auto &s : v)
+        for (int f = 0; f < nmat; ++f) {
+            lp::BandSys b{};
+            b.off = s.band_off + (long long)f * s.band_size;
+            b.stride = s.band_size;
+            b.vec = s.dof_off + (long long)f * s.ndof;
+            b.n = s.ndof;
+            b.bw = s.bw;
+            b.nrhs = 1;
+            out.push_back(b);
+        }
+    return out;
+}
+
+std::vector<lp::BandSys> solve_list(const std::vector<lp::SysDesc> &v, int nrhs) {
+    std::vector<lp::BandSys> out;
+    for (const auto &s : v) {
+        lp::BandSys b{};
+        b.off = s.band_off;
+        b.stride = s.band_size;
+        b.vec = s.dof_off;
+        b.n = s.ndof;
+        b.bw = s.bw;
+        b.nrhs = nrhs;
+        out.push_back(b);
+    }
+    return out;
+}
+
+double time_at(const lp_ctx *c, int64_t step) { return (double)step * c->prm.dt; }
+
+// run `sweeps` refinement sweeps (solve, then FP64 residual) on one batch
+template <typename T>
+lp_status refine_porous(lp_ctx *c, const lp::SysDesc *d_sys, int nsys, const lp::BandSys *d_sv, T *band, int maxbw,
+                        double *b, double *x, double *r, T *y, int *conv, double *rel, int *sw, long long ndof,
+                        int sweeps, double tol, hipStream_t st) {
+    lp::IrStartArgs ia{x, r, b, ndof, conv, rel, sw, 3LL * nsys};
+    lp::launch_ir_start(ia, st);
+    for (int s = 0; s < sweeps; ++s) {
+        lp::SolveArgs<T> sa{d_sv, band, r, x, y, conv, 3, nullptr};
+        if (!lp::launch_band_solve<T>(sa, nsys, 3, maxbw, st)) return fail(LP_ERR_UNSUPPORTED, "bandwidth too large for the solve kernels");
+        lp::ResidualArgs ra{d_sys, c->d_dof2, x, b, r, conv, rel, sw, tol, nullptr};
+        lp::launch_porous_residual(ra, nsys, st);
+    }
+    return LP_OK;
+}
+
+template <typename T>
+lp_status refine_oseen(lp_ctx *c, const lp::SysDesc *d_sys, int nsys, const lp::BandSys *d_sv, T *band, int maxbw,
+                       const double *W1x, const double *W1y, double *b, double *x, double *r, T *y, int *conv,
+                       double *rel, int *sw, long long ndof, int sweeps, double tol, const int *skip, hipStream_t st) {
+    lp::IrStartArgs ia{x, r, b, ndof, conv, rel, sw, (long long)nsys};
+    lp::launch_ir_start(ia, st);
+    for (int s = 0; s < sweeps; ++s) {
+        lp::SolveArgs<T> sa{d_sv, band, r, x, y, conv, 1, skip};
+        if (!lp::launch_band_solve<T>(sa, nsys, 1, maxbw, st)) return fail(LP_ERR_UNSUPPORTED, "bandwidth too large for the solve kernels");
+        lp::OseenApplyArgs<double> ra{};
+        ra.sys = d_sys; ra.cls2 = c->d_cls2; ra.dof2 = c->d_dof2; ra.dof1 = c->d_dof1;
+        ra.W1[0] = W1x; ra.W1[1] = W1y;
+        ra.x = x; ra.b = b; ra.r = r; ra.band = nullptr;
+        ra.conv = conv; ra.relres = rel; ra.sweeps = sw; ra.tol = tol; ra.skip = skip;
+        lp::launch_oseen_residual(ra, nsys, st);
+    }
+    return LP_OK;
+}
+
+template <typename T>
+lp_status factor_porous(lp_ctx *c, T *band, hipStream_t st) {
+    lp::AssembleArgs<T> aa{c->d_por, c->d_dof2, band};
+    lp::launch_porous_assemble<T>(aa, (int)c->P.por.size(), st);
+    lp::BandArgs<T> ba{c->d_lu_por, band, c->d_flags, nullptr};
+    if (!lp::launch_band_lu<T>(ba, 3 * (int)c->P.por.size(), c->maxbw_por, st))
+        return fail(LP_ERR_UNSUPPORTED, "porous bandwidth exceeds the factorisation kernels");
+    return LP_OK;
+}
+
+template <typename T>
+lp_status local_oseen(lp_ctx *c, hipStream_t st) {
+    const int nsys = (int)c->P.ose.size();
+    const long long nf2 = c->nf2;
+    const int o = c->ecur, nw = 1 - c->ecur;
+    // right-hand sides of (5.8) and Dirichlet values of the new corrections
+    lp::OseenArgs oa{};
+    oa.sys = c->d_ose; oa.cls2 = c->d_cls2; oa.dof2 = c->d_dof2; oa.cls1 = c->d_cls1; oa.dof1 = c->d_dof1;
+    oa.W1[0] = c->pro_U1; oa.W1[1] = c->pro_U1 + nf2;
+    oa.W0[0] = c->pro_U0; oa.W0[1] = c->pro_U0 + nf2;
+    oa.Pp = c->pro_p1;
+    oa.ex[0] = c->ex_f[3]; oa.ex[1] = c->ex_f[4];
+    for (int cc = 0; cc < 2; ++cc) for (int k = 0; k < 3; ++k) oa.load[cc][k] = c->ld_f[3 + cc][k];
+    oa.PF0 = c->pro_P0;
+    oa.e_old = c->e2[o]; oa.e_new = c->e2[nw]; oa.e_new1 = c->e1[nw];
+    oa.b = c->b_ose;
+    const double t1 = time_at(c, c->n + 1);
+    oa.tf[0] = std::cos(t1); oa.tf[1] = std::sin(t1); oa.tf[2] = oa.tf[0] * oa.tf[0];
+    oa.skip = nullptr;
+    lp::launch_oseen_rhs(oa, nsys, st);
+    // operator linearised about Pi_h u_cH^{n+1}: assemble and factor
+    T *band = (T *)c->band_ose;
+    HIPCHK(hipMemsetAsync(band, 0, (size_t)c->P.band_total_ose * sizeof(T), st));
+    lp::OseenApplyArgs<T> aa{};
+    aa.sys = c->d_ose; aa.cls2 = c->d_cls2; aa.dof2 = c->d_dof2; aa.dof1 = c->d_dof1;
+    aa.W1[0] = oa.W1[0]; aa.W1[1] = oa.W1[1]; aa.band = band;
+    lp::launch_oseen_assemble<T>(aa, nsys, st);
+    lp::BandArgs<T> ba{c->d_lu_ose, band, c->d_flags, nullptr};
+    if (!lp::launch_band_lu<T>(ba, nsys, c->maxbw_ose, st))
+        return fail(LP_ERR_UNSUPPORTED, "conduit bandwidth exceeds the factorisation kernels");
+    TRY(refine_oseen<T>(c, c->d_ose, nsys, c->d_sv_ose, band, c->maxbw_ose, oa.W1[0], oa.W1[1], c->b_ose, c->x_ose,
+                        c->r_ose, (T *)c->y_ose, c->conv_ose, c->rel_ose, c->sw_ose, c->P.dof_total_ose, c->opt.max_ir,
+                        c->opt.ir_tol, nullptr, st));
+    lp::FinalizeArgs fa{c->d_ose, c->d_dof2, c->d_dof1, c->x_ose, c->e2[nw], c->e1[nw], nullptr};
+    lp::launch_oseen_finalize(fa, nsys, st);
+    return LP_OK;
+}
+
+template <typename T>
+lp_status local_porous(lp_ctx *c, hipStream_t st) {
+    const int nsys = (int)c->P.por.size();
+    const long long nf2 = c->nf2;
+    const int o = c->ecur, nw = 1 - c->ecur;
+    lp::PorousArgs pa{};
+    pa.sys = c->d_por; pa.cls2 = c->d_cls2; pa.dof2 = c->d_dof2;
+    for (int f = 0; f < 3; ++f) {
+        pa.P1[f] = c->pro_P1 + f * nf2;
+        pa.P0[f] = c->pro_P0 + f * nf2;
+        pa.ex[f] = c->ex_f[f];
+        pa.load[f][0] = c->ld_f[f][0];
+        pa.load[f][1] = c->ld_f[f][1];
+    }
+    pa.Uy0 = c->pro_U0 + nf2;
+    pa.e_old = c->e2[o]; pa.e_new = c->e2[nw]; pa.b = c->b_por;
+    const double t1 = time_at(c, c->n + 1);
+    pa.tf[0] = std::cos(t1); pa.tf[1] = std::sin(t1); pa.tf[2] = pa.tf[0] * pa.tf[0];
+    lp::launch_porous_rhs(pa, nsys, st);
+    TRY(refine_porous<T>(c, c->d_por, nsys, c->d_sv_por, (T *)c->band_por, c->maxbw_por, c->b_por, c->x_por, c->r_por,
+                         (T *)c->y_por, c->conv_por, c->rel_por, c->sw_por, c->P.dof_total_por, c->opt.max_ir,
+                         c->opt.ir_tol, st));
+    lp::FinalizeArgs fa{c->d_por, c->d_dof2, c->d_dof1, c->x_por, c->e2[nw], nullptr, nullptr};
+    lp::launch_porous_finalize(fa, nsys, st);
+    return LP_OK;
+}
+
+void prolong_all(lp_ctx *c, int cnew, int cold, hipStream_t st) {
+    const long long nc2 = c->nc2, nf2 = c->nf2;
+    lp::ProlongArgs pa{};
+    pa.NH = c->P.NH; pa.Nh = c->P.Nh; pa.k = c->P.k;
+    pa.nfields = 6;
+    for (int f = 0; f < 3; ++f) {
+        pa.src[f] = c->cP[cnew] + f * nc2;
+        pa.dst[f] = c->pro_P1 + f * nf2;
+        pa.src[3 + f] = c->cP[cold] + f * nc2;
+        pa.dst[3 + f] = c->pro_P0 + f * nf2;
+    }
+    lp::launch_prolong_p2(pa, st);
+    pa.nfields = 4;
+    for (int cc = 0; cc < 2; ++cc) {
+        pa.src[cc] = c->cU[cnew] + cc * nc2;
+        pa.dst[cc] = c->pro_U1 + cc * nf2;
+        pa.src[2 + cc] = c->cU[cold] + cc * nc2;
+        pa.dst[2 + cc] = c->pro_U0 + cc * nf2;
+    }
+    lp::launch_prolong_p2(pa, st);
+    pa.nfields = 1;
+    pa.src[0] = c->cp[cnew];
+    pa.dst[0] = c->pro_p1;
+    lp::launch_prolong_p1(pa, st);
+}
+
+bool params_ok(const lp_params &p, std::string &why) {
+    for (int i = 0; i < 3; ++i)
+        if (!(p.phi[i] > 0 && p.C[i] > 0 && p.k[i] > 0)) { why = "phi, C and k must be positive"; return false; }
+    if (!(p.mu_tilde > 0 && p.rho > 0 && p.eta > 0 && p.nu > 0 && p.dt > 0)) { why = "mu_tilde, rho, eta, nu, dt must be positive"; return false; }
+    if (!(p.sigma >= 0 && p.sigma_star >= 0 && p.alpha >= 0)) { why = "sigma, sigma_star, alpha must be non-negative"; return false; }
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lp_last_error(void) { return g_err.c_str(); }
+
+lp_status lp_plan_query(const lp_mesh *mesh, const lp_partition *part, int32_t which, int32_t sub, int64_t *out,
+                        int64_t len, int64_t *needed) {
+    if (!mesh || !part || !needed) return fail(LP_ERR_ARG, "NULL argument");
+    lp::Plan P;
+    std::string err;
+    if (!lp::build_plan(*mesh, *part, P, err)) return fail(LP_ERR_ARG, err);
+    const int nsub = (int)(P.por.size() + P.ose.size());
+    std::vector<int64_t> v;
+    auto sysof = [&](int s) -> const lp::SysDesc * {
+        if (s < 0 || s >= nsub) return nullptr;
+        return s < (int)P.por.size() ? &P.por[s] : &P.ose[s - P.por.size()];
+    };
+    if (which == 0) {
+        for (int s = 0; s < nsub; ++s) {
+            const lp::SysDesc &S = *sysof(s);
+            const auto &cx = P.cuts[S.region][0], &cy = P.cuts[S.region][1];
+            int loc = S.region == lp::POROUS ? s : s - (int)P.por.size();
+            int kx = loc % P.nsx, ky = loc / P.nsx;
+            int64_t row[9] = {S.region, S.x0, S.x0 + S.cx, S.y0, S.y0 + S.cy, cx[kx], cx[kx + 1], cy[ky], cy[ky + 1]};
+            v.insert(v.end(), row, row + 9);
+        }
+    } else if (which >= 1 && which <= 4) {
+        const lp::SysDesc *S = sysof(sub);
+        if (!S) return fail(LP_ERR_ARG, "subdomain id out of range");
+        if (which == 4 && S->kind != lp::KIND_OSEEN) return fail(LP_ERR_ARG, "which = 4 needs a conduit subdomain");
+        long long n2 = (long long)S->lw2 * S->lh2, n1 = (long long)S->lw1 * S->lh1;
+        if (which == 1) for (long long q = 0; q < n2; ++q) v.push_back(P.cls2[S->node_off + q]);
+        if (which == 2) for (long long q = 0; q < n1; ++q) v.push_back(P.cls1[S->vert_off + q]);
+        if (which == 3) for (long long q = 0; q < n2; ++q) v.push_back(P.dof2[S->node_off + q]);
+        if (which == 4) for (long long q = 0; q < n1; ++q) v.push_back(P.dof1[S->vert_off + q]);
+    } else if (which == 5) {
+        for (int s = 0; s < nsub; ++s) { v.push_back(sysof(s)->ndof); v.push_back(sysof(s)->bw); }
+    } else {
+        return fail(LP_ERR_ARG, "unknown query");
+    }
+    *needed = (int64_t)v.size();
+    if (out && len >= (int64_t)v.size()) std::memcpy(out, v.data(), v.size() * sizeof(int64_t));
+    return LP_OK;
+}
+
+lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_params *prm, const lp_options *opt,
+                   const lp_allocator *alloc, void *stream, lp_ctx **out) {
+    if (!mesh || !part || !prm || !opt || !out) return fail(LP_ERR_ARG, "NULL argument");
+    *out = nullptr;
+    std::string why;
+    if (!params_ok(*prm, why)) return fail(LP_ERR_ARG, why);
+    if (opt->problem != LP_MMS_EX1_2D) return fail(LP_ERR_UNSUPPORTED, "only the Example 1 manufactured problem is built in");
+    if (opt->precision != LP_FP64 && opt->precision != LP_MIXED) return fail(LP_ERR_ARG, "precision must be LP_FP64 or LP_MIXED");
+    if (opt->max_ir < 1 || opt->max_newton < 1 || !(opt->ir_tol > 0) || !(opt->newton_tol > 0))
+        return fail(LP_ERR_ARG, "max_ir, max_newton >= 1 and positive tolerances required");
+    hipStream_t st = (hipStream_t)stream;
+    std::unique_ptr<lp_ctx> c(new lp_ctx());
+    if (!lp::build_plan(*mesh, *part, c->P, why)) return fail(LP_ERR_ARG, why);
+    c->prm = *prm;
+    c->opt = *opt;
+    c->mixed = opt->precision == LP_MIXED;
+    if (alloc && alloc->alloc && alloc->free) { c->alloc = *alloc; c->has_alloc = true; }
+    lp::Plan &P = c->P;
+    for (const auto &s : P.por) c->maxbw_por = std::max(c->maxbw_por, s.bw);
+    for (const auto &s : P.ose) c->maxbw_ose = std::max(c->maxbw_ose, s.bw);
+    if (std::max(c->maxbw_por, c->maxbw_ose) >= 160 || std::max(P.cpor.bw, P.cns.bw) >= 160)
+        return fail(LP_ERR_UNSUPPORTED, "local half-bandwidth " + std::to_string(std::max(c->maxbw_por, c->maxbw_ose)) +
+                                            " exceeds the 159 supported by the band kernels");
+    // coefficients (Section 3.1 / Algorithm 3)
+    lp::Coef &co = c->co;
+    for (int i = 0; i < 3; ++i) { co.tau[i] = prm->phi[i] * prm->C[i] / prm->dt; co.kap[i] = prm->k[i] / prm->mu_tilde; }
+    co.sst = prm->sigma_star * prm->k[1] / prm->mu_tilde;
+    co.s = prm->sigma * prm->k[2] / prm->mu_tilde;
+    co.eta = prm->eta; co.nu = prm->nu; co.rho = prm->rho; co.dt = prm->dt;
+    co.beta = prm->alpha * prm->nu / std::sqrt(prm->k[0]);
+    co.ctau = prm->eta * prm->nu * prm->alpha * std::sqrt(prm->k[0]) / prm->mu_tilde;
+    co.convection = opt->convection ? 1 : 0;
+    lp::build_refdata(c->ref);
+    HIPCHK(lp::upload_constants(c->ref, co, st));
+
+    c->nf2 = (long long)(2 * P.Nh + 1) * (2 * P.Nh + 1);
+    c->nf1 = (long long)(P.Nh + 1) * (P.Nh + 1);
+    c->nc2 = (long long)(2 * P.NH + 1) * (2 * P.NH + 1);
+    c->nc1 = (long long)(P.NH + 1) * (P.NH + 1);
+    // tables
+    std::vector<lp::SysDesc> cp{P.cpor}, cn{P.cns};
+    TRY(c->upload(&c->d_por, P.por, st));
+    TRY(c->upload(&c->d_ose, P.ose, st));
+    TRY(c->upload(&c->d_cpor, cp, st));
+    TRY(c->upload(&c->d_cns, cn, st));
+    TRY(c->upload(&c->d_cls2, P.cls2, st));
+    TRY(c->upload(&c->d_dof2, P.dof2, st));
+    TRY(c->upload(&c->d_cls1, P.cls1, st));
+    TRY(c->upload(&c->d_dof1, P.dof1, st));
+    TRY(c->upload(&c->d_lu_por, lu_list(P.por, 3), st));
+    TRY(c->upload(&c->d_lu_ose, lu_list(P.ose, 1), st));
+    TRY(c->upload(&c->d_lu_cpor, lu_list(cp, 3), st));
+    TRY(c->upload(&c->d_lu_cns, lu_list(cn, 1), st));
+    TRY(c->upload(&c->d_sv_por, solve_list(P.por, 3), st));
+    TRY(c->upload(&c->d_sv_ose, solve_list(P.ose, 1), st));
+    TRY(c->upload(&c->d_sv_cpor, solve_list(cp, 3), st));
+    TRY(c->upload(&c->d_sv_cns, solve_list(cn, 1), st));
+    for (int r = 0; r < 2; ++r)
+        for (int ax = 0; ax < 2; ++ax) {
+            TRY(c->upload(&c->d_own[r][ax][0], P.own2_lo[r][ax], st));
+            TRY(c->upload(&c->d_own[r][ax][1], P.own2_n[r][ax], st));
+            TRY(c->upload(&c->d_own[r][ax][2], P.own1_lo[r][ax], st));
+            TRY(c->upload(&c->d_own[r][ax][3], P.own1_n[r][ax], st));
+        }
+    // manufactured data
+    {
+        std::vector<double> exf[6], exc[6], lf[5][3], lc[5][3];
+        lp::exact_spatial(P.Nh, exf);
+        lp::exact_spatial(P.NH, exc);
+        lp::source_loads(P.Nh, *prm, lf);
+        lp::source_loads(P.NH, *prm, lc);
+        for (int f = 0; f < 6; ++f) { TRY(c->upload(&c->ex_f[f], exf[f], st)); TRY(c->upload(&c->ex_c[f], exc[f], st)); }
+        for (int f = 0; f < 5; ++f)
+            for (int k = 0; k < 3; ++k) { TRY(c->upload(&c->ld_f[f][k], lf[f][k], st)); TRY(c->upload(&c->ld_c[f][k], lc[f][k], st)); }
+        // coarse initial data: nodal interpolants at t = 0 (cos 0 = 1)
+        std::vector<double> P0(3 * c->nc2), U0(2 * c->nc2);
+        for (int f = 0; f < 3; ++f) std::copy(exc[f].begin(), exc[f].end(), P0.begin() + f * c->nc2);
+        for (int cc = 0; cc < 2; ++cc) std::copy(exc[3 + cc].begin(), exc[3 + cc].end(), U0.begin() + cc * c->nc2);
+        for (int l = 0; l < 2; ++l) {
+            TRY(c->upload(&c->cP[l], P0, st));
+            TRY(c->upload(&c->cU[l], U0, st));
+            TRY(c->upload(&c->cp[l], exc[5], st));
+        }
+    }
+    TRY(c->dalloc(&c->nwt_e, 2 * c->nc2));
+    TRY(c->dalloc(&c->nwt_e1, c->nc1));
+    TRY(c->dalloc(&c->d_done, 4));
+    TRY(c->dalloc(&c->d_its, 4));
+    TRY(c->dalloc(&c->d_flags, 4));
+    HIPCHK(hipMemsetAsync(c->d_flags, 0, 4 * sizeof(int), st));
+    HIPCHK(hipMemsetAsync(c->d_its, 0, 4 * sizeof(int), st));
+    TRY(c->dalloc(&c->pro_P1, 3 * c->nf2));
+    TRY(c->dalloc(&c->pro_P0, 3 * c->nf2));
+    TRY(c->dalloc(&c->pro_U1, 2 * c->nf2));
+    TRY(c->dalloc(&c->pro_U0, 2 * c->nf2));
+    TRY(c->dalloc(&c->pro_p1, c->nf1));
+    for (int l = 0; l < 2; ++l) { TRY(c->dalloc(&c->e2[l], P.e2_total)); TRY(c->dalloc(&c->e1[l], P.e1_total)); }
+    TRY(c->dalloc(&c->m_P, 3 * c->nf2));
+    TRY(c->dalloc(&c->m_U, 2 * c->nf2));
+    TRY(c->dalloc(&c->m_p, c->nf1));
+    const size_t tb = c->mixed ? sizeof(float) : sizeof(double);
+    {
+        void *p;
+        if (c->has_alloc) { p = c->alloc.alloc(P.band_total_por * tb + 256, c->alloc.user); }
+        else if (hipMalloc(&p, P.band_total_por * tb + 256) != hipSuccess) p = nullptr;
+        if (!p) return fail(LP_ERR_ALLOC, "porous band allocation failed");
+        c->owned.push_back(p); c->band_por = p;
+        if (c->has_alloc) { p = c->alloc.alloc(P.band_total_ose * tb + 256, c->alloc.user); }
+        else if (hipMalloc(&p, P.band_total_ose * tb + 256) != hipSuccess) p = nullptr;
+        if (!p) return fail(LP_ERR_ALLOC, "conduit band allocation failed");
+        c->owned.push_back(p); c->band_ose = p;
+        if (c->has_alloc) { p = c->alloc.alloc(P.dof_total_por * tb + 256, c->alloc.user); }
+        else if (hipMalloc(&p, P.dof_total_por * tb + 256) != hipSuccess) p = nullptr;
+        if (!p) return fail(LP_ERR_ALLOC, "scratch allocation failed");
+        c->owned.push_back(p); c->y_por = p;
+        if (c->has_alloc) { p = c->alloc.alloc(P.dof_total_ose * tb + 256, c->alloc.user); }
+        else if (hipMalloc(&p, P.dof_total_ose * tb + 256) != hipSuccess) p = nullptr;
+        if (!p) return fail(LP_ERR_ALLOC, "scratch allocation failed");
+        c->owned.push_back(p); c->y_ose = p;
+    }
+    TRY(c->dalloc(&c->band_cpor, P.cband_por));
+    TRY(c->dalloc(&c->band_cns, P.cband_ns));
+    TRY(c->dalloc(&c->b_por, P.dof_total_por)); TRY(c->dalloc(&c->x_por, P.dof_total_por)); TRY(c->dalloc(&c->r_por, P.dof_total_por));
+    TRY(c->dalloc(&c->b_ose, P.dof_total_ose)); TRY(c->dalloc(&c->x_ose, P.dof_total_ose)); TRY(c->dalloc(&c->r_ose, P.dof_total_ose));
+    const long long ncp = 3LL * P.cpor.ndof, ncn = P.cns.ndof;
+    TRY(c->dalloc(&c->b_cp, ncp)); TRY(c->dalloc(&c->x_cp, ncp)); TRY(c->dalloc(&c->r_cp, ncp)); TRY(c->dalloc(&c->y_cp, ncp));
+    TRY(c->dalloc(&c->b_cn, ncn)); TRY(c->dalloc(&c->x_cn, ncn)); TRY(c->dalloc(&c->r_cn, ncn)); TRY(c->dalloc(&c->y_cn, ncn));
+    const long long npf = 3LL * P.por.size(), nof = (long long)P.ose.size();
+    TRY(c->dalloc(&c->conv_por, npf)); TRY(c->dalloc(&c->rel_por, npf)); TRY(c->dalloc(&c->sw_por, npf));
+    TRY(c->dalloc(&c->conv_ose, nof)); TRY(c->dalloc(&c->rel_ose, nof)); TRY(c->dalloc(&c->sw_ose, nof));
+    TRY(c->dalloc(&c->conv_cp, 3)); TRY(c->dalloc(&c->rel_cp, 3)); TRY(c->dalloc(&c->sw_cp, 3));
+    TRY(c->dalloc(&c->conv_cn, 1)); TRY(c->dalloc(&c->rel_cn, 1)); TRY(c->dalloc(&c->sw_cn, 1));
+    HIPCHK(hipMemsetAsync(c->sw_ose, 0, nof * sizeof(int), st));
+    HIPCHK(hipMemsetAsync(c->sw_por, 0, npf * sizeof(int), st));
+    HIPCHK(hipMemsetAsync(c->rel_ose, 0, nof * sizeof(double), st));
+    HIPCHK(hipMemsetAsync(c->rel_por, 0, npf * sizeof(double), st));
+
+    // initial corrections e_j^0 = I_h x_0 - Pi_h x_H^0
+    c->ccur = 0;
+    c->ecur = 0;
+    prolong_all(c.get(), 0, 0, st);
+    {
+        lp::InitArgs ia{};
+        ia.sys = c->d_por; ia.cls2 = c->d_cls2;
+        for (int f = 0; f < 3; ++f) { ia.ex[f] = c->ex_f[f]; ia.pro[f] = c->pro_P1 + f * c->nf2; }
+        ia.e = c->e2[0]; ia.e1 = c->e1[0];
+        lp::launch_init_corrections(ia, (int)P.por.size(), st);
+        ia.sys = c->d_ose;
+        ia.ex[0] = c->ex_f[3]; ia.ex[1] = c->ex_f[4];
+        ia.pro[0] = c->pro_U1; ia.pro[1] = c->pro_U1 + c->nf2;
+        lp::launch_init_corrections(ia, (int)P.ose.size(), st);
+    }
+    // constant porous matrices: local (precision of the run) and coarse (FP64)
+    if (c->mixed) {
+        HIPCHK(hipMemsetAsync(c->band_por, 0, P.band_total_por * sizeof(float), st));
+        TRY(factor_porous<float>(c.get(), (float *)c->band_por, st));
+    } else {
+        HIPCHK(hipMemsetAsync(c->band_por, 0, P.band_total_por * sizeof(double), st));
+        TRY(factor_porous<double>(c.get(), (double *)c->band_por, st));
+    }
+    HIPCHK(hipMemsetAsync(c->band_cpor, 0, P.cband_por * sizeof(double), st));
+    {
+        lp::AssembleArgs<double> aa{c->d_cpor, c->d_dof2, c->band_cpor};
+        lp::launch_porous_assemble<double>(aa, 1, st);
+        lp::BandArgs<double> ba{c->d_lu_cpor, c->band_cpor, c->d_flags, nullptr};
+        if (!lp::launch_band_lu<double>(ba, 3, P.cpor.bw, st)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    int flags = 0;
+    HIPCHK(hipMemcpy(&flags, c->d_flags, sizeof(int), hipMemcpyDeviceToHost));
+    if (flags & 4) return fail(LP_ERR_NOCONV, "zero or non-finite pivot while factoring the porous matrices");
+    *out = c.release();
+    return LP_OK;
+}
+
+lp_status lp_coarse_step(lp_ctx *c, void *stream) {
+    if (!c) return fail(LP_ERR_ARG, "NULL context");
+    if (c->coarse_pending) return fail(LP_ERR_STATE, "lp_local_step must follow the previous lp_coarse_step");
+    hipStream_t st = (hipStream_t)stream;
+    const lp::Plan &P = c->P;
+    const int o = c->ccur, nw = 1 - c->ccur;
+    const long long nc2 = c->nc2;
+    const double t1 = time_at(c, c->n + 1);
+    const double tf[3] = {std::cos(t1), std::sin(t1), std::cos(t1) * std::cos(t1)};
+    // (5.1)-(5.3): three SPD solves with lagged exchange and lagged u^n on Gamma
+    lp::PorousArgs pa{};
+    pa.sys = c->d_cpor; pa.cls2 = c->d_cls2; pa.dof2 = c->d_dof2;
+    for (int f = 0; f < 3; ++f) {
+        pa.P1[f] = nullptr; pa.P0[f] = nullptr;
+        pa.ex[f] = c->ex_c[f];
+        pa.load[f][0] = c->ld_c[f][0];
+        pa.load[f][1] = c->ld_c[f][1];
+    }
+    pa.Uy0 = c->cU[o] + nc2;
+    pa.e_old = c->cP[o]; pa.e_new = c->cP[nw]; pa.b = c->b_cp;
+    for (int k = 0; k < 3; ++k) pa.tf[k] = tf[k];
+    lp::launch_porous_rhs(pa, 1, st);
+    TRY(refine_porous<double>(c, c->d_cpor, 1, c->d_sv_cpor, c->band_cpor, P.cpor.bw, c->b_cp, c->x_cp, c->r_cp, c->y_cp,
+                              c->conv_cp, c->rel_cp, c->sw_cp, 3LL * P.cpor.ndof, 2, 1e-13, st));
+    lp::FinalizeArgs fa{c->d_cpor, c->d_dof2, c->d_dof1, c->x_cp, c->cP[nw], nullptr, nullptr};
+    lp::launch_porous_finalize(fa, 1, st);
+    // (5.4): Navier-Stokes by Newton from (u^n, p^n); each iteration solves the
+    // Oseen system linearised about the current iterate
+    HIPCHK(hipMemcpyAsync(c->cU[nw], c->cU[o], 2 * nc2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(c->cp[nw], c->cp[o], c->nc1 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemsetAsync(c->d_done, 0, sizeof(int), st));
+    HIPCHK(hipMemsetAsync(c->d_its, 0, sizeof(int), st));
+    for (int it = 0; it < c->opt.max_newton; ++it) {
+        lp::OseenArgs oa{};
+        oa.sys = c->d_cns; oa.cls2 = c->d_cls2; oa.dof2 = c->d_dof2; oa.cls1 = c->d_cls1; oa.dof1 = c->d_dof1;
+        oa.W1[0] = c->cU[nw]; oa.W1[1] = c->cU[nw] + nc2;
+        oa.W0[0] = c->cU[o]; oa.W0[1] = c->cU[o] + nc2;
+        oa.Pp = c->cp[nw];
+        oa.ex[0] = c->ex_c[3]; oa.ex[1] = c->ex_c[4];
+        for (int cc = 0; cc < 2; ++cc) for (int k = 0; k < 3; ++k) oa.load[cc][k] = c->ld_c[3 + cc][k];
+        oa.PF0 = c->cP[o];
+        oa.e_old = nullptr; oa.e_new = c->nwt_e; oa.e_new1 = c->nwt_e1;
+        oa.b = c->b_cn;
+        for (int k = 0; k < 3; ++k) oa.tf[k] = tf[k];
+        oa.skip = c->d_done;
+        lp::launch_oseen_rhs(oa, 1, st);
+        HIPCHK(hipMemsetAsync(c->band_cns, 0, P.cband_ns * sizeof(double), st));
+        lp::OseenApplyArgs<double> aa{};
+        aa.sys = c->d_cns; aa.cls2 = c->d_cls2; aa.dof2 = c->d_dof2; aa.dof1 = c->d_dof1;
+        aa.W1[0] = oa.W1[0]; aa.W1[1] = oa.W1[1]; aa.band = c->band_cns; aa.skip = c->d_done;
+        lp::launch_oseen_assemble<double>(aa, 1, st);
+        lp::BandArgs<double> ba{c->d_lu_cns, c->band_cns, c->d_flags, c->d_done};
+        if (!lp::launch_band_lu<double>(ba, 1, P.cns.bw, st)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
+        TRY(refine_oseen<double>(c, c->d_cns, 1, c->d_sv_cns, c->band_cns, P.cns.bw, oa.W1[0], oa.W1[1], c->b_cn, c->x_cn,
+                                 c->r_cn, c->y_cn, c->conv_cn, c->rel_cn, c->sw_cn, P.cns.ndof, 2, 1e-14, c->d_done, st));
+        lp::FinalizeArgs fn{c->d_cns, c->d_dof2, c->d_dof1, c->x_cn, c->nwt_e, c->nwt_e1, c->d_done};
+        lp::launch_oseen_finalize(fn, 1, st);
+        lp::NewtonArgs na{c->cU[nw], c->cp[nw], c->nwt_e, c->nwt_e1, nc2, c->nc1, c->d_done, c->d_its, c->opt.newton_tol};
+        lp::launch_newton_update(na, st);
+    }
+    HIPCHK(hipGetLastError());
+    c->coarse_pending = true;
+    return LP_OK;
+}
+
+lp_status lp_local_step(lp_ctx *c, void *stream) {
+    if (!c) return fail(LP_ERR_ARG, "NULL context");
+    if (!c->coarse_pending) return fail(LP_ERR_STATE, "lp_local_step needs a preceding lp_coarse_step");
+    hipStream_t st = (hipStream_t)stream;
+    const int o = c->ccur, nw = 1 - c->ccur;
+    prolong_all(c, nw, o, st);
+    if (c->mixed) { TRY(local_porous<float>(c, st)); TRY(local_oseen<float>(c, st)); }
+    else { TRY(local_porous<double>(c, st)); TRY(local_oseen<double>(c, st)); }
+    const int en = 1 - c->ecur;
+    for (int r = 0; r < 2; ++r) {
+        lp::MergeArgs ma{};
+        ma.sys = r == lp::POROUS ? c->d_por : c->d_ose;
+        ma.nsx = c->P.nsx; ma.N = c->P.Nh; ma.region = r;
+        for (int ax = 0; ax < 2; ++ax) {
+            ma.own2_lo[ax] = c->d_own[r][ax][0]; ma.own2_n[ax] = c->d_own[r][ax][1];
+            ma.own1_lo[ax] = c->d_own[r][ax][2]; ma.own1_n[ax] = c->d_own[r][ax][3];
+        }
+        if (r == lp::POROUS) {
+            for (int f = 0; f < 3; ++f) { ma.base[f] = c->pro_P1 + f * c->nf2; ma.out[f] = c->m_P + f * c->nf2; }
+            ma.base1 = nullptr; ma.out1 = nullptr;
+        } else {
+            for (int f = 0; f < 2; ++f) { ma.base[f] = c->pro_U1 + f * c->nf2; ma.out[f] = c->m_U + f * c->nf2; }
+            ma.base1 = c->pro_p1; ma.out1 = c->m_p;
+        }
+        ma.e2 = c->e2[en]; ma.e1 = c->e1[en];
+        lp::launch_merge(ma, st);
+    }
+    HIPCHK(hipGetLastError());
+    c->ecur = en;
+    c->ccur = nw;
+    c->n += 1;
+    c->coarse_pending = false;
+    return LP_OK;
+}
+
+static lp_status locate(lp_ctx *c, int32_t field, int32_t level, int32_t sub, const double **ptr, int64_t *len) {
+    if (field < LP_U || field > LP_PM) return fail(LP_ERR_ARG, "unknown field");
+    const int latest = c->coarse_pending ? 1 - c->ccur : c->ccur;
+    if (level == LP_MERGED_FINE) {
+        if (field == LP_U) { *ptr = c->m_U; *len = 2 * c->nf2; }
+        else if (field == LP_P) { *ptr = c->m_p; *len = c->nf1; }
+        else { *ptr = c->m_P + (field - LP_PF) * c->nf2; *len = c->nf2; }
+    } else if (level == LP_COARSE) {
+        if (field == LP_U) { *ptr = c->cU[latest]; *len = 2 * c->nc2; }
+        else if (field == LP_P) { *ptr = c->cp[latest]; *len = c->nc1; }
+        else { *ptr = c->cP[latest] + (field - LP_PF) * c->nc2; *len = c->nc2; }
+    } else if (level == LP_LOCAL) {
+        const int np = (int)c->P.por.size(), nsub = np + (int)c->P.ose.size();
+        if (sub < 0 || sub >= nsub) return fail(LP_ERR_ARG, "subdomain id out of range");
+        const lp::SysDesc &S = sub < np ? c->P.por[sub] : c->P.ose[sub - np];
+        const long long nl = (long long)S.lw2 * S.lh2;
+        const double *e2 = c->e2[c->ecur], *e1 = c->e1[c->ecur];
+        if (S.region == lp::POROUS) {
+            if (field == LP_U || field == LP_P) return fail(LP_ERR_ARG, "porous subdomains carry p_F, p_f, p_m");
+            *ptr = e2 + S.e2_off + (field - LP_PF) * nl; *len = nl;
+        } else {
+            if (field == LP_U) { *ptr = e2 + S.e2_off; *len = 2 * nl; }
+            else if (field == LP_P) { *ptr = e1 + S.e1_off; *len = (long long)S.lw1 * S.lh1; }
+            else return fail(LP_ERR_ARG, "conduit subdomains carry u and p");
+        }
+    } else {
+        return fail(LP_ERR_ARG, "unknown level");
+    }
+    return LP_OK;
+}
+
+lp_status lp_get_size(lp_ctx *c, int32_t field, int32_t level, int32_t sub, int64_t *len) {
+    if (!c || !len) return fail(LP_ERR_ARG, "NULL argument");
+    const double *p;
+    return locate(c, field, level, sub, &p, len);
+}
+
+lp_status lp_get_solution(lp_ctx *c, int32_t field, int32_t level, int32_t sub, double *out, int64_t len,
+                          int32_t out_is_device, void *stream) {
+    if (!c || !out) return fail(LP_ERR_ARG, "NULL argument");
+    const double *p;
+    int64_t n;
+    TRY(locate(c, field, level, sub, &p, &n));
+    if (len < n) return fail(LP_ERR_ARG, "output buffer too short: need " + std::to_string(n));
+    hipStream_t st = (hipStream_t)stream;
+    if (out_is_device) {
+        HIPCHK(hipMemcpyAsync(out, p, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    } else {
+        HIPCHK(hipMemcpyAsync(out, p, n * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    return LP_OK;
+}
+
+lp_status lp_get_stats(lp_ctx *c, lp_stats *out) {
+    if (!c || !out) return fail(LP_ERR_ARG, "NULL argument");
+    HIPCHK(hipDeviceSynchronize());
+    std::memset(out, 0, sizeof(*out));
+    out->step = c->n;
+    out->n_porous = (int64_t)c->P.por.size();
+    out->n_conduit = (int64_t)c->P.ose.size();
+    out->local_dofs = c->P.local_dofs;
+    out->max_bw = c->P.max_bw;
+    int its = 0, done = 0, flags = 0;
+    HIPCHK(hipMemcpy(&its, c->d_its, sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&done, c->d_done, sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&flags, c->d_flags, sizeof(int), hipMemcpyDeviceToHost));
+    out->newton_its = its;
+    out->flags = flags & 4;
+    if (c->n > 0 && !done) out->flags |= 2;
+    std::vector<int> sw(3 * c->P.por.size() + c->P.ose.size()), cv(sw.size());
+    std::vector<double> rel(sw.size());
+    const size_t np = 3 * c->P.por.size(), no = c->P.ose.size();
+    HIPCHK(hipMemcpy(sw.data(), c->sw_por, np * sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(sw.data() + np, c->sw_ose, no * sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(rel.data(), c->rel_por, np * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(rel.data() + np, c->rel_ose, no * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(cv.data(), c->conv_por, np * sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(cv.data() + np, c->conv_ose, no * sizeof(int), hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < sw.size(); ++i) {
+        out->ir_sweeps = std::max(out->ir_sweeps, sw[i]);
+        out->ir_relres = std::max(out->ir_relres, rel[i]);
+        if (c->n > 0 && !cv[i]) out->flags |= 1;
+    }
+    return LP_OK;
+}
+
+void lp_destroy(lp_ctx *c) {
+    if (!c) return;
+    (void)hipDeviceSynchronize();
+    delete c;
+}
+
+}  // extern "C"

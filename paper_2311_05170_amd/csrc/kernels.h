@@ -1,0 +1,190 @@
+// Kernel argument blocks and launch wrappers (see kernels.hip).
+#pragma once
+
+#include "lp_internal.h"
+
+namespace lp {
+
+struct ProlongArgs {
+    const double *src[6];
+    double *dst[6];
+    int nfields;
+    int NH, Nh, k;
+};
+
+struct PorousArgs {
+    const SysDesc *sys;
+    const int8_t *cls2;
+    const int32_t *dof2;
+    const double *P1[3];          // background at t_{n+1} on the grid lattice (NULL = 0)
+    const double *P0[3];          // background at t_n (NULL = 0)
+    const double *ex[3];          // spatial parts of the exact p_F, p_f, p_m
+    const double *load[3][2];     // source loads (cos t, sin t parts)
+    const double *Uy0;            // conduit u_y at t_n on the same grid (Gamma flux), NULL = none
+    const double *e_old;          // previous corrections (local lattices)
+    double *e_new;
+    double *b;
+    double tf[3];                 // cos t_{n+1}, sin t_{n+1}, cos^2 t_{n+1}
+};
+
+struct ResidualArgs {
+    const SysDesc *sys;
+    const int32_t *dof2;
+    const double *x;
+    const double *b;
+    double *r;
+    int *conv;
+    double *relres;
+    int *sweeps;
+    double tol;
+    const int *skip;
+};
+
+struct FinalizeArgs {
+    const SysDesc *sys;
+    const int32_t *dof2;
+    const int32_t *dof1;
+    const double *x;
+    double *e_new;
+    double *e_new1;
+    const int *skip;
+};
+
+template <typename T>
+struct AssembleArgs {
+    const SysDesc *sys;
+    const int32_t *dof2;
+    T *band;
+};
+
+struct OseenArgs {
+    const SysDesc *sys;
+    const int8_t *cls2;
+    const int32_t *dof2;
+    const int8_t *cls1;
+    const int32_t *dof1;
+    const double *W1[2];          // velocity background at t_{n+1} (Newton iterate on T_H)
+    const double *W0[2];          // velocity background at t_n (NULL = 0)
+    const double *Pp;             // pressure background at t_{n+1} (P1 lattice)
+    const double *ex[2];          // spatial parts of the exact u
+    const double *load[2][3];     // source loads (cos, sin, cos^2 parts)
+    const double *PF0;            // porous p_F at t_n (Gamma terms)
+    const double *e_old;          // previous velocity corrections (NULL = 0)
+    double *e_new;
+    double *e_new1;
+    double *b;
+    double tf[3];
+    const int *skip;
+};
+
+template <typename T>
+struct OseenApplyArgs {
+    const SysDesc *sys;
+    const int8_t *cls2;
+    const int32_t *dof2;
+    const int32_t *dof1;
+    const double *W1[2];
+    const double *x;
+    const double *b;
+    double *r;
+    T *band;
+    int *conv;
+    double *relres;
+    int *sweeps;
+    double tol;
+    const int *skip;
+};
+
+struct BandSys {
+    long long off;                // band offset of the first matrix
+    long long stride;             // distance between the matrices of one system
+    long long vec;                // vector offset of the first right-hand side
+    int n, bw, nrhs, pad;
+};
+
+template <typename T>
+struct BandArgs {
+    const BandSys *sys;
+    T *band;
+    int *flags;
+    const int *skip;
+};
+
+template <typename T>
+struct SolveArgs {
+    const BandSys *sys;
+    const T *band;
+    const double *r;
+    double *x;
+    T *y;
+    const int *conv;
+    int rhs_per_sys;
+    const int *skip;
+};
+
+struct MergeArgs {
+    const SysDesc *sys;           // the region's subdomains (x fastest)
+    int nsx, N, region;
+    const int32_t *own2_lo[2], *own2_n[2], *own1_lo[2], *own1_n[2];
+    const double *base[3];
+    const double *base1;
+    const double *e2;
+    const double *e1;
+    double *out[3];
+    double *out1;
+};
+
+struct InitArgs {
+    const SysDesc *sys;
+    const int8_t *cls2;
+    const double *ex[3];
+    const double *pro[3];
+    double *e;
+    double *e1;
+};
+
+struct NewtonArgs {
+    double *U;
+    double *P;
+    const double *e;
+    const double *e1;
+    long long nu, np;
+    int *done;
+    int *its;
+    double tol;
+};
+
+struct IrStartArgs {
+    double *x;
+    double *r;
+    const double *b;
+    long long n;
+    int *conv;
+    double *relres;
+    int *sweeps;
+    long long nflags;
+};
+
+hipError_t upload_constants(const RefData &r, const Coef &c, hipStream_t st);
+void launch_prolong_p2(const ProlongArgs &a, hipStream_t st);
+void launch_prolong_p1(const ProlongArgs &a, hipStream_t st);
+void launch_porous_rhs(const PorousArgs &a, int nsys, hipStream_t st);
+void launch_porous_residual(const ResidualArgs &a, int nsys, hipStream_t st);
+void launch_porous_finalize(const FinalizeArgs &a, int nsys, hipStream_t st);
+template <typename T>
+void launch_porous_assemble(const AssembleArgs<T> &a, int nsys, hipStream_t st);
+void launch_oseen_rhs(const OseenArgs &a, int nsys, hipStream_t st);
+template <typename T>
+void launch_oseen_assemble(const OseenApplyArgs<T> &a, int nsys, hipStream_t st);
+void launch_oseen_residual(const OseenApplyArgs<double> &a, int nsys, hipStream_t st);
+void launch_oseen_finalize(const FinalizeArgs &a, int nsys, hipStream_t st);
+template <typename T>
+bool launch_band_lu(const BandArgs<T> &a, int nsys, int maxbw, hipStream_t st);
+template <typename T>
+bool launch_band_solve(const SolveArgs<T> &a, int nsys, int nrhs, int maxbw, hipStream_t st);
+void launch_merge(const MergeArgs &a, hipStream_t st);
+void launch_init_corrections(const InitArgs &a, int nsys, hipStream_t st);
+void launch_newton_update(const NewtonArgs &a, hipStream_t st);
+void launch_ir_start(const IrStartArgs &a, hipStream_t st);
+
+}  // namespace lp

@@ -1,0 +1,988 @@
+// HIP kernels of the local parallel stage (gfx950).
+//
+// Every local problem lives on a box of one grid (a subdomain Omega_j of T_h,
+// or a whole region of T_H for the coarse step).  Element work is done by
+// gather: one thread per local lattice node loops over the (at most six)
+// triangles of the box that contain the node and accumulates its own rows,
+// so results are deterministic without atomics.  Linear systems are banded
+// (lattice-row ordering) and factored without pivoting by one workgroup per
+// system with the active window held in registers; triangular solves run one
+// wavefront per right-hand side.
+#include <hip/hip_runtime.h>
+#include <cmath>
+
+#include "kernels.h"
+
+namespace lp {
+
+__constant__ RefData c_ref;
+__constant__ Coef c_co;
+
+hipError_t upload_constants(const RefData &r, const Coef &c, hipStream_t st) {
+    hipError_t e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_ref), &r, sizeof(RefData), 0, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    return hipMemcpyToSymbolAsync(HIP_SYMBOL(c_co), &c, sizeof(Coef), 0, hipMemcpyHostToDevice, st);
+}
+
+// ---------------------------------------------------------------------------
+// element helpers
+// ---------------------------------------------------------------------------
+// local index (0..5) of the P2 node at in-cell half coordinates (la, lb) in
+// orientation t, or -1 if the node is not on that triangle
+__device__ __forceinline__ int p2_local(int t, int la, int lb) {
+    if (t == 0) {
+        if (la < lb) return -1;
+        const int tab[3][3] = {{0, -1, -1}, {3, 5, -1}, {1, 4, 2}};   // [la][lb]
+        return tab[la][lb];
+    } else {
+        if (la > lb) return -1;
+        const int tab[3][3] = {{0, 5, 2}, {-1, 3, 4}, {-1, -1, 1}};
+        return tab[la][lb];
+    }
+}
+
+// P1 local index of the vertex at in-cell vertex coordinates (i, j)
+__device__ __forceinline__ int p1_local(int t, int i, int j) {
+    if (t == 0) { if (i == 0 && j == 0) return 0; if (i == 1 && j == 0) return 1; if (i == 1 && j == 1) return 2; return -1; }
+    if (i == 0 && j == 0) return 0; if (i == 1 && j == 1) return 1; if (i == 0 && j == 1) return 2; return -1;
+}
+
+// Visit the triangles of a box (cx x cy cells) containing the box-local P2
+// node (a, b): f(t, ci, cj, la) with box-local cell indices.
+template <class F>
+__device__ __forceinline__ void for_elements(int a, int b, int cx, int cy, F &&f) {
+    const int ci0 = (a - 1) >> 1 < 0 ? 0 : ((a - 1) >> 1);
+    const int ci1 = (a >> 1) < cx ? (a >> 1) : cx - 1;
+    const int cj0 = (b - 1) >> 1 < 0 ? 0 : ((b - 1) >> 1);
+    const int cj1 = (b >> 1) < cy ? (b >> 1) : cy - 1;
+    for (int cj = cj0; cj <= cj1; ++cj)
+        for (int ci = ci0; ci <= ci1; ++ci) {
+            const int la = a - 2 * ci, lb = b - 2 * cj;
+            if (la < 0 || la > 2 || lb < 0 || lb > 2) continue;
+            for (int t = 0; t < 2; ++t) {
+                const int k = p2_local(t, la, lb);
+                if (k >= 0) f(t, ci, cj, k);
+            }
+        }
+}
+
+// ---------------------------------------------------------------------------
+// Prolongation Pi_h (exact evaluation of coarse P2 / P1 functions at fine nodes)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void p2_values(double xi, double eta, double v[6]) {
+    const double l0 = 1.0 - xi - eta, l1 = xi, l2 = eta;
+    v[0] = l0 * (2 * l0 - 1); v[1] = l1 * (2 * l1 - 1); v[2] = l2 * (2 * l2 - 1);
+    v[3] = 4 * l0 * l1; v[4] = 4 * l1 * l2; v[5] = 4 * l0 * l2;
+}
+
+__global__ void k_prolong_p2(ProlongArgs A) {
+    const int nf = 2 * A.Nh + 1, nc = 2 * A.NH + 1;
+    const long long tot = (long long)nf * nf;
+    for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < tot; g += (long long)gridDim.x * blockDim.x) {
+        const int a = (int)(g % nf), b = (int)(g / nf);
+        const int k2 = 2 * A.k;                    // fine half-steps per coarse cell
+        int ci = a / k2, cj = b / k2;
+        if (ci >= A.NH) ci = A.NH - 1;
+        if (cj >= A.NH) cj = A.NH - 1;
+        const int la = a - k2 * ci, lb = b - k2 * cj;   // 0..k2
+        const double lx = (double)la / k2, ly = (double)lb / k2;
+        const int t = lb > la ? 1 : 0;
+        double xi, eta;
+        if (t == 0) { xi = lx - ly; eta = ly; } else { xi = lx; eta = ly - lx; }
+        double v[6];
+        p2_values(xi, eta, v);
+        for (int f = 0; f < A.nfields; ++f) {
+            const double *src = A.src[f];
+            double s = 0.0;
+            for (int q = 0; q < 6; ++q)
+                s += v[q] * src[(2 * ci + off2a(t, q)) + (long long)nc * (2 * cj + off2b(t, q))];
+            A.dst[f][g] = s;
+        }
+    }
+}
+
+__global__ void k_prolong_p1(ProlongArgs A) {
+    const int nf = A.Nh + 1, nc = A.NH + 1;
+    const long long tot = (long long)nf * nf;
+    for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < tot; g += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(g % nf), j = (int)(g / nf);
+        int ci = i / A.k, cj = j / A.k;
+        if (ci >= A.NH) ci = A.NH - 1;
+        if (cj >= A.NH) cj = A.NH - 1;
+        const double lx = (double)(i - A.k * ci) / A.k, ly = (double)(j - A.k * cj) / A.k;
+        const int t = (j - A.k * cj) > (i - A.k * ci) ? 1 : 0;
+        double l[3];
+        if (t == 0) { l[1] = lx - ly; l[2] = ly; } else { l[1] = lx; l[2] = ly - lx; }
+        l[0] = 1.0 - l[1] - l[2];
+        for (int f = 0; f < A.nfields; ++f) {
+            double s = 0.0;
+            for (int q = 0; q < 3; ++q) s += l[q] * A.src[f][(ci + off1a(t, q)) + (long long)nc * (cj + off1b(t, q))];
+            A.dst[f][g] = s;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Porous systems (Eqs. (5.1)-(5.3) on T_H, (5.5)-(5.7) on Omega_j)
+//   A_f = (tau_f + x_f) M + kap_f K,  x_F = s*, x_f = s + s*, x_m = s
+//   b_f = Q_f + M[tau_f (O_f - X_f) - x_f X_f + sum_k c_fk O_k] - kap_f K X_f + Gamma_f
+//   X_f = P_f^{n+1} + z_f (background at n+1 plus Dirichlet values of the correction),
+//   O_f = P_f^n + e_f^n (background at n plus the previous correction).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double porous_x(int f) { return f == 0 ? c_co.sst : f == 1 ? c_co.s + c_co.sst : c_co.s; }
+
+// Dirichlet value of field f of the correction at local P2 node q of system S
+__device__ __forceinline__ double porous_z(const SysDesc &S, const PorousArgs &A, int f, int q, long long G) {
+    const int c = A.cls2[S.node_off + q];
+    if (c != 1) return 0.0;
+    const double bg = A.P1[f] ? A.P1[f][G] : 0.0;
+    return A.ex[f][G] * A.tf[0] - bg;
+}
+
+__global__ __launch_bounds__(256) void k_porous_rhs(PorousArgs A) {
+    const SysDesc S = A.sys[blockIdx.x];
+    const int nloc = S.lw2 * S.lh2;
+    const int ng = 2 * S.N + 1;
+    const double h = S.h, h2 = h * h;
+    for (int q = threadIdx.x; q < nloc; q += blockDim.x) {
+        const int a = q % S.lw2, b = q / S.lw2;
+        const long long G = (2 * S.x0 + a) + (long long)ng * (2 * S.y0 + b);
+        const int cls = A.cls2[S.node_off + q];
+        for (int f = 0; f < 3; ++f) {
+            double *en = A.e_new + S.e2_off + (long long)f * nloc;
+            if (cls != 0) { en[q] = porous_z(S, A, f, q, G); continue; }
+            // sources at t_{n+1}
+            double r = A.load[f][0][G] * A.tf[0] + A.load[f][1][G] * A.tf[1];
+            const double tau = c_co.tau[f], xf = porous_x(f), kap = c_co.kap[f];
+            for_elements(a, b, S.cx, S.cy, [&](int t, int ci, int cj, int la) {
+                double mv = 0.0, kv = 0.0;
+                for (int k = 0; k < 6; ++k) {
+                    const int qa = 2 * ci + off2a(t, k), qb = 2 * cj + off2b(t, k);
+                    const int qk = qa + S.lw2 * qb;
+                    const long long Gk = (2 * S.x0 + qa) + (long long)ng * (2 * S.y0 + qb);
+                    double O[3], X;
+                    for (int g = 0; g < 3; ++g)
+                        O[g] = (A.P0[g] ? A.P0[g][Gk] : 0.0) + A.e_old[S.e2_off + (long long)g * nloc + qk];
+                    X = (A.P1[f] ? A.P1[f][Gk] : 0.0) + porous_z(S, A, f, qk, Gk);
+                    double m = tau * (O[f] - X) - xf * X;
+                    if (f == 0) m += c_co.sst * O[1];
+                    if (f == 1) m += c_co.s * O[2] + c_co.sst * O[0];
+                    if (f == 2) m += c_co.s * O[1];
+                    mv += c_ref.Me[t][la][k] * m;
+                    kv += c_ref.Ke[t][la][k] * X;
+                }
+                r += h2 * mv - kap * kv;
+            });
+            // + <u^n . n_c, v_F>_Gamma = -int_Gamma v_F u_y^n on the porous top row
+            if (f == 0 && S.gamma && 2 * S.y0 + b == 2 * S.N && A.Uy0) {
+                const int A0 = 2 * S.x0 + a;
+                const int ne = (A0 & 1) ? 1 : 2;
+                for (int e = 0; e < ne; ++e) {
+                    const int ie = (A0 & 1) ? (A0 >> 1) : (A0 >> 1) - 1 + e;
+                    if (ie < S.x0 || ie >= S.x0 + S.cx) continue;
+                    const int la = A0 - 2 * ie;
+                    double s = 0.0;
+                    for (int k = 0; k < 3; ++k) s += c_ref.Ge[la][k] * A.Uy0[2 * ie + k];   // conduit Gamma row b = 0
+                    r -= h * s;
+                }
+            }
+            A.b[S.dof_off + (long long)f * S.ndof + A.dof2[S.node_off + q]] = r;
+        }
+    }
+}
+
+// block reduction of ||r||^2 and ||b||^2; thread 0 records the relative
+// residual, counts the sweep and raises the convergence flag
+__device__ void block_norms_and_flag(double rr, double bb, const ResidualArgs &R, int id) {
+    __shared__ double s1[256], s2[256];
+    s1[threadIdx.x] = rr;
+    s2[threadIdx.x] = bb;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) { s1[threadIdx.x] += s1[threadIdx.x + s]; s2[threadIdx.x] += s2[threadIdx.x + s]; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double rel = s2[0] > 0.0 ? sqrt(s1[0] / s2[0]) : 0.0;
+        R.relres[id] = rel;
+        R.sweeps[id] += 1;
+        if (rel <= R.tol) R.conv[id] = 1;
+    }
+}
+
+// y = A_f x restricted to free rows (FP64, matrix-free); r = b - y; norms
+__global__ __launch_bounds__(256) void k_porous_residual(ResidualArgs R) {
+    const SysDesc S = R.sys[blockIdx.x];
+    const int f = blockIdx.y;
+    const int id = blockIdx.x * 3 + f;
+    if (R.skip && *R.skip) return;
+    if (R.conv[id]) return;
+    const int nloc = S.lw2 * S.lh2;
+    const double h2 = S.h * S.h;
+    const double tau = c_co.tau[f], xf = porous_x(f), kap = c_co.kap[f];
+    const double *x = R.x + S.dof_off + (long long)f * S.ndof;
+    const double *b = R.b + S.dof_off + (long long)f * S.ndof;
+    double *r = R.r + S.dof_off + (long long)f * S.ndof;
+    double rr = 0.0, bb = 0.0;
+    for (int q = threadIdx.x; q < nloc; q += blockDim.x) {
+        const int dq = R.dof2[S.node_off + q];
+        if (dq < 0) continue;
+        const int a = q % S.lw2, bq = q / S.lw2;
+        double y = 0.0;
+        for_elements(a, bq, S.cx, S.cy, [&](int t, int ci, int cj, int la) {
+            for (int k = 0; k < 6; ++k) {
+                const int qk = (2 * ci + off2a(t, k)) + S.lw2 * (2 * cj + off2b(t, k));
+                const int dk = R.dof2[S.node_off + qk];
+                if (dk < 0) continue;
+                y += ((tau + xf) * h2 * c_ref.Me[t][la][k] + kap * c_ref.Ke[t][la][k]) * x[dk];
+            }
+        });
+        const double rv = b[dq] - y;
+        r[dq] = rv;
+        rr += rv * rv;
+        bb += b[dq] * b[dq];
+    }
+    block_norms_and_flag(rr, bb, R, id);
+}
+
+__global__ __launch_bounds__(256) void k_porous_finalize(FinalizeArgs F) {
+    const SysDesc S = F.sys[blockIdx.x];
+    if (F.skip && *F.skip) return;
+    const int nloc = S.lw2 * S.lh2;
+    for (int q = threadIdx.x; q < nloc; q += blockDim.x) {
+        const int d = F.dof2[S.node_off + q];
+        if (d < 0) continue;
+        for (int f = 0; f < 3; ++f)
+            F.e_new[S.e2_off + (long long)f * nloc + q] = F.x[S.dof_off + (long long)f * S.ndof + d];
+    }
+}
+
+// band assembly of the constant porous matrices (setup)
+template <typename T>
+__global__ __launch_bounds__(256) void k_porous_assemble(AssembleArgs<T> A) {
+    const SysDesc S = A.sys[blockIdx.x];
+    const int nloc = S.lw2 * S.lh2;
+    const int ld = 2 * S.bw + 1;
+    const double h2 = S.h * S.h;
+    for (int q = threadIdx.x; q < nloc; q += blockDim.x) {
+        const int dq = A.dof2[S.node_off + q];
+        if (dq < 0) continue;
+        const int a = q % S.lw2, bq = q / S.lw2;
+        for (int f = 0; f < 3; ++f) {
+            T *band = A.band + S.band_off + (long long)f * S.band_size;
+            const double tau = c_co.tau[f], xf = porous_x(f), kap = c_co.kap[f];
+            for_elements(a, bq, S.cx, S.cy, [&](int t, int ci, int cj, int la) {
+                for (int k = 0; k < 6; ++k) {
+                    const int qk = (2 * ci + off2a(t, k)) + S.lw2 * (2 * cj + off2b(t, k));
+                    const int dk = A.dof2[S.node_off + qk];
+                    if (dk < 0) continue;
+                    const double v = (tau + xf) * h2 * c_ref.Me[t][la][k] + kap * c_ref.Ke[t][la][k];
+                    T *p = band + (long long)dk * ld + (dq - dk + S.bw);
+                    *p = (T)((double)*p + v);
+                }
+            });
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Oseen systems (Eq. (5.4) linearised by Newton on T_H, Eq. (5.8) on Omega_j)
+//   [eta/dt M + nu eta S + eta beta G_Gamma + eta N(W)] e - eta B^T d = b_u
+//   eta B e = b_q
+// ---------------------------------------------------------------------------
+// element values of the box-local velocity nodes of triangle (t, ci, cj)
+struct ElemVel {
+    double w[2][6];      // background W^{n+1}
+};
+
+// velocity Dirichlet value of the correction at local node q
+__device__ __forceinline__ double oseen_z(const SysDesc &S, const OseenArgs &A, int c, int q, long long G) {
+    if (A.cls2[S.node_off + q] != 1) return 0.0;
+    return A.ex[c][G] * A.tf[0] - A.W1[c][G];
+}
+
+// convection rows at test node la of triangle t (unit-cell reference data,
+// scaled by h): cW[c] = int ((W.grad)W)_c phi_la, Nz[c] = int (N(W) z)_c phi_la
+__device__ __forceinline__ void conv_rows(int t, int la, double h, const double W[2][6], const double Z[2][6],
+                                          bool want_c, double cW[2], double Nz[2]) {
+    cW[0] = cW[1] = Nz[0] = Nz[1] = 0.0;
+    for (int q = 0; q < NQ; ++q) {
+        double wv[2] = {0, 0}, gw[2][2] = {{0, 0}, {0, 0}}, zv[2] = {0, 0}, gz[2][2] = {{0, 0}, {0, 0}};
+        for (int k = 0; k < 6; ++k) {
+            const double p = c_ref.phi[q][k], dx = c_ref.dphi[t][q][k][0], dy = c_ref.dphi[t][q][k][1];
+            for (int c = 0; c < 2; ++c) {
+                wv[c] += W[c][k] * p;
+                gw[c][0] += W[c][k] * dx;
+                gw[c][1] += W[c][k] * dy;
+                zv[c] += Z[c][k] * p;
+                gz[c][0] += Z[c][k] * dx;
+                gz[c][1] += Z[c][k] * dy;
+            }
+        }
+        const double wt = c_ref.w[q] * c_ref.phi[q][la];
+        for (int c = 0; c < 2; ++c) {
+            if (want_c) cW[c] += wt * (wv[0] * gw[c][0] + wv[1] * gw[c][1]);
+            Nz[c] += wt * (zv[0] * gw[c][0] + zv[1] * gw[c][1] + wv[0] * gz[c][0] + wv[1] * gz[c][1]);
+        }
+    }
+    // h^2 (area) * 1/h (one derivative)
+    for (int c = 0; c < 2; ++c) { cW[c] *= h; Nz[c] *= h; }
+}
+
+__global__ __launch_bounds__(256) void k_oseen_rhs(OseenArgs A) {
+    const SysDesc S = A.sys[blockIdx.x];
+    if (A.skip && *A.skip) return;
+    const int nloc = S.lw2 * S.lh2, nv = S.lw1 * S.lh1;
+    const int ng = 2 * S.N + 1, ng1 = S.N + 1;
+    const double h = S.h, h2 = h * h;
+    const double eta = c_co.eta, edt = c_co.eta / c_co.dt, nue = c_co.nu * c_co.eta;
+    for (int q = threadIdx.x; q < nloc; q += blockDim.x) {
+        const int a = q % S.lw2, b = q / S.lw2;
+        const long long G = (2 * S.x0 + a) + (long long)ng * (2 * S.y0 + b);
+        const int cls = A.cls2[S.node_off + q];
+        double *en = A.e_new + S.e2_off;
+        const bool vertex = !(a & 1) && !(b & 1);
+        const int vq = vertex ? (a >> 1) + S.lw1 * (b >> 1) : -1;
+        if (cls != 0) {
+            for (int c = 0; c < 2; ++c) en[(long long)c * nloc + q] = oseen_z(S, A, c, q, G);
+        }
+        const bool prow = vertex && A.cls1[S.vert_off + vq] == 0;
+        if (vertex && !prow) A.e_new1[S.e1_off + vq] = 0.0;
+        if (cls != 0 && !prow) continue;
+        double rv[2] = {0.0, 0.0}, rq = 0.0;
+        if (cls == 0)
+            for (int c = 0; c < 2; ++c)
+                rv[c] = eta * (A.load[c][0][G] * A.tf[0] + A.load[c][1][G] * A.tf[1] + A.load[c][2][G] * A.tf[2]);
+        for_elements(a, b, S.cx, S.cy, [&](int t, int ci, int cj, int la) {
+            double W[2][6], Z[2][6], Y[2][6], O[2][6], P[3];
+            for (int k = 0; k < 6; ++k) {
+                const int qa = 2 * ci + off2a(t, k), qb = 2 * cj + off2b(t, k);
+                const int qk = qa + S.lw2 * qb;
+                const long long Gk = (2 * S.x0 + qa) + (long long)ng * (2 * S.y0 + qb);
+                for (int c = 0; c < 2; ++c) {
+                    W[c][k] = A.W1[c][Gk];
+                    Z[c][k] = oseen_z(S, A, c, qk, Gk);
+                    Y[c][k] = W[c][k] + Z[c][k];
+                    O[c][k] = (A.W0[c] ? A.W0[c][Gk] : 0.0) + (A.e_old ? A.e_old[S.e2_off + (long long)c * nloc + qk] : 0.0)
+                              - W[c][k] - Z[c][k];
+                }
+            }
+            for (int k = 0; k < 3; ++k)
+                P[k] = A.Pp[(S.x0 + ci + off1a(t, k)) + (long long)ng1 * (S.y0 + cj + off1b(t, k))];
+            if (cls == 0) {
+                double cW[2], Nz[2];
+                if (c_co.convection) conv_rows(t, la, h, W, Z, true, cW, Nz);
+                else cW[0] = cW[1] = Nz[0] = Nz[1] = 0.0;
+                for (int c = 0; c < 2; ++c) {
+                    double m = 0.0, s = 0.0, bt = 0.0;
+                    for (int k = 0; k < 6; ++k) {
+                        m += c_ref.Me[t][la][k] * O[c][k];
+                        for (int d = 0; d < 2; ++d) s += c_ref.Se[t][c * 6 + la][d * 6 + k] * Y[d][k];
+                    }
+                    for (int v = 0; v < 3; ++v) bt += c_ref.Be[t][v][c * 6 + la] * P[v];
+                    rv[c] += edt * h2 * m - nue * s - eta * (cW[c] + Nz[c]) + eta * h * bt;
+                }
+            }
+            if (prow) {
+                const int lv = p1_local(t, (a >> 1) - ci, (b >> 1) - cj);
+                double s = 0.0;
+                for (int d = 0; d < 2; ++d)
+                    for (int k = 0; k < 6; ++k) s += c_ref.Be[t][lv][d * 6 + k] * Y[d][k];
+                rq -= eta * h * s;
+            }
+        });
+        // Gamma edges (conduit bottom row): Beavers-Joseph on the x rows and the
+        // lagged p_F^n terms -(eta/rho) int p_F v.n_c - c_tau int d_x p_F v_x
+        if (cls == 0 && S.gamma && 2 * S.y0 + b == 0) {
+            const int A0 = 2 * S.x0 + a;
+            const int ne = (A0 & 1) ? 1 : 2;
+            for (int e = 0; e < ne; ++e) {
+                const int ie = (A0 & 1) ? (A0 >> 1) : (A0 >> 1) - 1 + e;
+                if (ie < S.x0 || ie >= S.x0 + S.cx) continue;
+                const int la = A0 - 2 * ie;
+                double bj = 0.0, pg = 0.0, pgx = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    const int qk = (2 * ie + k - 2 * S.x0);     // box-local, row 0
+                    const long long Gk = 2 * ie + k;           // grid conduit row 0
+                    bj += c_ref.Ge[la][k] * (A.W1[0][Gk] + oseen_z(S, A, 0, qk, Gk));
+                    const double pf = A.PF0[(2 * ie + k) + (long long)ng * (2 * S.N)];   // porous top row
+                    pg += c_ref.Ge[la][k] * pf;
+                    pgx += c_ref.Gxe[la][k] * pf;
+                }
+                rv[0] -= eta * c_co.beta * h * bj + c_co.ctau * pgx;
+                rv[1] += eta / c_co.rho * h * pg;
+            }
+        }
+        if (cls == 0) {
+            const int d = A.dof2[S.node_off + q];
+            A.b[S.dof_off + d] = rv[0];
+            A.b[S.dof_off + d + 1] = rv[1];
+        }
+        if (prow) A.b[S.dof_off + A.dof1[S.vert_off + vq]] = rq;
+    }
+}
+
+// Row application of the Oseen operator to x (FP64) or assembly of its band
+// entries (T).  Mode 0: residual r = b - K x.  Mode 1: band assembly.
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_oseen_apply(OseenApplyArgs<T> A) {
+    const SysDesc S = A.sys[blockIdx.x];
+    if (A.skip && *A.skip) return;
+    if (MODE == 0 && A.conv[blockIdx.x]) return;
+    const int nloc = S.lw2 * S.lh2;
+    const int ng = 2 * S.N + 1;
+    const double h = S.h, h2 = h * h;
+    const double eta = c_co.eta, edt = c_co.eta / c_co.dt, nue = c_co.nu * c_co.eta;
+    const int ld = 2 * S.bw + 1;
+    T *band = MODE == 1 ? A.band + S.band_off : nullptr;
+    const double *x = MODE == 0 ? A.x + S.dof_off : nullptr;
+    double rr = 0.0, bb = 0.0;
+    auto put = [&](int row, int col, double v) {
+        T *p = band + (long long)col * ld + (row - col + S.bw);
+        *p = (T)((double)*p + v);
+    };
+    for (int q = threadIdx.x; q < nloc; q += blockDim.x) {
+        const int a = q % S.lw2, b = q / S.lw2;
+        const int cls = A.cls2[S.node_off + q];
+        const bool vertex = !(a & 1) && !(b & 1);
+        const int vq = vertex ? (a >> 1) + S.lw1 * (b >> 1) : -1;
+        const int dv = cls == 0 ? A.dof2[S.node_off + q] : -1;
+        const int dp = vertex ? A.dof1[S.vert_off + vq] : -1;
+        if (dv < 0 && dp < 0) continue;
+        double yv[2] = {0.0, 0.0}, yq = 0.0;
+        for_elements(a, b, S.cx, S.cy, [&](int t, int ci, int cj, int la) {
+            double W[2][6], X[2][6];
+            int dk[6], pk[3];
+            for (int k = 0; k < 6; ++k) {
+                const int qa = 2 * ci + off2a(t, k), qb = 2 * cj + off2b(t, k);
+                const int qk = qa + S.lw2 * qb;
+                const long long Gk = (2 * S.x0 + qa) + (long long)ng * (2 * S.y0 + qb);
+                dk[k] = A.dof2[S.node_off + qk];
+                for (int c = 0; c < 2; ++c) {
+                    W[c][k] = A.W1[c][Gk];
+                    X[c][k] = (MODE == 0 && dk[k] >= 0) ? x[dk[k] + c] : 0.0;
+                }
+            }
+            for (int k = 0; k < 3; ++k)
+                pk[k] = A.dof1[S.vert_off + (ci + off1a(t, k)) + S.lw1 * (cj + off1b(t, k))];
+            if (dv >= 0) {
+                if (MODE == 0) {
+                    double cW[2], Nz[2];
+                    if (c_co.convection) conv_rows(t, la, h, W, X, false, cW, Nz);
+                    else Nz[0] = Nz[1] = 0.0;
+                    for (int c = 0; c < 2; ++c) {
+                        double m = 0.0, s = 0.0, bt = 0.0;
+                        for (int k = 0; k < 6; ++k) {
+                            m += c_ref.Me[t][la][k] * X[c][k];
+                            for (int d = 0; d < 2; ++d) s += c_ref.Se[t][c * 6 + la][d * 6 + k] * X[d][k];
+                        }
+                        for (int v = 0; v < 3; ++v)
+                            if (pk[v] >= 0) bt += c_ref.Be[t][v][c * 6 + la] * x[pk[v]];
+                        yv[c] += edt * h2 * m + nue * s + eta * Nz[c] - eta * h * bt;
+                    }
+                } else {
+                    // entries of rows (la, c) against columns (k, d) and pressure v
+                    double Nw[2][2][6];     // [c][d][k]
+                    for (int c = 0; c < 2; ++c) for (int d = 0; d < 2; ++d) for (int k = 0; k < 6; ++k) Nw[c][d][k] = 0.0;
+                    if (c_co.convection) {
+                        for (int qq = 0; qq < NQ; ++qq) {
+                            double wv[2] = {0, 0}, gw[2][2] = {{0, 0}, {0, 0}};
+                            for (int k = 0; k < 6; ++k) {
+                                const double p = c_ref.phi[qq][k];
+                                for (int c = 0; c < 2; ++c) {
+                                    wv[c] += W[c][k] * p;
+                                    gw[c][0] += W[c][k] * c_ref.dphi[t][qq][k][0];
+                                    gw[c][1] += W[c][k] * c_ref.dphi[t][qq][k][1];
+                                }
+                            }
+                            const double wt = c_ref.w[qq] * c_ref.phi[qq][la] * h;
+                            for (int k = 0; k < 6; ++k) {
+                                const double pk_ = c_ref.phi[qq][k];
+                                const double adv = wv[0] * c_ref.dphi[t][qq][k][0] + wv[1] * c_ref.dphi[t][qq][k][1];
+                                for (int c = 0; c < 2; ++c) {
+                                    for (int d = 0; d < 2; ++d) Nw[c][d][k] += wt * pk_ * gw[c][d];
+                                    Nw[c][c][k] += wt * adv;
+                                }
+                            }
+                        }
+                    }
+                    for (int k = 0; k < 6; ++k) {
+                        if (dk[k] < 0) continue;
+                        for (int c = 0; c < 2; ++c)
+                            for (int d = 0; d < 2; ++d) {
+                                double v = nue * c_ref.Se[t][c * 6 + la][d * 6 + k] + eta * Nw[c][d][k];
+                                if (c == d) v += edt * h2 * c_ref.Me[t][la][k];
+                                put(dv + c, dk[k] + d, v);
+                            }
+                    }
+                    for (int v = 0; v < 3; ++v)
+                        if (pk[v] >= 0)
+                            for (int c = 0; c < 2; ++c) put(dv + c, pk[v], -eta * h * c_ref.Be[t][v][c * 6 + la]);
+                }
+            }
+            if (dp >= 0) {
+                const int lv = p1_local(t, (a >> 1) - ci, (b >> 1) - cj);
+                if (MODE == 0) {
+                    double s = 0.0;
+                    for (int d = 0; d < 2; ++d)
+                        for (int k = 0; k < 6; ++k) s += c_ref.Be[t][lv][d * 6 + k] * X[d][k];
+                    yq += eta * h * s;
+                } else {
+                    for (int k = 0; k < 6; ++k)
+                        if (dk[k] >= 0)
+                            for (int d = 0; d < 2; ++d) put(dp, dk[k] + d, eta * h * c_ref.Be[t][lv][d * 6 + k]);
+                }
+            }
+        });
+        // Beavers-Joseph term on Gamma edges (x rows, x columns)
+        if (dv >= 0 && S.gamma && 2 * S.y0 + b == 0) {
+            const int A0 = 2 * S.x0 + a;
+            const int ne = (A0 & 1) ? 1 : 2;
+            for (int e = 0; e < ne; ++e) {
+                const int ie = (A0 & 1) ? (A0 >> 1) : (A0 >> 1) - 1 + e;
+                if (ie < S.x0 || ie >= S.x0 + S.cx) continue;
+                const int la = A0 - 2 * ie;
+                for (int k = 0; k < 3; ++k) {
+                    const int qk = 2 * ie + k - 2 * S.x0;
+                    const int dk = A.dof2[S.node_off + qk];
+                    if (dk < 0) continue;
+                    const double v = eta * c_co.beta * h * c_ref.Ge[la][k];
+                    if (MODE == 0) yv[0] += v * x[dk];
+                    else put(dv, dk, v);
+                }
+            }
+        }
+        if (MODE == 0) {
+            if (dv >= 0)
+                for (int c = 0; c < 2; ++c) {
+                    const double bv = A.b[S.dof_off + dv + c];
+                    const double rv = bv - yv[c];
+                    A.r[S.dof_off + dv + c] = rv;
+                    rr += rv * rv;
+                    bb += bv * bv;
+                }
+            if (dp >= 0) {
+                const double bv = A.b[S.dof_off + dp];
+                const double rv = bv - yq;
+                A.r[S.dof_off + dp] = rv;
+                rr += rv * rv;
+                bb += bv * bv;
+            }
+        }
+    }
+    if (MODE == 0) {
+        ResidualArgs R;
+        R.conv = A.conv; R.relres = A.relres; R.tol = A.tol; R.sweeps = A.sweeps;
+        block_norms_and_flag(rr, bb, R, blockIdx.x);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_oseen_finalize(FinalizeArgs F) {
+    const SysDesc S = F.sys[blockIdx.x];
+    if (F.skip && *F.skip) return;
+    const int nloc = S.lw2 * S.lh2, nv = S.lw1 * S.lh1;
+    for (int q = threadIdx.x; q < nloc; q += blockDim.x) {
+        const int d = F.dof2[S.node_off + q];
+        if (d < 0) continue;
+        F.e_new[S.e2_off + q] = F.x[S.dof_off + d];
+        F.e_new[S.e2_off + nloc + q] = F.x[S.dof_off + d + 1];
+    }
+    for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+        const int d = F.dof1[S.vert_off + v];
+        if (d >= 0) F.e_new1[S.e1_off + v] = F.x[S.dof_off + d];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Band LU without pivoting.  One workgroup per system; the active window of
+// WR x WC entries (rows k..k+WR-1, columns k..k+WC-1 relative to the current
+// pivot k) lives in registers, thread (tr, tc) holding an RB x CB block.
+// Each step shifts the window by one along the diagonal while applying the
+// rank-one update; block boundary rows/columns travel through LDS.  Factors
+// overwrite the column-major band (entry (i,j) at j*(2bw+1) + i - j + bw).
+// Requires WR, WC > bw.
+// ---------------------------------------------------------------------------
+template <typename T, int TR, int TC, int RB, int CB>
+__global__ __launch_bounds__(TR *TC) void k_band_lu(BandArgs<T> B) {
+    constexpr int WR = TR * RB, WC = TC * CB;
+    const BandSys Sy = B.sys[blockIdx.x];
+    if (B.skip && *B.skip) return;
+    const int n = Sy.n, bw = Sy.bw, ld = 2 * bw + 1;
+    T *M = B.band + Sy.off;
+    __shared__ T srow[2][TR][WC];
+    __shared__ T scol[2][TC][WR];
+    const int tid = threadIdx.x, tr = tid / TC, tc = tid % TC;
+    auto ldb = [&](long long i, long long j) -> T {
+        if (i < 0 || j < 0 || i >= n || j >= n) return T(0);
+        const long long d = i - j;
+        if (d > bw || d < -bw) return T(0);
+        return M[j * ld + d + bw];
+    };
+    T a[RB][CB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int jj = 0; jj < CB; ++jj) a[i][jj] = ldb(tr * RB + i, tc * CB + jj);
+    int bad = 0;
+    for (int k = 0; k < n; ++k) {
+        const int buf = k & 1;
+        T in_row[CB], in_col[RB];
+        if (tr == TR - 1) {
+#pragma unroll
+            for (int jj = 0; jj < CB; ++jj) in_row[jj] = ldb((long long)k + WR, (long long)k + 1 + tc * CB + jj);
+        }
+        if (tc == TC - 1) {
+#pragma unroll
+            for (int i = 0; i < RB; ++i) in_col[i] = ldb((long long)k + 1 + tr * RB + i, (long long)k + WC);
+        }
+#pragma unroll
+        for (int jj = 0; jj < CB; ++jj) srow[buf][tr][tc * CB + jj] = a[0][jj];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) scol[buf][tc][tr * RB + i] = a[i][0];
+        __syncthreads();
+        T piv = srow[buf][0][0];
+        if (!(fabs((double)piv) > 0.0) || !isfinite((double)piv)) { bad = 1; piv = T(1); }
+        const T inv = T(1) / piv;
+        // outputs: L column k and U row k
+        if (tc == 0) {
+#pragma unroll
+            for (int i = 0; i < RB; ++i) {
+                const int r = tr * RB + i;
+                if (r >= 1 && r <= bw && k + r < n) M[(long long)k * ld + r + bw] = a[i][0] * inv;
+            }
+        }
+        if (tr == 0) {
+#pragma unroll
+            for (int jj = 0; jj < CB; ++jj) {
+                const int c = tc * CB + jj;
+                if (c <= bw && k + c < n) M[(long long)(k + c) * ld + bw - c] = a[0][jj];
+            }
+        }
+        T l[RB], u[CB];
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+            const int r1 = tr * RB + i + 1;
+            l[i] = r1 < WR ? scol[buf][0][r1] * inv : T(0);
+        }
+#pragma unroll
+        for (int jj = 0; jj < CB; ++jj) {
+            const int c1 = tc * CB + jj + 1;
+            u[jj] = c1 < WC ? srow[buf][0][c1] : T(0);
+        }
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+#pragma unroll
+            for (int jj = 0; jj < CB; ++jj) {
+                T src;
+                if (i < RB - 1 && jj < CB - 1) src = a[i + 1][jj + 1];
+                else if (i == RB - 1 && jj < CB - 1) src = tr < TR - 1 ? srow[buf][tr + 1][tc * CB + jj + 1] : in_row[jj];
+                else if (i < RB - 1 && jj == CB - 1) src = tc < TC - 1 ? scol[buf][tc + 1][tr * RB + i + 1] : in_col[i];
+                else src = (tr < TR - 1 && tc < TC - 1) ? srow[buf][tr + 1][(tc + 1) * CB]
+                                                         : (tr == TR - 1 ? in_row[CB - 1] : in_col[RB - 1]);
+                a[i][jj] = src - l[i] * u[jj];
+            }
+    }
+    if (bad && tid == 0) atomicOr(B.flags, 4);
+}
+
+// ---------------------------------------------------------------------------
+// Band triangular solves, one wavefront per right-hand side: L y = r (unit
+// lower), U d = y, x += d.  The bw-row active window is spread circularly over
+// the 64 lanes (NR registers each); the finished entry is broadcast with
+// readlane and every lane updates its rows from a column of the factor.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T wave_bcast(T v, int lane);
+template <>
+__device__ __forceinline__ float wave_bcast<float>(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+template <>
+__device__ __forceinline__ double wave_bcast<double>(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
+}
+
+template <typename T, int NR>
+__global__ __launch_bounds__(64) void k_band_solve(SolveArgs<T> A) {
+    const int sysi = blockIdx.x, f = blockIdx.y;
+    const BandSys Sy = A.sys[sysi];
+    if (f >= Sy.nrhs) return;
+    const int id = sysi * A.rhs_per_sys + f;
+    if (A.skip && *A.skip) return;
+    if (A.conv && A.conv[id]) return;
+    const int n = Sy.n, bw = Sy.bw, ld = 2 * bw + 1;
+    const T *M = A.band + Sy.off + (long long)f * Sy.stride;
+    const double *r = A.r + Sy.vec + (long long)f * n;
+    double *x = A.x + Sy.vec + (long long)f * n;
+    T *y = A.y + Sy.vec + (long long)f * n;
+    const int lane = threadIdx.x;
+    const int W = bw > 0 ? bw : 1;
+    T win[NR];
+    int dist[NR];
+    // forward: window holds rows k..k+W-1 before step k, row i in slot i mod W
+#pragma unroll
+    for (int m = 0; m < NR; ++m) {
+        const int s = lane + 64 * m;
+        win[m] = (s < W && s < n) ? (T)r[s] : T(0);
+        dist[m] = s == 0 ? W : s;          // row - k for the slot at k = 0 after finishing row 0
+    }
+    int sk = 0;                             // slot of row k
+    for (int k = 0; k < n; ++k) {
+        const int ml = sk >> 6, ll = sk & 63;
+        T v = win[0];
+#pragma unroll
+        for (int m = 1; m < NR; ++m) if (m == ml) v = win[m];
+        const T yk = wave_bcast(v, ll);
+        if (lane == 0) y[k] = yk;
+        const T *col = M + (long long)k * ld + bw;
+#pragma unroll
+        for (int m = 0; m < NR; ++m) {
+            const int s = lane + 64 * m;
+            if (s >= W) continue;
+            const int d = dist[m];                 // this slot holds row k + d (d in 1..W)
+            const long long row = (long long)k + d;
+            T cur = win[m];
+            if (s == sk) cur = (row < n) ? (T)r[row] : T(0);   // slot of row k takes row k + W
+            if (row < n && d <= bw) cur -= col[d] * yk;
+            win[m] = cur;
+            dist[m] = d == 1 ? W : d - 1;
+        }
+        sk = sk + 1 == W ? 0 : sk + 1;
+    }
+    // y was written by lane 0 above; make it visible to every lane
+    __threadfence();
+    __syncthreads();
+    // backward: U d = y, window holds rows k-W+1..k before step k (descending)
+    const int k0 = n - 1;
+#pragma unroll
+    for (int m = 0; m < NR; ++m) {
+        const int s = lane + 64 * m;
+        // row k0 - j sits in slot (k0 - j) mod W for j = 0..W-1
+        if (s < W) {
+            int j = ((k0 % W) - s + W) % W;        // distance below k0
+            const long long row = (long long)k0 - j;
+            win[m] = row >= 0 ? y[row] : T(0);
+            dist[m] = j == 0 ? W : j;
+        } else { win[m] = T(0); dist[m] = 1; }
+    }
+    sk = k0 % W;
+    for (int k = k0; k >= 0; --k) {
+        const int ml = sk >> 6, ll = sk & 63;
+        T v = win[0];
+#pragma unroll
+        for (int m = 1; m < NR; ++m) if (m == ml) v = win[m];
+        const T *col = M + (long long)k * ld + bw;
+        const T dk = wave_bcast(v, ll) / col[0];
+        if (lane == 0) x[k] += (double)dk;
+#pragma unroll
+        for (int m = 0; m < NR; ++m) {
+            const int s = lane + 64 * m;
+            if (s >= W) continue;
+            const int d = dist[m];                 // this slot holds row k - d
+            const long long row = (long long)k - d;
+            T cur = win[m];
+            if (s == sk) cur = row >= 0 ? y[row] : T(0);
+            if (row >= 0 && d <= bw) cur -= col[-d] * dk;
+            win[m] = cur;
+            dist[m] = d == 1 ? W : d - 1;
+        }
+        sk = sk == 0 ? W - 1 : sk - 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Partition-of-unity merge (Algorithm 3 Step 4): x_h = Pi_h x_H + sum_j w_j e_j
+// over the closed cores containing the node, ascending j.
+// ---------------------------------------------------------------------------
+__global__ void k_merge(MergeArgs A) {
+    const int n2 = 2 * A.N + 1, n1 = A.N + 1;
+    const long long tot2 = (long long)n2 * n2, tot1 = (long long)n1 * n1;
+    for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < tot2 + tot1; g += (long long)gridDim.x * blockDim.x) {
+        const bool p1 = g >= tot2;
+        const long long gg = p1 ? g - tot2 : g;
+        const int nl = p1 ? n1 : n2;
+        const int a = (int)(gg % nl), b = (int)(gg / nl);
+        if (p1 && A.region == POROUS) continue;
+        const int *lox = p1 ? A.own1_lo[0] : A.own2_lo[0], *cnx = p1 ? A.own1_n[0] : A.own2_n[0];
+        const int *loy = p1 ? A.own1_lo[1] : A.own2_lo[1], *cny = p1 ? A.own1_n[1] : A.own2_n[1];
+        const double w = 1.0 / (double)(cnx[a] * cny[b]);
+        const int nf = p1 ? 1 : (A.region == POROUS ? 3 : 2);
+        double acc[3];
+        for (int f = 0; f < nf; ++f) acc[f] = p1 ? A.base1[gg] : A.base[f][gg];
+        for (int ky = loy[b]; ky < loy[b] + cny[b]; ++ky)
+            for (int kx = lox[a]; kx < lox[a] + cnx[a]; ++kx) {
+                const SysDesc &S = A.sys[kx + A.nsx * ky];
+                if (p1) {
+                    const int li = (a - S.x0) + S.lw1 * (b - S.y0);
+                    acc[0] += w * A.e1[S.e1_off + li];
+                } else {
+                    const int li = (a - 2 * S.x0) + S.lw2 * (b - 2 * S.y0);
+                    const long long nloc = (long long)S.lw2 * S.lh2;
+                    for (int f = 0; f < nf; ++f) acc[f] += w * A.e2[S.e2_off + f * nloc + li];
+                }
+            }
+        if (p1) A.out1[gg] = acc[0];
+        else for (int f = 0; f < nf; ++f) A.out[f][gg] = acc[f];
+    }
+}
+
+// initial corrections e_j^0 = I_h x_0 - Pi_h x_H^0 on each local lattice, zero
+// on artificial faces (the exact data is a(x) cos t, cos 0 = 1)
+__global__ void k_init_corrections(InitArgs A) {
+    const SysDesc S = A.sys[blockIdx.x];
+    const int nloc = S.lw2 * S.lh2, ng = 2 * S.N + 1;
+    const int nf = S.kind == KIND_POROUS ? 3 : 2;
+    for (int q = threadIdx.x; q < nloc; q += blockDim.x) {
+        const int a = q % S.lw2, b = q / S.lw2;
+        const long long G = (2 * S.x0 + a) + (long long)ng * (2 * S.y0 + b);
+        const int cls = A.cls2[S.node_off + q];
+        for (int f = 0; f < nf; ++f)
+            A.e[S.e2_off + (long long)f * nloc + q] = cls == 2 ? 0.0 : A.ex[f][G] - A.pro[f][G];
+    }
+    if (S.kind == KIND_OSEEN)
+        for (int v = threadIdx.x; v < S.lw1 * S.lh1; v += blockDim.x) A.e1[S.e1_off + v] = 0.0;
+}
+
+// Newton update of the coarse Navier-Stokes iterate: U += e, P += d, and the
+// convergence test ||(e, d)|| <= tol ||(U, P)|| (one workgroup)
+__global__ __launch_bounds__(256) void k_newton_update(NewtonArgs A) {
+    if (*A.done) return;
+    const long long nu = A.nu, np = A.np;
+    double dd = 0.0, xx = 0.0;
+    for (long long i = threadIdx.x; i < 2 * nu; i += blockDim.x) {
+        const double u = A.U[i] + A.e[i];
+        A.U[i] = u;
+        dd += A.e[i] * A.e[i];
+        xx += u * u;
+    }
+    for (long long i = threadIdx.x; i < np; i += blockDim.x) {
+        const double p = A.P[i] + A.e1[i];
+        A.P[i] = p;
+        dd += A.e1[i] * A.e1[i];
+        xx += p * p;
+    }
+    __shared__ double sd[256], sx[256];
+    sd[threadIdx.x] = dd;
+    sx[threadIdx.x] = xx;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) { sd[threadIdx.x] += sd[threadIdx.x + s]; sx[threadIdx.x] += sx[threadIdx.x + s]; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        A.its[0] += 1;
+        if (sqrt(sd[0]) <= A.tol * sqrt(sx[0])) *A.done = 1;
+    }
+}
+
+// x = 0, r = b, convergence flags cleared (start of refinement)
+__global__ void k_ir_start(IrStartArgs A) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < A.n; i += (long long)gridDim.x * blockDim.x) {
+        A.x[i] = 0.0;
+        A.r[i] = A.b[i];
+    }
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < A.nflags; i += (long long)gridDim.x * blockDim.x) {
+        A.conv[i] = 0;
+        A.relres[i] = 0.0;
+        A.sweeps[i] = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launch wrappers
+// ---------------------------------------------------------------------------
+static inline int grid_for(long long n, int block) {
+    long long g = (n + block - 1) / block;
+    if (g > 8192) g = 8192;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+void launch_prolong_p2(const ProlongArgs &a, hipStream_t st) {
+    long long n = (long long)(2 * a.Nh + 1) * (2 * a.Nh + 1);
+    hipLaunchKernelGGL(k_prolong_p2, dim3(grid_for(n, 256)), dim3(256), 0, st, a);
+}
+void launch_prolong_p1(const ProlongArgs &a, hipStream_t st) {
+    long long n = (long long)(a.Nh + 1) * (a.Nh + 1);
+    hipLaunchKernelGGL(k_prolong_p1, dim3(grid_for(n, 256)), dim3(256), 0, st, a);
+}
+void launch_porous_rhs(const PorousArgs &a, int nsys, hipStream_t st) {
+    hipLaunchKernelGGL(k_porous_rhs, dim3(nsys), dim3(256), 0, st, a);
+}
+void launch_porous_residual(const ResidualArgs &a, int nsys, hipStream_t st) {
+    hipLaunchKernelGGL(k_porous_residual, dim3(nsys, 3), dim3(256), 0, st, a);
+}
+void launch_porous_finalize(const FinalizeArgs &a, int nsys, hipStream_t st) {
+    hipLaunchKernelGGL(k_porous_finalize, dim3(nsys), dim3(256), 0, st, a);
+}
+template <typename T>
+void launch_porous_assemble(const AssembleArgs<T> &a, int nsys, hipStream_t st) {
+    hipLaunchKernelGGL(k_porous_assemble<T>, dim3(nsys), dim3(256), 0, st, a);
+}
+void launch_oseen_rhs(const OseenArgs &a, int nsys, hipStream_t st) {
+    hipLaunchKernelGGL(k_oseen_rhs, dim3(nsys), dim3(256), 0, st, a);
+}
+template <typename T>
+void launch_oseen_assemble(const OseenApplyArgs<T> &a, int nsys, hipStream_t st) {
+    hipLaunchKernelGGL((k_oseen_apply<T, 1>), dim3(nsys), dim3(256), 0, st, a);
+}
+void launch_oseen_residual(const OseenApplyArgs<double> &a, int nsys, hipStream_t st) {
+    hipLaunchKernelGGL((k_oseen_apply<double, 0>), dim3(nsys), dim3(256), 0, st, a);
+}
+void launch_oseen_finalize(const FinalizeArgs &a, int nsys, hipStream_t st) {
+    hipLaunchKernelGGL(k_oseen_finalize, dim3(nsys), dim3(256), 0, st, a);
+}
+
+template <typename T>
+bool launch_band_lu(const BandArgs<T> &a, int nsys, int maxbw, hipStream_t st) {
+    if (maxbw < 80) {
+        hipLaunchKernelGGL((k_band_lu<T, 16, 16, 5, 5>), dim3(nsys), dim3(256), 0, st, a);
+        return true;
+    }
+    if (maxbw < 160) {
+        if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_band_lu<T, 16, 16, 10, 10>), dim3(nsys), dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_band_lu<T, 32, 16, 5, 10>), dim3(nsys), dim3(512), 0, st, a);
+        return true;
+    }
+    return false;
+}
+
+template <typename T>
+bool launch_band_solve(const SolveArgs<T> &a, int nsys, int nrhs, int maxbw, hipStream_t st) {
+    dim3 g(nsys, nrhs);
+    if (maxbw <= 64) hipLaunchKernelGGL((k_band_solve<T, 1>), g, dim3(64), 0, st, a);
+    else if (maxbw <= 128) hipLaunchKernelGGL((k_band_solve<T, 2>), g, dim3(64), 0, st, a);
+    else if (maxbw <= 192) hipLaunchKernelGGL((k_band_solve<T, 3>), g, dim3(64), 0, st, a);
+    else if (maxbw <= 256) hipLaunchKernelGGL((k_band_solve<T, 4>), g, dim3(64), 0, st, a);
+    else return false;
+    return true;
+}
+
+void launch_merge(const MergeArgs &a, hipStream_t st) {
+    long long n = (long long)(2 * a.N + 1) * (2 * a.N + 1) + (long long)(a.N + 1) * (a.N + 1);
+    hipLaunchKernelGGL(k_merge, dim3(grid_for(n, 256)), dim3(256), 0, st, a);
+}
+void launch_init_corrections(const InitArgs &a, int nsys, hipStream_t st) {
+    hipLaunchKernelGGL(k_init_corrections, dim3(nsys), dim3(256), 0, st, a);
+}
+void launch_newton_update(const NewtonArgs &a, hipStream_t st) {
+    hipLaunchKernelGGL(k_newton_update, dim3(1), dim3(256), 0, st, a);
+}
+void launch_ir_start(const IrStartArgs &a, hipStream_t st) {
+    long long n = a.n > a.nflags ? a.n : a.nflags;
+    hipLaunchKernelGGL(k_ir_start, dim3(grid_for(n, 256)), dim3(256), 0, st, a);
+}
+
+template void launch_porous_assemble<float>(const AssembleArgs<float> &, int, hipStream_t);
+template void launch_porous_assemble<double>(const AssembleArgs<double> &, int, hipStream_t);
+template void launch_oseen_assemble<float>(const OseenApplyArgs<float> &, int, hipStream_t);
+template void launch_oseen_assemble<double>(const OseenApplyArgs<double> &, int, hipStream_t);
+template bool launch_band_lu<float>(const BandArgs<float> &, int, int, hipStream_t);
+template bool launch_band_lu<double>(const BandArgs<double> &, int, int, hipStream_t);
+template bool launch_band_solve<float>(const SolveArgs<float> &, int, int, int, hipStream_t);
+template bool launch_band_solve<double>(const SolveArgs<double> &, int, int, int, hipStream_t);
+
+}  // namespace lp

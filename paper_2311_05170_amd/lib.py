@@ -1,0 +1,225 @@
+"""ctypes binding of liblp.so (argument marshalling only: every step of the
+scheme runs in the library's HIP kernels).
+
+PyTorch supplies the HIP stream and, optionally, device memory through its
+caching allocator.  Importing this module loads the library and raises if it
+has not been built; there is no fallback implementation.
+"""
+import ctypes
+import os
+from ctypes import (CFUNCTYPE, POINTER, Structure, byref, c_char_p, c_double, c_int32, c_int64,
+                    c_size_t, c_void_p)
+
+import numpy as np
+# torch first: its bundled HIP runtime (same soname as the system one) must be
+# the one liblp.so binds to, so the library and torch share devices and streams
+import torch  # noqa: F401
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblp.so")
+
+LP_U, LP_P, LP_PF, LP_PFMI, LP_PM = range(5)
+LP_MERGED_FINE, LP_COARSE, LP_LOCAL = range(3)
+LP_FP64, LP_MIXED = 0, 1
+FIELD = {"u": LP_U, "p": LP_P, "pF": LP_PF, "pf": LP_PFMI, "pm": LP_PM}
+LEVEL = {"merged": LP_MERGED_FINE, "coarse": LP_COARSE, "local": LP_LOCAL}
+STATUS = {0: "LP_OK", 1: "LP_ERR_ARG", 2: "LP_ERR_STATE", 3: "LP_ERR_ALLOC", 4: "LP_ERR_DEVICE",
+          5: "LP_ERR_NOCONV", 6: "LP_ERR_UNSUPPORTED"}
+
+EXPORTS = ["lp_setup", "lp_coarse_step", "lp_local_step", "lp_get_size", "lp_get_solution",
+           "lp_get_stats", "lp_plan_query", "lp_destroy", "lp_last_error"]
+
+
+class LpMesh(Structure):
+    _fields_ = [("dim", c_int32), ("n_coarse", c_int32), ("refine", c_int32)]
+
+
+class LpPartition(Structure):
+    _fields_ = [("nsub", c_int32 * 2), ("overlap", c_int32), ("cuts", POINTER(c_int32))]
+
+
+class LpParams(Structure):
+    _fields_ = [("phi", c_double * 3), ("C", c_double * 3), ("k", c_double * 3),
+                ("mu_tilde", c_double), ("sigma", c_double), ("sigma_star", c_double),
+                ("rho", c_double), ("alpha", c_double), ("eta", c_double), ("nu", c_double),
+                ("dt", c_double)]
+
+
+class LpOptions(Structure):
+    _fields_ = [("problem", c_int32), ("precision", c_int32), ("convection", c_int32),
+                ("max_ir", c_int32), ("ir_tol", c_double), ("max_newton", c_int32),
+                ("newton_tol", c_double)]
+
+
+ALLOC_FN = CFUNCTYPE(c_void_p, c_size_t, c_void_p)
+FREE_FN = CFUNCTYPE(None, c_void_p, c_void_p)
+
+
+class LpAllocator(Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", c_void_p)]
+
+
+class LpStats(Structure):
+    _fields_ = [("step", c_int64), ("n_porous", c_int64), ("n_conduit", c_int64),
+                ("local_dofs", c_int64), ("max_bw", c_int64), ("newton_its", c_int32),
+                ("ir_sweeps", c_int32), ("ir_relres", c_double), ("flags", c_int32),
+                ("reserved", c_int32)]
+
+
+class LpError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+def load(path=LIB_PATH):
+    if not os.path.exists(path):
+        raise ImportError("liblp.so is not built (%s); run python -m paper_2311_05170_amd.build" % path)
+    lib = ctypes.CDLL(path)
+    lib.lp_setup.argtypes = [POINTER(LpMesh), POINTER(LpPartition), POINTER(LpParams), POINTER(LpOptions),
+                             POINTER(LpAllocator), c_void_p, POINTER(c_void_p)]
+    lib.lp_coarse_step.argtypes = [c_void_p, c_void_p]
+    lib.lp_local_step.argtypes = [c_void_p, c_void_p]
+    lib.lp_get_size.argtypes = [c_void_p, c_int32, c_int32, c_int32, POINTER(c_int64)]
+    lib.lp_get_solution.argtypes = [c_void_p, c_int32, c_int32, c_int32, POINTER(c_double), c_int64,
+                                    c_int32, c_void_p]
+    lib.lp_get_stats.argtypes = [c_void_p, POINTER(LpStats)]
+    lib.lp_plan_query.argtypes = [POINTER(LpMesh), POINTER(LpPartition), c_int32, c_int32,
+                                  POINTER(c_int64), c_int64, POINTER(c_int64)]
+    lib.lp_destroy.argtypes = [c_void_p]
+    lib.lp_destroy.restype = None
+    lib.lp_last_error.restype = c_char_p
+    for name in EXPORTS[:-2]:
+        getattr(lib, name).restype = c_int32
+    return lib
+
+
+_LIB = load()
+
+
+def _check(status):
+    if status != 0:
+        raise LpError(status, _LIB.lp_last_error().decode())
+
+
+def _structs(n_coarse, refine, nsub, overlap, cuts):
+    mesh = LpMesh(2, int(n_coarse), int(refine))
+    part = LpPartition()
+    part.nsub[0], part.nsub[1] = int(nsub[0]), int(nsub[1])
+    part.overlap = int(overlap)
+    keep = None
+    if cuts is not None:
+        keep = (c_int32 * len(cuts))(*[int(v) for v in cuts])
+        part.cuts = ctypes.cast(keep, POINTER(c_int32))
+    return mesh, part, keep
+
+
+def plan_query(n_coarse, refine, nsub, overlap, which, sub=0, cuts=None):
+    """Host-only partition tables (no device needed); see lp_plan_query."""
+    mesh, part, keep = _structs(n_coarse, refine, nsub, overlap, cuts)
+    need = c_int64(0)
+    _check(_LIB.lp_plan_query(byref(mesh), byref(part), which, sub, None, 0, byref(need)))
+    out = np.zeros(max(need.value, 1), dtype=np.int64)
+    _check(_LIB.lp_plan_query(byref(mesh), byref(part), which, sub,
+                              out.ctypes.data_as(POINTER(c_int64)), need.value, byref(need)))
+    return out[:need.value]
+
+
+def _params(prm, dt):
+    p = LpParams()
+    for i in range(3):
+        p.phi[i], p.C[i], p.k[i] = prm["phi"][i], prm["C"][i], prm["k"][i]
+    for key in ("mu_tilde", "sigma", "sigma_star", "rho", "alpha", "eta", "nu"):
+        setattr(p, key, float(prm[key]))
+    p.dt = float(dt)
+    return p
+
+
+class LocalParallel:
+    """One run of the local parallel scheme on the current HIP device.
+
+    precision: "mixed" (FP32 factorisations, FP64 refinement) or "fp64".
+    """
+
+    def __init__(self, n_coarse, refine, nsub, overlap, prm, dt, cuts=None, precision="mixed",
+                 convection=True, max_ir=8, ir_tol=None, max_newton=12, newton_tol=1e-13,
+                 torch_allocator=True):
+        import torch
+        self._torch = torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible")
+        mesh, part, keep = _structs(n_coarse, refine, nsub, overlap, cuts)
+        opt = LpOptions()
+        opt.problem = 0
+        opt.precision = LP_MIXED if precision == "mixed" else LP_FP64
+        opt.convection = 1 if convection else 0
+        opt.max_ir = int(max_ir)
+        opt.ir_tol = float(ir_tol if ir_tol is not None else (1e-10 if precision == "mixed" else 1e-12))
+        opt.max_newton = int(max_newton)
+        opt.newton_tol = float(newton_tol)
+        self._alloc = None
+        alloc_ptr = None
+        if torch_allocator:
+            def _a(nbytes, user):
+                return torch.cuda.caching_allocator_alloc(int(nbytes))
+
+            def _f(ptr, user):
+                torch.cuda.caching_allocator_delete(ptr)
+            self._cb = (ALLOC_FN(_a), FREE_FN(_f))
+            self._alloc = LpAllocator(self._cb[0], self._cb[1], None)
+            alloc_ptr = byref(self._alloc)
+        self.stream = torch.cuda.current_stream()
+        handle = c_void_p()
+        _check(_LIB.lp_setup(byref(mesh), byref(part), byref(_params(prm, dt)), byref(opt),
+                             alloc_ptr, c_void_p(self.stream.cuda_stream), byref(handle)))
+        self._h = handle
+        self.n_sub = 2 * nsub[0] * nsub[1]
+
+    def _s(self):
+        return c_void_p(self.stream.cuda_stream)
+
+    def coarse_step(self):
+        _check(_LIB.lp_coarse_step(self._h, self._s()))
+
+    def local_step(self):
+        _check(_LIB.lp_local_step(self._h, self._s()))
+
+    def step(self):
+        self.coarse_step()
+        self.local_step()
+
+    def size(self, field, level="merged", sub=0):
+        n = c_int64(0)
+        _check(_LIB.lp_get_size(self._h, FIELD[field], LEVEL[level], sub, byref(n)))
+        return n.value
+
+    def solution(self, field, level="merged", sub=0):
+        n = self.size(field, level, sub)
+        out = np.zeros(n, dtype=np.float64)
+        _check(_LIB.lp_get_solution(self._h, FIELD[field], LEVEL[level], sub,
+                                    out.ctypes.data_as(POINTER(c_double)), n, 0, self._s()))
+        return out
+
+    def solution_device(self, field, level="merged", sub=0):
+        torch = self._torch
+        n = self.size(field, level, sub)
+        out = torch.empty(n, dtype=torch.float64, device="cuda")
+        _check(_LIB.lp_get_solution(self._h, FIELD[field], LEVEL[level], sub,
+                                    ctypes.cast(out.data_ptr(), POINTER(c_double)), n, 1, self._s()))
+        return out
+
+    def stats(self):
+        s = LpStats()
+        _check(_LIB.lp_get_stats(self._h, byref(s)))
+        return {k: getattr(s, k) for k, _ in LpStats._fields_ if k != "reserved"}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _LIB.lp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
