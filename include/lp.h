@@ -172,6 +172,28 @@ lp_status lp_get_stats(lp_ctx *ctx, lp_stats *out);
 lp_status lp_plan_query(const lp_mesh *mesh, const lp_partition *part, int32_t which,
                         int32_t sub, int64_t *out, int64_t len, int64_t *needed);
 
+/* Stage timers: HIP events recorded on the caller's stream around the
+ * launches of the stages selected in `mask` (bit i = stage i below); 0 turns
+ * them off.  Setting a mask clears the accumulators.  lp_get_timing waits for
+ * the recorded events and returns, per stage, the summed milliseconds and the
+ * number of timed launches (arrays of length n <= LP_T_COUNT). */
+enum {
+    LP_T_PROLONG = 0,        /* coarse -> fine prolongation */
+    LP_T_POR_RHS = 1,        /* local porous right-hand sides */
+    LP_T_POR_SOLVE = 2,      /* local porous band solves (all refinement sweeps) */
+    LP_T_POR_RES = 3,        /* local porous FP64 residuals */
+    LP_T_OSE_RHS = 4,        /* local Oseen right-hand sides */
+    LP_T_OSE_ASM = 5,        /* local Oseen band assembly (incl. clearing the band) */
+    LP_T_OSE_LU = 6,         /* local Oseen band factorisation (one kernel launch) */
+    LP_T_OSE_SOLVE = 7,      /* local Oseen band solves (all sweeps) */
+    LP_T_OSE_RES = 8,        /* local Oseen FP64 residuals */
+    LP_T_MERGE = 9,          /* finalize + partition-of-unity merge */
+    LP_T_COARSE = 10,        /* the whole coarse step */
+    LP_T_COUNT = 11
+};
+lp_status lp_set_timing(lp_ctx *ctx, uint32_t mask);
+lp_status lp_get_timing(lp_ctx *ctx, double *ms, int64_t *launches, int32_t n);
+
 void lp_destroy(lp_ctx *ctx);
 
 const char *lp_last_error(void);

@@ -75,16 +75,38 @@ struct lp_ctx {
     double *band_cpor = nullptr, *band_cns = nullptr;
     double *b_por = nullptr, *x_por = nullptr, *r_por = nullptr;
     double *b_ose = nullptr, *x_ose = nullptr, *r_ose = nullptr;
-    void *y_por = nullptr, *y_ose = nullptr;
-    double *b_cp = nullptr, *x_cp = nullptr, *r_cp = nullptr, *y_cp = nullptr;
-    double *b_cn = nullptr, *x_cn = nullptr, *r_cn = nullptr, *y_cn = nullptr;
+    double *b_cp = nullptr, *x_cp = nullptr, *r_cp = nullptr;
+    double *b_cn = nullptr, *x_cn = nullptr, *r_cn = nullptr;
     int *conv_por = nullptr, *conv_ose = nullptr, *conv_cp = nullptr, *conv_cn = nullptr;
     double *rel_por = nullptr, *rel_ose = nullptr, *rel_cp = nullptr, *rel_cn = nullptr;
     int *sw_por = nullptr, *sw_ose = nullptr, *sw_cp = nullptr, *sw_cn = nullptr;
 
-    int maxbw_por = 0, maxbw_ose = 0;
+    int maxbw_por = 0, maxbw_ose = 0, maxn_por = 0, maxn_ose = 0;
+    double *lu_dummy = nullptr;        // sink of the factorisation's masked stores
+    double *consts = nullptr;          // [0.0 (8 bytes), 1.0 as double, 1.0f as float]: read by masked prefetches
+    template <typename T>
+    const T *const_one() const {
+        return sizeof(T) == 8 ? (const T *)(consts + 1) : (const T *)(consts + 2);
+    }
+
+    // stage timers (HIP events on the caller's stream)
+    uint32_t tmask = 0;
+    struct Rec { hipEvent_t a, b; int stage; };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    double tms[LP_T_COUNT] = {};
+    int64_t tcnt[LP_T_COUNT] = {};
+
+    hipEvent_t event() {
+        if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
 
     ~lp_ctx() {
+        for (auto &r : recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+        for (auto e : pool) (void)hipEventDestroy(e);
         for (void *p : owned) {
             if (has_alloc) alloc.free(p, alloc.user);
             else (void)hipFree(p);
@@ -119,6 +141,25 @@ namespace {
         lp_status _s = (expr);           \
         if (_s != LP_OK) return _s;      \
     } while (0)
+
+// brackets the launches of one stage with events when its bit is set
+struct StageTimer {
+    lp_ctx *c;
+    int stage;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    StageTimer(lp_ctx *c_, int stage_, hipStream_t st_) : c(c_), stage(stage_), st(st_) {
+        if (stage >= 0 && (c->tmask >> stage) & 1u) {
+            a = c->event();
+            if (a && hipEventRecord(a, st) != hipSuccess) a = nullptr;
+        }
+    }
+    ~StageTimer() {
+        if (!a) return;
+        hipEvent_t b = c->event();
+        if (b && hipEventRecord(b, st) == hipSuccess) c->recs.push_back({a, b, stage});
+    }
+};
 
 std::vector<lp::BandSys> lu_list(const std::vector<lp::SysDesc> &v, int nmat) {
     std::vector<lp::BandSys> out;
@@ -156,13 +197,17 @@ double time_at(const lp_ctx *c, int64_t step) { return (double)step * c->prm.dt;
 // run `sweeps` refinement sweeps (solve, then FP64 residual) on one batch
 template <typename T>
 lp_status refine_porous(lp_ctx *c, const lp::SysDesc *d_sys, int nsys, const lp::BandSys *d_sv, T *band, int maxbw,
-                        double *b, double *x, double *r, T *y, int *conv, double *rel, int *sw, long long ndof,
-                        int sweeps, double tol, hipStream_t st) {
+                        int maxn, double *b, double *x, double *r, int *conv, double *rel, int *sw, long long ndof,
+                        int sweeps, double tol, bool timed, hipStream_t st) {
     lp::IrStartArgs ia{x, r, b, ndof, conv, rel, sw, 3LL * nsys};
     lp::launch_ir_start(ia, st);
     for (int s = 0; s < sweeps; ++s) {
-        lp::SolveArgs<T> sa{d_sv, band, r, x, y, conv, 3, nullptr};
-        if (!lp::launch_band_solve<T>(sa, nsys, 3, maxbw, st)) return fail(LP_ERR_UNSUPPORTED, "bandwidth too large for the solve kernels");
+        {
+            StageTimer tm(c, timed ? LP_T_POR_SOLVE : -1, st);
+            lp::SolveArgs<T> sa{d_sv, band, r, x, conv, 3, nullptr, (const T *)c->consts, c->const_one<T>(), (const double *)c->consts};
+            if (!lp::launch_band_solve<T>(sa, nsys, 3, maxbw, maxn, st)) return fail(LP_ERR_UNSUPPORTED, "bandwidth too large for the solve kernels");
+        }
+        StageTimer tm(c, timed ? LP_T_POR_RES : -1, st);
         lp::ResidualArgs ra{d_sys, c->d_dof2, x, b, r, conv, rel, sw, tol, nullptr};
         lp::launch_porous_residual(ra, nsys, st);
     }
@@ -171,13 +216,18 @@ lp_status refine_porous(lp_ctx *c, const lp::SysDesc *d_sys, int nsys, const lp:
 
 template <typename T>
 lp_status refine_oseen(lp_ctx *c, const lp::SysDesc *d_sys, int nsys, const lp::BandSys *d_sv, T *band, int maxbw,
-                       const double *W1x, const double *W1y, double *b, double *x, double *r, T *y, int *conv,
-                       double *rel, int *sw, long long ndof, int sweeps, double tol, const int *skip, hipStream_t st) {
+                       int maxn, const double *W1x, const double *W1y, double *b, double *x, double *r, int *conv,
+                       double *rel, int *sw, long long ndof, int sweeps, double tol, const int *skip, bool timed,
+                       hipStream_t st) {
     lp::IrStartArgs ia{x, r, b, ndof, conv, rel, sw, (long long)nsys};
     lp::launch_ir_start(ia, st);
     for (int s = 0; s < sweeps; ++s) {
-        lp::SolveArgs<T> sa{d_sv, band, r, x, y, conv, 1, skip};
-        if (!lp::launch_band_solve<T>(sa, nsys, 1, maxbw, st)) return fail(LP_ERR_UNSUPPORTED, "bandwidth too large for the solve kernels");
+        {
+            StageTimer tm(c, timed ? LP_T_OSE_SOLVE : -1, st);
+            lp::SolveArgs<T> sa{d_sv, band, r, x, conv, 1, skip, (const T *)c->consts, c->const_one<T>(), (const double *)c->consts};
+            if (!lp::launch_band_solve<T>(sa, nsys, 1, maxbw, maxn, st)) return fail(LP_ERR_UNSUPPORTED, "bandwidth too large for the solve kernels");
+        }
+        StageTimer tm(c, timed ? LP_T_OSE_RES : -1, st);
         lp::OseenApplyArgs<double> ra{};
         ra.sys = d_sys; ra.cls2 = c->d_cls2; ra.dof2 = c->d_dof2; ra.dof1 = c->d_dof1;
         ra.W1[0] = W1x; ra.W1[1] = W1y;
@@ -192,7 +242,7 @@ template <typename T>
 lp_status factor_porous(lp_ctx *c, T *band, hipStream_t st) {
     lp::AssembleArgs<T> aa{c->d_por, c->d_dof2, band};
     lp::launch_porous_assemble<T>(aa, (int)c->P.por.size(), st);
-    lp::BandArgs<T> ba{c->d_lu_por, band, c->d_flags, nullptr};
+    lp::BandArgs<T> ba{c->d_lu_por, band, c->d_flags, nullptr, (T *)c->lu_dummy, (const T *)c->consts};
     if (!lp::launch_band_lu<T>(ba, 3 * (int)c->P.por.size(), c->maxbw_por, st))
         return fail(LP_ERR_UNSUPPORTED, "porous bandwidth exceeds the factorisation kernels");
     return LP_OK;
@@ -217,20 +267,30 @@ lp_status local_oseen(lp_ctx *c, hipStream_t st) {
     const double t1 = time_at(c, c->n + 1);
     oa.tf[0] = std::cos(t1); oa.tf[1] = std::sin(t1); oa.tf[2] = oa.tf[0] * oa.tf[0];
     oa.skip = nullptr;
-    lp::launch_oseen_rhs(oa, nsys, st);
+    {
+        StageTimer tm(c, LP_T_OSE_RHS, st);
+        lp::launch_oseen_rhs(oa, nsys, st);
+    }
     // operator linearised about Pi_h u_cH^{n+1}: assemble and factor
     T *band = (T *)c->band_ose;
-    HIPCHK(hipMemsetAsync(band, 0, (size_t)c->P.band_total_ose * sizeof(T), st));
-    lp::OseenApplyArgs<T> aa{};
-    aa.sys = c->d_ose; aa.cls2 = c->d_cls2; aa.dof2 = c->d_dof2; aa.dof1 = c->d_dof1;
-    aa.W1[0] = oa.W1[0]; aa.W1[1] = oa.W1[1]; aa.band = band;
-    lp::launch_oseen_assemble<T>(aa, nsys, st);
-    lp::BandArgs<T> ba{c->d_lu_ose, band, c->d_flags, nullptr};
-    if (!lp::launch_band_lu<T>(ba, nsys, c->maxbw_ose, st))
-        return fail(LP_ERR_UNSUPPORTED, "conduit bandwidth exceeds the factorisation kernels");
-    TRY(refine_oseen<T>(c, c->d_ose, nsys, c->d_sv_ose, band, c->maxbw_ose, oa.W1[0], oa.W1[1], c->b_ose, c->x_ose,
-                        c->r_ose, (T *)c->y_ose, c->conv_ose, c->rel_ose, c->sw_ose, c->P.dof_total_ose, c->opt.max_ir,
-                        c->opt.ir_tol, nullptr, st));
+    {
+        StageTimer tm(c, LP_T_OSE_ASM, st);
+        HIPCHK(hipMemsetAsync(band, 0, (size_t)c->P.band_total_ose * sizeof(T), st));
+        lp::OseenApplyArgs<T> aa{};
+        aa.sys = c->d_ose; aa.cls2 = c->d_cls2; aa.dof2 = c->d_dof2; aa.dof1 = c->d_dof1;
+        aa.W1[0] = oa.W1[0]; aa.W1[1] = oa.W1[1]; aa.band = band;
+        lp::launch_oseen_assemble<T>(aa, nsys, st);
+    }
+    {
+        StageTimer tm(c, LP_T_OSE_LU, st);
+        lp::BandArgs<T> ba{c->d_lu_ose, band, c->d_flags, nullptr, (T *)c->lu_dummy, (const T *)c->consts};
+        if (!lp::launch_band_lu<T>(ba, nsys, c->maxbw_ose, st))
+            return fail(LP_ERR_UNSUPPORTED, "conduit bandwidth exceeds the factorisation kernels");
+    }
+    TRY(refine_oseen<T>(c, c->d_ose, nsys, c->d_sv_ose, band, c->maxbw_ose, c->maxn_ose, oa.W1[0], oa.W1[1], c->b_ose,
+                        c->x_ose, c->r_ose, c->conv_ose, c->rel_ose, c->sw_ose, c->P.dof_total_ose, c->opt.max_ir,
+                        c->opt.ir_tol, nullptr, true, st));
+    StageTimer tm(c, LP_T_MERGE, st);
     lp::FinalizeArgs fa{c->d_ose, c->d_dof2, c->d_dof1, c->x_ose, c->e2[nw], c->e1[nw], nullptr};
     lp::launch_oseen_finalize(fa, nsys, st);
     return LP_OK;
@@ -254,10 +314,14 @@ lp_status local_porous(lp_ctx *c, hipStream_t st) {
     pa.e_old = c->e2[o]; pa.e_new = c->e2[nw]; pa.b = c->b_por;
     const double t1 = time_at(c, c->n + 1);
     pa.tf[0] = std::cos(t1); pa.tf[1] = std::sin(t1); pa.tf[2] = pa.tf[0] * pa.tf[0];
-    lp::launch_porous_rhs(pa, nsys, st);
-    TRY(refine_porous<T>(c, c->d_por, nsys, c->d_sv_por, (T *)c->band_por, c->maxbw_por, c->b_por, c->x_por, c->r_por,
-                         (T *)c->y_por, c->conv_por, c->rel_por, c->sw_por, c->P.dof_total_por, c->opt.max_ir,
-                         c->opt.ir_tol, st));
+    {
+        StageTimer tm(c, LP_T_POR_RHS, st);
+        lp::launch_porous_rhs(pa, nsys, st);
+    }
+    TRY(refine_porous<T>(c, c->d_por, nsys, c->d_sv_por, (T *)c->band_por, c->maxbw_por, c->maxn_por, c->b_por,
+                         c->x_por, c->r_por, c->conv_por, c->rel_por, c->sw_por, c->P.dof_total_por, c->opt.max_ir,
+                         c->opt.ir_tol, true, st));
+    StageTimer tm(c, LP_T_MERGE, st);
     lp::FinalizeArgs fa{c->d_por, c->d_dof2, c->d_dof1, c->x_por, c->e2[nw], nullptr, nullptr};
     lp::launch_porous_finalize(fa, nsys, st);
     return LP_OK;
@@ -361,8 +425,8 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     c->mixed = opt->precision == LP_MIXED;
     if (alloc && alloc->alloc && alloc->free) { c->alloc = *alloc; c->has_alloc = true; }
     lp::Plan &P = c->P;
-    for (const auto &s : P.por) c->maxbw_por = std::max(c->maxbw_por, s.bw);
-    for (const auto &s : P.ose) c->maxbw_ose = std::max(c->maxbw_ose, s.bw);
+    for (const auto &s : P.por) { c->maxbw_por = std::max(c->maxbw_por, s.bw); c->maxn_por = std::max(c->maxn_por, s.ndof); }
+    for (const auto &s : P.ose) { c->maxbw_ose = std::max(c->maxbw_ose, s.bw); c->maxn_ose = std::max(c->maxn_ose, s.ndof); }
     if (std::max(c->maxbw_por, c->maxbw_ose) >= 160 || std::max(P.cpor.bw, P.cns.bw) >= 160)
         return fail(LP_ERR_UNSUPPORTED, "local half-bandwidth " + std::to_string(std::max(c->maxbw_por, c->maxbw_ose)) +
                                             " exceeds the 159 supported by the band kernels");
@@ -454,22 +518,23 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
         else if (hipMalloc(&p, P.band_total_ose * tb + 256) != hipSuccess) p = nullptr;
         if (!p) return fail(LP_ERR_ALLOC, "conduit band allocation failed");
         c->owned.push_back(p); c->band_ose = p;
-        if (c->has_alloc) { p = c->alloc.alloc(P.dof_total_por * tb + 256, c->alloc.user); }
-        else if (hipMalloc(&p, P.dof_total_por * tb + 256) != hipSuccess) p = nullptr;
-        if (!p) return fail(LP_ERR_ALLOC, "scratch allocation failed");
-        c->owned.push_back(p); c->y_por = p;
-        if (c->has_alloc) { p = c->alloc.alloc(P.dof_total_ose * tb + 256, c->alloc.user); }
-        else if (hipMalloc(&p, P.dof_total_ose * tb + 256) != hipSuccess) p = nullptr;
-        if (!p) return fail(LP_ERR_ALLOC, "scratch allocation failed");
-        c->owned.push_back(p); c->y_ose = p;
+    }
+    {
+        const long long nlu = std::max<long long>(std::max<long long>(3LL * P.por.size(), (long long)P.ose.size()), 3);
+        TRY(c->dalloc(&c->lu_dummy, nlu * lp::LU_DUMMY_PER_SYS));
+        std::vector<double> k3(4, 0.0);
+        k3[1] = 1.0;
+        const float onef = 1.0f;
+        std::memcpy(&k3[2], &onef, sizeof(float));
+        TRY(c->upload(&c->consts, k3, st));
     }
     TRY(c->dalloc(&c->band_cpor, P.cband_por));
     TRY(c->dalloc(&c->band_cns, P.cband_ns));
     TRY(c->dalloc(&c->b_por, P.dof_total_por)); TRY(c->dalloc(&c->x_por, P.dof_total_por)); TRY(c->dalloc(&c->r_por, P.dof_total_por));
     TRY(c->dalloc(&c->b_ose, P.dof_total_ose)); TRY(c->dalloc(&c->x_ose, P.dof_total_ose)); TRY(c->dalloc(&c->r_ose, P.dof_total_ose));
     const long long ncp = 3LL * P.cpor.ndof, ncn = P.cns.ndof;
-    TRY(c->dalloc(&c->b_cp, ncp)); TRY(c->dalloc(&c->x_cp, ncp)); TRY(c->dalloc(&c->r_cp, ncp)); TRY(c->dalloc(&c->y_cp, ncp));
-    TRY(c->dalloc(&c->b_cn, ncn)); TRY(c->dalloc(&c->x_cn, ncn)); TRY(c->dalloc(&c->r_cn, ncn)); TRY(c->dalloc(&c->y_cn, ncn));
+    TRY(c->dalloc(&c->b_cp, ncp)); TRY(c->dalloc(&c->x_cp, ncp)); TRY(c->dalloc(&c->r_cp, ncp));
+    TRY(c->dalloc(&c->b_cn, ncn)); TRY(c->dalloc(&c->x_cn, ncn)); TRY(c->dalloc(&c->r_cn, ncn));
     const long long npf = 3LL * P.por.size(), nof = (long long)P.ose.size();
     TRY(c->dalloc(&c->conv_por, npf)); TRY(c->dalloc(&c->rel_por, npf)); TRY(c->dalloc(&c->sw_por, npf));
     TRY(c->dalloc(&c->conv_ose, nof)); TRY(c->dalloc(&c->rel_ose, nof)); TRY(c->dalloc(&c->sw_ose, nof));
@@ -507,7 +572,7 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     {
         lp::AssembleArgs<double> aa{c->d_cpor, c->d_dof2, c->band_cpor};
         lp::launch_porous_assemble<double>(aa, 1, st);
-        lp::BandArgs<double> ba{c->d_lu_cpor, c->band_cpor, c->d_flags, nullptr};
+        lp::BandArgs<double> ba{c->d_lu_cpor, c->band_cpor, c->d_flags, nullptr, (double *)c->lu_dummy, (const double *)c->consts};
         if (!lp::launch_band_lu<double>(ba, 3, P.cpor.bw, st)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
     }
     HIPCHK(hipGetLastError());
@@ -523,6 +588,7 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
     if (!c) return fail(LP_ERR_ARG, "NULL context");
     if (c->coarse_pending) return fail(LP_ERR_STATE, "lp_local_step must follow the previous lp_coarse_step");
     hipStream_t st = (hipStream_t)stream;
+    StageTimer ttot(c, LP_T_COARSE, st);
     const lp::Plan &P = c->P;
     const int o = c->ccur, nw = 1 - c->ccur;
     const long long nc2 = c->nc2;
@@ -541,8 +607,8 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
     pa.e_old = c->cP[o]; pa.e_new = c->cP[nw]; pa.b = c->b_cp;
     for (int k = 0; k < 3; ++k) pa.tf[k] = tf[k];
     lp::launch_porous_rhs(pa, 1, st);
-    TRY(refine_porous<double>(c, c->d_cpor, 1, c->d_sv_cpor, c->band_cpor, P.cpor.bw, c->b_cp, c->x_cp, c->r_cp, c->y_cp,
-                              c->conv_cp, c->rel_cp, c->sw_cp, 3LL * P.cpor.ndof, 2, 1e-13, st));
+    TRY(refine_porous<double>(c, c->d_cpor, 1, c->d_sv_cpor, c->band_cpor, P.cpor.bw, P.cpor.ndof, c->b_cp, c->x_cp,
+                              c->r_cp, c->conv_cp, c->rel_cp, c->sw_cp, 3LL * P.cpor.ndof, 2, 1e-13, false, st));
     lp::FinalizeArgs fa{c->d_cpor, c->d_dof2, c->d_dof1, c->x_cp, c->cP[nw], nullptr, nullptr};
     lp::launch_porous_finalize(fa, 1, st);
     // (5.4): Navier-Stokes by Newton from (u^n, p^n); each iteration solves the
@@ -570,10 +636,10 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
         aa.sys = c->d_cns; aa.cls2 = c->d_cls2; aa.dof2 = c->d_dof2; aa.dof1 = c->d_dof1;
         aa.W1[0] = oa.W1[0]; aa.W1[1] = oa.W1[1]; aa.band = c->band_cns; aa.skip = c->d_done;
         lp::launch_oseen_assemble<double>(aa, 1, st);
-        lp::BandArgs<double> ba{c->d_lu_cns, c->band_cns, c->d_flags, c->d_done};
+        lp::BandArgs<double> ba{c->d_lu_cns, c->band_cns, c->d_flags, c->d_done, (double *)c->lu_dummy, (const double *)c->consts};
         if (!lp::launch_band_lu<double>(ba, 1, P.cns.bw, st)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
-        TRY(refine_oseen<double>(c, c->d_cns, 1, c->d_sv_cns, c->band_cns, P.cns.bw, oa.W1[0], oa.W1[1], c->b_cn, c->x_cn,
-                                 c->r_cn, c->y_cn, c->conv_cn, c->rel_cn, c->sw_cn, P.cns.ndof, 2, 1e-14, c->d_done, st));
+        TRY(refine_oseen<double>(c, c->d_cns, 1, c->d_sv_cns, c->band_cns, P.cns.bw, P.cns.ndof, oa.W1[0], oa.W1[1],
+                                 c->b_cn, c->x_cn, c->r_cn, c->conv_cn, c->rel_cn, c->sw_cn, P.cns.ndof, 2, 1e-14, c->d_done, false, st));
         lp::FinalizeArgs fn{c->d_cns, c->d_dof2, c->d_dof1, c->x_cn, c->nwt_e, c->nwt_e1, c->d_done};
         lp::launch_oseen_finalize(fn, 1, st);
         lp::NewtonArgs na{c->cU[nw], c->cp[nw], c->nwt_e, c->nwt_e1, nc2, c->nc1, c->d_done, c->d_its, c->opt.newton_tol};
@@ -589,10 +655,14 @@ lp_status lp_local_step(lp_ctx *c, void *stream) {
     if (!c->coarse_pending) return fail(LP_ERR_STATE, "lp_local_step needs a preceding lp_coarse_step");
     hipStream_t st = (hipStream_t)stream;
     const int o = c->ccur, nw = 1 - c->ccur;
-    prolong_all(c, nw, o, st);
+    {
+        StageTimer tm(c, LP_T_PROLONG, st);
+        prolong_all(c, nw, o, st);
+    }
     if (c->mixed) { TRY(local_porous<float>(c, st)); TRY(local_oseen<float>(c, st)); }
     else { TRY(local_porous<double>(c, st)); TRY(local_oseen<double>(c, st)); }
     const int en = 1 - c->ecur;
+    StageTimer tm(c, LP_T_MERGE, st);
     for (int r = 0; r < 2; ++r) {
         lp::MergeArgs ma{};
         ma.sys = r == lp::POROUS ? c->d_por : c->d_ose;
@@ -703,6 +773,35 @@ lp_status lp_get_stats(lp_ctx *c, lp_stats *out) {
         out->ir_relres = std::max(out->ir_relres, rel[i]);
         if (c->n > 0 && !cv[i]) out->flags |= 1;
     }
+    return LP_OK;
+}
+
+lp_status lp_set_timing(lp_ctx *c, uint32_t mask) {
+    if (!c) return fail(LP_ERR_ARG, "NULL context");
+    for (auto &r : c->recs) {
+        (void)hipEventSynchronize(r.b);
+        c->pool.push_back(r.a);
+        c->pool.push_back(r.b);
+    }
+    c->recs.clear();
+    for (int i = 0; i < LP_T_COUNT; ++i) { c->tms[i] = 0.0; c->tcnt[i] = 0; }
+    c->tmask = mask;
+    return LP_OK;
+}
+
+lp_status lp_get_timing(lp_ctx *c, double *ms, int64_t *launches, int32_t n) {
+    if (!c || !ms || !launches || n < 0 || n > LP_T_COUNT) return fail(LP_ERR_ARG, "bad arguments");
+    for (auto &r : c->recs) {
+        HIPCHK(hipEventSynchronize(r.b));
+        float t = 0.0f;
+        HIPCHK(hipEventElapsedTime(&t, r.a, r.b));
+        c->tms[r.stage] += t;
+        c->tcnt[r.stage] += 1;
+        c->pool.push_back(r.a);
+        c->pool.push_back(r.b);
+    }
+    c->recs.clear();
+    for (int i = 0; i < n; ++i) { ms[i] = c->tms[i]; launches[i] = c->tcnt[i]; }
     return LP_OK;
 }
 

@@ -108,7 +108,11 @@ struct BandArgs {
     T *band;
     int *flags;
     const int *skip;
+    T *dummy;                     // LU_DUMMY_PER_SYS elements per system: sink for masked stores
+    const T *zero;                // a device zero, read by masked prefetches
 };
+
+constexpr long long LU_DUMMY_PER_SYS = 1024;
 
 template <typename T>
 struct SolveArgs {
@@ -116,10 +120,12 @@ struct SolveArgs {
     const T *band;
     const double *r;
     double *x;
-    T *y;
     const int *conv;
     int rhs_per_sys;
     const int *skip;
+    const T *zero;                // device constants read by masked prefetches
+    const T *one;
+    const double *zero64;
 };
 
 struct MergeArgs {
@@ -181,7 +187,7 @@ void launch_oseen_finalize(const FinalizeArgs &a, int nsys, hipStream_t st);
 template <typename T>
 bool launch_band_lu(const BandArgs<T> &a, int nsys, int maxbw, hipStream_t st);
 template <typename T>
-bool launch_band_solve(const SolveArgs<T> &a, int nsys, int nrhs, int maxbw, hipStream_t st);
+bool launch_band_solve(const SolveArgs<T> &a, int nsys, int nrhs, int maxbw, int maxn, hipStream_t st);
 void launch_merge(const MergeArgs &a, hipStream_t st);
 void launch_init_corrections(const InitArgs &a, int nsys, hipStream_t st);
 void launch_newton_update(const NewtonArgs &a, hipStream_t st);

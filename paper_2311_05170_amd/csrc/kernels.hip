@@ -601,86 +601,156 @@ __global__ __launch_bounds__(256) void k_oseen_finalize(FinalizeArgs F) {
 // rank-one update; block boundary rows/columns travel through LDS.  Factors
 // overwrite the column-major band (entry (i,j) at j*(2bw+1) + i - j + bw).
 // Requires WR, WC > bw.
+//
+// Memory traffic is kept off the critical path: every thread issues the same
+// number of global loads and stores per step (out-of-range lanes load a valid
+// address and discard it, or store into a private dummy slot), so the
+// compiler can wait on exactly the load issued D steps earlier instead of
+// draining the memory queue; barriers only order LDS.
 // ---------------------------------------------------------------------------
-template <typename T, int TR, int TC, int RB, int CB>
-__global__ __launch_bounds__(TR *TC) void k_band_lu(BandArgs<T> B) {
-    constexpr int WR = TR * RB, WC = TC * CB;
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Circular-window variant: the W x W window (W = TP*RB) never moves.  Row
+// slot rho holds the one window row congruent to rho mod W (owned by thread
+// row rho / RB, register rho % RB), column slots likewise.  At step k the
+// pivot row slot k mod W is output as U(k, .) and refilled with the entering
+// row k+W; the pivot column slot becomes L(., k) and is refilled with column
+// k+W.  Unrolling the step loop by RB steps makes the pivot register index
+// static, so only the pivot row and column (2W values) cross LDS per step;
+// entering values are prefetched RB steps ahead.  Requires W > bw.
+template <typename T, int TP, int RB>
+__global__ __launch_bounds__(TP *TP) void k_band_lu(BandArgs<T> B) {
+    constexpr int NT = TP * TP, W = TP * RB, U = RB, NE = 2 * W, NI = (NE + NT - 1) / NT;
     const BandSys Sy = B.sys[blockIdx.x];
     if (B.skip && *B.skip) return;
     const int n = Sy.n, bw = Sy.bw, ld = 2 * bw + 1;
     T *M = B.band + Sy.off;
-    __shared__ T srow[2][TR][WC];
-    __shared__ T scol[2][TC][WR];
-    const int tid = threadIdx.x, tr = tid / TC, tc = tid % TC;
-    auto ldb = [&](long long i, long long j) -> T {
-        if (i < 0 || j < 0 || i >= n || j >= n) return T(0);
-        const long long d = i - j;
-        if (d > bw || d < -bw) return T(0);
-        return M[j * ld + d + bw];
-    };
-    T a[RB][CB];
+    T *dummy = B.dummy + ((long long)blockIdx.x * NT + threadIdx.x) * NI;
+    __shared__ T ubuf[2][W];       // pivot row by column slot
+    __shared__ T lbuf[2][W];       // pivot column by row slot
+    __shared__ T ent[2][NE];       // entering row by column slot, then entering column by row slot
+    const int tid = threadIdx.x, tr = tid / TP, tc = tid % TP;
+    T a[RB][RB];
 #pragma unroll
     for (int i = 0; i < RB; ++i)
 #pragma unroll
-        for (int jj = 0; jj < CB; ++jj) a[i][jj] = ldb(tr * RB + i, tc * CB + jj);
+        for (int jj = 0; jj < RB; ++jj) {
+            const long long gi = tr * RB + i, gj = tc * RB + jj, d = gi - gj;
+            const bool ok = gi < n && gj < n && d <= bw && d >= -bw;
+            const T v = M[ok ? gj * ld + d + bw : 0];
+            a[i][jj] = ok ? v : T(0);
+        }
+    // Per-thread items q = tid + it*NT (q < 2W).  Fetch (for step kk): q < W is
+    // A(kk+W, kk+1+q), W <= q is A(kk+1+e, kk+W) with e = q - W; both at a fixed
+    // offset plus kk*ld, valid while kk < fend.  Output (step k): q < W is
+    // L(k+q, k) (q >= 1) from lbuf, W <= q is U(k, k+c) (c = q - W) from ubuf.
+    int foff[NI], fend[NI], soff[NI], send[NI], qq[NI];
+#pragma unroll
+    for (int it = 0; it < NI; ++it) {
+        const int q = tid + it * NT;
+        qq[it] = q < NE ? q : 0;
+        if (q < W) {
+            const int d = W - 1 - q;
+            foff[it] = (1 + q) * ld + d + bw;
+            fend[it] = (d <= bw) ? min(n - W, n - 1 - q) : 0;
+            soff[it] = q + bw;
+            send[it] = (q >= 1 && q <= bw) ? n - q : 0;
+        } else if (q < NE) {
+            const int e = q - W, d = 1 + e - W;
+            foff[it] = W * ld + d + bw;
+            fend[it] = (d >= -bw) ? min(n - 1 - e, n - W) : 0;
+            soff[it] = e * ld + bw - e;
+            send[it] = e <= bw ? n - e : 0;
+        } else {
+            foff[it] = soff[it] = 0;
+            fend[it] = send[it] = 0;
+        }
+    }
+    T fifo[U][NI];
+#pragma unroll
+    for (int s = 0; s < U; ++s)
+#pragma unroll
+        for (int it = 0; it < NI; ++it) fifo[s][it] = *(s < fend[it] ? M + (foff[it] + s * ld) : B.zero);
     int bad = 0;
-    for (int k = 0; k < n; ++k) {
-        const int buf = k & 1;
-        T in_row[CB], in_col[RB];
-        if (tr == TR - 1) {
+    int kw = 0;                                     // k0 mod W (a multiple of U)
+    for (int k0 = 0; k0 < n; k0 += U) {
 #pragma unroll
-            for (int jj = 0; jj < CB; ++jj) in_row[jj] = ldb((long long)k + WR, (long long)k + 1 + tc * CB + jj);
-        }
-        if (tc == TC - 1) {
+        for (int s = 0; s < U; ++s) {
+            const int k = k0 + s;
+            if (k >= n) break;
+            const int ps = s;                       // pivot register index (static)
+            const int kmod = kw + s;                // k mod W
+            const int ow = kmod / RB;               // owner thread row / column of the pivot slots
+            const bool orow = tr == ow, ocol = tc == ow;
+            const int buf = k & 1;
+            if (orow) {
 #pragma unroll
-            for (int i = 0; i < RB; ++i) in_col[i] = ldb((long long)k + 1 + tr * RB + i, (long long)k + WC);
-        }
-#pragma unroll
-        for (int jj = 0; jj < CB; ++jj) srow[buf][tr][tc * CB + jj] = a[0][jj];
-#pragma unroll
-        for (int i = 0; i < RB; ++i) scol[buf][tc][tr * RB + i] = a[i][0];
-        __syncthreads();
-        T piv = srow[buf][0][0];
-        if (!(fabs((double)piv) > 0.0) || !isfinite((double)piv)) { bad = 1; piv = T(1); }
-        const T inv = T(1) / piv;
-        // outputs: L column k and U row k
-        if (tc == 0) {
-#pragma unroll
-            for (int i = 0; i < RB; ++i) {
-                const int r = tr * RB + i;
-                if (r >= 1 && r <= bw && k + r < n) M[(long long)k * ld + r + bw] = a[i][0] * inv;
+                for (int jj = 0; jj < RB; ++jj) ubuf[buf][tc * RB + jj] = a[ps][jj];
             }
-        }
-        if (tr == 0) {
+            if (ocol) {
 #pragma unroll
-            for (int jj = 0; jj < CB; ++jj) {
-                const int c = tc * CB + jj;
-                if (c <= bw && k + c < n) M[(long long)(k + c) * ld + bw - c] = a[0][jj];
+                for (int i = 0; i < RB; ++i) lbuf[buf][tr * RB + i] = a[i][ps];
             }
-        }
-        T l[RB], u[CB];
+            // entering values of this step (fetched U steps ago) to their slots
 #pragma unroll
-        for (int i = 0; i < RB; ++i) {
-            const int r1 = tr * RB + i + 1;
-            l[i] = r1 < WR ? scol[buf][0][r1] * inv : T(0);
-        }
-#pragma unroll
-        for (int jj = 0; jj < CB; ++jj) {
-            const int c1 = tc * CB + jj + 1;
-            u[jj] = c1 < WC ? srow[buf][0][c1] : T(0);
-        }
-#pragma unroll
-        for (int i = 0; i < RB; ++i)
-#pragma unroll
-            for (int jj = 0; jj < CB; ++jj) {
-                T src;
-                if (i < RB - 1 && jj < CB - 1) src = a[i + 1][jj + 1];
-                else if (i == RB - 1 && jj < CB - 1) src = tr < TR - 1 ? srow[buf][tr + 1][tc * CB + jj + 1] : in_row[jj];
-                else if (i < RB - 1 && jj == CB - 1) src = tc < TC - 1 ? scol[buf][tc + 1][tr * RB + i + 1] : in_col[i];
-                else src = (tr < TR - 1 && tc < TC - 1) ? srow[buf][tr + 1][(tc + 1) * CB]
-                                                         : (tr == TR - 1 ? in_row[CB - 1] : in_col[RB - 1]);
-                a[i][jj] = src - l[i] * u[jj];
+            for (int it = 0; it < NI; ++it) {
+                const int q = tid + it * NT;
+                if (q < NE) {
+                    const int base = q < W ? 0 : W, o = q < W ? q : q - W;
+                    int sl = kmod + 1 + o;
+                    sl = sl >= W ? sl - W : sl;
+                    ent[buf][base + sl] = fifo[s][it];
+                }
             }
+            lds_barrier();
+            T piv = ubuf[buf][kmod];
+            if (!(fabs((double)piv) > 0.0) || !isfinite((double)piv)) { bad = 1; piv = T(1); }
+            const T inv = T(1) / piv;
+            const int kld = k * ld;
+#pragma unroll
+            for (int it = 0; it < NI; ++it) {
+                const bool isl = qq[it] < W;
+                const int o = isl ? qq[it] : qq[it] - W;
+                int sl = kmod + o;
+                sl = sl >= W ? sl - W : sl;
+                const T lv = lbuf[buf][sl] * inv;
+                const T uv = ubuf[buf][sl];
+                T *dst = k < send[it] ? M + (kld + soff[it]) : dummy + it;
+                *dst = isl ? lv : uv;
+            }
+            T l[RB], u[RB];
+#pragma unroll
+            for (int i = 0; i < RB; ++i) l[i] = lbuf[buf][tr * RB + i] * inv;
+#pragma unroll
+            for (int jj = 0; jj < RB; ++jj) u[jj] = ubuf[buf][tc * RB + jj];
+            T er[RB], ec[RB];
+            if (orow) {
+#pragma unroll
+                for (int jj = 0; jj < RB; ++jj) er[jj] = ent[buf][tc * RB + jj];
+            }
+            if (ocol) {
+#pragma unroll
+                for (int i = 0; i < RB; ++i) ec[i] = ent[buf][W + tr * RB + i];
+            }
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+#pragma unroll
+                for (int jj = 0; jj < RB; ++jj) {
+                    T v = a[i][jj] - l[i] * u[jj];
+                    if (i == ps) v = orow ? er[jj] : v;
+                    if (jj == ps) v = ocol ? ec[i] : v;
+                    a[i][jj] = v;
+                }
+            const int kf = k + U, kfl = kf * ld;
+#pragma unroll
+            for (int it = 0; it < NI; ++it) fifo[s][it] = *(kf < fend[it] ? M + (kfl + foff[it]) : B.zero);
+        }
+        kw += U;
+        kw = kw == W ? 0 : kw;
     }
     if (bad && tid == 0) atomicOr(B.flags, 4);
 }
@@ -705,7 +775,7 @@ __device__ __forceinline__ double wave_bcast<double>(double v, int lane) {
     return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
 }
 
-template <typename T, int NR>
+template <typename T, int NR, int D>
 __global__ __launch_bounds__(64) void k_band_solve(SolveArgs<T> A) {
     const int sysi = blockIdx.x, f = blockIdx.y;
     const BandSys Sy = A.sys[sysi];
@@ -713,84 +783,115 @@ __global__ __launch_bounds__(64) void k_band_solve(SolveArgs<T> A) {
     const int id = sysi * A.rhs_per_sys + f;
     if (A.skip && *A.skip) return;
     if (A.conv && A.conv[id]) return;
+    extern __shared__ unsigned char smem_raw[];
+    T *ys = reinterpret_cast<T *>(smem_raw);     // y, then the correction d, by row
     const int n = Sy.n, bw = Sy.bw, ld = 2 * bw + 1;
     const T *M = A.band + Sy.off + (long long)f * Sy.stride;
     const double *r = A.r + Sy.vec + (long long)f * n;
     double *x = A.x + Sy.vec + (long long)f * n;
-    T *y = A.y + Sy.vec + (long long)f * n;
     const int lane = threadIdx.x;
     const int W = bw > 0 ? bw : 1;
+    // Slot s = lane + 64 m of the circular window holds one row; the factor
+    // entry it needs at column kk is (row, kk), at band offset
+    // kk*(ld-1) + bw + row.  Entries are prefetched D columns ahead; rows that
+    // do not exist read the device zero.
     T win[NR];
-    int dist[NR];
-    // forward: window holds rows k..k+W-1 before step k, row i in slot i mod W
+    int row[NR], rpf[NR];
+    bool act[NR];
+    T cf[D][NR];
+    double rf[D];
+    // ---- forward: L y = r; before step k the window holds rows k..k+W-1 (row i in slot i mod W)
 #pragma unroll
     for (int m = 0; m < NR; ++m) {
-        const int s = lane + 64 * m;
-        win[m] = (s < W && s < n) ? (T)r[s] : T(0);
-        dist[m] = s == 0 ? W : s;          // row - k for the slot at k = 0 after finishing row 0
+        const int sl = lane + 64 * m;
+        act[m] = sl < W;
+        win[m] = (act[m] && sl < n) ? (T)r[sl] : T(0);
+        row[m] = sl;
+        rpf[m] = sl;
     }
-    int sk = 0;                             // slot of row k
-    for (int k = 0; k < n; ++k) {
-        const int ml = sk >> 6, ll = sk & 63;
-        T v = win[0];
-#pragma unroll
-        for (int m = 1; m < NR; ++m) if (m == ml) v = win[m];
-        const T yk = wave_bcast(v, ll);
-        if (lane == 0) y[k] = yk;
-        const T *col = M + (long long)k * ld + bw;
+    auto ffetch = [&](int kk, T *c, double &rv) {
+        const int base = kk * (ld - 1) + bw;
 #pragma unroll
         for (int m = 0; m < NR; ++m) {
-            const int s = lane + 64 * m;
-            if (s >= W) continue;
-            const int d = dist[m];                 // this slot holds row k + d (d in 1..W)
-            const long long row = (long long)k + d;
-            T cur = win[m];
-            if (s == sk) cur = (row < n) ? (T)r[row] : T(0);   // slot of row k takes row k + W
-            if (row < n && d <= bw) cur -= col[d] * yk;
-            win[m] = cur;
-            dist[m] = d == 1 ? W : d - 1;
+            if (rpf[m] == kk) rpf[m] += W;                 // the pivot slot takes row kk + W
+            const bool ok = act[m] && kk < n && rpf[m] < n;
+            c[m] = *(ok ? M + (base + rpf[m]) : A.zero);
         }
-        sk = sk + 1 == W ? 0 : sk + 1;
+        rv = *((kk + W < n) ? r + (kk + W) : A.zero64);
+    };
+#pragma unroll
+    for (int s = 0; s < D; ++s) ffetch(s, cf[s], rf[s]);
+    int sk = 0;
+    for (int k0 = 0; k0 < n; k0 += D) {
+#pragma unroll
+        for (int s = 0; s < D; ++s) {
+            const int k = k0 + s;
+            if (k >= n) break;
+            const int ml = sk >> 6, ll = sk & 63;
+            T v = win[0];
+#pragma unroll
+            for (int m = 1; m < NR; ++m) v = m == ml ? win[m] : v;
+            const T yk = wave_bcast(v, ll);
+            if (lane == 0) ys[k] = yk;
+#pragma unroll
+            for (int m = 0; m < NR; ++m) {
+                const bool piv = row[m] == k;
+                row[m] += piv ? W : 0;
+                win[m] = (piv ? (T)rf[s] : win[m]) - cf[s][m] * yk;
+            }
+            sk = sk + 1 == W ? 0 : sk + 1;
+            ffetch(k + D, cf[s], rf[s]);
+        }
     }
-    // y was written by lane 0 above; make it visible to every lane
-    __threadfence();
     __syncthreads();
-    // backward: U d = y, window holds rows k-W+1..k before step k (descending)
+    // ---- backward: U d = y; before step k (descending) the window holds rows k-W+1..k
     const int k0 = n - 1;
+    T uf[D];
 #pragma unroll
     for (int m = 0; m < NR; ++m) {
-        const int s = lane + 64 * m;
-        // row k0 - j sits in slot (k0 - j) mod W for j = 0..W-1
-        if (s < W) {
-            int j = ((k0 % W) - s + W) % W;        // distance below k0
-            const long long row = (long long)k0 - j;
-            win[m] = row >= 0 ? y[row] : T(0);
-            dist[m] = j == 0 ? W : j;
-        } else { win[m] = T(0); dist[m] = 1; }
+        const int sl = lane + 64 * m;
+        const int j = ((k0 % W) - sl + W) % W;            // distance below k0 of this slot's row
+        row[m] = k0 - j;
+        win[m] = (act[m] && row[m] >= 0) ? ys[row[m]] : T(0);
+        rpf[m] = row[m];
     }
-    sk = k0 % W;
-    for (int k = k0; k >= 0; --k) {
-        const int ml = sk >> 6, ll = sk & 63;
-        T v = win[0];
-#pragma unroll
-        for (int m = 1; m < NR; ++m) if (m == ml) v = win[m];
-        const T *col = M + (long long)k * ld + bw;
-        const T dk = wave_bcast(v, ll) / col[0];
-        if (lane == 0) x[k] += (double)dk;
+    auto bfetch = [&](int kk, T *c, T &dg) {
+        const int base = kk * (ld - 1) + bw;
 #pragma unroll
         for (int m = 0; m < NR; ++m) {
-            const int s = lane + 64 * m;
-            if (s >= W) continue;
-            const int d = dist[m];                 // this slot holds row k - d
-            const long long row = (long long)k - d;
-            T cur = win[m];
-            if (s == sk) cur = row >= 0 ? y[row] : T(0);
-            if (row >= 0 && d <= bw) cur -= col[-d] * dk;
-            win[m] = cur;
-            dist[m] = d == 1 ? W : d - 1;
+            if (rpf[m] == kk) rpf[m] -= W;
+            const bool ok = act[m] && kk >= 0 && rpf[m] >= 0;
+            c[m] = *(ok ? M + (base + rpf[m]) : A.zero);
         }
-        sk = sk == 0 ? W - 1 : sk - 1;
+        dg = *(kk >= 0 ? M + (kk * ld + bw) : A.one);
+    };
+#pragma unroll
+    for (int s = 0; s < D; ++s) bfetch(k0 - s, cf[s], uf[s]);
+    sk = k0 % W;
+    for (int kb = k0; kb >= 0; kb -= D) {
+#pragma unroll
+        for (int s = 0; s < D; ++s) {
+            const int k = kb - s;
+            if (k < 0) break;
+            const int ml = sk >> 6, ll = sk & 63;
+            T v = win[0];
+#pragma unroll
+            for (int m = 1; m < NR; ++m) v = m == ml ? win[m] : v;
+            const T dk = wave_bcast(v, ll) / uf[s];
+            const T enter = k - W >= 0 ? ys[k - W] : T(0);
+            if (lane == 0) ys[k] = dk;             // row k of y is consumed; keep d_k there
+#pragma unroll
+            for (int m = 0; m < NR; ++m) {
+                const bool piv = row[m] == k;
+                row[m] -= piv ? W : 0;
+                win[m] = (piv ? enter : win[m]) - cf[s][m] * dk;
+            }
+            sk = sk == 0 ? W - 1 : sk - 1;
+            bfetch(k - D, cf[s], uf[s]);
+        }
     }
+    __syncthreads();
+    for (int i = lane; i < n; i += 64) x[i] += (double)ys[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -939,24 +1040,26 @@ void launch_oseen_finalize(const FinalizeArgs &a, int nsys, hipStream_t st) {
 template <typename T>
 bool launch_band_lu(const BandArgs<T> &a, int nsys, int maxbw, hipStream_t st) {
     if (maxbw < 80) {
-        hipLaunchKernelGGL((k_band_lu<T, 16, 16, 5, 5>), dim3(nsys), dim3(256), 0, st, a);
+        hipLaunchKernelGGL((k_band_lu<T, 16, 5>), dim3(nsys), dim3(256), 0, st, a);
         return true;
     }
     if (maxbw < 160) {
-        if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_band_lu<T, 16, 16, 10, 10>), dim3(nsys), dim3(256), 0, st, a);
-        else hipLaunchKernelGGL((k_band_lu<T, 32, 16, 5, 10>), dim3(nsys), dim3(512), 0, st, a);
+        if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_band_lu<T, 32, 5>), dim3(nsys), dim3(1024), 0, st, a);
+        else hipLaunchKernelGGL((k_band_lu<T, 20, 8>), dim3(nsys), dim3(400), 0, st, a);
         return true;
     }
     return false;
 }
 
 template <typename T>
-bool launch_band_solve(const SolveArgs<T> &a, int nsys, int nrhs, int maxbw, hipStream_t st) {
+bool launch_band_solve(const SolveArgs<T> &a, int nsys, int nrhs, int maxbw, int maxn, hipStream_t st) {
     dim3 g(nsys, nrhs);
-    if (maxbw <= 64) hipLaunchKernelGGL((k_band_solve<T, 1>), g, dim3(64), 0, st, a);
-    else if (maxbw <= 128) hipLaunchKernelGGL((k_band_solve<T, 2>), g, dim3(64), 0, st, a);
-    else if (maxbw <= 192) hipLaunchKernelGGL((k_band_solve<T, 3>), g, dim3(64), 0, st, a);
-    else if (maxbw <= 256) hipLaunchKernelGGL((k_band_solve<T, 4>), g, dim3(64), 0, st, a);
+    const size_t sh = (size_t)maxn * sizeof(T);
+    if (sh > 160 * 1024) return false;
+    if (maxbw <= 64) hipLaunchKernelGGL((k_band_solve<T, 1, 8>), g, dim3(64), sh, st, a);
+    else if (maxbw <= 128) hipLaunchKernelGGL((k_band_solve<T, 2, 8>), g, dim3(64), sh, st, a);
+    else if (maxbw <= 192) hipLaunchKernelGGL((k_band_solve<T, 3, 8>), g, dim3(64), sh, st, a);
+    else if (maxbw <= 256) hipLaunchKernelGGL((k_band_solve<T, 4, 8>), g, dim3(64), sh, st, a);
     else return false;
     return true;
 }
@@ -982,7 +1085,7 @@ template void launch_oseen_assemble<float>(const OseenApplyArgs<float> &, int, h
 template void launch_oseen_assemble<double>(const OseenApplyArgs<double> &, int, hipStream_t);
 template bool launch_band_lu<float>(const BandArgs<float> &, int, int, hipStream_t);
 template bool launch_band_lu<double>(const BandArgs<double> &, int, int, hipStream_t);
-template bool launch_band_solve<float>(const SolveArgs<float> &, int, int, int, hipStream_t);
-template bool launch_band_solve<double>(const SolveArgs<double> &, int, int, int, hipStream_t);
+template bool launch_band_solve<float>(const SolveArgs<float> &, int, int, int, int, hipStream_t);
+template bool launch_band_solve<double>(const SolveArgs<double> &, int, int, int, int, hipStream_t);
 
 }  // namespace lp

@@ -142,7 +142,7 @@ class LocalParallel:
     """
 
     def __init__(self, n_coarse, refine, nsub, overlap, prm, dt, cuts=None, precision="mixed",
-                 convection=True, max_ir=8, ir_tol=None, max_newton=12, newton_tol=1e-13,
+                 convection=True, max_ir=8, ir_tol=None, max_newton=8, newton_tol=1e-13,
                  torch_allocator=True):
         import torch
         self._torch = torch
