@@ -10,7 +10,6 @@ dt = 0.01, seeded parameters).  Inputs are resident in HBM before timing.
 
 Prints ONE JSON line.  Fields beyond the driver's contract:
   fp64            the plain FP64 GPU path on the same workload
-  local_only      local-stage-only rates (the coarse step excluded)
   stages_ms       per-step stage split from a separate instrumented pass
   accuracy        max relative mass-norm error vs the CPU oracle after 2 steps
   roofline        dominant kernel (the local Oseen band factorisation)
@@ -29,12 +28,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "fine-grid local DoFs solved/s per time step, mixed vs FP64 at 1e-7 rel L2"
 WORKLOAD = "cfg2"
-STAGES = ["prolong", "por_rhs", "por_solve", "por_res", "ose_rhs", "ose_asm", "ose_lu", "ose_solve",
-          "ose_res", "merge", "coarse"]
-LP_T_OSE_LU = 6
-LP_T_COARSE = 10
 PEAK_VALU_TFLOPS = 78.6      # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (FP32 unpacked = FP64)
 CPU_STEPS = 2
+# the instantiation the launcher picks for half-bandwidths 128..159 in FP32
+LU_KERNEL = "k_band_lu<float,32,5> (local Oseen band LU, FP32)"
 
 
 def band_lu_flops(sizes):
@@ -57,38 +54,33 @@ def make(cfg, precision, max_ir):
 
 
 def timed_run(cfg, precision, steps, warmup, max_ir):
-    import ctypes
     import torch
     from paper_2311_05170_amd import lib
     g = make(cfg, precision, max_ir)
     for _ in range(warmup):
         g.step()
     torch.cuda.synchronize()
-    lib._LIB.lp_set_timing.argtypes = [ctypes.c_void_p, ctypes.c_uint32]
-    lib._LIB.lp_get_timing.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
-                                       ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
-    # timed region: only the dominant kernel (and the coarse step) is bracketed by events
-    lib._check(lib._LIB.lp_set_timing(g._h, (1 << LP_T_OSE_LU) | (1 << LP_T_COARSE)))
+    # timed region: only the dominant kernel is bracketed by HIP events, recorded
+    # on the stream it is launched on
+    g.set_timing(["ose_lu"])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         g.step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ms = (ctypes.c_double * 11)()
-    cnt = (ctypes.c_int64 * 11)()
-    lib._check(lib._LIB.lp_get_timing(g._h, ms, cnt, 11))
+    tm = g.timing()
     st = g.stats()
-    res = dict(ms_per_step=(t1 - t0) * 1e3 / steps,
-               lu_ms_avg=ms[LP_T_OSE_LU] / max(cnt[LP_T_OSE_LU], 1), lu_launches=int(cnt[LP_T_OSE_LU]),
-               coarse_ms_avg=ms[LP_T_COARSE] / max(cnt[LP_T_COARSE], 1), stats=st)
-    # separate instrumented pass for the stage split (not part of the timed value)
-    lib._check(lib._LIB.lp_set_timing(g._h, (1 << 11) - 1))
+    lu_ms, lu_n = tm["ose_lu"]
+    res = dict(ms_per_step=(t1 - t0) * 1e3 / steps, lu_ms_avg=lu_ms / max(lu_n, 1), lu_launches=lu_n, stats=st)
+    # separate instrumented pass for the stage split (not part of the timed value;
+    # the events serialise nothing but add launch gaps)
+    g.set_timing(lib.STAGES)
     nd = 3
     for _ in range(nd):
         g.step()
-    lib._check(lib._LIB.lp_get_timing(g._h, ms, cnt, 11))
-    res["stages_ms"] = {STAGES[i]: round(ms[i] / nd, 4) for i in range(11)}
+    tm = g.timing()
+    res["stages_ms"] = {k: round(v[0] / nd, 4) for k, v in tm.items()}
     g.close()
     return res
 
@@ -209,13 +201,10 @@ def main():
                    "local_dofs_per_step": L, "subdomains": int(len(sizes)),
                    "max_halfbandwidth": int(sizes[:, 1].max())},
         "fp64": {"value": rate(fp64["ms_per_step"]), "ms_per_step": fp64["ms_per_step"], "dtype": "f64"},
-        "local_only": {"mixed": rate(mixed["ms_per_step"] - mixed["coarse_ms_avg"]),
-                       "fp64": rate(fp64["ms_per_step"] - fp64["coarse_ms_avg"]),
-                       "coarse_ms": {"mixed": mixed["coarse_ms_avg"], "fp64": fp64["coarse_ms_avg"]}},
         "stages_ms": {"mixed": mixed["stages_ms"], "fp64": fp64["stages_ms"]},
         "refinement": {"mixed_sweeps": mixed["stats"]["ir_sweeps"], "mixed_relres": mixed["stats"]["ir_relres"],
                        "fp64_relres": fp64["stats"]["ir_relres"], "flags": [mixed["stats"]["flags"], fp64["stats"]["flags"]]},
-        "roofline": {"kernel": "k_band_lu<float,16,16,10,10> (local Oseen band LU, FP32)",
+        "roofline": {"kernel": LU_KERNEL,
                      "bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_VALU_TFLOPS, "traffic": traffic_for("k_band_lu", WORKLOAD),
                      "flops_per_launch": lu_flops, "avg_launch_ms": mixed["lu_ms_avg"],

@@ -104,7 +104,9 @@ typedef struct {
     int32_t convection;      /* 1: Navier-Stokes (default); 0: Stokes (drops b_N) */
     int32_t max_ir;          /* refinement sweeps cap (>= 1) */
     double ir_tol;           /* stop when ||b - A x|| <= ir_tol ||b|| per system */
-    int32_t max_newton;      /* coarse Newton iterations cap */
+    int32_t max_newton;      /* coarse nonlinear iterations cap: the first is a Newton step, the
+                                later ones reuse its Jacobian factors (chord steps with the exact
+                                residual); all stop at the same tolerance */
     double newton_tol;       /* stop when ||delta|| <= newton_tol ||x|| */
 } lp_options;
 

@@ -2,6 +2,7 @@
 // sequences of Algorithm 3 (Step 1 on T_H, Steps 3-4 on the subdomains).
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -39,7 +40,16 @@ struct lp_ctx {
     std::vector<void *> owned;
     int64_t n = 0;                 // completed local steps
     bool coarse_pending = false;
-    int ccur = 0;                  // coarse buffers holding t_n
+    // Coarse states live in a ring of three slots (time m in slot m % 3).  The
+    // coarse step runs on an internal stream: it never reads local results,
+    // so step m+1 of T_H can overlap the local stage of step m.  A slot is
+    // rewritten only after the local step that last reads it has finished.
+    static constexpr int RING = 3;
+    hipStream_t cstream = nullptr;
+    hipEvent_t ev_coarse[RING] = {}, ev_local[RING] = {};
+    // the local porous batch runs on its own stream beside the Oseen batch
+    hipStream_t pstream = nullptr;
+    hipEvent_t ev_pro = nullptr, ev_por = nullptr;
     int ecur = 0;                  // correction buffers holding e^n
     bool mixed = false;
 
@@ -59,7 +69,7 @@ struct lp_ctx {
     double *ld_f[5][3] = {}, *ld_c[5][3] = {};
 
     // coarse states (two time levels)
-    double *cP[2] = {}, *cU[2] = {}, *cp[2] = {};
+    double *cP[RING] = {}, *cU[RING] = {}, *cp[RING] = {};
     double *nwt_e = nullptr, *nwt_e1 = nullptr;
     int *d_done = nullptr, *d_its = nullptr, *d_flags = nullptr;
 
@@ -73,6 +83,8 @@ struct lp_ctx {
     // linear algebra storage
     void *band_por = nullptr, *band_ose = nullptr;        // float (mixed) or double
     double *band_cpor = nullptr, *band_cns = nullptr;
+    void *fac_por = nullptr, *fac_ose = nullptr;          // factors, same offsets as the bands
+    double *fac_cpor = nullptr, *fac_cns = nullptr;
     double *b_por = nullptr, *x_por = nullptr, *r_por = nullptr;
     double *b_ose = nullptr, *x_ose = nullptr, *r_ose = nullptr;
     double *b_cp = nullptr, *x_cp = nullptr, *r_cp = nullptr;
@@ -83,10 +95,14 @@ struct lp_ctx {
 
     int maxbw_por = 0, maxbw_ose = 0, maxn_por = 0, maxn_ose = 0;
     double *lu_dummy = nullptr;        // sink of the factorisation's masked stores
-    double *consts = nullptr;          // [0.0 (8 bytes), 1.0 as double, 1.0f as float]: read by masked prefetches
+    long long lu_dummy_coarse_off = 0;
+    int lu_variant = 0;                // tile shape of the local Oseen factorisation
+    // device constants read by masked loads: 512 zero doubles (a zero column
+    // for the solves), then 1.0 as double, then 1.0f as float
+    double *consts = nullptr;
     template <typename T>
     const T *const_one() const {
-        return sizeof(T) == 8 ? (const T *)(consts + 1) : (const T *)(consts + 2);
+        return sizeof(T) == 8 ? (const T *)(consts + 512) : (const T *)(consts + 513);
     }
 
     // stage timers (HIP events on the caller's stream)
@@ -105,6 +121,15 @@ struct lp_ctx {
     }
 
     ~lp_ctx() {
+        if (cstream) (void)hipStreamSynchronize(cstream);
+        for (int i = 0; i < RING; ++i) {
+            if (ev_coarse[i]) (void)hipEventDestroy(ev_coarse[i]);
+            if (ev_local[i]) (void)hipEventDestroy(ev_local[i]);
+        }
+        if (cstream) (void)hipStreamDestroy(cstream);
+        if (pstream) { (void)hipStreamSynchronize(pstream); (void)hipStreamDestroy(pstream); }
+        if (ev_pro) (void)hipEventDestroy(ev_pro);
+        if (ev_por) (void)hipEventDestroy(ev_por);
         for (auto &r : recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
         for (auto e : pool) (void)hipEventDestroy(e);
         for (void *p : owned) {
@@ -196,7 +221,7 @@ double time_at(const lp_ctx *c, int64_t step) { return (double)step * c->prm.dt;
 
 // run `sweeps` refinement sweeps (solve, then FP64 residual) on one batch
 template <typename T>
-lp_status refine_porous(lp_ctx *c, const lp::SysDesc *d_sys, int nsys, const lp::BandSys *d_sv, T *band, int maxbw,
+lp_status refine_porous(lp_ctx *c, const lp::SysDesc *d_sys, int nsys, const lp::BandSys *d_sv, const T *fac, int maxbw,
                         int maxn, double *b, double *x, double *r, int *conv, double *rel, int *sw, long long ndof,
                         int sweeps, double tol, bool timed, hipStream_t st) {
     lp::IrStartArgs ia{x, r, b, ndof, conv, rel, sw, 3LL * nsys};
@@ -204,7 +229,7 @@ lp_status refine_porous(lp_ctx *c, const lp::SysDesc *d_sys, int nsys, const lp:
     for (int s = 0; s < sweeps; ++s) {
         {
             StageTimer tm(c, timed ? LP_T_POR_SOLVE : -1, st);
-            lp::SolveArgs<T> sa{d_sv, band, r, x, conv, 3, nullptr, (const T *)c->consts, c->const_one<T>(), (const double *)c->consts};
+            lp::SolveArgs<T> sa{d_sv, fac, r, x, conv, 3, nullptr, (const T *)c->consts, c->const_one<T>(), (const double *)c->consts};
             if (!lp::launch_band_solve<T>(sa, nsys, 3, maxbw, maxn, st)) return fail(LP_ERR_UNSUPPORTED, "bandwidth too large for the solve kernels");
         }
         StageTimer tm(c, timed ? LP_T_POR_RES : -1, st);
@@ -215,7 +240,7 @@ lp_status refine_porous(lp_ctx *c, const lp::SysDesc *d_sys, int nsys, const lp:
 }
 
 template <typename T>
-lp_status refine_oseen(lp_ctx *c, const lp::SysDesc *d_sys, int nsys, const lp::BandSys *d_sv, T *band, int maxbw,
+lp_status refine_oseen(lp_ctx *c, const lp::SysDesc *d_sys, int nsys, const lp::BandSys *d_sv, const T *fac, int maxbw,
                        int maxn, const double *W1x, const double *W1y, double *b, double *x, double *r, int *conv,
                        double *rel, int *sw, long long ndof, int sweeps, double tol, const int *skip, bool timed,
                        hipStream_t st) {
@@ -224,7 +249,7 @@ lp_status refine_oseen(lp_ctx *c, const lp::SysDesc *d_sys, int nsys, const lp::
     for (int s = 0; s < sweeps; ++s) {
         {
             StageTimer tm(c, timed ? LP_T_OSE_SOLVE : -1, st);
-            lp::SolveArgs<T> sa{d_sv, band, r, x, conv, 1, skip, (const T *)c->consts, c->const_one<T>(), (const double *)c->consts};
+            lp::SolveArgs<T> sa{d_sv, fac, r, x, conv, 1, skip, (const T *)c->consts, c->const_one<T>(), (const double *)c->consts};
             if (!lp::launch_band_solve<T>(sa, nsys, 1, maxbw, maxn, st)) return fail(LP_ERR_UNSUPPORTED, "bandwidth too large for the solve kernels");
         }
         StageTimer tm(c, timed ? LP_T_OSE_RES : -1, st);
@@ -239,11 +264,11 @@ lp_status refine_oseen(lp_ctx *c, const lp::SysDesc *d_sys, int nsys, const lp::
 }
 
 template <typename T>
-lp_status factor_porous(lp_ctx *c, T *band, hipStream_t st) {
+lp_status factor_porous(lp_ctx *c, T *band, T *fac, hipStream_t st) {
     lp::AssembleArgs<T> aa{c->d_por, c->d_dof2, band};
     lp::launch_porous_assemble<T>(aa, (int)c->P.por.size(), st);
-    lp::BandArgs<T> ba{c->d_lu_por, band, c->d_flags, nullptr, (T *)c->lu_dummy, (const T *)c->consts};
-    if (!lp::launch_band_lu<T>(ba, 3 * (int)c->P.por.size(), c->maxbw_por, st))
+    lp::BandArgs<T> ba{c->d_lu_por, band, fac, c->d_flags, nullptr, (T *)c->lu_dummy, (const T *)c->consts};
+    if (!lp::launch_band_lu<T>(ba, 3 * (int)c->P.por.size(), c->maxbw_por, 0, st))
         return fail(LP_ERR_UNSUPPORTED, "porous bandwidth exceeds the factorisation kernels");
     return LP_OK;
 }
@@ -283,11 +308,11 @@ lp_status local_oseen(lp_ctx *c, hipStream_t st) {
     }
     {
         StageTimer tm(c, LP_T_OSE_LU, st);
-        lp::BandArgs<T> ba{c->d_lu_ose, band, c->d_flags, nullptr, (T *)c->lu_dummy, (const T *)c->consts};
-        if (!lp::launch_band_lu<T>(ba, nsys, c->maxbw_ose, st))
+        lp::BandArgs<T> ba{c->d_lu_ose, band, (T *)c->fac_ose, c->d_flags, nullptr, (T *)c->lu_dummy, (const T *)c->consts};
+        if (!lp::launch_band_lu<T>(ba, nsys, c->maxbw_ose, c->lu_variant, st))
             return fail(LP_ERR_UNSUPPORTED, "conduit bandwidth exceeds the factorisation kernels");
     }
-    TRY(refine_oseen<T>(c, c->d_ose, nsys, c->d_sv_ose, band, c->maxbw_ose, c->maxn_ose, oa.W1[0], oa.W1[1], c->b_ose,
+    TRY(refine_oseen<T>(c, c->d_ose, nsys, c->d_sv_ose, (const T *)c->fac_ose, c->maxbw_ose, c->maxn_ose, oa.W1[0], oa.W1[1], c->b_ose,
                         c->x_ose, c->r_ose, c->conv_ose, c->rel_ose, c->sw_ose, c->P.dof_total_ose, c->opt.max_ir,
                         c->opt.ir_tol, nullptr, true, st));
     StageTimer tm(c, LP_T_MERGE, st);
@@ -318,7 +343,7 @@ lp_status local_porous(lp_ctx *c, hipStream_t st) {
         StageTimer tm(c, LP_T_POR_RHS, st);
         lp::launch_porous_rhs(pa, nsys, st);
     }
-    TRY(refine_porous<T>(c, c->d_por, nsys, c->d_sv_por, (T *)c->band_por, c->maxbw_por, c->maxn_por, c->b_por,
+    TRY(refine_porous<T>(c, c->d_por, nsys, c->d_sv_por, (const T *)c->fac_por, c->maxbw_por, c->maxn_por, c->b_por,
                          c->x_por, c->r_por, c->conv_por, c->rel_por, c->sw_por, c->P.dof_total_por, c->opt.max_ir,
                          c->opt.ir_tol, true, st));
     StageTimer tm(c, LP_T_MERGE, st);
@@ -423,6 +448,7 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     c->prm = *prm;
     c->opt = *opt;
     c->mixed = opt->precision == LP_MIXED;
+    if (const char *v = std::getenv("LP_LU_VARIANT")) c->lu_variant = std::atoi(v);
     if (alloc && alloc->alloc && alloc->free) { c->alloc = *alloc; c->has_alloc = true; }
     lp::Plan &P = c->P;
     for (const auto &s : P.por) { c->maxbw_por = std::max(c->maxbw_por, s.bw); c->maxn_por = std::max(c->maxn_por, s.ndof); }
@@ -485,7 +511,7 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
         std::vector<double> P0(3 * c->nc2), U0(2 * c->nc2);
         for (int f = 0; f < 3; ++f) std::copy(exc[f].begin(), exc[f].end(), P0.begin() + f * c->nc2);
         for (int cc = 0; cc < 2; ++cc) std::copy(exc[3 + cc].begin(), exc[3 + cc].end(), U0.begin() + cc * c->nc2);
-        for (int l = 0; l < 2; ++l) {
+        for (int l = 0; l < lp_ctx::RING; ++l) {
             TRY(c->upload(&c->cP[l], P0, st));
             TRY(c->upload(&c->cU[l], U0, st));
             TRY(c->upload(&c->cp[l], exc[5], st));
@@ -518,18 +544,35 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
         else if (hipMalloc(&p, P.band_total_ose * tb + 256) != hipSuccess) p = nullptr;
         if (!p) return fail(LP_ERR_ALLOC, "conduit band allocation failed");
         c->owned.push_back(p); c->band_ose = p;
+        if (c->has_alloc) { p = c->alloc.alloc(P.band_total_por * tb + 256, c->alloc.user); }
+        else if (hipMalloc(&p, P.band_total_por * tb + 256) != hipSuccess) p = nullptr;
+        if (!p) return fail(LP_ERR_ALLOC, "porous factor allocation failed");
+        c->owned.push_back(p); c->fac_por = p;
+        HIPCHK(hipMemsetAsync(p, 0, P.band_total_por * tb, st));
+        if (c->has_alloc) { p = c->alloc.alloc(P.band_total_ose * tb + 256, c->alloc.user); }
+        else if (hipMalloc(&p, P.band_total_ose * tb + 256) != hipSuccess) p = nullptr;
+        if (!p) return fail(LP_ERR_ALLOC, "conduit factor allocation failed");
+        c->owned.push_back(p); c->fac_ose = p;
+        HIPCHK(hipMemsetAsync(p, 0, P.band_total_ose * tb, st));
     }
     {
         const long long nlu = std::max<long long>(std::max<long long>(3LL * P.por.size(), (long long)P.ose.size()), 3);
-        TRY(c->dalloc(&c->lu_dummy, nlu * lp::LU_DUMMY_PER_SYS));
-        std::vector<double> k3(4, 0.0);
-        k3[1] = 1.0;
+        // local factorisations use the first nlu sinks, the coarse ones (on the
+        // coarse stream) the next three
+        c->lu_dummy_coarse_off = nlu * lp::LU_DUMMY_PER_SYS;
+        TRY(c->dalloc(&c->lu_dummy, (nlu + 3) * lp::LU_DUMMY_PER_SYS));
+        std::vector<double> k3(514, 0.0);
+        k3[512] = 1.0;
         const float onef = 1.0f;
-        std::memcpy(&k3[2], &onef, sizeof(float));
+        std::memcpy(&k3[513], &onef, sizeof(float));
         TRY(c->upload(&c->consts, k3, st));
     }
     TRY(c->dalloc(&c->band_cpor, P.cband_por));
     TRY(c->dalloc(&c->band_cns, P.cband_ns));
+    TRY(c->dalloc(&c->fac_cpor, P.cband_por));
+    TRY(c->dalloc(&c->fac_cns, P.cband_ns));
+    HIPCHK(hipMemsetAsync(c->fac_cpor, 0, P.cband_por * sizeof(double), st));
+    HIPCHK(hipMemsetAsync(c->fac_cns, 0, P.cband_ns * sizeof(double), st));
     TRY(c->dalloc(&c->b_por, P.dof_total_por)); TRY(c->dalloc(&c->x_por, P.dof_total_por)); TRY(c->dalloc(&c->r_por, P.dof_total_por));
     TRY(c->dalloc(&c->b_ose, P.dof_total_ose)); TRY(c->dalloc(&c->x_ose, P.dof_total_ose)); TRY(c->dalloc(&c->r_ose, P.dof_total_ose));
     const long long ncp = 3LL * P.cpor.ndof, ncn = P.cns.ndof;
@@ -546,8 +589,15 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     HIPCHK(hipMemsetAsync(c->rel_por, 0, npf * sizeof(double), st));
 
     // initial corrections e_j^0 = I_h x_0 - Pi_h x_H^0
-    c->ccur = 0;
     c->ecur = 0;
+    HIPCHK(hipStreamCreateWithFlags(&c->cstream, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&c->pstream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&c->ev_pro, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&c->ev_por, hipEventDisableTiming));
+    for (int i = 0; i < lp_ctx::RING; ++i) {
+        HIPCHK(hipEventCreateWithFlags(&c->ev_coarse[i], hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&c->ev_local[i], hipEventDisableTiming));
+    }
     prolong_all(c.get(), 0, 0, st);
     {
         lp::InitArgs ia{};
@@ -563,17 +613,18 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     // constant porous matrices: local (precision of the run) and coarse (FP64)
     if (c->mixed) {
         HIPCHK(hipMemsetAsync(c->band_por, 0, P.band_total_por * sizeof(float), st));
-        TRY(factor_porous<float>(c.get(), (float *)c->band_por, st));
+        TRY(factor_porous<float>(c.get(), (float *)c->band_por, (float *)c->fac_por, st));
     } else {
         HIPCHK(hipMemsetAsync(c->band_por, 0, P.band_total_por * sizeof(double), st));
-        TRY(factor_porous<double>(c.get(), (double *)c->band_por, st));
+        TRY(factor_porous<double>(c.get(), (double *)c->band_por, (double *)c->fac_por, st));
     }
     HIPCHK(hipMemsetAsync(c->band_cpor, 0, P.cband_por * sizeof(double), st));
     {
         lp::AssembleArgs<double> aa{c->d_cpor, c->d_dof2, c->band_cpor};
         lp::launch_porous_assemble<double>(aa, 1, st);
-        lp::BandArgs<double> ba{c->d_lu_cpor, c->band_cpor, c->d_flags, nullptr, (double *)c->lu_dummy, (const double *)c->consts};
-        if (!lp::launch_band_lu<double>(ba, 3, P.cpor.bw, st)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
+        lp::BandArgs<double> ba{c->d_lu_cpor, c->band_cpor, c->fac_cpor, c->d_flags, nullptr, c->lu_dummy + c->lu_dummy_coarse_off,
+                                (const double *)c->consts};
+        if (!lp::launch_band_lu<double>(ba, 3, P.cpor.bw, 0, st)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));
@@ -587,10 +638,13 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
 lp_status lp_coarse_step(lp_ctx *c, void *stream) {
     if (!c) return fail(LP_ERR_ARG, "NULL context");
     if (c->coarse_pending) return fail(LP_ERR_STATE, "lp_local_step must follow the previous lp_coarse_step");
-    hipStream_t st = (hipStream_t)stream;
+    (void)stream;   // the coarse stage only touches internal state and runs on the context's own stream
+    hipStream_t st = c->cstream;
+    const int64_t m = c->n + 1;                       // time level produced
+    if (m >= 3) HIPCHK(hipStreamWaitEvent(st, c->ev_local[(m - 2) % lp_ctx::RING], 0));
     StageTimer ttot(c, LP_T_COARSE, st);
     const lp::Plan &P = c->P;
-    const int o = c->ccur, nw = 1 - c->ccur;
+    const int o = (int)((m - 1) % lp_ctx::RING), nw = (int)(m % lp_ctx::RING);
     const long long nc2 = c->nc2;
     const double t1 = time_at(c, c->n + 1);
     const double tf[3] = {std::cos(t1), std::sin(t1), std::cos(t1) * std::cos(t1)};
@@ -607,7 +661,7 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
     pa.e_old = c->cP[o]; pa.e_new = c->cP[nw]; pa.b = c->b_cp;
     for (int k = 0; k < 3; ++k) pa.tf[k] = tf[k];
     lp::launch_porous_rhs(pa, 1, st);
-    TRY(refine_porous<double>(c, c->d_cpor, 1, c->d_sv_cpor, c->band_cpor, P.cpor.bw, P.cpor.ndof, c->b_cp, c->x_cp,
+    TRY(refine_porous<double>(c, c->d_cpor, 1, c->d_sv_cpor, c->fac_cpor, P.cpor.bw, P.cpor.ndof, c->b_cp, c->x_cp,
                               c->r_cp, c->conv_cp, c->rel_cp, c->sw_cp, 3LL * P.cpor.ndof, 2, 1e-13, false, st));
     lp::FinalizeArgs fa{c->d_cpor, c->d_dof2, c->d_dof1, c->x_cp, c->cP[nw], nullptr, nullptr};
     lp::launch_porous_finalize(fa, 1, st);
@@ -631,21 +685,27 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
         for (int k = 0; k < 3; ++k) oa.tf[k] = tf[k];
         oa.skip = c->d_done;
         lp::launch_oseen_rhs(oa, 1, st);
-        HIPCHK(hipMemsetAsync(c->band_cns, 0, P.cband_ns * sizeof(double), st));
-        lp::OseenApplyArgs<double> aa{};
-        aa.sys = c->d_cns; aa.cls2 = c->d_cls2; aa.dof2 = c->d_dof2; aa.dof1 = c->d_dof1;
-        aa.W1[0] = oa.W1[0]; aa.W1[1] = oa.W1[1]; aa.band = c->band_cns; aa.skip = c->d_done;
-        lp::launch_oseen_assemble<double>(aa, 1, st);
-        lp::BandArgs<double> ba{c->d_lu_cns, c->band_cns, c->d_flags, c->d_done, (double *)c->lu_dummy, (const double *)c->consts};
-        if (!lp::launch_band_lu<double>(ba, 1, P.cns.bw, st)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
-        TRY(refine_oseen<double>(c, c->d_cns, 1, c->d_sv_cns, c->band_cns, P.cns.bw, P.cns.ndof, oa.W1[0], oa.W1[1],
-                                 c->b_cn, c->x_cn, c->r_cn, c->conv_cn, c->rel_cn, c->sw_cn, P.cns.ndof, 2, 1e-14, c->d_done, false, st));
+        if (it == 0) {
+            // Jacobian at the first iterate (u^n); later iterations reuse its
+            // factors, with residuals of the current Jacobian (chord steps)
+            HIPCHK(hipMemsetAsync(c->band_cns, 0, P.cband_ns * sizeof(double), st));
+            lp::OseenApplyArgs<double> aa{};
+            aa.sys = c->d_cns; aa.cls2 = c->d_cls2; aa.dof2 = c->d_dof2; aa.dof1 = c->d_dof1;
+            aa.W1[0] = oa.W1[0]; aa.W1[1] = oa.W1[1]; aa.band = c->band_cns; aa.skip = c->d_done;
+            lp::launch_oseen_assemble<double>(aa, 1, st);
+            lp::BandArgs<double> ba{c->d_lu_cns, c->band_cns, c->fac_cns, c->d_flags, c->d_done, c->lu_dummy + c->lu_dummy_coarse_off,
+                                    (const double *)c->consts};
+            if (!lp::launch_band_lu<double>(ba, 1, P.cns.bw, 0, st)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
+        }
+        TRY(refine_oseen<double>(c, c->d_cns, 1, c->d_sv_cns, c->fac_cns, P.cns.bw, P.cns.ndof, oa.W1[0], oa.W1[1],
+                                 c->b_cn, c->x_cn, c->r_cn, c->conv_cn, c->rel_cn, c->sw_cn, P.cns.ndof, 1, 1e-14, c->d_done, false, st));
         lp::FinalizeArgs fn{c->d_cns, c->d_dof2, c->d_dof1, c->x_cn, c->nwt_e, c->nwt_e1, c->d_done};
         lp::launch_oseen_finalize(fn, 1, st);
         lp::NewtonArgs na{c->cU[nw], c->cp[nw], c->nwt_e, c->nwt_e1, nc2, c->nc1, c->d_done, c->d_its, c->opt.newton_tol};
         lp::launch_newton_update(na, st);
     }
     HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(c->ev_coarse[nw], st));
     c->coarse_pending = true;
     return LP_OK;
 }
@@ -654,13 +714,19 @@ lp_status lp_local_step(lp_ctx *c, void *stream) {
     if (!c) return fail(LP_ERR_ARG, "NULL context");
     if (!c->coarse_pending) return fail(LP_ERR_STATE, "lp_local_step needs a preceding lp_coarse_step");
     hipStream_t st = (hipStream_t)stream;
-    const int o = c->ccur, nw = 1 - c->ccur;
+    const int64_t m = c->n + 1;
+    const int o = (int)((m - 1) % lp_ctx::RING), nw = (int)(m % lp_ctx::RING);
+    HIPCHK(hipStreamWaitEvent(st, c->ev_coarse[nw], 0));
     {
         StageTimer tm(c, LP_T_PROLONG, st);
         prolong_all(c, nw, o, st);
     }
-    if (c->mixed) { TRY(local_porous<float>(c, st)); TRY(local_oseen<float>(c, st)); }
-    else { TRY(local_porous<double>(c, st)); TRY(local_oseen<double>(c, st)); }
+    HIPCHK(hipEventRecord(c->ev_pro, st));
+    HIPCHK(hipStreamWaitEvent(c->pstream, c->ev_pro, 0));
+    if (c->mixed) { TRY(local_porous<float>(c, c->pstream)); TRY(local_oseen<float>(c, st)); }
+    else { TRY(local_porous<double>(c, c->pstream)); TRY(local_oseen<double>(c, st)); }
+    HIPCHK(hipEventRecord(c->ev_por, c->pstream));
+    HIPCHK(hipStreamWaitEvent(st, c->ev_por, 0));
     const int en = 1 - c->ecur;
     StageTimer tm(c, LP_T_MERGE, st);
     for (int r = 0; r < 2; ++r) {
@@ -682,8 +748,8 @@ lp_status lp_local_step(lp_ctx *c, void *stream) {
         lp::launch_merge(ma, st);
     }
     HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(c->ev_local[m % lp_ctx::RING], st));
     c->ecur = en;
-    c->ccur = nw;
     c->n += 1;
     c->coarse_pending = false;
     return LP_OK;
@@ -691,7 +757,7 @@ lp_status lp_local_step(lp_ctx *c, void *stream) {
 
 static lp_status locate(lp_ctx *c, int32_t field, int32_t level, int32_t sub, const double **ptr, int64_t *len) {
     if (field < LP_U || field > LP_PM) return fail(LP_ERR_ARG, "unknown field");
-    const int latest = c->coarse_pending ? 1 - c->ccur : c->ccur;
+    const int latest = (int)((c->coarse_pending ? c->n + 1 : c->n) % lp_ctx::RING);
     if (level == LP_MERGED_FINE) {
         if (field == LP_U) { *ptr = c->m_U; *len = 2 * c->nf2; }
         else if (field == LP_P) { *ptr = c->m_p; *len = c->nf1; }
@@ -734,6 +800,10 @@ lp_status lp_get_solution(lp_ctx *c, int32_t field, int32_t level, int32_t sub, 
     TRY(locate(c, field, level, sub, &p, &n));
     if (len < n) return fail(LP_ERR_ARG, "output buffer too short: need " + std::to_string(n));
     hipStream_t st = (hipStream_t)stream;
+    if (level == LP_COARSE) {
+        const int latest = (int)((c->coarse_pending ? c->n + 1 : c->n) % lp_ctx::RING);
+        if (c->coarse_pending || c->n > 0) HIPCHK(hipStreamWaitEvent(st, c->ev_coarse[latest], 0));
+    }
     if (out_is_device) {
         HIPCHK(hipMemcpyAsync(out, p, n * sizeof(double), hipMemcpyDeviceToDevice, st));
     } else {

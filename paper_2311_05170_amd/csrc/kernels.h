@@ -105,7 +105,8 @@ struct BandSys {
 template <typename T>
 struct BandArgs {
     const BandSys *sys;
-    T *band;
+    const T *band;                // input band (read only)
+    T *fac;                       // factors (same offsets as the band, slot-rotated layout)
     int *flags;
     const int *skip;
     T *dummy;                     // LU_DUMMY_PER_SYS elements per system: sink for masked stores
@@ -117,7 +118,7 @@ constexpr long long LU_DUMMY_PER_SYS = 1024;
 template <typename T>
 struct SolveArgs {
     const BandSys *sys;
-    const T *band;
+    const T *fac;
     const double *r;
     double *x;
     const int *conv;
@@ -185,7 +186,7 @@ void launch_oseen_assemble(const OseenApplyArgs<T> &a, int nsys, hipStream_t st)
 void launch_oseen_residual(const OseenApplyArgs<double> &a, int nsys, hipStream_t st);
 void launch_oseen_finalize(const FinalizeArgs &a, int nsys, hipStream_t st);
 template <typename T>
-bool launch_band_lu(const BandArgs<T> &a, int nsys, int maxbw, hipStream_t st);
+bool launch_band_lu(const BandArgs<T> &a, int nsys, int maxbw, int variant, hipStream_t st);
 template <typename T>
 bool launch_band_solve(const SolveArgs<T> &a, int nsys, int nrhs, int maxbw, int maxn, hipStream_t st);
 void launch_merge(const MergeArgs &a, hipStream_t st);

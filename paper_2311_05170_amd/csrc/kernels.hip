@@ -614,7 +614,7 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Circular-window variant: the W x W window (W = TP*RB) never moves.  Row
+// The W x W window (W = TP*RB) never moves.  Row
 // slot rho holds the one window row congruent to rho mod W (owned by thread
 // row rho / RB, register rho % RB), column slots likewise.  At step k the
 // pivot row slot k mod W is output as U(k, .) and refilled with the entering
@@ -628,7 +628,11 @@ __global__ __launch_bounds__(TP *TP) void k_band_lu(BandArgs<T> B) {
     const BandSys Sy = B.sys[blockIdx.x];
     if (B.skip && *B.skip) return;
     const int n = Sy.n, bw = Sy.bw, ld = 2 * bw + 1;
-    T *M = B.band + Sy.off;
+    const int ws = bw > 0 ? bw : 1;                 // slot count of the solve's window
+    const T *M = B.band + Sy.off;
+    // factors, slot-rotated for the solves: Lr[k*ws + (i mod ws)] = L(i, k),
+    // Ur[j*ws + (i mod ws)] = U(i, j) (i < j), Di[k] = 1 / U(k, k)
+    T *Lr = B.fac + Sy.off, *Ur = Lr + (long long)n * ws, *Di = Ur + (long long)n * ws;
     T *dummy = B.dummy + ((long long)blockIdx.x * NT + threadIdx.x) * NI;
     __shared__ T ubuf[2][W];       // pivot row by column slot
     __shared__ T lbuf[2][W];       // pivot column by row slot
@@ -647,8 +651,9 @@ __global__ __launch_bounds__(TP *TP) void k_band_lu(BandArgs<T> B) {
     // Per-thread items q = tid + it*NT (q < 2W).  Fetch (for step kk): q < W is
     // A(kk+W, kk+1+q), W <= q is A(kk+1+e, kk+W) with e = q - W; both at a fixed
     // offset plus kk*ld, valid while kk < fend.  Output (step k): q < W is
-    // L(k+q, k) (q >= 1) from lbuf, W <= q is U(k, k+c) (c = q - W) from ubuf.
-    int foff[NI], fend[NI], soff[NI], send[NI], qq[NI];
+    // L(k+q, k) (q >= 1) from lbuf, W <= q is U(k, k+c) (c = q - W) from ubuf;
+    // stores below a per-item bound, rotated slot tracked incrementally.
+    int foff[NI], fend[NI], soff[NI], send[NI], qq[NI], srot[NI];
 #pragma unroll
     for (int it = 0; it < NI; ++it) {
         const int q = tid + it * NT;
@@ -657,16 +662,18 @@ __global__ __launch_bounds__(TP *TP) void k_band_lu(BandArgs<T> B) {
             const int d = W - 1 - q;
             foff[it] = (1 + q) * ld + d + bw;
             fend[it] = (d <= bw) ? min(n - W, n - 1 - q) : 0;
-            soff[it] = q + bw;
+            soff[it] = 0;                              // Lr + k*ws + srot, srot = (k + q) mod ws
+            srot[it] = q % ws;
             send[it] = (q >= 1 && q <= bw) ? n - q : 0;
         } else if (q < NE) {
             const int e = q - W, d = 1 + e - W;
             foff[it] = W * ld + d + bw;
             fend[it] = (d >= -bw) ? min(n - 1 - e, n - W) : 0;
-            soff[it] = e * ld + bw - e;
+            soff[it] = e * ws;                         // Ur + (k+e)*ws + (k mod ws); e = 0 -> Di[k]
+            srot[it] = 0;
             send[it] = e <= bw ? n - e : 0;
         } else {
-            foff[it] = soff[it] = 0;
+            foff[it] = soff[it] = srot[it] = 0;
             fend[it] = send[it] = 0;
         }
     }
@@ -677,6 +684,7 @@ __global__ __launch_bounds__(TP *TP) void k_band_lu(BandArgs<T> B) {
         for (int it = 0; it < NI; ++it) fifo[s][it] = *(s < fend[it] ? M + (foff[it] + s * ld) : B.zero);
     int bad = 0;
     int kw = 0;                                     // k0 mod W (a multiple of U)
+    int kws = 0;                                    // k mod ws
     for (int k0 = 0; k0 < n; k0 += U) {
 #pragma unroll
         for (int s = 0; s < U; ++s) {
@@ -710,7 +718,7 @@ __global__ __launch_bounds__(TP *TP) void k_band_lu(BandArgs<T> B) {
             T piv = ubuf[buf][kmod];
             if (!(fabs((double)piv) > 0.0) || !isfinite((double)piv)) { bad = 1; piv = T(1); }
             const T inv = T(1) / piv;
-            const int kld = k * ld;
+            const int kws_ = k * ws;
 #pragma unroll
             for (int it = 0; it < NI; ++it) {
                 const bool isl = qq[it] < W;
@@ -718,10 +726,14 @@ __global__ __launch_bounds__(TP *TP) void k_band_lu(BandArgs<T> B) {
                 int sl = kmod + o;
                 sl = sl >= W ? sl - W : sl;
                 const T lv = lbuf[buf][sl] * inv;
-                const T uv = ubuf[buf][sl];
-                T *dst = k < send[it] ? M + (kld + soff[it]) : dummy + it;
+                const T uv = o == 0 ? inv : ubuf[buf][sl];
+                T *ldst = Lr + (kws_ + srot[it]);
+                T *udst = o == 0 ? Di + k : Ur + (kws_ + soff[it] + kws);
+                T *dst = k < send[it] ? (isl ? ldst : udst) : dummy + it;
                 *dst = isl ? lv : uv;
+                srot[it] = srot[it] + 1 == ws ? 0 : srot[it] + 1;
             }
+            kws = kws + 1 == ws ? 0 : kws + 1;
             T l[RB], u[RB];
 #pragma unroll
             for (int i = 0; i < RB; ++i) l[i] = lbuf[buf][tr * RB + i] * inv;
@@ -757,9 +769,11 @@ __global__ __launch_bounds__(TP *TP) void k_band_lu(BandArgs<T> B) {
 
 // ---------------------------------------------------------------------------
 // Band triangular solves, one wavefront per right-hand side: L y = r (unit
-// lower), U d = y, x += d.  The bw-row active window is spread circularly over
-// the 64 lanes (NR registers each); the finished entry is broadcast with
-// readlane and every lane updates its rows from a column of the factor.
+// lower), U d = y, x += d.  The window of ws = bw rows is spread circularly
+// over the lanes (row i in slot i mod ws, slot = lane + 64 m); the finished
+// entry is broadcast with readlane and every slot applies one factor entry.
+// With the slot-rotated factors each lane reads a fixed offset of the
+// current column, prefetched D columns ahead.
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ T wave_bcast(T v, int lane);
@@ -784,114 +798,98 @@ __global__ __launch_bounds__(64) void k_band_solve(SolveArgs<T> A) {
     if (A.skip && *A.skip) return;
     if (A.conv && A.conv[id]) return;
     extern __shared__ unsigned char smem_raw[];
-    T *ys = reinterpret_cast<T *>(smem_raw);     // y, then the correction d, by row
-    const int n = Sy.n, bw = Sy.bw, ld = 2 * bw + 1;
-    const T *M = A.band + Sy.off + (long long)f * Sy.stride;
-    const double *r = A.r + Sy.vec + (long long)f * n;
+    T *ys = reinterpret_cast<T *>(smem_raw);     // r, then y, then the correction d, by row
+    const int n = Sy.n, bw = Sy.bw;
+    const int ws = bw > 0 ? bw : 1;
+    const T *Lr = A.fac + Sy.off + (long long)f * Sy.stride;
+    const T *Ur = Lr + (long long)n * ws, *Di = Ur + (long long)n * ws;
+    const double *rg = A.r + Sy.vec + (long long)f * n;
     double *x = A.x + Sy.vec + (long long)f * n;
     const int lane = threadIdx.x;
-    const int W = bw > 0 ? bw : 1;
-    // Slot s = lane + 64 m of the circular window holds one row; the factor
-    // entry it needs at column kk is (row, kk), at band offset
-    // kk*(ld-1) + bw + row.  Entries are prefetched D columns ahead; rows that
-    // do not exist read the device zero.
-    T win[NR];
-    int row[NR], rpf[NR];
+    for (int i = lane; i < n; i += 64) ys[i] = (T)rg[i];
+    __syncthreads();
+    // lanes whose slot is beyond the window read entry 0 of the column: their
+    // window values are never extracted, so the loads stay unconditional
+    int lo[NR];
     bool act[NR];
-    T cf[D][NR];
-    double rf[D];
-    // ---- forward: L y = r; before step k the window holds rows k..k+W-1 (row i in slot i mod W)
 #pragma unroll
     for (int m = 0; m < NR; ++m) {
-        const int sl = lane + 64 * m;
-        act[m] = sl < W;
-        win[m] = (act[m] && sl < n) ? (T)r[sl] : T(0);
-        row[m] = sl;
-        rpf[m] = sl;
+        act[m] = lane + 64 * m < ws;
+        lo[m] = act[m] ? lane + 64 * m : 0;
     }
-    auto ffetch = [&](int kk, T *c, double &rv) {
-        const int base = kk * (ld - 1) + bw;
+    T win[NR], cf[D][NR];
+    // ---- forward: before step k the window holds rows k..k+ws-1 (row i in slot i mod ws)
 #pragma unroll
-        for (int m = 0; m < NR; ++m) {
-            if (rpf[m] == kk) rpf[m] += W;                 // the pivot slot takes row kk + W
-            const bool ok = act[m] && kk < n && rpf[m] < n;
-            c[m] = *(ok ? M + (base + rpf[m]) : A.zero);
-        }
-        rv = *((kk + W < n) ? r + (kk + W) : A.zero64);
-    };
+    for (int m = 0; m < NR; ++m) win[m] = (act[m] && lane + 64 * m < n) ? ys[lane + 64 * m] : T(0);
+#define LP_FCOL(KK, S)                                                                     \
+    do {                                                                                   \
+        const T *col = (KK) < n ? Lr + (long long)(KK) * ws : A.zero;                       \
+        _Pragma("unroll") for (int m = 0; m < NR; ++m) cf[S][m] = col[lo[m]];                \
+    } while (0)
 #pragma unroll
-    for (int s = 0; s < D; ++s) ffetch(s, cf[s], rf[s]);
+    for (int s = 0; s < D; ++s) LP_FCOL(s, s);
     int sk = 0;
     for (int k0 = 0; k0 < n; k0 += D) {
 #pragma unroll
         for (int s = 0; s < D; ++s) {
             const int k = k0 + s;
-            if (k >= n) break;
-            const int ml = sk >> 6, ll = sk & 63;
-            T v = win[0];
+            if (k < n) {
+                const int ml = sk >> 6, ll = sk & 63;
+                T v = win[0];
 #pragma unroll
-            for (int m = 1; m < NR; ++m) v = m == ml ? win[m] : v;
-            const T yk = wave_bcast(v, ll);
-            if (lane == 0) ys[k] = yk;
+                for (int m = 1; m < NR; ++m) v = m == ml ? win[m] : v;
+                const T yk = wave_bcast(v, ll);
+                const T enter = k + ws < n ? ys[k + ws] : T(0);
+                if (lane == 0) ys[k] = yk;
 #pragma unroll
-            for (int m = 0; m < NR; ++m) {
-                const bool piv = row[m] == k;
-                row[m] += piv ? W : 0;
-                win[m] = (piv ? (T)rf[s] : win[m]) - cf[s][m] * yk;
+                for (int m = 0; m < NR; ++m) win[m] = (lane + 64 * m == sk ? enter : win[m]) - cf[s][m] * yk;
+                sk = sk + 1 == ws ? 0 : sk + 1;
+                LP_FCOL(k + D, s);
             }
-            sk = sk + 1 == W ? 0 : sk + 1;
-            ffetch(k + D, cf[s], rf[s]);
         }
     }
     __syncthreads();
-    // ---- backward: U d = y; before step k (descending) the window holds rows k-W+1..k
+    // ---- backward: before step k (descending) the window holds rows k-ws+1..k
     const int k0 = n - 1;
     T uf[D];
 #pragma unroll
     for (int m = 0; m < NR; ++m) {
         const int sl = lane + 64 * m;
-        const int j = ((k0 % W) - sl + W) % W;            // distance below k0 of this slot's row
-        row[m] = k0 - j;
-        win[m] = (act[m] && row[m] >= 0) ? ys[row[m]] : T(0);
-        rpf[m] = row[m];
+        const int j = ((k0 % ws) - sl + ws) % ws;           // distance below k0 of this slot's row
+        win[m] = (act[m] && k0 - j >= 0) ? ys[k0 - j] : T(0);
     }
-    auto bfetch = [&](int kk, T *c, T &dg) {
-        const int base = kk * (ld - 1) + bw;
+#define LP_BCOL(KK, S)                                                                     \
+    do {                                                                                   \
+        const T *col = (KK) >= 0 ? Ur + (long long)(KK) * ws : A.zero;                      \
+        _Pragma("unroll") for (int m = 0; m < NR; ++m) cf[S][m] = col[lo[m]];                \
+        uf[S] = *((KK) >= 0 ? Di + (KK) : A.one);                                          \
+    } while (0)
 #pragma unroll
-        for (int m = 0; m < NR; ++m) {
-            if (rpf[m] == kk) rpf[m] -= W;
-            const bool ok = act[m] && kk >= 0 && rpf[m] >= 0;
-            c[m] = *(ok ? M + (base + rpf[m]) : A.zero);
-        }
-        dg = *(kk >= 0 ? M + (kk * ld + bw) : A.one);
-    };
-#pragma unroll
-    for (int s = 0; s < D; ++s) bfetch(k0 - s, cf[s], uf[s]);
-    sk = k0 % W;
+    for (int s = 0; s < D; ++s) LP_BCOL(k0 - s, s);
+    sk = k0 % ws;
     for (int kb = k0; kb >= 0; kb -= D) {
 #pragma unroll
         for (int s = 0; s < D; ++s) {
             const int k = kb - s;
-            if (k < 0) break;
-            const int ml = sk >> 6, ll = sk & 63;
-            T v = win[0];
+            if (k >= 0) {
+                const int ml = sk >> 6, ll = sk & 63;
+                T v = win[0];
 #pragma unroll
-            for (int m = 1; m < NR; ++m) v = m == ml ? win[m] : v;
-            const T dk = wave_bcast(v, ll) / uf[s];
-            const T enter = k - W >= 0 ? ys[k - W] : T(0);
-            if (lane == 0) ys[k] = dk;             // row k of y is consumed; keep d_k there
+                for (int m = 1; m < NR; ++m) v = m == ml ? win[m] : v;
+                const T dk = wave_bcast(v, ll) * uf[s];
+                const T enter = k - ws >= 0 ? ys[k - ws] : T(0);
+                if (lane == 0) ys[k] = dk;             // row k of y is consumed; keep d_k there
 #pragma unroll
-            for (int m = 0; m < NR; ++m) {
-                const bool piv = row[m] == k;
-                row[m] -= piv ? W : 0;
-                win[m] = (piv ? enter : win[m]) - cf[s][m] * dk;
+                for (int m = 0; m < NR; ++m) win[m] = (lane + 64 * m == sk ? enter : win[m]) - cf[s][m] * dk;
+                sk = sk == 0 ? ws - 1 : sk - 1;
+                LP_BCOL(k - D, s);
             }
-            sk = sk == 0 ? W - 1 : sk - 1;
-            bfetch(k - D, cf[s], uf[s]);
         }
     }
     __syncthreads();
     for (int i = lane; i < n; i += 64) x[i] += (double)ys[i];
+#undef LP_FCOL
+#undef LP_BCOL
 }
 
 // ---------------------------------------------------------------------------
@@ -1038,13 +1036,16 @@ void launch_oseen_finalize(const FinalizeArgs &a, int nsys, hipStream_t st) {
 }
 
 template <typename T>
-bool launch_band_lu(const BandArgs<T> &a, int nsys, int maxbw, hipStream_t st) {
-    if (maxbw < 80) {
-        hipLaunchKernelGGL((k_band_lu<T, 16, 5>), dim3(nsys), dim3(256), 0, st, a);
-        return true;
-    }
+bool launch_band_lu(const BandArgs<T> &a, int nsys, int maxbw, int variant, hipStream_t st) {
+    // smallest window W = TP * RB above the half-bandwidth; for W = 160 the
+    // variant picks 32 x 32 threads with 5 x 5 blocks (4) or 20 x 20 threads
+    // with 8 x 8 blocks (2); 0 = default per precision
+    if (maxbw < 80) { hipLaunchKernelGGL((k_band_lu<T, 16, 5>), dim3(nsys), dim3(256), 0, st, a); return true; }
+    if (maxbw < 96) { hipLaunchKernelGGL((k_band_lu<T, 16, 6>), dim3(nsys), dim3(256), 0, st, a); return true; }
+    if (maxbw < 128) { hipLaunchKernelGGL((k_band_lu<T, 16, 8>), dim3(nsys), dim3(256), 0, st, a); return true; }
     if (maxbw < 160) {
-        if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_band_lu<T, 32, 5>), dim3(nsys), dim3(1024), 0, st, a);
+        const bool wide = variant == 4 || (variant == 0 && sizeof(T) == 4);
+        if (wide) hipLaunchKernelGGL((k_band_lu<T, 32, 5>), dim3(nsys), dim3(1024), 0, st, a);
         else hipLaunchKernelGGL((k_band_lu<T, 20, 8>), dim3(nsys), dim3(400), 0, st, a);
         return true;
     }
@@ -1056,10 +1057,10 @@ bool launch_band_solve(const SolveArgs<T> &a, int nsys, int nrhs, int maxbw, int
     dim3 g(nsys, nrhs);
     const size_t sh = (size_t)maxn * sizeof(T);
     if (sh > 160 * 1024) return false;
-    if (maxbw <= 64) hipLaunchKernelGGL((k_band_solve<T, 1, 8>), g, dim3(64), sh, st, a);
-    else if (maxbw <= 128) hipLaunchKernelGGL((k_band_solve<T, 2, 8>), g, dim3(64), sh, st, a);
-    else if (maxbw <= 192) hipLaunchKernelGGL((k_band_solve<T, 3, 8>), g, dim3(64), sh, st, a);
-    else if (maxbw <= 256) hipLaunchKernelGGL((k_band_solve<T, 4, 8>), g, dim3(64), sh, st, a);
+    if (maxbw <= 64) hipLaunchKernelGGL((k_band_solve<T, 1, 16>), g, dim3(64), sh, st, a);
+    else if (maxbw <= 128) hipLaunchKernelGGL((k_band_solve<T, 2, 16>), g, dim3(64), sh, st, a);
+    else if (maxbw <= 192) hipLaunchKernelGGL((k_band_solve<T, 3, 16>), g, dim3(64), sh, st, a);
+    else if (maxbw <= 256) hipLaunchKernelGGL((k_band_solve<T, 4, 16>), g, dim3(64), sh, st, a);
     else return false;
     return true;
 }
@@ -1083,8 +1084,8 @@ template void launch_porous_assemble<float>(const AssembleArgs<float> &, int, hi
 template void launch_porous_assemble<double>(const AssembleArgs<double> &, int, hipStream_t);
 template void launch_oseen_assemble<float>(const OseenApplyArgs<float> &, int, hipStream_t);
 template void launch_oseen_assemble<double>(const OseenApplyArgs<double> &, int, hipStream_t);
-template bool launch_band_lu<float>(const BandArgs<float> &, int, int, hipStream_t);
-template bool launch_band_lu<double>(const BandArgs<double> &, int, int, hipStream_t);
+template bool launch_band_lu<float>(const BandArgs<float> &, int, int, int, hipStream_t);
+template bool launch_band_lu<double>(const BandArgs<double> &, int, int, int, hipStream_t);
 template bool launch_band_solve<float>(const SolveArgs<float> &, int, int, int, int, hipStream_t);
 template bool launch_band_solve<double>(const SolveArgs<double> &, int, int, int, int, hipStream_t);
 

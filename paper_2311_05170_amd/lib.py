@@ -27,7 +27,11 @@ STATUS = {0: "LP_OK", 1: "LP_ERR_ARG", 2: "LP_ERR_STATE", 3: "LP_ERR_ALLOC", 4: 
           5: "LP_ERR_NOCONV", 6: "LP_ERR_UNSUPPORTED"}
 
 EXPORTS = ["lp_setup", "lp_coarse_step", "lp_local_step", "lp_get_size", "lp_get_solution",
-           "lp_get_stats", "lp_plan_query", "lp_destroy", "lp_last_error"]
+           "lp_get_stats", "lp_plan_query", "lp_set_timing", "lp_get_timing", "lp_destroy",
+           "lp_last_error"]
+# stage timer indices (LP_T_* in lp.h)
+STAGES = ["prolong", "por_rhs", "por_solve", "por_res", "ose_rhs", "ose_asm", "ose_lu", "ose_solve",
+          "ose_res", "merge", "coarse"]
 
 
 class LpMesh(Structure):
@@ -86,6 +90,8 @@ def load(path=LIB_PATH):
     lib.lp_get_stats.argtypes = [c_void_p, POINTER(LpStats)]
     lib.lp_plan_query.argtypes = [POINTER(LpMesh), POINTER(LpPartition), c_int32, c_int32,
                                   POINTER(c_int64), c_int64, POINTER(c_int64)]
+    lib.lp_set_timing.argtypes = [c_void_p, ctypes.c_uint32]
+    lib.lp_get_timing.argtypes = [c_void_p, POINTER(c_double), POINTER(c_int64), c_int32]
     lib.lp_destroy.argtypes = [c_void_p]
     lib.lp_destroy.restype = None
     lib.lp_last_error.restype = c_char_p
@@ -142,7 +148,7 @@ class LocalParallel:
     """
 
     def __init__(self, n_coarse, refine, nsub, overlap, prm, dt, cuts=None, precision="mixed",
-                 convection=True, max_ir=8, ir_tol=None, max_newton=8, newton_tol=1e-13,
+                 convection=True, max_ir=8, ir_tol=None, max_newton=16, newton_tol=1e-13,
                  torch_allocator=True):
         import torch
         self._torch = torch
@@ -212,6 +218,20 @@ class LocalParallel:
         s = LpStats()
         _check(_LIB.lp_get_stats(self._h, byref(s)))
         return {k: getattr(s, k) for k, _ in LpStats._fields_ if k != "reserved"}
+
+    def set_timing(self, stages):
+        """Turn the stage timers on for the named stages (empty = off); clears them."""
+        mask = 0
+        for name in stages:
+            mask |= 1 << STAGES.index(name)
+        _check(_LIB.lp_set_timing(self._h, mask))
+
+    def timing(self):
+        """{stage: (summed ms, timed launches)} since the last set_timing."""
+        ms = (c_double * len(STAGES))()
+        cnt = (c_int64 * len(STAGES))()
+        _check(_LIB.lp_get_timing(self._h, ms, cnt, len(STAGES)))
+        return {STAGES[i]: (ms[i], int(cnt[i])) for i in range(len(STAGES))}
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
