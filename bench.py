@@ -129,6 +129,20 @@ def accuracy(cfg, ref_path):
     return out
 
 
+def calibrate_copy(n=1 << 26, reps=3):
+    """A device-to-device copy of n FP32 values (reads and writes 4 n bytes per
+    launch): the yardstick that converts the FETCH_SIZE / WRITE_SIZE counters
+    into HBM bytes."""
+    import torch
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": reps}), flush=True)
+
+
 def traffic_for(kernel, workload):
     """HBM bytes per launch from the committed counter summary, if it was taken
     on the current kernel source."""
@@ -154,9 +168,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-leg", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of known size (HBM counter calibration)")
     args = ap.parse_args()
     if args.cpu_leg:
         cpu_leg(args.cpu_leg)
+        return
+    if args.calibrate_copy:
+        calibrate_copy()
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the local stage needs no communication while "
