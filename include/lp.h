@@ -140,8 +140,12 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
                    const lp_options *opt, const lp_allocator *alloc, void *stream,
                    lp_ctx **out);
 
-/* Algorithm 3 Step 1 for t_n -> t_{n+1} on T_H (FP64).  LP_ERR_STATE if the
- * previous coarse step has not been followed by lp_local_step. */
+/* Algorithm 3 Step 1 for t_n -> t_{n+1} on T_H (FP64).  The coarse step runs
+ * on an internal stream (it never reads local results); the local Oseen
+ * operators of Step 3, which depend only on u_cH^{n+1}, are assembled and
+ * factored right after it on a second internal stream, so they overlap the
+ * local solves of the previous step.  LP_ERR_STATE if the previous coarse step
+ * has not been followed by lp_local_step. */
 lp_status lp_coarse_step(lp_ctx *ctx, void *stream);
 
 /* Algorithm 3 Steps 3-4 for t_{n+1}: prolongation, local right-hand sides,
@@ -174,8 +178,10 @@ lp_status lp_get_stats(lp_ctx *ctx, lp_stats *out);
 lp_status lp_plan_query(const lp_mesh *mesh, const lp_partition *part, int32_t which,
                         int32_t sub, int64_t *out, int64_t len, int64_t *needed);
 
-/* Stage timers: HIP events recorded on the caller's stream around the
- * launches of the stages selected in `mask` (bit i = stage i below); 0 turns
+/* Stage timers: HIP events recorded around the launches of the stages
+ * selected in `mask`, on the stream each stage runs on (bit i = stage i below;
+ * the coarse step, the porous batch and the Oseen assembly and factorisation
+ * run on the context's internal streams, the rest on the caller's); 0 turns
  * them off.  Setting a mask clears the accumulators.  lp_get_timing waits for
  * the recorded events and returns, per stage, the summed milliseconds and the
  * number of timed launches (arrays of length n <= LP_T_COUNT). */
@@ -185,7 +191,7 @@ enum {
     LP_T_POR_SOLVE = 2,      /* local porous band solves (all refinement sweeps) */
     LP_T_POR_RES = 3,        /* local porous FP64 residuals */
     LP_T_OSE_RHS = 4,        /* local Oseen right-hand sides */
-    LP_T_OSE_ASM = 5,        /* local Oseen band assembly (incl. clearing the band) */
+    LP_T_OSE_ASM = 5,        /* local Oseen band assembly (incl. prolonging u_cH and clearing the band) */
     LP_T_OSE_LU = 6,         /* local Oseen band factorisation (one kernel launch) */
     LP_T_OSE_SOLVE = 7,      /* local Oseen band solves (all sweeps) */
     LP_T_OSE_RES = 8,        /* local Oseen FP64 residuals */

@@ -50,6 +50,12 @@ struct lp_ctx {
     // the local porous batch runs on its own stream beside the Oseen batch
     hipStream_t pstream = nullptr;
     hipEvent_t ev_pro = nullptr, ev_por = nullptr;
+    // The local Oseen operator of step m depends only on u_cH^m, so its
+    // assembly and factorisation run on a third stream as soon as coarse step
+    // m is done, overlapping the solves of step m-1.  Factors of step m go to
+    // slot m % 2.
+    hipStream_t fstream = nullptr;
+    hipEvent_t ev_fac[2] = {};
     int ecur = 0;                  // correction buffers holding e^n
     bool mixed = false;
 
@@ -83,7 +89,8 @@ struct lp_ctx {
     // linear algebra storage
     void *band_por = nullptr, *band_ose = nullptr;        // float (mixed) or double
     double *band_cpor = nullptr, *band_cns = nullptr;
-    void *fac_por = nullptr, *fac_ose = nullptr;          // factors, same offsets as the bands
+    void *fac_por = nullptr, *fac_ose[2] = {};            // factors, same offsets as the bands
+    double *pro_Uf = nullptr;                            // u_cH^m prolonged for the factor stream
     double *fac_cpor = nullptr, *fac_cns = nullptr;
     double *b_por = nullptr, *x_por = nullptr, *r_por = nullptr;
     double *b_ose = nullptr, *x_ose = nullptr, *r_ose = nullptr;
@@ -128,6 +135,9 @@ struct lp_ctx {
         }
         if (cstream) (void)hipStreamDestroy(cstream);
         if (pstream) { (void)hipStreamSynchronize(pstream); (void)hipStreamDestroy(pstream); }
+        if (fstream) { (void)hipStreamSynchronize(fstream); (void)hipStreamDestroy(fstream); }
+        for (int i = 0; i < 2; ++i)
+            if (ev_fac[i]) (void)hipEventDestroy(ev_fac[i]);
         if (ev_pro) (void)hipEventDestroy(ev_pro);
         if (ev_por) (void)hipEventDestroy(ev_por);
         for (auto &r : recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
@@ -296,28 +306,49 @@ lp_status local_oseen(lp_ctx *c, hipStream_t st) {
         StageTimer tm(c, LP_T_OSE_RHS, st);
         lp::launch_oseen_rhs(oa, nsys, st);
     }
-    // operator linearised about Pi_h u_cH^{n+1}: assemble and factor
-    T *band = (T *)c->band_ose;
-    {
-        StageTimer tm(c, LP_T_OSE_ASM, st);
-        HIPCHK(hipMemsetAsync(band, 0, (size_t)c->P.band_total_ose * sizeof(T), st));
-        lp::OseenApplyArgs<T> aa{};
-        aa.sys = c->d_ose; aa.cls2 = c->d_cls2; aa.dof2 = c->d_dof2; aa.dof1 = c->d_dof1;
-        aa.W1[0] = oa.W1[0]; aa.W1[1] = oa.W1[1]; aa.band = band;
-        lp::launch_oseen_assemble<T>(aa, nsys, st);
-    }
-    {
-        StageTimer tm(c, LP_T_OSE_LU, st);
-        lp::BandArgs<T> ba{c->d_lu_ose, band, (T *)c->fac_ose, c->d_flags, nullptr, (T *)c->lu_dummy, (const T *)c->consts};
-        if (!lp::launch_band_lu<T>(ba, nsys, c->maxbw_ose, c->lu_variant, st))
-            return fail(LP_ERR_UNSUPPORTED, "conduit bandwidth exceeds the factorisation kernels");
-    }
-    TRY(refine_oseen<T>(c, c->d_ose, nsys, c->d_sv_ose, (const T *)c->fac_ose, c->maxbw_ose, c->maxn_ose, oa.W1[0], oa.W1[1], c->b_ose,
+    // factors of the operator linearised about Pi_h u_cH^{n+1} (factor stream)
+    const int fs = (int)((c->n + 1) % 2);
+    HIPCHK(hipStreamWaitEvent(st, c->ev_fac[fs], 0));
+    TRY(refine_oseen<T>(c, c->d_ose, nsys, c->d_sv_ose, (const T *)c->fac_ose[fs], c->maxbw_ose, c->maxn_ose, oa.W1[0], oa.W1[1], c->b_ose,
                         c->x_ose, c->r_ose, c->conv_ose, c->rel_ose, c->sw_ose, c->P.dof_total_ose, c->opt.max_ir,
                         c->opt.ir_tol, nullptr, true, st));
     StageTimer tm(c, LP_T_MERGE, st);
     lp::FinalizeArgs fa{c->d_ose, c->d_dof2, c->d_dof1, c->x_ose, c->e2[nw], c->e1[nw], nullptr};
     lp::launch_oseen_finalize(fa, nsys, st);
+    return LP_OK;
+}
+
+// Assemble and factor the local Oseen operators of time level m (linearised
+// about Pi_h u_cH^m) on the factor stream, into factor slot m % 2.  Ordered
+// after coarse step m; the slot's previous user, local step m-2, finished
+// before coarse step m started.
+template <typename T>
+lp_status factor_oseen(lp_ctx *c, int64_t m) {
+    hipStream_t st = c->fstream;
+    const int nw = (int)(m % lp_ctx::RING), fs = (int)(m % 2);
+    const int nsys = (int)c->P.ose.size();
+    HIPCHK(hipStreamWaitEvent(st, c->ev_coarse[nw], 0));
+    T *band = (T *)c->band_ose;
+    {
+        StageTimer tm(c, LP_T_OSE_ASM, st);
+        lp::ProlongArgs pa{};
+        pa.NH = c->P.NH; pa.Nh = c->P.Nh; pa.k = c->P.k;
+        pa.nfields = 2;
+        for (int cc = 0; cc < 2; ++cc) { pa.src[cc] = c->cU[nw] + cc * c->nc2; pa.dst[cc] = c->pro_Uf + cc * c->nf2; }
+        lp::launch_prolong_p2(pa, st);
+        HIPCHK(hipMemsetAsync(band, 0, (size_t)c->P.band_total_ose * sizeof(T), st));
+        lp::OseenApplyArgs<T> aa{};
+        aa.sys = c->d_ose; aa.cls2 = c->d_cls2; aa.dof2 = c->d_dof2; aa.dof1 = c->d_dof1;
+        aa.W1[0] = c->pro_Uf; aa.W1[1] = c->pro_Uf + c->nf2; aa.band = band;
+        lp::launch_oseen_assemble<T>(aa, nsys, st);
+    }
+    {
+        StageTimer tm(c, LP_T_OSE_LU, st);
+        lp::BandArgs<T> ba{c->d_lu_ose, band, (T *)c->fac_ose[fs], c->d_flags, nullptr, (T *)c->lu_dummy, (const T *)c->consts};
+        if (!lp::launch_band_lu<T>(ba, nsys, c->maxbw_ose, c->lu_variant, st))
+            return fail(LP_ERR_UNSUPPORTED, "conduit bandwidth exceeds the factorisation kernels");
+    }
+    HIPCHK(hipEventRecord(c->ev_fac[fs], st));
     return LP_OK;
 }
 
@@ -529,6 +560,7 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     TRY(c->dalloc(&c->pro_U1, 2 * c->nf2));
     TRY(c->dalloc(&c->pro_U0, 2 * c->nf2));
     TRY(c->dalloc(&c->pro_p1, c->nf1));
+    TRY(c->dalloc(&c->pro_Uf, 2 * c->nf2));
     for (int l = 0; l < 2; ++l) { TRY(c->dalloc(&c->e2[l], P.e2_total)); TRY(c->dalloc(&c->e1[l], P.e1_total)); }
     TRY(c->dalloc(&c->m_P, 3 * c->nf2));
     TRY(c->dalloc(&c->m_U, 2 * c->nf2));
@@ -549,11 +581,13 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
         if (!p) return fail(LP_ERR_ALLOC, "porous factor allocation failed");
         c->owned.push_back(p); c->fac_por = p;
         HIPCHK(hipMemsetAsync(p, 0, P.band_total_por * tb, st));
-        if (c->has_alloc) { p = c->alloc.alloc(P.band_total_ose * tb + 256, c->alloc.user); }
-        else if (hipMalloc(&p, P.band_total_ose * tb + 256) != hipSuccess) p = nullptr;
-        if (!p) return fail(LP_ERR_ALLOC, "conduit factor allocation failed");
-        c->owned.push_back(p); c->fac_ose = p;
-        HIPCHK(hipMemsetAsync(p, 0, P.band_total_ose * tb, st));
+        for (int l = 0; l < 2; ++l) {
+            if (c->has_alloc) { p = c->alloc.alloc(P.band_total_ose * tb + 256, c->alloc.user); }
+            else if (hipMalloc(&p, P.band_total_ose * tb + 256) != hipSuccess) p = nullptr;
+            if (!p) return fail(LP_ERR_ALLOC, "conduit factor allocation failed");
+            c->owned.push_back(p); c->fac_ose[l] = p;
+            HIPCHK(hipMemsetAsync(p, 0, P.band_total_ose * tb, st));
+        }
     }
     {
         const long long nlu = std::max<long long>(std::max<long long>(3LL * P.por.size(), (long long)P.ose.size()), 3);
@@ -592,6 +626,8 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     c->ecur = 0;
     HIPCHK(hipStreamCreateWithFlags(&c->cstream, hipStreamNonBlocking));
     HIPCHK(hipStreamCreateWithFlags(&c->pstream, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&c->fstream, hipStreamNonBlocking));
+    for (int i = 0; i < 2; ++i) HIPCHK(hipEventCreateWithFlags(&c->ev_fac[i], hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&c->ev_pro, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&c->ev_por, hipEventDisableTiming));
     for (int i = 0; i < lp_ctx::RING; ++i) {
@@ -706,6 +742,9 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(c->ev_coarse[nw], st));
+    if (c->mixed) TRY(factor_oseen<float>(c, m));
+    else TRY(factor_oseen<double>(c, m));
+    HIPCHK(hipGetLastError());
     c->coarse_pending = true;
     return LP_OK;
 }
