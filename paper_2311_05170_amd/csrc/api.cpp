@@ -101,6 +101,12 @@ struct lp_ctx {
     int *sw_por = nullptr, *sw_ose = nullptr, *sw_cp = nullptr, *sw_cn = nullptr;
 
     int maxbw_por = 0, maxbw_ose = 0, maxn_por = 0, maxn_ose = 0;
+    // largest local P2 lattice per batch (node blocks of the gather kernels)
+    int nodes_por = 0, nodes_ose = 0, nodes_cpor = 0, nodes_cns = 0;
+    // residual norm partials and arrival counters, one set per batch (the
+    // batches run on different streams)
+    double *part_por = nullptr, *part_ose = nullptr, *part_cp = nullptr, *part_cn = nullptr;
+    int *tick_por = nullptr, *tick_ose = nullptr, *tick_cp = nullptr, *tick_cn = nullptr;
     double *lu_dummy = nullptr;        // sink of the factorisation's masked stores
     long long lu_dummy_coarse_off = 0;
     int lu_variant = 0;                // tile shape of the local Oseen factorisation
@@ -231,9 +237,10 @@ double time_at(const lp_ctx *c, int64_t step) { return (double)step * c->prm.dt;
 
 // run `sweeps` refinement sweeps (solve, then FP64 residual) on one batch
 template <typename T>
-lp_status refine_porous(lp_ctx *c, const lp::SysDesc *d_sys, int nsys, const lp::BandSys *d_sv, const T *fac, int maxbw,
-                        int maxn, double *b, double *x, double *r, int *conv, double *rel, int *sw, long long ndof,
-                        int sweeps, double tol, bool timed, hipStream_t st) {
+lp_status refine_porous(lp_ctx *c, const lp::SysDesc *d_sys, int nsys, int maxnodes, double *part, int *ticket,
+                        const lp::BandSys *d_sv, const T *fac, int maxbw, int maxn, double *b, double *x, double *r,
+                        int *conv, double *rel, int *sw, long long ndof, int sweeps, double tol, bool timed,
+                        hipStream_t st) {
     lp::IrStartArgs ia{x, r, b, ndof, conv, rel, sw, 3LL * nsys};
     lp::launch_ir_start(ia, st);
     for (int s = 0; s < sweeps; ++s) {
@@ -243,17 +250,17 @@ lp_status refine_porous(lp_ctx *c, const lp::SysDesc *d_sys, int nsys, const lp:
             if (!lp::launch_band_solve<T>(sa, nsys, 3, maxbw, maxn, st)) return fail(LP_ERR_UNSUPPORTED, "bandwidth too large for the solve kernels");
         }
         StageTimer tm(c, timed ? LP_T_POR_RES : -1, st);
-        lp::ResidualArgs ra{d_sys, c->d_dof2, x, b, r, conv, rel, sw, tol, nullptr};
-        lp::launch_porous_residual(ra, nsys, st);
+        lp::ResidualArgs ra{d_sys, c->d_dof2, x, b, r, conv, rel, sw, tol, nullptr, part, ticket};
+        lp::launch_porous_residual(ra, nsys, maxnodes, st);
     }
     return LP_OK;
 }
 
 template <typename T>
-lp_status refine_oseen(lp_ctx *c, const lp::SysDesc *d_sys, int nsys, const lp::BandSys *d_sv, const T *fac, int maxbw,
-                       int maxn, const double *W1x, const double *W1y, double *b, double *x, double *r, int *conv,
-                       double *rel, int *sw, long long ndof, int sweeps, double tol, const int *skip, bool timed,
-                       hipStream_t st) {
+lp_status refine_oseen(lp_ctx *c, const lp::SysDesc *d_sys, int nsys, int maxnodes, double *part, int *ticket,
+                       const lp::BandSys *d_sv, const T *fac, int maxbw, int maxn, const double *W1x, const double *W1y,
+                       double *b, double *x, double *r, int *conv, double *rel, int *sw, long long ndof, int sweeps,
+                       double tol, const int *skip, bool timed, hipStream_t st) {
     lp::IrStartArgs ia{x, r, b, ndof, conv, rel, sw, (long long)nsys};
     lp::launch_ir_start(ia, st);
     for (int s = 0; s < sweeps; ++s) {
@@ -268,7 +275,8 @@ lp_status refine_oseen(lp_ctx *c, const lp::SysDesc *d_sys, int nsys, const lp::
         ra.W1[0] = W1x; ra.W1[1] = W1y;
         ra.x = x; ra.b = b; ra.r = r; ra.band = nullptr;
         ra.conv = conv; ra.relres = rel; ra.sweeps = sw; ra.tol = tol; ra.skip = skip;
-        lp::launch_oseen_residual(ra, nsys, st);
+        ra.part = part; ra.ticket = ticket;
+        lp::launch_oseen_residual(ra, nsys, maxnodes, st);
     }
     return LP_OK;
 }
@@ -304,17 +312,17 @@ lp_status local_oseen(lp_ctx *c, hipStream_t st) {
     oa.skip = nullptr;
     {
         StageTimer tm(c, LP_T_OSE_RHS, st);
-        lp::launch_oseen_rhs(oa, nsys, st);
+        lp::launch_oseen_rhs(oa, nsys, c->nodes_ose, st);
     }
     // factors of the operator linearised about Pi_h u_cH^{n+1} (factor stream)
     const int fs = (int)((c->n + 1) % 2);
     HIPCHK(hipStreamWaitEvent(st, c->ev_fac[fs], 0));
-    TRY(refine_oseen<T>(c, c->d_ose, nsys, c->d_sv_ose, (const T *)c->fac_ose[fs], c->maxbw_ose, c->maxn_ose, oa.W1[0], oa.W1[1], c->b_ose,
+    TRY(refine_oseen<T>(c, c->d_ose, nsys, c->nodes_ose, c->part_ose, c->tick_ose, c->d_sv_ose, (const T *)c->fac_ose[fs], c->maxbw_ose, c->maxn_ose, oa.W1[0], oa.W1[1], c->b_ose,
                         c->x_ose, c->r_ose, c->conv_ose, c->rel_ose, c->sw_ose, c->P.dof_total_ose, c->opt.max_ir,
                         c->opt.ir_tol, nullptr, true, st));
     StageTimer tm(c, LP_T_MERGE, st);
     lp::FinalizeArgs fa{c->d_ose, c->d_dof2, c->d_dof1, c->x_ose, c->e2[nw], c->e1[nw], nullptr};
-    lp::launch_oseen_finalize(fa, nsys, st);
+    lp::launch_oseen_finalize(fa, nsys, c->nodes_ose, st);
     return LP_OK;
 }
 
@@ -340,7 +348,7 @@ lp_status factor_oseen(lp_ctx *c, int64_t m) {
         lp::OseenApplyArgs<T> aa{};
         aa.sys = c->d_ose; aa.cls2 = c->d_cls2; aa.dof2 = c->d_dof2; aa.dof1 = c->d_dof1;
         aa.W1[0] = c->pro_Uf; aa.W1[1] = c->pro_Uf + c->nf2; aa.band = band;
-        lp::launch_oseen_assemble<T>(aa, nsys, st);
+        lp::launch_oseen_assemble<T>(aa, nsys, c->nodes_ose, st);
     }
     {
         StageTimer tm(c, LP_T_OSE_LU, st);
@@ -372,14 +380,14 @@ lp_status local_porous(lp_ctx *c, hipStream_t st) {
     pa.tf[0] = std::cos(t1); pa.tf[1] = std::sin(t1); pa.tf[2] = pa.tf[0] * pa.tf[0];
     {
         StageTimer tm(c, LP_T_POR_RHS, st);
-        lp::launch_porous_rhs(pa, nsys, st);
+        lp::launch_porous_rhs(pa, nsys, c->nodes_por, st);
     }
-    TRY(refine_porous<T>(c, c->d_por, nsys, c->d_sv_por, (const T *)c->fac_por, c->maxbw_por, c->maxn_por, c->b_por,
+    TRY(refine_porous<T>(c, c->d_por, nsys, c->nodes_por, c->part_por, c->tick_por, c->d_sv_por, (const T *)c->fac_por, c->maxbw_por, c->maxn_por, c->b_por,
                          c->x_por, c->r_por, c->conv_por, c->rel_por, c->sw_por, c->P.dof_total_por, c->opt.max_ir,
                          c->opt.ir_tol, true, st));
     StageTimer tm(c, LP_T_MERGE, st);
     lp::FinalizeArgs fa{c->d_por, c->d_dof2, c->d_dof1, c->x_por, c->e2[nw], nullptr, nullptr};
-    lp::launch_porous_finalize(fa, nsys, st);
+    lp::launch_porous_finalize(fa, nsys, c->nodes_por, st);
     return LP_OK;
 }
 
@@ -484,6 +492,10 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     lp::Plan &P = c->P;
     for (const auto &s : P.por) { c->maxbw_por = std::max(c->maxbw_por, s.bw); c->maxn_por = std::max(c->maxn_por, s.ndof); }
     for (const auto &s : P.ose) { c->maxbw_ose = std::max(c->maxbw_ose, s.bw); c->maxn_ose = std::max(c->maxn_ose, s.ndof); }
+    for (const auto &s : P.por) c->nodes_por = std::max(c->nodes_por, s.lw2 * s.lh2);
+    for (const auto &s : P.ose) c->nodes_ose = std::max(c->nodes_ose, s.lw2 * s.lh2);
+    c->nodes_cpor = P.cpor.lw2 * P.cpor.lh2;
+    c->nodes_cns = P.cns.lw2 * P.cns.lh2;
     if (std::max(c->maxbw_por, c->maxbw_ose) >= 160 || std::max(P.cpor.bw, P.cns.bw) >= 160)
         return fail(LP_ERR_UNSUPPORTED, "local half-bandwidth " + std::to_string(std::max(c->maxbw_por, c->maxbw_ose)) +
                                             " exceeds the 159 supported by the band kernels");
@@ -617,6 +629,17 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     TRY(c->dalloc(&c->conv_ose, nof)); TRY(c->dalloc(&c->rel_ose, nof)); TRY(c->dalloc(&c->sw_ose, nof));
     TRY(c->dalloc(&c->conv_cp, 3)); TRY(c->dalloc(&c->rel_cp, 3)); TRY(c->dalloc(&c->sw_cp, 3));
     TRY(c->dalloc(&c->conv_cn, 1)); TRY(c->dalloc(&c->rel_cn, 1)); TRY(c->dalloc(&c->sw_cn, 1));
+    {
+        auto nb = [](int nodes) { return (long long)lp::node_blocks(nodes); };
+        TRY(c->dalloc(&c->part_por, 2 * npf * nb(c->nodes_por))); TRY(c->dalloc(&c->tick_por, npf));
+        TRY(c->dalloc(&c->part_ose, 2 * nof * nb(c->nodes_ose))); TRY(c->dalloc(&c->tick_ose, nof));
+        TRY(c->dalloc(&c->part_cp, 2 * 3 * nb(c->nodes_cpor))); TRY(c->dalloc(&c->tick_cp, 3));
+        TRY(c->dalloc(&c->part_cn, 2 * nb(c->nodes_cns))); TRY(c->dalloc(&c->tick_cn, 1));
+        HIPCHK(hipMemsetAsync(c->tick_por, 0, npf * sizeof(int), st));
+        HIPCHK(hipMemsetAsync(c->tick_ose, 0, nof * sizeof(int), st));
+        HIPCHK(hipMemsetAsync(c->tick_cp, 0, 3 * sizeof(int), st));
+        HIPCHK(hipMemsetAsync(c->tick_cn, 0, sizeof(int), st));
+    }
     HIPCHK(hipMemsetAsync(c->sw_ose, 0, nof * sizeof(int), st));
     HIPCHK(hipMemsetAsync(c->sw_por, 0, npf * sizeof(int), st));
     HIPCHK(hipMemsetAsync(c->rel_ose, 0, nof * sizeof(double), st));
@@ -696,11 +719,11 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
     pa.Uy0 = c->cU[o] + nc2;
     pa.e_old = c->cP[o]; pa.e_new = c->cP[nw]; pa.b = c->b_cp;
     for (int k = 0; k < 3; ++k) pa.tf[k] = tf[k];
-    lp::launch_porous_rhs(pa, 1, st);
-    TRY(refine_porous<double>(c, c->d_cpor, 1, c->d_sv_cpor, c->fac_cpor, P.cpor.bw, P.cpor.ndof, c->b_cp, c->x_cp,
+    lp::launch_porous_rhs(pa, 1, c->nodes_cpor, st);
+    TRY(refine_porous<double>(c, c->d_cpor, 1, c->nodes_cpor, c->part_cp, c->tick_cp, c->d_sv_cpor, c->fac_cpor, P.cpor.bw, P.cpor.ndof, c->b_cp, c->x_cp,
                               c->r_cp, c->conv_cp, c->rel_cp, c->sw_cp, 3LL * P.cpor.ndof, 2, 1e-13, false, st));
     lp::FinalizeArgs fa{c->d_cpor, c->d_dof2, c->d_dof1, c->x_cp, c->cP[nw], nullptr, nullptr};
-    lp::launch_porous_finalize(fa, 1, st);
+    lp::launch_porous_finalize(fa, 1, c->nodes_cpor, st);
     // (5.4): Navier-Stokes by Newton from (u^n, p^n); each iteration solves the
     // Oseen system linearised about the current iterate
     HIPCHK(hipMemcpyAsync(c->cU[nw], c->cU[o], 2 * nc2 * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -720,7 +743,7 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
         oa.b = c->b_cn;
         for (int k = 0; k < 3; ++k) oa.tf[k] = tf[k];
         oa.skip = c->d_done;
-        lp::launch_oseen_rhs(oa, 1, st);
+        lp::launch_oseen_rhs(oa, 1, c->nodes_cns, st);
         if (it == 0) {
             // Jacobian at the first iterate (u^n); later iterations reuse its
             // factors, with residuals of the current Jacobian (chord steps)
@@ -728,15 +751,15 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
             lp::OseenApplyArgs<double> aa{};
             aa.sys = c->d_cns; aa.cls2 = c->d_cls2; aa.dof2 = c->d_dof2; aa.dof1 = c->d_dof1;
             aa.W1[0] = oa.W1[0]; aa.W1[1] = oa.W1[1]; aa.band = c->band_cns; aa.skip = c->d_done;
-            lp::launch_oseen_assemble<double>(aa, 1, st);
+            lp::launch_oseen_assemble<double>(aa, 1, c->nodes_cns, st);
             lp::BandArgs<double> ba{c->d_lu_cns, c->band_cns, c->fac_cns, c->d_flags, c->d_done, c->lu_dummy + c->lu_dummy_coarse_off,
                                     (const double *)c->consts};
             if (!lp::launch_band_lu<double>(ba, 1, P.cns.bw, 0, st)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
         }
-        TRY(refine_oseen<double>(c, c->d_cns, 1, c->d_sv_cns, c->fac_cns, P.cns.bw, P.cns.ndof, oa.W1[0], oa.W1[1],
+        TRY(refine_oseen<double>(c, c->d_cns, 1, c->nodes_cns, c->part_cn, c->tick_cn, c->d_sv_cns, c->fac_cns, P.cns.bw, P.cns.ndof, oa.W1[0], oa.W1[1],
                                  c->b_cn, c->x_cn, c->r_cn, c->conv_cn, c->rel_cn, c->sw_cn, P.cns.ndof, 1, 1e-14, c->d_done, false, st));
         lp::FinalizeArgs fn{c->d_cns, c->d_dof2, c->d_dof1, c->x_cn, c->nwt_e, c->nwt_e1, c->d_done};
-        lp::launch_oseen_finalize(fn, 1, st);
+        lp::launch_oseen_finalize(fn, 1, c->nodes_cns, st);
         lp::NewtonArgs na{c->cU[nw], c->cp[nw], c->nwt_e, c->nwt_e1, nc2, c->nc1, c->d_done, c->d_its, c->opt.newton_tol};
         lp::launch_newton_update(na, st);
     }

@@ -38,6 +38,8 @@ struct ResidualArgs {
     int *sweeps;
     double tol;
     const int *skip;
+    double *part;                 // per-(system, node block) partial norms: 2 * nblocks doubles per id
+    int *ticket;                  // per-id arrival counters, zero between launches
 };
 
 struct FinalizeArgs {
@@ -93,6 +95,8 @@ struct OseenApplyArgs {
     int *sweeps;
     double tol;
     const int *skip;
+    double *part;                 // residual mode: partial norms and counters as in ResidualArgs
+    int *ticket;
 };
 
 struct BandSys {
@@ -175,16 +179,20 @@ struct IrStartArgs {
 hipError_t upload_constants(const RefData &r, const Coef &c, hipStream_t st);
 void launch_prolong_p2(const ProlongArgs &a, hipStream_t st);
 void launch_prolong_p1(const ProlongArgs &a, hipStream_t st);
-void launch_porous_rhs(const PorousArgs &a, int nsys, hipStream_t st);
-void launch_porous_residual(const ResidualArgs &a, int nsys, hipStream_t st);
-void launch_porous_finalize(const FinalizeArgs &a, int nsys, hipStream_t st);
+// Node-gather kernels run gridDim = (node blocks of GB threads, systems);
+// maxnodes is the largest local P2 lattice of the batch.
+constexpr int GB = 128;
+int node_blocks(int maxnodes);
+void launch_porous_rhs(const PorousArgs &a, int nsys, int maxnodes, hipStream_t st);
+void launch_porous_residual(const ResidualArgs &a, int nsys, int maxnodes, hipStream_t st);
+void launch_porous_finalize(const FinalizeArgs &a, int nsys, int maxnodes, hipStream_t st);
 template <typename T>
 void launch_porous_assemble(const AssembleArgs<T> &a, int nsys, hipStream_t st);
-void launch_oseen_rhs(const OseenArgs &a, int nsys, hipStream_t st);
+void launch_oseen_rhs(const OseenArgs &a, int nsys, int maxnodes, hipStream_t st);
 template <typename T>
-void launch_oseen_assemble(const OseenApplyArgs<T> &a, int nsys, hipStream_t st);
-void launch_oseen_residual(const OseenApplyArgs<double> &a, int nsys, hipStream_t st);
-void launch_oseen_finalize(const FinalizeArgs &a, int nsys, hipStream_t st);
+void launch_oseen_assemble(const OseenApplyArgs<T> &a, int nsys, int maxnodes, hipStream_t st);
+void launch_oseen_residual(const OseenApplyArgs<double> &a, int nsys, int maxnodes, hipStream_t st);
+void launch_oseen_finalize(const FinalizeArgs &a, int nsys, int maxnodes, hipStream_t st);
 template <typename T>
 bool launch_band_lu(const BandArgs<T> &a, int nsys, int maxbw, int variant, hipStream_t st);
 template <typename T>

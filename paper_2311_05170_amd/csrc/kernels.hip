@@ -139,12 +139,12 @@ __device__ __forceinline__ double porous_z(const SysDesc &S, const PorousArgs &A
     return A.ex[f][G] * A.tf[0] - bg;
 }
 
-__global__ __launch_bounds__(256) void k_porous_rhs(PorousArgs A) {
-    const SysDesc S = A.sys[blockIdx.x];
+__global__ __launch_bounds__(GB) void k_porous_rhs(PorousArgs A) {
+    const SysDesc S = A.sys[blockIdx.y];
     const int nloc = S.lw2 * S.lh2;
     const int ng = 2 * S.N + 1;
     const double h = S.h, h2 = h * h;
-    for (int q = threadIdx.x; q < nloc; q += blockDim.x) {
+    for (int q = blockIdx.x * GB + threadIdx.x; q < nloc; q += gridDim.x * GB) {
         const int a = q % S.lw2, b = q / S.lw2;
         const long long G = (2 * S.x0 + a) + (long long)ng * (2 * S.y0 + b);
         const int cls = A.cls2[S.node_off + q];
@@ -191,30 +191,56 @@ __global__ __launch_bounds__(256) void k_porous_rhs(PorousArgs A) {
     }
 }
 
-// block reduction of ||r||^2 and ||b||^2; thread 0 records the relative
-// residual, counts the sweep and raises the convergence flag
-__device__ void block_norms_and_flag(double rr, double bb, const ResidualArgs &R, int id) {
-    __shared__ double s1[256], s2[256];
-    s1[threadIdx.x] = rr;
-    s2[threadIdx.x] = bb;
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Reduction of ||r||^2 and ||b||^2 of system `id` over the gridDim.x node
+// blocks that share it.  Each block stores its partial sums; the block that
+// arrives last (ticket counter) adds the partials in block order, so the
+// result does not depend on scheduling, records the relative residual,
+// counts the sweep, raises the convergence flag and rearms the counter.
+__device__ void grid_norms_and_flag(double rr, double bb, double *part, int *ticket, int *conv, double *relres,
+                                    int *sweeps, double tol, int id) {
+    __shared__ double s1[GB / 64], s2[GB / 64];
+    __shared__ int last;
+    rr = wave_sum(rr);
+    bb = wave_sum(bb);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { s1[w] = rr; s2[w] = bb; }
     __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) { s1[threadIdx.x] += s1[threadIdx.x + s]; s2[threadIdx.x] += s2[threadIdx.x + s]; }
-        __syncthreads();
-    }
+    const long long base = 2LL * id * gridDim.x;
     if (threadIdx.x == 0) {
-        const double rel = s2[0] > 0.0 ? sqrt(s1[0] / s2[0]) : 0.0;
-        R.relres[id] = rel;
-        R.sweeps[id] += 1;
-        if (rel <= R.tol) R.conv[id] = 1;
+        double a = 0.0, b = 0.0;
+        for (int i = 0; i < GB / 64; ++i) { a += s1[i]; b += s2[i]; }
+        part[base + 2 * blockIdx.x] = a;
+        part[base + 2 * blockIdx.x + 1] = b;
+        __threadfence();
+        last = atomicAdd(ticket + id, 1) == (int)gridDim.x - 1;
+    }
+    __syncthreads();
+    if (last && threadIdx.x == 0) {
+        __threadfence();
+        double a = 0.0, b = 0.0;
+        for (int i = 0; i < (int)gridDim.x; ++i) {
+            a += part[base + 2 * i];
+            b += part[base + 2 * i + 1];
+        }
+        ticket[id] = 0;
+        const double rel = b > 0.0 ? sqrt(a / b) : 0.0;
+        relres[id] = rel;
+        sweeps[id] += 1;
+        if (rel <= tol) conv[id] = 1;
     }
 }
 
 // y = A_f x restricted to free rows (FP64, matrix-free); r = b - y; norms
-__global__ __launch_bounds__(256) void k_porous_residual(ResidualArgs R) {
-    const SysDesc S = R.sys[blockIdx.x];
-    const int f = blockIdx.y;
-    const int id = blockIdx.x * 3 + f;
+__global__ __launch_bounds__(GB) void k_porous_residual(ResidualArgs R) {
+    const SysDesc S = R.sys[blockIdx.y];
+    const int f = blockIdx.z;
+    const int id = blockIdx.y * 3 + f;
     if (R.skip && *R.skip) return;
     if (R.conv[id]) return;
     const int nloc = S.lw2 * S.lh2;
@@ -224,7 +250,7 @@ __global__ __launch_bounds__(256) void k_porous_residual(ResidualArgs R) {
     const double *b = R.b + S.dof_off + (long long)f * S.ndof;
     double *r = R.r + S.dof_off + (long long)f * S.ndof;
     double rr = 0.0, bb = 0.0;
-    for (int q = threadIdx.x; q < nloc; q += blockDim.x) {
+    for (int q = blockIdx.x * GB + threadIdx.x; q < nloc; q += gridDim.x * GB) {
         const int dq = R.dof2[S.node_off + q];
         if (dq < 0) continue;
         const int a = q % S.lw2, bq = q / S.lw2;
@@ -242,14 +268,14 @@ __global__ __launch_bounds__(256) void k_porous_residual(ResidualArgs R) {
         rr += rv * rv;
         bb += b[dq] * b[dq];
     }
-    block_norms_and_flag(rr, bb, R, id);
+    grid_norms_and_flag(rr, bb, R.part, R.ticket, R.conv, R.relres, R.sweeps, R.tol, id);
 }
 
-__global__ __launch_bounds__(256) void k_porous_finalize(FinalizeArgs F) {
-    const SysDesc S = F.sys[blockIdx.x];
+__global__ __launch_bounds__(GB) void k_porous_finalize(FinalizeArgs F) {
+    const SysDesc S = F.sys[blockIdx.y];
     if (F.skip && *F.skip) return;
     const int nloc = S.lw2 * S.lh2;
-    for (int q = threadIdx.x; q < nloc; q += blockDim.x) {
+    for (int q = blockIdx.x * GB + threadIdx.x; q < nloc; q += gridDim.x * GB) {
         const int d = F.dof2[S.node_off + q];
         if (d < 0) continue;
         for (int f = 0; f < 3; ++f)
@@ -329,14 +355,14 @@ __device__ __forceinline__ void conv_rows(int t, int la, double h, const double 
     for (int c = 0; c < 2; ++c) { cW[c] *= h; Nz[c] *= h; }
 }
 
-__global__ __launch_bounds__(256) void k_oseen_rhs(OseenArgs A) {
-    const SysDesc S = A.sys[blockIdx.x];
+__global__ __launch_bounds__(GB) void k_oseen_rhs(OseenArgs A) {
+    const SysDesc S = A.sys[blockIdx.y];
     if (A.skip && *A.skip) return;
-    const int nloc = S.lw2 * S.lh2, nv = S.lw1 * S.lh1;
+    const int nloc = S.lw2 * S.lh2;
     const int ng = 2 * S.N + 1, ng1 = S.N + 1;
     const double h = S.h, h2 = h * h;
     const double eta = c_co.eta, edt = c_co.eta / c_co.dt, nue = c_co.nu * c_co.eta;
-    for (int q = threadIdx.x; q < nloc; q += blockDim.x) {
+    for (int q = blockIdx.x * GB + threadIdx.x; q < nloc; q += gridDim.x * GB) {
         const int a = q % S.lw2, b = q / S.lw2;
         const long long G = (2 * S.x0 + a) + (long long)ng * (2 * S.y0 + b);
         const int cls = A.cls2[S.node_off + q];
@@ -425,10 +451,10 @@ __global__ __launch_bounds__(256) void k_oseen_rhs(OseenArgs A) {
 // Row application of the Oseen operator to x (FP64) or assembly of its band
 // entries (T).  Mode 0: residual r = b - K x.  Mode 1: band assembly.
 template <typename T, int MODE>
-__global__ __launch_bounds__(256) void k_oseen_apply(OseenApplyArgs<T> A) {
-    const SysDesc S = A.sys[blockIdx.x];
+__global__ __launch_bounds__(GB) void k_oseen_apply(OseenApplyArgs<T> A) {
+    const SysDesc S = A.sys[blockIdx.y];
     if (A.skip && *A.skip) return;
-    if (MODE == 0 && A.conv[blockIdx.x]) return;
+    if (MODE == 0 && A.conv[blockIdx.y]) return;
     const int nloc = S.lw2 * S.lh2;
     const int ng = 2 * S.N + 1;
     const double h = S.h, h2 = h * h;
@@ -441,7 +467,7 @@ __global__ __launch_bounds__(256) void k_oseen_apply(OseenApplyArgs<T> A) {
         T *p = band + (long long)col * ld + (row - col + S.bw);
         *p = (T)((double)*p + v);
     };
-    for (int q = threadIdx.x; q < nloc; q += blockDim.x) {
+    for (int q = blockIdx.x * GB + threadIdx.x; q < nloc; q += gridDim.x * GB) {
         const int a = q % S.lw2, b = q / S.lw2;
         const int cls = A.cls2[S.node_off + q];
         const bool vertex = !(a & 1) && !(b & 1);
@@ -570,24 +596,20 @@ __global__ __launch_bounds__(256) void k_oseen_apply(OseenApplyArgs<T> A) {
             }
         }
     }
-    if (MODE == 0) {
-        ResidualArgs R;
-        R.conv = A.conv; R.relres = A.relres; R.tol = A.tol; R.sweeps = A.sweeps;
-        block_norms_and_flag(rr, bb, R, blockIdx.x);
-    }
+    if (MODE == 0) grid_norms_and_flag(rr, bb, A.part, A.ticket, A.conv, A.relres, A.sweeps, A.tol, blockIdx.y);
 }
 
-__global__ __launch_bounds__(256) void k_oseen_finalize(FinalizeArgs F) {
-    const SysDesc S = F.sys[blockIdx.x];
+__global__ __launch_bounds__(GB) void k_oseen_finalize(FinalizeArgs F) {
+    const SysDesc S = F.sys[blockIdx.y];
     if (F.skip && *F.skip) return;
     const int nloc = S.lw2 * S.lh2, nv = S.lw1 * S.lh1;
-    for (int q = threadIdx.x; q < nloc; q += blockDim.x) {
+    for (int q = blockIdx.x * GB + threadIdx.x; q < nloc; q += gridDim.x * GB) {
         const int d = F.dof2[S.node_off + q];
         if (d < 0) continue;
         F.e_new[S.e2_off + q] = F.x[S.dof_off + d];
         F.e_new[S.e2_off + nloc + q] = F.x[S.dof_off + d + 1];
     }
-    for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+    for (int v = blockIdx.x * GB + threadIdx.x; v < nv; v += gridDim.x * GB) {
         const int d = F.dof1[S.vert_off + v];
         if (d >= 0) F.e_new1[S.e1_off + v] = F.x[S.dof_off + d];
     }
@@ -1008,31 +1030,33 @@ void launch_prolong_p1(const ProlongArgs &a, hipStream_t st) {
     long long n = (long long)(a.Nh + 1) * (a.Nh + 1);
     hipLaunchKernelGGL(k_prolong_p1, dim3(grid_for(n, 256)), dim3(256), 0, st, a);
 }
-void launch_porous_rhs(const PorousArgs &a, int nsys, hipStream_t st) {
-    hipLaunchKernelGGL(k_porous_rhs, dim3(nsys), dim3(256), 0, st, a);
+int node_blocks(int maxnodes) { return maxnodes > 0 ? (maxnodes + GB - 1) / GB : 1; }
+
+void launch_porous_rhs(const PorousArgs &a, int nsys, int maxnodes, hipStream_t st) {
+    hipLaunchKernelGGL(k_porous_rhs, dim3(node_blocks(maxnodes), nsys), dim3(GB), 0, st, a);
 }
-void launch_porous_residual(const ResidualArgs &a, int nsys, hipStream_t st) {
-    hipLaunchKernelGGL(k_porous_residual, dim3(nsys, 3), dim3(256), 0, st, a);
+void launch_porous_residual(const ResidualArgs &a, int nsys, int maxnodes, hipStream_t st) {
+    hipLaunchKernelGGL(k_porous_residual, dim3(node_blocks(maxnodes), nsys, 3), dim3(GB), 0, st, a);
 }
-void launch_porous_finalize(const FinalizeArgs &a, int nsys, hipStream_t st) {
-    hipLaunchKernelGGL(k_porous_finalize, dim3(nsys), dim3(256), 0, st, a);
+void launch_porous_finalize(const FinalizeArgs &a, int nsys, int maxnodes, hipStream_t st) {
+    hipLaunchKernelGGL(k_porous_finalize, dim3(node_blocks(maxnodes), nsys), dim3(GB), 0, st, a);
 }
 template <typename T>
 void launch_porous_assemble(const AssembleArgs<T> &a, int nsys, hipStream_t st) {
     hipLaunchKernelGGL(k_porous_assemble<T>, dim3(nsys), dim3(256), 0, st, a);
 }
-void launch_oseen_rhs(const OseenArgs &a, int nsys, hipStream_t st) {
-    hipLaunchKernelGGL(k_oseen_rhs, dim3(nsys), dim3(256), 0, st, a);
+void launch_oseen_rhs(const OseenArgs &a, int nsys, int maxnodes, hipStream_t st) {
+    hipLaunchKernelGGL(k_oseen_rhs, dim3(node_blocks(maxnodes), nsys), dim3(GB), 0, st, a);
 }
 template <typename T>
-void launch_oseen_assemble(const OseenApplyArgs<T> &a, int nsys, hipStream_t st) {
-    hipLaunchKernelGGL((k_oseen_apply<T, 1>), dim3(nsys), dim3(256), 0, st, a);
+void launch_oseen_assemble(const OseenApplyArgs<T> &a, int nsys, int maxnodes, hipStream_t st) {
+    hipLaunchKernelGGL((k_oseen_apply<T, 1>), dim3(node_blocks(maxnodes), nsys), dim3(GB), 0, st, a);
 }
-void launch_oseen_residual(const OseenApplyArgs<double> &a, int nsys, hipStream_t st) {
-    hipLaunchKernelGGL((k_oseen_apply<double, 0>), dim3(nsys), dim3(256), 0, st, a);
+void launch_oseen_residual(const OseenApplyArgs<double> &a, int nsys, int maxnodes, hipStream_t st) {
+    hipLaunchKernelGGL((k_oseen_apply<double, 0>), dim3(node_blocks(maxnodes), nsys), dim3(GB), 0, st, a);
 }
-void launch_oseen_finalize(const FinalizeArgs &a, int nsys, hipStream_t st) {
-    hipLaunchKernelGGL(k_oseen_finalize, dim3(nsys), dim3(256), 0, st, a);
+void launch_oseen_finalize(const FinalizeArgs &a, int nsys, int maxnodes, hipStream_t st) {
+    hipLaunchKernelGGL(k_oseen_finalize, dim3(node_blocks(maxnodes), nsys), dim3(GB), 0, st, a);
 }
 
 template <typename T>
@@ -1082,8 +1106,8 @@ void launch_ir_start(const IrStartArgs &a, hipStream_t st) {
 
 template void launch_porous_assemble<float>(const AssembleArgs<float> &, int, hipStream_t);
 template void launch_porous_assemble<double>(const AssembleArgs<double> &, int, hipStream_t);
-template void launch_oseen_assemble<float>(const OseenApplyArgs<float> &, int, hipStream_t);
-template void launch_oseen_assemble<double>(const OseenApplyArgs<double> &, int, hipStream_t);
+template void launch_oseen_assemble<float>(const OseenApplyArgs<float> &, int, int, hipStream_t);
+template void launch_oseen_assemble<double>(const OseenApplyArgs<double> &, int, int, hipStream_t);
 template bool launch_band_lu<float>(const BandArgs<float> &, int, int, int, hipStream_t);
 template bool launch_band_lu<double>(const BandArgs<double> &, int, int, int, hipStream_t);
 template bool launch_band_solve<float>(const SolveArgs<float> &, int, int, int, int, hipStream_t);
