@@ -89,6 +89,10 @@ struct lp_ctx {
     // linear algebra storage
     void *band_por = nullptr, *band_ose = nullptr;        // float (mixed) or double
     double *band_cpor = nullptr, *band_cns = nullptr;
+    // explicit inverses of the small coarse matrices (column-major), the
+    // identity right-hand sides that produce them, and their solve lists
+    double *inv_cp = nullptr, *inv_cn = nullptr, *eye_cp = nullptr, *eye_cn = nullptr;
+    lp::BandSys *d_iv_cpor = nullptr, *d_iv_cns = nullptr;
     void *fac_por = nullptr, *fac_ose[2] = {};            // factors, same offsets as the bands
     double *pro_Uf = nullptr;                            // u_cH^m prolonged for the factor stream
     double *fac_cpor = nullptr, *fac_cns = nullptr;
@@ -234,6 +238,32 @@ std::vector<lp::BandSys> solve_list(const std::vector<lp::SysDesc> &v, int nrhs)
 }
 
 double time_at(const lp_ctx *c, int64_t step) { return (double)step * c->prm.dt; }
+
+// solve list that turns nmat factored band matrices of system s into their
+// inverses: every right-hand side of matrix f shares its factors (stride 0)
+// and column j of the inverse is the solution for the j-th unit vector
+std::vector<lp::BandSys> inverse_list(const lp::SysDesc &s, int nmat) {
+    std::vector<lp::BandSys> out;
+    const long long n = s.ndof;
+    for (int f = 0; f < nmat; ++f) {
+        lp::BandSys b{};
+        b.off = s.band_off + (long long)f * s.band_size;
+        b.stride = 0;
+        b.vec = (long long)f * n * n;
+        b.n = s.ndof;
+        b.bw = s.bw;
+        b.nrhs = s.ndof;
+        out.push_back(b);
+    }
+    return out;
+}
+
+std::vector<double> identities(long long n, int nmat) {
+    std::vector<double> e((size_t)nmat * n * n, 0.0);
+    for (int f = 0; f < nmat; ++f)
+        for (long long j = 0; j < n; ++j) e[(size_t)f * n * n + j * n + j] = 1.0;
+    return e;
+}
 
 // run `sweeps` refinement sweeps (solve, then FP64 residual) on one batch
 template <typename T>
@@ -684,6 +714,19 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
         lp::BandArgs<double> ba{c->d_lu_cpor, c->band_cpor, c->fac_cpor, c->d_flags, nullptr, c->lu_dummy + c->lu_dummy_coarse_off,
                                 (const double *)c->consts};
         if (!lp::launch_band_lu<double>(ba, 3, P.cpor.bw, 0, st)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
+        // the coarse porous matrices are constant: invert them once
+        const long long n = P.cpor.ndof;
+        TRY(c->upload(&c->eye_cp, identities(n, 3), st));
+        TRY(c->upload(&c->d_iv_cpor, inverse_list(P.cpor, 3), st));
+        TRY(c->dalloc(&c->inv_cp, 3 * n * n));
+        HIPCHK(hipMemsetAsync(c->inv_cp, 0, 3 * n * n * sizeof(double), st));
+        lp::SolveArgs<double> sa{c->d_iv_cpor, c->fac_cpor, c->eye_cp, c->inv_cp, nullptr, (int)n, nullptr,
+                                 (const double *)c->consts, c->const_one<double>(), (const double *)c->consts};
+        if (!lp::launch_band_solve<double>(sa, 3, (int)n, P.cpor.bw, (int)n, st)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
+        const long long m = P.cns.ndof;
+        TRY(c->upload(&c->eye_cn, identities(m, 1), st));
+        TRY(c->upload(&c->d_iv_cns, inverse_list(P.cns, 1), st));
+        TRY(c->dalloc(&c->inv_cn, m * m));
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));
@@ -720,8 +763,10 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
     pa.e_old = c->cP[o]; pa.e_new = c->cP[nw]; pa.b = c->b_cp;
     for (int k = 0; k < 3; ++k) pa.tf[k] = tf[k];
     lp::launch_porous_rhs(pa, 1, c->nodes_cpor, st);
-    TRY(refine_porous<double>(c, c->d_cpor, 1, c->nodes_cpor, c->part_cp, c->tick_cp, c->d_sv_cpor, c->fac_cpor, P.cpor.bw, P.cpor.ndof, c->b_cp, c->x_cp,
-                              c->r_cp, c->conv_cp, c->rel_cp, c->sw_cp, 3LL * P.cpor.ndof, 2, 1e-13, false, st));
+    {
+        lp::DenseArgs da{c->inv_cp, c->b_cp, c->x_cp, P.cpor.ndof, nullptr};
+        lp::launch_dense_apply(da, 3, st);
+    }
     lp::FinalizeArgs fa{c->d_cpor, c->d_dof2, c->d_dof1, c->x_cp, c->cP[nw], nullptr, nullptr};
     lp::launch_porous_finalize(fa, 1, c->nodes_cpor, st);
     // (5.4): Navier-Stokes by Newton from (u^n, p^n); each iteration solves the
@@ -755,9 +800,16 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
             lp::BandArgs<double> ba{c->d_lu_cns, c->band_cns, c->fac_cns, c->d_flags, c->d_done, c->lu_dummy + c->lu_dummy_coarse_off,
                                     (const double *)c->consts};
             if (!lp::launch_band_lu<double>(ba, 1, P.cns.bw, 0, st)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
+            // explicit inverse of the Jacobian: each chord step is then one
+            // dense product instead of a serial band solve
+            const int n = P.cns.ndof;
+            HIPCHK(hipMemsetAsync(c->inv_cn, 0, (size_t)n * n * sizeof(double), st));
+            lp::SolveArgs<double> sa{c->d_iv_cns, c->fac_cns, c->eye_cn, c->inv_cn, nullptr, n, c->d_done,
+                                     (const double *)c->consts, c->const_one<double>(), (const double *)c->consts};
+            if (!lp::launch_band_solve<double>(sa, 1, n, P.cns.bw, n, st)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
         }
-        TRY(refine_oseen<double>(c, c->d_cns, 1, c->nodes_cns, c->part_cn, c->tick_cn, c->d_sv_cns, c->fac_cns, P.cns.bw, P.cns.ndof, oa.W1[0], oa.W1[1],
-                                 c->b_cn, c->x_cn, c->r_cn, c->conv_cn, c->rel_cn, c->sw_cn, P.cns.ndof, 1, 1e-14, c->d_done, false, st));
+        lp::DenseArgs da{c->inv_cn, c->b_cn, c->x_cn, P.cns.ndof, c->d_done};
+        lp::launch_dense_apply(da, 1, st);
         lp::FinalizeArgs fn{c->d_cns, c->d_dof2, c->d_dof1, c->x_cn, c->nwt_e, c->nwt_e1, c->d_done};
         lp::launch_oseen_finalize(fn, 1, c->nodes_cns, st);
         lp::NewtonArgs na{c->cU[nw], c->cp[nw], c->nwt_e, c->nwt_e1, nc2, c->nc1, c->d_done, c->d_its, c->opt.newton_tol};

@@ -133,6 +133,14 @@ struct SolveArgs {
     const double *zero64;
 };
 
+struct DenseArgs {
+    const double *inv;            // nsys column-major n x n inverses
+    const double *b;              // nsys vectors of length n
+    double *x;                    // x_s = inv_s b_s
+    int n;
+    const int *skip;
+};
+
 struct MergeArgs {
     const SysDesc *sys;           // the region's subdomains (x fastest)
     int nsx, N, region;
@@ -197,6 +205,7 @@ template <typename T>
 bool launch_band_lu(const BandArgs<T> &a, int nsys, int maxbw, int variant, hipStream_t st);
 template <typename T>
 bool launch_band_solve(const SolveArgs<T> &a, int nsys, int nrhs, int maxbw, int maxn, hipStream_t st);
+void launch_dense_apply(const DenseArgs &a, int nsys, hipStream_t st);
 void launch_merge(const MergeArgs &a, hipStream_t st);
 void launch_init_corrections(const InitArgs &a, int nsys, hipStream_t st);
 void launch_newton_update(const NewtonArgs &a, hipStream_t st);

@@ -915,6 +915,29 @@ __global__ __launch_bounds__(64) void k_band_solve(SolveArgs<T> A) {
 }
 
 // ---------------------------------------------------------------------------
+// Dense application of explicit inverses (the small coarse systems): for each
+// system s, x_s = Ainv_s b_s with Ainv_s column-major, Ainv_s[f n + i].  A block
+// covers 64 rows; its four wavefronts split the columns and add their partial
+// sums in a fixed order.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_dense_apply(DenseArgs A) {
+    if (A.skip && *A.skip) return;
+    const int n = A.n, s = blockIdx.y;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + lane;
+    const int ic = i < n ? i : n - 1;
+    const double *inv = A.inv + (long long)s * n * n;
+    const double *b = A.b + (long long)s * n;
+    const int f0 = (n * w) >> 2, f1 = (n * (w + 1)) >> 2;
+    double acc = 0.0;
+    for (int f = f0; f < f1; ++f) acc += inv[(long long)f * n + ic] * b[f];
+    __shared__ double red[4][64];
+    red[w][lane] = acc;
+    __syncthreads();
+    if (w == 0 && i < n) A.x[(long long)s * n + i] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+}
+
+// ---------------------------------------------------------------------------
 // Partition-of-unity merge (Algorithm 3 Step 4): x_h = Pi_h x_H + sum_j w_j e_j
 // over the closed cores containing the node, ascending j.
 // ---------------------------------------------------------------------------
@@ -1087,6 +1110,10 @@ bool launch_band_solve(const SolveArgs<T> &a, int nsys, int nrhs, int maxbw, int
     else if (maxbw <= 256) hipLaunchKernelGGL((k_band_solve<T, 4, 16>), g, dim3(64), sh, st, a);
     else return false;
     return true;
+}
+
+void launch_dense_apply(const DenseArgs &a, int nsys, hipStream_t st) {
+    hipLaunchKernelGGL(k_dense_apply, dim3((a.n + 63) / 64, nsys), dim3(256), 0, st, a);
 }
 
 void launch_merge(const MergeArgs &a, hipStream_t st) {
