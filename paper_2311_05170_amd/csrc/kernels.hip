@@ -796,6 +796,13 @@ __global__ __launch_bounds__(TP *TP) void k_band_lu(BandArgs<T> B) {
 // entry is broadcast with readlane and every slot applies one factor entry.
 // With the slot-rotated factors each lane reads a fixed offset of the
 // current column, prefetched D columns ahead.
+//
+// Columns run in blocks of D with no branch inside a block, so the waits on
+// the prefetched factor loads count back exactly D columns.  The right-hand
+// side sits in LDS between zero pads (rows outside 0..n-1 read zero); the
+// entering rows of the next block are read from LDS one block ahead, and the
+// finished entries of a block are gathered into lanes 0..D-1 and stored with
+// one masked LDS write per block.
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ T wave_bcast(T v, int lane);
@@ -810,9 +817,13 @@ __device__ __forceinline__ double wave_bcast<double>(double v, int lane) {
     const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
     return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
 }
+// LDS pad (rows) on each side of the right-hand side: at least the largest
+// window (4 x 64) plus two blocks
+constexpr int SOLVE_PAD = 4 * 64 + 2 * 16;
 
 template <typename T, int NR, int D>
 __global__ __launch_bounds__(64) void k_band_solve(SolveArgs<T> A) {
+    static_assert(NR * 64 + 2 * D <= SOLVE_PAD, "pad too small");
     const int sysi = blockIdx.x, f = blockIdx.y;
     const BandSys Sy = A.sys[sysi];
     if (f >= Sy.nrhs) return;
@@ -820,7 +831,7 @@ __global__ __launch_bounds__(64) void k_band_solve(SolveArgs<T> A) {
     if (A.skip && *A.skip) return;
     if (A.conv && A.conv[id]) return;
     extern __shared__ unsigned char smem_raw[];
-    T *ys = reinterpret_cast<T *>(smem_raw);     // r, then y, then the correction d, by row
+    T *ys = reinterpret_cast<T *>(smem_raw) + SOLVE_PAD;   // r, then y, then the correction d, by row
     const int n = Sy.n, bw = Sy.bw;
     const int ws = bw > 0 ? bw : 1;
     const T *Lr = A.fac + Sy.off + (long long)f * Sy.stride;
@@ -828,21 +839,17 @@ __global__ __launch_bounds__(64) void k_band_solve(SolveArgs<T> A) {
     const double *rg = A.r + Sy.vec + (long long)f * n;
     double *x = A.x + Sy.vec + (long long)f * n;
     const int lane = threadIdx.x;
-    for (int i = lane; i < n; i += 64) ys[i] = (T)rg[i];
+    for (int i = lane - SOLVE_PAD; i < n + SOLVE_PAD; i += 64) ys[i] = (i >= 0 && i < n) ? (T)rg[i] : T(0);
     __syncthreads();
     // lanes whose slot is beyond the window read entry 0 of the column: their
     // window values are never extracted, so the loads stay unconditional
     int lo[NR];
-    bool act[NR];
 #pragma unroll
-    for (int m = 0; m < NR; ++m) {
-        act[m] = lane + 64 * m < ws;
-        lo[m] = act[m] ? lane + 64 * m : 0;
-    }
-    T win[NR], cf[D][NR];
+    for (int m = 0; m < NR; ++m) lo[m] = lane + 64 * m < ws ? lane + 64 * m : 0;
+    T win[NR], cf[D][NR], ent[D], nxt[D];
     // ---- forward: before step k the window holds rows k..k+ws-1 (row i in slot i mod ws)
 #pragma unroll
-    for (int m = 0; m < NR; ++m) win[m] = (act[m] && lane + 64 * m < n) ? ys[lane + 64 * m] : T(0);
+    for (int m = 0; m < NR; ++m) win[m] = lane + 64 * m < ws ? ys[lane + 64 * m] : T(0);
 #define LP_FCOL(KK, S)                                                                     \
     do {                                                                                   \
         const T *col = (KK) < n ? Lr + (long long)(KK) * ws : A.zero;                       \
@@ -850,35 +857,56 @@ __global__ __launch_bounds__(64) void k_band_solve(SolveArgs<T> A) {
     } while (0)
 #pragma unroll
     for (int s = 0; s < D; ++s) LP_FCOL(s, s);
+#pragma unroll
+    for (int s = 0; s < D; ++s) ent[s] = ys[s + ws];
     int sk = 0;
-    for (int k0 = 0; k0 < n; k0 += D) {
+    const int nfull = n - n % D;
+    for (int k0 = 0; k0 < nfull; k0 += D) {
+#pragma unroll
+        for (int s = 0; s < D; ++s) nxt[s] = ys[k0 + D + s + ws];
+        T yb = T(0);
 #pragma unroll
         for (int s = 0; s < D; ++s) {
             const int k = k0 + s;
-            if (k < n) {
-                const int ml = sk >> 6, ll = sk & 63;
-                T v = win[0];
+            const int ml = sk >> 6, ll = sk & 63;
+            T v = win[0];
 #pragma unroll
-                for (int m = 1; m < NR; ++m) v = m == ml ? win[m] : v;
-                const T yk = wave_bcast(v, ll);
-                const T enter = k + ws < n ? ys[k + ws] : T(0);
-                if (lane == 0) ys[k] = yk;
+            for (int m = 1; m < NR; ++m) v = m == ml ? win[m] : v;
+            const T yk = wave_bcast(v, ll);
+            yb = lane == s ? yk : yb;
 #pragma unroll
-                for (int m = 0; m < NR; ++m) win[m] = (lane + 64 * m == sk ? enter : win[m]) - cf[s][m] * yk;
-                sk = sk + 1 == ws ? 0 : sk + 1;
-                LP_FCOL(k + D, s);
-            }
+            for (int m = 0; m < NR; ++m) win[m] = (lane + 64 * m == sk ? ent[s] : win[m]) - cf[s][m] * yk;
+            sk = sk + 1 == ws ? 0 : sk + 1;
+            LP_FCOL(k + D, s);
         }
+        if (lane < D) ys[k0 + lane] = yb;
+#pragma unroll
+        for (int s = 0; s < D; ++s) ent[s] = nxt[s];
+    }
+    for (int s = 0; s < D; ++s) {                     // tail: the last n % D columns
+        const int k = nfull + s;
+        if (k >= n) break;
+        const int ml = sk >> 6, ll = sk & 63;
+        T v = win[0];
+#pragma unroll
+        for (int m = 1; m < NR; ++m) v = m == ml ? win[m] : v;
+        const T yk = wave_bcast(v, ll);
+        const T *col = Lr + (long long)k * ws;
+        const T e = ys[k + ws];
+        if (lane == 0) ys[k] = yk;
+#pragma unroll
+        for (int m = 0; m < NR; ++m) win[m] = (lane + 64 * m == sk ? e : win[m]) - col[lo[m]] * yk;
+        sk = sk + 1 == ws ? 0 : sk + 1;
     }
     __syncthreads();
     // ---- backward: before step k (descending) the window holds rows k-ws+1..k
-    const int k0 = n - 1;
+    const int kt = n - 1;
     T uf[D];
 #pragma unroll
     for (int m = 0; m < NR; ++m) {
         const int sl = lane + 64 * m;
-        const int j = ((k0 % ws) - sl + ws) % ws;           // distance below k0 of this slot's row
-        win[m] = (act[m] && k0 - j >= 0) ? ys[k0 - j] : T(0);
+        const int j = ((kt % ws) - sl + ws) % ws;           // distance below kt of this slot's row
+        win[m] = sl < ws ? ys[kt - j] : T(0);
     }
 #define LP_BCOL(KK, S)                                                                     \
     do {                                                                                   \
@@ -887,26 +915,47 @@ __global__ __launch_bounds__(64) void k_band_solve(SolveArgs<T> A) {
         uf[S] = *((KK) >= 0 ? Di + (KK) : A.one);                                          \
     } while (0)
 #pragma unroll
-    for (int s = 0; s < D; ++s) LP_BCOL(k0 - s, s);
-    sk = k0 % ws;
-    for (int kb = k0; kb >= 0; kb -= D) {
+    for (int s = 0; s < D; ++s) LP_BCOL(kt - s, s);
+#pragma unroll
+    for (int s = 0; s < D; ++s) ent[s] = ys[kt - s - ws];
+    sk = kt % ws;
+    const int bfull = n - n % D;                        // columns kt .. kt-bfull+1 in full blocks
+    for (int kb = kt; kb > kt - bfull; kb -= D) {
+#pragma unroll
+        for (int s = 0; s < D; ++s) nxt[s] = ys[kb - D - s - ws];
+        T db = T(0);
 #pragma unroll
         for (int s = 0; s < D; ++s) {
             const int k = kb - s;
-            if (k >= 0) {
-                const int ml = sk >> 6, ll = sk & 63;
-                T v = win[0];
+            const int ml = sk >> 6, ll = sk & 63;
+            T v = win[0];
 #pragma unroll
-                for (int m = 1; m < NR; ++m) v = m == ml ? win[m] : v;
-                const T dk = wave_bcast(v, ll) * uf[s];
-                const T enter = k - ws >= 0 ? ys[k - ws] : T(0);
-                if (lane == 0) ys[k] = dk;             // row k of y is consumed; keep d_k there
+            for (int m = 1; m < NR; ++m) v = m == ml ? win[m] : v;
+            const T dk = wave_bcast(v, ll) * uf[s];
+            db = lane == s ? dk : db;
 #pragma unroll
-                for (int m = 0; m < NR; ++m) win[m] = (lane + 64 * m == sk ? enter : win[m]) - cf[s][m] * dk;
-                sk = sk == 0 ? ws - 1 : sk - 1;
-                LP_BCOL(k - D, s);
-            }
+            for (int m = 0; m < NR; ++m) win[m] = (lane + 64 * m == sk ? ent[s] : win[m]) - cf[s][m] * dk;
+            sk = sk == 0 ? ws - 1 : sk - 1;
+            LP_BCOL(k - D, s);
         }
+        if (lane < D) ys[kb - lane] = db;                // row k of y is consumed; keep d_k there
+#pragma unroll
+        for (int s = 0; s < D; ++s) ent[s] = nxt[s];
+    }
+    for (int s = 0; s < D; ++s) {                     // tail: rows n%D-1 .. 0
+        const int k = kt - bfull - s;
+        if (k < 0) break;
+        const int ml = sk >> 6, ll = sk & 63;
+        T v = win[0];
+#pragma unroll
+        for (int m = 1; m < NR; ++m) v = m == ml ? win[m] : v;
+        const T dk = wave_bcast(v, ll) * Di[k];
+        const T *col = Ur + (long long)k * ws;
+        const T e = ys[k - ws];
+        if (lane == 0) ys[k] = dk;
+#pragma unroll
+        for (int m = 0; m < NR; ++m) win[m] = (lane + 64 * m == sk ? e : win[m]) - col[lo[m]] * dk;
+        sk = sk == 0 ? ws - 1 : sk - 1;
     }
     __syncthreads();
     for (int i = lane; i < n; i += 64) x[i] += (double)ys[i];
@@ -1102,7 +1151,7 @@ bool launch_band_lu(const BandArgs<T> &a, int nsys, int maxbw, int variant, hipS
 template <typename T>
 bool launch_band_solve(const SolveArgs<T> &a, int nsys, int nrhs, int maxbw, int maxn, hipStream_t st) {
     dim3 g(nsys, nrhs);
-    const size_t sh = (size_t)maxn * sizeof(T);
+    const size_t sh = (size_t)(maxn + 2 * SOLVE_PAD) * sizeof(T);
     if (sh > 160 * 1024) return false;
     if (maxbw <= 64) hipLaunchKernelGGL((k_band_solve<T, 1, 16>), g, dim3(64), sh, st, a);
     else if (maxbw <= 128) hipLaunchKernelGGL((k_band_solve<T, 2, 16>), g, dim3(64), sh, st, a);
