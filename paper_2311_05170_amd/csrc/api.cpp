@@ -93,7 +93,7 @@ struct lp_ctx {
     // identity right-hand sides that produce them, and their solve lists
     double *inv_cp = nullptr, *inv_cn = nullptr, *eye_cp = nullptr, *eye_cn = nullptr;
     lp::BandSys *d_iv_cpor = nullptr, *d_iv_cns = nullptr;
-    void *fac_por = nullptr, *fac_ose[2] = {};            // factors, same offsets as the bands
+    void *fac_por = nullptr, *fac_ose[2] = {};            // factors (layout: fac_layout)
     double *pro_Uf = nullptr;                            // u_cH^m prolonged for the factor stream
     double *fac_cpor = nullptr, *fac_cns = nullptr;
     double *b_por = nullptr, *x_por = nullptr, *r_por = nullptr;
@@ -114,6 +114,7 @@ struct lp_ctx {
     double *lu_dummy = nullptr;        // sink of the factorisation's masked stores
     long long lu_dummy_coarse_off = 0;
     int lu_variant = 0;                // tile shape of the local Oseen factorisation
+    int solve_depth = 32;              // factor columns prefetched by the band solves (16 or 32)
     // device constants read by masked loads: 512 zero doubles (a zero column
     // for the solves), then 1.0 as double, then 1.0f as float
     double *consts = nullptr;
@@ -206,32 +207,60 @@ struct StageTimer {
     }
 };
 
-std::vector<lp::BandSys> lu_list(const std::vector<lp::SysDesc> &v, int nmat) {
-    std::vector<lp::BandSys> out;
+// Factor storage of a batch: per (system, matrix) n (2 ldf + 1) entries,
+// ldf = 64 NR for the solve's NR registers per lane (L and U columns of ldf
+// entries, then 1/U(k,k)), each block rounded up to 64 entries.
+struct FacLayout {
+    std::vector<long long> off;
+    long long total = 0;
+    int ldf = 0;
+};
+
+FacLayout fac_layout(const std::vector<lp::SysDesc> &v, int nmat, int maxbw) {
+    FacLayout L;
+    L.ldf = 64 * lp::solve_nr(maxbw);
     for (const auto &s : v)
         for (int f = 0; f < nmat; ++f) {
+            L.off.push_back(L.total);
+            L.total += ((long long)s.ndof * (2 * L.ldf + 1) + 63) / 64 * 64;
+        }
+    return L;
+}
+
+std::vector<lp::BandSys> lu_list(const std::vector<lp::SysDesc> &v, int nmat, const FacLayout &L) {
+    std::vector<lp::BandSys> out;
+    size_t i = 0;
+    for (const auto &s : v)
+        for (int f = 0; f < nmat; ++f, ++i) {
             lp::BandSys b{};
             b.off = s.band_off + (long long)f * s.band_size;
             b.stride = s.band_size;
             b.vec = s.dof_off + (long long)f * s.ndof;
+            b.foff = L.off[i];
+            b.fstride = 0;
             b.n = s.ndof;
             b.bw = s.bw;
             b.nrhs = 1;
+            b.ldf = L.ldf;
             out.push_back(b);
         }
     return out;
 }
 
-std::vector<lp::BandSys> solve_list(const std::vector<lp::SysDesc> &v, int nrhs) {
+std::vector<lp::BandSys> solve_list(const std::vector<lp::SysDesc> &v, int nrhs, const FacLayout &L) {
     std::vector<lp::BandSys> out;
-    for (const auto &s : v) {
+    for (size_t j = 0; j < v.size(); ++j) {
+        const auto &s = v[j];
         lp::BandSys b{};
         b.off = s.band_off;
         b.stride = s.band_size;
         b.vec = s.dof_off;
+        b.foff = L.off[j * nrhs];
+        b.fstride = nrhs > 1 ? L.off[j * nrhs + 1] - L.off[j * nrhs] : 0;
         b.n = s.ndof;
         b.bw = s.bw;
         b.nrhs = nrhs;
+        b.ldf = L.ldf;
         out.push_back(b);
     }
     return out;
@@ -242,7 +271,7 @@ double time_at(const lp_ctx *c, int64_t step) { return (double)step * c->prm.dt;
 // solve list that turns nmat factored band matrices of system s into their
 // inverses: every right-hand side of matrix f shares its factors (stride 0)
 // and column j of the inverse is the solution for the j-th unit vector
-std::vector<lp::BandSys> inverse_list(const lp::SysDesc &s, int nmat) {
+std::vector<lp::BandSys> inverse_list(const lp::SysDesc &s, int nmat, const FacLayout &L) {
     std::vector<lp::BandSys> out;
     const long long n = s.ndof;
     for (int f = 0; f < nmat; ++f) {
@@ -250,9 +279,12 @@ std::vector<lp::BandSys> inverse_list(const lp::SysDesc &s, int nmat) {
         b.off = s.band_off + (long long)f * s.band_size;
         b.stride = 0;
         b.vec = (long long)f * n * n;
+        b.foff = L.off[f];
+        b.fstride = 0;
         b.n = s.ndof;
         b.bw = s.bw;
         b.nrhs = s.ndof;
+        b.ldf = L.ldf;
         out.push_back(b);
     }
     return out;
@@ -277,7 +309,7 @@ lp_status refine_porous(lp_ctx *c, const lp::SysDesc *d_sys, int nsys, int maxno
         {
             StageTimer tm(c, timed ? LP_T_POR_SOLVE : -1, st);
             lp::SolveArgs<T> sa{d_sv, fac, r, x, conv, 3, nullptr, (const T *)c->consts, c->const_one<T>(), (const double *)c->consts};
-            if (!lp::launch_band_solve<T>(sa, nsys, 3, maxbw, maxn, st)) return fail(LP_ERR_UNSUPPORTED, "bandwidth too large for the solve kernels");
+            if (!lp::launch_band_solve<T>(sa, nsys, 3, maxbw, maxn, c->solve_depth, st)) return fail(LP_ERR_UNSUPPORTED, "bandwidth too large for the solve kernels");
         }
         StageTimer tm(c, timed ? LP_T_POR_RES : -1, st);
         lp::ResidualArgs ra{d_sys, c->d_dof2, x, b, r, conv, rel, sw, tol, nullptr, part, ticket};
@@ -297,7 +329,7 @@ lp_status refine_oseen(lp_ctx *c, const lp::SysDesc *d_sys, int nsys, int maxnod
         {
             StageTimer tm(c, timed ? LP_T_OSE_SOLVE : -1, st);
             lp::SolveArgs<T> sa{d_sv, fac, r, x, conv, 1, skip, (const T *)c->consts, c->const_one<T>(), (const double *)c->consts};
-            if (!lp::launch_band_solve<T>(sa, nsys, 1, maxbw, maxn, st)) return fail(LP_ERR_UNSUPPORTED, "bandwidth too large for the solve kernels");
+            if (!lp::launch_band_solve<T>(sa, nsys, 1, maxbw, maxn, c->solve_depth, st)) return fail(LP_ERR_UNSUPPORTED, "bandwidth too large for the solve kernels");
         }
         StageTimer tm(c, timed ? LP_T_OSE_RES : -1, st);
         lp::OseenApplyArgs<double> ra{};
@@ -518,6 +550,7 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     c->opt = *opt;
     c->mixed = opt->precision == LP_MIXED;
     if (const char *v = std::getenv("LP_LU_VARIANT")) c->lu_variant = std::atoi(v);
+    if (const char *v = std::getenv("LP_SOLVE_DEPTH")) c->solve_depth = std::atoi(v) == 16 ? 16 : 32;
     if (alloc && alloc->alloc && alloc->free) { c->alloc = *alloc; c->has_alloc = true; }
     lp::Plan &P = c->P;
     for (const auto &s : P.por) { c->maxbw_por = std::max(c->maxbw_por, s.bw); c->maxn_por = std::max(c->maxn_por, s.ndof); }
@@ -555,14 +588,16 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     TRY(c->upload(&c->d_dof2, P.dof2, st));
     TRY(c->upload(&c->d_cls1, P.cls1, st));
     TRY(c->upload(&c->d_dof1, P.dof1, st));
-    TRY(c->upload(&c->d_lu_por, lu_list(P.por, 3), st));
-    TRY(c->upload(&c->d_lu_ose, lu_list(P.ose, 1), st));
-    TRY(c->upload(&c->d_lu_cpor, lu_list(cp, 3), st));
-    TRY(c->upload(&c->d_lu_cns, lu_list(cn, 1), st));
-    TRY(c->upload(&c->d_sv_por, solve_list(P.por, 3), st));
-    TRY(c->upload(&c->d_sv_ose, solve_list(P.ose, 1), st));
-    TRY(c->upload(&c->d_sv_cpor, solve_list(cp, 3), st));
-    TRY(c->upload(&c->d_sv_cns, solve_list(cn, 1), st));
+    const FacLayout fl_por = fac_layout(P.por, 3, c->maxbw_por), fl_ose = fac_layout(P.ose, 1, c->maxbw_ose);
+    const FacLayout fl_cpor = fac_layout(cp, 3, P.cpor.bw), fl_cns = fac_layout(cn, 1, P.cns.bw);
+    TRY(c->upload(&c->d_lu_por, lu_list(P.por, 3, fl_por), st));
+    TRY(c->upload(&c->d_lu_ose, lu_list(P.ose, 1, fl_ose), st));
+    TRY(c->upload(&c->d_lu_cpor, lu_list(cp, 3, fl_cpor), st));
+    TRY(c->upload(&c->d_lu_cns, lu_list(cn, 1, fl_cns), st));
+    TRY(c->upload(&c->d_sv_por, solve_list(P.por, 3, fl_por), st));
+    TRY(c->upload(&c->d_sv_ose, solve_list(P.ose, 1, fl_ose), st));
+    TRY(c->upload(&c->d_sv_cpor, solve_list(cp, 3, fl_cpor), st));
+    TRY(c->upload(&c->d_sv_cns, solve_list(cn, 1, fl_cns), st));
     for (int r = 0; r < 2; ++r)
         for (int ax = 0; ax < 2; ++ax) {
             TRY(c->upload(&c->d_own[r][ax][0], P.own2_lo[r][ax], st));
@@ -618,17 +653,17 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
         else if (hipMalloc(&p, P.band_total_ose * tb + 256) != hipSuccess) p = nullptr;
         if (!p) return fail(LP_ERR_ALLOC, "conduit band allocation failed");
         c->owned.push_back(p); c->band_ose = p;
-        if (c->has_alloc) { p = c->alloc.alloc(P.band_total_por * tb + 256, c->alloc.user); }
-        else if (hipMalloc(&p, P.band_total_por * tb + 256) != hipSuccess) p = nullptr;
+        if (c->has_alloc) { p = c->alloc.alloc(fl_por.total * tb + 256, c->alloc.user); }
+        else if (hipMalloc(&p, fl_por.total * tb + 256) != hipSuccess) p = nullptr;
         if (!p) return fail(LP_ERR_ALLOC, "porous factor allocation failed");
         c->owned.push_back(p); c->fac_por = p;
-        HIPCHK(hipMemsetAsync(p, 0, P.band_total_por * tb, st));
+        HIPCHK(hipMemsetAsync(p, 0, fl_por.total * tb, st));
         for (int l = 0; l < 2; ++l) {
-            if (c->has_alloc) { p = c->alloc.alloc(P.band_total_ose * tb + 256, c->alloc.user); }
-            else if (hipMalloc(&p, P.band_total_ose * tb + 256) != hipSuccess) p = nullptr;
+            if (c->has_alloc) { p = c->alloc.alloc(fl_ose.total * tb + 256, c->alloc.user); }
+            else if (hipMalloc(&p, fl_ose.total * tb + 256) != hipSuccess) p = nullptr;
             if (!p) return fail(LP_ERR_ALLOC, "conduit factor allocation failed");
             c->owned.push_back(p); c->fac_ose[l] = p;
-            HIPCHK(hipMemsetAsync(p, 0, P.band_total_ose * tb, st));
+            HIPCHK(hipMemsetAsync(p, 0, fl_ose.total * tb, st));
         }
     }
     {
@@ -645,10 +680,10 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     }
     TRY(c->dalloc(&c->band_cpor, P.cband_por));
     TRY(c->dalloc(&c->band_cns, P.cband_ns));
-    TRY(c->dalloc(&c->fac_cpor, P.cband_por));
-    TRY(c->dalloc(&c->fac_cns, P.cband_ns));
-    HIPCHK(hipMemsetAsync(c->fac_cpor, 0, P.cband_por * sizeof(double), st));
-    HIPCHK(hipMemsetAsync(c->fac_cns, 0, P.cband_ns * sizeof(double), st));
+    TRY(c->dalloc(&c->fac_cpor, fl_cpor.total + 32));
+    TRY(c->dalloc(&c->fac_cns, fl_cns.total + 32));
+    HIPCHK(hipMemsetAsync(c->fac_cpor, 0, fl_cpor.total * sizeof(double), st));
+    HIPCHK(hipMemsetAsync(c->fac_cns, 0, fl_cns.total * sizeof(double), st));
     TRY(c->dalloc(&c->b_por, P.dof_total_por)); TRY(c->dalloc(&c->x_por, P.dof_total_por)); TRY(c->dalloc(&c->r_por, P.dof_total_por));
     TRY(c->dalloc(&c->b_ose, P.dof_total_ose)); TRY(c->dalloc(&c->x_ose, P.dof_total_ose)); TRY(c->dalloc(&c->r_ose, P.dof_total_ose));
     const long long ncp = 3LL * P.cpor.ndof, ncn = P.cns.ndof;
@@ -717,15 +752,15 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
         // the coarse porous matrices are constant: invert them once
         const long long n = P.cpor.ndof;
         TRY(c->upload(&c->eye_cp, identities(n, 3), st));
-        TRY(c->upload(&c->d_iv_cpor, inverse_list(P.cpor, 3), st));
+        TRY(c->upload(&c->d_iv_cpor, inverse_list(P.cpor, 3, fl_cpor), st));
         TRY(c->dalloc(&c->inv_cp, 3 * n * n));
         HIPCHK(hipMemsetAsync(c->inv_cp, 0, 3 * n * n * sizeof(double), st));
         lp::SolveArgs<double> sa{c->d_iv_cpor, c->fac_cpor, c->eye_cp, c->inv_cp, nullptr, (int)n, nullptr,
                                  (const double *)c->consts, c->const_one<double>(), (const double *)c->consts};
-        if (!lp::launch_band_solve<double>(sa, 3, (int)n, P.cpor.bw, (int)n, st)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
+        if (!lp::launch_band_solve<double>(sa, 3, (int)n, P.cpor.bw, (int)n, c->solve_depth, st)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
         const long long m = P.cns.ndof;
         TRY(c->upload(&c->eye_cn, identities(m, 1), st));
-        TRY(c->upload(&c->d_iv_cns, inverse_list(P.cns, 1), st));
+        TRY(c->upload(&c->d_iv_cns, inverse_list(P.cns, 1, fl_cns), st));
         TRY(c->dalloc(&c->inv_cn, m * m));
     }
     HIPCHK(hipGetLastError());
@@ -806,7 +841,7 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
             HIPCHK(hipMemsetAsync(c->inv_cn, 0, (size_t)n * n * sizeof(double), st));
             lp::SolveArgs<double> sa{c->d_iv_cns, c->fac_cns, c->eye_cn, c->inv_cn, nullptr, n, c->d_done,
                                      (const double *)c->consts, c->const_one<double>(), (const double *)c->consts};
-            if (!lp::launch_band_solve<double>(sa, 1, n, P.cns.bw, n, st)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
+            if (!lp::launch_band_solve<double>(sa, 1, n, P.cns.bw, n, c->solve_depth, st)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
         }
         lp::DenseArgs da{c->inv_cn, c->b_cn, c->x_cn, P.cns.ndof, c->d_done};
         lp::launch_dense_apply(da, 1, st);

@@ -103,14 +103,20 @@ struct BandSys {
     long long off;                // band offset of the first matrix
     long long stride;             // distance between the matrices of one system
     long long vec;                // vector offset of the first right-hand side
-    int n, bw, nrhs, pad;
+    long long foff;               // factor offset of the first matrix
+    long long fstride;            // distance between the factors of the matrices of one system
+    int n, bw, nrhs;
+    int ldf;                      // factor column length, 64 x (solve registers per lane)
 };
+
+// window registers per lane of the band solve for a half-bandwidth (0: unsupported)
+inline int solve_nr(int maxbw) { return maxbw <= 64 ? 1 : maxbw <= 128 ? 2 : maxbw <= 192 ? 3 : maxbw <= 256 ? 4 : 0; }
 
 template <typename T>
 struct BandArgs {
     const BandSys *sys;
     const T *band;                // input band (read only)
-    T *fac;                       // factors (same offsets as the band, slot-rotated layout)
+    T *fac;                       // factors (offsets foff, lane-grouped slot-rotated layout)
     int *flags;
     const int *skip;
     T *dummy;                     // LU_DUMMY_PER_SYS elements per system: sink for masked stores
@@ -204,7 +210,7 @@ void launch_oseen_finalize(const FinalizeArgs &a, int nsys, int maxnodes, hipStr
 template <typename T>
 bool launch_band_lu(const BandArgs<T> &a, int nsys, int maxbw, int variant, hipStream_t st);
 template <typename T>
-bool launch_band_solve(const SolveArgs<T> &a, int nsys, int nrhs, int maxbw, int maxn, hipStream_t st);
+bool launch_band_solve(const SolveArgs<T> &a, int nsys, int nrhs, int maxbw, int maxn, int depth, hipStream_t st);
 void launch_dense_apply(const DenseArgs &a, int nsys, hipStream_t st);
 void launch_merge(const MergeArgs &a, hipStream_t st);
 void launch_init_corrections(const InitArgs &a, int nsys, hipStream_t st);

@@ -652,9 +652,13 @@ __global__ __launch_bounds__(TP *TP) void k_band_lu(BandArgs<T> B) {
     const int n = Sy.n, bw = Sy.bw, ld = 2 * bw + 1;
     const int ws = bw > 0 ? bw : 1;                 // slot count of the solve's window
     const T *M = B.band + Sy.off;
-    // factors, slot-rotated for the solves: Lr[k*ws + (i mod ws)] = L(i, k),
-    // Ur[j*ws + (i mod ws)] = U(i, j) (i < j), Di[k] = 1 / U(k, k)
-    T *Lr = B.fac + Sy.off, *Ur = Lr + (long long)n * ws, *Di = Ur + (long long)n * ws;
+    // factors, slot-rotated and lane-grouped for the solves: with slot
+    // s = i mod ws held by lane s mod 64 in register s / 64 (nrf registers per
+    // lane), pos(s) = (s mod 64) nrf + s / 64 and
+    //   Lr[k ldf + pos(i mod ws)] = L(i, k), Ur[j ldf + pos(i mod ws)] = U(i, j) (i < j),
+    //   Di[k] = 1 / U(k, k)
+    const int ldf = Sy.ldf, nrf = ldf >> 6;
+    T *Lr = B.fac + Sy.foff, *Ur = Lr + (long long)n * ldf, *Di = Ur + (long long)n * ldf;
     T *dummy = B.dummy + ((long long)blockIdx.x * NT + threadIdx.x) * NI;
     __shared__ T ubuf[2][W];       // pivot row by column slot
     __shared__ T lbuf[2][W];       // pivot column by row slot
@@ -684,14 +688,14 @@ __global__ __launch_bounds__(TP *TP) void k_band_lu(BandArgs<T> B) {
             const int d = W - 1 - q;
             foff[it] = (1 + q) * ld + d + bw;
             fend[it] = (d <= bw) ? min(n - W, n - 1 - q) : 0;
-            soff[it] = 0;                              // Lr + k*ws + srot, srot = (k + q) mod ws
+            soff[it] = 0;                              // Lr + k*ldf + pos(srot), srot = (k + q) mod ws
             srot[it] = q % ws;
             send[it] = (q >= 1 && q <= bw) ? n - q : 0;
         } else if (q < NE) {
             const int e = q - W, d = 1 + e - W;
             foff[it] = W * ld + d + bw;
             fend[it] = (d >= -bw) ? min(n - 1 - e, n - W) : 0;
-            soff[it] = e * ws;                         // Ur + (k+e)*ws + (k mod ws); e = 0 -> Di[k]
+            soff[it] = e * ldf;                        // Ur + (k+e)*ldf + pos(k mod ws); e = 0 -> Di[k]
             srot[it] = 0;
             send[it] = e <= bw ? n - e : 0;
         } else {
@@ -740,7 +744,7 @@ __global__ __launch_bounds__(TP *TP) void k_band_lu(BandArgs<T> B) {
             T piv = ubuf[buf][kmod];
             if (!(fabs((double)piv) > 0.0) || !isfinite((double)piv)) { bad = 1; piv = T(1); }
             const T inv = T(1) / piv;
-            const int kws_ = k * ws;
+            const int kl = k * ldf, pk = (kws & 63) * nrf + (kws >> 6);
 #pragma unroll
             for (int it = 0; it < NI; ++it) {
                 const bool isl = qq[it] < W;
@@ -749,8 +753,8 @@ __global__ __launch_bounds__(TP *TP) void k_band_lu(BandArgs<T> B) {
                 sl = sl >= W ? sl - W : sl;
                 const T lv = lbuf[buf][sl] * inv;
                 const T uv = o == 0 ? inv : ubuf[buf][sl];
-                T *ldst = Lr + (kws_ + srot[it]);
-                T *udst = o == 0 ? Di + k : Ur + (kws_ + soff[it] + kws);
+                T *ldst = Lr + (kl + (srot[it] & 63) * nrf + (srot[it] >> 6));
+                T *udst = o == 0 ? Di + k : Ur + (kl + soff[it] + pk);
                 T *dst = k < send[it] ? (isl ? ldst : udst) : dummy + it;
                 *dst = isl ? lv : uv;
                 srot[it] = srot[it] + 1 == ws ? 0 : srot[it] + 1;
@@ -819,11 +823,12 @@ __device__ __forceinline__ double wave_bcast<double>(double v, int lane) {
 }
 // LDS pad (rows) on each side of the right-hand side: at least the largest
 // window (4 x 64) plus two blocks
-constexpr int SOLVE_PAD = 4 * 64 + 2 * 16;
+constexpr int SOLVE_PAD = 4 * 64 + 2 * 32;
 
 template <typename T, int NR, int D>
 __global__ __launch_bounds__(64) void k_band_solve(SolveArgs<T> A) {
     static_assert(NR * 64 + 2 * D <= SOLVE_PAD, "pad too small");
+    static_assert(2 * D <= 64, "prefetched loads must fit the memory counter");
     const int sysi = blockIdx.x, f = blockIdx.y;
     const BandSys Sy = A.sys[sysi];
     if (f >= Sy.nrhs) return;
@@ -834,26 +839,28 @@ __global__ __launch_bounds__(64) void k_band_solve(SolveArgs<T> A) {
     T *ys = reinterpret_cast<T *>(smem_raw) + SOLVE_PAD;   // r, then y, then the correction d, by row
     const int n = Sy.n, bw = Sy.bw;
     const int ws = bw > 0 ? bw : 1;
-    const T *Lr = A.fac + Sy.off + (long long)f * Sy.stride;
-    const T *Ur = Lr + (long long)n * ws, *Di = Ur + (long long)n * ws;
+    const int ldf = 64 * NR;                       // factor column length (lane-grouped layout)
+    const T *Lr = A.fac + Sy.foff + (long long)f * Sy.fstride;
+    const T *Ur = Lr + (long long)n * ldf, *Di = Ur + (long long)n * ldf;
     const double *rg = A.r + Sy.vec + (long long)f * n;
     double *x = A.x + Sy.vec + (long long)f * n;
     const int lane = threadIdx.x;
     for (int i = lane - SOLVE_PAD; i < n + SOLVE_PAD; i += 64) ys[i] = (i >= 0 && i < n) ? (T)rg[i] : T(0);
     __syncthreads();
-    // lanes whose slot is beyond the window read entry 0 of the column: their
-    // window values are never extracted, so the loads stay unconditional
-    int lo[NR];
-#pragma unroll
-    for (int m = 0; m < NR; ++m) lo[m] = lane + 64 * m < ws ? lane + 64 * m : 0;
+    // lane l holds slots l + 64 m, stored at l NR + m of each factor column:
+    // one vector load per column (slots beyond the window hold values that are
+    // never extracted)
+    struct Grp { T v[NR]; };
+    const int lo = lane * NR;
     T win[NR], cf[D][NR], ent[D], nxt[D];
     // ---- forward: before step k the window holds rows k..k+ws-1 (row i in slot i mod ws)
 #pragma unroll
     for (int m = 0; m < NR; ++m) win[m] = lane + 64 * m < ws ? ys[lane + 64 * m] : T(0);
 #define LP_FCOL(KK, S)                                                                     \
     do {                                                                                   \
-        const T *col = (KK) < n ? Lr + (long long)(KK) * ws : A.zero;                       \
-        _Pragma("unroll") for (int m = 0; m < NR; ++m) cf[S][m] = col[lo[m]];                \
+        const T *col = (KK) < n ? Lr + (long long)(KK) * ldf : A.zero;                      \
+        const Grp g = *reinterpret_cast<const Grp *>(col + lo);                            \
+        _Pragma("unroll") for (int m = 0; m < NR; ++m) cf[S][m] = g.v[m];                   \
     } while (0)
 #pragma unroll
     for (int s = 0; s < D; ++s) LP_FCOL(s, s);
@@ -891,11 +898,11 @@ __global__ __launch_bounds__(64) void k_band_solve(SolveArgs<T> A) {
 #pragma unroll
         for (int m = 1; m < NR; ++m) v = m == ml ? win[m] : v;
         const T yk = wave_bcast(v, ll);
-        const T *col = Lr + (long long)k * ws;
+        const T *col = Lr + (long long)k * ldf;
         const T e = ys[k + ws];
         if (lane == 0) ys[k] = yk;
 #pragma unroll
-        for (int m = 0; m < NR; ++m) win[m] = (lane + 64 * m == sk ? e : win[m]) - col[lo[m]] * yk;
+        for (int m = 0; m < NR; ++m) win[m] = (lane + 64 * m == sk ? e : win[m]) - col[lo + m] * yk;
         sk = sk + 1 == ws ? 0 : sk + 1;
     }
     __syncthreads();
@@ -910,8 +917,9 @@ __global__ __launch_bounds__(64) void k_band_solve(SolveArgs<T> A) {
     }
 #define LP_BCOL(KK, S)                                                                     \
     do {                                                                                   \
-        const T *col = (KK) >= 0 ? Ur + (long long)(KK) * ws : A.zero;                      \
-        _Pragma("unroll") for (int m = 0; m < NR; ++m) cf[S][m] = col[lo[m]];                \
+        const T *col = (KK) >= 0 ? Ur + (long long)(KK) * ldf : A.zero;                     \
+        const Grp g = *reinterpret_cast<const Grp *>(col + lo);                            \
+        _Pragma("unroll") for (int m = 0; m < NR; ++m) cf[S][m] = g.v[m];                   \
         uf[S] = *((KK) >= 0 ? Di + (KK) : A.one);                                          \
     } while (0)
 #pragma unroll
@@ -950,11 +958,11 @@ __global__ __launch_bounds__(64) void k_band_solve(SolveArgs<T> A) {
 #pragma unroll
         for (int m = 1; m < NR; ++m) v = m == ml ? win[m] : v;
         const T dk = wave_bcast(v, ll) * Di[k];
-        const T *col = Ur + (long long)k * ws;
+        const T *col = Ur + (long long)k * ldf;
         const T e = ys[k - ws];
         if (lane == 0) ys[k] = dk;
 #pragma unroll
-        for (int m = 0; m < NR; ++m) win[m] = (lane + 64 * m == sk ? e : win[m]) - col[lo[m]] * dk;
+        for (int m = 0; m < NR; ++m) win[m] = (lane + 64 * m == sk ? e : win[m]) - col[lo + m] * dk;
         sk = sk == 0 ? ws - 1 : sk - 1;
     }
     __syncthreads();
@@ -1148,17 +1156,26 @@ bool launch_band_lu(const BandArgs<T> &a, int nsys, int maxbw, int variant, hipS
     return false;
 }
 
-template <typename T>
-bool launch_band_solve(const SolveArgs<T> &a, int nsys, int nrhs, int maxbw, int maxn, hipStream_t st) {
+template <typename T, int D>
+bool launch_band_solve_d(const SolveArgs<T> &a, int nsys, int nrhs, int maxbw, int maxn, hipStream_t st) {
     dim3 g(nsys, nrhs);
     const size_t sh = (size_t)(maxn + 2 * SOLVE_PAD) * sizeof(T);
     if (sh > 160 * 1024) return false;
-    if (maxbw <= 64) hipLaunchKernelGGL((k_band_solve<T, 1, 16>), g, dim3(64), sh, st, a);
-    else if (maxbw <= 128) hipLaunchKernelGGL((k_band_solve<T, 2, 16>), g, dim3(64), sh, st, a);
-    else if (maxbw <= 192) hipLaunchKernelGGL((k_band_solve<T, 3, 16>), g, dim3(64), sh, st, a);
-    else if (maxbw <= 256) hipLaunchKernelGGL((k_band_solve<T, 4, 16>), g, dim3(64), sh, st, a);
-    else return false;
+    switch (solve_nr(maxbw)) {
+    case 1: hipLaunchKernelGGL((k_band_solve<T, 1, D>), g, dim3(64), sh, st, a); break;
+    case 2: hipLaunchKernelGGL((k_band_solve<T, 2, D>), g, dim3(64), sh, st, a); break;
+    case 3: hipLaunchKernelGGL((k_band_solve<T, 3, D>), g, dim3(64), sh, st, a); break;
+    case 4: hipLaunchKernelGGL((k_band_solve<T, 4, D>), g, dim3(64), sh, st, a); break;
+    default: return false;
+    }
     return true;
+}
+
+// depth: columns of factor prefetch (16 or 32)
+template <typename T>
+bool launch_band_solve(const SolveArgs<T> &a, int nsys, int nrhs, int maxbw, int maxn, int depth, hipStream_t st) {
+    return depth == 16 ? launch_band_solve_d<T, 16>(a, nsys, nrhs, maxbw, maxn, st)
+                       : launch_band_solve_d<T, 32>(a, nsys, nrhs, maxbw, maxn, st);
 }
 
 void launch_dense_apply(const DenseArgs &a, int nsys, hipStream_t st) {
@@ -1186,7 +1203,7 @@ template void launch_oseen_assemble<float>(const OseenApplyArgs<float> &, int, i
 template void launch_oseen_assemble<double>(const OseenApplyArgs<double> &, int, int, hipStream_t);
 template bool launch_band_lu<float>(const BandArgs<float> &, int, int, int, hipStream_t);
 template bool launch_band_lu<double>(const BandArgs<double> &, int, int, int, hipStream_t);
-template bool launch_band_solve<float>(const SolveArgs<float> &, int, int, int, int, hipStream_t);
-template bool launch_band_solve<double>(const SolveArgs<double> &, int, int, int, int, hipStream_t);
+template bool launch_band_solve<float>(const SolveArgs<float> &, int, int, int, int, int, hipStream_t);
+template bool launch_band_solve<double>(const SolveArgs<double> &, int, int, int, int, int, hipStream_t);
 
 }  // namespace lp
