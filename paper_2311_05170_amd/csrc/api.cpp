@@ -40,22 +40,27 @@ struct lp_ctx {
     std::vector<void *> owned;
     int64_t n = 0;                 // completed local steps
     bool coarse_pending = false;
-    // Coarse states live in a ring of three slots (time m in slot m % 3).  The
-    // coarse step runs on an internal stream: it never reads local results,
-    // so step m+1 of T_H can overlap the local stage of step m.  A slot is
-    // rewritten only after the local step that last reads it has finished.
-    static constexpr int RING = 3;
+    // Coarse states live in a ring of RING slots (time m in slot m % RING).
+    // The coarse step runs on an internal stream: it never reads local
+    // results, so coarse steps run ahead of the local stage (up to RING - 2
+    // steps).  A slot is rewritten only after the local step that last reads
+    // it has finished.
+    static constexpr int RING = 5;
+    static constexpr int FSLOTS = 3;   // factor slots of the local Oseen operators (< RING)
     hipStream_t cstream = nullptr;
     hipEvent_t ev_coarse[RING] = {}, ev_local[RING] = {};
     // the local porous batch runs on its own stream beside the Oseen batch
     hipStream_t pstream = nullptr;
     hipEvent_t ev_pro = nullptr, ev_por = nullptr;
     // The local Oseen operator of step m depends only on u_cH^m, so its
-    // assembly and factorisation run on a third stream as soon as coarse step
-    // m is done, overlapping the solves of step m-1.  Factors of step m go to
-    // slot m % 2.
-    hipStream_t fstream = nullptr;
-    hipEvent_t ev_fac[2] = {};
+    // assembly and factorisation run on factor stream m % 2 as soon as coarse
+    // step m is done, overlapping the solves of step m-1 and the factorisation
+    // of step m-1 (one workgroup per system leaves most CUs to the other).
+    // Band and prolonged velocity of step m use slot m % 2 (ordered by the
+    // stream), factors slot m % FSLOTS, rewritten once local step m - FSLOTS
+    // has finished.
+    hipStream_t fstream[2] = {};
+    hipEvent_t ev_fac[FSLOTS] = {};
     int ecur = 0;                  // correction buffers holding e^n
     bool mixed = false;
 
@@ -87,14 +92,14 @@ struct lp_ctx {
     double *m_P = nullptr, *m_U = nullptr, *m_p = nullptr;
 
     // linear algebra storage
-    void *band_por = nullptr, *band_ose = nullptr;        // float (mixed) or double
+    void *band_por = nullptr, *band_ose[2] = {};          // float (mixed) or double
     double *band_cpor = nullptr, *band_cns = nullptr;
     // explicit inverses of the small coarse matrices (column-major), the
     // identity right-hand sides that produce them, and their solve lists
     double *inv_cp = nullptr, *inv_cn = nullptr, *eye_cp = nullptr, *eye_cn = nullptr;
     lp::BandSys *d_iv_cpor = nullptr, *d_iv_cns = nullptr;
-    void *fac_por = nullptr, *fac_ose[2] = {};            // factors (layout: fac_layout)
-    double *pro_Uf = nullptr;                            // u_cH^m prolonged for the factor stream
+    void *fac_por = nullptr, *fac_ose[FSLOTS] = {};       // factors (layout: fac_layout)
+    double *pro_Uf[2] = {};                              // u_cH^m prolonged for factor stream m % 2
     double *fac_cpor = nullptr, *fac_cns = nullptr;
     double *b_por = nullptr, *x_por = nullptr, *r_por = nullptr;
     double *b_ose = nullptr, *x_ose = nullptr, *r_ose = nullptr;
@@ -146,8 +151,9 @@ struct lp_ctx {
         }
         if (cstream) (void)hipStreamDestroy(cstream);
         if (pstream) { (void)hipStreamSynchronize(pstream); (void)hipStreamDestroy(pstream); }
-        if (fstream) { (void)hipStreamSynchronize(fstream); (void)hipStreamDestroy(fstream); }
         for (int i = 0; i < 2; ++i)
+            if (fstream[i]) { (void)hipStreamSynchronize(fstream[i]); (void)hipStreamDestroy(fstream[i]); }
+        for (int i = 0; i < FSLOTS; ++i)
             if (ev_fac[i]) (void)hipEventDestroy(ev_fac[i]);
         if (ev_pro) (void)hipEventDestroy(ev_pro);
         if (ev_por) (void)hipEventDestroy(ev_por);
@@ -377,7 +383,7 @@ lp_status local_oseen(lp_ctx *c, hipStream_t st) {
         lp::launch_oseen_rhs(oa, nsys, c->nodes_ose, st);
     }
     // factors of the operator linearised about Pi_h u_cH^{n+1} (factor stream)
-    const int fs = (int)((c->n + 1) % 2);
+    const int fs = (int)((c->n + 1) % lp_ctx::FSLOTS);
     HIPCHK(hipStreamWaitEvent(st, c->ev_fac[fs], 0));
     TRY(refine_oseen<T>(c, c->d_ose, nsys, c->nodes_ose, c->part_ose, c->tick_ose, c->d_sv_ose, (const T *)c->fac_ose[fs], c->maxbw_ose, c->maxn_ose, oa.W1[0], oa.W1[1], c->b_ose,
                         c->x_ose, c->r_ose, c->conv_ose, c->rel_ose, c->sw_ose, c->P.dof_total_ose, c->opt.max_ir,
@@ -394,22 +400,25 @@ lp_status local_oseen(lp_ctx *c, hipStream_t st) {
 // before coarse step m started.
 template <typename T>
 lp_status factor_oseen(lp_ctx *c, int64_t m) {
-    hipStream_t st = c->fstream;
-    const int nw = (int)(m % lp_ctx::RING), fs = (int)(m % 2);
+    const int nw = (int)(m % lp_ctx::RING), bs = (int)(m % 2), fs = (int)(m % lp_ctx::FSLOTS);
+    hipStream_t st = c->fstream[bs];
     const int nsys = (int)c->P.ose.size();
     HIPCHK(hipStreamWaitEvent(st, c->ev_coarse[nw], 0));
-    T *band = (T *)c->band_ose;
+    // factor slot fs was last read by local step m - FSLOTS
+    if (m > lp_ctx::FSLOTS) HIPCHK(hipStreamWaitEvent(st, c->ev_local[(m - lp_ctx::FSLOTS) % lp_ctx::RING], 0));
+    T *band = (T *)c->band_ose[bs];
+    double *pro_Uf = c->pro_Uf[bs];
     {
         StageTimer tm(c, LP_T_OSE_ASM, st);
         lp::ProlongArgs pa{};
         pa.NH = c->P.NH; pa.Nh = c->P.Nh; pa.k = c->P.k;
         pa.nfields = 2;
-        for (int cc = 0; cc < 2; ++cc) { pa.src[cc] = c->cU[nw] + cc * c->nc2; pa.dst[cc] = c->pro_Uf + cc * c->nf2; }
+        for (int cc = 0; cc < 2; ++cc) { pa.src[cc] = c->cU[nw] + cc * c->nc2; pa.dst[cc] = pro_Uf + cc * c->nf2; }
         lp::launch_prolong_p2(pa, st);
         HIPCHK(hipMemsetAsync(band, 0, (size_t)c->P.band_total_ose * sizeof(T), st));
         lp::OseenApplyArgs<T> aa{};
         aa.sys = c->d_ose; aa.cls2 = c->d_cls2; aa.dof2 = c->d_dof2; aa.dof1 = c->d_dof1;
-        aa.W1[0] = c->pro_Uf; aa.W1[1] = c->pro_Uf + c->nf2; aa.band = band;
+        aa.W1[0] = pro_Uf; aa.W1[1] = pro_Uf + c->nf2; aa.band = band;
         lp::launch_oseen_assemble<T>(aa, nsys, c->nodes_ose, st);
     }
     {
@@ -637,7 +646,7 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     TRY(c->dalloc(&c->pro_U1, 2 * c->nf2));
     TRY(c->dalloc(&c->pro_U0, 2 * c->nf2));
     TRY(c->dalloc(&c->pro_p1, c->nf1));
-    TRY(c->dalloc(&c->pro_Uf, 2 * c->nf2));
+    for (int l = 0; l < 2; ++l) TRY(c->dalloc(&c->pro_Uf[l], 2 * c->nf2));
     for (int l = 0; l < 2; ++l) { TRY(c->dalloc(&c->e2[l], P.e2_total)); TRY(c->dalloc(&c->e1[l], P.e1_total)); }
     TRY(c->dalloc(&c->m_P, 3 * c->nf2));
     TRY(c->dalloc(&c->m_U, 2 * c->nf2));
@@ -649,16 +658,18 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
         else if (hipMalloc(&p, P.band_total_por * tb + 256) != hipSuccess) p = nullptr;
         if (!p) return fail(LP_ERR_ALLOC, "porous band allocation failed");
         c->owned.push_back(p); c->band_por = p;
-        if (c->has_alloc) { p = c->alloc.alloc(P.band_total_ose * tb + 256, c->alloc.user); }
-        else if (hipMalloc(&p, P.band_total_ose * tb + 256) != hipSuccess) p = nullptr;
-        if (!p) return fail(LP_ERR_ALLOC, "conduit band allocation failed");
-        c->owned.push_back(p); c->band_ose = p;
+        for (int l = 0; l < 2; ++l) {
+            if (c->has_alloc) { p = c->alloc.alloc(P.band_total_ose * tb + 256, c->alloc.user); }
+            else if (hipMalloc(&p, P.band_total_ose * tb + 256) != hipSuccess) p = nullptr;
+            if (!p) return fail(LP_ERR_ALLOC, "conduit band allocation failed");
+            c->owned.push_back(p); c->band_ose[l] = p;
+        }
         if (c->has_alloc) { p = c->alloc.alloc(fl_por.total * tb + 256, c->alloc.user); }
         else if (hipMalloc(&p, fl_por.total * tb + 256) != hipSuccess) p = nullptr;
         if (!p) return fail(LP_ERR_ALLOC, "porous factor allocation failed");
         c->owned.push_back(p); c->fac_por = p;
         HIPCHK(hipMemsetAsync(p, 0, fl_por.total * tb, st));
-        for (int l = 0; l < 2; ++l) {
+        for (int l = 0; l < lp_ctx::FSLOTS; ++l) {
             if (c->has_alloc) { p = c->alloc.alloc(fl_ose.total * tb + 256, c->alloc.user); }
             else if (hipMalloc(&p, fl_ose.total * tb + 256) != hipSuccess) p = nullptr;
             if (!p) return fail(LP_ERR_ALLOC, "conduit factor allocation failed");
@@ -714,8 +725,8 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     c->ecur = 0;
     HIPCHK(hipStreamCreateWithFlags(&c->cstream, hipStreamNonBlocking));
     HIPCHK(hipStreamCreateWithFlags(&c->pstream, hipStreamNonBlocking));
-    HIPCHK(hipStreamCreateWithFlags(&c->fstream, hipStreamNonBlocking));
-    for (int i = 0; i < 2; ++i) HIPCHK(hipEventCreateWithFlags(&c->ev_fac[i], hipEventDisableTiming));
+    for (int l = 0; l < 2; ++l) HIPCHK(hipStreamCreateWithFlags(&c->fstream[l], hipStreamNonBlocking));
+    for (int i = 0; i < lp_ctx::FSLOTS; ++i) HIPCHK(hipEventCreateWithFlags(&c->ev_fac[i], hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&c->ev_pro, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&c->ev_por, hipEventDisableTiming));
     for (int i = 0; i < lp_ctx::RING; ++i) {
@@ -778,7 +789,8 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
     (void)stream;   // the coarse stage only touches internal state and runs on the context's own stream
     hipStream_t st = c->cstream;
     const int64_t m = c->n + 1;                       // time level produced
-    if (m >= 3) HIPCHK(hipStreamWaitEvent(st, c->ev_local[(m - 2) % lp_ctx::RING], 0));
+    // slot m % RING was last read by local step m - RING + 1
+    if (m >= lp_ctx::RING) HIPCHK(hipStreamWaitEvent(st, c->ev_local[(m - lp_ctx::RING + 1) % lp_ctx::RING], 0));
     StageTimer ttot(c, LP_T_COARSE, st);
     const lp::Plan &P = c->P;
     const int o = (int)((m - 1) % lp_ctx::RING), nw = (int)(m % lp_ctx::RING);

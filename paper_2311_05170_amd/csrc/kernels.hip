@@ -974,24 +974,36 @@ __global__ __launch_bounds__(64) void k_band_solve(SolveArgs<T> A) {
 // ---------------------------------------------------------------------------
 // Dense application of explicit inverses (the small coarse systems): for each
 // system s, x_s = Ainv_s b_s with Ainv_s column-major, Ainv_s[f n + i].  A block
-// covers 64 rows; its four wavefronts split the columns and add their partial
-// sums in a fixed order.
+// covers 64 rows; its 16 wavefronts split the columns (each a contiguous
+// range, eight loads in flight per lane) and their partial sums are added in
+// wavefront order.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_dense_apply(DenseArgs A) {
+__global__ __launch_bounds__(1024) void k_dense_apply(DenseArgs A) {
     if (A.skip && *A.skip) return;
     const int n = A.n, s = blockIdx.y;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int i = blockIdx.x * 64 + lane;
     const int ic = i < n ? i : n - 1;
-    const double *inv = A.inv + (long long)s * n * n;
+    const double *inv = A.inv + (long long)s * n * n + ic;
     const double *b = A.b + (long long)s * n;
-    const int f0 = (n * w) >> 2, f1 = (n * (w + 1)) >> 2;
-    double acc = 0.0;
-    for (int f = f0; f < f1; ++f) acc += inv[(long long)f * n + ic] * b[f];
-    __shared__ double red[4][64];
-    red[w][lane] = acc;
+    const int f0 = (n * w) >> 4, f1 = (n * (w + 1)) >> 4;
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int f = f0;
+    for (; f + 8 <= f1; f += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] += inv[(long long)(f + u) * n] * b[f + u];
+    }
+    for (; f < f1; ++f) acc[0] += inv[(long long)f * n] * b[f];
+    const double a = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    __shared__ double red[16][64];
+    red[w][lane] = a;
     __syncthreads();
-    if (w == 0 && i < n) A.x[(long long)s * n + i] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+    if (w == 0 && i < n) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) t += red[k][lane];
+        A.x[(long long)s * n + i] = t;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1179,7 +1191,7 @@ bool launch_band_solve(const SolveArgs<T> &a, int nsys, int nrhs, int maxbw, int
 }
 
 void launch_dense_apply(const DenseArgs &a, int nsys, hipStream_t st) {
-    hipLaunchKernelGGL(k_dense_apply, dim3((a.n + 63) / 64, nsys), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_dense_apply, dim3((a.n + 63) / 64, nsys), dim3(1024), 0, st, a);
 }
 
 void launch_merge(const MergeArgs &a, hipStream_t st) {
