@@ -118,7 +118,8 @@ struct lp_ctx {
     int *tick_por = nullptr, *tick_ose = nullptr, *tick_cp = nullptr, *tick_cn = nullptr;
     double *lu_dummy = nullptr;        // sink of the factorisation's masked stores
     long long lu_dummy_coarse_off = 0;
-    int lu_variant = 0;                // tile shape of the local Oseen factorisation
+    int lu_variant = 0;                // factorisation kernel of the porous and coarse systems (0: default)
+    int lu_variant_ose = 0;            // of the local Oseen systems (mixed: 8, the blocked MFMA kernel)
     int solve_depth = 32;              // factor columns prefetched by the band solves (16 or 32)
     // device constants read by masked loads: 512 zero doubles (a zero column
     // for the solves), then 1.0 as double, then 1.0f as float
@@ -353,8 +354,8 @@ template <typename T>
 lp_status factor_porous(lp_ctx *c, T *band, T *fac, hipStream_t st) {
     lp::AssembleArgs<T> aa{c->d_por, c->d_dof2, band};
     lp::launch_porous_assemble<T>(aa, (int)c->P.por.size(), st);
-    lp::BandArgs<T> ba{c->d_lu_por, band, fac, c->d_flags, nullptr, (T *)c->lu_dummy, (const T *)c->consts};
-    if (!lp::launch_band_lu<T>(ba, 3 * (int)c->P.por.size(), c->maxbw_por, 0, st))
+    lp::BandArgs<T> ba{c->d_lu_por, band, fac, c->d_flags, nullptr, (T *)c->lu_dummy, (const T *)c->consts, c->const_one<T>()};
+    if (!lp::launch_band_lu<T>(ba, 3 * (int)c->P.por.size(), c->maxbw_por, c->lu_variant, st))
         return fail(LP_ERR_UNSUPPORTED, "porous bandwidth exceeds the factorisation kernels");
     return LP_OK;
 }
@@ -380,7 +381,7 @@ lp_status local_oseen(lp_ctx *c, hipStream_t st) {
     oa.skip = nullptr;
     {
         StageTimer tm(c, LP_T_OSE_RHS, st);
-        lp::launch_oseen_rhs(oa, nsys, c->nodes_ose, st);
+        lp::launch_oseen_rhs(oa, nsys, c->nodes_ose, 1, st);
     }
     // factors of the operator linearised about Pi_h u_cH^{n+1} (factor stream)
     const int fs = (int)((c->n + 1) % lp_ctx::FSLOTS);
@@ -423,8 +424,9 @@ lp_status factor_oseen(lp_ctx *c, int64_t m) {
     }
     {
         StageTimer tm(c, LP_T_OSE_LU, st);
-        lp::BandArgs<T> ba{c->d_lu_ose, band, (T *)c->fac_ose[fs], c->d_flags, nullptr, (T *)c->lu_dummy, (const T *)c->consts};
-        if (!lp::launch_band_lu<T>(ba, nsys, c->maxbw_ose, c->lu_variant, st))
+        lp::BandArgs<T> ba{c->d_lu_ose, band, (T *)c->fac_ose[fs], c->d_flags, nullptr, (T *)c->lu_dummy, (const T *)c->consts,
+                           c->const_one<T>()};
+        if (!lp::launch_band_lu<T>(ba, nsys, c->maxbw_ose, c->lu_variant_ose, st))
             return fail(LP_ERR_UNSUPPORTED, "conduit bandwidth exceeds the factorisation kernels");
     }
     HIPCHK(hipEventRecord(c->ev_fac[fs], st));
@@ -558,7 +560,8 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     c->prm = *prm;
     c->opt = *opt;
     c->mixed = opt->precision == LP_MIXED;
-    if (const char *v = std::getenv("LP_LU_VARIANT")) c->lu_variant = std::atoi(v);
+    c->lu_variant_ose = c->mixed ? 8 : 0;
+    if (const char *v = std::getenv("LP_LU_VARIANT")) c->lu_variant = c->lu_variant_ose = std::atoi(v);
     if (const char *v = std::getenv("LP_SOLVE_DEPTH")) c->solve_depth = std::atoi(v) == 16 ? 16 : 32;
     if (alloc && alloc->alloc && alloc->free) { c->alloc = *alloc; c->has_alloc = true; }
     lp::Plan &P = c->P;
@@ -758,8 +761,8 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
         lp::AssembleArgs<double> aa{c->d_cpor, c->d_dof2, c->band_cpor};
         lp::launch_porous_assemble<double>(aa, 1, st);
         lp::BandArgs<double> ba{c->d_lu_cpor, c->band_cpor, c->fac_cpor, c->d_flags, nullptr, c->lu_dummy + c->lu_dummy_coarse_off,
-                                (const double *)c->consts};
-        if (!lp::launch_band_lu<double>(ba, 3, P.cpor.bw, 0, st)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
+                                (const double *)c->consts, c->const_one<double>()};
+        if (!lp::launch_band_lu<double>(ba, 3, P.cpor.bw, c->lu_variant, st)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
         // the coarse porous matrices are constant: invert them once
         const long long n = P.cpor.ndof;
         TRY(c->upload(&c->eye_cp, identities(n, 3), st));
@@ -835,7 +838,7 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
         oa.b = c->b_cn;
         for (int k = 0; k < 3; ++k) oa.tf[k] = tf[k];
         oa.skip = c->d_done;
-        lp::launch_oseen_rhs(oa, 1, c->nodes_cns, st);
+        lp::launch_oseen_rhs(oa, 1, c->nodes_cns, 8, st);
         if (it == 0) {
             // Jacobian at the first iterate (u^n); later iterations reuse its
             // factors, with residuals of the current Jacobian (chord steps)
@@ -845,8 +848,8 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
             aa.W1[0] = oa.W1[0]; aa.W1[1] = oa.W1[1]; aa.band = c->band_cns; aa.skip = c->d_done;
             lp::launch_oseen_assemble<double>(aa, 1, c->nodes_cns, st);
             lp::BandArgs<double> ba{c->d_lu_cns, c->band_cns, c->fac_cns, c->d_flags, c->d_done, c->lu_dummy + c->lu_dummy_coarse_off,
-                                    (const double *)c->consts};
-            if (!lp::launch_band_lu<double>(ba, 1, P.cns.bw, 0, st)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
+                                    (const double *)c->consts, c->const_one<double>()};
+            if (!lp::launch_band_lu<double>(ba, 1, P.cns.bw, c->lu_variant, st)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
             // explicit inverse of the Jacobian: each chord step is then one
             // dense product instead of a serial band solve
             const int n = P.cns.ndof;

@@ -121,6 +121,7 @@ struct BandArgs {
     const int *skip;
     T *dummy;                     // LU_DUMMY_PER_SYS elements per system: sink for masked stores
     const T *zero;                // a device zero, read by masked prefetches
+    const T *one;                 // a device one (identity padding beyond n)
 };
 
 constexpr long long LU_DUMMY_PER_SYS = 1024;
@@ -202,7 +203,8 @@ void launch_porous_residual(const ResidualArgs &a, int nsys, int maxnodes, hipSt
 void launch_porous_finalize(const FinalizeArgs &a, int nsys, int maxnodes, hipStream_t st);
 template <typename T>
 void launch_porous_assemble(const AssembleArgs<T> &a, int nsys, hipStream_t st);
-void launch_oseen_rhs(const OseenArgs &a, int nsys, int maxnodes, hipStream_t st);
+// split: lanes per node (1, or 8 for small problems: one lane per adjacent triangle)
+void launch_oseen_rhs(const OseenArgs &a, int nsys, int maxnodes, int split, hipStream_t st);
 template <typename T>
 void launch_oseen_assemble(const OseenApplyArgs<T> &a, int nsys, int maxnodes, hipStream_t st);
 void launch_oseen_residual(const OseenApplyArgs<double> &a, int nsys, int maxnodes, hipStream_t st);

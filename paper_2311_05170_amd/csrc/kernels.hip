@@ -355,31 +355,72 @@ __device__ __forceinline__ void conv_rows(int t, int la, double h, const double 
     for (int c = 0; c < 2; ++c) { cW[c] *= h; Nz[c] *= h; }
 }
 
+// The e-th triangle (e = 0..5) around box-local P2 node (a, b), in the order
+// for_elements visits them; false if the node has fewer.
+__device__ __forceinline__ bool nth_element(int a, int b, int cx, int cy, int e, int &t_, int &ci_, int &cj_, int &la_) {
+    const int ci0 = (a - 1) >> 1 < 0 ? 0 : ((a - 1) >> 1);
+    const int ci1 = (a >> 1) < cx ? (a >> 1) : cx - 1;
+    const int cj0 = (b - 1) >> 1 < 0 ? 0 : ((b - 1) >> 1);
+    const int cj1 = (b >> 1) < cy ? (b >> 1) : cy - 1;
+    int cnt = 0;
+    bool found = false;
+    for (int cj = cj0; cj <= cj1; ++cj)
+        for (int ci = ci0; ci <= ci1; ++ci) {
+            const int la = a - 2 * ci, lb = b - 2 * cj;
+            if (la < 0 || la > 2 || lb < 0 || lb > 2) continue;
+            for (int t = 0; t < 2; ++t) {
+                const int k = p2_local(t, la, lb);
+                if (k >= 0) {
+                    if (cnt == e) { t_ = t; ci_ = ci; cj_ = cj; la_ = k; found = true; }
+                    ++cnt;
+                }
+            }
+        }
+    return found;
+}
+
+// sum over the SPLIT consecutive lanes of a node group
+template <int SPLIT>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+    for (int o = SPLIT / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, SPLIT);
+    return v;
+}
+
+// SPLIT = 1: one thread per node walks the node's triangles.  SPLIT = 8: eight
+// lanes per node, lane e takes the e-th triangle and the group adds up (for
+// the small coarse problem, where a thread per node leaves the chip idle and
+// the per-node work is the latency).
+template <int SPLIT>
 __global__ __launch_bounds__(GB) void k_oseen_rhs(OseenArgs A) {
+    static_assert(GB % SPLIT == 0, "node groups within a block");
     const SysDesc S = A.sys[blockIdx.y];
     if (A.skip && *A.skip) return;
     const int nloc = S.lw2 * S.lh2;
     const int ng = 2 * S.N + 1, ng1 = S.N + 1;
     const double h = S.h, h2 = h * h;
     const double eta = c_co.eta, edt = c_co.eta / c_co.dt, nue = c_co.nu * c_co.eta;
-    for (int q = blockIdx.x * GB + threadIdx.x; q < nloc; q += gridDim.x * GB) {
+    const int sub = SPLIT > 1 ? (int)(threadIdx.x % SPLIT) : 0;
+    for (int qq = blockIdx.x * GB + threadIdx.x; qq < nloc * SPLIT; qq += gridDim.x * GB) {
+        const int q = qq / SPLIT;
         const int a = q % S.lw2, b = q / S.lw2;
         const long long G = (2 * S.x0 + a) + (long long)ng * (2 * S.y0 + b);
         const int cls = A.cls2[S.node_off + q];
         double *en = A.e_new + S.e2_off;
         const bool vertex = !(a & 1) && !(b & 1);
         const int vq = vertex ? (a >> 1) + S.lw1 * (b >> 1) : -1;
-        if (cls != 0) {
-            for (int c = 0; c < 2; ++c) en[(long long)c * nloc + q] = oseen_z(S, A, c, q, G);
-        }
         const bool prow = vertex && A.cls1[S.vert_off + vq] == 0;
-        if (vertex && !prow) A.e_new1[S.e1_off + vq] = 0.0;
-        if (cls != 0 && !prow) continue;
+        if (sub == 0) {
+            if (cls != 0)
+                for (int c = 0; c < 2; ++c) en[(long long)c * nloc + q] = oseen_z(S, A, c, q, G);
+            if (vertex && !prow) A.e_new1[S.e1_off + vq] = 0.0;
+        }
+        const bool active = cls == 0 || prow;
         double rv[2] = {0.0, 0.0}, rq = 0.0;
-        if (cls == 0)
+        if (active && cls == 0 && sub == 0)
             for (int c = 0; c < 2; ++c)
                 rv[c] = eta * (A.load[c][0][G] * A.tf[0] + A.load[c][1][G] * A.tf[1] + A.load[c][2][G] * A.tf[2]);
-        for_elements(a, b, S.cx, S.cy, [&](int t, int ci, int cj, int la) {
+        auto elem = [&](int t, int ci, int cj, int la) {
             double W[2][6], Z[2][6], Y[2][6], O[2][6], P[3];
             for (int k = 0; k < 6; ++k) {
                 const int qa = 2 * ci + off2a(t, k), qb = 2 * cj + off2b(t, k);
@@ -400,23 +441,38 @@ __global__ __launch_bounds__(GB) void k_oseen_rhs(OseenArgs A) {
                 if (c_co.convection) conv_rows(t, la, h, W, Z, true, cW, Nz);
                 else cW[0] = cW[1] = Nz[0] = Nz[1] = 0.0;
                 for (int c = 0; c < 2; ++c) {
-                    double m = 0.0, s = 0.0, bt = 0.0;
+                    double m = 0.0, sv = 0.0, bt = 0.0;
                     for (int k = 0; k < 6; ++k) {
                         m += c_ref.Me[t][la][k] * O[c][k];
-                        for (int d = 0; d < 2; ++d) s += c_ref.Se[t][c * 6 + la][d * 6 + k] * Y[d][k];
+                        for (int d = 0; d < 2; ++d) sv += c_ref.Se[t][c * 6 + la][d * 6 + k] * Y[d][k];
                     }
                     for (int v = 0; v < 3; ++v) bt += c_ref.Be[t][v][c * 6 + la] * P[v];
-                    rv[c] += edt * h2 * m - nue * s - eta * (cW[c] + Nz[c]) + eta * h * bt;
+                    rv[c] += edt * h2 * m - nue * sv - eta * (cW[c] + Nz[c]) + eta * h * bt;
                 }
             }
             if (prow) {
                 const int lv = p1_local(t, (a >> 1) - ci, (b >> 1) - cj);
-                double s = 0.0;
+                double sv = 0.0;
                 for (int d = 0; d < 2; ++d)
-                    for (int k = 0; k < 6; ++k) s += c_ref.Be[t][lv][d * 6 + k] * Y[d][k];
-                rq -= eta * h * s;
+                    for (int k = 0; k < 6; ++k) sv += c_ref.Be[t][lv][d * 6 + k] * Y[d][k];
+                rq -= eta * h * sv;
             }
-        });
+        };
+        if (active) {
+            if (SPLIT == 1) {
+                for_elements(a, b, S.cx, S.cy, elem);
+            } else {
+                int t, ci, cj, la;
+                if (nth_element(a, b, S.cx, S.cy, sub, t, ci, cj, la)) elem(t, ci, cj, la);
+            }
+        }
+        if (SPLIT > 1) {
+            // every lane of the group takes part (same node, same branch)
+            rv[0] = group_sum<SPLIT>(rv[0]);
+            rv[1] = group_sum<SPLIT>(rv[1]);
+            rq = group_sum<SPLIT>(rq);
+        }
+        if (!active || sub != 0) continue;
         // Gamma edges (conduit bottom row): Beavers-Joseph on the x rows and the
         // lagged p_F^n terms -(eta/rho) int p_F v.n_c - c_tau int d_x p_F v_x
         if (cls == 0 && S.gamma && 2 * S.y0 + b == 0) {
@@ -793,6 +849,301 @@ __global__ __launch_bounds__(TP *TP) void k_band_lu(BandArgs<T> B) {
     if (bad && tid == 0) atomicOr(B.flags, 4);
 }
 
+// value of v in lane `lane` of the wavefront (uniform lane index)
+template <typename T>
+__device__ __forceinline__ T wave_bcast(T v, int lane);
+template <>
+__device__ __forceinline__ float wave_bcast<float>(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+template <>
+__device__ __forceinline__ double wave_bcast<double>(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
+}
+// ---------------------------------------------------------------------------
+// Blocked band LU without pivoting on the matrix cores (MFMA 16x16x4).
+// The window of W = 16 TT rows and columns (W >= bw + 16) is split into
+// 16 x 16 tiles held in MFMA accumulators, tile (I, J) by wavefront
+// (I TT + J) mod NW.  Tile slots are circular like the rows: global row i sits
+// in slot i mod W, so panel p (columns 16p .. 16p+15) is tile column and tile
+// row P = p mod TT and no data moves between registers when the window
+// advances.  Per panel:
+//   1. the panel tile row and column go to LDS, and their accumulators are
+//      refilled with the entering rows / columns of the next window (loads
+//      that have the panel factorisation to arrive);
+//   2. a writer wavefront factors the diagonal tile (L11 U11);
+//   3. the writers solve l U11 = a for every other row of the tile column and
+//      L11 u = a for every other column of the tile row, one thread each;
+//   4. the writers store L and U of the panel in the solves' factor layout
+//      while
+//   5. the NW tile wavefronts take C -= L(I, P) U(P, J) on every other tile as
+//      four MFMA steps.
+// Tile and writer wavefronts (LU_NS of them, holding no tiles) run separate
+// loops with the same barriers.  The tile wavefronts issue only loads and the
+// writers only stores, so no wait for a load ever waits for a store (the
+// memory counter is shared by both, in order, per wavefront), and the writers'
+// registers are free of the window.  The arithmetic is that of the unblocked
+// elimination in a different order.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 op(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    // accumulator register r of lane l holds tile row crow(l, r), column l mod 16
+    static __device__ __forceinline__ int crow(int l, int r) { return 4 * (l >> 4) + r; }
+};
+template <>
+struct Mfma<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 op(double a, double b, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    static __device__ __forceinline__ int crow(int l, int r) { return (l >> 4) + 4 * r; }
+};
+
+constexpr int gcd_int(int a, int b) { return b == 0 ? a : gcd_int(b, a % b); }
+constexpr int LU_NS = 5;           // writer wavefronts of the blocked factorisation
+
+template <typename T, int TT, int NW>
+__global__ __launch_bounds__(64 * (NW + LU_NS)) void k_band_lu_mfma(BandArgs<T> B) {
+    typedef typename Mfma<T>::v4 v4;
+    constexpr int W = 16 * TT, NTILE = TT * TT, MT = (NTILE + NW - 1) / NW;
+    static_assert(2 * (W - 16) <= 64 * LU_NS, "one writer thread per panel row and column");
+    const BandSys Sy = B.sys[blockIdx.x];
+    if (B.skip && *B.skip) return;
+    const int n = Sy.n, bw = Sy.bw, ld = 2 * bw + 1;
+    const int ws = bw > 0 ? bw : 1, ldf = Sy.ldf, nrf = ldf >> 6;
+    const T *M = B.band + Sy.off;
+    __shared__ T Pc[W][17];        // panel tile column by row slot (L11\U11 in the diagonal tile, then L21)
+    __shared__ T Pr[16][W + 1];    // panel tile row by column slot (then U12)
+    __shared__ T dinv[16];
+    // the wavefront index is uniform: keep tile coordinates and branches scalar
+    const int tid = threadIdx.x, wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63, lc = lane & 15;
+    const int npan = (n + 15) / 16;
+    if (wv < NW) {
+        // ---- tile wavefronts: hold the window, refill it, apply the trailing updates
+        v4 acc[MT];
+        auto base_of = [](int S, int P, int k0) { return k0 + 16 * ((S - P + TT) % TT); };
+        // tile (I, J) of the window whose panel starts at k0 (slot P), from the
+        // band: outside the band zero, beyond n the identity (pivots 1)
+#define LP_TILE_LOAD(DST_, I_, J_, P_, K0_)                                                    \
+        do {                                                                                  \
+            const int gi0 = base_of(I_, P_, K0_), gj = base_of(J_, P_, K0_) + lc;             \
+            _Pragma("unroll") for (int r = 0; r < 4; ++r) {                                    \
+                const int gi = gi0 + Mfma<T>::crow(lane, r), d = gi - gj;                      \
+                const bool in = gi < n && gj < n && d <= bw && d >= -bw;                       \
+                const T *src = in ? M + ((long long)gj * ld + d + bw) : (gi == gj ? B.one : B.zero); \
+                DST_[r] = *src;                                                               \
+            }                                                                                 \
+        } while (0)
+#pragma unroll
+        for (int t = 0; t < MT; ++t) {
+            const int q = wv + NW * t;
+            if (q < NTILE) LP_TILE_LOAD(acc[t], q / TT, q % TT, 0, 0);
+        }
+        for (int p = 0; p < npan; ++p) {
+            const int k0 = 16 * p, P = p % TT;
+            // 1. panel tiles to LDS, then their accumulators refilled with the
+            //    entering tiles (all writes first: a write that waits on the
+            //    previous panel's loads must not also wait on these)
+#pragma unroll
+            for (int t = 0; t < MT; ++t) {
+                const int q = wv + NW * t;
+                if (q >= NTILE) continue;
+                const int I = q / TT, J = q % TT;
+                if (J == P) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) Pc[16 * I + Mfma<T>::crow(lane, r)][lc] = acc[t][r];
+                } else if (I == P) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) Pr[Mfma<T>::crow(lane, r)][16 * J + lc] = acc[t][r];
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < MT; ++t) {
+                const int q = wv + NW * t;
+                if (q >= NTILE) continue;
+                const int I = q / TT, J = q % TT;
+                if (I == P || J == P) LP_TILE_LOAD(acc[t], I, J, (P + 1) % TT, k0 + 16);
+            }
+            lds_barrier();                 // A: panel in LDS
+            lds_barrier();                 // B: diagonal tile factored
+            lds_barrier();                 // C: L21 and U12 ready
+            // 5. trailing update of the other tiles: operands of two tiles at a time, then their MFMAs
+#pragma unroll
+            for (int t0 = 0; t0 < MT; t0 += 2) {
+                T av[2][4], bv[2][4];
+#pragma unroll
+                for (int t = t0; t < t0 + 2 && t < MT; ++t) {
+                    const int q = wv + NW * t;
+                    const int I = q < NTILE ? q / TT : 0, J = q < NTILE ? q % TT : 0;
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) {
+                        av[t - t0][kk] = -Pc[16 * I + lc][4 * kk + (lane >> 4)];
+                        bv[t - t0][kk] = Pr[4 * kk + (lane >> 4)][16 * J + lc];
+                    }
+                }
+#pragma unroll
+                for (int t = t0; t < t0 + 2 && t < MT; ++t) {
+                    const int q = wv + NW * t;
+                    if (q >= NTILE) continue;
+                    const int I = q / TT, J = q % TT;
+                    if (I == P || J == P) continue;
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) acc[t] = Mfma<T>::op(av[t - t0][kk], bv[t - t0][kk], acc[t]);
+                }
+            }
+            lds_barrier();                 // D: LDS free for the next panel
+        }
+#undef LP_TILE_LOAD
+    } else {
+        // ---- writer wavefronts: factor the panel and write L and U out
+        const int wr = wv - NW, wt = tid - 64 * NW;     // writer wavefront / thread index
+        T *Lr = B.fac + Sy.foff, *Ur = Lr + (long long)n * ldf, *Di = Ur + (long long)n * ldf;
+        int bad = 0;
+        for (int p = 0; p < npan; ++p) {
+            const int k0 = 16 * p, P = p % TT;
+            lds_barrier();                 // A
+            // 2. diagonal tile: lanes 0..15 of writer 0 hold its rows
+            if (wr == 0) {
+                T d[16];
+                const int rr = 16 * P + lc;
+#pragma unroll
+                for (int c = 0; c < 16; ++c) d[c] = Pc[rr][c];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    T piv = wave_bcast(d[j], j);
+                    if (!(fabs((double)piv) > 0.0) || !isfinite((double)piv)) { bad = 1; piv = T(1); }
+                    const T inv = T(1) / piv;
+                    if (lane == j) dinv[j] = inv;
+                    const T l = d[j] * inv;
+#pragma unroll
+                    for (int c = j + 1; c < 16; ++c) {
+                        const T u = wave_bcast(d[c], j);
+                        d[c] = lc > j ? d[c] - l * u : d[c];
+                    }
+                    d[j] = lc > j ? l : d[j];
+                }
+                if (lane < 16) {
+#pragma unroll
+                    for (int c = 0; c < 16; ++c) Pc[rr][c] = d[c];
+                }
+            }
+            lds_barrier();                 // B
+            // 3. the other rows of the tile column (l U11 = a) and columns of the tile row (L11 u = a)
+            if (wt < W - 16) {
+                // one row, U11 rows streamed from LDS one row ahead
+                const int rho = (16 * (P + 1) + wt) % W;
+                T a[16], ur[16], un[16];
+#pragma unroll
+                for (int c = 0; c < 16; ++c) a[c] = Pc[rho][c];
+#pragma unroll
+                for (int c2 = 0; c2 < 16; ++c2) un[c2] = Pc[16 * P][c2];
+                un[0] = dinv[0];
+#pragma unroll
+                for (int c = 0; c < 16; ++c) {
+#pragma unroll
+                    for (int c2 = c; c2 < 16; ++c2) ur[c2] = un[c2];
+                    if (c + 1 < 16) {
+#pragma unroll
+                        for (int c2 = c + 2; c2 < 16; ++c2) un[c2] = Pc[16 * P + c + 1][c2];
+                        un[c + 1] = dinv[c + 1];
+                    }
+                    a[c] *= ur[c];
+#pragma unroll
+                    for (int c2 = c + 1; c2 < 16; ++c2) a[c2] -= a[c] * ur[c2];
+                }
+#pragma unroll
+                for (int c = 0; c < 16; ++c) Pc[rho][c] = a[c];
+            } else if (wt < 2 * (W - 16)) {
+                // one column (unit lower L11), L11 columns streamed from LDS one ahead
+                const int sig = (16 * (P + 1) + wt - (W - 16)) % W;
+                T u[16], lr[16], ln[16];
+#pragma unroll
+                for (int r = 0; r < 16; ++r) u[r] = Pr[r][sig];
+#pragma unroll
+                for (int r2 = 1; r2 < 16; ++r2) ln[r2] = Pc[16 * P + r2][0];
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+#pragma unroll
+                    for (int r2 = r + 1; r2 < 16; ++r2) lr[r2] = ln[r2];
+                    if (r + 1 < 16) {
+#pragma unroll
+                        for (int r2 = r + 2; r2 < 16; ++r2) ln[r2] = Pc[16 * P + r2][r + 1];
+                    }
+#pragma unroll
+                    for (int r2 = r + 1; r2 < 16; ++r2) u[r2] -= lr[r2] * u[r];
+                }
+#pragma unroll
+                for (int r = 0; r < 16; ++r) Pr[r][sig] = u[r];
+            }
+            lds_barrier();                 // C
+            // 4. factors of columns / rows k0 .. k0+15 in the solves' layout, with
+            //    fixed trip counts so that all LDS reads go out before the stores
+            const int km0 = k0 % ws;
+            {
+                // L(k + o, k): column c = wr + LU_NS j, lanes over consecutive o
+                constexpr int NC = (16 + LU_NS - 1) / LU_NS, NO = W / 64 + 1;
+                T lv[NC][NO];
+                long long la[NC][NO];
+#pragma unroll
+                for (int j = 0; j < NC; ++j) {
+                    const int c0 = wr + LU_NS * j, c = c0 < 16 ? c0 : 15, k = k0 + c;
+                    int kmod = km0 + c;
+                    kmod = kmod >= ws ? kmod - ws : kmod;
+#pragma unroll
+                    for (int u = 0; u < NO; ++u) {
+                        const int o = lane + 1 + 64 * u, i = k + o;
+                        const bool ok = c0 < 16 && o <= ws && k < n && i < n;
+                        int sl = kmod + o;
+                        sl = sl >= ws ? sl - ws : sl;
+                        int iw = 16 * P + c + o;
+                        iw = iw >= W ? iw - W : iw;
+                        lv[j][u] = ok ? Pc[iw][c] : T(0);
+                        la[j][u] = ok ? (long long)k * ldf + (sl & 63) * nrf + (sl >> 6) : -1;
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < NC; ++j)
+#pragma unroll
+                    for (int u = 0; u < NO; ++u)
+                        if (la[j][u] >= 0) Lr[la[j][u]] = lv[j][u];
+            }
+            {
+                // U(k0 + c, j), j = k0 + c + 1 .. k0 + c + bw: four columns j per
+                // pass, lanes c = 0..15 over the panel rows
+                constexpr int NJ = (W + 4 * LU_NS - 1) / (4 * LU_NS);
+                const int c = lane & 15, k = k0 + c;
+                int kmod = km0 + c;
+                kmod = kmod >= ws ? kmod - ws : kmod;
+                const int pk = (kmod & 63) * nrf + (kmod >> 6);
+                T uvv[NJ];
+                long long ua[NJ];
+#pragma unroll
+                for (int u = 0; u < NJ; ++u) {
+                    const int jo = (lane >> 4) + 4 * wr + 4 * LU_NS * u;
+                    const int j = k0 + 1 + jo;
+                    const bool ok = jo < 15 + ws && j > k && j - k <= ws && j < n;
+                    int jw = 16 * P + 1 + jo;
+                    jw = jw >= W ? jw - W : jw;
+                    jw = jw >= W ? jw - W : jw;
+                    uvv[u] = ok ? (j < k0 + 16 ? Pc[16 * P + c][(j - k0) & 15] : Pr[c][jw]) : T(0);
+                    ua[u] = ok ? (long long)j * ldf + pk : -1;
+                }
+#pragma unroll
+                for (int u = 0; u < NJ; ++u)
+                    if (ua[u] >= 0) Ur[ua[u]] = uvv[u];
+            }
+            if (wr == 0 && lane < 16 && k0 + lane < n) Di[k0 + lane] = dinv[lane];
+            lds_barrier();                 // D
+        }
+        if (bad && lane == 0) atomicOr(B.flags, 4);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Band triangular solves, one wavefront per right-hand side: L y = r (unit
 // lower), U d = y, x += d.  The window of ws = bw rows is spread circularly
@@ -808,19 +1159,6 @@ __global__ __launch_bounds__(TP *TP) void k_band_lu(BandArgs<T> B) {
 // finished entries of a block are gathered into lanes 0..D-1 and stored with
 // one masked LDS write per block.
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ T wave_bcast(T v, int lane);
-template <>
-__device__ __forceinline__ float wave_bcast<float>(float v, int lane) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
-}
-template <>
-__device__ __forceinline__ double wave_bcast<double>(double v, int lane) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-    return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
-}
 // LDS pad (rows) on each side of the right-hand side: at least the largest
 // window (4 x 64) plus two blocks
 constexpr int SOLVE_PAD = 4 * 64 + 2 * 32;
@@ -1137,8 +1475,9 @@ template <typename T>
 void launch_porous_assemble(const AssembleArgs<T> &a, int nsys, hipStream_t st) {
     hipLaunchKernelGGL(k_porous_assemble<T>, dim3(nsys), dim3(256), 0, st, a);
 }
-void launch_oseen_rhs(const OseenArgs &a, int nsys, int maxnodes, hipStream_t st) {
-    hipLaunchKernelGGL(k_oseen_rhs, dim3(node_blocks(maxnodes), nsys), dim3(GB), 0, st, a);
+void launch_oseen_rhs(const OseenArgs &a, int nsys, int maxnodes, int split, hipStream_t st) {
+    if (split == 8) hipLaunchKernelGGL((k_oseen_rhs<8>), dim3(node_blocks(8 * maxnodes), nsys), dim3(GB), 0, st, a);
+    else hipLaunchKernelGGL((k_oseen_rhs<1>), dim3(node_blocks(maxnodes), nsys), dim3(GB), 0, st, a);
 }
 template <typename T>
 void launch_oseen_assemble(const OseenApplyArgs<T> &a, int nsys, int maxnodes, hipStream_t st) {
@@ -1153,6 +1492,15 @@ void launch_oseen_finalize(const FinalizeArgs &a, int nsys, int maxnodes, hipStr
 
 template <typename T>
 bool launch_band_lu(const BandArgs<T> &a, int nsys, int maxbw, int variant, hipStream_t st) {
+    if (variant == 8) {
+        // blocked factorisation on the matrix cores: window 16 TT >= bw + 16
+        constexpr int X = 64 * LU_NS;
+        if (maxbw <= 64) { hipLaunchKernelGGL((k_band_lu_mfma<T, 5, 4>), dim3(nsys), dim3(256 + X), 0, st, a); return true; }
+        if (maxbw <= 96) { hipLaunchKernelGGL((k_band_lu_mfma<T, 7, 8>), dim3(nsys), dim3(512 + X), 0, st, a); return true; }
+        if (maxbw <= 128) { hipLaunchKernelGGL((k_band_lu_mfma<T, 9, 8>), dim3(nsys), dim3(512 + X), 0, st, a); return true; }
+        if (maxbw <= 160) { hipLaunchKernelGGL((k_band_lu_mfma<T, 11, 8>), dim3(nsys), dim3(512 + X), 0, st, a); return true; }
+        return false;
+    }
     // smallest window W = TP * RB above the half-bandwidth; for W = 160 the
     // variant picks 32 x 32 threads with 5 x 5 blocks (4) or 20 x 20 threads
     // with 8 x 8 blocks (2); 0 = default per precision
