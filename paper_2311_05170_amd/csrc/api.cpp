@@ -62,6 +62,7 @@ struct lp_ctx {
     hipStream_t fstream[2] = {};
     hipEvent_t ev_fac[FSLOTS] = {};
     int ecur = 0;                  // correction buffers holding e^n
+    bool serial = false;           // diagnostic (LP_SERIAL=1): all stages on one stream, no overlap
     bool mixed = false;
 
     // sizes
@@ -151,6 +152,7 @@ struct lp_ctx {
             if (ev_local[i]) (void)hipEventDestroy(ev_local[i]);
         }
         if (cstream) (void)hipStreamDestroy(cstream);
+        if (serial) pstream = fstream[0] = fstream[1] = nullptr;
         if (pstream) { (void)hipStreamSynchronize(pstream); (void)hipStreamDestroy(pstream); }
         for (int i = 0; i < 2; ++i)
             if (fstream[i]) { (void)hipStreamSynchronize(fstream[i]); (void)hipStreamDestroy(fstream[i]); }
@@ -727,8 +729,14 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     // initial corrections e_j^0 = I_h x_0 - Pi_h x_H^0
     c->ecur = 0;
     HIPCHK(hipStreamCreateWithFlags(&c->cstream, hipStreamNonBlocking));
-    HIPCHK(hipStreamCreateWithFlags(&c->pstream, hipStreamNonBlocking));
-    for (int l = 0; l < 2; ++l) HIPCHK(hipStreamCreateWithFlags(&c->fstream[l], hipStreamNonBlocking));
+    if (const char *v = std::getenv("LP_SERIAL")) c->serial = std::atoi(v) != 0;
+    if (c->serial) {
+        // diagnostic: every stage on one internal stream, in program order
+        c->pstream = c->fstream[0] = c->fstream[1] = c->cstream;
+    } else {
+        HIPCHK(hipStreamCreateWithFlags(&c->pstream, hipStreamNonBlocking));
+        for (int l = 0; l < 2; ++l) HIPCHK(hipStreamCreateWithFlags(&c->fstream[l], hipStreamNonBlocking));
+    }
     for (int i = 0; i < lp_ctx::FSLOTS; ++i) HIPCHK(hipEventCreateWithFlags(&c->ev_fac[i], hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&c->ev_pro, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&c->ev_por, hipEventDisableTiming));
@@ -877,7 +885,8 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
 lp_status lp_local_step(lp_ctx *c, void *stream) {
     if (!c) return fail(LP_ERR_ARG, "NULL context");
     if (!c->coarse_pending) return fail(LP_ERR_STATE, "lp_local_step needs a preceding lp_coarse_step");
-    hipStream_t st = (hipStream_t)stream;
+    hipStream_t st = (hipStream_t)stream, st_user = st;
+    if (c->serial) st = c->cstream;
     const int64_t m = c->n + 1;
     const int o = (int)((m - 1) % lp_ctx::RING), nw = (int)(m % lp_ctx::RING);
     HIPCHK(hipStreamWaitEvent(st, c->ev_coarse[nw], 0));
@@ -913,6 +922,7 @@ lp_status lp_local_step(lp_ctx *c, void *stream) {
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(c->ev_local[m % lp_ctx::RING], st));
+    if (st != st_user) HIPCHK(hipStreamWaitEvent(st_user, c->ev_local[m % lp_ctx::RING], 0));
     c->ecur = en;
     c->n += 1;
     c->coarse_pending = false;

@@ -118,3 +118,74 @@ def test_state_machine_errors():
     with pytest.raises(LpError):
         g.solution("u", "local", sub=0)        # porous subdomain has no velocity
     g.close()
+
+
+RAGGED_PRM = dict(W.unit_params(), nu=0.05, k=[0.3, 0.02, 0.004], sigma=2.0, sigma_star=0.5)
+
+
+def _ragged():
+    return W.small(NH=3, refine=4, nsub=3, overlap=1, dt=0.02, prm=RAGGED_PRM)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("variant", ["0", "8"])
+def test_parity_lu_kernels(precision, variant, monkeypatch):
+    """Both band factorisations (variant 0: elimination on the vector units;
+    8: blocked, trailing updates on the matrix cores) for every system of the
+    run (porous, coarse and local Oseen) agree with the oracle."""
+    monkeypatch.setenv("LP_LU_VARIANT", variant)
+    run_parity(_ragged(), precision, 3)
+
+
+def _fields(g):
+    return {f: g.solution(f) for f in ("u", "p", "pF", "pf", "pm")}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_streams_do_not_change_results(precision, monkeypatch):
+    """The overlapped schedule (coarse steps ahead of the local stage, porous
+    and factor streams) gives bit-identical fields to running every stage on
+    one stream in program order: no race, no order-dependent arithmetic."""
+    cfg = W.config("cfg1")
+    g = _gpu(cfg, precision)
+    for _ in range(3):
+        g.step()
+    a = _fields(g)
+    g.close()
+    monkeypatch.setenv("LP_SERIAL", "1")
+    g = _gpu(cfg, precision)
+    for _ in range(3):
+        g.step()
+    b = _fields(g)
+    g.close()
+    for f in a:
+        assert np.array_equal(a[f], b[f]), f
+
+
+def test_h_equals_H_gives_zero_corrections():
+    """With T_h = T_H the local residual equations have zero data (every test
+    function is supported inside Omega_j), so every correction vanishes and the
+    merged field equals the coarse one."""
+    cfg = W.small(NH=8, refine=1, nsub=4, overlap=1, dt=0.05)
+    g = _gpu(cfg, "fp64")
+    for _ in range(2):
+        g.step()
+    nsub = 2 * cfg["nsub"][0] * cfg["nsub"][1]
+    for sub in range(nsub):
+        fields = ("pF", "pf", "pm") if sub < nsub // 2 else ("u", "p")
+        for f in fields:
+            assert np.max(np.abs(g.solution(f, "local", sub))) < 1e-10, (sub, f)
+    for f in ("u", "p", "pF", "pf", "pm"):
+        assert np.max(np.abs(g.solution(f) - g.solution(f, "coarse"))) < 1e-10, f
+    g.close()
+
+
+def test_unsupported_bandwidth_is_reported():
+    """The uneven h = 1/256 workload needs half-bandwidths up to 399: lp_setup
+    refuses it with LP_ERR_UNSUPPORTED instead of running out of the kernels'
+    window."""
+    from paper_2311_05170_amd.lib import LpError
+    with pytest.raises(LpError) as e:
+        _gpu(W.config("cfg3"), "mixed")
+    assert e.value.status == 6
+    assert "bandwidth" in str(e.value)
