@@ -197,7 +197,10 @@ enum {
     LP_T_OSE_RES = 8,        /* local Oseen FP64 residuals */
     LP_T_MERGE = 9,          /* finalize + partition-of-unity merge */
     LP_T_COARSE = 10,        /* the whole coarse step */
-    LP_T_COUNT = 11
+    LP_T_WAIT_COARSE = 11,   /* local step start waiting for its coarse step */
+    LP_T_WAIT_FAC = 12,      /* local Oseen solves waiting for their factors */
+    LP_T_WAIT_POR = 13,      /* merge waiting for the porous batch */
+    LP_T_COUNT = 14
 };
 lp_status lp_set_timing(lp_ctx *ctx, uint32_t mask);
 lp_status lp_get_timing(lp_ctx *ctx, double *ms, int64_t *launches, int32_t n);

@@ -45,12 +45,13 @@ struct lp_ctx {
     // results, so coarse steps run ahead of the local stage (up to RING - 2
     // steps).  A slot is rewritten only after the local step that last reads
     // it has finished.
-    static constexpr int RING = 5;
-    static constexpr int FSLOTS = 3;   // factor slots of the local Oseen operators (< RING)
+    static constexpr int RING = 8;
+    static constexpr int FSLOTS = 5;   // factor slots of the local Oseen operators (< RING)
     hipStream_t cstream = nullptr;
     hipEvent_t ev_coarse[RING] = {}, ev_local[RING] = {};
-    // the local porous batch runs on its own stream beside the Oseen batch
-    hipStream_t pstream = nullptr;
+    // the local porous batch of step m runs on factor stream m % 2, after that
+    // step's Oseen factorisation, beside the Oseen solves (four streams in all,
+    // within HIP's default of four hardware queues per process)
     hipEvent_t ev_pro = nullptr, ev_por = nullptr;
     // The local Oseen operator of step m depends only on u_cH^m, so its
     // assembly and factorisation run on factor stream m % 2 as soon as coarse
@@ -152,8 +153,7 @@ struct lp_ctx {
             if (ev_local[i]) (void)hipEventDestroy(ev_local[i]);
         }
         if (cstream) (void)hipStreamDestroy(cstream);
-        if (serial) pstream = fstream[0] = fstream[1] = nullptr;
-        if (pstream) { (void)hipStreamSynchronize(pstream); (void)hipStreamDestroy(pstream); }
+        if (serial) fstream[0] = fstream[1] = nullptr;
         for (int i = 0; i < 2; ++i)
             if (fstream[i]) { (void)hipStreamSynchronize(fstream[i]); (void)hipStreamDestroy(fstream[i]); }
         for (int i = 0; i < FSLOTS; ++i)
@@ -387,7 +387,10 @@ lp_status local_oseen(lp_ctx *c, hipStream_t st) {
     }
     // factors of the operator linearised about Pi_h u_cH^{n+1} (factor stream)
     const int fs = (int)((c->n + 1) % lp_ctx::FSLOTS);
-    HIPCHK(hipStreamWaitEvent(st, c->ev_fac[fs], 0));
+    {
+        StageTimer tm(c, LP_T_WAIT_FAC, st);
+        HIPCHK(hipStreamWaitEvent(st, c->ev_fac[fs], 0));
+    }
     TRY(refine_oseen<T>(c, c->d_ose, nsys, c->nodes_ose, c->part_ose, c->tick_ose, c->d_sv_ose, (const T *)c->fac_ose[fs], c->maxbw_ose, c->maxn_ose, oa.W1[0], oa.W1[1], c->b_ose,
                         c->x_ose, c->r_ose, c->conv_ose, c->rel_ose, c->sw_ose, c->P.dof_total_ose, c->opt.max_ir,
                         c->opt.ir_tol, nullptr, true, st));
@@ -732,9 +735,8 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     if (const char *v = std::getenv("LP_SERIAL")) c->serial = std::atoi(v) != 0;
     if (c->serial) {
         // diagnostic: every stage on one internal stream, in program order
-        c->pstream = c->fstream[0] = c->fstream[1] = c->cstream;
+        c->fstream[0] = c->fstream[1] = c->cstream;
     } else {
-        HIPCHK(hipStreamCreateWithFlags(&c->pstream, hipStreamNonBlocking));
         for (int l = 0; l < 2; ++l) HIPCHK(hipStreamCreateWithFlags(&c->fstream[l], hipStreamNonBlocking));
     }
     for (int i = 0; i < lp_ctx::FSLOTS; ++i) HIPCHK(hipEventCreateWithFlags(&c->ev_fac[i], hipEventDisableTiming));
@@ -889,17 +891,24 @@ lp_status lp_local_step(lp_ctx *c, void *stream) {
     if (c->serial) st = c->cstream;
     const int64_t m = c->n + 1;
     const int o = (int)((m - 1) % lp_ctx::RING), nw = (int)(m % lp_ctx::RING);
-    HIPCHK(hipStreamWaitEvent(st, c->ev_coarse[nw], 0));
+    {
+        StageTimer tm(c, LP_T_WAIT_COARSE, st);
+        HIPCHK(hipStreamWaitEvent(st, c->ev_coarse[nw], 0));
+    }
     {
         StageTimer tm(c, LP_T_PROLONG, st);
         prolong_all(c, nw, o, st);
     }
     HIPCHK(hipEventRecord(c->ev_pro, st));
-    HIPCHK(hipStreamWaitEvent(c->pstream, c->ev_pro, 0));
-    if (c->mixed) { TRY(local_porous<float>(c, c->pstream)); TRY(local_oseen<float>(c, st)); }
-    else { TRY(local_porous<double>(c, c->pstream)); TRY(local_oseen<double>(c, st)); }
-    HIPCHK(hipEventRecord(c->ev_por, c->pstream));
-    HIPCHK(hipStreamWaitEvent(st, c->ev_por, 0));
+    hipStream_t ps = c->fstream[m % 2];
+    HIPCHK(hipStreamWaitEvent(ps, c->ev_pro, 0));
+    if (c->mixed) { TRY(local_porous<float>(c, ps)); TRY(local_oseen<float>(c, st)); }
+    else { TRY(local_porous<double>(c, ps)); TRY(local_oseen<double>(c, st)); }
+    HIPCHK(hipEventRecord(c->ev_por, ps));
+    {
+        StageTimer tm(c, LP_T_WAIT_POR, st);
+        HIPCHK(hipStreamWaitEvent(st, c->ev_por, 0));
+    }
     const int en = 1 - c->ecur;
     StageTimer tm(c, LP_T_MERGE, st);
     for (int r = 0; r < 2; ++r) {
@@ -1035,10 +1044,18 @@ lp_status lp_set_timing(lp_ctx *c, uint32_t mask) {
 
 lp_status lp_get_timing(lp_ctx *c, double *ms, int64_t *launches, int32_t n) {
     if (!c || !ms || !launches || n < 0 || n > LP_T_COUNT) return fail(LP_ERR_ARG, "bad arguments");
+    // diagnostic: LP_TRACE=1 prints every timed interval relative to the first one
+    const bool trace = std::getenv("LP_TRACE") && !c->recs.empty();
     for (auto &r : c->recs) {
         HIPCHK(hipEventSynchronize(r.b));
         float t = 0.0f;
         HIPCHK(hipEventElapsedTime(&t, r.a, r.b));
+        if (trace) {
+            float ta = 0.0f, tb = 0.0f;
+            HIPCHK(hipEventElapsedTime(&ta, c->recs[0].a, r.a));
+            HIPCHK(hipEventElapsedTime(&tb, c->recs[0].a, r.b));
+            std::fprintf(stderr, "LP_TRACE %d %.4f %.4f\n", r.stage, ta, tb);
+        }
         c->tms[r.stage] += t;
         c->tcnt[r.stage] += 1;
         c->pool.push_back(r.a);

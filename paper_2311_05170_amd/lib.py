@@ -31,7 +31,7 @@ EXPORTS = ["lp_setup", "lp_coarse_step", "lp_local_step", "lp_get_size", "lp_get
            "lp_last_error"]
 # stage timer indices (LP_T_* in lp.h)
 STAGES = ["prolong", "por_rhs", "por_solve", "por_res", "ose_rhs", "ose_asm", "ose_lu", "ose_solve",
-          "ose_res", "merge", "coarse"]
+          "ose_res", "merge", "coarse", "wait_coarse", "wait_fac", "wait_por"]
 
 
 class LpMesh(Structure):
