@@ -122,7 +122,7 @@ struct lp_ctx {
     long long lu_dummy_coarse_off = 0;
     int lu_variant = 0;                // factorisation kernel of the porous and coarse systems (0: default)
     int lu_variant_ose = 0;            // of the local Oseen systems (mixed: 8, the blocked MFMA kernel)
-    int solve_depth = 32;              // factor columns prefetched by the band solves (16 or 32)
+    int solve_depth = 0;               // factor columns prefetched by the band solves (16, 32; 0 = by precision and bandwidth)
     // device constants read by masked loads: 512 zero doubles (a zero column
     // for the solves), then 1.0 as double, then 1.0f as float
     double *consts = nullptr;
@@ -567,7 +567,7 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     c->mixed = opt->precision == LP_MIXED;
     c->lu_variant_ose = c->mixed ? 8 : 0;
     if (const char *v = std::getenv("LP_LU_VARIANT")) c->lu_variant = c->lu_variant_ose = std::atoi(v);
-    if (const char *v = std::getenv("LP_SOLVE_DEPTH")) c->solve_depth = std::atoi(v) == 16 ? 16 : 32;
+    if (const char *v = std::getenv("LP_SOLVE_DEPTH")) c->solve_depth = std::atoi(v);
     if (alloc && alloc->alloc && alloc->free) { c->alloc = *alloc; c->has_alloc = true; }
     lp::Plan &P = c->P;
     for (const auto &s : P.por) { c->maxbw_por = std::max(c->maxbw_por, s.bw); c->maxn_por = std::max(c->maxn_por, s.ndof); }

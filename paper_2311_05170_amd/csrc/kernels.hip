@@ -1162,6 +1162,8 @@ __global__ __launch_bounds__(64 * (NW + LU_NS)) void k_band_lu_mfma(BandArgs<T> 
 // LDS pad (rows) on each side of the right-hand side: at least the largest
 // window (4 x 64) plus two blocks
 constexpr int SOLVE_PAD = 4 * 64 + 2 * 32;
+// rows per lane in flight when moving the right-hand side and the solution
+constexpr int SOLVE_LD = 8;
 
 template <typename T, int NR, int D>
 __global__ __launch_bounds__(64) void k_band_solve(SolveArgs<T> A) {
@@ -1183,7 +1185,18 @@ __global__ __launch_bounds__(64) void k_band_solve(SolveArgs<T> A) {
     const double *rg = A.r + Sy.vec + (long long)f * n;
     double *x = A.x + Sy.vec + (long long)f * n;
     const int lane = threadIdx.x;
-    for (int i = lane - SOLVE_PAD; i < n + SOLVE_PAD; i += 64) ys[i] = (i >= 0 && i < n) ? (T)rg[i] : T(0);
+    // the right-hand side into LDS, SOLVE_LD rows per lane in flight (clamped
+    // unconditional loads, then masked stores)
+    for (int i0 = lane - SOLVE_PAD; i0 < n + SOLVE_PAD; i0 += 64 * SOLVE_LD) {
+        double v[SOLVE_LD];
+#pragma unroll
+        for (int u = 0; u < SOLVE_LD; ++u) v[u] = rg[min(max(i0 + 64 * u, 0), n - 1)];
+#pragma unroll
+        for (int u = 0; u < SOLVE_LD; ++u) {
+            const int i = i0 + 64 * u;
+            if (i < n + SOLVE_PAD) ys[i] = (i >= 0 && i < n) ? (T)v[u] : T(0);
+        }
+    }
     __syncthreads();
     // lane l holds slots l + 64 m, stored at l NR + m of each factor column:
     // one vector load per column (slots beyond the window hold values that are
@@ -1194,14 +1207,19 @@ __global__ __launch_bounds__(64) void k_band_solve(SolveArgs<T> A) {
     // ---- forward: before step k the window holds rows k..k+ws-1 (row i in slot i mod ws)
 #pragma unroll
     for (int m = 0; m < NR; ++m) win[m] = lane + 64 * m < ws ? ys[lane + 64 * m] : T(0);
+    // columns past either end are prefetched but never used: a clamped column
+    // index keeps every block straight-line
 #define LP_FCOL(KK, S)                                                                     \
     do {                                                                                   \
-        const T *col = (KK) < n ? Lr + (long long)(KK) * ldf : A.zero;                      \
+        const T *col = Lr + (long long)min((KK), n - 1) * ldf;                              \
         const Grp g = *reinterpret_cast<const Grp *>(col + lo);                            \
         _Pragma("unroll") for (int m = 0; m < NR; ++m) cf[S][m] = g.v[m];                   \
     } while (0)
 #pragma unroll
-    for (int s = 0; s < D; ++s) LP_FCOL(s, s);
+    for (int s = 0; s < D; ++s) {
+        LP_FCOL(s, s);
+        __builtin_amdgcn_sched_barrier(0);   // issue in the loop body's order
+    }
 #pragma unroll
     for (int s = 0; s < D; ++s) ent[s] = ys[s + ws];
     int sk = 0;
@@ -1223,12 +1241,15 @@ __global__ __launch_bounds__(64) void k_band_solve(SolveArgs<T> A) {
             for (int m = 0; m < NR; ++m) win[m] = (lane + 64 * m == sk ? ent[s] : win[m]) - cf[s][m] * yk;
             sk = sk + 1 == ws ? 0 : sk + 1;
             LP_FCOL(k + D, s);
+            __builtin_amdgcn_sched_barrier(0);   // keep each prefetch in its column
         }
         if (lane < D) ys[k0 + lane] = yb;
 #pragma unroll
         for (int s = 0; s < D; ++s) ent[s] = nxt[s];
     }
-    for (int s = 0; s < D; ++s) {                     // tail: the last n % D columns
+    // tail: the last n % D columns, already prefetched (cf[s] holds column nfull + s)
+#pragma unroll
+    for (int s = 0; s < D; ++s) {
         const int k = nfull + s;
         if (k >= n) break;
         const int ml = sk >> 6, ll = sk & 63;
@@ -1236,11 +1257,10 @@ __global__ __launch_bounds__(64) void k_band_solve(SolveArgs<T> A) {
 #pragma unroll
         for (int m = 1; m < NR; ++m) v = m == ml ? win[m] : v;
         const T yk = wave_bcast(v, ll);
-        const T *col = Lr + (long long)k * ldf;
         const T e = ys[k + ws];
         if (lane == 0) ys[k] = yk;
 #pragma unroll
-        for (int m = 0; m < NR; ++m) win[m] = (lane + 64 * m == sk ? e : win[m]) - col[lo + m] * yk;
+        for (int m = 0; m < NR; ++m) win[m] = (lane + 64 * m == sk ? e : win[m]) - cf[s][m] * yk;
         sk = sk + 1 == ws ? 0 : sk + 1;
     }
     __syncthreads();
@@ -1255,13 +1275,17 @@ __global__ __launch_bounds__(64) void k_band_solve(SolveArgs<T> A) {
     }
 #define LP_BCOL(KK, S)                                                                     \
     do {                                                                                   \
-        const T *col = (KK) >= 0 ? Ur + (long long)(KK) * ldf : A.zero;                     \
+        const int kc = max((KK), 0);                                                       \
+        const T *col = Ur + (long long)kc * ldf;                                           \
         const Grp g = *reinterpret_cast<const Grp *>(col + lo);                            \
         _Pragma("unroll") for (int m = 0; m < NR; ++m) cf[S][m] = g.v[m];                   \
-        uf[S] = *((KK) >= 0 ? Di + (KK) : A.one);                                          \
+        uf[S] = Di[kc];                                                                    \
     } while (0)
 #pragma unroll
-    for (int s = 0; s < D; ++s) LP_BCOL(kt - s, s);
+    for (int s = 0; s < D; ++s) {
+        LP_BCOL(kt - s, s);
+        __builtin_amdgcn_sched_barrier(0);
+    }
 #pragma unroll
     for (int s = 0; s < D; ++s) ent[s] = ys[kt - s - ws];
     sk = kt % ws;
@@ -1283,28 +1307,39 @@ __global__ __launch_bounds__(64) void k_band_solve(SolveArgs<T> A) {
             for (int m = 0; m < NR; ++m) win[m] = (lane + 64 * m == sk ? ent[s] : win[m]) - cf[s][m] * dk;
             sk = sk == 0 ? ws - 1 : sk - 1;
             LP_BCOL(k - D, s);
+            __builtin_amdgcn_sched_barrier(0);
         }
         if (lane < D) ys[kb - lane] = db;                // row k of y is consumed; keep d_k there
 #pragma unroll
         for (int s = 0; s < D; ++s) ent[s] = nxt[s];
     }
-    for (int s = 0; s < D; ++s) {                     // tail: rows n%D-1 .. 0
+    // tail: rows n % D - 1 .. 0, already prefetched (cf[s], uf[s] hold column kt - bfull - s)
+#pragma unroll
+    for (int s = 0; s < D; ++s) {
         const int k = kt - bfull - s;
         if (k < 0) break;
         const int ml = sk >> 6, ll = sk & 63;
         T v = win[0];
 #pragma unroll
         for (int m = 1; m < NR; ++m) v = m == ml ? win[m] : v;
-        const T dk = wave_bcast(v, ll) * Di[k];
-        const T *col = Ur + (long long)k * ldf;
+        const T dk = wave_bcast(v, ll) * uf[s];
         const T e = ys[k - ws];
         if (lane == 0) ys[k] = dk;
 #pragma unroll
-        for (int m = 0; m < NR; ++m) win[m] = (lane + 64 * m == sk ? e : win[m]) - col[lo + m] * dk;
+        for (int m = 0; m < NR; ++m) win[m] = (lane + 64 * m == sk ? e : win[m]) - cf[s][m] * dk;
         sk = sk == 0 ? ws - 1 : sk - 1;
     }
     __syncthreads();
-    for (int i = lane; i < n; i += 64) x[i] += (double)ys[i];
+    for (int i0 = lane; i0 < n; i0 += 64 * SOLVE_LD) {
+        double v[SOLVE_LD];
+#pragma unroll
+        for (int u = 0; u < SOLVE_LD; ++u) v[u] = x[min(i0 + 64 * u, n - 1)];
+#pragma unroll
+        for (int u = 0; u < SOLVE_LD; ++u) {
+            const int i = i0 + 64 * u;
+            if (i < n) x[i] = v[u] + (double)ys[i];
+        }
+    }
 #undef LP_FCOL
 #undef LP_BCOL
 }
@@ -1534,6 +1569,10 @@ bool launch_band_solve_d(const SolveArgs<T> &a, int nsys, int nrhs, int maxbw, i
 // depth: columns of factor prefetch (16 or 32)
 template <typename T>
 bool launch_band_solve(const SolveArgs<T> &a, int nsys, int nrhs, int maxbw, int maxn, int depth, hipStream_t st) {
+    // automatic depth: 32 columns in flight while the prefetched factors fit
+    // in the 256 architectural registers next to the window (FP32, or FP64
+    // with one register per lane), else 16
+    if (depth != 16 && depth != 32) depth = (sizeof(T) == 4 || solve_nr(maxbw) == 1) ? 32 : 16;
     return depth == 16 ? launch_band_solve_d<T, 16>(a, nsys, nrhs, maxbw, maxn, st)
                        : launch_band_solve_d<T, 32>(a, nsys, nrhs, maxbw, maxn, st);
 }
