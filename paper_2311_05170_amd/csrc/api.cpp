@@ -118,10 +118,12 @@ struct lp_ctx {
     // batches run on different streams)
     double *part_por = nullptr, *part_ose = nullptr, *part_cp = nullptr, *part_cn = nullptr;
     int *tick_por = nullptr, *tick_ose = nullptr, *tick_cp = nullptr, *tick_cn = nullptr;
+    int *tick_dn = nullptr, *tick_dp = nullptr;        // last-block tickets of the fused coarse kernels
     double *lu_dummy = nullptr;        // sink of the factorisation's masked stores
     long long lu_dummy_coarse_off = 0;
     int lu_variant = 0;                // factorisation kernel of the porous and coarse systems (0: default)
-    int lu_variant_ose = 0;            // of the local Oseen systems (mixed: 8, the blocked MFMA kernel)
+    int lu_variant_ose = 0;            // of the local Oseen systems (mixed: 9, blocked on the matrix cores with lookahead)
+    int lu_variant_cns = 8;            // of the coarse Navier-Stokes Jacobian (8: blocked on the matrix cores)
     int solve_depth = 0;               // factor columns prefetched by the band solves (16, 32; 0 = by precision and bandwidth)
     // device constants read by masked loads: 512 zero doubles (a zero column
     // for the solves), then 1.0 as double, then 1.0f as float
@@ -565,8 +567,9 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     c->prm = *prm;
     c->opt = *opt;
     c->mixed = opt->precision == LP_MIXED;
-    c->lu_variant_ose = c->mixed ? 8 : 0;
-    if (const char *v = std::getenv("LP_LU_VARIANT")) c->lu_variant = c->lu_variant_ose = std::atoi(v);
+    c->lu_variant_ose = c->mixed ? 9 : 0;
+    if (const char *v = std::getenv("LP_LU_VARIANT")) c->lu_variant = c->lu_variant_ose = c->lu_variant_cns = std::atoi(v);
+    if (const char *v = std::getenv("LP_LU_VARIANT_COARSE")) c->lu_variant_cns = std::atoi(v);
     if (const char *v = std::getenv("LP_SOLVE_DEPTH")) c->solve_depth = std::atoi(v);
     if (alloc && alloc->alloc && alloc->free) { c->alloc = *alloc; c->has_alloc = true; }
     lp::Plan &P = c->P;
@@ -723,6 +726,9 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
         HIPCHK(hipMemsetAsync(c->tick_ose, 0, nof * sizeof(int), st));
         HIPCHK(hipMemsetAsync(c->tick_cp, 0, 3 * sizeof(int), st));
         HIPCHK(hipMemsetAsync(c->tick_cn, 0, sizeof(int), st));
+        TRY(c->dalloc(&c->tick_dn, 1)); TRY(c->dalloc(&c->tick_dp, 1));
+        HIPCHK(hipMemsetAsync(c->tick_dn, 0, sizeof(int), st));
+        HIPCHK(hipMemsetAsync(c->tick_dp, 0, sizeof(int), st));
     }
     HIPCHK(hipMemsetAsync(c->sw_ose, 0, nof * sizeof(int), st));
     HIPCHK(hipMemsetAsync(c->sw_por, 0, npf * sizeof(int), st));
@@ -824,17 +830,19 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
     for (int k = 0; k < 3; ++k) pa.tf[k] = tf[k];
     lp::launch_porous_rhs(pa, 1, c->nodes_cpor, st);
     {
-        lp::DenseArgs da{c->inv_cp, c->b_cp, c->x_cp, P.cpor.ndof, nullptr};
-        lp::launch_dense_apply(da, 3, st);
+        // the three solves with the explicit inverses, then the node layout
+        lp::DensePorousArgs dp{};
+        dp.d = lp::DenseArgs{c->inv_cp, c->b_cp, c->x_cp, P.cpor.ndof, nullptr};
+        dp.f = lp::FinalizeArgs{c->d_cpor, c->d_dof2, c->d_dof1, c->x_cp, c->cP[nw], nullptr, nullptr};
+        dp.ticket = c->tick_dp;
+        lp::launch_dense_porous(dp, 3, st);
     }
-    lp::FinalizeArgs fa{c->d_cpor, c->d_dof2, c->d_dof1, c->x_cp, c->cP[nw], nullptr, nullptr};
-    lp::launch_porous_finalize(fa, 1, c->nodes_cpor, st);
     // (5.4): Navier-Stokes by Newton from (u^n, p^n); each iteration solves the
     // Oseen system linearised about the current iterate
-    HIPCHK(hipMemcpyAsync(c->cU[nw], c->cU[o], 2 * nc2 * sizeof(double), hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(c->cp[nw], c->cp[o], c->nc1 * sizeof(double), hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemsetAsync(c->d_done, 0, sizeof(int), st));
-    HIPCHK(hipMemsetAsync(c->d_its, 0, sizeof(int), st));
+    {
+        lp::NewtonStartArgs ns{c->cU[o], c->cp[o], c->cU[nw], c->cp[nw], 2 * nc2, c->nc1, c->d_done, c->d_its};
+        lp::launch_newton_start(ns, st);
+    }
     for (int it = 0; it < c->opt.max_newton; ++it) {
         lp::OseenArgs oa{};
         oa.sys = c->d_cns; oa.cls2 = c->d_cls2; oa.dof2 = c->d_dof2; oa.cls1 = c->d_cls1; oa.dof1 = c->d_dof1;
@@ -859,7 +867,7 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
             lp::launch_oseen_assemble<double>(aa, 1, c->nodes_cns, st);
             lp::BandArgs<double> ba{c->d_lu_cns, c->band_cns, c->fac_cns, c->d_flags, c->d_done, c->lu_dummy + c->lu_dummy_coarse_off,
                                     (const double *)c->consts, c->const_one<double>()};
-            if (!lp::launch_band_lu<double>(ba, 1, P.cns.bw, c->lu_variant, st)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
+            if (!lp::launch_band_lu<double>(ba, 1, P.cns.bw, c->lu_variant_cns, st)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
             // explicit inverse of the Jacobian: each chord step is then one
             // dense product instead of a serial band solve
             const int n = P.cns.ndof;
@@ -868,12 +876,14 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
                                      (const double *)c->consts, c->const_one<double>(), (const double *)c->consts};
             if (!lp::launch_band_solve<double>(sa, 1, n, P.cns.bw, n, c->solve_depth, st)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
         }
-        lp::DenseArgs da{c->inv_cn, c->b_cn, c->x_cn, P.cns.ndof, c->d_done};
-        lp::launch_dense_apply(da, 1, st);
-        lp::FinalizeArgs fn{c->d_cns, c->d_dof2, c->d_dof1, c->x_cn, c->nwt_e, c->nwt_e1, c->d_done};
-        lp::launch_oseen_finalize(fn, 1, c->nodes_cns, st);
-        lp::NewtonArgs na{c->cU[nw], c->cp[nw], c->nwt_e, c->nwt_e1, nc2, c->nc1, c->d_done, c->d_its, c->opt.newton_tol};
-        lp::launch_newton_update(na, st);
+        // chord step: x = J^-1 b, the correction to the node layout and the
+        // update with its convergence test, in one launch
+        lp::DenseNewtonArgs dn{};
+        dn.d = lp::DenseArgs{c->inv_cn, c->b_cn, c->x_cn, P.cns.ndof, c->d_done};
+        dn.f = lp::FinalizeArgs{c->d_cns, c->d_dof2, c->d_dof1, c->x_cn, c->nwt_e, c->nwt_e1, c->d_done};
+        dn.u = lp::NewtonArgs{c->cU[nw], c->cp[nw], c->nwt_e, c->nwt_e1, nc2, c->nc1, c->d_done, c->d_its, c->opt.newton_tol};
+        dn.ticket = c->tick_dn;
+        lp::launch_dense_newton(dn, st);
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(c->ev_coarse[nw], st));

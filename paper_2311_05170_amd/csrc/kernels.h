@@ -110,7 +110,7 @@ struct BandSys {
 };
 
 // window registers per lane of the band solve for a half-bandwidth (0: unsupported)
-inline int solve_nr(int maxbw) { return maxbw <= 64 ? 1 : maxbw <= 128 ? 2 : maxbw <= 192 ? 3 : maxbw <= 256 ? 4 : 0; }
+constexpr int solve_nr(int maxbw) { return maxbw <= 64 ? 1 : maxbw <= 128 ? 2 : maxbw <= 192 ? 3 : maxbw <= 256 ? 4 : 0; }
 
 template <typename T>
 struct BandArgs {
@@ -180,6 +180,26 @@ struct NewtonArgs {
     double tol;
 };
 
+struct DenseNewtonArgs {
+    DenseArgs d;                  // one system: x = J^-1 b
+    FinalizeArgs f;               // x to e_new, e_new1
+    NewtonArgs u;                 // the update and its convergence test
+    int *ticket;                  // blocks finished (reset by the last)
+};
+
+struct DensePorousArgs {
+    DenseArgs d;                  // the three porous fields of one system
+    FinalizeArgs f;
+    int *ticket;
+};
+
+struct NewtonStartArgs {
+    const double *U0, *P0;
+    double *U1, *P1;
+    long long nu2, np;
+    int *done, *its;
+};
+
 struct IrStartArgs {
     double *x;
     double *r;
@@ -217,6 +237,9 @@ void launch_dense_apply(const DenseArgs &a, int nsys, hipStream_t st);
 void launch_merge(const MergeArgs &a, hipStream_t st);
 void launch_init_corrections(const InitArgs &a, int nsys, hipStream_t st);
 void launch_newton_update(const NewtonArgs &a, hipStream_t st);
+void launch_dense_newton(const DenseNewtonArgs &a, hipStream_t st);
+void launch_dense_porous(const DensePorousArgs &a, int nsys, hipStream_t st);
+void launch_newton_start(const NewtonStartArgs &a, hipStream_t st);
 void launch_ir_start(const IrStartArgs &a, hipStream_t st);
 
 }  // namespace lp

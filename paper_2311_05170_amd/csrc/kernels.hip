@@ -271,16 +271,19 @@ __global__ __launch_bounds__(GB) void k_porous_residual(ResidualArgs R) {
     grid_norms_and_flag(rr, bb, R.part, R.ticket, R.conv, R.relres, R.sweeps, R.tol, id);
 }
 
-__global__ __launch_bounds__(GB) void k_porous_finalize(FinalizeArgs F) {
-    const SysDesc S = F.sys[blockIdx.y];
-    if (F.skip && *F.skip) return;
+__device__ __forceinline__ void porous_finalize_rows(const FinalizeArgs &F, const SysDesc &S, int start, int stride) {
     const int nloc = S.lw2 * S.lh2;
-    for (int q = blockIdx.x * GB + threadIdx.x; q < nloc; q += gridDim.x * GB) {
+    for (int q = start; q < nloc; q += stride) {
         const int d = F.dof2[S.node_off + q];
         if (d < 0) continue;
         for (int f = 0; f < 3; ++f)
             F.e_new[S.e2_off + (long long)f * nloc + q] = F.x[S.dof_off + (long long)f * S.ndof + d];
     }
+}
+__global__ __launch_bounds__(GB) void k_porous_finalize(FinalizeArgs F) {
+    const SysDesc S = F.sys[blockIdx.y];
+    if (F.skip && *F.skip) return;
+    porous_finalize_rows(F, S, blockIdx.x * GB + threadIdx.x, gridDim.x * GB);
 }
 
 // band assembly of the constant porous matrices (setup)
@@ -655,20 +658,23 @@ __global__ __launch_bounds__(GB) void k_oseen_apply(OseenApplyArgs<T> A) {
     if (MODE == 0) grid_norms_and_flag(rr, bb, A.part, A.ticket, A.conv, A.relres, A.sweeps, A.tol, blockIdx.y);
 }
 
-__global__ __launch_bounds__(GB) void k_oseen_finalize(FinalizeArgs F) {
-    const SysDesc S = F.sys[blockIdx.y];
-    if (F.skip && *F.skip) return;
+__device__ __forceinline__ void oseen_finalize_rows(const FinalizeArgs &F, const SysDesc &S, int start, int stride) {
     const int nloc = S.lw2 * S.lh2, nv = S.lw1 * S.lh1;
-    for (int q = blockIdx.x * GB + threadIdx.x; q < nloc; q += gridDim.x * GB) {
+    for (int q = start; q < nloc; q += stride) {
         const int d = F.dof2[S.node_off + q];
         if (d < 0) continue;
         F.e_new[S.e2_off + q] = F.x[S.dof_off + d];
         F.e_new[S.e2_off + nloc + q] = F.x[S.dof_off + d + 1];
     }
-    for (int v = blockIdx.x * GB + threadIdx.x; v < nv; v += gridDim.x * GB) {
+    for (int v = start; v < nv; v += stride) {
         const int d = F.dof1[S.vert_off + v];
         if (d >= 0) F.e_new1[S.e1_off + v] = F.x[S.dof_off + d];
     }
+}
+__global__ __launch_bounds__(GB) void k_oseen_finalize(FinalizeArgs F) {
+    const SysDesc S = F.sys[blockIdx.y];
+    if (F.skip && *F.skip) return;
+    oseen_finalize_rows(F, S, blockIdx.x * GB + threadIdx.x, gridDim.x * GB);
 }
 
 // ---------------------------------------------------------------------------
@@ -1145,6 +1151,365 @@ __global__ __launch_bounds__(64 * (NW + LU_NS)) void k_band_lu_mfma(BandArgs<T> 
 }
 
 // ---------------------------------------------------------------------------
+// Blocked band LU with a one-panel lookahead.  Same window, tiles, elimination
+// and factor layout as the kernel above; the order of the work differs:
+//   tile wavefronts, panel p (window slot P, next slot P1):
+//     L1. apply panel p to the tiles of slot row and column P1 only, write
+//         them to the other LDS buffer (the raw panel p+1) and refill them;
+//     L2. apply panel p to every other tile;
+//   writer wavefronts, panel p:
+//     S.  store L and U of panel p (factored one panel earlier);
+//     F.  factor panel p+1 (after L1), alongside L2.
+// Each writer wavefront factors the 16 x 16 diagonal tile of the panel into
+// its own LDS copy, so the writers never wait for one another: two barriers
+// per panel.  Panel tiles sit in LDS by row with the elimination index
+// permuted (index 4 kk + g at 4 g + kk) so that a lane of lane group g reads
+// its four MFMA operands with one 16-byte access; the L21 block is kept
+// negated (the update is C += (-L21) U12).  Each wavefront holds bit masks of
+// its tiles by window slot row and column.
+// ---------------------------------------------------------------------------
+constexpr int LU_LDP = 20;                  // LDS row pitch of a panel (16 used)
+__device__ __forceinline__ int lu_perm(int k) { return (k & 3) * 4 + (k >> 2); }
+
+template <typename T>
+struct alignas(16) Quad { T v[4]; };
+
+template <typename T, int TT>
+__global__ __launch_bounds__(64 * (TT + LU_NS)) void k_band_lu_la(BandArgs<T> B) {
+    typedef typename Mfma<T>::v4 v4;
+    // TT tile wavefronts; wavefront w holds tile t = 0..TT-1 at window slots
+    // (t, (w + t) mod TT): one tile in every slot row and every slot column
+    constexpr int NW = TT, W = 16 * TT, MT = TT;
+    constexpr int NRF = solve_nr(W - 16);         // solve registers per lane of this window's bandwidths
+    static_assert(2 * (W - 16) <= 64 * LU_NS, "one writer thread per panel row and column");
+    const BandSys Sy = B.sys[blockIdx.x];
+    if (B.skip && *B.skip) return;
+    const int n = Sy.n, bw = Sy.bw, ld = 2 * bw + 1;
+    const int ws = bw > 0 ? bw : 1, ldf = Sy.ldf;
+    if (n <= 0) return;
+    if (ldf != 64 * NRF || bw > W - 16) {          // layout not made for this window: report, write nothing
+        if (threadIdx.x == 0) atomicOr(B.flags, 4);
+        return;
+    }
+    const T *M = B.band + Sy.off;
+    __shared__ Quad<T> PcQ[2][W][LU_LDP / 4];      // panel tile column by row slot (L21 negated)
+    __shared__ Quad<T> PrQ[2][W][LU_LDP / 4];      // panel tile row by column slot (U12), transposed
+    __shared__ Quad<T> DgQ[LU_NS][16][4];          // factored diagonal tile by rows, per writer wavefront
+    __shared__ T Dt[LU_NS][16][16];                // the same by columns
+    __shared__ T Dv[LU_NS][16];                    // pivot reciprocals
+    __shared__ T Zs[1];                            // a zero, read by masked lanes
+    T (*Pc)[W][LU_LDP] = reinterpret_cast<T (*)[W][LU_LDP]>(&PcQ[0][0][0]);
+    T (*Pr)[W][LU_LDP] = reinterpret_cast<T (*)[W][LU_LDP]>(&PrQ[0][0][0]);
+    T (*Dg)[16][16] = reinterpret_cast<T (*)[16][16]>(&DgQ[0][0][0]);
+    const int tid = threadIdx.x, wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63, lc = lane & 15, lg = lane >> 4;
+    const int npan = (n + 15) / 16;
+    if (wv < NW) {
+        // ---- tile wavefronts
+        v4 acc[MT];
+        auto base_of = [](int S, int P, int k0) { return k0 + 16 * ((S - P + TT) % TT); };
+        auto col_of = [&](int t) { return wv + t < TT ? wv + t : wv + t - TT; };
+        // bits of this wavefront's tiles in slot row S (tile S) and column S
+        auto rmask = [&](int S) { return 1u << S; };
+        auto cmask = [&](int S) { return 1u << (S >= wv ? S - wv : S - wv + TT); };
+        // tile (I, J) of the window whose panel starts at K0 (slot P), from the
+        // band: outside the band zero, beyond n the identity
+#define LP_TILE_LOAD(DST_, I_, J_, P_, K0_)                                                    \
+        do {                                                                                  \
+            const int gi0 = base_of(I_, P_, K0_), gj = base_of(J_, P_, K0_) + lc;             \
+            _Pragma("unroll") for (int r = 0; r < 4; ++r) {                                    \
+                const int gi = gi0 + Mfma<T>::crow(lane, r), d = gi - gj;                      \
+                const bool in = gi < n && gj < n && d <= bw && d >= -bw;                       \
+                const T *src = in ? M + ((long long)gj * ld + d + bw) : (gi == gj ? B.one : B.zero); \
+                DST_[r] = *src;                                                               \
+            }                                                                                 \
+        } while (0)
+        // entering tiles in flight: staging registers, filled by loads from
+        // clamped (always valid) band addresses; out-of-band and beyond-n
+        // elements are set when the tile reaches its accumulator
+        constexpr int NSTG = 2;
+        T stg[NSTG][4];
+        int loff[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) loff[r] = lc * (ld - 1) + Mfma<T>::crow(lane, r);
+        const int nld = n * ld;
+        auto inside = [&](int gi0, int gj0) {
+            return gi0 - gj0 <= bw - 15 && gj0 - gi0 <= bw - 15 && gi0 + 15 < n && gj0 + 15 < n;
+        };
+        // slot PN tiles (the column tile first) to buffer BB, then their
+        // replacements, entering when the panel at K0N leaves the window, into
+        // the staging registers (they reach the accumulators one panel later)
+#define LP_EMIT(PN, BB, K0N)                                                                   \
+        do {                                                                                  \
+            const unsigned cmk = cmask(PN), rmk = rmask(PN);                                  \
+            _Pragma("unroll") for (int t = 0; t < MT; ++t) {                                   \
+                const int I = t, J = col_of(t);                                               \
+                if ((cmk >> t) & 1) {                                                         \
+                    _Pragma("unroll") for (int r = 0; r < 4; ++r)                              \
+                        Pc[BB][16 * I + Mfma<T>::crow(lane, r)][lu_perm(lc)] = acc[t][r];     \
+                } else if ((rmk >> t) & 1) {                                                  \
+                    _Pragma("unroll") for (int r = 0; r < 4; ++r)                              \
+                        Pr[BB][16 * J + lc][lu_perm(Mfma<T>::crow(lane, r))] = acc[t][r];     \
+                }                                                                             \
+            }                                                                                 \
+            const int PN2 = (PN) + 1 == TT ? 0 : (PN) + 1;                                    \
+            unsigned emk = cmk | rmk;                                                         \
+            _Pragma("unroll") for (int si = 0; si < NSTG; ++si) {                              \
+                if (emk == 0) break;                                                          \
+                const int t = __builtin_ctz(emk);                                             \
+                emk &= emk - 1u;                                                              \
+                const int gi0 = base_of(t, PN2, (K0N) + 16), gj0 = base_of(col_of(t), PN2, (K0N) + 16); \
+                const int b0 = gj0 * ld + gi0 - gj0 + bw;                                     \
+                _Pragma("unroll") for (int r = 0; r < 4; ++r)                                  \
+                    stg[si][r] = M[min(max(b0 + loff[r], 0), nld - 1)];                       \
+            }                                                                                 \
+        } while (0)
+        // the tiles of slot PN staged one panel ago (when the window's panel
+        // slot was PS at K0S) into their accumulators
+#define LP_ARRIVE(PN, PS, K0S)                                                                 \
+        do {                                                                                  \
+            const unsigned amk = cmask(PN) | rmask(PN);                                       \
+            _Pragma("unroll") for (int t = 0; t < MT; ++t) {                                   \
+                if ((amk >> t) & 1) {                                                         \
+                    const bool second = (amk & ((1u << t) - 1u)) != 0;                        \
+                    const int gi0 = base_of(t, PS, K0S), gj0 = base_of(col_of(t), PS, K0S);   \
+                    _Pragma("unroll") for (int r = 0; r < 4; ++r) acc[t][r] = second ? stg[1][r] : stg[0][r]; \
+                    if (!inside(gi0, gj0)) {                                                  \
+                        const int gj = gj0 + lc;                                              \
+                        _Pragma("unroll") for (int r = 0; r < 4; ++r) {                        \
+                            const int gi = gi0 + Mfma<T>::crow(lane, r), d = gi - gj;          \
+                            const bool in = gi < n && gj < n && d <= bw && d >= -bw;           \
+                            acc[t][r] = in ? acc[t][r] : (gi == gj ? T(1) : T(0));            \
+                        }                                                                     \
+                    }                                                                         \
+                }                                                                             \
+            }                                                                                 \
+        } while (0)
+        // C += (-L21) U12 from buffer BB on the tiles in MASK, operands of two
+        // tiles at a time
+#define LP_UPDATE(BB, MASK)                                                                    \
+        do {                                                                                  \
+            _Pragma("unroll") for (int t0 = 0; t0 < MT; t0 += 2) {                             \
+                if ((((MASK) >> t0) & 3u) == 0) continue;                                     \
+                Quad<T> av[2], bv[2];                                                         \
+                _Pragma("unroll") for (int t = t0; t < t0 + 2 && t < MT; ++t) {                \
+                    av[t - t0] = PcQ[BB][16 * t + lc][lg];                                    \
+                    bv[t - t0] = PrQ[BB][16 * col_of(t) + lc][lg];                            \
+                }                                                                             \
+                _Pragma("unroll") for (int t = t0; t < t0 + 2 && t < MT; ++t) {                \
+                    if (!(((MASK) >> t) & 1)) continue;                                       \
+                    _Pragma("unroll") for (int kk = 0; kk < 4; ++kk)                           \
+                        acc[t] = Mfma<T>::op(av[t - t0].v[kk], bv[t - t0].v[kk], acc[t]);     \
+                }                                                                             \
+            }                                                                                 \
+        } while (0)
+#pragma unroll
+        for (int t = 0; t < MT; ++t) LP_TILE_LOAD(acc[t], t, col_of(t), 0, 0);
+        LP_EMIT(0, 0, 0);
+        lds_barrier();                     // raw panel 0 in buffer 0
+        lds_barrier();                     // panel 0 factored
+        const unsigned valid = (1u << MT) - 1u;
+        for (int p = 0; p + 1 < npan; ++p) {
+            const int k0 = 16 * p, P = p % TT, P1 = P + 1 == TT ? 0 : P + 1, b = p & 1;
+            const unsigned mP = cmask(P) | rmask(P), mP1 = cmask(P1) | rmask(P1);
+            LP_ARRIVE(P, P1, k0 + 16);
+            LP_UPDATE(b, mP1 & ~mP);                          // L1
+            LP_EMIT(P1, b ^ 1, k0 + 16);
+            lds_barrier();                 // A: raw panel p+1 in buffer b^1
+            LP_UPDATE(b, valid & ~(mP | mP1));                // L2
+            lds_barrier();                 // D: panel p+1 factored, buffer b free
+        }
+#undef LP_TILE_LOAD
+#undef LP_EMIT
+#undef LP_ARRIVE
+#undef LP_UPDATE
+    } else {
+        // ---- writer wavefronts
+        const int wr = wv - NW, wt = tid - 64 * NW;
+        T *Lr = B.fac + Sy.foff, *Ur = Lr + (long long)n * ldf, *Di = Ur + (long long)n * ldf;
+        int bad = 0;
+        auto factor = [&](int pf, int bb) {
+            const int P = pf % TT;
+            {
+                // diagonal tile: lane l holds row l mod 16; this wavefront's copy
+                T d[16];
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const Quad<T> x = PcQ[bb][16 * P + lc][g];
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) d[4 * kk + g] = x.v[kk];
+                }
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    T piv = wave_bcast(d[j], j);
+                    if (!(fabs((double)piv) > 0.0) || !isfinite((double)piv)) { bad = 1; piv = T(1); }
+                    T inv;
+                    if constexpr (sizeof(T) == 4) {
+                        inv = __builtin_amdgcn_rcpf(piv);           // then one Newton step
+                        inv = fmaf(inv, fmaf(-piv, inv, 1.0f), inv);
+                    } else {
+                        inv = T(1) / piv;
+                    }
+                    if (lane == j) Dv[wr][j] = inv;
+                    const T l = d[j] * inv;
+                    const T lm = lc > j ? l : T(0);
+#pragma unroll
+                    for (int c = j + 1; c < 16; ++c) d[c] = fma(-lm, wave_bcast(d[c], j), d[c]);
+                    d[j] = lc > j ? l : d[j];
+                }
+                if (lane < 16) {
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) {
+                        Quad<T> x;
+#pragma unroll
+                        for (int kk = 0; kk < 4; ++kk) x.v[kk] = d[4 * g + kk];
+                        DgQ[wr][lc][g] = x;
+                    }
+#pragma unroll
+                    for (int c = 0; c < 16; ++c) Dt[wr][c][lc] = d[c];
+                }
+            }
+            // the copy is read back by other lanes of this wavefront only
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+            if (wt < W - 16) {
+                // one L21 row: l U11 = a, stored negated
+                const int rho = (16 * (P + 1) + wt) % W;
+                T a[16];
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const Quad<T> x = PcQ[bb][rho][g];
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) a[4 * kk + g] = x.v[kk];
+                }
+#pragma unroll
+                for (int c = 0; c < 16; ++c) {
+                    a[c] *= Dv[wr][c];
+                    if (c + 1 < 16) {
+                        T u[16];
+#pragma unroll
+                        for (int g = 0; g < 4; ++g) {
+                            const Quad<T> x = DgQ[wr][c][g];
+#pragma unroll
+                            for (int kk = 0; kk < 4; ++kk) u[4 * g + kk] = x.v[kk];
+                        }
+#pragma unroll
+                        for (int c2 = c + 1; c2 < 16; ++c2) a[c2] = fma(-a[c], u[c2], a[c2]);
+                    }
+                }
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    Quad<T> x;
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) x.v[kk] = -a[4 * kk + g];
+                    PcQ[bb][rho][g] = x;
+                }
+            } else if (wt < 2 * (W - 16)) {
+                // one U12 column: L11 u = a
+                const int sig = (16 * (P + 1) + wt - (W - 16)) % W;
+                T u[16];
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const Quad<T> x = PrQ[bb][sig][g];
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) u[4 * kk + g] = x.v[kk];
+                }
+#pragma unroll
+                for (int r = 0; r + 1 < 16; ++r) {
+                    T l[16];
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) {
+                        const Quad<T> x = reinterpret_cast<const Quad<T> *>(&Dt[wr][r][0])[g];
+#pragma unroll
+                        for (int kk = 0; kk < 4; ++kk) l[4 * g + kk] = x.v[kk];
+                    }
+#pragma unroll
+                    for (int r2 = r + 1; r2 < 16; ++r2) u[r2] = fma(-l[r2], u[r], u[r2]);
+                }
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    Quad<T> x;
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) x.v[kk] = u[4 * kk + g];
+                    PrQ[bb][sig][g] = x;
+                }
+            }
+        };
+        // L and U of panel ps from buffer bb (diagonal tile from this
+        // wavefront's copy) in the solves' slot-rotated layout
+        int km0 = 0;                                  // k0 mod ws
+        auto store = [&](int ps, int bb) {
+            const int k0 = 16 * ps, P = ps % TT;
+            struct Grp { T v[NRF]; };
+            // L: column c = wr + LU_NS j, lane l fills slots l + 64 m (one vector store)
+#pragma unroll
+            for (int j = 0; j < (16 + LU_NS - 1) / LU_NS; ++j) {
+                const int c = wr + LU_NS * j, k = k0 + c;
+                if (c >= 16 || k >= n) break;
+                int kmod = km0 + c;
+                while (kmod >= ws) kmod -= ws;
+                Grp gv;
+#pragma unroll
+                for (int m = 0; m < NRF; ++m) {
+                    const int s = lane + 64 * m;
+                    int o = s - kmod - 1;
+                    o = o < 0 ? o + ws : o;
+                    o += 1;                                   // row k + o, 1 <= o <= ws
+                    const int dr = c + o;
+                    int iw = 16 * P + dr;
+                    iw = iw >= W ? iw - W : iw;
+                    const bool ok = s < ws && k + o < n;
+                    // one unconditional LDS read: L11 from the copy, -L21 from the panel, else zero
+                    const T *src = dr < 16 ? &Dg[wr][dr & 15][c] : &Pc[bb][iw][lu_perm(c)];
+                    src = ok ? src : &Zs[0];
+                    const T v = *src;
+                    gv.v[m] = dr < 16 ? v : -v;
+                }
+                *reinterpret_cast<Grp *>(Lr + (long long)k * ldf + lane * NRF) = gv;
+            }
+            // U(k0 + c, j), j = k0 + c + 1 .. k0 + c + ws: lanes c = 0..15 over
+            // the panel rows, four columns per pass
+            {
+                constexpr int NJ = (W + 4 * LU_NS - 1) / (4 * LU_NS);
+                const int c = lc, k = k0 + c;
+                int kmod = km0 + c;
+                while (kmod >= ws) kmod -= ws;
+                const int pk = (kmod & 63) * NRF + (kmod >> 6);
+#pragma unroll
+                for (int u = 0; u < NJ; ++u) {
+                    const int jo = lg + 4 * wr + 4 * LU_NS * u;
+                    const int j = k0 + 1 + jo;
+                    const bool ok = jo < 15 + ws && j > k && j - k <= ws && j < n;
+                    int jw = 16 * P + 1 + jo;
+                    jw = jw >= W ? jw - W : jw;
+                    jw = jw >= W ? jw - W : jw;
+                    const int dj = j - k0;
+                    const T *src = dj < 16 ? &Dg[wr][c][dj & 15] : &Pr[bb][jw][lu_perm(c)];
+                    const T v = *src;
+                    if (ok) Ur[(long long)j * ldf + pk] = v;
+                }
+            }
+            if (wr == 0 && lane < 16 && k0 + lane < n) Di[k0 + lane] = Dv[0][lane];
+            km0 += 16;
+            while (km0 >= ws) km0 -= ws;
+        };
+        if (wt == 0) Zs[0] = T(0);
+        lds_barrier();                     // raw panel 0 in buffer 0
+        factor(0, 0);
+        lds_barrier();                     // panel 0 factored
+        for (int p = 0; p + 1 < npan; ++p) {
+            const int b = p & 1;
+            store(p, b);
+            lds_barrier();                 // A
+            factor(p + 1, b ^ 1);
+            lds_barrier();                 // D
+        }
+        if (npan > 0) store(npan - 1, (npan - 1) & 1);
+        if (bad && lane == 0) atomicOr(B.flags, 4);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Band triangular solves, one wavefront per right-hand side: L y = r (unit
 // lower), U d = y, x += d.  The window of ws = bw rows is spread circularly
 // over the lanes (row i in slot i mod ws, slot = lane + 64 m); the finished
@@ -1351,11 +1716,10 @@ __global__ __launch_bounds__(64) void k_band_solve(SolveArgs<T> A) {
 // range, eight loads in flight per lane) and their partial sums are added in
 // wavefront order.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_dense_apply(DenseArgs A) {
-    if (A.skip && *A.skip) return;
-    const int n = A.n, s = blockIdx.y;
+__device__ __forceinline__ void dense_rows(const DenseArgs &A, int s, int bx) {
+    const int n = A.n;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int i = blockIdx.x * 64 + lane;
+    const int i = bx * 64 + lane;
     const int ic = i < n ? i : n - 1;
     const double *inv = A.inv + (long long)s * n * n + ic;
     const double *b = A.b + (long long)s * n;
@@ -1377,6 +1741,26 @@ __global__ __launch_bounds__(1024) void k_dense_apply(DenseArgs A) {
         for (int k = 0; k < 16; ++k) t += red[k][lane];
         A.x[(long long)s * n + i] = t;
     }
+}
+__global__ __launch_bounds__(1024) void k_dense_apply(DenseArgs A) {
+    if (A.skip && *A.skip) return;
+    dense_rows(A, blockIdx.y, blockIdx.x);
+}
+
+// true in the one block that finishes last (all blocks' global writes are
+// then visible to it); the ticket is reset for the next launch
+__device__ __forceinline__ bool last_block(int *ticket) {
+    __shared__ int last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nb = (int)(gridDim.x * gridDim.y);
+        last = atomicAdd(ticket, 1) == nb - 1;
+        if (last) *ticket = 0;
+    }
+    __syncthreads();
+    if (last) __threadfence();
+    return last;
 }
 
 // ---------------------------------------------------------------------------
@@ -1433,34 +1817,78 @@ __global__ void k_init_corrections(InitArgs A) {
 }
 
 // Newton update of the coarse Navier-Stokes iterate: U += e, P += d, and the
-// convergence test ||(e, d)|| <= tol ||(U, P)|| (one workgroup)
-__global__ __launch_bounds__(256) void k_newton_update(NewtonArgs A) {
-    if (*A.done) return;
+// convergence test ||(e, d)|| <= tol ||(U, P)||, by the first 256 threads of
+// a block (every thread of the block takes the barriers)
+__device__ void newton_update_block(const NewtonArgs &A) {
+    constexpr int NT = 256;
+    const int tid = threadIdx.x;
     const long long nu = A.nu, np = A.np;
     double dd = 0.0, xx = 0.0;
-    for (long long i = threadIdx.x; i < 2 * nu; i += blockDim.x) {
-        const double u = A.U[i] + A.e[i];
-        A.U[i] = u;
-        dd += A.e[i] * A.e[i];
-        xx += u * u;
+    if (tid < NT) {
+        for (long long i = tid; i < 2 * nu; i += NT) {
+            const double u = A.U[i] + A.e[i];
+            A.U[i] = u;
+            dd += A.e[i] * A.e[i];
+            xx += u * u;
+        }
+        for (long long i = tid; i < np; i += NT) {
+            const double p = A.P[i] + A.e1[i];
+            A.P[i] = p;
+            dd += A.e1[i] * A.e1[i];
+            xx += p * p;
+        }
     }
-    for (long long i = threadIdx.x; i < np; i += blockDim.x) {
-        const double p = A.P[i] + A.e1[i];
-        A.P[i] = p;
-        dd += A.e1[i] * A.e1[i];
-        xx += p * p;
+    __shared__ double sd[NT], sx[NT];
+    if (tid < NT) {
+        sd[tid] = dd;
+        sx[tid] = xx;
     }
-    __shared__ double sd[256], sx[256];
-    sd[threadIdx.x] = dd;
-    sx[threadIdx.x] = xx;
     __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) { sd[threadIdx.x] += sd[threadIdx.x + s]; sx[threadIdx.x] += sx[threadIdx.x + s]; }
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if (tid < s) { sd[tid] += sd[tid + s]; sx[tid] += sx[tid + s]; }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         A.its[0] += 1;
         if (sqrt(sd[0]) <= A.tol * sqrt(sx[0])) *A.done = 1;
+    }
+}
+__global__ __launch_bounds__(256) void k_newton_update(NewtonArgs A) {
+    if (*A.done) return;
+    newton_update_block(A);
+}
+
+// One chord step of the coarse Navier-Stokes solve after its right-hand side:
+// x = J^-1 b by row blocks, then (last block) the correction to the node
+// layout and the Newton update with its convergence test
+__global__ __launch_bounds__(1024) void k_dense_newton(DenseNewtonArgs A) {
+    if (*A.u.done) return;
+    dense_rows(A.d, 0, blockIdx.x);
+    if (!last_block(A.ticket)) return;
+    oseen_finalize_rows(A.f, A.f.sys[0], threadIdx.x, blockDim.x);
+    __syncthreads();
+    newton_update_block(A.u);
+}
+
+// The three coarse porous solves: x_f = A_f^-1 b_f, then (last block) the
+// solution to the node layout
+__global__ __launch_bounds__(1024) void k_dense_porous(DensePorousArgs A) {
+    dense_rows(A.d, blockIdx.y, blockIdx.x);
+    if (!last_block(A.ticket)) return;
+    porous_finalize_rows(A.f, A.f.sys[0], threadIdx.x, blockDim.x);
+}
+
+// start of the coarse Newton solve: the iterate from the previous time level,
+// counters cleared
+__global__ void k_newton_start(NewtonStartArgs A) {
+    const long long tot = A.nu2 + A.np;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < tot; i += (long long)gridDim.x * blockDim.x) {
+        if (i < A.nu2) A.U1[i] = A.U0[i];
+        else A.P1[i - A.nu2] = A.P0[i - A.nu2];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *A.done = 0;
+        *A.its = 0;
     }
 }
 
@@ -1527,6 +1955,16 @@ void launch_oseen_finalize(const FinalizeArgs &a, int nsys, int maxnodes, hipStr
 
 template <typename T>
 bool launch_band_lu(const BandArgs<T> &a, int nsys, int maxbw, int variant, hipStream_t st) {
+    if constexpr (sizeof(T) == 4) {
+        if (variant == 9) {
+            // the same with a one-panel lookahead (FP32 factors)
+            if (maxbw <= 64) { hipLaunchKernelGGL((k_band_lu_la<T, 5>), dim3(nsys), dim3(64 * (5 + LU_NS)), 0, st, a); return true; }
+            if (maxbw <= 96) { hipLaunchKernelGGL((k_band_lu_la<T, 7>), dim3(nsys), dim3(64 * (7 + LU_NS)), 0, st, a); return true; }
+            if (maxbw <= 128) { hipLaunchKernelGGL((k_band_lu_la<T, 9>), dim3(nsys), dim3(64 * (9 + LU_NS)), 0, st, a); return true; }
+            if (maxbw <= 160) { hipLaunchKernelGGL((k_band_lu_la<T, 11>), dim3(nsys), dim3(64 * (11 + LU_NS)), 0, st, a); return true; }
+            return false;
+        }
+    }
     if (variant == 8) {
         // blocked factorisation on the matrix cores: window 16 TT >= bw + 16
         constexpr int X = 64 * LU_NS;
@@ -1587,6 +2025,15 @@ void launch_merge(const MergeArgs &a, hipStream_t st) {
 }
 void launch_init_corrections(const InitArgs &a, int nsys, hipStream_t st) {
     hipLaunchKernelGGL(k_init_corrections, dim3(nsys), dim3(256), 0, st, a);
+}
+void launch_dense_newton(const DenseNewtonArgs &a, hipStream_t st) {
+    hipLaunchKernelGGL(k_dense_newton, dim3((a.d.n + 63) / 64), dim3(1024), 0, st, a);
+}
+void launch_dense_porous(const DensePorousArgs &a, int nsys, hipStream_t st) {
+    hipLaunchKernelGGL(k_dense_porous, dim3((a.d.n + 63) / 64, nsys), dim3(1024), 0, st, a);
+}
+void launch_newton_start(const NewtonStartArgs &a, hipStream_t st) {
+    hipLaunchKernelGGL(k_newton_start, dim3(8), dim3(256), 0, st, a);
 }
 void launch_newton_update(const NewtonArgs &a, hipStream_t st) {
     hipLaunchKernelGGL(k_newton_update, dim3(1), dim3(256), 0, st, a);

@@ -128,11 +128,12 @@ def _ragged():
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("variant", ["0", "8"])
+@pytest.mark.parametrize("variant", ["0", "8", "9"])
 def test_parity_lu_kernels(precision, variant, monkeypatch):
-    """Both band factorisations (variant 0: elimination on the vector units;
-    8: blocked, trailing updates on the matrix cores) for every system of the
-    run (porous, coarse and local Oseen) agree with the oracle."""
+    """Every band factorisation (variant 0: elimination on the vector units;
+    8: blocked, trailing updates on the matrix cores; 9: the blocked one with
+    a one-panel lookahead, FP32 factors only) for every system of the run
+    (porous, coarse and local Oseen) agrees with the oracle."""
     monkeypatch.setenv("LP_LU_VARIANT", variant)
     run_parity(_ragged(), precision, 3)
 
