@@ -122,8 +122,8 @@ struct lp_ctx {
     double *lu_dummy = nullptr;        // sink of the factorisation's masked stores
     long long lu_dummy_coarse_off = 0;
     int lu_variant = 0;                // factorisation kernel of the porous and coarse systems (0: default)
-    int lu_variant_ose = 0;            // of the local Oseen systems (mixed: 9, blocked on the matrix cores with lookahead)
-    int lu_variant_cns = 8;            // of the coarse Navier-Stokes Jacobian (8: blocked on the matrix cores)
+    int lu_variant_ose = 9;            // of the local Oseen systems (blocked on the matrix cores with lookahead)
+    int lu_variant_cns = 9;            // of the coarse Navier-Stokes Jacobian (9: blocked on the matrix cores with lookahead)
     int solve_depth = 0;               // factor columns prefetched by the band solves (16, 32; 0 = by precision and bandwidth)
     // device constants read by masked loads: 512 zero doubles (a zero column
     // for the solves), then 1.0 as double, then 1.0f as float
@@ -567,7 +567,7 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     c->prm = *prm;
     c->opt = *opt;
     c->mixed = opt->precision == LP_MIXED;
-    c->lu_variant_ose = c->mixed ? 9 : 0;
+    c->lu_variant_ose = 9;
     if (const char *v = std::getenv("LP_LU_VARIANT")) c->lu_variant = c->lu_variant_ose = c->lu_variant_cns = std::atoi(v);
     if (const char *v = std::getenv("LP_LU_VARIANT_COARSE")) c->lu_variant_cns = std::atoi(v);
     if (const char *v = std::getenv("LP_SOLVE_DEPTH")) c->solve_depth = std::atoi(v);
@@ -837,10 +837,14 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
         dp.ticket = c->tick_dp;
         lp::launch_dense_porous(dp, 3, st);
     }
-    // (5.4): Navier-Stokes by Newton from (u^n, p^n); each iteration solves the
-    // Oseen system linearised about the current iterate
+    // (5.4): Navier-Stokes by Newton from the extrapolation 2 (u^n, p^n) -
+    // (u^(n-1), p^(n-1)) (from (u^n, p^n) at the first step); each iteration
+    // solves the Oseen system linearised about the current iterate
     {
-        lp::NewtonStartArgs ns{c->cU[o], c->cp[o], c->cU[nw], c->cp[nw], 2 * nc2, c->nc1, c->d_done, c->d_its};
+        const int om = (int)((m + lp_ctx::RING - 2) % lp_ctx::RING);
+        const bool ex = m >= 2;
+        lp::NewtonStartArgs ns{c->cU[o], c->cp[o], ex ? c->cU[om] : nullptr, ex ? c->cp[om] : nullptr,
+                               c->cU[nw], c->cp[nw], 2 * nc2, c->nc1, c->d_done, c->d_its};
         lp::launch_newton_start(ns, st);
     }
     for (int it = 0; it < c->opt.max_newton; ++it) {
@@ -871,9 +875,8 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
             // explicit inverse of the Jacobian: each chord step is then one
             // dense product instead of a serial band solve
             const int n = P.cns.ndof;
-            HIPCHK(hipMemsetAsync(c->inv_cn, 0, (size_t)n * n * sizeof(double), st));
             lp::SolveArgs<double> sa{c->d_iv_cns, c->fac_cns, c->eye_cn, c->inv_cn, nullptr, n, c->d_done,
-                                     (const double *)c->consts, c->const_one<double>(), (const double *)c->consts};
+                                     (const double *)c->consts, c->const_one<double>(), (const double *)c->consts, 1};
             if (!lp::launch_band_solve<double>(sa, 1, n, P.cns.bw, n, c->solve_depth, st)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
         }
         // chord step: x = J^-1 b, the correction to the node layout and the

@@ -138,6 +138,7 @@ struct SolveArgs {
     const T *zero;                // device constants read by masked prefetches
     const T *one;
     const double *zero64;
+    int assign = 0;               // 1: x = d (no prior x read), 0: x += d
 };
 
 struct DenseArgs {
@@ -194,8 +195,9 @@ struct DensePorousArgs {
 };
 
 struct NewtonStartArgs {
-    const double *U0, *P0;
-    double *U1, *P1;
+    const double *U0, *P0;        // level n
+    const double *Um, *Pm;        // level n-1 (null at the first step)
+    double *U1, *P1;              // first iterate for level n+1
     long long nu2, np;
     int *done, *its;
 };

@@ -591,18 +591,55 @@ __global__ __launch_bounds__(GB) void k_oseen_apply(OseenApplyArgs<T> A) {
                             }
                         }
                     }
-                    for (int k = 0; k < 6; ++k) {
-                        if (dk[k] < 0) continue;
-                        for (int c = 0; c < 2; ++c)
-                            for (int d = 0; d < 2; ++d) {
-                                double v = nue * c_ref.Se[t][c * 6 + la][d * 6 + k] + eta * Nw[c][d][k];
-                                if (c == d) v += edt * h2 * c_ref.Me[t][la][k];
-                                put(dv + c, dk[k] + d, v);
-                            }
+                    // read-modify-write of the element's entries in batches: the
+                    // entries of one batch are distinct (distinct columns of a
+                    // row), so all their loads go out before the first store
+                    // (masked entries read the band's first word and write nothing)
+                    {
+                        int off[24];
+                        T old[24];
+#pragma unroll
+                        for (int k = 0; k < 6; ++k)
+#pragma unroll
+                            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                                for (int d = 0; d < 2; ++d) {
+                                    const int col = dk[k] + d;
+                                    off[4 * k + 2 * c + d] = dk[k] >= 0 ? col * ld + (dv + c - col + S.bw) : 0;
+                                }
+#pragma unroll
+                        for (int i = 0; i < 24; ++i) old[i] = band[off[i]];
+#pragma unroll
+                        for (int k = 0; k < 6; ++k) {
+                            if (dk[k] < 0) continue;
+#pragma unroll
+                            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                                for (int d = 0; d < 2; ++d) {
+                                    double v = nue * c_ref.Se[t][c * 6 + la][d * 6 + k] + eta * Nw[c][d][k];
+                                    if (c == d) v += edt * h2 * c_ref.Me[t][la][k];
+                                    const int i = 4 * k + 2 * c + d;
+                                    band[off[i]] = (T)((double)old[i] + v);
+                                }
+                        }
                     }
-                    for (int v = 0; v < 3; ++v)
-                        if (pk[v] >= 0)
-                            for (int c = 0; c < 2; ++c) put(dv + c, pk[v], -eta * h * c_ref.Be[t][v][c * 6 + la]);
+                    {
+                        int off[6];
+                        T old[6];
+#pragma unroll
+                        for (int v = 0; v < 3; ++v)
+#pragma unroll
+                            for (int c = 0; c < 2; ++c)
+                                off[2 * v + c] = pk[v] >= 0 ? pk[v] * ld + (dv + c - pk[v] + S.bw) : 0;
+#pragma unroll
+                        for (int i = 0; i < 6; ++i) old[i] = band[off[i]];
+#pragma unroll
+                        for (int v = 0; v < 3; ++v)
+                            if (pk[v] >= 0)
+#pragma unroll
+                                for (int c = 0; c < 2; ++c)
+                                    band[off[2 * v + c]] = (T)((double)old[2 * v + c] - eta * h * c_ref.Be[t][v][c * 6 + la]);
+                    }
                 }
             }
             if (dp >= 0) {
@@ -613,9 +650,23 @@ __global__ __launch_bounds__(GB) void k_oseen_apply(OseenApplyArgs<T> A) {
                         for (int k = 0; k < 6; ++k) s += c_ref.Be[t][lv][d * 6 + k] * X[d][k];
                     yq += eta * h * s;
                 } else {
+                    int off[12];
+                    T old[12];
+#pragma unroll
+                    for (int k = 0; k < 6; ++k)
+#pragma unroll
+                        for (int d = 0; d < 2; ++d) {
+                            const int col = dk[k] + d;
+                            off[2 * k + d] = dk[k] >= 0 ? col * ld + (dp - col + S.bw) : 0;
+                        }
+#pragma unroll
+                    for (int i = 0; i < 12; ++i) old[i] = band[off[i]];
+#pragma unroll
                     for (int k = 0; k < 6; ++k)
                         if (dk[k] >= 0)
-                            for (int d = 0; d < 2; ++d) put(dp, dk[k] + d, eta * h * c_ref.Be[t][lv][d * 6 + k]);
+#pragma unroll
+                            for (int d = 0; d < 2; ++d)
+                                band[off[2 * k + d]] = (T)((double)old[2 * k + d] + eta * h * c_ref.Be[t][lv][d * 6 + k]);
                 }
             }
         });
@@ -1695,14 +1746,18 @@ __global__ __launch_bounds__(64) void k_band_solve(SolveArgs<T> A) {
         sk = sk == 0 ? ws - 1 : sk - 1;
     }
     __syncthreads();
-    for (int i0 = lane; i0 < n; i0 += 64 * SOLVE_LD) {
-        double v[SOLVE_LD];
+    if (A.assign) {
+        for (int i = lane; i < n; i += 64) x[i] = (double)ys[i];
+    } else {
+        for (int i0 = lane; i0 < n; i0 += 64 * SOLVE_LD) {
+            double v[SOLVE_LD];
 #pragma unroll
-        for (int u = 0; u < SOLVE_LD; ++u) v[u] = x[min(i0 + 64 * u, n - 1)];
+            for (int u = 0; u < SOLVE_LD; ++u) v[u] = x[min(i0 + 64 * u, n - 1)];
 #pragma unroll
-        for (int u = 0; u < SOLVE_LD; ++u) {
-            const int i = i0 + 64 * u;
-            if (i < n) x[i] = v[u] + (double)ys[i];
+            for (int u = 0; u < SOLVE_LD; ++u) {
+                const int i = i0 + 64 * u;
+                if (i < n) x[i] = v[u] + (double)ys[i];
+            }
         }
     }
 #undef LP_FCOL
@@ -1878,13 +1933,19 @@ __global__ __launch_bounds__(1024) void k_dense_porous(DensePorousArgs A) {
     porous_finalize_rows(A.f, A.f.sys[0], threadIdx.x, blockDim.x);
 }
 
-// start of the coarse Newton solve: the iterate from the previous time level,
-// counters cleared
+// start of the coarse Newton solve: the first iterate is the linear
+// extrapolation 2 x^n - x^(n-1) of the two previous levels (x^n at the first
+// step), counters cleared
 __global__ void k_newton_start(NewtonStartArgs A) {
     const long long tot = A.nu2 + A.np;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < tot; i += (long long)gridDim.x * blockDim.x) {
-        if (i < A.nu2) A.U1[i] = A.U0[i];
-        else A.P1[i - A.nu2] = A.P0[i - A.nu2];
+        const bool u = i < A.nu2;
+        const long long j = u ? i : i - A.nu2;
+        const double x0 = u ? A.U0[j] : A.P0[j];
+        const double xm = A.Um ? (u ? A.Um[j] : A.Pm[j]) : x0;
+        const double x1 = 2.0 * x0 - xm;
+        if (u) A.U1[j] = x1;
+        else A.P1[j] = x1;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         *A.done = 0;
@@ -1955,15 +2016,13 @@ void launch_oseen_finalize(const FinalizeArgs &a, int nsys, int maxnodes, hipStr
 
 template <typename T>
 bool launch_band_lu(const BandArgs<T> &a, int nsys, int maxbw, int variant, hipStream_t st) {
-    if constexpr (sizeof(T) == 4) {
-        if (variant == 9) {
-            // the same with a one-panel lookahead (FP32 factors)
-            if (maxbw <= 64) { hipLaunchKernelGGL((k_band_lu_la<T, 5>), dim3(nsys), dim3(64 * (5 + LU_NS)), 0, st, a); return true; }
-            if (maxbw <= 96) { hipLaunchKernelGGL((k_band_lu_la<T, 7>), dim3(nsys), dim3(64 * (7 + LU_NS)), 0, st, a); return true; }
-            if (maxbw <= 128) { hipLaunchKernelGGL((k_band_lu_la<T, 9>), dim3(nsys), dim3(64 * (9 + LU_NS)), 0, st, a); return true; }
-            if (maxbw <= 160) { hipLaunchKernelGGL((k_band_lu_la<T, 11>), dim3(nsys), dim3(64 * (11 + LU_NS)), 0, st, a); return true; }
-            return false;
-        }
+    if (variant == 9) {
+        // the same with a one-panel lookahead
+        if (maxbw <= 64) { hipLaunchKernelGGL((k_band_lu_la<T, 5>), dim3(nsys), dim3(64 * (5 + LU_NS)), 0, st, a); return true; }
+        if (maxbw <= 96) { hipLaunchKernelGGL((k_band_lu_la<T, 7>), dim3(nsys), dim3(64 * (7 + LU_NS)), 0, st, a); return true; }
+        if (maxbw <= 128) { hipLaunchKernelGGL((k_band_lu_la<T, 9>), dim3(nsys), dim3(64 * (9 + LU_NS)), 0, st, a); return true; }
+        if (maxbw <= 160) { hipLaunchKernelGGL((k_band_lu_la<T, 11>), dim3(nsys), dim3(64 * (11 + LU_NS)), 0, st, a); return true; }
+        return false;
     }
     if (variant == 8) {
         // blocked factorisation on the matrix cores: window 16 TT >= bw + 16
