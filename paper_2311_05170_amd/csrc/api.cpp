@@ -49,10 +49,11 @@ struct lp_ctx {
     static constexpr int FSLOTS = 5;   // factor slots of the local Oseen operators (< RING)
     hipStream_t cstream = nullptr;
     hipEvent_t ev_coarse[RING] = {}, ev_local[RING] = {};
+    hipEvent_t ev_cpor[RING] = {};     // coarse porous solves of a level done (they run on a factor stream)
     // the local porous batch of step m runs on factor stream m % 2, after that
     // step's Oseen factorisation, beside the Oseen solves (four streams in all,
     // within HIP's default of four hardware queues per process)
-    hipEvent_t ev_pro = nullptr, ev_por = nullptr;
+    hipEvent_t ev_por = nullptr;                       // porous batch of the latest local step done
     // The local Oseen operator of step m depends only on u_cH^m, so its
     // assembly and factorisation run on factor stream m % 2 as soon as coarse
     // step m is done, overlapping the solves of step m-1 and the factorisation
@@ -102,6 +103,8 @@ struct lp_ctx {
     lp::BandSys *d_iv_cpor = nullptr, *d_iv_cns = nullptr;
     void *fac_por = nullptr, *fac_ose[FSLOTS] = {};       // factors (layout: fac_layout)
     double *pro_Uf[2] = {};                              // u_cH^m prolonged for factor stream m % 2
+    double *pro_Pb[2] = {};                              // the porous batch's prolonged inputs, per factor stream:
+                                                         // p^(n+1) (3 fields), p^n (3 fields), u_y^n
     double *fac_cpor = nullptr, *fac_cns = nullptr;
     double *b_por = nullptr, *x_por = nullptr, *r_por = nullptr;
     double *b_ose = nullptr, *x_ose = nullptr, *r_ose = nullptr;
@@ -153,6 +156,7 @@ struct lp_ctx {
         for (int i = 0; i < RING; ++i) {
             if (ev_coarse[i]) (void)hipEventDestroy(ev_coarse[i]);
             if (ev_local[i]) (void)hipEventDestroy(ev_local[i]);
+            if (ev_cpor[i]) (void)hipEventDestroy(ev_cpor[i]);
         }
         if (cstream) (void)hipStreamDestroy(cstream);
         if (serial) fstream[0] = fstream[1] = nullptr;
@@ -160,7 +164,6 @@ struct lp_ctx {
             if (fstream[i]) { (void)hipStreamSynchronize(fstream[i]); (void)hipStreamDestroy(fstream[i]); }
         for (int i = 0; i < FSLOTS; ++i)
             if (ev_fac[i]) (void)hipEventDestroy(ev_fac[i]);
-        if (ev_pro) (void)hipEventDestroy(ev_pro);
         if (ev_por) (void)hipEventDestroy(ev_por);
         for (auto &r : recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
         for (auto e : pool) (void)hipEventDestroy(e);
@@ -440,21 +443,41 @@ lp_status factor_oseen(lp_ctx *c, int64_t m) {
     return LP_OK;
 }
 
+// the porous batch's coarse inputs on its own stream: p^(n+1), p^n and u_y^n
+// prolonged into pro (7 fields)
+void prolong_porous(lp_ctx *c, double *pro, int cnew, int cold, hipStream_t st) {
+    const long long nc2 = c->nc2, nf2 = c->nf2;
+    lp::ProlongArgs pa{};
+    pa.NH = c->P.NH; pa.Nh = c->P.Nh; pa.k = c->P.k;
+    pa.nfields = 6;
+    for (int f = 0; f < 3; ++f) {
+        pa.src[f] = c->cP[cnew] + f * nc2;
+        pa.dst[f] = pro + f * nf2;
+        pa.src[3 + f] = c->cP[cold] + f * nc2;
+        pa.dst[3 + f] = pro + (3 + f) * nf2;
+    }
+    lp::launch_prolong_p2(pa, st);
+    pa.nfields = 1;
+    pa.src[0] = c->cU[cold] + nc2;
+    pa.dst[0] = pro + 6 * nf2;
+    lp::launch_prolong_p2(pa, st);
+}
+
 template <typename T>
-lp_status local_porous(lp_ctx *c, hipStream_t st) {
+lp_status local_porous(lp_ctx *c, const double *pro, hipStream_t st) {
     const int nsys = (int)c->P.por.size();
     const long long nf2 = c->nf2;
     const int o = c->ecur, nw = 1 - c->ecur;
     lp::PorousArgs pa{};
     pa.sys = c->d_por; pa.cls2 = c->d_cls2; pa.dof2 = c->d_dof2;
     for (int f = 0; f < 3; ++f) {
-        pa.P1[f] = c->pro_P1 + f * nf2;
-        pa.P0[f] = c->pro_P0 + f * nf2;
+        pa.P1[f] = pro + f * nf2;
+        pa.P0[f] = pro + (3 + f) * nf2;
         pa.ex[f] = c->ex_f[f];
         pa.load[f][0] = c->ld_f[f][0];
         pa.load[f][1] = c->ld_f[f][1];
     }
-    pa.Uy0 = c->pro_U0 + nf2;
+    pa.Uy0 = pro + 6 * nf2;
     pa.e_old = c->e2[o]; pa.e_new = c->e2[nw]; pa.b = c->b_por;
     const double t1 = time_at(c, c->n + 1);
     pa.tf[0] = std::cos(t1); pa.tf[1] = std::sin(t1); pa.tf[2] = pa.tf[0] * pa.tf[0];
@@ -658,6 +681,7 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     TRY(c->dalloc(&c->pro_U0, 2 * c->nf2));
     TRY(c->dalloc(&c->pro_p1, c->nf1));
     for (int l = 0; l < 2; ++l) TRY(c->dalloc(&c->pro_Uf[l], 2 * c->nf2));
+    for (int l = 0; l < 2; ++l) TRY(c->dalloc(&c->pro_Pb[l], 7 * c->nf2));
     for (int l = 0; l < 2; ++l) { TRY(c->dalloc(&c->e2[l], P.e2_total)); TRY(c->dalloc(&c->e1[l], P.e1_total)); }
     TRY(c->dalloc(&c->m_P, 3 * c->nf2));
     TRY(c->dalloc(&c->m_U, 2 * c->nf2));
@@ -746,11 +770,11 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
         for (int l = 0; l < 2; ++l) HIPCHK(hipStreamCreateWithFlags(&c->fstream[l], hipStreamNonBlocking));
     }
     for (int i = 0; i < lp_ctx::FSLOTS; ++i) HIPCHK(hipEventCreateWithFlags(&c->ev_fac[i], hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&c->ev_pro, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&c->ev_por, hipEventDisableTiming));
     for (int i = 0; i < lp_ctx::RING; ++i) {
         HIPCHK(hipEventCreateWithFlags(&c->ev_coarse[i], hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&c->ev_local[i], hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&c->ev_cpor[i], hipEventDisableTiming));
     }
     prolong_all(c.get(), 0, 0, st);
     {
@@ -808,11 +832,25 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
     (void)stream;   // the coarse stage only touches internal state and runs on the context's own stream
     hipStream_t st = c->cstream;
     const int64_t m = c->n + 1;                       // time level produced
-    // slot m % RING was last read by local step m - RING + 1
-    if (m >= lp_ctx::RING) HIPCHK(hipStreamWaitEvent(st, c->ev_local[(m - lp_ctx::RING + 1) % lp_ctx::RING], 0));
-    StageTimer ttot(c, LP_T_COARSE, st);
+    // The porous solves and the Navier-Stokes solve of a coarse step do not
+    // read each other (each takes the other's previous level), so the porous
+    // part runs on the factor stream of this step, off the coarse stream.
+    hipStream_t ps = c->fstream[m % 2];
     const lp::Plan &P = c->P;
     const int o = (int)((m - 1) % lp_ctx::RING), nw = (int)(m % lp_ctx::RING);
+    // slot m % RING was last read by local step m - RING + 1
+    if (m >= lp_ctx::RING) {
+        HIPCHK(hipStreamWaitEvent(st, c->ev_local[(m - lp_ctx::RING + 1) % lp_ctx::RING], 0));
+        HIPCHK(hipStreamWaitEvent(ps, c->ev_local[(m - lp_ctx::RING + 1) % lp_ctx::RING], 0));
+    }
+    // level n: the porous part reads u^n on Gamma and p^n, the Navier-Stokes
+    // part reads p_F^n (level 0 is complete at setup)
+    if (m >= 2) {
+        HIPCHK(hipStreamWaitEvent(ps, c->ev_coarse[o], 0));
+        HIPCHK(hipStreamWaitEvent(ps, c->ev_cpor[o], 0));
+        HIPCHK(hipStreamWaitEvent(st, c->ev_cpor[o], 0));
+    }
+    StageTimer ttot(c, LP_T_COARSE, st);
     const long long nc2 = c->nc2;
     const double t1 = time_at(c, c->n + 1);
     const double tf[3] = {std::cos(t1), std::sin(t1), std::cos(t1) * std::cos(t1)};
@@ -828,15 +866,16 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
     pa.Uy0 = c->cU[o] + nc2;
     pa.e_old = c->cP[o]; pa.e_new = c->cP[nw]; pa.b = c->b_cp;
     for (int k = 0; k < 3; ++k) pa.tf[k] = tf[k];
-    lp::launch_porous_rhs(pa, 1, c->nodes_cpor, st);
+    lp::launch_porous_rhs(pa, 1, c->nodes_cpor, ps);
     {
         // the three solves with the explicit inverses, then the node layout
         lp::DensePorousArgs dp{};
         dp.d = lp::DenseArgs{c->inv_cp, c->b_cp, c->x_cp, P.cpor.ndof, nullptr};
         dp.f = lp::FinalizeArgs{c->d_cpor, c->d_dof2, c->d_dof1, c->x_cp, c->cP[nw], nullptr, nullptr};
         dp.ticket = c->tick_dp;
-        lp::launch_dense_porous(dp, 3, st);
+        lp::launch_dense_porous(dp, 3, ps);
     }
+    HIPCHK(hipEventRecord(c->ev_cpor[nw], ps));
     // (5.4): Navier-Stokes by Newton from the extrapolation 2 (u^n, p^n) -
     // (u^(n-1), p^(n-1)) (from (u^n, p^n) at the first step); each iteration
     // solves the Oseen system linearised about the current iterate
@@ -907,16 +946,26 @@ lp_status lp_local_step(lp_ctx *c, void *stream) {
     {
         StageTimer tm(c, LP_T_WAIT_COARSE, st);
         HIPCHK(hipStreamWaitEvent(st, c->ev_coarse[nw], 0));
+        HIPCHK(hipStreamWaitEvent(st, c->ev_cpor[nw], 0));
     }
     {
         StageTimer tm(c, LP_T_PROLONG, st);
         prolong_all(c, nw, o, st);
     }
-    HIPCHK(hipEventRecord(c->ev_pro, st));
+    // The porous batch runs on the factor stream of this step from its own
+    // prolongation, so it waits for the coarse level, not for the local Oseen
+    // chain of the previous step.  It reads the corrections of step m-1 (the
+    // previous porous batch, on the other factor stream) and overwrites the
+    // buffers that the merge of step m-2 read.
     hipStream_t ps = c->fstream[m % 2];
-    HIPCHK(hipStreamWaitEvent(ps, c->ev_pro, 0));
-    if (c->mixed) { TRY(local_porous<float>(c, ps)); TRY(local_oseen<float>(c, st)); }
-    else { TRY(local_porous<double>(c, ps)); TRY(local_oseen<double>(c, st)); }
+    double *pro = c->pro_Pb[m % 2];
+    HIPCHK(hipStreamWaitEvent(ps, c->ev_coarse[nw], 0));
+    HIPCHK(hipStreamWaitEvent(ps, c->ev_cpor[nw], 0));
+    if (m >= 2) HIPCHK(hipStreamWaitEvent(ps, c->ev_por, 0));
+    if (m >= 3) HIPCHK(hipStreamWaitEvent(ps, c->ev_local[(m - 2) % lp_ctx::RING], 0));
+    prolong_porous(c, pro, nw, o, ps);
+    if (c->mixed) { TRY(local_porous<float>(c, pro, ps)); TRY(local_oseen<float>(c, st)); }
+    else { TRY(local_porous<double>(c, pro, ps)); TRY(local_oseen<double>(c, st)); }
     HIPCHK(hipEventRecord(c->ev_por, ps));
     {
         StageTimer tm(c, LP_T_WAIT_POR, st);
@@ -933,7 +982,7 @@ lp_status lp_local_step(lp_ctx *c, void *stream) {
             ma.own1_lo[ax] = c->d_own[r][ax][2]; ma.own1_n[ax] = c->d_own[r][ax][3];
         }
         if (r == lp::POROUS) {
-            for (int f = 0; f < 3; ++f) { ma.base[f] = c->pro_P1 + f * c->nf2; ma.out[f] = c->m_P + f * c->nf2; }
+            for (int f = 0; f < 3; ++f) { ma.base[f] = pro + f * c->nf2; ma.out[f] = c->m_P + f * c->nf2; }
             ma.base1 = nullptr; ma.out1 = nullptr;
         } else {
             for (int f = 0; f < 2; ++f) { ma.base[f] = c->pro_U1 + f * c->nf2; ma.out[f] = c->m_U + f * c->nf2; }
@@ -998,7 +1047,10 @@ lp_status lp_get_solution(lp_ctx *c, int32_t field, int32_t level, int32_t sub, 
     hipStream_t st = (hipStream_t)stream;
     if (level == LP_COARSE) {
         const int latest = (int)((c->coarse_pending ? c->n + 1 : c->n) % lp_ctx::RING);
-        if (c->coarse_pending || c->n > 0) HIPCHK(hipStreamWaitEvent(st, c->ev_coarse[latest], 0));
+        if (c->coarse_pending || c->n > 0) {
+            HIPCHK(hipStreamWaitEvent(st, c->ev_coarse[latest], 0));
+            HIPCHK(hipStreamWaitEvent(st, c->ev_cpor[latest], 0));
+        }
     }
     if (out_is_device) {
         HIPCHK(hipMemcpyAsync(out, p, n * sizeof(double), hipMemcpyDeviceToDevice, st));

@@ -110,7 +110,23 @@ struct BandSys {
 };
 
 // window registers per lane of the band solve for a half-bandwidth (0: unsupported)
-constexpr int solve_nr(int maxbw) { return maxbw <= 64 ? 1 : maxbw <= 128 ? 2 : maxbw <= 192 ? 3 : maxbw <= 256 ? 4 : 0; }
+// Factor layout shared by the factorisations and the solves.  The solve keeps
+// a window of R = 64 NR rows in NR registers per lane, in halves of 32 rows:
+// row i sits in slot s = i mod R, half h = s / 32 (register h / 2, lanes
+// 32 (h mod 2) + (s mod 32)).  A factor column holds ldf = R values, lane l's
+// NR values contiguous: slot s at fac_pos(s) = lane(s) NR + register(s).
+//   Lr[k ldf + fac_pos(i mod R)] = L(i, k),                 k < i <= k + bw
+//   Ur[(n-1-j) ldf + fac_pos((n-1-i) mod R)] = U(i, j) / U(i, i),  j - bw <= i < j
+//   Di[i] = 1 / U(i, i)
+// and zero at every other position of a column (buffers cleared at setup).
+// NR covers the bandwidth class of the factorisation window plus one block
+// of 32 rows: R >= bw + 32.
+constexpr int lu_window_bw(int bw) { return bw <= 64 ? 64 : bw <= 96 ? 96 : bw <= 128 ? 128 : bw <= 160 ? 160 : bw; }
+constexpr int solve_nr(int maxbw) { return lu_window_bw(maxbw) <= 160 ? (lu_window_bw(maxbw) + 32 + 63) / 64 : 0; }
+__host__ __device__ inline int fac_pos(int s, int nr) {
+    const int h = s >> 5;
+    return ((s & 31) | ((h & 1) << 5)) * nr + (h >> 1);
+}
 
 template <typename T>
 struct BandArgs {

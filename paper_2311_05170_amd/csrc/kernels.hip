@@ -763,14 +763,10 @@ __global__ __launch_bounds__(TP *TP) void k_band_lu(BandArgs<T> B) {
     const BandSys Sy = B.sys[blockIdx.x];
     if (B.skip && *B.skip) return;
     const int n = Sy.n, bw = Sy.bw, ld = 2 * bw + 1;
-    const int ws = bw > 0 ? bw : 1;                 // slot count of the solve's window
     const T *M = B.band + Sy.off;
-    // factors, slot-rotated and lane-grouped for the solves: with slot
-    // s = i mod ws held by lane s mod 64 in register s / 64 (nrf registers per
-    // lane), pos(s) = (s mod 64) nrf + s / 64 and
-    //   Lr[k ldf + pos(i mod ws)] = L(i, k), Ur[j ldf + pos(i mod ws)] = U(i, j) (i < j),
-    //   Di[k] = 1 / U(k, k)
-    const int ldf = Sy.ldf, nrf = ldf >> 6;
+    // factors in the solves' layout (fac_pos): R = ldf slots per column,
+    // L by columns, U row-scaled by columns in reverse order, 1 / U(k, k)
+    const int ldf = Sy.ldf, nrf = ldf >> 6, R = ldf;
     T *Lr = B.fac + Sy.foff, *Ur = Lr + (long long)n * ldf, *Di = Ur + (long long)n * ldf;
     T *dummy = B.dummy + ((long long)blockIdx.x * NT + threadIdx.x) * NI;
     __shared__ T ubuf[2][W];       // pivot row by column slot
@@ -801,14 +797,14 @@ __global__ __launch_bounds__(TP *TP) void k_band_lu(BandArgs<T> B) {
             const int d = W - 1 - q;
             foff[it] = (1 + q) * ld + d + bw;
             fend[it] = (d <= bw) ? min(n - W, n - 1 - q) : 0;
-            soff[it] = 0;                              // Lr + k*ldf + pos(srot), srot = (k + q) mod ws
-            srot[it] = q % ws;
+            soff[it] = 0;                              // Lr + k*ldf + fac_pos(srot), srot = (k + q) mod R
+            srot[it] = q % R;
             send[it] = (q >= 1 && q <= bw) ? n - q : 0;
         } else if (q < NE) {
             const int e = q - W, d = 1 + e - W;
             foff[it] = W * ld + d + bw;
             fend[it] = (d >= -bw) ? min(n - 1 - e, n - W) : 0;
-            soff[it] = e * ldf;                        // Ur + (k+e)*ldf + pos(k mod ws); e = 0 -> Di[k]
+            soff[it] = -e * ldf;                       // Ur + (n-1-k-e)*ldf + fac_pos((n-1-k) mod R); e = 0 -> Di[k]
             srot[it] = 0;
             send[it] = e <= bw ? n - e : 0;
         } else {
@@ -823,7 +819,7 @@ __global__ __launch_bounds__(TP *TP) void k_band_lu(BandArgs<T> B) {
         for (int it = 0; it < NI; ++it) fifo[s][it] = *(s < fend[it] ? M + (foff[it] + s * ld) : B.zero);
     int bad = 0;
     int kw = 0;                                     // k0 mod W (a multiple of U)
-    int kws = 0;                                    // k mod ws
+    int rk = (n - 1) % R;                           // (n-1-k) mod R
     for (int k0 = 0; k0 < n; k0 += U) {
 #pragma unroll
         for (int s = 0; s < U; ++s) {
@@ -857,7 +853,7 @@ __global__ __launch_bounds__(TP *TP) void k_band_lu(BandArgs<T> B) {
             T piv = ubuf[buf][kmod];
             if (!(fabs((double)piv) > 0.0) || !isfinite((double)piv)) { bad = 1; piv = T(1); }
             const T inv = T(1) / piv;
-            const int kl = k * ldf, pk = (kws & 63) * nrf + (kws >> 6);
+            const int kl = k * ldf, rl = (n - 1 - k) * ldf + fac_pos(rk, nrf);
 #pragma unroll
             for (int it = 0; it < NI; ++it) {
                 const bool isl = qq[it] < W;
@@ -865,14 +861,14 @@ __global__ __launch_bounds__(TP *TP) void k_band_lu(BandArgs<T> B) {
                 int sl = kmod + o;
                 sl = sl >= W ? sl - W : sl;
                 const T lv = lbuf[buf][sl] * inv;
-                const T uv = o == 0 ? inv : ubuf[buf][sl];
-                T *ldst = Lr + (kl + (srot[it] & 63) * nrf + (srot[it] >> 6));
-                T *udst = o == 0 ? Di + k : Ur + (kl + soff[it] + pk);
+                const T uv = o == 0 ? inv : ubuf[buf][sl] * inv;
+                T *ldst = Lr + (kl + fac_pos(srot[it], nrf));
+                T *udst = o == 0 ? Di + k : Ur + (rl + soff[it]);
                 T *dst = k < send[it] ? (isl ? ldst : udst) : dummy + it;
                 *dst = isl ? lv : uv;
-                srot[it] = srot[it] + 1 == ws ? 0 : srot[it] + 1;
+                srot[it] = srot[it] + 1 == R ? 0 : srot[it] + 1;
             }
-            kws = kws + 1 == ws ? 0 : kws + 1;
+            rk = rk == 0 ? R - 1 : rk - 1;
             T l[RB], u[RB];
 #pragma unroll
             for (int i = 0; i < RB; ++i) l[i] = lbuf[buf][tr * RB + i] * inv;
@@ -972,7 +968,7 @@ __global__ __launch_bounds__(64 * (NW + LU_NS)) void k_band_lu_mfma(BandArgs<T> 
     const BandSys Sy = B.sys[blockIdx.x];
     if (B.skip && *B.skip) return;
     const int n = Sy.n, bw = Sy.bw, ld = 2 * bw + 1;
-    const int ws = bw > 0 ? bw : 1, ldf = Sy.ldf, nrf = ldf >> 6;
+    const int ws = bw > 0 ? bw : 1, ldf = Sy.ldf, nrf = ldf >> 6, R = ldf;
     const T *M = B.band + Sy.off;
     __shared__ T Pc[W][17];        // panel tile column by row slot (L11\U11 in the diagonal tile, then L21)
     __shared__ T Pr[16][W + 1];    // panel tile row by column slot (then U12)
@@ -1140,7 +1136,7 @@ __global__ __launch_bounds__(64 * (NW + LU_NS)) void k_band_lu_mfma(BandArgs<T> 
             lds_barrier();                 // C
             // 4. factors of columns / rows k0 .. k0+15 in the solves' layout, with
             //    fixed trip counts so that all LDS reads go out before the stores
-            const int km0 = k0 % ws;
+            const int kr0 = k0 % R, rr0 = (n - 1 - k0) % R;     // k0 mod R, (n-1-k0) mod R
             {
                 // L(k + o, k): column c = wr + LU_NS j, lanes over consecutive o
                 constexpr int NC = (16 + LU_NS - 1) / LU_NS, NO = W / 64 + 1;
@@ -1149,18 +1145,18 @@ __global__ __launch_bounds__(64 * (NW + LU_NS)) void k_band_lu_mfma(BandArgs<T> 
 #pragma unroll
                 for (int j = 0; j < NC; ++j) {
                     const int c0 = wr + LU_NS * j, c = c0 < 16 ? c0 : 15, k = k0 + c;
-                    int kmod = km0 + c;
-                    kmod = kmod >= ws ? kmod - ws : kmod;
+                    int kmod = kr0 + c;                  // k mod R
+                    kmod = kmod >= R ? kmod - R : kmod;
 #pragma unroll
                     for (int u = 0; u < NO; ++u) {
                         const int o = lane + 1 + 64 * u, i = k + o;
                         const bool ok = c0 < 16 && o <= ws && k < n && i < n;
-                        int sl = kmod + o;
-                        sl = sl >= ws ? sl - ws : sl;
+                        int sl = kmod + o;                   // (k + o) mod R
+                        sl = sl >= R ? sl - R : sl;
                         int iw = 16 * P + c + o;
                         iw = iw >= W ? iw - W : iw;
                         lv[j][u] = ok ? Pc[iw][c] : T(0);
-                        la[j][u] = ok ? (long long)k * ldf + (sl & 63) * nrf + (sl >> 6) : -1;
+                        la[j][u] = ok ? (long long)k * ldf + fac_pos(sl, nrf) : -1;
                     }
                 }
 #pragma unroll
@@ -1174,9 +1170,10 @@ __global__ __launch_bounds__(64 * (NW + LU_NS)) void k_band_lu_mfma(BandArgs<T> 
                 // pass, lanes c = 0..15 over the panel rows
                 constexpr int NJ = (W + 4 * LU_NS - 1) / (4 * LU_NS);
                 const int c = lane & 15, k = k0 + c;
-                int kmod = km0 + c;
-                kmod = kmod >= ws ? kmod - ws : kmod;
-                const int pk = (kmod & 63) * nrf + (kmod >> 6);
+                int rk = rr0 - c;                        // (n-1-k) mod R
+                rk = rk < 0 ? rk + R : rk;
+                const int pk = fac_pos(rk, nrf);
+                const T dk = dinv[c];
                 T uvv[NJ];
                 long long ua[NJ];
 #pragma unroll
@@ -1187,8 +1184,8 @@ __global__ __launch_bounds__(64 * (NW + LU_NS)) void k_band_lu_mfma(BandArgs<T> 
                     int jw = 16 * P + 1 + jo;
                     jw = jw >= W ? jw - W : jw;
                     jw = jw >= W ? jw - W : jw;
-                    uvv[u] = ok ? (j < k0 + 16 ? Pc[16 * P + c][(j - k0) & 15] : Pr[c][jw]) : T(0);
-                    ua[u] = ok ? (long long)j * ldf + pk : -1;
+                    uvv[u] = ok ? (j < k0 + 16 ? Pc[16 * P + c][(j - k0) & 15] : Pr[c][jw]) * dk : T(0);
+                    ua[u] = ok ? (long long)(n - 1 - j) * ldf + pk : -1;
                 }
 #pragma unroll
                 for (int u = 0; u < NJ; ++u)
@@ -1487,29 +1484,31 @@ __global__ __launch_bounds__(64 * (TT + LU_NS)) void k_band_lu_la(BandArgs<T> B)
             }
         };
         // L and U of panel ps from buffer bb (diagonal tile from this
-        // wavefront's copy) in the solves' slot-rotated layout
-        int km0 = 0;                                  // k0 mod ws
+        // wavefront's copy) in the solves' layout (fac_pos, R slots)
+        constexpr int R = 64 * NRF;
+        int kr0 = 1 % R, rr0 = (n - 1) % R;            // (k0 + 1) mod R, (n - 1 - k0) mod R
         auto store = [&](int ps, int bb) {
             const int k0 = 16 * ps, P = ps % TT;
             struct Grp { T v[NRF]; };
-            // L: column c = wr + LU_NS j, lane l fills slots l + 64 m (one vector store)
+            // L: column c = wr + LU_NS j; lane l, register m holds slot
+            // 32 (2m + l / 32) + l mod 32 (one vector store per lane)
 #pragma unroll
             for (int j = 0; j < (16 + LU_NS - 1) / LU_NS; ++j) {
                 const int c = wr + LU_NS * j, k = k0 + c;
                 if (c >= 16 || k >= n) break;
-                int kmod = km0 + c;
-                while (kmod >= ws) kmod -= ws;
+                int k1 = kr0 + c;                             // (k + 1) mod R
+                k1 = k1 >= R ? k1 - R : k1;
                 Grp gv;
 #pragma unroll
                 for (int m = 0; m < NRF; ++m) {
-                    const int s = lane + 64 * m;
-                    int o = s - kmod - 1;
-                    o = o < 0 ? o + ws : o;
-                    o += 1;                                   // row k + o, 1 <= o <= ws
+                    const int s = 32 * (2 * m + (lane >> 5)) + (lane & 31);
+                    int o = s - k1;
+                    o = o < 0 ? o + R : o;
+                    o += 1;                                   // row k + o with (k + o) mod R = s, 1 <= o <= R
                     const int dr = c + o;
                     int iw = 16 * P + dr;
                     iw = iw >= W ? iw - W : iw;
-                    const bool ok = s < ws && k + o < n;
+                    const bool ok = o <= ws && k + o < n;
                     // one unconditional LDS read: L11 from the copy, -L21 from the panel, else zero
                     const T *src = dr < 16 ? &Dg[wr][dr & 15][c] : &Pc[bb][iw][lu_perm(c)];
                     src = ok ? src : &Zs[0];
@@ -1518,14 +1517,15 @@ __global__ __launch_bounds__(64 * (TT + LU_NS)) void k_band_lu_la(BandArgs<T> B)
                 }
                 *reinterpret_cast<Grp *>(Lr + (long long)k * ldf + lane * NRF) = gv;
             }
-            // U(k0 + c, j), j = k0 + c + 1 .. k0 + c + ws: lanes c = 0..15 over
-            // the panel rows, four columns per pass
+            // U(k0 + c, j) / U(k0 + c, k0 + c), j = k0 + c + 1 .. k0 + c + ws:
+            // lanes c = 0..15 over the panel rows, four columns per pass
             {
                 constexpr int NJ = (W + 4 * LU_NS - 1) / (4 * LU_NS);
                 const int c = lc, k = k0 + c;
-                int kmod = km0 + c;
-                while (kmod >= ws) kmod -= ws;
-                const int pk = (kmod & 63) * NRF + (kmod >> 6);
+                int rk = rr0 - c;                             // (n - 1 - k) mod R
+                rk = rk < 0 ? rk + R : rk;
+                const int pk = fac_pos(rk, NRF);
+                const T dk = Dv[wr][c];
 #pragma unroll
                 for (int u = 0; u < NJ; ++u) {
                     const int jo = lg + 4 * wr + 4 * LU_NS * u;
@@ -1537,12 +1537,14 @@ __global__ __launch_bounds__(64 * (TT + LU_NS)) void k_band_lu_la(BandArgs<T> B)
                     const int dj = j - k0;
                     const T *src = dj < 16 ? &Dg[wr][c][dj & 15] : &Pr[bb][jw][lu_perm(c)];
                     const T v = *src;
-                    if (ok) Ur[(long long)j * ldf + pk] = v;
+                    if (ok) Ur[(long long)(n - 1 - j) * ldf + pk] = v * dk;
                 }
             }
             if (wr == 0 && lane < 16 && k0 + lane < n) Di[k0 + lane] = Dv[0][lane];
-            km0 += 16;
-            while (km0 >= ws) km0 -= ws;
+            kr0 += 16;
+            kr0 = kr0 >= R ? kr0 - R : kr0;
+            rr0 -= 16;
+            rr0 = rr0 < 0 ? rr0 + R : rr0;
         };
         if (wt == 0) Zs[0] = T(0);
         lds_barrier();                     // raw panel 0 in buffer 0
@@ -1562,29 +1564,85 @@ __global__ __launch_bounds__(64 * (TT + LU_NS)) void k_band_lu_la(BandArgs<T> B)
 
 // ---------------------------------------------------------------------------
 // Band triangular solves, one wavefront per right-hand side: L y = r (unit
-// lower), U d = y, x += d.  The window of ws = bw rows is spread circularly
-// over the lanes (row i in slot i mod ws, slot = lane + 64 m); the finished
-// entry is broadcast with readlane and every slot applies one factor entry.
-// With the slot-rotated factors each lane reads a fixed offset of the
-// current column, prefetched D columns ahead.
+// lower), z = D^-1 y, then U' d = z with U' = D^-1 U (unit upper), x += d.
+// The second is the first on reversed indices (row i -> n-1-i), so one pass
+// routine serves both: a unit lower band solve over columns 0 .. n-1.
 //
-// Columns run in blocks of D with no branch inside a block, so the waits on
-// the prefetched factor loads count back exactly D columns.  The right-hand
-// side sits in LDS between zero pads (rows outside 0..n-1 read zero); the
-// entering rows of the next block are read from LDS one block ahead, and the
-// finished entries of a block are gathered into lanes 0..D-1 and stored with
-// one masked LDS write per block.
+// The pass keeps R = 64 NR rows in NR registers per lane, in 2 NR halves of
+// 32 rows (the slot map of fac_pos).  Columns go in blocks of 32; the rows of
+// block b sit in half b mod 2NR, so with the block loop unrolled 2NR times the
+// half holding the current rows is static: column k costs one broadcast of
+// row k (readlane), NR FMAs on the window and one vector load of column k+D.
+// Rows at or above k hold a zero coefficient in column k, so after its 32
+// columns a block's half holds its finished values: they go to LDS and the
+// half is refilled with the rows R further on.  The column index is clamped
+// at n-1, whose column is zero (no row below n-1), and rows at or past n are
+// zero, so the last block and the prefetch run straight through.
 // ---------------------------------------------------------------------------
-// LDS pad (rows) on each side of the right-hand side: at least the largest
-// window (4 x 64) plus two blocks
-constexpr int SOLVE_PAD = 4 * 64 + 2 * 32;
+// LDS pad (rows) on each side of the right-hand side: a window and a
+// super-block of blocks beyond the end (rows read past n are zero)
+constexpr int SOLVE_PAD = 3 * 256 + 64;
 // rows per lane in flight when moving the right-hand side and the solution
 constexpr int SOLVE_LD = 8;
 
+template <typename T, int NR, int D, bool REV>
+__device__ __forceinline__ void band_pass(const T *C, int n, int ldf, T *ys, const T *dl, int lane) {
+    constexpr int H = 2 * NR, R = 64 * NR;
+    static_assert(32 % D == 0, "prefetch ring divides a block");
+    struct Grp { T v[NR]; };
+    // row r of the pass (reversed rows for the second pass) in LDS
+    auto yat = [&](int r) -> T & { return REV ? ys[n - 1 - r] : ys[r]; };
+    T win[NR], cf[D][NR];
+    // slot of (register m, this lane): rows s, s + R, ... in turn
+#pragma unroll
+    for (int m = 0; m < NR; ++m) win[m] = yat(32 * (2 * m + (lane >> 5)) + (lane & 31));
+    const int lo = lane * NR;
+    const int nb = (n + 31) >> 5;
+#define LP_COL(KK, S)                                                                      \
+    do {                                                                                   \
+        const Grp g = *reinterpret_cast<const Grp *>(C + (long long)min((KK), n - 1) * ldf + lo); \
+        _Pragma("unroll") for (int m = 0; m < NR; ++m) cf[S][m] = g.v[m];                   \
+    } while (0)
+#pragma unroll
+    for (int s = 0; s < D; ++s) {
+        LP_COL(s, s);
+        __builtin_amdgcn_sched_barrier(0);   // issue in the loop body's order
+    }
+    for (int b0 = 0; b0 < nb; b0 += H) {
+#pragma unroll
+        for (int hb = 0; hb < H; ++hb) {
+            // block b = b0 + hb in half hb: register hb / 2, lanes 32 (hb % 2) ..
+            const int b = b0 + hb;
+            const int mh = hb >> 1, lh = (hb & 1) << 5;
+            const T ent = yat(32 * (b + H) + (lane & 31));      // the rows entering this half next
+#pragma unroll
+            for (int s = 0; s < 32; ++s) {
+                const T yk = wave_bcast(win[mh], lh + s);
+                win[mh] = fma(-cf[s % D][mh], yk, win[mh]);      // the half the next broadcast reads first
+#pragma unroll
+                for (int m = 0; m < NR; ++m)
+                    if (m != mh) win[m] = fma(-cf[s % D][m], yk, win[m]);
+                // every column's updates happen in its column (otherwise the
+                // compiler defers the other halves' chains to the block end and
+                // keeps all their factor registers alive): an empty statement
+                // that reads and writes the window
+#pragma unroll
+                for (int m = 0; m < NR; ++m) asm volatile("" : "+v"(win[m]));
+                LP_COL(32 * b + s + D, s % D);
+                __builtin_amdgcn_sched_barrier(0);              // keep each prefetch in its column
+            }
+            const bool mine = (lane & 32) == lh;
+            const int r = 32 * b + (lane & 31);
+            if (mine) yat(r) = REV ? win[mh] : win[mh] * dl[r];  // first pass: z = D^-1 y
+            win[mh] = mine ? ent : win[mh];
+        }
+    }
+#undef LP_COL
+}
+
 template <typename T, int NR, int D>
 __global__ __launch_bounds__(64) void k_band_solve(SolveArgs<T> A) {
-    static_assert(NR * 64 + 2 * D <= SOLVE_PAD, "pad too small");
-    static_assert(2 * D <= 64, "prefetched loads must fit the memory counter");
+    static_assert(64 * NR + 32 * 2 * NR <= SOLVE_PAD, "pad too small");
     const int sysi = blockIdx.x, f = blockIdx.y;
     const BandSys Sy = A.sys[sysi];
     if (f >= Sy.nrhs) return;
@@ -1592,159 +1650,38 @@ __global__ __launch_bounds__(64) void k_band_solve(SolveArgs<T> A) {
     if (A.skip && *A.skip) return;
     if (A.conv && A.conv[id]) return;
     extern __shared__ unsigned char smem_raw[];
-    T *ys = reinterpret_cast<T *>(smem_raw) + SOLVE_PAD;   // r, then y, then the correction d, by row
-    const int n = Sy.n, bw = Sy.bw;
-    const int ws = bw > 0 ? bw : 1;
-    const int ldf = 64 * NR;                       // factor column length (lane-grouped layout)
+    const int n = Sy.n;
+    T *ys = reinterpret_cast<T *>(smem_raw) + SOLVE_PAD;   // r, then z, then d, by row
+    T *dl = ys + n + SOLVE_PAD;                             // 1 / U(i, i), zero past n
+    const int ldf = Sy.ldf;
     const T *Lr = A.fac + Sy.foff + (long long)f * Sy.fstride;
     const T *Ur = Lr + (long long)n * ldf, *Di = Ur + (long long)n * ldf;
     const double *rg = A.r + Sy.vec + (long long)f * n;
     double *x = A.x + Sy.vec + (long long)f * n;
     const int lane = threadIdx.x;
-    // the right-hand side into LDS, SOLVE_LD rows per lane in flight (clamped
-    // unconditional loads, then masked stores)
+    // the right-hand side and the pivot reciprocals into LDS, SOLVE_LD rows
+    // per lane in flight (clamped unconditional loads, then masked stores)
     for (int i0 = lane - SOLVE_PAD; i0 < n + SOLVE_PAD; i0 += 64 * SOLVE_LD) {
         double v[SOLVE_LD];
+        T dv[SOLVE_LD];
 #pragma unroll
-        for (int u = 0; u < SOLVE_LD; ++u) v[u] = rg[min(max(i0 + 64 * u, 0), n - 1)];
+        for (int u = 0; u < SOLVE_LD; ++u) {
+            const int ic = min(max(i0 + 64 * u, 0), n - 1);
+            v[u] = rg[ic];
+            dv[u] = Di[ic];
+        }
 #pragma unroll
         for (int u = 0; u < SOLVE_LD; ++u) {
             const int i = i0 + 64 * u;
-            if (i < n + SOLVE_PAD) ys[i] = (i >= 0 && i < n) ? (T)v[u] : T(0);
+            const bool in = i >= 0 && i < n;
+            if (i < n + SOLVE_PAD) ys[i] = in ? (T)v[u] : T(0);
+            if (i >= 0 && i < n + SOLVE_PAD) dl[i] = in ? dv[u] : T(0);
         }
     }
     __syncthreads();
-    // lane l holds slots l + 64 m, stored at l NR + m of each factor column:
-    // one vector load per column (slots beyond the window hold values that are
-    // never extracted)
-    struct Grp { T v[NR]; };
-    const int lo = lane * NR;
-    T win[NR], cf[D][NR], ent[D], nxt[D];
-    // ---- forward: before step k the window holds rows k..k+ws-1 (row i in slot i mod ws)
-#pragma unroll
-    for (int m = 0; m < NR; ++m) win[m] = lane + 64 * m < ws ? ys[lane + 64 * m] : T(0);
-    // columns past either end are prefetched but never used: a clamped column
-    // index keeps every block straight-line
-#define LP_FCOL(KK, S)                                                                     \
-    do {                                                                                   \
-        const T *col = Lr + (long long)min((KK), n - 1) * ldf;                              \
-        const Grp g = *reinterpret_cast<const Grp *>(col + lo);                            \
-        _Pragma("unroll") for (int m = 0; m < NR; ++m) cf[S][m] = g.v[m];                   \
-    } while (0)
-#pragma unroll
-    for (int s = 0; s < D; ++s) {
-        LP_FCOL(s, s);
-        __builtin_amdgcn_sched_barrier(0);   // issue in the loop body's order
-    }
-#pragma unroll
-    for (int s = 0; s < D; ++s) ent[s] = ys[s + ws];
-    int sk = 0;
-    const int nfull = n - n % D;
-    for (int k0 = 0; k0 < nfull; k0 += D) {
-#pragma unroll
-        for (int s = 0; s < D; ++s) nxt[s] = ys[k0 + D + s + ws];
-        T yb = T(0);
-#pragma unroll
-        for (int s = 0; s < D; ++s) {
-            const int k = k0 + s;
-            const int ml = sk >> 6, ll = sk & 63;
-            T v = win[0];
-#pragma unroll
-            for (int m = 1; m < NR; ++m) v = m == ml ? win[m] : v;
-            const T yk = wave_bcast(v, ll);
-            yb = lane == s ? yk : yb;
-#pragma unroll
-            for (int m = 0; m < NR; ++m) win[m] = (lane + 64 * m == sk ? ent[s] : win[m]) - cf[s][m] * yk;
-            sk = sk + 1 == ws ? 0 : sk + 1;
-            LP_FCOL(k + D, s);
-            __builtin_amdgcn_sched_barrier(0);   // keep each prefetch in its column
-        }
-        if (lane < D) ys[k0 + lane] = yb;
-#pragma unroll
-        for (int s = 0; s < D; ++s) ent[s] = nxt[s];
-    }
-    // tail: the last n % D columns, already prefetched (cf[s] holds column nfull + s)
-#pragma unroll
-    for (int s = 0; s < D; ++s) {
-        const int k = nfull + s;
-        if (k >= n) break;
-        const int ml = sk >> 6, ll = sk & 63;
-        T v = win[0];
-#pragma unroll
-        for (int m = 1; m < NR; ++m) v = m == ml ? win[m] : v;
-        const T yk = wave_bcast(v, ll);
-        const T e = ys[k + ws];
-        if (lane == 0) ys[k] = yk;
-#pragma unroll
-        for (int m = 0; m < NR; ++m) win[m] = (lane + 64 * m == sk ? e : win[m]) - cf[s][m] * yk;
-        sk = sk + 1 == ws ? 0 : sk + 1;
-    }
+    band_pass<T, NR, D, false>(Lr, n, ldf, ys, dl, lane);
     __syncthreads();
-    // ---- backward: before step k (descending) the window holds rows k-ws+1..k
-    const int kt = n - 1;
-    T uf[D];
-#pragma unroll
-    for (int m = 0; m < NR; ++m) {
-        const int sl = lane + 64 * m;
-        const int j = ((kt % ws) - sl + ws) % ws;           // distance below kt of this slot's row
-        win[m] = sl < ws ? ys[kt - j] : T(0);
-    }
-#define LP_BCOL(KK, S)                                                                     \
-    do {                                                                                   \
-        const int kc = max((KK), 0);                                                       \
-        const T *col = Ur + (long long)kc * ldf;                                           \
-        const Grp g = *reinterpret_cast<const Grp *>(col + lo);                            \
-        _Pragma("unroll") for (int m = 0; m < NR; ++m) cf[S][m] = g.v[m];                   \
-        uf[S] = Di[kc];                                                                    \
-    } while (0)
-#pragma unroll
-    for (int s = 0; s < D; ++s) {
-        LP_BCOL(kt - s, s);
-        __builtin_amdgcn_sched_barrier(0);
-    }
-#pragma unroll
-    for (int s = 0; s < D; ++s) ent[s] = ys[kt - s - ws];
-    sk = kt % ws;
-    const int bfull = n - n % D;                        // columns kt .. kt-bfull+1 in full blocks
-    for (int kb = kt; kb > kt - bfull; kb -= D) {
-#pragma unroll
-        for (int s = 0; s < D; ++s) nxt[s] = ys[kb - D - s - ws];
-        T db = T(0);
-#pragma unroll
-        for (int s = 0; s < D; ++s) {
-            const int k = kb - s;
-            const int ml = sk >> 6, ll = sk & 63;
-            T v = win[0];
-#pragma unroll
-            for (int m = 1; m < NR; ++m) v = m == ml ? win[m] : v;
-            const T dk = wave_bcast(v, ll) * uf[s];
-            db = lane == s ? dk : db;
-#pragma unroll
-            for (int m = 0; m < NR; ++m) win[m] = (lane + 64 * m == sk ? ent[s] : win[m]) - cf[s][m] * dk;
-            sk = sk == 0 ? ws - 1 : sk - 1;
-            LP_BCOL(k - D, s);
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        if (lane < D) ys[kb - lane] = db;                // row k of y is consumed; keep d_k there
-#pragma unroll
-        for (int s = 0; s < D; ++s) ent[s] = nxt[s];
-    }
-    // tail: rows n % D - 1 .. 0, already prefetched (cf[s], uf[s] hold column kt - bfull - s)
-#pragma unroll
-    for (int s = 0; s < D; ++s) {
-        const int k = kt - bfull - s;
-        if (k < 0) break;
-        const int ml = sk >> 6, ll = sk & 63;
-        T v = win[0];
-#pragma unroll
-        for (int m = 1; m < NR; ++m) v = m == ml ? win[m] : v;
-        const T dk = wave_bcast(v, ll) * uf[s];
-        const T e = ys[k - ws];
-        if (lane == 0) ys[k] = dk;
-#pragma unroll
-        for (int m = 0; m < NR; ++m) win[m] = (lane + 64 * m == sk ? e : win[m]) - cf[s][m] * dk;
-        sk = sk == 0 ? ws - 1 : sk - 1;
-    }
+    band_pass<T, NR, D, true>(Ur, n, ldf, ys, dl, lane);
     __syncthreads();
     if (A.assign) {
         for (int i = lane; i < n; i += 64) x[i] = (double)ys[i];
@@ -1760,8 +1697,6 @@ __global__ __launch_bounds__(64) void k_band_solve(SolveArgs<T> A) {
             }
         }
     }
-#undef LP_FCOL
-#undef LP_BCOL
 }
 
 // ---------------------------------------------------------------------------
@@ -2051,13 +1986,11 @@ bool launch_band_lu(const BandArgs<T> &a, int nsys, int maxbw, int variant, hipS
 template <typename T, int D>
 bool launch_band_solve_d(const SolveArgs<T> &a, int nsys, int nrhs, int maxbw, int maxn, hipStream_t st) {
     dim3 g(nsys, nrhs);
-    const size_t sh = (size_t)(maxn + 2 * SOLVE_PAD) * sizeof(T);
+    const size_t sh = (size_t)(2 * maxn + 3 * SOLVE_PAD) * sizeof(T);
     if (sh > 160 * 1024) return false;
     switch (solve_nr(maxbw)) {
-    case 1: hipLaunchKernelGGL((k_band_solve<T, 1, D>), g, dim3(64), sh, st, a); break;
     case 2: hipLaunchKernelGGL((k_band_solve<T, 2, D>), g, dim3(64), sh, st, a); break;
     case 3: hipLaunchKernelGGL((k_band_solve<T, 3, D>), g, dim3(64), sh, st, a); break;
-    case 4: hipLaunchKernelGGL((k_band_solve<T, 4, D>), g, dim3(64), sh, st, a); break;
     default: return false;
     }
     return true;
@@ -2067,9 +2000,8 @@ bool launch_band_solve_d(const SolveArgs<T> &a, int nsys, int nrhs, int maxbw, i
 template <typename T>
 bool launch_band_solve(const SolveArgs<T> &a, int nsys, int nrhs, int maxbw, int maxn, int depth, hipStream_t st) {
     // automatic depth: 32 columns in flight while the prefetched factors fit
-    // in the 256 architectural registers next to the window (FP32, or FP64
-    // with one register per lane), else 16
-    if (depth != 16 && depth != 32) depth = (sizeof(T) == 4 || solve_nr(maxbw) == 1) ? 32 : 16;
+    // in the 256 architectural registers next to the window (FP32), else 16
+    if (depth != 16 && depth != 32) depth = sizeof(T) == 4 ? 32 : 16;
     return depth == 16 ? launch_band_solve_d<T, 16>(a, nsys, nrhs, maxbw, maxn, st)
                        : launch_band_solve_d<T, 32>(a, nsys, nrhs, maxbw, maxn, st);
 }
