@@ -883,7 +883,7 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
         const int om = (int)((m + lp_ctx::RING - 2) % lp_ctx::RING);
         const bool ex = m >= 2;
         lp::NewtonStartArgs ns{c->cU[o], c->cp[o], ex ? c->cU[om] : nullptr, ex ? c->cp[om] : nullptr,
-                               c->cU[nw], c->cp[nw], 2 * nc2, c->nc1, c->d_done, c->d_its};
+                               c->cU[nw], c->cp[nw], 2 * nc2, c->nc1, c->d_done, c->d_its, c->band_cns, P.cband_ns};
         lp::launch_newton_start(ns, st);
     }
     for (int it = 0; it < c->opt.max_newton; ++it) {
@@ -903,7 +903,6 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
         if (it == 0) {
             // Jacobian at the first iterate (u^n); later iterations reuse its
             // factors, with residuals of the current Jacobian (chord steps)
-            HIPCHK(hipMemsetAsync(c->band_cns, 0, P.cband_ns * sizeof(double), st));
             lp::OseenApplyArgs<double> aa{};
             aa.sys = c->d_cns; aa.cls2 = c->d_cls2; aa.dof2 = c->d_dof2; aa.dof1 = c->d_dof1;
             aa.W1[0] = oa.W1[0]; aa.W1[1] = oa.W1[1]; aa.band = c->band_cns; aa.skip = c->d_done;

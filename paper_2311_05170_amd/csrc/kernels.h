@@ -216,6 +216,8 @@ struct NewtonStartArgs {
     double *U1, *P1;              // first iterate for level n+1
     long long nu2, np;
     int *done, *its;
+    double *band;                 // the Jacobian band, cleared for its assembly
+    long long band_n;
 };
 
 struct IrStartArgs {

@@ -75,6 +75,13 @@ __device__ __forceinline__ void p2_values(double xi, double eta, double v[6]) {
     v[3] = 4 * l0 * l1; v[4] = 4 * l1 * l2; v[5] = 4 * l0 * l2;
 }
 
+// A latency-bound kernel claims the whole register file of each SIMD it runs
+// on (v255 and a255 count as used, 512 registers), so no wavefront of the
+// concurrent streams shares its instruction issue.  Only for workgroups of at
+// most four wavefronts (one per SIMD of the compute unit): a larger workgroup
+// with this allocation cannot be dispatched.
+__device__ __forceinline__ void own_simd() { asm volatile("" ::: "v255", "a255"); }
+
 __global__ void k_prolong_p2(ProlongArgs A) {
     const int nf = 2 * A.Nh + 1, nc = 2 * A.NH + 1;
     const long long tot = (long long)nf * nf;
@@ -1643,6 +1650,8 @@ __device__ __forceinline__ void band_pass(const T *C, int n, int ldf, T *ys, con
 template <typename T, int NR, int D>
 __global__ __launch_bounds__(64) void k_band_solve(SolveArgs<T> A) {
     static_assert(64 * NR + 32 * 2 * NR <= SOLVE_PAD, "pad too small");
+    // one wavefront whose speed is its instruction issue: it owns its SIMD
+    own_simd();
     const int sysi = blockIdx.x, f = blockIdx.y;
     const BandSys Sy = A.sys[sysi];
     if (f >= Sy.nrhs) return;
@@ -1870,9 +1879,11 @@ __global__ __launch_bounds__(1024) void k_dense_porous(DensePorousArgs A) {
 
 // start of the coarse Newton solve: the first iterate is the linear
 // extrapolation 2 x^n - x^(n-1) of the two previous levels (x^n at the first
-// step), counters cleared
+// step), counters and the Jacobian band cleared
 __global__ void k_newton_start(NewtonStartArgs A) {
     const long long tot = A.nu2 + A.np;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < A.band_n; i += (long long)gridDim.x * blockDim.x)
+        A.band[i] = 0.0;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < tot; i += (long long)gridDim.x * blockDim.x) {
         const bool u = i < A.nu2;
         const long long j = u ? i : i - A.nu2;
@@ -2024,7 +2035,9 @@ void launch_dense_porous(const DensePorousArgs &a, int nsys, hipStream_t st) {
     hipLaunchKernelGGL(k_dense_porous, dim3((a.d.n + 63) / 64, nsys), dim3(1024), 0, st, a);
 }
 void launch_newton_start(const NewtonStartArgs &a, hipStream_t st) {
-    hipLaunchKernelGGL(k_newton_start, dim3(8), dim3(256), 0, st, a);
+    const long long work = a.band_n > a.nu2 + a.np ? a.band_n : a.nu2 + a.np;
+    const int nb = (int)std::min<long long>(1024, (work + 255) / 256);
+    hipLaunchKernelGGL(k_newton_start, dim3(nb > 0 ? nb : 1), dim3(256), 0, st, a);
 }
 void launch_newton_update(const NewtonArgs &a, hipStream_t st) {
     hipLaunchKernelGGL(k_newton_update, dim3(1), dim3(256), 0, st, a);
