@@ -9,6 +9,7 @@
 // system with the active window held in registers; triangular solves run one
 // wavefront per right-hand side.
 #include <hip/hip_runtime.h>
+#include <type_traits>
 #include <cmath>
 
 #include "kernels.h"
@@ -1212,9 +1213,9 @@ __global__ __launch_bounds__(64 * (NW + LU_NS)) void k_band_lu_mfma(BandArgs<T> 
 //     L1. apply panel p to the tiles of slot row and column P1 only, write
 //         them to the other LDS buffer (the raw panel p+1) and refill them;
 //     L2. apply panel p to every other tile;
+//     S.  store L and U of panel p (factored one panel earlier), after L2;
 //   writer wavefronts, panel p:
-//     S.  store L and U of panel p (factored one panel earlier);
-//     F.  factor panel p+1 (after L1), alongside L2.
+//     F.  factor panel p+1 (after L1), alongside L2 and S.
 // Each writer wavefront factors the 16 x 16 diagonal tile of the panel into
 // its own LDS copy, so the writers never wait for one another: two barriers
 // per panel.  Panel tiles sit in LDS by row with the elimination index
@@ -1253,11 +1254,75 @@ __global__ __launch_bounds__(64 * (TT + LU_NS)) void k_band_lu_la(BandArgs<T> B)
     __shared__ T Dt[LU_NS][16][16];                // the same by columns
     __shared__ T Dv[LU_NS][16];                    // pivot reciprocals
     __shared__ T Zs[1];                            // a zero, read by masked lanes
+    __shared__ Quad<T> DgSQ[2][16][4];             // factored diagonal tile of panels of each parity (for the stores)
+    __shared__ T DvS[2][16];
     T (*Pc)[W][LU_LDP] = reinterpret_cast<T (*)[W][LU_LDP]>(&PcQ[0][0][0]);
     T (*Pr)[W][LU_LDP] = reinterpret_cast<T (*)[W][LU_LDP]>(&PrQ[0][0][0]);
     T (*Dg)[16][16] = reinterpret_cast<T (*)[16][16]>(&DgQ[0][0][0]);
+    T (*DgS)[16][16] = reinterpret_cast<T (*)[16][16]>(&DgSQ[0][0][0]);
     const int tid = threadIdx.x, wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63, lc = lane & 15, lg = lane >> 4;
     const int npan = (n + 15) / 16;
+    T *Lr = B.fac + Sy.foff, *Ur = Lr + (long long)n * ldf, *Di = Ur + (long long)n * ldf;
+    // L and U of panel ps from buffer bb in the solves' layout (fac_pos, R
+    // slots per column), by worker w of NWK (its share of the columns and rows)
+    constexpr int R = 64 * NRF;
+    auto store = [&](int ps, int bb, int w, auto nwk) {
+        constexpr int NWK = decltype(nwk)::value;
+        const int k0 = 16 * ps, P = ps % TT, q = ps & 1;
+        const int kr0 = (k0 + 1) % R, rr0 = (n - 1 - k0) % R;   // (k0 + 1) mod R, (n - 1 - k0) mod R
+        struct Grp { T v[NRF]; };
+        // L: column c = w + NWK j; lane l, register m holds slot
+        // 32 (2m + l / 32) + l mod 32 (one vector store per lane)
+#pragma unroll
+        for (int j = 0; j < (16 + NWK - 1) / NWK; ++j) {
+            const int c = w + NWK * j, k = k0 + c;
+            if (c >= 16 || k >= n) break;
+            int k1 = kr0 + c;                             // (k + 1) mod R
+            k1 = k1 >= R ? k1 - R : k1;
+            Grp gv;
+#pragma unroll
+            for (int m = 0; m < NRF; ++m) {
+                const int s = 32 * (2 * m + (lane >> 5)) + (lane & 31);
+                int o = s - k1;
+                o = o < 0 ? o + R : o;
+                o += 1;                                   // row k + o with (k + o) mod R = s, 1 <= o <= R
+                const int dr = c + o;
+                int iw = 16 * P + dr;
+                iw = iw >= W ? iw - W : iw;
+                const bool ok = o <= ws && k + o < n;
+                // one unconditional LDS read: L11 from the copy, -L21 from the panel, else zero
+                const T *src = dr < 16 ? &DgS[q][dr & 15][c] : &Pc[bb][iw][lu_perm(c)];
+                src = ok ? src : &Zs[0];
+                const T v = *src;
+                gv.v[m] = dr < 16 ? v : -v;
+            }
+            *reinterpret_cast<Grp *>(Lr + (long long)k * ldf + lane * NRF) = gv;
+        }
+        // U(k0 + c, j) / U(k0 + c, k0 + c), j = k0 + c + 1 .. k0 + c + ws:
+        // lanes c = 0..15 over the panel rows, four columns per pass
+        {
+            constexpr int NJ = (W + 4 * NWK - 1) / (4 * NWK);
+            const int c = lc, k = k0 + c;
+            int rk = rr0 - c;                             // (n - 1 - k) mod R
+            rk = rk < 0 ? rk + R : rk;
+            const int pk = fac_pos(rk, NRF);
+            const T dk = DvS[q][c];
+#pragma unroll
+            for (int u = 0; u < NJ; ++u) {
+                const int jo = lg + 4 * w + 4 * NWK * u;
+                const int j = k0 + 1 + jo;
+                const bool ok = jo < 15 + ws && j > k && j - k <= ws && j < n;
+                int jw = 16 * P + 1 + jo;
+                jw = jw >= W ? jw - W : jw;
+                jw = jw >= W ? jw - W : jw;
+                const int dj = j - k0;
+                const T *src = dj < 16 ? &DgS[q][c][dj & 15] : &Pr[bb][jw][lu_perm(c)];
+                const T v = *src;
+                if (ok) Ur[(long long)(n - 1 - j) * ldf + pk] = v * dk;
+            }
+        }
+        if (w == 0 && lane < 16 && k0 + lane < n) Di[k0 + lane] = DvS[q][lane];
+    };
     if (wv < NW) {
         // ---- tile wavefronts
         v4 acc[MT];
@@ -1371,8 +1436,10 @@ __global__ __launch_bounds__(64 * (TT + LU_NS)) void k_band_lu_la(BandArgs<T> B)
             LP_EMIT(P1, b ^ 1, k0 + 16);
             lds_barrier();                 // A: raw panel p+1 in buffer b^1
             LP_UPDATE(b, valid & ~(mP | mP1));                // L2
+            store(p, b, wv, std::integral_constant<int, NW>());   // the factors of panel p
             lds_barrier();                 // D: panel p+1 factored, buffer b free
         }
+        store(npan - 1, (npan - 1) & 1, wv, std::integral_constant<int, NW>());
 #undef LP_TILE_LOAD
 #undef LP_EMIT
 #undef LP_ARRIVE
@@ -1380,7 +1447,6 @@ __global__ __launch_bounds__(64 * (TT + LU_NS)) void k_band_lu_la(BandArgs<T> B)
     } else {
         // ---- writer wavefronts
         const int wr = wv - NW, wt = tid - 64 * NW;
-        T *Lr = B.fac + Sy.foff, *Ur = Lr + (long long)n * ldf, *Di = Ur + (long long)n * ldf;
         int bad = 0;
         auto factor = [&](int pf, int bb) {
             const int P = pf % TT;
@@ -1405,6 +1471,7 @@ __global__ __launch_bounds__(64 * (TT + LU_NS)) void k_band_lu_la(BandArgs<T> B)
                         inv = T(1) / piv;
                     }
                     if (lane == j) Dv[wr][j] = inv;
+                    if (wr == 0 && lane == j) DvS[pf & 1][j] = inv;
                     const T l = d[j] * inv;
                     const T lm = lc > j ? l : T(0);
 #pragma unroll
@@ -1418,6 +1485,7 @@ __global__ __launch_bounds__(64 * (TT + LU_NS)) void k_band_lu_la(BandArgs<T> B)
 #pragma unroll
                         for (int kk = 0; kk < 4; ++kk) x.v[kk] = d[4 * g + kk];
                         DgQ[wr][lc][g] = x;
+                        if (wr == 0) DgSQ[pf & 1][lc][g] = x;
                     }
 #pragma unroll
                     for (int c = 0; c < 16; ++c) Dt[wr][c][lc] = d[c];
@@ -1490,81 +1558,16 @@ __global__ __launch_bounds__(64 * (TT + LU_NS)) void k_band_lu_la(BandArgs<T> B)
                 }
             }
         };
-        // L and U of panel ps from buffer bb (diagonal tile from this
-        // wavefront's copy) in the solves' layout (fac_pos, R slots)
-        constexpr int R = 64 * NRF;
-        int kr0 = 1 % R, rr0 = (n - 1) % R;            // (k0 + 1) mod R, (n - 1 - k0) mod R
-        auto store = [&](int ps, int bb) {
-            const int k0 = 16 * ps, P = ps % TT;
-            struct Grp { T v[NRF]; };
-            // L: column c = wr + LU_NS j; lane l, register m holds slot
-            // 32 (2m + l / 32) + l mod 32 (one vector store per lane)
-#pragma unroll
-            for (int j = 0; j < (16 + LU_NS - 1) / LU_NS; ++j) {
-                const int c = wr + LU_NS * j, k = k0 + c;
-                if (c >= 16 || k >= n) break;
-                int k1 = kr0 + c;                             // (k + 1) mod R
-                k1 = k1 >= R ? k1 - R : k1;
-                Grp gv;
-#pragma unroll
-                for (int m = 0; m < NRF; ++m) {
-                    const int s = 32 * (2 * m + (lane >> 5)) + (lane & 31);
-                    int o = s - k1;
-                    o = o < 0 ? o + R : o;
-                    o += 1;                                   // row k + o with (k + o) mod R = s, 1 <= o <= R
-                    const int dr = c + o;
-                    int iw = 16 * P + dr;
-                    iw = iw >= W ? iw - W : iw;
-                    const bool ok = o <= ws && k + o < n;
-                    // one unconditional LDS read: L11 from the copy, -L21 from the panel, else zero
-                    const T *src = dr < 16 ? &Dg[wr][dr & 15][c] : &Pc[bb][iw][lu_perm(c)];
-                    src = ok ? src : &Zs[0];
-                    const T v = *src;
-                    gv.v[m] = dr < 16 ? v : -v;
-                }
-                *reinterpret_cast<Grp *>(Lr + (long long)k * ldf + lane * NRF) = gv;
-            }
-            // U(k0 + c, j) / U(k0 + c, k0 + c), j = k0 + c + 1 .. k0 + c + ws:
-            // lanes c = 0..15 over the panel rows, four columns per pass
-            {
-                constexpr int NJ = (W + 4 * LU_NS - 1) / (4 * LU_NS);
-                const int c = lc, k = k0 + c;
-                int rk = rr0 - c;                             // (n - 1 - k) mod R
-                rk = rk < 0 ? rk + R : rk;
-                const int pk = fac_pos(rk, NRF);
-                const T dk = Dv[wr][c];
-#pragma unroll
-                for (int u = 0; u < NJ; ++u) {
-                    const int jo = lg + 4 * wr + 4 * LU_NS * u;
-                    const int j = k0 + 1 + jo;
-                    const bool ok = jo < 15 + ws && j > k && j - k <= ws && j < n;
-                    int jw = 16 * P + 1 + jo;
-                    jw = jw >= W ? jw - W : jw;
-                    jw = jw >= W ? jw - W : jw;
-                    const int dj = j - k0;
-                    const T *src = dj < 16 ? &Dg[wr][c][dj & 15] : &Pr[bb][jw][lu_perm(c)];
-                    const T v = *src;
-                    if (ok) Ur[(long long)(n - 1 - j) * ldf + pk] = v * dk;
-                }
-            }
-            if (wr == 0 && lane < 16 && k0 + lane < n) Di[k0 + lane] = Dv[0][lane];
-            kr0 += 16;
-            kr0 = kr0 >= R ? kr0 - R : kr0;
-            rr0 -= 16;
-            rr0 = rr0 < 0 ? rr0 + R : rr0;
-        };
         if (wt == 0) Zs[0] = T(0);
         lds_barrier();                     // raw panel 0 in buffer 0
         factor(0, 0);
         lds_barrier();                     // panel 0 factored
         for (int p = 0; p + 1 < npan; ++p) {
             const int b = p & 1;
-            store(p, b);
             lds_barrier();                 // A
             factor(p + 1, b ^ 1);
             lds_barrier();                 // D
         }
-        if (npan > 0) store(npan - 1, (npan - 1) & 1);
         if (bad && lane == 0) atomicOr(B.flags, 4);
     }
 }
