@@ -125,7 +125,8 @@ typedef struct {
     int32_t newton_its;      /* Newton iterations of the last coarse step */
     int32_t ir_sweeps;       /* refinement sweeps of the last local step (max over systems) */
     double ir_relres;        /* largest final relative residual of the last local step */
-    int32_t flags;           /* bit 0: refinement did not converge; bit 1: Newton did not converge;
+    int32_t flags;           /* bit 0: refinement of the last local step did not converge;
+                                bit 1: Newton did not converge in some coarse step so far;
                                 bit 2: zero or non-finite pivot */
     int32_t reserved;
 } lp_stats;

@@ -675,6 +675,13 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     TRY(c->dalloc(&c->d_flags, 4));
     HIPCHK(hipMemsetAsync(c->d_flags, 0, 4 * sizeof(int), st));
     HIPCHK(hipMemsetAsync(c->d_its, 0, 4 * sizeof(int), st));
+    {
+        // "converged" before the first coarse step (the Newton start reports
+        // an unconverged previous step into the flags)
+        const std::vector<int> one{1, 0, 0, 0};
+        HIPCHK(hipMemcpyAsync(c->d_done, one.data(), 4 * sizeof(int), hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
     TRY(c->dalloc(&c->pro_P1, 3 * c->nf2));
     TRY(c->dalloc(&c->pro_P0, 3 * c->nf2));
     TRY(c->dalloc(&c->pro_U1, 2 * c->nf2));
@@ -726,6 +733,8 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     }
     TRY(c->dalloc(&c->band_cpor, P.cband_por));
     TRY(c->dalloc(&c->band_cns, P.cband_ns));
+    // the Jacobian assembly stores whole rows; entries outside the matrix stay zero
+    HIPCHK(hipMemsetAsync(c->band_cns, 0, P.cband_ns * sizeof(double), st));
     TRY(c->dalloc(&c->fac_cpor, fl_cpor.total + 32));
     TRY(c->dalloc(&c->fac_cns, fl_cns.total + 32));
     HIPCHK(hipMemsetAsync(c->fac_cpor, 0, fl_cpor.total * sizeof(double), st));
@@ -883,7 +892,7 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
         const int om = (int)((m + lp_ctx::RING - 2) % lp_ctx::RING);
         const bool ex = m >= 2;
         lp::NewtonStartArgs ns{c->cU[o], c->cp[o], ex ? c->cU[om] : nullptr, ex ? c->cp[om] : nullptr,
-                               c->cU[nw], c->cp[nw], 2 * nc2, c->nc1, c->d_done, c->d_its, c->band_cns, P.cband_ns};
+                               c->cU[nw], c->cp[nw], 2 * nc2, c->nc1, c->d_done, c->d_its, nullptr, 0, c->d_flags};
         lp::launch_newton_start(ns, st);
     }
     for (int it = 0; it < c->opt.max_newton; ++it) {
@@ -906,7 +915,7 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
             lp::OseenApplyArgs<double> aa{};
             aa.sys = c->d_cns; aa.cls2 = c->d_cls2; aa.dof2 = c->d_dof2; aa.dof1 = c->d_dof1;
             aa.W1[0] = oa.W1[0]; aa.W1[1] = oa.W1[1]; aa.band = c->band_cns; aa.skip = c->d_done;
-            lp::launch_oseen_assemble<double>(aa, 1, c->nodes_cns, st);
+            lp::launch_oseen_rows<double>(aa, 1, c->nodes_cns, P.cns.bw, st);
             lp::BandArgs<double> ba{c->d_lu_cns, c->band_cns, c->fac_cns, c->d_flags, c->d_done, c->lu_dummy + c->lu_dummy_coarse_off,
                                     (const double *)c->consts, c->const_one<double>()};
             if (!lp::launch_band_lu<double>(ba, 1, P.cns.bw, c->lu_variant_cns, st)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
@@ -1074,7 +1083,7 @@ lp_status lp_get_stats(lp_ctx *c, lp_stats *out) {
     HIPCHK(hipMemcpy(&done, c->d_done, sizeof(int), hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(&flags, c->d_flags, sizeof(int), hipMemcpyDeviceToHost));
     out->newton_its = its;
-    out->flags = flags & 4;
+    out->flags = flags & 6;
     if (c->n > 0 && !done) out->flags |= 2;
     std::vector<int> sw(3 * c->P.por.size() + c->P.ose.size()), cv(sw.size());
     std::vector<double> rel(sw.size());

@@ -216,8 +216,9 @@ struct NewtonStartArgs {
     double *U1, *P1;              // first iterate for level n+1
     long long nu2, np;
     int *done, *its;
-    double *band;                 // the Jacobian band, cleared for its assembly
+    double *band;                 // the Jacobian band, cleared for its assembly (or null)
     long long band_n;
+    int *flags;                   // bit 1 set if the previous coarse step ended unconverged
 };
 
 struct IrStartArgs {
@@ -247,6 +248,10 @@ void launch_porous_assemble(const AssembleArgs<T> &a, int nsys, hipStream_t st);
 void launch_oseen_rhs(const OseenArgs &a, int nsys, int maxnodes, int split, hipStream_t st);
 template <typename T>
 void launch_oseen_assemble(const OseenApplyArgs<T> &a, int nsys, int maxnodes, hipStream_t st);
+// the same band entries as launch_oseen_assemble, one wavefront per lattice
+// node, whole rows stored (no clearing needed); LDS 3 (2 maxbw + 1) entries
+template <typename T>
+void launch_oseen_rows(const OseenApplyArgs<T> &a, int nsys, int maxnodes, int maxbw, hipStream_t st);
 void launch_oseen_residual(const OseenApplyArgs<double> &a, int nsys, int maxnodes, hipStream_t st);
 void launch_oseen_finalize(const FinalizeArgs &a, int nsys, int maxnodes, hipStream_t st);
 template <typename T>

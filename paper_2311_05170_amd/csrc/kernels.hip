@@ -4,7 +4,8 @@
 // or a whole region of T_H for the coarse step).  Element work is done by
 // gather: one thread per local lattice node loops over the (at most six)
 // triangles of the box that contain the node and accumulates its own rows,
-// so results are deterministic without atomics.  Linear systems are banded
+// so results are deterministic without atomics (the single coarse Jacobian
+// takes one wavefront per node instead, the lanes splitting the triangles).  Linear systems are banded
 // (lattice-row ordering) and factored without pivoting by one workgroup per
 // system with the active window held in registers; triangular solves run one
 // wavefront per right-hand side.
@@ -715,6 +716,145 @@ __global__ __launch_bounds__(GB) void k_oseen_apply(OseenApplyArgs<T> A) {
         }
     }
     if (MODE == 0) grid_norms_and_flag(rr, bb, A.part, A.ticket, A.conv, A.relres, A.sweeps, A.tol, blockIdx.y);
+}
+
+// Jacobian rows of a few large-lattice Oseen systems (the coarse Navier-Stokes
+// Jacobian: one system of a few hundred nodes, where one thread per node leaves
+// the GPU idle).  One wavefront per lattice node: lane 8 e + s takes triangle
+// slot e of the node (the visiting order of for_elements) and column node s of
+// that triangle, so the quadrature of all triangles runs at once.  The node's
+// rows are summed in LDS, triangle after triangle in that same order (the
+// entries of one triangle are distinct columns), and then stored whole: every
+// band entry of a row is written, untouched ones as zero, so the band needs no
+// clearing.  Same entries, same summation order per entry as the node-thread
+// kernel's assembly mode.
+template <typename T>
+__global__ __launch_bounds__(64) void k_oseen_rows(OseenApplyArgs<T> A) {
+    const SysDesc S = A.sys[blockIdx.y];
+    if (A.skip && *A.skip) return;
+    const int q = blockIdx.x;
+    const int nloc = S.lw2 * S.lh2;
+    if (q >= nloc) return;
+    const int lane = threadIdx.x;
+    const int a = q % S.lw2, b = q / S.lw2;
+    const int cls = A.cls2[S.node_off + q];
+    const bool vertex = !(a & 1) && !(b & 1);
+    const int dv = cls == 0 ? A.dof2[S.node_off + q] : -1;
+    const int dp = vertex ? A.dof1[S.vert_off + (a >> 1) + S.lw1 * (b >> 1)] : -1;
+    if (dv < 0 && dp < 0) return;
+    const int ng = 2 * S.N + 1, ld = 2 * S.bw + 1;
+    const double h = S.h, h2 = h * h;
+    const double eta = c_co.eta, edt = c_co.eta / c_co.dt, nue = c_co.nu * c_co.eta;
+    extern __shared__ double rows_dyn[];
+    T *row = reinterpret_cast<T *>(rows_dyn);            // [3][ld]: rows dv, dv + 1, dp
+    for (int j = lane; j < 3 * ld; j += 64) row[j] = (T)0;
+    // this lane's triangle and column node
+    const int e = lane >> 3, s = lane & 7;
+    const int t = e & 1;
+    const int ci0 = (a - 1) >> 1 < 0 ? 0 : ((a - 1) >> 1);
+    const int ci1 = (a >> 1) < S.cx ? (a >> 1) : S.cx - 1;
+    const int cj0 = (b - 1) >> 1 < 0 ? 0 : ((b - 1) >> 1);
+    const int cj1 = (b >> 1) < S.cy ? (b >> 1) : S.cy - 1;
+    const int ci = ci0 + ((e >> 1) & 1), cj = cj0 + (e >> 2);
+    const int la_ = a - 2 * ci, lb_ = b - 2 * cj;
+    bool on = ci <= ci1 && cj <= cj1 && la_ >= 0 && la_ <= 2 && lb_ >= 0 && lb_ <= 2;
+    const int la = on ? p2_local(t, la_, lb_) : -1;
+    on = on && la >= 0 && s < 6;
+    // entry values and their row slots / columns
+    double vv[2][2] = {{0, 0}, {0, 0}}, vp[2] = {0, 0}, vq[2] = {0, 0};
+    int dks = -1, pks = -1;
+    if (on) {
+        const int k = s;
+        dks = A.dof2[S.node_off + (2 * ci + off2a(t, k)) + S.lw2 * (2 * cj + off2b(t, k))];
+        if (k < 3) pks = A.dof1[S.vert_off + (ci + off1a(t, k)) + S.lw1 * (cj + off1b(t, k))];
+        if (dv >= 0) {
+            double Nw[2][2] = {{0, 0}, {0, 0}};
+            if (c_co.convection) {
+                double W[2][6];
+                for (int kk = 0; kk < 6; ++kk) {
+                    const long long Gk = (2 * S.x0 + 2 * ci + off2a(t, kk)) + (long long)ng * (2 * S.y0 + 2 * cj + off2b(t, kk));
+                    for (int c = 0; c < 2; ++c) W[c][kk] = A.W1[c][Gk];
+                }
+                for (int qq = 0; qq < NQ; ++qq) {
+                    double wv[2] = {0, 0}, gw[2][2] = {{0, 0}, {0, 0}};
+                    for (int kk = 0; kk < 6; ++kk) {
+                        const double p = c_ref.phi[qq][kk];
+                        for (int c = 0; c < 2; ++c) {
+                            wv[c] += W[c][kk] * p;
+                            gw[c][0] += W[c][kk] * c_ref.dphi[t][qq][kk][0];
+                            gw[c][1] += W[c][kk] * c_ref.dphi[t][qq][kk][1];
+                        }
+                    }
+                    const double wt = c_ref.w[qq] * c_ref.phi[qq][la] * h;
+                    const double pk_ = c_ref.phi[qq][k];
+                    const double adv = wv[0] * c_ref.dphi[t][qq][k][0] + wv[1] * c_ref.dphi[t][qq][k][1];
+                    for (int c = 0; c < 2; ++c) {
+                        for (int d = 0; d < 2; ++d) Nw[c][d] += wt * pk_ * gw[c][d];
+                        Nw[c][c] += wt * adv;
+                    }
+                }
+            }
+            for (int c = 0; c < 2; ++c)
+                for (int d = 0; d < 2; ++d) {
+                    double v = nue * c_ref.Se[t][c * 6 + la][d * 6 + k] + eta * Nw[c][d];
+                    if (c == d) v += edt * h2 * c_ref.Me[t][la][k];
+                    vv[c][d] = v;
+                }
+            if (k < 3)
+                for (int c = 0; c < 2; ++c) vp[c] = eta * h * c_ref.Be[t][k][c * 6 + la];
+        }
+        if (dp >= 0) {
+            const int lv = p1_local(t, (a >> 1) - ci, (b >> 1) - cj);
+            for (int d = 0; d < 2; ++d) vq[d] = eta * h * c_ref.Be[t][lv][d * 6 + k];
+        }
+    }
+    // triangle after triangle: lanes of one triangle touch distinct columns,
+    // and the LDS operations of one wavefront complete in program order
+    auto add = [&](int r, int col, int rowi, double v) {
+        T &x = row[r * ld + (col - rowi + S.bw)];
+        x = (T)((double)x + v);
+    };
+    for (int ee = 0; ee < 8; ++ee) {
+        if (on && e == ee) {
+            if (dv >= 0 && dks >= 0)
+                for (int c = 0; c < 2; ++c)
+                    for (int d = 0; d < 2; ++d) add(c, dks + d, dv + c, vv[c][d]);
+            if (dv >= 0 && pks >= 0)
+                for (int c = 0; c < 2; ++c) {
+                    T &x = row[c * ld + (pks - (dv + c) + S.bw)];
+                    x = (T)((double)x - vp[c]);
+                }
+            if (dp >= 0 && dks >= 0)
+                for (int d = 0; d < 2; ++d) add(2, dks + d, dp, vq[d]);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    // Beavers-Joseph term on Gamma edges (x rows, x columns), after the triangles
+    if (lane == 0 && dv >= 0 && S.gamma && 2 * S.y0 + b == 0) {
+        const int A0 = 2 * S.x0 + a;
+        const int ne = (A0 & 1) ? 1 : 2;
+        for (int e2 = 0; e2 < ne; ++e2) {
+            const int ie = (A0 & 1) ? (A0 >> 1) : (A0 >> 1) - 1 + e2;
+            if (ie < S.x0 || ie >= S.x0 + S.cx) continue;
+            const int lg = A0 - 2 * ie;
+            for (int k = 0; k < 3; ++k) {
+                const int dk = A.dof2[S.node_off + 2 * ie + k - 2 * S.x0];
+                if (dk < 0) continue;
+                add(0, dk, dv, eta * c_co.beta * h * c_ref.Ge[lg][k]);
+            }
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    // whole rows into the column-major band: entry (r, col) at col * ld + r - col + bw
+    T *band = A.band + S.band_off;
+    for (int r = 0; r < 3; ++r) {
+        const int R = r < 2 ? (dv >= 0 ? dv + r : -1) : dp;
+        if (R < 0) continue;
+        for (int j = lane; j < ld; j += 64) {
+            const int col = R - S.bw + j;
+            if (col >= 0 && col < S.ndof) band[(long long)col * ld + (2 * S.bw - j)] = row[r * ld + j];
+        }
+    }
 }
 
 __device__ __forceinline__ void oseen_finalize_rows(const FinalizeArgs &F, const SysDesc &S, int start, int stride) {
@@ -1897,6 +2037,8 @@ __global__ void k_newton_start(NewtonStartArgs A) {
         else A.P1[j] = x1;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // done starts at 1 (setup), so this reports the previous step only
+        if (*A.done == 0) atomicOr(A.flags, 2);
         *A.done = 0;
         *A.its = 0;
     }
@@ -1955,6 +2097,10 @@ void launch_oseen_rhs(const OseenArgs &a, int nsys, int maxnodes, int split, hip
 template <typename T>
 void launch_oseen_assemble(const OseenApplyArgs<T> &a, int nsys, int maxnodes, hipStream_t st) {
     hipLaunchKernelGGL((k_oseen_apply<T, 1>), dim3(node_blocks(maxnodes), nsys), dim3(GB), 0, st, a);
+}
+template <typename T>
+void launch_oseen_rows(const OseenApplyArgs<T> &a, int nsys, int maxnodes, int maxbw, hipStream_t st) {
+    hipLaunchKernelGGL((k_oseen_rows<T>), dim3(maxnodes, nsys), dim3(64), 3 * (2 * maxbw + 1) * sizeof(T), st, a);
 }
 void launch_oseen_residual(const OseenApplyArgs<double> &a, int nsys, int maxnodes, hipStream_t st) {
     hipLaunchKernelGGL((k_oseen_apply<double, 0>), dim3(node_blocks(maxnodes), nsys), dim3(GB), 0, st, a);
@@ -2054,6 +2200,7 @@ template void launch_porous_assemble<float>(const AssembleArgs<float> &, int, hi
 template void launch_porous_assemble<double>(const AssembleArgs<double> &, int, hipStream_t);
 template void launch_oseen_assemble<float>(const OseenApplyArgs<float> &, int, int, hipStream_t);
 template void launch_oseen_assemble<double>(const OseenApplyArgs<double> &, int, int, hipStream_t);
+template void launch_oseen_rows<double>(const OseenApplyArgs<double> &, int, int, int, hipStream_t);
 template bool launch_band_lu<float>(const BandArgs<float> &, int, int, int, hipStream_t);
 template bool launch_band_lu<double>(const BandArgs<double> &, int, int, int, hipStream_t);
 template bool launch_band_solve<float>(const SolveArgs<float> &, int, int, int, int, int, hipStream_t);

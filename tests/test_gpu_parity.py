@@ -64,6 +64,8 @@ def run_parity(cfg, precision, steps, **kw):
         worst = max(worst, max(ec.values()), max(em.values()))
         assert max(ec.values()) < 1e-10, ec
         assert max(em.values()) < TOL[precision], em
+    # no coarse step ended unconverged, no bad pivot
+    assert g.stats()["flags"] & 6 == 0, g.stats()
     g.close()
     return worst
 
