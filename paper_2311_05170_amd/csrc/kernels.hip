@@ -1588,10 +1588,17 @@ __global__ __launch_bounds__(64 * (TT + LU_NS)) void k_band_lu_la(BandArgs<T> B)
         // ---- writer wavefronts
         const int wr = wv - NW, wt = tid - 64 * NW;
         int bad = 0;
+        // Factor panel pf (raw in buffer bb): every writer wavefront factors
+        // the diagonal tile itself (lane l < 16 holds row l), then lane wt
+        // solves one L21 row (l U11 = a, stored negated) or one U12 column
+        // (L11 u = a).  Both are the same forward substitution over a row of
+        // 16 values read from this wavefront's copy of the tile: row c of U11
+        // for the L21 rows (then scaled by 1 / U(c, c)), column c of L11 for
+        // the U12 columns, so no wavefront diverges between the two.
         auto factor = [&](int pf, int bb) {
             const int P = pf % TT;
+            T dinv = T(0);
             {
-                // diagonal tile: lane l holds row l mod 16; this wavefront's copy
                 T d[16];
 #pragma unroll
                 for (int g = 0; g < 4; ++g) {
@@ -1601,24 +1608,28 @@ __global__ __launch_bounds__(64 * (TT + LU_NS)) void k_band_lu_la(BandArgs<T> B)
                 }
 #pragma unroll
                 for (int j = 0; j < 16; ++j) {
-                    T piv = wave_bcast(d[j], j);
-                    if (!(fabs((double)piv) > 0.0) || !isfinite((double)piv)) { bad = 1; piv = T(1); }
+                    const T piv = wave_bcast(d[j], j);
                     T inv;
                     if constexpr (sizeof(T) == 4) {
                         inv = __builtin_amdgcn_rcpf(piv);           // then one Newton step
                         inv = fmaf(inv, fmaf(-piv, inv, 1.0f), inv);
                     } else {
-                        inv = T(1) / piv;
+                        inv = __builtin_amdgcn_rcp(piv);            // then two Newton steps
+                        inv = fma(inv, fma(-piv, inv, 1.0), inv);
+                        inv = fma(inv, fma(-piv, inv, 1.0), inv);
                     }
-                    if (lane == j) Dv[wr][j] = inv;
-                    if (wr == 0 && lane == j) DvS[pf & 1][j] = inv;
+                    dinv = lane == j ? inv : dinv;
                     const T l = d[j] * inv;
                     const T lm = lc > j ? l : T(0);
 #pragma unroll
                     for (int c = j + 1; c < 16; ++c) d[c] = fma(-lm, wave_bcast(d[c], j), d[c]);
                     d[j] = lc > j ? l : d[j];
                 }
+                // a zero, tiny or non-finite pivot leaves a zero or non-finite reciprocal
+                if (lane < 16 && !(fabs((double)dinv) > 0.0 && isfinite((double)dinv))) bad = 1;
                 if (lane < 16) {
+                    Dv[wr][lane] = dinv;
+                    if (wr == 0) DvS[pf & 1][lane] = dinv;
 #pragma unroll
                     for (int g = 0; g < 4; ++g) {
                         Quad<T> x;
@@ -1635,66 +1646,44 @@ __global__ __launch_bounds__(64 * (TT + LU_NS)) void k_band_lu_la(BandArgs<T> B)
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-            if (wt < W - 16) {
-                // one L21 row: l U11 = a, stored negated
-                const int rho = (16 * (P + 1) + wt) % W;
-                T a[16];
+            if (wt < 2 * (W - 16)) {
+                const bool isrow = wt < W - 16;
+                const int idx = (16 * (P + 1) + (isrow ? wt : wt - (W - 16))) % W;
+                Quad<T> *io = isrow ? &PcQ[bb][idx][0] : &PrQ[bb][idx][0];
+                const Quad<T> *mq = isrow ? &DgQ[wr][0][0] : reinterpret_cast<const Quad<T> *>(&Dt[wr][0][0]);
+                T x[16];
 #pragma unroll
                 for (int g = 0; g < 4; ++g) {
-                    const Quad<T> x = PcQ[bb][rho][g];
+                    const Quad<T> v = io[g];
 #pragma unroll
-                    for (int kk = 0; kk < 4; ++kk) a[4 * kk + g] = x.v[kk];
+                    for (int kk = 0; kk < 4; ++kk) x[4 * kk + g] = v.v[kk];
                 }
+                // row c + 1 is read while step c runs (the scheduling barriers
+                // keep the reads from being hoisted all at once)
+                Quad<T> m[2][4];
+#pragma unroll
+                for (int g = 0; g < 4; ++g) m[0][g] = mq[g];
 #pragma unroll
                 for (int c = 0; c < 16; ++c) {
-                    a[c] *= Dv[wr][c];
+                    if (c + 1 < 15) {
+#pragma unroll
+                        for (int g = 0; g < 4; ++g) m[(c + 1) & 1][g] = mq[4 * (c + 1) + g];
+                    }
+                    const T sc = wave_bcast(dinv, c);
+                    x[c] *= isrow ? sc : T(1);
                     if (c + 1 < 16) {
-                        T u[16];
 #pragma unroll
-                        for (int g = 0; g < 4; ++g) {
-                            const Quad<T> x = DgQ[wr][c][g];
-#pragma unroll
-                            for (int kk = 0; kk < 4; ++kk) u[4 * g + kk] = x.v[kk];
-                        }
-#pragma unroll
-                        for (int c2 = c + 1; c2 < 16; ++c2) a[c2] = fma(-a[c], u[c2], a[c2]);
+                        for (int c2 = c + 1; c2 < 16; ++c2) x[c2] = fma(-x[c], m[c & 1][c2 >> 2].v[c2 & 3], x[c2]);
                     }
+                    __builtin_amdgcn_sched_barrier(0);
                 }
+                const T sg = isrow ? T(-1) : T(1);
 #pragma unroll
                 for (int g = 0; g < 4; ++g) {
-                    Quad<T> x;
+                    Quad<T> v;
 #pragma unroll
-                    for (int kk = 0; kk < 4; ++kk) x.v[kk] = -a[4 * kk + g];
-                    PcQ[bb][rho][g] = x;
-                }
-            } else if (wt < 2 * (W - 16)) {
-                // one U12 column: L11 u = a
-                const int sig = (16 * (P + 1) + wt - (W - 16)) % W;
-                T u[16];
-#pragma unroll
-                for (int g = 0; g < 4; ++g) {
-                    const Quad<T> x = PrQ[bb][sig][g];
-#pragma unroll
-                    for (int kk = 0; kk < 4; ++kk) u[4 * kk + g] = x.v[kk];
-                }
-#pragma unroll
-                for (int r = 0; r + 1 < 16; ++r) {
-                    T l[16];
-#pragma unroll
-                    for (int g = 0; g < 4; ++g) {
-                        const Quad<T> x = reinterpret_cast<const Quad<T> *>(&Dt[wr][r][0])[g];
-#pragma unroll
-                        for (int kk = 0; kk < 4; ++kk) l[4 * g + kk] = x.v[kk];
-                    }
-#pragma unroll
-                    for (int r2 = r + 1; r2 < 16; ++r2) u[r2] = fma(-l[r2], u[r], u[r2]);
-                }
-#pragma unroll
-                for (int g = 0; g < 4; ++g) {
-                    Quad<T> x;
-#pragma unroll
-                    for (int kk = 0; kk < 4; ++kk) x.v[kk] = u[4 * kk + g];
-                    PrQ[bb][sig][g] = x;
+                    for (int kk = 0; kk < 4; ++kk) v.v[kk] = sg * x[4 * kk + g];
+                    io[g] = v;
                 }
             }
         };
