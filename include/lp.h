@@ -104,10 +104,12 @@ typedef struct {
     int32_t convection;      /* 1: Navier-Stokes (default); 0: Stokes (drops b_N) */
     int32_t max_ir;          /* refinement sweeps cap (>= 1) */
     double ir_tol;           /* stop when ||b - A x|| <= ir_tol ||b|| per system */
-    int32_t max_newton;      /* coarse nonlinear iterations cap: the first is a Newton step, the
-                                later ones reuse its Jacobian factors (chord steps with the exact
-                                residual); all stop at the same tolerance */
+    int32_t max_newton;      /* coarse nonlinear iterations cap per step: chord steps with the
+                                exact residual and the inverse of the Jacobian formed at the
+                                first iterate of a refresh step; all stop at newton_tol */
     double newton_tol;       /* stop when ||delta|| <= newton_tol ||x|| */
+    int32_t jacobian_every;  /* the coarse Jacobian is formed at steps 1, 1 + J, 1 + 2 J, ...
+                                and reused in between (0 or 1: every step) */
 } lp_options;
 
 /* Optional device allocator (e.g. a framework's caching allocator). */
@@ -128,7 +130,7 @@ typedef struct {
     int32_t flags;           /* bit 0: refinement of the last local step did not converge;
                                 bit 1: Newton did not converge in some coarse step so far;
                                 bit 2: zero or non-finite pivot */
-    int32_t reserved;
+    int32_t newton_its_max;  /* most Newton iterations of any coarse step so far */
 } lp_stats;
 
 /* Build meshes, partition, reference data and device buffers; interpolate the

@@ -582,7 +582,7 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     if (!params_ok(*prm, why)) return fail(LP_ERR_ARG, why);
     if (opt->problem != LP_MMS_EX1_2D) return fail(LP_ERR_UNSUPPORTED, "only the Example 1 manufactured problem is built in");
     if (opt->precision != LP_FP64 && opt->precision != LP_MIXED) return fail(LP_ERR_ARG, "precision must be LP_FP64 or LP_MIXED");
-    if (opt->max_ir < 1 || opt->max_newton < 1 || !(opt->ir_tol > 0) || !(opt->newton_tol > 0))
+    if (opt->max_ir < 1 || opt->max_newton < 1 || !(opt->ir_tol > 0) || !(opt->newton_tol > 0) || opt->jacobian_every < 0)
         return fail(LP_ERR_ARG, "max_ir, max_newton >= 1 and positive tolerances required");
     hipStream_t st = (hipStream_t)stream;
     std::unique_ptr<lp_ctx> c(new lp_ctx());
@@ -842,9 +842,11 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
     hipStream_t st = c->cstream;
     const int64_t m = c->n + 1;                       // time level produced
     // The porous solves and the Navier-Stokes solve of a coarse step do not
-    // read each other (each takes the other's previous level), so the porous
-    // part runs on the factor stream of this step, off the coarse stream.
-    hipStream_t ps = c->fstream[m % 2];
+    // read each other (each takes the other's previous level).  Both stay on
+    // the coarse stream: on a factor stream the porous part would queue behind
+    // the local porous batch of step m - 2 and tie the coarse steps to the
+    // local stage.
+    hipStream_t ps = st;
     const lp::Plan &P = c->P;
     const int o = (int)((m - 1) % lp_ctx::RING), nw = (int)(m % lp_ctx::RING);
     // slot m % RING was last read by local step m - RING + 1
@@ -895,6 +897,10 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
                                c->cU[nw], c->cp[nw], 2 * nc2, c->nc1, c->d_done, c->d_its, nullptr, 0, c->d_flags};
         lp::launch_newton_start(ns, st);
     }
+    // the Jacobian of a refresh step stays in use (its explicit inverse) until
+    // the next refresh
+    const int jev = c->opt.jacobian_every > 1 ? c->opt.jacobian_every : 1;
+    const bool refresh = (m - 1) % jev == 0;
     for (int it = 0; it < c->opt.max_newton; ++it) {
         lp::OseenArgs oa{};
         oa.sys = c->d_cns; oa.cls2 = c->d_cls2; oa.dof2 = c->d_dof2; oa.cls1 = c->d_cls1; oa.dof1 = c->d_dof1;
@@ -909,9 +915,10 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
         for (int k = 0; k < 3; ++k) oa.tf[k] = tf[k];
         oa.skip = c->d_done;
         lp::launch_oseen_rhs(oa, 1, c->nodes_cns, 8, st);
-        if (it == 0) {
-            // Jacobian at the first iterate (u^n); later iterations reuse its
-            // factors, with residuals of the current Jacobian (chord steps)
+        if (it == 0 && refresh) {
+            // Jacobian at the first iterate; later iterations (and steps, up to
+            // the next refresh) reuse its inverse, with residuals of the
+            // current iterate (chord steps)
             lp::OseenApplyArgs<double> aa{};
             aa.sys = c->d_cns; aa.cls2 = c->d_cls2; aa.dof2 = c->d_dof2; aa.dof1 = c->d_dof1;
             aa.W1[0] = oa.W1[0]; aa.W1[1] = oa.W1[1]; aa.band = c->band_cns; aa.skip = c->d_done;
@@ -1083,6 +1090,8 @@ lp_status lp_get_stats(lp_ctx *c, lp_stats *out) {
     HIPCHK(hipMemcpy(&done, c->d_done, sizeof(int), hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(&flags, c->d_flags, sizeof(int), hipMemcpyDeviceToHost));
     out->newton_its = its;
+    HIPCHK(hipMemcpy(&its, c->d_its + 1, sizeof(int), hipMemcpyDeviceToHost));
+    out->newton_its_max = std::max(its, out->newton_its);
     out->flags = flags & 6;
     if (c->n > 0 && !done) out->flags |= 2;
     std::vector<int> sw(3 * c->P.por.size() + c->P.ose.size()), cv(sw.size());

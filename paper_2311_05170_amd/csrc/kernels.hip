@@ -11,6 +11,7 @@
 // wavefront per right-hand side.
 #include <hip/hip_runtime.h>
 #include <type_traits>
+#include <utility>
 #include <cmath>
 
 #include "kernels.h"
@@ -344,10 +345,20 @@ __device__ __forceinline__ double oseen_z(const SysDesc &S, const OseenArgs &A, 
 __device__ __forceinline__ void conv_rows(int t, int la, double h, const double W[2][6], const double Z[2][6],
                                           bool want_c, double cW[2], double Nz[2]) {
     cW[0] = cW[1] = Nz[0] = Nz[1] = 0.0;
+    // Reference values are read at uniform addresses (scalar loads) and the
+    // lane picks its orientation and test node from them: indexing by the
+    // per-lane t or la would turn every read into a vector memory access.
+#pragma unroll 2
     for (int q = 0; q < NQ; ++q) {
         double wv[2] = {0, 0}, gw[2][2] = {{0, 0}, {0, 0}}, zv[2] = {0, 0}, gz[2][2] = {{0, 0}, {0, 0}};
+        double pla = 0.0;
+#pragma unroll
         for (int k = 0; k < 6; ++k) {
-            const double p = c_ref.phi[q][k], dx = c_ref.dphi[t][q][k][0], dy = c_ref.dphi[t][q][k][1];
+            const double p = c_ref.phi[q][k];
+            const double dx0 = c_ref.dphi[0][q][k][0], dx1 = c_ref.dphi[1][q][k][0];
+            const double dy0 = c_ref.dphi[0][q][k][1], dy1 = c_ref.dphi[1][q][k][1];
+            const double dx = t ? dx1 : dx0, dy = t ? dy1 : dy0;
+            pla = la == k ? p : pla;
             for (int c = 0; c < 2; ++c) {
                 wv[c] += W[c][k] * p;
                 gw[c][0] += W[c][k] * dx;
@@ -357,7 +368,7 @@ __device__ __forceinline__ void conv_rows(int t, int la, double h, const double 
                 gz[c][1] += Z[c][k] * dy;
             }
         }
-        const double wt = c_ref.w[q] * c_ref.phi[q][la];
+        const double wt = c_ref.w[q] * pla;
         for (int c = 0; c < 2; ++c) {
             if (want_c) cW[c] += wt * (wv[0] * gw[c][0] + wv[1] * gw[c][1]);
             Nz[c] += wt * (zv[0] * gw[c][0] + zv[1] * gw[c][1] + wv[0] * gz[c][0] + wv[1] * gz[c][1]);
@@ -1064,6 +1075,47 @@ __device__ __forceinline__ double wave_bcast<double>(double v, int lane) {
     const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
     return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
 }
+// value of v in lane J of each row of 16 lanes (DPP row broadcast, no SGPR
+// round trip)
+template <int J>
+__device__ __forceinline__ float row_bcast(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + J, 0xF, 0xF, true));
+}
+template <int J>
+__device__ __forceinline__ double row_bcast(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), 0x150 + J, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x150 + J, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
+}
+
+// Elimination step J of a 16 x 16 tile held by rows (lane l: row l mod 16, the
+// four rows of 16 lanes identical): multipliers stored below the diagonal,
+// the reciprocal of pivot J kept in lane J of dinv.
+template <int J, typename T>
+__device__ __forceinline__ void tile_lu_step(T (&d)[16], int lc, int lane, T &dinv) {
+    const T piv = row_bcast<J>(d[J]);
+    T inv;
+    if constexpr (sizeof(T) == 4) {
+        inv = __builtin_amdgcn_rcpf(piv);           // then one Newton step
+        inv = fmaf(inv, fmaf(-piv, inv, 1.0f), inv);
+    } else {
+        inv = __builtin_amdgcn_rcp(piv);            // then two Newton steps
+        inv = fma(inv, fma(-piv, inv, 1.0), inv);
+        inv = fma(inv, fma(-piv, inv, 1.0), inv);
+    }
+    dinv = lane == J ? inv : dinv;
+    const T l = d[J] * inv;
+    const T lm = lc > J ? l : T(0);
+#pragma unroll
+    for (int c = J + 1; c < 16; ++c) d[c] = fma(-lm, row_bcast<J>(d[c]), d[c]);
+    d[J] = lc > J ? l : d[J];
+}
+template <typename T, int... J>
+__device__ __forceinline__ void tile_lu(T (&d)[16], int lc, int lane, T &dinv, std::integer_sequence<int, J...>) {
+    (tile_lu_step<J>(d, lc, lane, dinv), ...);
+}
+
 // ---------------------------------------------------------------------------
 // Blocked band LU without pivoting on the matrix cores (MFMA 16x16x4).
 // The window of W = 16 TT rows and columns (W >= bw + 16) is split into
@@ -1606,25 +1658,7 @@ __global__ __launch_bounds__(64 * (TT + LU_NS)) void k_band_lu_la(BandArgs<T> B)
 #pragma unroll
                     for (int kk = 0; kk < 4; ++kk) d[4 * kk + g] = x.v[kk];
                 }
-#pragma unroll
-                for (int j = 0; j < 16; ++j) {
-                    const T piv = wave_bcast(d[j], j);
-                    T inv;
-                    if constexpr (sizeof(T) == 4) {
-                        inv = __builtin_amdgcn_rcpf(piv);           // then one Newton step
-                        inv = fmaf(inv, fmaf(-piv, inv, 1.0f), inv);
-                    } else {
-                        inv = __builtin_amdgcn_rcp(piv);            // then two Newton steps
-                        inv = fma(inv, fma(-piv, inv, 1.0), inv);
-                        inv = fma(inv, fma(-piv, inv, 1.0), inv);
-                    }
-                    dinv = lane == j ? inv : dinv;
-                    const T l = d[j] * inv;
-                    const T lm = lc > j ? l : T(0);
-#pragma unroll
-                    for (int c = j + 1; c < 16; ++c) d[c] = fma(-lm, wave_bcast(d[c], j), d[c]);
-                    d[j] = lc > j ? l : d[j];
-                }
+                tile_lu(d, lc, lane, dinv, std::make_integer_sequence<int, 16>());
                 // a zero, tiny or non-finite pivot leaves a zero or non-finite reciprocal
                 if (lane < 16 && !(fabs((double)dinv) > 0.0 && isfinite((double)dinv))) bad = 1;
                 if (lane < 16) {
@@ -2028,6 +2062,7 @@ __global__ void k_newton_start(NewtonStartArgs A) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         // done starts at 1 (setup), so this reports the previous step only
         if (*A.done == 0) atomicOr(A.flags, 2);
+        A.its[1] = max(A.its[1], A.its[0]);
         *A.done = 0;
         *A.its = 0;
     }

@@ -52,7 +52,7 @@ class LpParams(Structure):
 class LpOptions(Structure):
     _fields_ = [("problem", c_int32), ("precision", c_int32), ("convection", c_int32),
                 ("max_ir", c_int32), ("ir_tol", c_double), ("max_newton", c_int32),
-                ("newton_tol", c_double)]
+                ("newton_tol", c_double), ("jacobian_every", c_int32)]
 
 
 ALLOC_FN = CFUNCTYPE(c_void_p, c_size_t, c_void_p)
@@ -67,7 +67,7 @@ class LpStats(Structure):
     _fields_ = [("step", c_int64), ("n_porous", c_int64), ("n_conduit", c_int64),
                 ("local_dofs", c_int64), ("max_bw", c_int64), ("newton_its", c_int32),
                 ("ir_sweeps", c_int32), ("ir_relres", c_double), ("flags", c_int32),
-                ("reserved", c_int32)]
+                ("newton_its_max", c_int32)]
 
 
 class LpError(RuntimeError):
@@ -149,7 +149,7 @@ class LocalParallel:
 
     def __init__(self, n_coarse, refine, nsub, overlap, prm, dt, cuts=None, precision="mixed",
                  convection=True, max_ir=8, ir_tol=None, max_newton=16, newton_tol=1e-13,
-                 torch_allocator=True):
+                 jacobian_every=1, torch_allocator=True):
         import torch
         self._torch = torch
         if not torch.cuda.is_available():
@@ -163,6 +163,7 @@ class LocalParallel:
         opt.ir_tol = float(ir_tol if ir_tol is not None else (1e-10 if precision == "mixed" else 1e-12))
         opt.max_newton = int(max_newton)
         opt.newton_tol = float(newton_tol)
+        opt.jacobian_every = int(jacobian_every)
         self._alloc = None
         alloc_ptr = None
         if torch_allocator:
@@ -217,7 +218,7 @@ class LocalParallel:
     def stats(self):
         s = LpStats()
         _check(_LIB.lp_get_stats(self._h, byref(s)))
-        return {k: getattr(s, k) for k, _ in LpStats._fields_ if k != "reserved"}
+        return {k: getattr(s, k) for k, _ in LpStats._fields_}
 
     def set_timing(self, stages):
         """Turn the stage timers on for the named stages (empty = off); clears them."""

@@ -101,6 +101,14 @@ def test_parity_cfg2_first_steps(precision):
     run_parity(cfg, precision, 2)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_parity_jacobian_reuse(precision):
+    """The coarse Jacobian formed every third step and reused in between
+    (chord steps to the same tolerance) agrees with the oracle too."""
+    cfg = W.config("cfg1")
+    run_parity(cfg, precision, cfg["steps"], jacobian_every=3)
+
+
 def test_stokes_mode_parity():
     """Convection switched off (Stokes conduit) agrees too."""
     run_parity(W.small(), "fp64", 2, convection=False)
