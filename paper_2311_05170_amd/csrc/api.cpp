@@ -483,7 +483,7 @@ lp_status local_porous(lp_ctx *c, const double *pro, hipStream_t st) {
     pa.tf[0] = std::cos(t1); pa.tf[1] = std::sin(t1); pa.tf[2] = pa.tf[0] * pa.tf[0];
     {
         StageTimer tm(c, LP_T_POR_RHS, st);
-        lp::launch_porous_rhs(pa, nsys, c->nodes_por, st);
+        lp::launch_porous_rhs(pa, nsys, c->nodes_por, 1, st);
     }
     TRY(refine_porous<T>(c, c->d_por, nsys, c->nodes_por, c->part_por, c->tick_por, c->d_sv_por, (const T *)c->fac_por, c->maxbw_por, c->maxn_por, c->b_por,
                          c->x_por, c->r_por, c->conv_por, c->rel_por, c->sw_por, c->P.dof_total_por, c->opt.max_ir,
@@ -877,7 +877,7 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
     pa.Uy0 = c->cU[o] + nc2;
     pa.e_old = c->cP[o]; pa.e_new = c->cP[nw]; pa.b = c->b_cp;
     for (int k = 0; k < 3; ++k) pa.tf[k] = tf[k];
-    lp::launch_porous_rhs(pa, 1, c->nodes_cpor, ps);
+    lp::launch_porous_rhs(pa, 1, c->nodes_cpor, 8, ps);
     {
         // the three solves with the explicit inverses, then the node layout
         lp::DensePorousArgs dp{};

@@ -239,7 +239,7 @@ void launch_prolong_p1(const ProlongArgs &a, hipStream_t st);
 // maxnodes is the largest local P2 lattice of the batch.
 constexpr int GB = 128;
 int node_blocks(int maxnodes);
-void launch_porous_rhs(const PorousArgs &a, int nsys, int maxnodes, hipStream_t st);
+void launch_porous_rhs(const PorousArgs &a, int nsys, int maxnodes, int split, hipStream_t st);   // split 1 or 8 lanes per node
 void launch_porous_residual(const ResidualArgs &a, int nsys, int maxnodes, hipStream_t st);
 void launch_porous_finalize(const FinalizeArgs &a, int nsys, int maxnodes, hipStream_t st);
 template <typename T>

@@ -149,22 +149,64 @@ __device__ __forceinline__ double porous_z(const SysDesc &S, const PorousArgs &A
     return A.ex[f][G] * A.tf[0] - bg;
 }
 
+// The e-th triangle (e = 0..5) around box-local P2 node (a, b), in the order
+// for_elements visits them; false if the node has fewer.
+__device__ __forceinline__ bool nth_element(int a, int b, int cx, int cy, int e, int &t_, int &ci_, int &cj_, int &la_) {
+    const int ci0 = (a - 1) >> 1 < 0 ? 0 : ((a - 1) >> 1);
+    const int ci1 = (a >> 1) < cx ? (a >> 1) : cx - 1;
+    const int cj0 = (b - 1) >> 1 < 0 ? 0 : ((b - 1) >> 1);
+    const int cj1 = (b >> 1) < cy ? (b >> 1) : cy - 1;
+    int cnt = 0;
+    bool found = false;
+    for (int cj = cj0; cj <= cj1; ++cj)
+        for (int ci = ci0; ci <= ci1; ++ci) {
+            const int la = a - 2 * ci, lb = b - 2 * cj;
+            if (la < 0 || la > 2 || lb < 0 || lb > 2) continue;
+            for (int t = 0; t < 2; ++t) {
+                const int k = p2_local(t, la, lb);
+                if (k >= 0) {
+                    if (cnt == e) { t_ = t; ci_ = ci; cj_ = cj; la_ = k; found = true; }
+                    ++cnt;
+                }
+            }
+        }
+    return found;
+}
+
+// sum over the SPLIT consecutive lanes of a node group
+template <int SPLIT>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+    for (int o = SPLIT / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, SPLIT);
+    return v;
+}
+
+// SPLIT = 1: one thread per node walks the node's triangles.  SPLIT = 8: eight
+// lanes per node, lane e takes the e-th triangle and the group adds up (the
+// single coarse system, where a thread per node leaves the chip idle).
+template <int SPLIT>
 __global__ __launch_bounds__(GB) void k_porous_rhs(PorousArgs A) {
+    static_assert(GB % SPLIT == 0, "node groups within a block");
     const SysDesc S = A.sys[blockIdx.y];
     const int nloc = S.lw2 * S.lh2;
     const int ng = 2 * S.N + 1;
     const double h = S.h, h2 = h * h;
-    for (int q = blockIdx.x * GB + threadIdx.x; q < nloc; q += gridDim.x * GB) {
+    const int sub = SPLIT > 1 ? (int)(threadIdx.x % SPLIT) : 0;
+    for (int qq = blockIdx.x * GB + threadIdx.x; qq < nloc * SPLIT; qq += gridDim.x * GB) {
+        const int q = qq / SPLIT;
         const int a = q % S.lw2, b = q / S.lw2;
         const long long G = (2 * S.x0 + a) + (long long)ng * (2 * S.y0 + b);
         const int cls = A.cls2[S.node_off + q];
         for (int f = 0; f < 3; ++f) {
             double *en = A.e_new + S.e2_off + (long long)f * nloc;
-            if (cls != 0) { en[q] = porous_z(S, A, f, q, G); continue; }
+            if (cls != 0) {
+                if (sub == 0) en[q] = porous_z(S, A, f, q, G);
+                continue;
+            }
             // sources at t_{n+1}
-            double r = A.load[f][0][G] * A.tf[0] + A.load[f][1][G] * A.tf[1];
+            double r = sub == 0 ? A.load[f][0][G] * A.tf[0] + A.load[f][1][G] * A.tf[1] : 0.0;
             const double tau = c_co.tau[f], xf = porous_x(f), kap = c_co.kap[f];
-            for_elements(a, b, S.cx, S.cy, [&](int t, int ci, int cj, int la) {
+            auto elem = [&](int t, int ci, int cj, int la) {
                 double mv = 0.0, kv = 0.0;
                 for (int k = 0; k < 6; ++k) {
                     const int qa = 2 * ci + off2a(t, k), qb = 2 * cj + off2b(t, k);
@@ -182,7 +224,16 @@ __global__ __launch_bounds__(GB) void k_porous_rhs(PorousArgs A) {
                     kv += c_ref.Ke[t][la][k] * X;
                 }
                 r += h2 * mv - kap * kv;
-            });
+            };
+            if (SPLIT == 1) {
+                for_elements(a, b, S.cx, S.cy, elem);
+            } else {
+                int t, ci, cj, la;
+                if (nth_element(a, b, S.cx, S.cy, sub, t, ci, cj, la)) elem(t, ci, cj, la);
+                // every lane of the group takes part (same node, same branch)
+                r = group_sum<SPLIT>(r);
+                if (sub != 0) continue;
+            }
             // + <u^n . n_c, v_F>_Gamma = -int_Gamma v_F u_y^n on the porous top row
             if (f == 0 && S.gamma && 2 * S.y0 + b == 2 * S.N && A.Uy0) {
                 const int A0 = 2 * S.x0 + a;
@@ -378,37 +429,6 @@ __device__ __forceinline__ void conv_rows(int t, int la, double h, const double 
     for (int c = 0; c < 2; ++c) { cW[c] *= h; Nz[c] *= h; }
 }
 
-// The e-th triangle (e = 0..5) around box-local P2 node (a, b), in the order
-// for_elements visits them; false if the node has fewer.
-__device__ __forceinline__ bool nth_element(int a, int b, int cx, int cy, int e, int &t_, int &ci_, int &cj_, int &la_) {
-    const int ci0 = (a - 1) >> 1 < 0 ? 0 : ((a - 1) >> 1);
-    const int ci1 = (a >> 1) < cx ? (a >> 1) : cx - 1;
-    const int cj0 = (b - 1) >> 1 < 0 ? 0 : ((b - 1) >> 1);
-    const int cj1 = (b >> 1) < cy ? (b >> 1) : cy - 1;
-    int cnt = 0;
-    bool found = false;
-    for (int cj = cj0; cj <= cj1; ++cj)
-        for (int ci = ci0; ci <= ci1; ++ci) {
-            const int la = a - 2 * ci, lb = b - 2 * cj;
-            if (la < 0 || la > 2 || lb < 0 || lb > 2) continue;
-            for (int t = 0; t < 2; ++t) {
-                const int k = p2_local(t, la, lb);
-                if (k >= 0) {
-                    if (cnt == e) { t_ = t; ci_ = ci; cj_ = cj; la_ = k; found = true; }
-                    ++cnt;
-                }
-            }
-        }
-    return found;
-}
-
-// sum over the SPLIT consecutive lanes of a node group
-template <int SPLIT>
-__device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-    for (int o = SPLIT / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, SPLIT);
-    return v;
-}
 
 // SPLIT = 1: one thread per node walks the node's triangles.  SPLIT = 8: eight
 // lanes per node, lane e takes the e-th triangle and the group adds up (for
@@ -2101,8 +2121,9 @@ void launch_prolong_p1(const ProlongArgs &a, hipStream_t st) {
 }
 int node_blocks(int maxnodes) { return maxnodes > 0 ? (maxnodes + GB - 1) / GB : 1; }
 
-void launch_porous_rhs(const PorousArgs &a, int nsys, int maxnodes, hipStream_t st) {
-    hipLaunchKernelGGL(k_porous_rhs, dim3(node_blocks(maxnodes), nsys), dim3(GB), 0, st, a);
+void launch_porous_rhs(const PorousArgs &a, int nsys, int maxnodes, int split, hipStream_t st) {
+    if (split == 8) hipLaunchKernelGGL((k_porous_rhs<8>), dim3(node_blocks(8 * maxnodes), nsys), dim3(GB), 0, st, a);
+    else hipLaunchKernelGGL((k_porous_rhs<1>), dim3(node_blocks(maxnodes), nsys), dim3(GB), 0, st, a);
 }
 void launch_porous_residual(const ResidualArgs &a, int nsys, int maxnodes, hipStream_t st) {
     hipLaunchKernelGGL(k_porous_residual, dim3(node_blocks(maxnodes), nsys, 3), dim3(GB), 0, st, a);
