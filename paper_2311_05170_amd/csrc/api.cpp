@@ -127,7 +127,7 @@ struct lp_ctx {
     int lu_variant = 0;                // factorisation kernel of the porous and coarse systems (0: default)
     int lu_variant_ose = 9;            // of the local Oseen systems (blocked on the matrix cores with lookahead)
     int lu_variant_cns = 9;            // of the coarse Navier-Stokes Jacobian (9: blocked on the matrix cores with lookahead)
-    int solve_depth = 0;               // factor columns prefetched by the band solves (16, 32; 0 = by precision and bandwidth)
+    int solve_depth = 0;               // factor columns prefetched by the band solves (16, 32, 64 (FP32); 0 = by precision)
     // device constants read by masked loads: 512 zero doubles (a zero column
     // for the solves), then 1.0 as double, then 1.0f as float
     double *consts = nullptr;

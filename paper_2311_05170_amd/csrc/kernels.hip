@@ -1781,7 +1781,8 @@ constexpr int SOLVE_LD = 8;
 template <typename T, int NR, int D, bool REV>
 __device__ __forceinline__ void band_pass(const T *C, int n, int ldf, T *ys, const T *dl, int lane) {
     constexpr int H = 2 * NR, R = 64 * NR;
-    static_assert(32 % D == 0, "prefetch ring divides a block");
+    // column k sits in ring slot k mod D, static within the unrolled super-block
+    static_assert((32 * H) % D == 0, "prefetch ring divides a super-block");
     struct Grp { T v[NR]; };
     // row r of the pass (reversed rows for the second pass) in LDS
     auto yat = [&](int r) -> T & { return REV ? ys[n - 1 - r] : ys[r]; };
@@ -1810,18 +1811,19 @@ __device__ __forceinline__ void band_pass(const T *C, int n, int ldf, T *ys, con
             const T ent = yat(32 * (b + H) + (lane & 31));      // the rows entering this half next
 #pragma unroll
             for (int s = 0; s < 32; ++s) {
+                const int sl = (32 * hb + s) % D;
                 const T yk = wave_bcast(win[mh], lh + s);
-                win[mh] = fma(-cf[s % D][mh], yk, win[mh]);      // the half the next broadcast reads first
+                win[mh] = fma(-cf[sl][mh], yk, win[mh]);      // the half the next broadcast reads first
 #pragma unroll
                 for (int m = 0; m < NR; ++m)
-                    if (m != mh) win[m] = fma(-cf[s % D][m], yk, win[m]);
+                    if (m != mh) win[m] = fma(-cf[sl][m], yk, win[m]);
                 // every column's updates happen in its column (otherwise the
                 // compiler defers the other halves' chains to the block end and
                 // keeps all their factor registers alive): an empty statement
                 // that reads and writes the window
 #pragma unroll
                 for (int m = 0; m < NR; ++m) asm volatile("" : "+v"(win[m]));
-                LP_COL(32 * b + s + D, s % D);
+                LP_COL(32 * b + s + D, sl);
                 __builtin_amdgcn_sched_barrier(0);              // keep each prefetch in its column
             }
             const bool mine = (lane & 32) == lh;
@@ -2201,12 +2203,15 @@ bool launch_band_solve_d(const SolveArgs<T> &a, int nsys, int nrhs, int maxbw, i
     return true;
 }
 
-// depth: columns of factor prefetch (16 or 32)
+// depth: columns of factor prefetch (16, 32 or 64)
 template <typename T>
 bool launch_band_solve(const SolveArgs<T> &a, int nsys, int nrhs, int maxbw, int maxn, int depth, hipStream_t st) {
-    // automatic depth: 32 columns in flight while the prefetched factors fit
-    // in the 256 architectural registers next to the window (FP32), else 16
-    if (depth != 16 && depth != 32) depth = sizeof(T) == 4 ? 32 : 16;
+    // automatic depth: 32 columns in flight for FP32, 16 for FP64 (deeper
+    // prefetch measured no faster: the column chain, not the loads, sets the pace)
+    if (depth != 16 && depth != 32 && depth != 64) depth = sizeof(T) == 4 ? 32 : 16;
+    if constexpr (sizeof(T) == 4) {
+        if (depth == 64) return launch_band_solve_d<T, 64>(a, nsys, nrhs, maxbw, maxn, st);
+    }
     return depth == 16 ? launch_band_solve_d<T, 16>(a, nsys, nrhs, maxbw, maxn, st)
                        : launch_band_solve_d<T, 32>(a, nsys, nrhs, maxbw, maxn, st);
 }

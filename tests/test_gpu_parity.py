@@ -148,6 +148,14 @@ def test_parity_lu_kernels(precision, variant, monkeypatch):
     run_parity(_ragged(), precision, 3)
 
 
+@pytest.mark.parametrize("depth", ["16", "32", "64"])
+def test_parity_solve_prefetch_depths(depth, monkeypatch):
+    """The band solves with 16, 32 or 64 factor columns in flight (64: FP32
+    only, the FP64 solves then take 32) agree with the oracle."""
+    monkeypatch.setenv("LP_SOLVE_DEPTH", depth)
+    run_parity(_ragged(), "mixed", 2)
+
+
 def _fields(g):
     return {f: g.solution(f) for f in ("u", "p", "pF", "pf", "pm")}
 
