@@ -154,11 +154,12 @@ def calibrate_copy(n=1 << 26, reps=3):
 
 
 def kernel_sha():
-    """Hash of the roofline kernel's source: the matrix-core traits through the
-    end of the lookahead factorisation, with the barrier and broadcast helpers
-    it calls (a change anywhere else in the file leaves it alone)."""
+    """Hash of the roofline kernel's source: the row broadcast and diagonal-tile
+    elimination helpers and the matrix-core traits through the end of the
+    lookahead factorisation, with the barrier and broadcast helpers it calls (a
+    change anywhere else in the file leaves it alone)."""
     src = open(os.path.join(ROOT, "paper_2311_05170_amd", "csrc", "kernels.hip")).read()
-    a = src.index("template <typename T>\nstruct Mfma;")
+    a = src.index("template <int J>\n__device__ __forceinline__ float row_bcast(")
     b = src.index("void k_band_lu_la(")
     b = src.index("\n}\n", b) + 3
     parts = [src[a:b]]
