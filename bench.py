@@ -51,7 +51,7 @@ def band_lu_flops(sizes):
 # converged; with the Jacobian formed every JACOBIAN_EVERY steps they take at
 # most eight on this workload, and a step that hits the cap unconverged sets
 # bit 1 of the reported flags.
-MAX_NEWTON = 12
+MAX_NEWTON = 10
 JACOBIAN_EVERY = 3
 
 

@@ -891,9 +891,10 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
     // (u^(n-1), p^(n-1)) (from (u^n, p^n) at the first step); each iteration
     // solves the Oseen system linearised about the current iterate
     {
-        const int om = (int)((m + lp_ctx::RING - 2) % lp_ctx::RING);
-        const bool ex = m >= 2;
+        const int om = (int)((m + lp_ctx::RING - 2) % lp_ctx::RING), omm = (int)((m + lp_ctx::RING - 3) % lp_ctx::RING);
+        const bool ex = m >= 2, ex2 = m >= 3;
         lp::NewtonStartArgs ns{c->cU[o], c->cp[o], ex ? c->cU[om] : nullptr, ex ? c->cp[om] : nullptr,
+                               ex2 ? c->cU[omm] : nullptr, ex2 ? c->cp[omm] : nullptr,
                                c->cU[nw], c->cp[nw], 2 * nc2, c->nc1, c->d_done, c->d_its, nullptr, 0, c->d_flags};
         lp::launch_newton_start(ns, st);
     }

@@ -213,6 +213,7 @@ struct DensePorousArgs {
 struct NewtonStartArgs {
     const double *U0, *P0;        // level n
     const double *Um, *Pm;        // level n-1 (null at the first step)
+    const double *Umm, *Pmm;      // level n-2 (null at the first two steps)
     double *U1, *P1;              // first iterate for level n+1
     long long nu2, np;
     int *done, *its;

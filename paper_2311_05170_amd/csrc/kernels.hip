@@ -2075,9 +2075,10 @@ __global__ void k_newton_start(NewtonStartArgs A) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < tot; i += (long long)gridDim.x * blockDim.x) {
         const bool u = i < A.nu2;
         const long long j = u ? i : i - A.nu2;
+        // extrapolation through the last three levels (two at the second step)
         const double x0 = u ? A.U0[j] : A.P0[j];
         const double xm = A.Um ? (u ? A.Um[j] : A.Pm[j]) : x0;
-        const double x1 = 2.0 * x0 - xm;
+        const double x1 = A.Umm ? 3.0 * (x0 - xm) + (u ? A.Umm[j] : A.Pmm[j]) : 2.0 * x0 - xm;
         if (u) A.U1[j] = x1;
         else A.P1[j] = x1;
     }
