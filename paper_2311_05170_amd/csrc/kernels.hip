@@ -1660,6 +1660,10 @@ __global__ __launch_bounds__(64 * (TT + LU_NS)) void k_band_lu_la(BandArgs<T> B)
         // ---- writer wavefronts
         const int wr = wv - NW, wt = tid - 64 * NW;
         int bad = 0;
+        // The writers' elimination is the panel's critical path and shares
+        // its SIMDs with tile wavefronts doing the off-path trailing update and
+        // stores: their instructions go first.
+        __builtin_amdgcn_s_setprio(3);
         // Factor panel pf (raw in buffer bb): every writer wavefront factors
         // the diagonal tile itself (lane l < 16 holds row l), then lane wt
         // solves one L21 row (l U11 = a, stored negated) or one U12 column
