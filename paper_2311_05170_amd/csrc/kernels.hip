@@ -1782,6 +1782,31 @@ constexpr int SOLVE_PAD = 3 * 256 + 64;
 // rows per lane in flight when moving the right-hand side and the solution
 constexpr int SOLVE_LD = 8;
 
+// NR consecutive values of T at byte offset voff + soff of a buffer resource
+// (raw buffer load: the column offset rides in an SGPR, the lane offset in a
+// loop-invariant VGPR, so a column costs no vector address arithmetic)
+template <typename T, int NR>
+__device__ __forceinline__ void col_load(__amdgpu_buffer_rsrc_t rs, int voff, int soff, T (&dst)[NR]) {
+    constexpr int NB = NR * (int)sizeof(T);
+    unsigned w[NB / 4];
+    if constexpr (NB == 8) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0);
+        w[0] = v[0]; w[1] = v[1];
+    } else if constexpr (NB == 12) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b96(rs, voff, soff, 0);
+        w[0] = v[0]; w[1] = v[1]; w[2] = v[2];
+    } else if constexpr (NB == 16) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0);
+        w[0] = v[0]; w[1] = v[1]; w[2] = v[2]; w[3] = v[3];
+    } else {
+        static_assert(NB == 24, "two or three values per lane");
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0);
+        const auto u = __builtin_amdgcn_raw_buffer_load_b64(rs, voff + 16, soff, 0);
+        w[0] = v[0]; w[1] = v[1]; w[2] = v[2]; w[3] = v[3]; w[4] = u[0]; w[5] = u[1];
+    }
+    __builtin_memcpy(dst, w, NB);
+}
+
 template <typename T, int NR, int D, bool REV>
 __device__ __forceinline__ void band_pass(const T *C, int n, int ldf, T *ys, const T *dl, int lane) {
     constexpr int H = 2 * NR, R = 64 * NR;
@@ -1794,13 +1819,16 @@ __device__ __forceinline__ void band_pass(const T *C, int n, int ldf, T *ys, con
     // slot of (register m, this lane): rows s, s + R, ... in turn
 #pragma unroll
     for (int m = 0; m < NR; ++m) win[m] = yat(32 * (2 * m + (lane >> 5)) + (lane & 31));
-    const int lo = lane * NR;
     const int nb = (n + 31) >> 5;
-#define LP_COL(KK, S)                                                                      \
-    do {                                                                                   \
-        const Grp g = *reinterpret_cast<const Grp *>(C + (long long)min((KK), n - 1) * ldf + lo); \
-        _Pragma("unroll") for (int m = 0; m < NR; ++m) cf[S][m] = g.v[m];                   \
-    } while (0)
+    // the resource from wavefront-uniform values (scalar registers)
+    const unsigned long long cb = reinterpret_cast<unsigned long long>(C);
+    const unsigned long long cu = ((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(cb >> 32)) << 32) |
+                                  (unsigned)__builtin_amdgcn_readfirstlane((unsigned)cb);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void *>(cu), (short)0,
+                                                                         __builtin_amdgcn_readfirstlane(n * ldf * (int)sizeof(T)),
+                                                                         0x00020000);
+    const int voff = lane * NR * (int)sizeof(T);
+#define LP_COL(KK, S) col_load<T, NR>(rs, voff, min((KK), n - 1) * ldf * (int)sizeof(T), cf[S])
 #pragma unroll
     for (int s = 0; s < D; ++s) {
         LP_COL(s, s);
