@@ -197,58 +197,63 @@ __global__ __launch_bounds__(GB) void k_porous_rhs(PorousArgs A) {
         const int a = q % S.lw2, b = q / S.lw2;
         const long long G = (2 * S.x0 + a) + (long long)ng * (2 * S.y0 + b);
         const int cls = A.cls2[S.node_off + q];
-        for (int f = 0; f < 3; ++f) {
-            double *en = A.e_new + S.e2_off + (long long)f * nloc;
-            if (cls != 0) {
-                if (sub == 0) en[q] = porous_z(S, A, f, q, G);
-                continue;
-            }
-            // sources at t_{n+1}
-            double r = sub == 0 ? A.load[f][0][G] * A.tf[0] + A.load[f][1][G] * A.tf[1] : 0.0;
-            const double tau = c_co.tau[f], xf = porous_x(f), kap = c_co.kap[f];
-            auto elem = [&](int t, int ci, int cj, int la) {
-                double mv = 0.0, kv = 0.0;
-                for (int k = 0; k < 6; ++k) {
-                    const int qa = 2 * ci + off2a(t, k), qb = 2 * cj + off2b(t, k);
-                    const int qk = qa + S.lw2 * qb;
-                    const long long Gk = (2 * S.x0 + qa) + (long long)ng * (2 * S.y0 + qb);
-                    double O[3], X;
-                    for (int g = 0; g < 3; ++g)
-                        O[g] = (A.P0[g] ? A.P0[g][Gk] : 0.0) + A.e_old[S.e2_off + (long long)g * nloc + qk];
-                    X = (A.P1[f] ? A.P1[f][Gk] : 0.0) + porous_z(S, A, f, qk, Gk);
-                    double m = tau * (O[f] - X) - xf * X;
+        if (cls != 0) {
+            if (sub == 0)
+                for (int f = 0; f < 3; ++f) A.e_new[S.e2_off + (long long)f * nloc + q] = porous_z(S, A, f, q, G);
+            continue;
+        }
+        // sources at t_{n+1}; the three fields together, so each node of a
+        // triangle is read once for all of them
+        double r[3];
+        for (int f = 0; f < 3; ++f) r[f] = sub == 0 ? A.load[f][0][G] * A.tf[0] + A.load[f][1][G] * A.tf[1] : 0.0;
+        auto elem = [&](int t, int ci, int cj, int la) {
+            double mv[3] = {0.0, 0.0, 0.0}, kv[3] = {0.0, 0.0, 0.0};
+            for (int k = 0; k < 6; ++k) {
+                const int qa = 2 * ci + off2a(t, k), qb = 2 * cj + off2b(t, k);
+                const int qk = qa + S.lw2 * qb;
+                const long long Gk = (2 * S.x0 + qa) + (long long)ng * (2 * S.y0 + qb);
+                const bool dir = A.cls2[S.node_off + qk] == 1;
+                double O[3], X[3];
+                for (int g = 0; g < 3; ++g) {
+                    const double p1 = A.P1[g] ? A.P1[g][Gk] : 0.0;
+                    O[g] = (A.P0[g] ? A.P0[g][Gk] : 0.0) + A.e_old[S.e2_off + (long long)g * nloc + qk];
+                    X[g] = p1 + (dir ? A.ex[g][Gk] * A.tf[0] - p1 : 0.0);
+                }
+                for (int f = 0; f < 3; ++f) {
+                    double m = c_co.tau[f] * (O[f] - X[f]) - porous_x(f) * X[f];
                     if (f == 0) m += c_co.sst * O[1];
                     if (f == 1) m += c_co.s * O[2] + c_co.sst * O[0];
                     if (f == 2) m += c_co.s * O[1];
-                    mv += c_ref.Me[t][la][k] * m;
-                    kv += c_ref.Ke[t][la][k] * X;
-                }
-                r += h2 * mv - kap * kv;
-            };
-            if (SPLIT == 1) {
-                for_elements(a, b, S.cx, S.cy, elem);
-            } else {
-                int t, ci, cj, la;
-                if (nth_element(a, b, S.cx, S.cy, sub, t, ci, cj, la)) elem(t, ci, cj, la);
-                // every lane of the group takes part (same node, same branch)
-                r = group_sum<SPLIT>(r);
-                if (sub != 0) continue;
-            }
-            // + <u^n . n_c, v_F>_Gamma = -int_Gamma v_F u_y^n on the porous top row
-            if (f == 0 && S.gamma && 2 * S.y0 + b == 2 * S.N && A.Uy0) {
-                const int A0 = 2 * S.x0 + a;
-                const int ne = (A0 & 1) ? 1 : 2;
-                for (int e = 0; e < ne; ++e) {
-                    const int ie = (A0 & 1) ? (A0 >> 1) : (A0 >> 1) - 1 + e;
-                    if (ie < S.x0 || ie >= S.x0 + S.cx) continue;
-                    const int la = A0 - 2 * ie;
-                    double s = 0.0;
-                    for (int k = 0; k < 3; ++k) s += c_ref.Ge[la][k] * A.Uy0[2 * ie + k];   // conduit Gamma row b = 0
-                    r -= h * s;
+                    mv[f] += c_ref.Me[t][la][k] * m;
+                    kv[f] += c_ref.Ke[t][la][k] * X[f];
                 }
             }
-            A.b[S.dof_off + (long long)f * S.ndof + A.dof2[S.node_off + q]] = r;
+            for (int f = 0; f < 3; ++f) r[f] += h2 * mv[f] - c_co.kap[f] * kv[f];
+        };
+        if (SPLIT == 1) {
+            for_elements(a, b, S.cx, S.cy, elem);
+        } else {
+            int t, ci, cj, la;
+            if (nth_element(a, b, S.cx, S.cy, sub, t, ci, cj, la)) elem(t, ci, cj, la);
+            // every lane of the group takes part (same node, same branch)
+            for (int f = 0; f < 3; ++f) r[f] = group_sum<SPLIT>(r[f]);
+            if (sub != 0) continue;
         }
+        // + <u^n . n_c, v_F>_Gamma = -int_Gamma v_F u_y^n on the porous top row
+        if (S.gamma && 2 * S.y0 + b == 2 * S.N && A.Uy0) {
+            const int A0 = 2 * S.x0 + a;
+            const int ne = (A0 & 1) ? 1 : 2;
+            for (int e = 0; e < ne; ++e) {
+                const int ie = (A0 & 1) ? (A0 >> 1) : (A0 >> 1) - 1 + e;
+                if (ie < S.x0 || ie >= S.x0 + S.cx) continue;
+                const int la = A0 - 2 * ie;
+                double sg = 0.0;
+                for (int k = 0; k < 3; ++k) sg += c_ref.Ge[la][k] * A.Uy0[2 * ie + k];   // conduit Gamma row b = 0
+                r[0] -= h * sg;
+            }
+        }
+        const int d = A.dof2[S.node_off + q];
+        for (int f = 0; f < 3; ++f) A.b[S.dof_off + (long long)f * S.ndof + d] = r[f];
     }
 }
 
