@@ -303,38 +303,48 @@ __device__ void grid_norms_and_flag(double rr, double bb, double *part, int *tic
 }
 
 // y = A_f x restricted to free rows (FP64, matrix-free); r = b - y; norms
+// The three fields of a system in one pass (each node's triangles and their
+// degrees of freedom read once); a converged field is left alone.
 __global__ __launch_bounds__(GB) void k_porous_residual(ResidualArgs R) {
     const SysDesc S = R.sys[blockIdx.y];
-    const int f = blockIdx.z;
-    const int id = blockIdx.y * 3 + f;
     if (R.skip && *R.skip) return;
-    if (R.conv[id]) return;
+    const int id0 = blockIdx.y * 3;
+    bool act[3];
+    for (int f = 0; f < 3; ++f) act[f] = !R.conv[id0 + f];
+    if (!act[0] && !act[1] && !act[2]) return;
     const int nloc = S.lw2 * S.lh2;
     const double h2 = S.h * S.h;
-    const double tau = c_co.tau[f], xf = porous_x(f), kap = c_co.kap[f];
-    const double *x = R.x + S.dof_off + (long long)f * S.ndof;
-    const double *b = R.b + S.dof_off + (long long)f * S.ndof;
-    double *r = R.r + S.dof_off + (long long)f * S.ndof;
-    double rr = 0.0, bb = 0.0;
+    double cm[3], ck[3];
+    for (int f = 0; f < 3; ++f) { cm[f] = (c_co.tau[f] + porous_x(f)) * h2; ck[f] = c_co.kap[f]; }
+    const double *x = R.x + S.dof_off, *b = R.b + S.dof_off;
+    double *r = R.r + S.dof_off;
+    const long long nd = S.ndof;
+    double rr[3] = {0.0, 0.0, 0.0}, bb[3] = {0.0, 0.0, 0.0};
     for (int q = blockIdx.x * GB + threadIdx.x; q < nloc; q += gridDim.x * GB) {
         const int dq = R.dof2[S.node_off + q];
         if (dq < 0) continue;
         const int a = q % S.lw2, bq = q / S.lw2;
-        double y = 0.0;
+        double y[3] = {0.0, 0.0, 0.0};
         for_elements(a, bq, S.cx, S.cy, [&](int t, int ci, int cj, int la) {
             for (int k = 0; k < 6; ++k) {
                 const int qk = (2 * ci + off2a(t, k)) + S.lw2 * (2 * cj + off2b(t, k));
                 const int dk = R.dof2[S.node_off + qk];
                 if (dk < 0) continue;
-                y += ((tau + xf) * h2 * c_ref.Me[t][la][k] + kap * c_ref.Ke[t][la][k]) * x[dk];
+                const double me = c_ref.Me[t][la][k], ke = c_ref.Ke[t][la][k];
+                for (int f = 0; f < 3; ++f)
+                    if (act[f]) y[f] += (cm[f] * me + ck[f] * ke) * x[f * nd + dk];
             }
         });
-        const double rv = b[dq] - y;
-        r[dq] = rv;
-        rr += rv * rv;
-        bb += b[dq] * b[dq];
+        for (int f = 0; f < 3; ++f) {
+            if (!act[f]) continue;
+            const double bv = b[f * nd + dq], rv = bv - y[f];
+            r[f * nd + dq] = rv;
+            rr[f] += rv * rv;
+            bb[f] += bv * bv;
+        }
     }
-    grid_norms_and_flag(rr, bb, R.part, R.ticket, R.conv, R.relres, R.sweeps, R.tol, id);
+    for (int f = 0; f < 3; ++f)
+        if (act[f]) grid_norms_and_flag(rr[f], bb[f], R.part, R.ticket, R.conv, R.relres, R.sweeps, R.tol, id0 + f);
 }
 
 __device__ __forceinline__ void porous_finalize_rows(const FinalizeArgs &F, const SysDesc &S, int start, int stride) {
@@ -2166,7 +2176,7 @@ void launch_porous_rhs(const PorousArgs &a, int nsys, int maxnodes, int split, h
     else hipLaunchKernelGGL((k_porous_rhs<1>), dim3(node_blocks(maxnodes), nsys), dim3(GB), 0, st, a);
 }
 void launch_porous_residual(const ResidualArgs &a, int nsys, int maxnodes, hipStream_t st) {
-    hipLaunchKernelGGL(k_porous_residual, dim3(node_blocks(maxnodes), nsys, 3), dim3(GB), 0, st, a);
+    hipLaunchKernelGGL(k_porous_residual, dim3(node_blocks(maxnodes), nsys), dim3(GB), 0, st, a);
 }
 void launch_porous_finalize(const FinalizeArgs &a, int nsys, int maxnodes, hipStream_t st) {
     hipLaunchKernelGGL(k_porous_finalize, dim3(node_blocks(maxnodes), nsys), dim3(GB), 0, st, a);
