@@ -406,9 +406,9 @@ lp_status local_oseen(lp_ctx *c, hipStream_t st) {
 }
 
 // Assemble and factor the local Oseen operators of time level m (linearised
-// about Pi_h u_cH^m) on the factor stream, into factor slot m % 2.  Ordered
-// after coarse step m; the slot's previous user, local step m-2, finished
-// before coarse step m started.
+// about Pi_h u_cH^m) on factor stream m % 2 (band slot m % 2, ordered by that
+// stream), into factor slot m % FSLOTS.  Ordered after coarse step m; the
+// factor slot's previous reader, local step m - FSLOTS, is waited for.
 template <typename T>
 lp_status factor_oseen(lp_ctx *c, int64_t m) {
     const int nw = (int)(m % lp_ctx::RING), bs = (int)(m % 2), fs = (int)(m % lp_ctx::FSLOTS);

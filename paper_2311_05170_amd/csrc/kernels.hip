@@ -2112,9 +2112,10 @@ __global__ __launch_bounds__(1024) void k_dense_porous(DensePorousArgs A) {
     porous_finalize_rows(A.f, A.f.sys[0], threadIdx.x, blockDim.x);
 }
 
-// start of the coarse Newton solve: the first iterate is the linear
-// extrapolation 2 x^n - x^(n-1) of the two previous levels (x^n at the first
-// step), counters and the Jacobian band cleared
+// start of the coarse Newton solve: the first iterate is the extrapolation
+// of the previous levels (quadratic through three, linear through two at the
+// second step, x^n at the first), counters reset (an unconverged previous step
+// reported), and optionally a band cleared
 __global__ void k_newton_start(NewtonStartArgs A) {
     const long long tot = A.nu2 + A.np;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < A.band_n; i += (long long)gridDim.x * blockDim.x)

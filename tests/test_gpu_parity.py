@@ -130,6 +130,23 @@ def test_state_machine_errors():
     g.close()
 
 
+def test_newton_cap_sets_sticky_flag():
+    """A coarse step that reaches the iteration cap unconverged raises flag bit
+    1, and the flag stays set after later steps (one chord step cannot reach
+    1e-13 from the extrapolated start)."""
+    g = _gpu(W.small(), "fp64", max_newton=1)
+    g.step()
+    g.step()
+    assert g.stats()["flags"] & 2
+    g.close()
+    g = _gpu(W.small(), "fp64")
+    for _ in range(3):
+        g.step()
+    st = g.stats()
+    assert st["flags"] == 0 and 1 <= st["newton_its"] <= st["newton_its_max"] <= 16, st
+    g.close()
+
+
 RAGGED_PRM = dict(W.unit_params(), nu=0.05, k=[0.3, 0.02, 0.004], sigma=2.0, sigma_star=0.5)
 
 
