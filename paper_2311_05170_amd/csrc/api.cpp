@@ -117,6 +117,7 @@ struct lp_ctx {
     int maxbw_por = 0, maxbw_ose = 0, maxn_por = 0, maxn_ose = 0;
     // largest local P2 lattice per batch (node blocks of the gather kernels)
     int nodes_por = 0, nodes_ose = 0, nodes_cpor = 0, nodes_cns = 0;
+    int tiles_ose = 0;                 // most residual tiles of a local Oseen box
     // residual norm partials and arrival counters, one set per batch (the
     // batches run on different streams)
     double *part_por = nullptr, *part_ose = nullptr, *part_cp = nullptr, *part_cn = nullptr;
@@ -352,7 +353,7 @@ lp_status refine_oseen(lp_ctx *c, const lp::SysDesc *d_sys, int nsys, int maxnod
         ra.x = x; ra.b = b; ra.r = r; ra.band = nullptr;
         ra.conv = conv; ra.relres = rel; ra.sweeps = sw; ra.tol = tol; ra.skip = skip;
         ra.part = part; ra.ticket = ticket;
-        lp::launch_oseen_residual(ra, nsys, maxnodes, st);
+        lp::launch_oseen_residual_tiled(ra, nsys, c->tiles_ose, st);
     }
     return LP_OK;
 }
@@ -597,7 +598,11 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     if (alloc && alloc->alloc && alloc->free) { c->alloc = *alloc; c->has_alloc = true; }
     lp::Plan &P = c->P;
     for (const auto &s : P.por) { c->maxbw_por = std::max(c->maxbw_por, s.bw); c->maxn_por = std::max(c->maxn_por, s.ndof); }
-    for (const auto &s : P.ose) { c->maxbw_ose = std::max(c->maxbw_ose, s.bw); c->maxn_ose = std::max(c->maxn_ose, s.ndof); }
+    for (const auto &s : P.ose) {
+        c->maxbw_ose = std::max(c->maxbw_ose, s.bw);
+        c->maxn_ose = std::max(c->maxn_ose, s.ndof);
+        c->tiles_ose = std::max(c->tiles_ose, lp::residual_tiles(s.cx, s.cy));
+    }
     for (const auto &s : P.por) c->nodes_por = std::max(c->nodes_por, s.lw2 * s.lh2);
     for (const auto &s : P.ose) c->nodes_ose = std::max(c->nodes_ose, s.lw2 * s.lh2);
     c->nodes_cpor = P.cpor.lw2 * P.cpor.lh2;
@@ -752,7 +757,7 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     {
         auto nb = [](int nodes) { return (long long)lp::node_blocks(nodes); };
         TRY(c->dalloc(&c->part_por, 2 * npf * nb(c->nodes_por))); TRY(c->dalloc(&c->tick_por, npf));
-        TRY(c->dalloc(&c->part_ose, 2 * nof * nb(c->nodes_ose))); TRY(c->dalloc(&c->tick_ose, nof));
+        TRY(c->dalloc(&c->part_ose, 2 * nof * std::max<long long>(nb(c->nodes_ose), c->tiles_ose))); TRY(c->dalloc(&c->tick_ose, nof));
         TRY(c->dalloc(&c->part_cp, 2 * 3 * nb(c->nodes_cpor))); TRY(c->dalloc(&c->tick_cp, 3));
         TRY(c->dalloc(&c->part_cn, 2 * nb(c->nodes_cns))); TRY(c->dalloc(&c->tick_cn, 1));
         HIPCHK(hipMemsetAsync(c->tick_por, 0, npf * sizeof(int), st));

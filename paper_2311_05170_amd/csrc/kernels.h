@@ -254,6 +254,11 @@ void launch_oseen_assemble(const OseenApplyArgs<T> &a, int nsys, int maxnodes, h
 template <typename T>
 void launch_oseen_rows(const OseenApplyArgs<T> &a, int nsys, int maxnodes, int maxbw, hipStream_t st);
 void launch_oseen_residual(const OseenApplyArgs<double> &a, int nsys, int maxnodes, hipStream_t st);
+// the same residual by tiles of 8 x 8 cells (each triangle integrated once);
+// maxtiles = max over the systems of residual_tiles(cx, cy); its norm partials
+// take 2 maxtiles doubles per system
+int residual_tiles(int cx, int cy);
+void launch_oseen_residual_tiled(const OseenApplyArgs<double> &a, int nsys, int maxtiles, hipStream_t st);
 void launch_oseen_finalize(const FinalizeArgs &a, int nsys, int maxnodes, hipStream_t st);
 template <typename T>
 bool launch_band_lu(const BandArgs<T> &a, int nsys, int maxbw, int variant, hipStream_t st);

@@ -270,17 +270,17 @@ __device__ __forceinline__ double wave_sum(double v) {
 // counts the sweep, raises the convergence flag and rearms the counter.
 __device__ void grid_norms_and_flag(double rr, double bb, double *part, int *ticket, int *conv, double *relres,
                                     int *sweeps, double tol, int id) {
-    __shared__ double s1[GB / 64], s2[GB / 64];
+    __shared__ double s1[16], s2[16];       // one per wavefront (blocks of up to 1024 threads)
     __shared__ int last;
     rr = wave_sum(rr);
     bb = wave_sum(bb);
-    const int w = threadIdx.x >> 6;
+    const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
     if ((threadIdx.x & 63) == 0) { s1[w] = rr; s2[w] = bb; }
     __syncthreads();
     const long long base = 2LL * id * gridDim.x;
     if (threadIdx.x == 0) {
         double a = 0.0, b = 0.0;
-        for (int i = 0; i < GB / 64; ++i) { a += s1[i]; b += s2[i]; }
+        for (int i = 0; i < nw; ++i) { a += s1[i]; b += s2[i]; }
         part[base + 2 * blockIdx.x] = a;
         part[base + 2 * blockIdx.x + 1] = b;
         __threadfence();
@@ -762,6 +762,154 @@ __global__ __launch_bounds__(GB) void k_oseen_apply(OseenApplyArgs<T> A) {
         }
     }
     if (MODE == 0) grid_norms_and_flag(rr, bb, A.part, A.ticket, A.conv, A.relres, A.sweeps, A.tol, blockIdx.y);
+}
+
+// Oseen residual r = b - K x (FP64) by tiles of RT x RT cells of a box: each
+// triangle of the tile (and of a one-cell halo below and to the left) is
+// integrated once, for all six of its nodes' rows (the quadrature of the
+// convection term shared by them) into LDS; then every node of the tile adds
+// the contributions of its triangles in the node-thread order, so a node's
+// sum does not depend on the tiling.  Blocks past a box's tile count only
+// take part in the norm reduction.
+constexpr int RT = 8;
+constexpr int RT_TRI = 2 * (RT + 1) * (RT + 1);
+int residual_tiles(int cx, int cy) { return ((cx + RT - 1) / RT) * ((cy + RT - 1) / RT); }
+
+__global__ __launch_bounds__(256) void k_oseen_residual_tiled(OseenApplyArgs<double> A) {
+    const SysDesc S = A.sys[blockIdx.y];
+    if (A.skip && *A.skip) return;
+    if (A.conv[blockIdx.y]) return;
+    const int ntx = (S.cx + RT - 1) / RT, nty = (S.cy + RT - 1) / RT;
+    const bool has = (int)blockIdx.x < ntx * nty;
+    const int tx = has ? (int)blockIdx.x % ntx : 0, ty = has ? (int)blockIdx.x / ntx : 0;
+    const int ci_lo = tx * RT - 1, cj_lo = ty * RT - 1;    // first (halo) cell of the tile's triangles
+    const int ng = 2 * S.N + 1;
+    const double h = S.h, h2 = h * h;
+    const double eta = c_co.eta, edt = c_co.eta / c_co.dt, nue = c_co.nu * c_co.eta;
+    const double *x = A.x + S.dof_off;
+    __shared__ double cv[RT_TRI][6][2];     // velocity rows: (triangle, its node la, component)
+    __shared__ double cp[RT_TRI][3];        // pressure rows: (triangle, its vertex)
+    const int tid = threadIdx.x;
+    if (has) {
+        for (int e = tid; e < RT_TRI; e += blockDim.x) {
+            const int t = e & 1, cc = e >> 1;
+            const int ci = ci_lo + cc % (RT + 1), cj = cj_lo + cc / (RT + 1);
+            if (ci < 0 || cj < 0 || ci >= S.cx || cj >= S.cy) continue;
+            double W[2][6], X[2][6], Pv[3];
+            for (int k = 0; k < 6; ++k) {
+                const int qa = 2 * ci + off2a(t, k), qb = 2 * cj + off2b(t, k);
+                const long long Gk = (2 * S.x0 + qa) + (long long)ng * (2 * S.y0 + qb);
+                const int dk = A.dof2[S.node_off + qa + S.lw2 * qb];
+                for (int c = 0; c < 2; ++c) {
+                    W[c][k] = A.W1[c][Gk];
+                    X[c][k] = dk >= 0 ? x[dk + c] : 0.0;
+                }
+            }
+            for (int v = 0; v < 3; ++v) {
+                const int pk = A.dof1[S.vert_off + (ci + off1a(t, v)) + S.lw1 * (cj + off1b(t, v))];
+                Pv[v] = pk >= 0 ? x[pk] : 0.0;
+            }
+            // int (N(W) X)_c phi_la for the six test nodes at once
+            double Nz[6][2];
+            for (int l = 0; l < 6; ++l) Nz[l][0] = Nz[l][1] = 0.0;
+            if (c_co.convection) {
+                for (int q = 0; q < NQ; ++q) {
+                    double wv[2] = {0, 0}, gw[2][2] = {{0, 0}, {0, 0}}, zv[2] = {0, 0}, gz[2][2] = {{0, 0}, {0, 0}};
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) {
+                        const double p = c_ref.phi[q][k];
+                        const double dx0 = c_ref.dphi[0][q][k][0], dx1 = c_ref.dphi[1][q][k][0];
+                        const double dy0 = c_ref.dphi[0][q][k][1], dy1 = c_ref.dphi[1][q][k][1];
+                        const double dx = t ? dx1 : dx0, dy = t ? dy1 : dy0;
+                        for (int c = 0; c < 2; ++c) {
+                            wv[c] += W[c][k] * p;
+                            gw[c][0] += W[c][k] * dx;
+                            gw[c][1] += W[c][k] * dy;
+                            zv[c] += X[c][k] * p;
+                            gz[c][0] += X[c][k] * dx;
+                            gz[c][1] += X[c][k] * dy;
+                        }
+                    }
+                    double g[2];
+                    for (int c = 0; c < 2; ++c) g[c] = zv[0] * gw[c][0] + zv[1] * gw[c][1] + wv[0] * gz[c][0] + wv[1] * gz[c][1];
+#pragma unroll
+                    for (int l = 0; l < 6; ++l) {
+                        const double wt = c_ref.w[q] * c_ref.phi[q][l];
+                        for (int c = 0; c < 2; ++c) Nz[l][c] += wt * g[c];
+                    }
+                }
+                for (int l = 0; l < 6; ++l) { Nz[l][0] *= h; Nz[l][1] *= h; }
+            }
+            for (int l = 0; l < 6; ++l)
+                for (int c = 0; c < 2; ++c) {
+                    double m = 0.0, sv = 0.0, bt = 0.0;
+                    for (int k = 0; k < 6; ++k) {
+                        m += c_ref.Me[t][l][k] * X[c][k];
+                        for (int d = 0; d < 2; ++d) sv += c_ref.Se[t][c * 6 + l][d * 6 + k] * X[d][k];
+                    }
+                    for (int v = 0; v < 3; ++v) bt += c_ref.Be[t][v][c * 6 + l] * Pv[v];
+                    cv[e][l][c] = edt * h2 * m + nue * sv + eta * Nz[l][c] - eta * h * bt;
+                }
+            for (int v = 0; v < 3; ++v) {
+                double sv = 0.0;
+                for (int d = 0; d < 2; ++d)
+                    for (int k = 0; k < 6; ++k) sv += c_ref.Be[t][v][d * 6 + k] * X[d][k];
+                cp[e][v] = eta * h * sv;
+            }
+        }
+    }
+    __syncthreads();
+    double rr = 0.0, bb = 0.0;
+    if (has) {
+        // nodes of the tile: lattice columns 2 RT tx .. (the last tile to the box's edge)
+        const int a0 = 2 * RT * tx, a1 = tx == ntx - 1 ? 2 * S.cx : 2 * RT * (tx + 1) - 1;
+        const int b0 = 2 * RT * ty, b1 = ty == nty - 1 ? 2 * S.cy : 2 * RT * (ty + 1) - 1;
+        const int wa = a1 - a0 + 1, cnt = wa * (b1 - b0 + 1);
+        for (int idx = tid; idx < cnt; idx += blockDim.x) {
+            const int a = a0 + idx % wa, b = b0 + idx / wa;
+            const int q = a + S.lw2 * b;
+            const int cls = A.cls2[S.node_off + q];
+            const bool vertex = !(a & 1) && !(b & 1);
+            const int dv = cls == 0 ? A.dof2[S.node_off + q] : -1;
+            const int dp = vertex ? A.dof1[S.vert_off + (a >> 1) + S.lw1 * (b >> 1)] : -1;
+            if (dv < 0 && dp < 0) continue;
+            double yv[2] = {0.0, 0.0}, yq = 0.0;
+            for_elements(a, b, S.cx, S.cy, [&](int t, int ci, int cj, int la) {
+                const int e = 2 * ((ci - ci_lo) + (RT + 1) * (cj - cj_lo)) + t;
+                if (dv >= 0) { yv[0] += cv[e][la][0]; yv[1] += cv[e][la][1]; }
+                if (dp >= 0) yq += cp[e][p1_local(t, (a >> 1) - ci, (b >> 1) - cj)];
+            });
+            // Beavers-Joseph term on Gamma edges (x rows, x columns)
+            if (dv >= 0 && S.gamma && 2 * S.y0 + b == 0) {
+                const int A0 = 2 * S.x0 + a;
+                const int ne = (A0 & 1) ? 1 : 2;
+                for (int e2 = 0; e2 < ne; ++e2) {
+                    const int ie = (A0 & 1) ? (A0 >> 1) : (A0 >> 1) - 1 + e2;
+                    if (ie < S.x0 || ie >= S.x0 + S.cx) continue;
+                    const int lg = A0 - 2 * ie;
+                    for (int k = 0; k < 3; ++k) {
+                        const int dk = A.dof2[S.node_off + (2 * ie + k - 2 * S.x0)];
+                        if (dk < 0) continue;
+                        yv[0] += eta * c_co.beta * h * c_ref.Ge[lg][k] * x[dk];
+                    }
+                }
+            }
+            if (dv >= 0)
+                for (int c = 0; c < 2; ++c) {
+                    const double bv = A.b[S.dof_off + dv + c], rv = bv - yv[c];
+                    A.r[S.dof_off + dv + c] = rv;
+                    rr += rv * rv;
+                    bb += bv * bv;
+                }
+            if (dp >= 0) {
+                const double bv = A.b[S.dof_off + dp], rv = bv - yq;
+                A.r[S.dof_off + dp] = rv;
+                rr += rv * rv;
+                bb += bv * bv;
+            }
+        }
+    }
+    grid_norms_and_flag(rr, bb, A.part, A.ticket, A.conv, A.relres, A.sweeps, A.tol, blockIdx.y);
 }
 
 // Jacobian rows of a few large-lattice Oseen systems (the coarse Navier-Stokes
@@ -2200,6 +2348,9 @@ void launch_oseen_rows(const OseenApplyArgs<T> &a, int nsys, int maxnodes, int m
 }
 void launch_oseen_residual(const OseenApplyArgs<double> &a, int nsys, int maxnodes, hipStream_t st) {
     hipLaunchKernelGGL((k_oseen_apply<double, 0>), dim3(node_blocks(maxnodes), nsys), dim3(GB), 0, st, a);
+}
+void launch_oseen_residual_tiled(const OseenApplyArgs<double> &a, int nsys, int maxtiles, hipStream_t st) {
+    hipLaunchKernelGGL(k_oseen_residual_tiled, dim3(maxtiles > 0 ? maxtiles : 1, nsys), dim3(256), 0, st, a);
 }
 void launch_oseen_finalize(const FinalizeArgs &a, int nsys, int maxnodes, hipStream_t st) {
     hipLaunchKernelGGL(k_oseen_finalize, dim3(node_blocks(maxnodes), nsys), dim3(GB), 0, st, a);
