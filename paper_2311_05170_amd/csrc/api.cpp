@@ -389,7 +389,7 @@ lp_status local_oseen(lp_ctx *c, hipStream_t st) {
     oa.skip = nullptr;
     {
         StageTimer tm(c, LP_T_OSE_RHS, st);
-        lp::launch_oseen_rhs(oa, nsys, c->nodes_ose, 1, st);
+        lp::launch_oseen_rhs_tiled(oa, nsys, c->tiles_ose, st);
     }
     // factors of the operator linearised about Pi_h u_cH^{n+1} (factor stream)
     const int fs = (int)((c->n + 1) % lp_ctx::FSLOTS);

@@ -912,6 +912,149 @@ __global__ __launch_bounds__(256) void k_oseen_residual_tiled(OseenApplyArgs<dou
     grid_norms_and_flag(rr, bb, A.part, A.ticket, A.conv, A.relres, A.sweeps, A.tol, blockIdx.y);
 }
 
+// Local Oseen right-hand sides by the same tiles as the residual: each
+// triangle's contributions to its six velocity rows and three pressure rows
+// once into LDS, then the node threads (Dirichlet values, sources, Gamma
+// terms) add their triangles in the node-thread order.
+__global__ __launch_bounds__(256) void k_oseen_rhs_tiled(OseenArgs A) {
+    const SysDesc S = A.sys[blockIdx.y];
+    if (A.skip && *A.skip) return;
+    const int ntx = (S.cx + RT - 1) / RT, nty = (S.cy + RT - 1) / RT;
+    if ((int)blockIdx.x >= ntx * nty) return;
+    const int tx = (int)blockIdx.x % ntx, ty = (int)blockIdx.x / ntx;
+    const int ci_lo = tx * RT - 1, cj_lo = ty * RT - 1;
+    const int nloc = S.lw2 * S.lh2;
+    const int ng = 2 * S.N + 1, ng1 = S.N + 1;
+    const double h = S.h, h2 = h * h;
+    const double eta = c_co.eta, edt = c_co.eta / c_co.dt, nue = c_co.nu * c_co.eta;
+    __shared__ double cv[RT_TRI][6][2];
+    __shared__ double cp[RT_TRI][3];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < RT_TRI; e += blockDim.x) {
+        const int t = e & 1, cc = e >> 1;
+        const int ci = ci_lo + cc % (RT + 1), cj = cj_lo + cc / (RT + 1);
+        if (ci < 0 || cj < 0 || ci >= S.cx || cj >= S.cy) continue;
+        double W[2][6], Z[2][6], Y[2][6], O[2][6], P[3];
+        for (int k = 0; k < 6; ++k) {
+            const int qa = 2 * ci + off2a(t, k), qb = 2 * cj + off2b(t, k);
+            const int qk = qa + S.lw2 * qb;
+            const long long Gk = (2 * S.x0 + qa) + (long long)ng * (2 * S.y0 + qb);
+            for (int c = 0; c < 2; ++c) {
+                W[c][k] = A.W1[c][Gk];
+                Z[c][k] = oseen_z(S, A, c, qk, Gk);
+                Y[c][k] = W[c][k] + Z[c][k];
+                O[c][k] = (A.W0[c] ? A.W0[c][Gk] : 0.0) + (A.e_old ? A.e_old[S.e2_off + (long long)c * nloc + qk] : 0.0)
+                          - W[c][k] - Z[c][k];
+            }
+        }
+        for (int k = 0; k < 3; ++k)
+            P[k] = A.Pp[(S.x0 + ci + off1a(t, k)) + (long long)ng1 * (S.y0 + cj + off1b(t, k))];
+        // int ((W.grad)W + N(W) Z)_c phi_la for the six test nodes at once
+        double CN[6][2];
+        for (int l = 0; l < 6; ++l) CN[l][0] = CN[l][1] = 0.0;
+        if (c_co.convection) {
+            for (int q = 0; q < NQ; ++q) {
+                double wv[2] = {0, 0}, gw[2][2] = {{0, 0}, {0, 0}}, zv[2] = {0, 0}, gz[2][2] = {{0, 0}, {0, 0}};
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    const double p = c_ref.phi[q][k];
+                    const double dx0 = c_ref.dphi[0][q][k][0], dx1 = c_ref.dphi[1][q][k][0];
+                    const double dy0 = c_ref.dphi[0][q][k][1], dy1 = c_ref.dphi[1][q][k][1];
+                    const double dx = t ? dx1 : dx0, dy = t ? dy1 : dy0;
+                    for (int c = 0; c < 2; ++c) {
+                        wv[c] += W[c][k] * p;
+                        gw[c][0] += W[c][k] * dx;
+                        gw[c][1] += W[c][k] * dy;
+                        zv[c] += Z[c][k] * p;
+                        gz[c][0] += Z[c][k] * dx;
+                        gz[c][1] += Z[c][k] * dy;
+                    }
+                }
+                double g[2];
+                for (int c = 0; c < 2; ++c)
+                    g[c] = wv[0] * gw[c][0] + wv[1] * gw[c][1] + (zv[0] * gw[c][0] + zv[1] * gw[c][1] + wv[0] * gz[c][0] + wv[1] * gz[c][1]);
+#pragma unroll
+                for (int l = 0; l < 6; ++l) {
+                    const double wt = c_ref.w[q] * c_ref.phi[q][l];
+                    for (int c = 0; c < 2; ++c) CN[l][c] += wt * g[c];
+                }
+            }
+            for (int l = 0; l < 6; ++l) { CN[l][0] *= h; CN[l][1] *= h; }
+        }
+        for (int l = 0; l < 6; ++l)
+            for (int c = 0; c < 2; ++c) {
+                double m = 0.0, sv = 0.0, bt = 0.0;
+                for (int k = 0; k < 6; ++k) {
+                    m += c_ref.Me[t][l][k] * O[c][k];
+                    for (int d = 0; d < 2; ++d) sv += c_ref.Se[t][c * 6 + l][d * 6 + k] * Y[d][k];
+                }
+                for (int v = 0; v < 3; ++v) bt += c_ref.Be[t][v][c * 6 + l] * P[v];
+                cv[e][l][c] = edt * h2 * m - nue * sv - eta * CN[l][c] + eta * h * bt;
+            }
+        for (int v = 0; v < 3; ++v) {
+            double sv = 0.0;
+            for (int d = 0; d < 2; ++d)
+                for (int k = 0; k < 6; ++k) sv += c_ref.Be[t][v][d * 6 + k] * Y[d][k];
+            cp[e][v] = -eta * h * sv;
+        }
+    }
+    __syncthreads();
+    const int a0 = 2 * RT * tx, a1 = tx == ntx - 1 ? 2 * S.cx : 2 * RT * (tx + 1) - 1;
+    const int b0 = 2 * RT * ty, b1 = ty == nty - 1 ? 2 * S.cy : 2 * RT * (ty + 1) - 1;
+    const int wa = a1 - a0 + 1, cnt = wa * (b1 - b0 + 1);
+    double *en = A.e_new + S.e2_off;
+    for (int idx = tid; idx < cnt; idx += blockDim.x) {
+        const int a = a0 + idx % wa, b = b0 + idx / wa;
+        const int q = a + S.lw2 * b;
+        const long long G = (2 * S.x0 + a) + (long long)ng * (2 * S.y0 + b);
+        const int cls = A.cls2[S.node_off + q];
+        const bool vertex = !(a & 1) && !(b & 1);
+        const int vq = vertex ? (a >> 1) + S.lw1 * (b >> 1) : -1;
+        const bool prow = vertex && A.cls1[S.vert_off + vq] == 0;
+        if (cls != 0)
+            for (int c = 0; c < 2; ++c) en[(long long)c * nloc + q] = oseen_z(S, A, c, q, G);
+        if (vertex && !prow) A.e_new1[S.e1_off + vq] = 0.0;
+        if (cls != 0 && !prow) continue;
+        double rv[2] = {0.0, 0.0}, rq = 0.0;
+        if (cls == 0)
+            for (int c = 0; c < 2; ++c)
+                rv[c] = eta * (A.load[c][0][G] * A.tf[0] + A.load[c][1][G] * A.tf[1] + A.load[c][2][G] * A.tf[2]);
+        for_elements(a, b, S.cx, S.cy, [&](int t, int ci, int cj, int la) {
+            const int e = 2 * ((ci - ci_lo) + (RT + 1) * (cj - cj_lo)) + t;
+            if (cls == 0) { rv[0] += cv[e][la][0]; rv[1] += cv[e][la][1]; }
+            if (prow) rq += cp[e][p1_local(t, (a >> 1) - ci, (b >> 1) - cj)];
+        });
+        // Gamma edges (conduit bottom row): Beavers-Joseph on the x rows and the
+        // lagged p_F^n terms -(eta/rho) int p_F v.n_c - c_tau int d_x p_F v_x
+        if (cls == 0 && S.gamma && 2 * S.y0 + b == 0) {
+            const int A0 = 2 * S.x0 + a;
+            const int ne = (A0 & 1) ? 1 : 2;
+            for (int e2 = 0; e2 < ne; ++e2) {
+                const int ie = (A0 & 1) ? (A0 >> 1) : (A0 >> 1) - 1 + e2;
+                if (ie < S.x0 || ie >= S.x0 + S.cx) continue;
+                const int lg = A0 - 2 * ie;
+                double bj = 0.0, pg = 0.0, pgx = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    const int qk = (2 * ie + k - 2 * S.x0);     // box-local, row 0
+                    const long long Gk = 2 * ie + k;           // grid conduit row 0
+                    bj += c_ref.Ge[lg][k] * (A.W1[0][Gk] + oseen_z(S, A, 0, qk, Gk));
+                    const double pf = A.PF0[(2 * ie + k) + (long long)ng * (2 * S.N)];   // porous top row
+                    pg += c_ref.Ge[lg][k] * pf;
+                    pgx += c_ref.Gxe[lg][k] * pf;
+                }
+                rv[0] -= eta * c_co.beta * h * bj + c_co.ctau * pgx;
+                rv[1] += eta / c_co.rho * h * pg;
+            }
+        }
+        if (cls == 0) {
+            const int d = A.dof2[S.node_off + q];
+            A.b[S.dof_off + d] = rv[0];
+            A.b[S.dof_off + d + 1] = rv[1];
+        }
+        if (prow) A.b[S.dof_off + A.dof1[S.vert_off + vq]] = rq;
+    }
+}
+
 // Jacobian rows of a few large-lattice Oseen systems (the coarse Navier-Stokes
 // Jacobian: one system of a few hundred nodes, where one thread per node leaves
 // the GPU idle).  One wavefront per lattice node: lane 8 e + s takes triangle
@@ -2348,6 +2491,9 @@ void launch_oseen_rows(const OseenApplyArgs<T> &a, int nsys, int maxnodes, int m
 }
 void launch_oseen_residual(const OseenApplyArgs<double> &a, int nsys, int maxnodes, hipStream_t st) {
     hipLaunchKernelGGL((k_oseen_apply<double, 0>), dim3(node_blocks(maxnodes), nsys), dim3(GB), 0, st, a);
+}
+void launch_oseen_rhs_tiled(const OseenArgs &a, int nsys, int maxtiles, hipStream_t st) {
+    hipLaunchKernelGGL(k_oseen_rhs_tiled, dim3(maxtiles > 0 ? maxtiles : 1, nsys), dim3(256), 0, st, a);
 }
 void launch_oseen_residual_tiled(const OseenApplyArgs<double> &a, int nsys, int maxtiles, hipStream_t st) {
     hipLaunchKernelGGL(k_oseen_residual_tiled, dim3(maxtiles > 0 ? maxtiles : 1, nsys), dim3(256), 0, st, a);
