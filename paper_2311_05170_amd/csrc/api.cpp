@@ -117,7 +117,7 @@ struct lp_ctx {
     int maxbw_por = 0, maxbw_ose = 0, maxn_por = 0, maxn_ose = 0;
     // largest local P2 lattice per batch (node blocks of the gather kernels)
     int nodes_por = 0, nodes_ose = 0, nodes_cpor = 0, nodes_cns = 0;
-    int tiles_ose = 0;                 // most residual tiles of a local Oseen box
+    int tiles_ose = 0, tiles_por = 0;  // most residual tiles of a local Oseen / porous box
     // residual norm partials and arrival counters, one set per batch (the
     // batches run on different streams)
     double *part_por = nullptr, *part_ose = nullptr, *part_cp = nullptr, *part_cn = nullptr;
@@ -328,7 +328,7 @@ lp_status refine_porous(lp_ctx *c, const lp::SysDesc *d_sys, int nsys, int maxno
         }
         StageTimer tm(c, timed ? LP_T_POR_RES : -1, st);
         lp::ResidualArgs ra{d_sys, c->d_dof2, x, b, r, conv, rel, sw, tol, nullptr, part, ticket};
-        lp::launch_porous_residual(ra, nsys, maxnodes, st);
+        lp::launch_porous_residual_tiled(ra, nsys, c->tiles_por, st);
     }
     return LP_OK;
 }
@@ -603,7 +603,10 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
         c->maxn_ose = std::max(c->maxn_ose, s.ndof);
         c->tiles_ose = std::max(c->tiles_ose, lp::residual_tiles(s.cx, s.cy));
     }
-    for (const auto &s : P.por) c->nodes_por = std::max(c->nodes_por, s.lw2 * s.lh2);
+    for (const auto &s : P.por) {
+        c->nodes_por = std::max(c->nodes_por, s.lw2 * s.lh2);
+        c->tiles_por = std::max(c->tiles_por, lp::residual_tiles(s.cx, s.cy));
+    }
     for (const auto &s : P.ose) c->nodes_ose = std::max(c->nodes_ose, s.lw2 * s.lh2);
     c->nodes_cpor = P.cpor.lw2 * P.cpor.lh2;
     c->nodes_cns = P.cns.lw2 * P.cns.lh2;
@@ -756,7 +759,7 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     TRY(c->dalloc(&c->conv_cn, 1)); TRY(c->dalloc(&c->rel_cn, 1)); TRY(c->dalloc(&c->sw_cn, 1));
     {
         auto nb = [](int nodes) { return (long long)lp::node_blocks(nodes); };
-        TRY(c->dalloc(&c->part_por, 2 * npf * nb(c->nodes_por))); TRY(c->dalloc(&c->tick_por, npf));
+        TRY(c->dalloc(&c->part_por, 2 * npf * std::max<long long>(nb(c->nodes_por), c->tiles_por))); TRY(c->dalloc(&c->tick_por, npf));
         TRY(c->dalloc(&c->part_ose, 2 * nof * std::max<long long>(nb(c->nodes_ose), c->tiles_ose))); TRY(c->dalloc(&c->tick_ose, nof));
         TRY(c->dalloc(&c->part_cp, 2 * 3 * nb(c->nodes_cpor))); TRY(c->dalloc(&c->tick_cp, 3));
         TRY(c->dalloc(&c->part_cn, 2 * nb(c->nodes_cns))); TRY(c->dalloc(&c->tick_cn, 1));

@@ -1055,6 +1055,77 @@ __global__ __launch_bounds__(256) void k_oseen_rhs_tiled(OseenArgs A) {
     }
 }
 
+// Porous residuals of the three fields by the same tiles of cells: each
+// triangle's contributions to its six rows once into LDS, the node threads
+// add their triangles in the node-thread order.  A converged field is left
+// alone; blocks past a box's tile count only take part in the reductions.
+__global__ __launch_bounds__(256) void k_porous_residual_tiled(ResidualArgs R) {
+    const SysDesc S = R.sys[blockIdx.y];
+    if (R.skip && *R.skip) return;
+    const int id0 = blockIdx.y * 3;
+    bool act[3];
+    for (int f = 0; f < 3; ++f) act[f] = !R.conv[id0 + f];
+    if (!act[0] && !act[1] && !act[2]) return;
+    const int ntx = (S.cx + RT - 1) / RT, nty = (S.cy + RT - 1) / RT;
+    const bool has = (int)blockIdx.x < ntx * nty;
+    const int tx = has ? (int)blockIdx.x % ntx : 0, ty = has ? (int)blockIdx.x / ntx : 0;
+    const int ci_lo = tx * RT - 1, cj_lo = ty * RT - 1;
+    const double h2 = S.h * S.h;
+    double cm[3], ck[3];
+    for (int f = 0; f < 3; ++f) { cm[f] = (c_co.tau[f] + porous_x(f)) * h2; ck[f] = c_co.kap[f]; }
+    const double *x = R.x + S.dof_off, *b = R.b + S.dof_off;
+    double *r = R.r + S.dof_off;
+    const long long nd = S.ndof;
+    __shared__ double cy[RT_TRI][6][3];     // (triangle, its node la, field)
+    const int tid = threadIdx.x;
+    if (has) {
+        for (int e = tid; e < RT_TRI; e += blockDim.x) {
+            const int t = e & 1, cc = e >> 1;
+            const int ci = ci_lo + cc % (RT + 1), cj = cj_lo + cc / (RT + 1);
+            if (ci < 0 || cj < 0 || ci >= S.cx || cj >= S.cy) continue;
+            double X[3][6];
+            for (int k = 0; k < 6; ++k) {
+                const int dk = R.dof2[S.node_off + (2 * ci + off2a(t, k)) + S.lw2 * (2 * cj + off2b(t, k))];
+                for (int f = 0; f < 3; ++f) X[f][k] = dk >= 0 && act[f] ? x[f * nd + dk] : 0.0;
+            }
+            for (int l = 0; l < 6; ++l) {
+                double y[3] = {0.0, 0.0, 0.0};
+                for (int k = 0; k < 6; ++k) {
+                    const double me = c_ref.Me[t][l][k], ke = c_ref.Ke[t][l][k];
+                    for (int f = 0; f < 3; ++f) y[f] += (cm[f] * me + ck[f] * ke) * X[f][k];
+                }
+                for (int f = 0; f < 3; ++f) cy[e][l][f] = y[f];
+            }
+        }
+    }
+    __syncthreads();
+    double rr[3] = {0.0, 0.0, 0.0}, bb[3] = {0.0, 0.0, 0.0};
+    if (has) {
+        const int a0 = 2 * RT * tx, a1 = tx == ntx - 1 ? 2 * S.cx : 2 * RT * (tx + 1) - 1;
+        const int b0 = 2 * RT * ty, b1 = ty == nty - 1 ? 2 * S.cy : 2 * RT * (ty + 1) - 1;
+        const int wa = a1 - a0 + 1, cnt = wa * (b1 - b0 + 1);
+        for (int idx = tid; idx < cnt; idx += blockDim.x) {
+            const int a = a0 + idx % wa, bq = b0 + idx / wa;
+            const int dq = R.dof2[S.node_off + a + S.lw2 * bq];
+            if (dq < 0) continue;
+            double y[3] = {0.0, 0.0, 0.0};
+            for_elements(a, bq, S.cx, S.cy, [&](int t, int ci, int cj, int la) {
+                const int e = 2 * ((ci - ci_lo) + (RT + 1) * (cj - cj_lo)) + t;
+                for (int f = 0; f < 3; ++f) y[f] += cy[e][la][f];
+            });
+            for (int f = 0; f < 3; ++f) {
+                if (!act[f]) continue;
+                const double bv = b[f * nd + dq], rv = bv - y[f];
+                r[f * nd + dq] = rv;
+                rr[f] += rv * rv;
+                bb[f] += bv * bv;
+            }
+        }
+    }
+    for (int f = 0; f < 3; ++f)
+        if (act[f]) grid_norms_and_flag(rr[f], bb[f], R.part, R.ticket, R.conv, R.relres, R.sweeps, R.tol, id0 + f);
+}
+
 // Jacobian rows of a few large-lattice Oseen systems (the coarse Navier-Stokes
 // Jacobian: one system of a few hundred nodes, where one thread per node leaves
 // the GPU idle).  One wavefront per lattice node: lane 8 e + s takes triangle
@@ -2466,6 +2537,9 @@ int node_blocks(int maxnodes) { return maxnodes > 0 ? (maxnodes + GB - 1) / GB :
 void launch_porous_rhs(const PorousArgs &a, int nsys, int maxnodes, int split, hipStream_t st) {
     if (split == 8) hipLaunchKernelGGL((k_porous_rhs<8>), dim3(node_blocks(8 * maxnodes), nsys), dim3(GB), 0, st, a);
     else hipLaunchKernelGGL((k_porous_rhs<1>), dim3(node_blocks(maxnodes), nsys), dim3(GB), 0, st, a);
+}
+void launch_porous_residual_tiled(const ResidualArgs &a, int nsys, int maxtiles, hipStream_t st) {
+    hipLaunchKernelGGL(k_porous_residual_tiled, dim3(maxtiles > 0 ? maxtiles : 1, nsys), dim3(256), 0, st, a);
 }
 void launch_porous_residual(const ResidualArgs &a, int nsys, int maxnodes, hipStream_t st) {
     hipLaunchKernelGGL(k_porous_residual, dim3(node_blocks(maxnodes), nsys), dim3(GB), 0, st, a);
