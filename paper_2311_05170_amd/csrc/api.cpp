@@ -484,7 +484,7 @@ lp_status local_porous(lp_ctx *c, const double *pro, hipStream_t st) {
     pa.tf[0] = std::cos(t1); pa.tf[1] = std::sin(t1); pa.tf[2] = pa.tf[0] * pa.tf[0];
     {
         StageTimer tm(c, LP_T_POR_RHS, st);
-        lp::launch_porous_rhs(pa, nsys, c->nodes_por, 1, st);
+        lp::launch_porous_rhs_tiled(pa, nsys, c->tiles_por, st);
     }
     TRY(refine_porous<T>(c, c->d_por, nsys, c->nodes_por, c->part_por, c->tick_por, c->d_sv_por, (const T *)c->fac_por, c->maxbw_por, c->maxn_por, c->b_por,
                          c->x_por, c->r_por, c->conv_por, c->rel_por, c->sw_por, c->P.dof_total_por, c->opt.max_ir,

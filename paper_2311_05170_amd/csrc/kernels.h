@@ -263,6 +263,8 @@ void launch_oseen_residual_tiled(const OseenApplyArgs<double> &a, int nsys, int 
 void launch_oseen_rhs_tiled(const OseenArgs &a, int nsys, int maxtiles, hipStream_t st);
 // porous residuals (three fields) by the same tiles; partials as the Oseen one
 void launch_porous_residual_tiled(const ResidualArgs &a, int nsys, int maxtiles, hipStream_t st);
+// local porous right-hand sides by the same tiles
+void launch_porous_rhs_tiled(const PorousArgs &a, int nsys, int maxtiles, hipStream_t st);
 void launch_oseen_finalize(const FinalizeArgs &a, int nsys, int maxnodes, hipStream_t st);
 template <typename T>
 bool launch_band_lu(const BandArgs<T> &a, int nsys, int maxbw, int variant, hipStream_t st);

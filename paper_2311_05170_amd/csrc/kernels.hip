@@ -1126,6 +1126,93 @@ __global__ __launch_bounds__(256) void k_porous_residual_tiled(ResidualArgs R) {
         if (act[f]) grid_norms_and_flag(rr[f], bb[f], R.part, R.ticket, R.conv, R.relres, R.sweeps, R.tol, id0 + f);
 }
 
+// Local porous right-hand sides by the same tiles: each triangle's mass and
+// stiffness contributions to its six rows (three fields) once into LDS, then
+// the node threads (Dirichlet values, sources, the Gamma term) add their
+// triangles in the node-thread order.
+__global__ __launch_bounds__(256) void k_porous_rhs_tiled(PorousArgs A) {
+    const SysDesc S = A.sys[blockIdx.y];
+    const int ntx = (S.cx + RT - 1) / RT, nty = (S.cy + RT - 1) / RT;
+    if ((int)blockIdx.x >= ntx * nty) return;
+    const int tx = (int)blockIdx.x % ntx, ty = (int)blockIdx.x / ntx;
+    const int ci_lo = tx * RT - 1, cj_lo = ty * RT - 1;
+    const int nloc = S.lw2 * S.lh2;
+    const int ng = 2 * S.N + 1;
+    const double h = S.h, h2 = h * h;
+    __shared__ double cr[RT_TRI][6][3];     // (triangle, its node la, field)
+    const int tid = threadIdx.x;
+    for (int e = tid; e < RT_TRI; e += blockDim.x) {
+        const int t = e & 1, cc = e >> 1;
+        const int ci = ci_lo + cc % (RT + 1), cj = cj_lo + cc / (RT + 1);
+        if (ci < 0 || cj < 0 || ci >= S.cx || cj >= S.cy) continue;
+        double M3[3][6], X3[3][6];      // mass-term and stiffness-term nodal values per field
+        for (int k = 0; k < 6; ++k) {
+            const int qa = 2 * ci + off2a(t, k), qb = 2 * cj + off2b(t, k);
+            const int qk = qa + S.lw2 * qb;
+            const long long Gk = (2 * S.x0 + qa) + (long long)ng * (2 * S.y0 + qb);
+            const bool dir = A.cls2[S.node_off + qk] == 1;
+            double O[3], X[3];
+            for (int g = 0; g < 3; ++g) {
+                const double p1 = A.P1[g] ? A.P1[g][Gk] : 0.0;
+                O[g] = (A.P0[g] ? A.P0[g][Gk] : 0.0) + A.e_old[S.e2_off + (long long)g * nloc + qk];
+                X[g] = p1 + (dir ? A.ex[g][Gk] * A.tf[0] - p1 : 0.0);
+            }
+            for (int f = 0; f < 3; ++f) {
+                double m = c_co.tau[f] * (O[f] - X[f]) - porous_x(f) * X[f];
+                if (f == 0) m += c_co.sst * O[1];
+                if (f == 1) m += c_co.s * O[2] + c_co.sst * O[0];
+                if (f == 2) m += c_co.s * O[1];
+                M3[f][k] = m;
+                X3[f][k] = X[f];
+            }
+        }
+        for (int l = 0; l < 6; ++l) {
+            double mv[3] = {0.0, 0.0, 0.0}, kv[3] = {0.0, 0.0, 0.0};
+            for (int k = 0; k < 6; ++k) {
+                const double me = c_ref.Me[t][l][k], ke = c_ref.Ke[t][l][k];
+                for (int f = 0; f < 3; ++f) { mv[f] += me * M3[f][k]; kv[f] += ke * X3[f][k]; }
+            }
+            for (int f = 0; f < 3; ++f) cr[e][l][f] = h2 * mv[f] - c_co.kap[f] * kv[f];
+        }
+    }
+    __syncthreads();
+    const int a0 = 2 * RT * tx, a1 = tx == ntx - 1 ? 2 * S.cx : 2 * RT * (tx + 1) - 1;
+    const int b0 = 2 * RT * ty, b1 = ty == nty - 1 ? 2 * S.cy : 2 * RT * (ty + 1) - 1;
+    const int wa = a1 - a0 + 1, cnt = wa * (b1 - b0 + 1);
+    for (int idx = tid; idx < cnt; idx += blockDim.x) {
+        const int a = a0 + idx % wa, b = b0 + idx / wa;
+        const int q = a + S.lw2 * b;
+        const long long G = (2 * S.x0 + a) + (long long)ng * (2 * S.y0 + b);
+        const int cls = A.cls2[S.node_off + q];
+        if (cls != 0) {
+            for (int f = 0; f < 3; ++f) A.e_new[S.e2_off + (long long)f * nloc + q] = porous_z(S, A, f, q, G);
+            continue;
+        }
+        // sources at t_{n+1}
+        double r[3];
+        for (int f = 0; f < 3; ++f) r[f] = A.load[f][0][G] * A.tf[0] + A.load[f][1][G] * A.tf[1];
+        for_elements(a, b, S.cx, S.cy, [&](int t, int ci, int cj, int la) {
+            const int e = 2 * ((ci - ci_lo) + (RT + 1) * (cj - cj_lo)) + t;
+            for (int f = 0; f < 3; ++f) r[f] += cr[e][la][f];
+        });
+        // + <u^n . n_c, v_F>_Gamma = -int_Gamma v_F u_y^n on the porous top row
+        if (S.gamma && 2 * S.y0 + b == 2 * S.N && A.Uy0) {
+            const int A0 = 2 * S.x0 + a;
+            const int ne = (A0 & 1) ? 1 : 2;
+            for (int e2 = 0; e2 < ne; ++e2) {
+                const int ie = (A0 & 1) ? (A0 >> 1) : (A0 >> 1) - 1 + e2;
+                if (ie < S.x0 || ie >= S.x0 + S.cx) continue;
+                const int lg = A0 - 2 * ie;
+                double sg = 0.0;
+                for (int k = 0; k < 3; ++k) sg += c_ref.Ge[lg][k] * A.Uy0[2 * ie + k];   // conduit Gamma row b = 0
+                r[0] -= h * sg;
+            }
+        }
+        const int d = A.dof2[S.node_off + q];
+        for (int f = 0; f < 3; ++f) A.b[S.dof_off + (long long)f * S.ndof + d] = r[f];
+    }
+}
+
 // Jacobian rows of a few large-lattice Oseen systems (the coarse Navier-Stokes
 // Jacobian: one system of a few hundred nodes, where one thread per node leaves
 // the GPU idle).  One wavefront per lattice node: lane 8 e + s takes triangle
@@ -2537,6 +2624,9 @@ int node_blocks(int maxnodes) { return maxnodes > 0 ? (maxnodes + GB - 1) / GB :
 void launch_porous_rhs(const PorousArgs &a, int nsys, int maxnodes, int split, hipStream_t st) {
     if (split == 8) hipLaunchKernelGGL((k_porous_rhs<8>), dim3(node_blocks(8 * maxnodes), nsys), dim3(GB), 0, st, a);
     else hipLaunchKernelGGL((k_porous_rhs<1>), dim3(node_blocks(maxnodes), nsys), dim3(GB), 0, st, a);
+}
+void launch_porous_rhs_tiled(const PorousArgs &a, int nsys, int maxtiles, hipStream_t st) {
+    hipLaunchKernelGGL(k_porous_rhs_tiled, dim3(maxtiles > 0 ? maxtiles : 1, nsys), dim3(256), 0, st, a);
 }
 void launch_porous_residual_tiled(const ResidualArgs &a, int nsys, int maxtiles, hipStream_t st) {
     hipLaunchKernelGGL(k_porous_residual_tiled, dim3(maxtiles > 0 ? maxtiles : 1, nsys), dim3(256), 0, st, a);
