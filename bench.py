@@ -55,7 +55,7 @@ MAX_NEWTON = 10
 JACOBIAN_EVERY = 3
 # refinement sweeps launched per local step in the mixed path (each skips once
 # its system has converged; two reach the 1e-10 tolerance on this workload)
-MAX_IR_MIXED = 3
+MAX_IR_MIXED = 2
 
 
 def make(cfg, precision, max_ir):

@@ -495,25 +495,32 @@ lp_status local_porous(lp_ctx *c, const double *pro, hipStream_t st) {
     return LP_OK;
 }
 
-void prolong_all(lp_ctx *c, int cnew, int cold, hipStream_t st) {
+// The coarse fields the local Oseen stage reads, prolonged: u^(n+1), u^n, p_F^n
+// (its Gamma terms) on the P2 lattice, p^(n+1) on P1.  At setup (all) also the
+// three porous pressures of both levels, for the initial corrections; per step
+// the porous batch prolongs its own inputs.
+void prolong_all(lp_ctx *c, int cnew, int cold, hipStream_t st, bool all = false) {
     const long long nc2 = c->nc2, nf2 = c->nf2;
     lp::ProlongArgs pa{};
     pa.NH = c->P.NH; pa.Nh = c->P.Nh; pa.k = c->P.k;
-    pa.nfields = 6;
-    for (int f = 0; f < 3; ++f) {
-        pa.src[f] = c->cP[cnew] + f * nc2;
-        pa.dst[f] = c->pro_P1 + f * nf2;
-        pa.src[3 + f] = c->cP[cold] + f * nc2;
-        pa.dst[3 + f] = c->pro_P0 + f * nf2;
+    if (all) {
+        pa.nfields = 6;
+        for (int f = 0; f < 3; ++f) {
+            pa.src[f] = c->cP[cnew] + f * nc2;
+            pa.dst[f] = c->pro_P1 + f * nf2;
+            pa.src[3 + f] = c->cP[cold] + f * nc2;
+            pa.dst[3 + f] = c->pro_P0 + f * nf2;
+        }
+        lp::launch_prolong_p2(pa, st);
     }
-    lp::launch_prolong_p2(pa, st);
-    pa.nfields = 4;
+    pa.nfields = all ? 4 : 5;
     for (int cc = 0; cc < 2; ++cc) {
         pa.src[cc] = c->cU[cnew] + cc * nc2;
         pa.dst[cc] = c->pro_U1 + cc * nf2;
         pa.src[2 + cc] = c->cU[cold] + cc * nc2;
         pa.dst[2 + cc] = c->pro_U0 + cc * nf2;
     }
+    if (!all) { pa.src[4] = c->cP[cold]; pa.dst[4] = c->pro_P0; }
     lp::launch_prolong_p2(pa, st);
     pa.nfields = 1;
     pa.src[0] = c->cp[cnew];
@@ -793,7 +800,7 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
         HIPCHK(hipEventCreateWithFlags(&c->ev_local[i], hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&c->ev_cpor[i], hipEventDisableTiming));
     }
-    prolong_all(c.get(), 0, 0, st);
+    prolong_all(c.get(), 0, 0, st, true);
     {
         lp::InitArgs ia{};
         ia.sys = c->d_por; ia.cls2 = c->d_cls2;
