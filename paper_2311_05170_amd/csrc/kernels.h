@@ -241,7 +241,6 @@ void launch_prolong_p1(const ProlongArgs &a, hipStream_t st);
 constexpr int GB = 128;
 int node_blocks(int maxnodes);
 void launch_porous_rhs(const PorousArgs &a, int nsys, int maxnodes, int split, hipStream_t st);   // split 1 or 8 lanes per node
-void launch_porous_residual(const ResidualArgs &a, int nsys, int maxnodes, hipStream_t st);
 void launch_porous_finalize(const FinalizeArgs &a, int nsys, int maxnodes, hipStream_t st);
 template <typename T>
 void launch_porous_assemble(const AssembleArgs<T> &a, int nsys, hipStream_t st);
@@ -253,7 +252,6 @@ void launch_oseen_assemble(const OseenApplyArgs<T> &a, int nsys, int maxnodes, h
 // node, whole rows stored (no clearing needed); LDS 3 (2 maxbw + 1) entries
 template <typename T>
 void launch_oseen_rows(const OseenApplyArgs<T> &a, int nsys, int maxnodes, int maxbw, hipStream_t st);
-void launch_oseen_residual(const OseenApplyArgs<double> &a, int nsys, int maxnodes, hipStream_t st);
 // the same residual by tiles of 8 x 8 cells (each triangle integrated once);
 // maxtiles = max over the systems of residual_tiles(cx, cy); its norm partials
 // take 2 maxtiles doubles per system

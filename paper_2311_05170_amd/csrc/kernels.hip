@@ -1,14 +1,16 @@
 // HIP kernels of the local parallel stage (gfx950).
 //
 // Every local problem lives on a box of one grid (a subdomain Omega_j of T_h,
-// or a whole region of T_H for the coarse step).  Element work is done by
-// gather: one thread per local lattice node loops over the (at most six)
-// triangles of the box that contain the node and accumulates its own rows,
-// so results are deterministic without atomics (the single coarse Jacobian
-// takes one wavefront per node instead, the lanes splitting the triangles).  Linear systems are banded
-// (lattice-row ordering) and factored without pivoting by one workgroup per
-// system with the active window held in registers; triangular solves run one
-// wavefront per right-hand side.
+// or a whole region of T_H for the coarse step).  Element work never scatters:
+// either a node gathers its rows from the (at most six) triangles around it
+// (one thread per node for the band assembly, eight lanes per node or one
+// wavefront per node on the single coarse system), or a workgroup integrates
+// the triangles of a tile of cells once into LDS and its node threads gather
+// from there (the local right-hand sides and residuals).  A node always adds
+// its triangles in the same order, so results are deterministic without
+// atomics.  Linear systems are banded (lattice-row ordering) and factored
+// without pivoting by one workgroup per system with the active window held in
+// registers; triangular solves run one wavefront per right-hand side.
 #include <hip/hip_runtime.h>
 #include <type_traits>
 #include <utility>
@@ -303,50 +305,6 @@ __device__ void grid_norms_and_flag(double rr, double bb, double *part, int *tic
 }
 
 // y = A_f x restricted to free rows (FP64, matrix-free); r = b - y; norms
-// The three fields of a system in one pass (each node's triangles and their
-// degrees of freedom read once); a converged field is left alone.
-__global__ __launch_bounds__(GB) void k_porous_residual(ResidualArgs R) {
-    const SysDesc S = R.sys[blockIdx.y];
-    if (R.skip && *R.skip) return;
-    const int id0 = blockIdx.y * 3;
-    bool act[3];
-    for (int f = 0; f < 3; ++f) act[f] = !R.conv[id0 + f];
-    if (!act[0] && !act[1] && !act[2]) return;
-    const int nloc = S.lw2 * S.lh2;
-    const double h2 = S.h * S.h;
-    double cm[3], ck[3];
-    for (int f = 0; f < 3; ++f) { cm[f] = (c_co.tau[f] + porous_x(f)) * h2; ck[f] = c_co.kap[f]; }
-    const double *x = R.x + S.dof_off, *b = R.b + S.dof_off;
-    double *r = R.r + S.dof_off;
-    const long long nd = S.ndof;
-    double rr[3] = {0.0, 0.0, 0.0}, bb[3] = {0.0, 0.0, 0.0};
-    for (int q = blockIdx.x * GB + threadIdx.x; q < nloc; q += gridDim.x * GB) {
-        const int dq = R.dof2[S.node_off + q];
-        if (dq < 0) continue;
-        const int a = q % S.lw2, bq = q / S.lw2;
-        double y[3] = {0.0, 0.0, 0.0};
-        for_elements(a, bq, S.cx, S.cy, [&](int t, int ci, int cj, int la) {
-            for (int k = 0; k < 6; ++k) {
-                const int qk = (2 * ci + off2a(t, k)) + S.lw2 * (2 * cj + off2b(t, k));
-                const int dk = R.dof2[S.node_off + qk];
-                if (dk < 0) continue;
-                const double me = c_ref.Me[t][la][k], ke = c_ref.Ke[t][la][k];
-                for (int f = 0; f < 3; ++f)
-                    if (act[f]) y[f] += (cm[f] * me + ck[f] * ke) * x[f * nd + dk];
-            }
-        });
-        for (int f = 0; f < 3; ++f) {
-            if (!act[f]) continue;
-            const double bv = b[f * nd + dq], rv = bv - y[f];
-            r[f * nd + dq] = rv;
-            rr[f] += rv * rv;
-            bb[f] += bv * bv;
-        }
-    }
-    for (int f = 0; f < 3; ++f)
-        if (act[f]) grid_norms_and_flag(rr[f], bb[f], R.part, R.ticket, R.conv, R.relres, R.sweeps, R.tol, id0 + f);
-}
-
 __device__ __forceinline__ void porous_finalize_rows(const FinalizeArgs &F, const SysDesc &S, int start, int stride) {
     const int nloc = S.lw2 * S.lh2;
     for (int q = start; q < nloc; q += stride) {
@@ -562,21 +520,18 @@ __global__ __launch_bounds__(GB) void k_oseen_rhs(OseenArgs A) {
     }
 }
 
-// Row application of the Oseen operator to x (FP64) or assembly of its band
-// entries (T).  Mode 0: residual r = b - K x.  Mode 1: band assembly.
-template <typename T, int MODE>
-__global__ __launch_bounds__(GB) void k_oseen_apply(OseenApplyArgs<T> A) {
+// Band assembly of the local Oseen operators (T), one thread per node: its
+// rows, added element by element into the cleared band.
+template <typename T>
+__global__ __launch_bounds__(GB) void k_oseen_assemble(OseenApplyArgs<T> A) {
     const SysDesc S = A.sys[blockIdx.y];
     if (A.skip && *A.skip) return;
-    if (MODE == 0 && A.conv[blockIdx.y]) return;
     const int nloc = S.lw2 * S.lh2;
     const int ng = 2 * S.N + 1;
     const double h = S.h, h2 = h * h;
     const double eta = c_co.eta, edt = c_co.eta / c_co.dt, nue = c_co.nu * c_co.eta;
     const int ld = 2 * S.bw + 1;
-    T *band = MODE == 1 ? A.band + S.band_off : nullptr;
-    const double *x = MODE == 0 ? A.x + S.dof_off : nullptr;
-    double rr = 0.0, bb = 0.0;
+    T *band = A.band + S.band_off;
     auto put = [&](int row, int col, double v) {
         T *p = band + (long long)col * ld + (row - col + S.bw);
         *p = (T)((double)*p + v);
@@ -589,38 +544,20 @@ __global__ __launch_bounds__(GB) void k_oseen_apply(OseenApplyArgs<T> A) {
         const int dv = cls == 0 ? A.dof2[S.node_off + q] : -1;
         const int dp = vertex ? A.dof1[S.vert_off + vq] : -1;
         if (dv < 0 && dp < 0) continue;
-        double yv[2] = {0.0, 0.0}, yq = 0.0;
         for_elements(a, b, S.cx, S.cy, [&](int t, int ci, int cj, int la) {
-            double W[2][6], X[2][6];
+            double W[2][6];
             int dk[6], pk[3];
             for (int k = 0; k < 6; ++k) {
                 const int qa = 2 * ci + off2a(t, k), qb = 2 * cj + off2b(t, k);
                 const int qk = qa + S.lw2 * qb;
                 const long long Gk = (2 * S.x0 + qa) + (long long)ng * (2 * S.y0 + qb);
                 dk[k] = A.dof2[S.node_off + qk];
-                for (int c = 0; c < 2; ++c) {
-                    W[c][k] = A.W1[c][Gk];
-                    X[c][k] = (MODE == 0 && dk[k] >= 0) ? x[dk[k] + c] : 0.0;
-                }
+                for (int c = 0; c < 2; ++c) W[c][k] = A.W1[c][Gk];
             }
             for (int k = 0; k < 3; ++k)
                 pk[k] = A.dof1[S.vert_off + (ci + off1a(t, k)) + S.lw1 * (cj + off1b(t, k))];
             if (dv >= 0) {
-                if (MODE == 0) {
-                    double cW[2], Nz[2];
-                    if (c_co.convection) conv_rows(t, la, h, W, X, false, cW, Nz);
-                    else Nz[0] = Nz[1] = 0.0;
-                    for (int c = 0; c < 2; ++c) {
-                        double m = 0.0, s = 0.0, bt = 0.0;
-                        for (int k = 0; k < 6; ++k) {
-                            m += c_ref.Me[t][la][k] * X[c][k];
-                            for (int d = 0; d < 2; ++d) s += c_ref.Se[t][c * 6 + la][d * 6 + k] * X[d][k];
-                        }
-                        for (int v = 0; v < 3; ++v)
-                            if (pk[v] >= 0) bt += c_ref.Be[t][v][c * 6 + la] * x[pk[v]];
-                        yv[c] += edt * h2 * m + nue * s + eta * Nz[c] - eta * h * bt;
-                    }
-                } else {
+                {
                     // entries of rows (la, c) against columns (k, d) and pressure v
                     double Nw[2][2][6];     // [c][d][k]
                     for (int c = 0; c < 2; ++c) for (int d = 0; d < 2; ++d) for (int k = 0; k < 6; ++k) Nw[c][d][k] = 0.0;
@@ -699,12 +636,7 @@ __global__ __launch_bounds__(GB) void k_oseen_apply(OseenApplyArgs<T> A) {
             }
             if (dp >= 0) {
                 const int lv = p1_local(t, (a >> 1) - ci, (b >> 1) - cj);
-                if (MODE == 0) {
-                    double s = 0.0;
-                    for (int d = 0; d < 2; ++d)
-                        for (int k = 0; k < 6; ++k) s += c_ref.Be[t][lv][d * 6 + k] * X[d][k];
-                    yq += eta * h * s;
-                } else {
+                {
                     int off[12];
                     T old[12];
 #pragma unroll
@@ -738,30 +670,11 @@ __global__ __launch_bounds__(GB) void k_oseen_apply(OseenApplyArgs<T> A) {
                     const int dk = A.dof2[S.node_off + qk];
                     if (dk < 0) continue;
                     const double v = eta * c_co.beta * h * c_ref.Ge[la][k];
-                    if (MODE == 0) yv[0] += v * x[dk];
-                    else put(dv, dk, v);
+                    put(dv, dk, v);
                 }
-            }
-        }
-        if (MODE == 0) {
-            if (dv >= 0)
-                for (int c = 0; c < 2; ++c) {
-                    const double bv = A.b[S.dof_off + dv + c];
-                    const double rv = bv - yv[c];
-                    A.r[S.dof_off + dv + c] = rv;
-                    rr += rv * rv;
-                    bb += bv * bv;
-                }
-            if (dp >= 0) {
-                const double bv = A.b[S.dof_off + dp];
-                const double rv = bv - yq;
-                A.r[S.dof_off + dp] = rv;
-                rr += rv * rv;
-                bb += bv * bv;
             }
         }
     }
-    if (MODE == 0) grid_norms_and_flag(rr, bb, A.part, A.ticket, A.conv, A.relres, A.sweeps, A.tol, blockIdx.y);
 }
 
 // Oseen residual r = b - K x (FP64) by tiles of RT x RT cells of a box: each
@@ -2631,9 +2544,6 @@ void launch_porous_rhs_tiled(const PorousArgs &a, int nsys, int maxtiles, hipStr
 void launch_porous_residual_tiled(const ResidualArgs &a, int nsys, int maxtiles, hipStream_t st) {
     hipLaunchKernelGGL(k_porous_residual_tiled, dim3(maxtiles > 0 ? maxtiles : 1, nsys), dim3(256), 0, st, a);
 }
-void launch_porous_residual(const ResidualArgs &a, int nsys, int maxnodes, hipStream_t st) {
-    hipLaunchKernelGGL(k_porous_residual, dim3(node_blocks(maxnodes), nsys), dim3(GB), 0, st, a);
-}
 void launch_porous_finalize(const FinalizeArgs &a, int nsys, int maxnodes, hipStream_t st) {
     hipLaunchKernelGGL(k_porous_finalize, dim3(node_blocks(maxnodes), nsys), dim3(GB), 0, st, a);
 }
@@ -2647,14 +2557,11 @@ void launch_oseen_rhs(const OseenArgs &a, int nsys, int maxnodes, int split, hip
 }
 template <typename T>
 void launch_oseen_assemble(const OseenApplyArgs<T> &a, int nsys, int maxnodes, hipStream_t st) {
-    hipLaunchKernelGGL((k_oseen_apply<T, 1>), dim3(node_blocks(maxnodes), nsys), dim3(GB), 0, st, a);
+    hipLaunchKernelGGL((k_oseen_assemble<T>), dim3(node_blocks(maxnodes), nsys), dim3(GB), 0, st, a);
 }
 template <typename T>
 void launch_oseen_rows(const OseenApplyArgs<T> &a, int nsys, int maxnodes, int maxbw, hipStream_t st) {
     hipLaunchKernelGGL((k_oseen_rows<T>), dim3(maxnodes, nsys), dim3(64), 3 * (2 * maxbw + 1) * sizeof(T), st, a);
-}
-void launch_oseen_residual(const OseenApplyArgs<double> &a, int nsys, int maxnodes, hipStream_t st) {
-    hipLaunchKernelGGL((k_oseen_apply<double, 0>), dim3(node_blocks(maxnodes), nsys), dim3(GB), 0, st, a);
 }
 void launch_oseen_rhs_tiled(const OseenArgs &a, int nsys, int maxtiles, hipStream_t st) {
     hipLaunchKernelGGL(k_oseen_rhs_tiled, dim3(maxtiles > 0 ? maxtiles : 1, nsys), dim3(256), 0, st, a);
