@@ -318,8 +318,7 @@ lp_status refine_porous(lp_ctx *c, const lp::SysDesc *d_sys, int nsys, int maxno
                         const lp::BandSys *d_sv, const T *fac, int maxbw, int maxn, double *b, double *x, double *r,
                         int *conv, double *rel, int *sw, long long ndof, int sweeps, double tol, bool timed,
                         hipStream_t st) {
-    lp::IrStartArgs ia{x, r, b, ndof, conv, rel, sw, 3LL * nsys};
-    lp::launch_ir_start(ia, st);
+    // x = 0, r = b and the flags were set by the right-hand side kernel
     for (int s = 0; s < sweeps; ++s) {
         {
             StageTimer tm(c, timed ? LP_T_POR_SOLVE : -1, st);
@@ -338,8 +337,7 @@ lp_status refine_oseen(lp_ctx *c, const lp::SysDesc *d_sys, int nsys, int maxnod
                        const lp::BandSys *d_sv, const T *fac, int maxbw, int maxn, const double *W1x, const double *W1y,
                        double *b, double *x, double *r, int *conv, double *rel, int *sw, long long ndof, int sweeps,
                        double tol, const int *skip, bool timed, hipStream_t st) {
-    lp::IrStartArgs ia{x, r, b, ndof, conv, rel, sw, (long long)nsys};
-    lp::launch_ir_start(ia, st);
+    // x = 0, r = b and the flags were set by the right-hand side kernel
     for (int s = 0; s < sweeps; ++s) {
         {
             StageTimer tm(c, timed ? LP_T_OSE_SOLVE : -1, st);
@@ -384,6 +382,7 @@ lp_status local_oseen(lp_ctx *c, hipStream_t st) {
     oa.PF0 = c->pro_P0;
     oa.e_old = c->e2[o]; oa.e_new = c->e2[nw]; oa.e_new1 = c->e1[nw];
     oa.b = c->b_ose;
+    oa.ir = lp::IrStart{c->x_ose, c->r_ose, c->conv_ose, c->rel_ose, c->sw_ose};
     const double t1 = time_at(c, c->n + 1);
     oa.tf[0] = std::cos(t1); oa.tf[1] = std::sin(t1); oa.tf[2] = oa.tf[0] * oa.tf[0];
     oa.skip = nullptr;
@@ -480,6 +479,7 @@ lp_status local_porous(lp_ctx *c, const double *pro, hipStream_t st) {
     }
     pa.Uy0 = pro + 6 * nf2;
     pa.e_old = c->e2[o]; pa.e_new = c->e2[nw]; pa.b = c->b_por;
+    pa.ir = lp::IrStart{c->x_por, c->r_por, c->conv_por, c->rel_por, c->sw_por};
     const double t1 = time_at(c, c->n + 1);
     pa.tf[0] = std::cos(t1); pa.tf[1] = std::sin(t1); pa.tf[2] = pa.tf[0] * pa.tf[0];
     {
@@ -1004,8 +1004,10 @@ lp_status lp_local_step(lp_ctx *c, void *stream) {
     }
     const int en = 1 - c->ecur;
     StageTimer tm(c, LP_T_MERGE, st);
+    lp::MergeArgs mr[2];
     for (int r = 0; r < 2; ++r) {
-        lp::MergeArgs ma{};
+        lp::MergeArgs &ma = mr[r];
+        ma = lp::MergeArgs{};
         ma.sys = r == lp::POROUS ? c->d_por : c->d_ose;
         ma.nsx = c->P.nsx; ma.N = c->P.Nh; ma.region = r;
         for (int ax = 0; ax < 2; ++ax) {
@@ -1020,8 +1022,8 @@ lp_status lp_local_step(lp_ctx *c, void *stream) {
             ma.base1 = c->pro_p1; ma.out1 = c->m_p;
         }
         ma.e2 = c->e2[en]; ma.e1 = c->e1[en];
-        lp::launch_merge(ma, st);
     }
+    lp::launch_merge(mr[lp::POROUS], mr[lp::CONDUIT], st);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(c->ev_local[m % lp_ctx::RING], st));
     if (st != st_user) HIPCHK(hipStreamWaitEvent(st_user, c->ev_local[m % lp_ctx::RING], 0));

@@ -12,6 +12,16 @@ struct ProlongArgs {
     int NH, Nh, k;
 };
 
+// Start of a refinement, written by the local right-hand side kernels beside
+// b: x = 0 and r = b on every row, and the per-system flags cleared (null:
+// not written)
+struct IrStart {
+    double *x, *r;
+    int *conv;
+    double *relres;
+    int *sweeps;
+};
+
 struct PorousArgs {
     const SysDesc *sys;
     const int8_t *cls2;
@@ -25,6 +35,7 @@ struct PorousArgs {
     double *e_new;
     double *b;
     double tf[3];                 // cos t_{n+1}, sin t_{n+1}, cos^2 t_{n+1}
+    IrStart ir;                   // three flags per system
 };
 
 struct ResidualArgs {
@@ -77,6 +88,7 @@ struct OseenArgs {
     double *b;
     double tf[3];
     const int *skip;
+    IrStart ir;                   // one flag per system
 };
 
 template <typename T>
@@ -222,17 +234,6 @@ struct NewtonStartArgs {
     int *flags;                   // bit 1 set if the previous coarse step ended unconverged
 };
 
-struct IrStartArgs {
-    double *x;
-    double *r;
-    const double *b;
-    long long n;
-    int *conv;
-    double *relres;
-    int *sweeps;
-    long long nflags;
-};
-
 hipError_t upload_constants(const RefData &r, const Coef &c, hipStream_t st);
 void launch_prolong_p2(const ProlongArgs &a, hipStream_t st);
 void launch_prolong_p1(const ProlongArgs &a, hipStream_t st);
@@ -269,12 +270,11 @@ bool launch_band_lu(const BandArgs<T> &a, int nsys, int maxbw, int variant, hipS
 template <typename T>
 bool launch_band_solve(const SolveArgs<T> &a, int nsys, int nrhs, int maxbw, int maxn, int depth, hipStream_t st);
 void launch_dense_apply(const DenseArgs &a, int nsys, hipStream_t st);
-void launch_merge(const MergeArgs &a, hipStream_t st);
+void launch_merge(const MergeArgs &porous, const MergeArgs &conduit, hipStream_t st);   // both regions, one launch
 void launch_init_corrections(const InitArgs &a, int nsys, hipStream_t st);
 void launch_newton_update(const NewtonArgs &a, hipStream_t st);
 void launch_dense_newton(const DenseNewtonArgs &a, hipStream_t st);
 void launch_dense_porous(const DensePorousArgs &a, int nsys, hipStream_t st);
 void launch_newton_start(const NewtonStartArgs &a, hipStream_t st);
-void launch_ir_start(const IrStartArgs &a, hipStream_t st);
 
 }  // namespace lp

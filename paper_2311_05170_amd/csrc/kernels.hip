@@ -843,6 +843,11 @@ __global__ __launch_bounds__(256) void k_oseen_rhs_tiled(OseenArgs A) {
     __shared__ double cv[RT_TRI][6][2];
     __shared__ double cp[RT_TRI][3];
     const int tid = threadIdx.x;
+    if (A.ir.conv && blockIdx.x == 0 && tid == 0) {
+        A.ir.conv[blockIdx.y] = 0;
+        A.ir.relres[blockIdx.y] = 0.0;
+        A.ir.sweeps[blockIdx.y] = 0;
+    }
     for (int e = tid; e < RT_TRI; e += blockDim.x) {
         const int t = e & 1, cc = e >> 1;
         const int ci = ci_lo + cc % (RT + 1), cj = cj_lo + cc / (RT + 1);
@@ -959,12 +964,16 @@ __global__ __launch_bounds__(256) void k_oseen_rhs_tiled(OseenArgs A) {
                 rv[1] += eta / c_co.rho * h * pg;
             }
         }
+        auto put = [&](long long row, double v) {
+            A.b[row] = v;
+            if (A.ir.r) { A.ir.r[row] = v; A.ir.x[row] = 0.0; }
+        };
         if (cls == 0) {
-            const int d = A.dof2[S.node_off + q];
-            A.b[S.dof_off + d] = rv[0];
-            A.b[S.dof_off + d + 1] = rv[1];
+            const long long d = S.dof_off + A.dof2[S.node_off + q];
+            put(d, rv[0]);
+            put(d + 1, rv[1]);
         }
-        if (prow) A.b[S.dof_off + A.dof1[S.vert_off + vq]] = rq;
+        if (prow) put(S.dof_off + A.dof1[S.vert_off + vq], rq);
     }
 }
 
@@ -1054,6 +1063,11 @@ __global__ __launch_bounds__(256) void k_porous_rhs_tiled(PorousArgs A) {
     const double h = S.h, h2 = h * h;
     __shared__ double cr[RT_TRI][6][3];     // (triangle, its node la, field)
     const int tid = threadIdx.x;
+    if (A.ir.conv && blockIdx.x == 0 && tid < 3) {
+        A.ir.conv[3 * blockIdx.y + tid] = 0;
+        A.ir.relres[3 * blockIdx.y + tid] = 0.0;
+        A.ir.sweeps[3 * blockIdx.y + tid] = 0;
+    }
     for (int e = tid; e < RT_TRI; e += blockDim.x) {
         const int t = e & 1, cc = e >> 1;
         const int ci = ci_lo + cc % (RT + 1), cj = cj_lo + cc / (RT + 1);
@@ -1122,7 +1136,11 @@ __global__ __launch_bounds__(256) void k_porous_rhs_tiled(PorousArgs A) {
             }
         }
         const int d = A.dof2[S.node_off + q];
-        for (int f = 0; f < 3; ++f) A.b[S.dof_off + (long long)f * S.ndof + d] = r[f];
+        for (int f = 0; f < 3; ++f) {
+            const long long row = S.dof_off + (long long)f * S.ndof + d;
+            A.b[row] = r[f];
+            if (A.ir.r) { A.ir.r[row] = r[f]; A.ir.x[row] = 0.0; }
+        }
     }
 }
 
@@ -2363,7 +2381,9 @@ __device__ __forceinline__ bool last_block(int *ticket) {
 // Partition-of-unity merge (Algorithm 3 Step 4): x_h = Pi_h x_H + sum_j w_j e_j
 // over the closed cores containing the node, ascending j.
 // ---------------------------------------------------------------------------
-__global__ void k_merge(MergeArgs A) {
+// both regions in one launch (grid row = region)
+__global__ void k_merge(MergeArgs Ap, MergeArgs Ac) {
+    const MergeArgs &A = blockIdx.y == 0 ? Ap : Ac;
     const int n2 = 2 * A.N + 1, n1 = A.N + 1;
     const long long tot2 = (long long)n2 * n2, tot1 = (long long)n1 * n1;
     for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < tot2 + tot1; g += (long long)gridDim.x * blockDim.x) {
@@ -2501,18 +2521,6 @@ __global__ void k_newton_start(NewtonStartArgs A) {
     }
 }
 
-// x = 0, r = b, convergence flags cleared (start of refinement)
-__global__ void k_ir_start(IrStartArgs A) {
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < A.n; i += (long long)gridDim.x * blockDim.x) {
-        A.x[i] = 0.0;
-        A.r[i] = A.b[i];
-    }
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < A.nflags; i += (long long)gridDim.x * blockDim.x) {
-        A.conv[i] = 0;
-        A.relres[i] = 0.0;
-        A.sweeps[i] = 0;
-    }
-}
 
 // ---------------------------------------------------------------------------
 // launch wrappers
@@ -2637,9 +2645,9 @@ void launch_dense_apply(const DenseArgs &a, int nsys, hipStream_t st) {
     hipLaunchKernelGGL(k_dense_apply, dim3((a.n + 63) / 64, nsys), dim3(1024), 0, st, a);
 }
 
-void launch_merge(const MergeArgs &a, hipStream_t st) {
-    long long n = (long long)(2 * a.N + 1) * (2 * a.N + 1) + (long long)(a.N + 1) * (a.N + 1);
-    hipLaunchKernelGGL(k_merge, dim3(grid_for(n, 256)), dim3(256), 0, st, a);
+void launch_merge(const MergeArgs &porous, const MergeArgs &conduit, hipStream_t st) {
+    long long n = (long long)(2 * porous.N + 1) * (2 * porous.N + 1) + (long long)(porous.N + 1) * (porous.N + 1);
+    hipLaunchKernelGGL(k_merge, dim3(grid_for(n, 256), 2), dim3(256), 0, st, porous, conduit);
 }
 void launch_init_corrections(const InitArgs &a, int nsys, hipStream_t st) {
     hipLaunchKernelGGL(k_init_corrections, dim3(nsys), dim3(256), 0, st, a);
@@ -2658,11 +2666,6 @@ void launch_newton_start(const NewtonStartArgs &a, hipStream_t st) {
 void launch_newton_update(const NewtonArgs &a, hipStream_t st) {
     hipLaunchKernelGGL(k_newton_update, dim3(1), dim3(256), 0, st, a);
 }
-void launch_ir_start(const IrStartArgs &a, hipStream_t st) {
-    long long n = a.n > a.nflags ? a.n : a.nflags;
-    hipLaunchKernelGGL(k_ir_start, dim3(grid_for(n, 256)), dim3(256), 0, st, a);
-}
-
 template void launch_porous_assemble<float>(const AssembleArgs<float> &, int, hipStream_t);
 template void launch_porous_assemble<double>(const AssembleArgs<double> &, int, hipStream_t);
 template void launch_oseen_assemble<float>(const OseenApplyArgs<float> &, int, int, hipStream_t);
