@@ -1510,21 +1510,23 @@ __device__ __forceinline__ double row_bcast(double v) {
 template <int J, typename T>
 __device__ __forceinline__ void tile_lu_step(T (&d)[16], int lc, int lane, T &dinv) {
     const T piv = row_bcast<J>(d[J]);
+    const T dj = lc > J ? d[J] : T(0);          // masked before the reciprocal is known
     T inv;
     if constexpr (sizeof(T) == 4) {
-        inv = __builtin_amdgcn_rcpf(piv);           // then one Newton step
-        inv = fmaf(inv, fmaf(-piv, inv, 1.0f), inv);
+        // the hardware reciprocal (1 ulp): the chain from one pivot to the
+        // next is broadcast, reciprocal, multiply, FMA; the refinement sweeps
+        // absorb the factor's rounding
+        inv = __builtin_amdgcn_rcpf(piv);
     } else {
         inv = __builtin_amdgcn_rcp(piv);            // then two Newton steps
         inv = fma(inv, fma(-piv, inv, 1.0), inv);
         inv = fma(inv, fma(-piv, inv, 1.0), inv);
     }
     dinv = lane == J ? inv : dinv;
-    const T l = d[J] * inv;
-    const T lm = lc > J ? l : T(0);
+    const T lm = dj * inv;
 #pragma unroll
     for (int c = J + 1; c < 16; ++c) d[c] = fma(-lm, row_bcast<J>(d[c]), d[c]);
-    d[J] = lc > J ? l : d[J];
+    d[J] = lc > J ? lm : d[J];
 }
 template <typename T, int... J>
 __device__ __forceinline__ void tile_lu(T (&d)[16], int lc, int lane, T &dinv, std::integer_sequence<int, J...>) {
