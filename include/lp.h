@@ -183,13 +183,15 @@ lp_status lp_plan_query(const lp_mesh *mesh, const lp_partition *part, int32_t w
 
 /* Stage timers: HIP events recorded around the launches of the stages
  * selected in `mask`, on the stream each stage runs on (bit i = stage i below;
- * the coarse step, the porous batch and the Oseen assembly and factorisation
- * run on the context's internal streams, the rest on the caller's); 0 turns
+ * the coarse step, the prolongation, the porous batch and the Oseen assembly
+ * and factorisation run on the context's internal streams, the rest on the
+ * caller's); 0 turns
  * them off.  Setting a mask clears the accumulators.  lp_get_timing waits for
  * the recorded events and returns, per stage, the summed milliseconds and the
  * number of timed launches (arrays of length n <= LP_T_COUNT). */
 enum {
-    LP_T_PROLONG = 0,        /* coarse -> fine prolongation */
+    LP_T_PROLONG = 0,        /* coarse -> fine prolongation for the Oseen assembly, the local
+                                Oseen stage and the merge (internal stream, before the assembly) */
     LP_T_POR_RHS = 1,        /* local porous right-hand sides */
     LP_T_POR_SOLVE = 2,      /* local porous band solves (all refinement sweeps) */
     LP_T_POR_RES = 3,        /* local porous FP64 residuals */

@@ -50,6 +50,7 @@ struct lp_ctx {
     hipStream_t cstream = nullptr;
     hipEvent_t ev_coarse[RING] = {}, ev_local[RING] = {};
     hipEvent_t ev_cpor[RING] = {};     // coarse porous solves of a level done (they run on a factor stream)
+    hipEvent_t ev_pro[RING] = {};      // prolongation slot of a level written (on its factor stream)
     // the local porous batch of step m runs on factor stream m % 2, after that
     // step's Oseen factorisation, beside the Oseen solves (four streams in all,
     // within HIP's default of four hardware queues per process)
@@ -87,8 +88,14 @@ struct lp_ctx {
     double *nwt_e = nullptr, *nwt_e1 = nullptr;
     int *d_done = nullptr, *d_its = nullptr, *d_flags = nullptr;
 
-    // prolonged coarse fields on the fine lattices
-    double *pro_P1 = nullptr, *pro_P0 = nullptr, *pro_U1 = nullptr, *pro_U0 = nullptr, *pro_p1 = nullptr;
+    // prolonged coarse fields on the fine lattices.  Setup: the porous
+    // pressures and the velocity of level 0, for the initial corrections.
+    // Per step, slot m % RING (written after coarse step m, on its stream):
+    // u^m (2 fields), u^(m-1) (2 fields), p_F^(m-1) on P2, then p^m on P1.
+    double *pro_P1 = nullptr, *pro_U1 = nullptr;
+    double *pro_ring = nullptr;
+    long long pro_stride = 0;
+    double *pro_slot(int s) const { return pro_ring + (long long)s * pro_stride; }
 
     // local corrections (two time levels) and merged output
     double *e2[2] = {}, *e1[2] = {};
@@ -102,7 +109,6 @@ struct lp_ctx {
     double *inv_cp = nullptr, *inv_cn = nullptr, *eye_cp = nullptr, *eye_cn = nullptr;
     lp::BandSys *d_iv_cpor = nullptr, *d_iv_cns = nullptr;
     void *fac_por = nullptr, *fac_ose[FSLOTS] = {};       // factors (layout: fac_layout)
-    double *pro_Uf[2] = {};                              // u_cH^m prolonged for factor stream m % 2
     double *pro_Pb[2] = {};                              // the porous batch's prolonged inputs, per factor stream:
                                                          // p^(n+1) (3 fields), p^n (3 fields), u_y^n
     double *fac_cpor = nullptr, *fac_cns = nullptr;
@@ -158,6 +164,7 @@ struct lp_ctx {
             if (ev_coarse[i]) (void)hipEventDestroy(ev_coarse[i]);
             if (ev_local[i]) (void)hipEventDestroy(ev_local[i]);
             if (ev_cpor[i]) (void)hipEventDestroy(ev_cpor[i]);
+            if (ev_pro[i]) (void)hipEventDestroy(ev_pro[i]);
         }
         if (cstream) (void)hipStreamDestroy(cstream);
         if (serial) fstream[0] = fstream[1] = nullptr;
@@ -374,12 +381,13 @@ lp_status local_oseen(lp_ctx *c, hipStream_t st) {
     // right-hand sides of (5.8) and Dirichlet values of the new corrections
     lp::OseenArgs oa{};
     oa.sys = c->d_ose; oa.cls2 = c->d_cls2; oa.dof2 = c->d_dof2; oa.cls1 = c->d_cls1; oa.dof1 = c->d_dof1;
-    oa.W1[0] = c->pro_U1; oa.W1[1] = c->pro_U1 + nf2;
-    oa.W0[0] = c->pro_U0; oa.W0[1] = c->pro_U0 + nf2;
-    oa.Pp = c->pro_p1;
+    const double *pro = c->pro_slot((int)((c->n + 1) % lp_ctx::RING));
+    oa.W1[0] = pro; oa.W1[1] = pro + nf2;
+    oa.W0[0] = pro + 2 * nf2; oa.W0[1] = pro + 3 * nf2;
+    oa.Pp = pro + 5 * nf2;
     oa.ex[0] = c->ex_f[3]; oa.ex[1] = c->ex_f[4];
     for (int cc = 0; cc < 2; ++cc) for (int k = 0; k < 3; ++k) oa.load[cc][k] = c->ld_f[3 + cc][k];
-    oa.PF0 = c->pro_P0;
+    oa.PF0 = pro + 4 * nf2;
     oa.e_old = c->e2[o]; oa.e_new = c->e2[nw]; oa.e_new1 = c->e1[nw];
     oa.b = c->b_ose;
     oa.ir = lp::IrStart{c->x_ose, c->r_ose, c->conv_ose, c->rel_ose, c->sw_ose};
@@ -405,6 +413,8 @@ lp_status local_oseen(lp_ctx *c, hipStream_t st) {
     return LP_OK;
 }
 
+void prolong_step(lp_ctx *c, int cnew, int cold, int slot, hipStream_t st);
+
 // Assemble and factor the local Oseen operators of time level m (linearised
 // about Pi_h u_cH^m) on factor stream m % 2 (band slot m % 2, ordered by that
 // stream), into factor slot m % FSLOTS.  Ordered after coarse step m; the
@@ -418,14 +428,18 @@ lp_status factor_oseen(lp_ctx *c, int64_t m) {
     // factor slot fs was last read by local step m - FSLOTS
     if (m > lp_ctx::FSLOTS) HIPCHK(hipStreamWaitEvent(st, c->ev_local[(m - lp_ctx::FSLOTS) % lp_ctx::RING], 0));
     T *band = (T *)c->band_ose[bs];
-    double *pro_Uf = c->pro_Uf[bs];
+    // the fine-lattice prolongations of level m, for this assembly, the local
+    // Oseen stage and the merge of step m; slot nw was last read by local step
+    // m - RING, finished before local step m - RING + 1 (coarse step m waited
+    // for it)
+    {
+        StageTimer tm(c, LP_T_PROLONG, st);
+        prolong_step(c, nw, (int)((m - 1) % lp_ctx::RING), nw, st);
+    }
+    HIPCHK(hipEventRecord(c->ev_pro[nw], st));
+    const double *pro_Uf = c->pro_slot(nw);
     {
         StageTimer tm(c, LP_T_OSE_ASM, st);
-        lp::ProlongArgs pa{};
-        pa.NH = c->P.NH; pa.Nh = c->P.Nh; pa.k = c->P.k;
-        pa.nfields = 2;
-        for (int cc = 0; cc < 2; ++cc) { pa.src[cc] = c->cU[nw] + cc * c->nc2; pa.dst[cc] = pro_Uf + cc * c->nf2; }
-        lp::launch_prolong_p2(pa, st);
         HIPCHK(hipMemsetAsync(band, 0, (size_t)c->P.band_total_ose * sizeof(T), st));
         lp::OseenApplyArgs<T> aa{};
         aa.sys = c->d_ose; aa.cls2 = c->d_cls2; aa.dof2 = c->d_dof2; aa.dof1 = c->d_dof1;
@@ -495,37 +509,47 @@ lp_status local_porous(lp_ctx *c, const double *pro, hipStream_t st) {
     return LP_OK;
 }
 
-// The coarse fields the local Oseen stage reads, prolonged: u^(n+1), u^n, p_F^n
-// (its Gamma terms) on the P2 lattice, p^(n+1) on P1.  At setup (all) also the
-// three porous pressures of both levels, for the initial corrections; per step
-// the porous batch prolongs its own inputs.
-void prolong_all(lp_ctx *c, int cnew, int cold, hipStream_t st, bool all = false) {
+// The coarse fields that the assembly, the local Oseen stage and the merge of
+// step m read, prolonged into slot `slot`: u^m, u^(m-1), p_F^(m-1) (the Gamma
+// terms) on the P2 lattice, p^m on P1.  The porous batch prolongs its own
+// inputs.
+void prolong_step(lp_ctx *c, int cnew, int cold, int slot, hipStream_t st) {
     const long long nc2 = c->nc2, nf2 = c->nf2;
+    double *d = c->pro_slot(slot);
     lp::ProlongArgs pa{};
     pa.NH = c->P.NH; pa.Nh = c->P.Nh; pa.k = c->P.k;
-    if (all) {
-        pa.nfields = 6;
-        for (int f = 0; f < 3; ++f) {
-            pa.src[f] = c->cP[cnew] + f * nc2;
-            pa.dst[f] = c->pro_P1 + f * nf2;
-            pa.src[3 + f] = c->cP[cold] + f * nc2;
-            pa.dst[3 + f] = c->pro_P0 + f * nf2;
-        }
-        lp::launch_prolong_p2(pa, st);
-    }
-    pa.nfields = all ? 4 : 5;
+    pa.nfields = 5;
     for (int cc = 0; cc < 2; ++cc) {
         pa.src[cc] = c->cU[cnew] + cc * nc2;
-        pa.dst[cc] = c->pro_U1 + cc * nf2;
+        pa.dst[cc] = d + cc * nf2;
         pa.src[2 + cc] = c->cU[cold] + cc * nc2;
-        pa.dst[2 + cc] = c->pro_U0 + cc * nf2;
+        pa.dst[2 + cc] = d + (2 + cc) * nf2;
     }
-    if (!all) { pa.src[4] = c->cP[cold]; pa.dst[4] = c->pro_P0; }
+    pa.src[4] = c->cP[cold];
+    pa.dst[4] = d + 4 * nf2;
     lp::launch_prolong_p2(pa, st);
     pa.nfields = 1;
     pa.src[0] = c->cp[cnew];
-    pa.dst[0] = c->pro_p1;
+    pa.dst[0] = d + 5 * nf2;
     lp::launch_prolong_p1(pa, st);
+}
+
+// level 0 prolonged for the initial corrections: the three porous pressures
+// and the velocity
+void prolong_setup(lp_ctx *c, hipStream_t st) {
+    const long long nc2 = c->nc2, nf2 = c->nf2;
+    lp::ProlongArgs pa{};
+    pa.NH = c->P.NH; pa.Nh = c->P.Nh; pa.k = c->P.k;
+    pa.nfields = 5;
+    for (int f = 0; f < 3; ++f) {
+        pa.src[f] = c->cP[0] + f * nc2;
+        pa.dst[f] = c->pro_P1 + f * nf2;
+    }
+    for (int cc = 0; cc < 2; ++cc) {
+        pa.src[3 + cc] = c->cU[0] + cc * nc2;
+        pa.dst[3 + cc] = c->pro_U1 + cc * nf2;
+    }
+    lp::launch_prolong_p2(pa, st);
 }
 
 bool params_ok(const lp_params &p, std::string &why) {
@@ -698,11 +722,9 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
         HIPCHK(hipStreamSynchronize(st));
     }
     TRY(c->dalloc(&c->pro_P1, 3 * c->nf2));
-    TRY(c->dalloc(&c->pro_P0, 3 * c->nf2));
     TRY(c->dalloc(&c->pro_U1, 2 * c->nf2));
-    TRY(c->dalloc(&c->pro_U0, 2 * c->nf2));
-    TRY(c->dalloc(&c->pro_p1, c->nf1));
-    for (int l = 0; l < 2; ++l) TRY(c->dalloc(&c->pro_Uf[l], 2 * c->nf2));
+    c->pro_stride = (5 * c->nf2 + c->nf1 + 63) / 64 * 64;
+    TRY(c->dalloc(&c->pro_ring, lp_ctx::RING * c->pro_stride));
     for (int l = 0; l < 2; ++l) TRY(c->dalloc(&c->pro_Pb[l], 7 * c->nf2));
     for (int l = 0; l < 2; ++l) { TRY(c->dalloc(&c->e2[l], P.e2_total)); TRY(c->dalloc(&c->e1[l], P.e1_total)); }
     TRY(c->dalloc(&c->m_P, 3 * c->nf2));
@@ -799,8 +821,9 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
         HIPCHK(hipEventCreateWithFlags(&c->ev_coarse[i], hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&c->ev_local[i], hipEventDisableTiming));
         HIPCHK(hipEventCreateWithFlags(&c->ev_cpor[i], hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&c->ev_pro[i], hipEventDisableTiming));
     }
-    prolong_all(c.get(), 0, 0, st, true);
+    prolong_setup(c.get(), st);
     {
         lp::InitArgs ia{};
         ia.sys = c->d_por; ia.cls2 = c->d_cls2;
@@ -978,10 +1001,7 @@ lp_status lp_local_step(lp_ctx *c, void *stream) {
         StageTimer tm(c, LP_T_WAIT_COARSE, st);
         HIPCHK(hipStreamWaitEvent(st, c->ev_coarse[nw], 0));
         HIPCHK(hipStreamWaitEvent(st, c->ev_cpor[nw], 0));
-    }
-    {
-        StageTimer tm(c, LP_T_PROLONG, st);
-        prolong_all(c, nw, o, st);
+        HIPCHK(hipStreamWaitEvent(st, c->ev_pro[nw], 0));
     }
     // The porous batch runs on the factor stream of this step from its own
     // prolongation, so it waits for the coarse level, not for the local Oseen
@@ -1018,8 +1038,9 @@ lp_status lp_local_step(lp_ctx *c, void *stream) {
             for (int f = 0; f < 3; ++f) { ma.base[f] = pro + f * c->nf2; ma.out[f] = c->m_P + f * c->nf2; }
             ma.base1 = nullptr; ma.out1 = nullptr;
         } else {
-            for (int f = 0; f < 2; ++f) { ma.base[f] = c->pro_U1 + f * c->nf2; ma.out[f] = c->m_U + f * c->nf2; }
-            ma.base1 = c->pro_p1; ma.out1 = c->m_p;
+            const double *pu = c->pro_slot(nw);
+            for (int f = 0; f < 2; ++f) { ma.base[f] = pu + f * c->nf2; ma.out[f] = c->m_U + f * c->nf2; }
+            ma.base1 = pu + 5 * c->nf2; ma.out1 = c->m_p;
         }
         ma.e2 = c->e2[en]; ma.e1 = c->e1[en];
     }
