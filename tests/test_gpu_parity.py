@@ -2,6 +2,8 @@
 same seeded inputs.  Fields are compared after every step in the relative
 mass-matrix norm: <= 1e-8 for the FP64 path, <= 1e-7 for the mixed path
 (FP32 factorisations won back by FP64 iterative refinement)."""
+import functools
+
 import numpy as np
 import pytest
 
@@ -191,6 +193,49 @@ def test_streams_do_not_change_results(precision, monkeypatch):
     monkeypatch.setenv("LP_SERIAL", "1")
     g = _gpu(cfg, precision)
     for _ in range(3):
+        g.step()
+    b = _fields(g)
+    g.close()
+    for f in a:
+        assert np.array_equal(a[f], b[f]), f
+
+
+RING_STEPS = 18
+
+
+@functools.lru_cache(maxsize=1)
+def _oracle_after(name, steps):
+    cfg = W.config(name)
+    o = _oracle(cfg)
+    for _ in range(steps):
+        o.coarse_step()
+        o.local_step()
+    return o
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_pipeline_wraps_its_rings(precision, monkeypatch):
+    """18 steps issued back to back, with no host synchronisation between them:
+    the coarse trajectory runs ahead, and the rings of coarse states and
+    prolongations (8 slots) and of factor slots (5) wrap twice or more.  The
+    fields are bit-identical to the serial schedule's and agree with the
+    oracle after the last step (coarse Jacobian every third step, as timed)."""
+    cfg = W.config("cfg1")
+    kw = dict(jacobian_every=3, max_newton=10)
+    g = _gpu(cfg, precision, **kw)
+    for _ in range(RING_STEPS):
+        g.step()
+    a = _fields(g)
+    o = _oracle_after("cfg1", RING_STEPS)
+    em = compare(o, g, "merged")
+    st = g.stats()
+    g.close()
+    print("after", RING_STEPS, "steps", {k: "%.1e" % v for k, v in em.items()}, st, flush=True)
+    assert max(em.values()) < TOL[precision], em
+    assert st["flags"] & 6 == 0, st
+    monkeypatch.setenv("LP_SERIAL", "1")
+    g = _gpu(cfg, precision, **kw)
+    for _ in range(RING_STEPS):
         g.step()
     b = _fields(g)
     g.close()
