@@ -87,9 +87,13 @@ def timed_run(cfg, precision, steps, warmup, max_ir):
     lu_ms, lu_n = tm["ose_lu"]
     res = dict(ms_per_step=(t1 - t0) * 1e3 / steps, lu_ms_avg=lu_ms / max(lu_n, 1), lu_launches=lu_n, stats=st)
     # separate instrumented pass for the stage split (not part of the timed value;
-    # the events serialise nothing but add launch gaps)
+    # the events serialise nothing but add launch gaps).  A few steps issued
+    # first let the coarse trajectory run ahead again, so that the split is the
+    # steady state's, not the refill's.
+    for _ in range(4):
+        g.step()
     g.set_timing(lib.STAGES)
-    nd = 3
+    nd = 10
     for _ in range(nd):
         g.step()
     tm = g.timing()

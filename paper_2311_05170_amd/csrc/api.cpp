@@ -1003,12 +1003,15 @@ lp_status lp_local_step(lp_ctx *c, void *stream) {
         HIPCHK(hipStreamWaitEvent(st, c->ev_cpor[nw], 0));
         HIPCHK(hipStreamWaitEvent(st, c->ev_pro[nw], 0));
     }
-    // The porous batch runs on the factor stream of this step from its own
-    // prolongation, so it waits for the coarse level, not for the local Oseen
-    // chain of the previous step.  It reads the corrections of step m-1 (the
-    // previous porous batch, on the other factor stream) and overwrites the
-    // buffers that the merge of step m-2 read.
-    hipStream_t ps = c->fstream[m % 2];
+    // The porous batch runs from its own prolongation, so it waits for the
+    // coarse level, not for the local Oseen chain of the previous step.  It
+    // reads the corrections of step m-1 (the previous porous batch) and
+    // overwrites the buffers that the merge of step m-2 read.  In the mixed
+    // path it runs on the factor stream of this step, beside the local Oseen
+    // chain, which has no idle time.  In the FP64 path the factorisation (over
+    // twice as long) keeps the factor streams busy while the local Oseen chain
+    // waits for it, so the batch runs on this stream, before that wait.
+    hipStream_t ps = c->mixed ? c->fstream[m % 2] : st;
     double *pro = c->pro_Pb[m % 2];
     HIPCHK(hipStreamWaitEvent(ps, c->ev_coarse[nw], 0));
     HIPCHK(hipStreamWaitEvent(ps, c->ev_cpor[nw], 0));
