@@ -51,17 +51,18 @@ struct lp_ctx {
     hipEvent_t ev_coarse[RING] = {}, ev_local[RING] = {};
     hipEvent_t ev_cpor[RING] = {};     // coarse porous solves of a level done (they run on a factor stream)
     hipEvent_t ev_pro[RING] = {};      // prolongation slot of a level written (on its factor stream)
-    // the local porous batch of step m runs on factor stream m % 2, after that
-    // step's Oseen factorisation, beside the Oseen solves (four streams in all,
-    // within HIP's default of four hardware queues per process)
+    // the local porous batch of step m runs on factor stream m % 2 (mixed
+    // path), after that step's Oseen factorisation, beside the Oseen solves, or
+    // on the caller's stream ahead of them (FP64 path); four streams in all,
+    // within HIP's default of four hardware queues per process
     hipEvent_t ev_por = nullptr;                       // porous batch of the latest local step done
     // The local Oseen operator of step m depends only on u_cH^m, so its
     // assembly and factorisation run on factor stream m % 2 as soon as coarse
     // step m is done, overlapping the solves of step m-1 and the factorisation
     // of step m-1 (one workgroup per system leaves most CUs to the other).
-    // Band and prolonged velocity of step m use slot m % 2 (ordered by the
-    // stream), factors slot m % FSLOTS, rewritten once local step m - FSLOTS
-    // has finished.
+    // The band of step m uses slot m % 2 (ordered by the stream), its
+    // prolonged fields ring slot m % RING, its factors slot m % FSLOTS,
+    // rewritten once local step m - FSLOTS has finished.
     hipStream_t fstream[2] = {};
     hipEvent_t ev_fac[FSLOTS] = {};
     int ecur = 0;                  // correction buffers holding e^n
@@ -109,7 +110,7 @@ struct lp_ctx {
     double *inv_cp = nullptr, *inv_cn = nullptr, *eye_cp = nullptr, *eye_cn = nullptr;
     lp::BandSys *d_iv_cpor = nullptr, *d_iv_cns = nullptr;
     void *fac_por = nullptr, *fac_ose[FSLOTS] = {};       // factors (layout: fac_layout)
-    double *pro_Pb[2] = {};                              // the porous batch's prolonged inputs, per factor stream:
+    double *pro_Pb[2] = {};                              // the porous batch's prolonged inputs, per step parity:
                                                          // p^(n+1) (3 fields), p^n (3 fields), u_y^n
     double *fac_cpor = nullptr, *fac_cns = nullptr;
     double *b_por = nullptr, *x_por = nullptr, *r_por = nullptr;
@@ -457,8 +458,8 @@ lp_status factor_oseen(lp_ctx *c, int64_t m) {
     return LP_OK;
 }
 
-// the porous batch's coarse inputs on its own stream: p^(n+1), p^n and u_y^n
-// prolonged into pro (7 fields)
+// the porous batch's coarse inputs on the batch's stream: p^(n+1), p^n and
+// u_y^n prolonged into pro (7 fields)
 void prolong_porous(lp_ctx *c, double *pro, int cnew, int cold, hipStream_t st) {
     const long long nc2 = c->nc2, nf2 = c->nf2;
     lp::ProlongArgs pa{};
