@@ -88,6 +88,14 @@ def test_parity_small_ragged(precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_parity_single_subdomain_per_region(precision):
+    """The degenerate partition: one subdomain per region, so no artificial
+    boundary and one owner per merged node (each local problem is its whole
+    region on the fine mesh, with the coarse solution as lagged data)."""
+    run_parity(W.small(NH=2, refine=4, nsub=1, overlap=1), precision, 3)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_parity_cfg1(precision):
     """The 2D FP64 workload: H = 1/4, h = 1/16, 4 x 4 + 4 x 4 subdomains,
     overlap H/2, dt = 0.1, T = 0.5 (all 5 steps)."""
