@@ -96,6 +96,16 @@ def test_parity_single_subdomain_per_region(precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_parity_extreme_parameters(precision):
+    """Small viscosity (nu = 1e-3: convection-dominated local Oseen systems,
+    factored without pivoting), permeabilities down to 1e-4 and strong
+    exchange (sigma = 10, sigma* = 0.1): the FP32 factorisations of the mixed
+    path are less accurate and the refinement must still reach the tolerance."""
+    prm = dict(W.unit_params(), nu=1e-3, k=[1e-4, 1e-3, 1e-2], sigma=10.0, sigma_star=0.1)
+    run_parity(W.small(NH=2, refine=4, nsub=2, overlap=1, dt=0.01, prm=prm), precision, 3)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_parity_cfg1(precision):
     """The 2D FP64 workload: H = 1/4, h = 1/16, 4 x 4 + 4 x 4 subdomains,
     overlap H/2, dt = 0.1, T = 0.5 (all 5 steps)."""
