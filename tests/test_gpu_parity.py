@@ -122,6 +122,38 @@ def test_parity_cfg2_first_steps(precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_parity_cfg2_timed_configuration(precision):
+    """cfg2 in the configuration that bench.py times: two refinement sweeps
+    launched in the mixed path, the coarse Jacobian formed every third step,
+    at most ten chord steps."""
+    cfg = W.config("cfg2")
+    run_parity(cfg, precision, 2, max_ir=2, jacobian_every=3, max_newton=10)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_cfg2_pipeline_matches_serial(precision, monkeypatch):
+    """At full size, 12 steps issued back to back (every ring wraps) give
+    bit-identical fields to the serial schedule, with no flag raised."""
+    cfg = W.config("cfg2")
+    kw = dict(max_ir=2, jacobian_every=3, max_newton=10)
+    g = _gpu(cfg, precision, **kw)
+    for _ in range(12):
+        g.step()
+    a = _fields(g)
+    st = g.stats()
+    g.close()
+    assert st["flags"] == 0, st
+    monkeypatch.setenv("LP_SERIAL", "1")
+    g = _gpu(cfg, precision, **kw)
+    for _ in range(12):
+        g.step()
+    b = _fields(g)
+    g.close()
+    for f in a:
+        assert np.array_equal(a[f], b[f]), f
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_parity_jacobian_reuse(precision):
     """The coarse Jacobian formed every third step and reused in between
     (chord steps to the same tolerance) agrees with the oracle too."""
