@@ -11,9 +11,14 @@ dt = 0.01, seeded parameters).  Inputs are resident in HBM before timing.
 Prints ONE JSON line.  Fields beyond the driver's contract:
   fp64            the plain FP64 GPU path on the same workload
   stages_ms       per-step stage split from a separate instrumented pass
-  accuracy        max relative mass-norm error vs the CPU oracle after 2 steps
-  roofline        dominant kernel (the local Oseen band factorisation)
-  cpu_baseline    the CPU oracle on the host (2 steps of the same workload)
+  refinement      run-long refinement and Newton statistics of the timed runs
+                  (sticky flags: the run exits non-zero if any is raised)
+  accuracy        relative mass-norm error vs the CPU oracle after 2 steps
+  roofline        dominant kernel (the local Oseen band factorisation) against
+                  its binding roof, plus whole-step roofline fractions of the
+                  mixed and FP64 paths
+  cpu_baseline    the CPU oracle on the host: a process pool over subdomains
+                  on the host cores (and one thread), 2 steps of the workload
 """
 import argparse
 import hashlib
@@ -29,7 +34,11 @@ sys.path.insert(0, ROOT)
 METRIC = "fine-grid local DoFs solved/s per time step, mixed vs FP64 at 1e-7 rel L2"
 WORKLOAD = "cfg2"
 PEAK_MFMA_FP32_TFLOPS = 157.3   # MI355X dense FP32 matrix peak (the factorisation's trailing updates run on MFMA)
+PEAK_FP64_TFLOPS = 78.6         # MI355X FP64 vector and matrix peak
+PEAK_HBM_GBS = 8000.0           # MI355X HBM3E
 CPU_STEPS = 2
+CPU_POOL_MAX = 16               # host cores given to one GPU's share
+SERIAL_STEPS = 8                # roofline pass: LU launches timed on an uncontended stream
 # the instantiation the launcher picks for half-bandwidths 129..160 in FP32
 LU_KERNEL = "k_band_lu_la<float,11> (local Oseen blocked band LU with one-panel lookahead, FP32, MFMA 16x16x4)"
 LU_NAME = "k_band_lu_la<float,11>"
@@ -73,19 +82,15 @@ def timed_run(cfg, precision, steps, warmup, max_ir):
     for _ in range(warmup):
         g.step()
     torch.cuda.synchronize()
-    # timed region: only the dominant kernel is bracketed by HIP events, recorded
-    # on the stream it is launched on
-    g.set_timing(["ose_lu"])
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         g.step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    tm = g.timing()
+    # run-long statistics: the flags are sticky and the refinement maxima
+    # cover every step so far (warmup and timed)
     st = g.stats()
-    lu_ms, lu_n = tm["ose_lu"]
-    res = dict(ms_per_step=(t1 - t0) * 1e3 / steps, lu_ms_avg=lu_ms / max(lu_n, 1), lu_launches=lu_n, stats=st)
+    res = dict(ms_per_step=(t1 - t0) * 1e3 / steps, stats=st)
     # separate instrumented pass for the stage split (not part of the timed value;
     # the events serialise nothing but add launch gaps).  A few steps issued
     # first let the coarse trajectory run ahead again, so that the split is the
@@ -102,22 +107,126 @@ def timed_run(cfg, precision, steps, warmup, max_ir):
     return res
 
 
-def cpu_leg(out_path):
-    """Time the oracle on the host (single thread) over CPU_STEPS steps of the
-    workload and store its merged fields."""
+def serial_lu_time(cfg, precision, max_ir, steps=SERIAL_STEPS):
+    """Average duration of the local Oseen factorisation with nothing beside it:
+    every stage on one stream in program order (LP_SERIAL=1), HIP events
+    recorded around each launch on that stream.  In the overlapped schedule the
+    same kernel shares the chip with the coarse chain and the solves, so its
+    event interval there also holds waiting for compute units."""
+    import torch
+    os.environ["LP_SERIAL"] = "1"
+    try:
+        g = make(cfg, precision, max_ir)
+    finally:
+        del os.environ["LP_SERIAL"]
+    for _ in range(2):
+        g.step()
+    torch.cuda.synchronize()
+    g.set_timing(["ose_lu"])
+    for _ in range(steps):
+        g.step()
+    ms, n = g.timing()["ose_lu"]
+    g.close()
+    return ms / max(n, 1), n
+
+
+def step_roofline(cfg, sizes, tab, coarse, stats, T, jacobian_every):
+    """Roofline time of one step: the sum over the stages of
+    max(algorithmic bytes / HBM bandwidth, algorithmic flops / peak), each input
+    read once and each output written once from HBM, at the measured sweep and
+    Newton counts.  T = bytes per band / factor entry (4 mixed, 8 FP64).
+    Returns (milliseconds, {stage: (bytes, flops)})."""
     import numpy as np
+    npor = cfg["nsub"][0] * cfg["nsub"][1]
+    n = sizes[:, 0].astype(np.float64)
+    bw = sizes[:, 1].astype(np.float64)
+    # local lattice nodes per subdomain: (2 cx + 1)(2 cy + 1) P2, (cx + 1)(cy + 1) P1
+    cx = (tab[:, 2] - tab[:, 1]).astype(np.float64)
+    cy = (tab[:, 4] - tab[:, 3]).astype(np.float64)
+    n2 = (2 * cx + 1) * (2 * cy + 1)
+    n1 = (cx + 1) * (cy + 1)
+    P, O = slice(0, npor), slice(npor, None)
+    Nh, NH = cfg["Nh"], cfg["NH"]
+    nf2, nf1 = (2 * Nh + 1) ** 2, (Nh + 1) ** 2
+    sweeps = max(int(stats["ir_sweeps"]), 1)
+    band = lambda nn, bb: nn * (2 * bb + 1) * T                   # noqa: E731
+    fac = lambda nn, bb: (2 * nn * bb + nn) * T                   # noqa: E731
+    lu_fl = float(band_lu_flops(sizes[O]))
+    st = {}
+    # Algorithm 3 Step 1 (coarse): each chord step reads the n x n inverse once;
+    # a refresh step forms the band (written, read by the LU), its factors and
+    # the inverse (written once)
+    ncp, bcp, ncn, bcn = (float(v) for v in coarse)
+    its = max(int(stats["newton_its"]), 1)
+    refresh = (8.0 * ncn ** 2 + 2 * 8.0 * ncn * (2 * bcn + 1)) / max(jacobian_every, 1)
+    st["coarse"] = (its * 8.0 * ncn ** 2 + 3 * 8.0 * ncp ** 2 + refresh,
+                    its * 2.0 * ncn ** 2 + 3 * 2.0 * ncp ** 2 + float(band_lu_flops([(ncn, bcn)])) / max(jacobian_every, 1))
+    # Pi_h: 6 + 7 fine fields written
+    st["prolong"] = (8.0 * (12 * nf2 + nf1), 0.0)
+    # local right-hand sides: read the prolonged fields and e^n, write b and e^{n+1}'s Dirichlet values
+    st["por_rhs"] = (float((8.0 * (7 + 3 + 3 + 3) * n2[P]).sum()), 0.0)
+    st["ose_rhs"] = (float((8.0 * (6 + 2 + 2 + 3) * n2[O] + 8.0 * 2 * n1[O]).sum()), 0.0)
+    st["ose_asm"] = (float(band(n[O], bw[O]).sum()), 0.0)
+    st["ose_lu"] = (float(band(n[O], bw[O]).sum() + fac(n[O], bw[O]).sum()), lu_fl)
+    # per sweep: factors read once, r read and x updated (FP64); FP64 residual: x, b read, r written
+    st["ose_solve"] = (sweeps * float((fac(n[O], bw[O]) + 24.0 * n[O]).sum()), sweeps * float((4 * n[O] * bw[O]).sum()))
+    st["por_solve"] = (sweeps * float(3 * (fac(n[P], bw[P]) + 24.0 * n[P]).sum()), sweeps * float((12 * n[P] * bw[P]).sum()))
+    st["ose_res"] = (sweeps * float((24.0 * n[O] + 16.0 * n2[O]).sum()), 0.0)
+    st["por_res"] = (sweeps * float((3 * 24.0 * n[P]).sum()), 0.0)
+    # finalize and merge: e^{n+1} written once, read by the merge with the
+    # prolonged base; the merged fields written
+    st["merge"] = (float(8.0 * (3 * n2[P].sum() + 2 * n2[O].sum() + n1[O].sum())) * 2 + 8.0 * 2 * (5 * nf2 + nf1), 0.0)
+    peak = (PEAK_MFMA_FP32_TFLOPS if T == 4 else PEAK_FP64_TFLOPS) * 1e12
+    t = sum(max(b / (PEAK_HBM_GBS * 1e9), f / peak) for b, f in st.values())
+    return t * 1e3, {k: {"bytes": v[0], "flops": v[1]} for k, v in st.items()}
+
+
+def cpu_leg(out_path, pool):
+    """Time the oracle on the host over CPU_STEPS steps of the workload and
+    store its merged fields.  pool = 1: one thread; pool > 1: each step's local
+    solves (Step 3, independent per subdomain) go to `pool` forked worker
+    processes, one BLAS thread each, the coarse step and the merge stay in the
+    parent.  The oracle's constant local porous operators are built before the
+    clock starts (the library factors them at setup as well)."""
+    import multiprocessing as mp
+    import numpy as np
+    from oracle.mesh import POROUS
     from oracle.scheme import Oracle2D
     from paper_2311_05170_amd import workloads as W
     cfg = W.config(WORKLOAD)
     o = Oracle2D(cfg["NH"], cfg["Nh"], cfg["cuts"], cfg["overlap"], cfg["prm"], cfg["dt"])
     o.init()
+    for sd in o.subs:
+        if sd.region == POROUS:
+            o._porous_ops(sd)
+    ctx = mp.get_context("fork")
     t0 = time.perf_counter()
     for _ in range(CPU_STEPS):
         o.coarse_step()
-        o.local_step()
+        if pool <= 1:
+            o.local_step()
+            continue
+        pro = o.prolonged()
+        _POOL_STATE["o"], _POOL_STATE["pro"] = o, pro
+        order = sorted(o.subs, key=lambda sd: -(sd.x1 - sd.x0) * (sd.y1 - sd.y0) * (1 if sd.region == POROUS else 3))
+        with ctx.Pool(pool) as pl:
+            res = pl.map(_pool_solve, [sd.sid for sd in order], chunksize=1)
+        o.e = dict(res)
+        o.n += 1
+        o._pro = pro
     t1 = time.perf_counter()
     m = o.merged()
     np.savez(out_path, seconds=t1 - t0, **m)
+
+
+_POOL_STATE = {}
+
+
+def _pool_solve(sid):
+    from oracle.mesh import POROUS
+    o, pro = _POOL_STATE["o"], _POOL_STATE["pro"]
+    sd = o.subs[sid]
+    return sid, (o.local_porous(sd, pro) if sd.region == POROUS else o.local_conduit(sd, pro))
 
 
 def accuracy(cfg, ref_path):
@@ -193,6 +302,33 @@ def traffic_for(kernel, workload):
     return None
 
 
+def host_cores():
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return avail, model
+
+
+def run_cpu_leg(pool):
+    import numpy as np
+    import tempfile
+    td = tempfile.mkdtemp()
+    ref = os.path.join(td, "oracle.npz")
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-leg", ref, "--cpu-pool", str(pool)],
+                   check=True, env=env)
+    return float(np.load(ref)["seconds"]), ref
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -200,11 +336,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-leg", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--cpu-pool", type=int, default=1, help=argparse.SUPPRESS)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (HBM counter calibration)")
     args = ap.parse_args()
     if args.cpu_leg:
-        cpu_leg(args.cpu_leg)
+        cpu_leg(args.cpu_leg, args.cpu_pool)
         return
     if args.calibrate_copy:
         calibrate_copy()
@@ -222,18 +359,33 @@ def main():
         print("warmup + steps + 3 exceeds the workload's %d time steps" % cfg["steps"], file=sys.stderr)
         sys.exit(2)
     flat = W.flat_cuts(cfg["cuts"])
-    sizes = lib.plan_query(cfg["NH"], cfg["refine"], cfg["nsub"], cfg["overlap"], 5, cuts=flat).reshape(-1, 2)
+    qargs = (cfg["NH"], cfg["refine"], cfg["nsub"], cfg["overlap"])
+    sizes = lib.plan_query(*qargs, 5, cuts=flat).reshape(-1, 2)
+    tab = lib.plan_query(*qargs, 0, cuts=flat).reshape(-1, 9)
     npor = cfg["nsub"][0] * cfg["nsub"][1]
     L = int(3 * sizes[:npor, 0].sum() + sizes[npor:, 0].sum())
     lu_flops = band_lu_flops(sizes[npor:])
+    ose = sizes[npor:].astype(float)
+    lu_bytes = float((ose[:, 0] * (2 * ose[:, 1] + 1) * 4 + (2 * ose[:, 0] * ose[:, 1] + ose[:, 0]) * 4).sum())
 
     mixed = timed_run(cfg, "mixed", args.steps, args.warmup, MAX_IR_MIXED)
     fp64 = timed_run(cfg, "fp64", args.steps, args.warmup, 2)
+    lu_ms, lu_n = serial_lu_time(cfg, "mixed", MAX_IR_MIXED)
 
     def rate(ms):
         return L / (ms * 1e-3)
 
-    achieved = lu_flops / (mixed["lu_ms_avg"] * 1e-3) / 1e12     # algorithmic flops (unblocked count)
+    # the factorisation's arithmetic intensity (flops per algorithmic byte) is
+    # below the FP32 ridge (peak flops / HBM bandwidth), so HBM is its binding roof
+    intensity = lu_flops / lu_bytes
+    ridge = PEAK_MFMA_FP32_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
+    bound = "hbm" if intensity < ridge else "mfma"
+    gbs = lu_bytes / (lu_ms * 1e-3) / 1e9
+    tflops = lu_flops / (lu_ms * 1e-3) / 1e12
+    coarse = lib.plan_query(*qargs, 6, cuts=flat)
+    roof_ms_mixed, stages_mixed = step_roofline(cfg, sizes, tab, coarse, mixed["stats"], 4, JACOBIAN_EVERY)
+    roof_ms_fp64, stages_fp64 = step_roofline(cfg, sizes, tab, coarse, fp64["stats"], 8, JACOBIAN_EVERY)
+    flags = [mixed["stats"]["flags"], fp64["stats"]["flags"]]
     line = {
         "metric": METRIC,
         "value": rate(mixed["ms_per_step"]),
@@ -253,31 +405,44 @@ def main():
                    "max_halfbandwidth": int(sizes[:, 1].max())},
         "fp64": {"value": rate(fp64["ms_per_step"]), "ms_per_step": fp64["ms_per_step"], "dtype": "f64"},
         "stages_ms": {"mixed": mixed["stages_ms"], "fp64": fp64["stages_ms"]},
-        "refinement": {"mixed_sweeps": mixed["stats"]["ir_sweeps"], "mixed_max_sweeps": MAX_IR_MIXED,
-                       "mixed_relres": mixed["stats"]["ir_relres"],
-                       "fp64_relres": fp64["stats"]["ir_relres"], "flags": [mixed["stats"]["flags"], fp64["stats"]["flags"]],
+        "refinement": {"scope": "every step of the run (warmup + timed), sticky",
+                       "mixed_sweeps_max": mixed["stats"]["ir_sweeps_max"], "mixed_max_sweeps": MAX_IR_MIXED,
+                       "mixed_relres_max": mixed["stats"]["ir_relres_max"],
+                       "fp64_sweeps_max": fp64["stats"]["ir_sweeps_max"],
+                       "fp64_relres_max": fp64["stats"]["ir_relres_max"], "flags": flags,
                        "newton_its_max": [mixed["stats"]["newton_its_max"], fp64["stats"]["newton_its_max"]],
                        "max_newton": MAX_NEWTON, "jacobian_every": JACOBIAN_EVERY},
         "roofline": {"kernel": LU_KERNEL,
-                     "bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_MFMA_FP32_TFLOPS, "traffic": traffic_for(LU_NAME, WORKLOAD),
-                     "flops_per_launch": lu_flops, "avg_launch_ms": mixed["lu_ms_avg"],
-                     "launches": mixed["lu_launches"]},
+                     "bound": bound, "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": gbs / PEAK_HBM_GBS, "traffic": traffic_for(LU_NAME, WORKLOAD),
+                     "bytes_per_launch": lu_bytes, "flops_per_launch": lu_flops,
+                     "intensity_flop_per_byte": intensity, "ridge_flop_per_byte": ridge,
+                     "mfma_frac": tflops / PEAK_MFMA_FP32_TFLOPS,
+                     "avg_launch_ms": lu_ms, "launches": lu_n,
+                     "timing": "HIP events around each launch, every stage on one stream (LP_SERIAL=1)",
+                     "step": {"mixed": {"roofline_ms": roof_ms_mixed, "measured_ms": mixed["ms_per_step"],
+                                        "frac": roof_ms_mixed / mixed["ms_per_step"], "stages": stages_mixed},
+                              "fp64": {"roofline_ms": roof_ms_fp64, "measured_ms": fp64["ms_per_step"],
+                                       "frac": roof_ms_fp64 / fp64["ms_per_step"], "stages": stages_fp64}}},
     }
     if not args.no_cpu:
-        import tempfile
-        with tempfile.TemporaryDirectory() as td:
-            ref = os.path.join(td, "oracle.npz")
-            env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
-            subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-leg", ref], check=True, env=env)
-            import numpy as np
-            secs = float(np.load(ref)["seconds"])
-            line["cpu_baseline"] = {"value": L * CPU_STEPS / secs, "unit": "local DoF/s", "cores": 1,
-                                    "kind": "oracle",
-                                    "sample": "%d full steps (coarse + local) of the same workload, "
-                                              "NumPy/SciPy FP64, one thread, %.1f s" % (CPU_STEPS, secs)}
-            line["accuracy"] = accuracy(cfg, ref)
+        cores, model = host_cores()
+        pool = max(1, min(CPU_POOL_MAX, cores))
+        secs1, ref = run_cpu_leg(1)
+        secsp, _ = run_cpu_leg(pool) if pool > 1 else (secs1, ref)
+        line["cpu_baseline"] = {"value": L * CPU_STEPS / secsp, "unit": "local DoF/s", "cores": pool,
+                                "kind": "oracle",
+                                "sample": "%d full steps (coarse + local) of the same workload, NumPy/SciPy FP64, "
+                                          "local solves over a pool of %d forked processes (one BLAS thread each), "
+                                          "%.1f s; host: %d cores available, %s" % (CPU_STEPS, pool, secsp, cores, model),
+                                "single_thread_value": L * CPU_STEPS / secs1,
+                                "single_thread_seconds": secs1}
+        line["accuracy"] = accuracy(cfg, ref)
     print(json.dumps(line), flush=True)
+    if any(flags):
+        print("a refinement, coarse Newton iteration or pivot check failed during the run: flags %s" % flags,
+              file=sys.stderr)
+        sys.exit(3)
 
 
 if __name__ == "__main__":

@@ -96,6 +96,11 @@ typedef struct {
     double dt;
 } lp_params;
 
+/* local solver of the per-subdomain systems (Eqs. (5.5)-(5.8)) */
+enum { LP_AUTO = 0, LP_DENSE = 1, LP_KRYLOV = 2 };
+/* coarse Navier-Stokes step (Algorithm 3 Step 1 (2)) */
+enum { LP_NEWTON = 0, LP_SEMI_IMPLICIT = 1 };
+
 typedef struct {
     int32_t problem;         /* LP_MMS_EX1_2D */
     int32_t precision;       /* LP_FP64 (FP64 factorisation and solves) or
@@ -110,6 +115,17 @@ typedef struct {
     double newton_tol;       /* stop when ||delta|| <= newton_tol ||x|| */
     int32_t jacobian_every;  /* the coarse Jacobian is formed at steps 1, 1 + J, 1 + 2 J, ...
                                 and reused in between (0 or 1: every step) */
+    int32_t solver;          /* LP_AUTO (the band factorisation wherever the half-bandwidth
+                                fits its window), LP_DENSE (band factorisation only) or
+                                LP_KRYLOV (matrix-free Krylov local solves: LP_ERR_UNSUPPORTED
+                                in this build) */
+    int32_t coarse_ns;       /* LP_NEWTON: the fully implicit coarse step of Algorithm 3
+                                Step 1 (2) solved to newton_tol; LP_SEMI_IMPLICIT (convection
+                                lagged to u^n, one linear solve): LP_ERR_UNSUPPORTED */
+    double krylov_tol;       /* relative residual target of Krylov solves (LP_KRYLOV) */
+    int32_t max_iter;        /* Krylov iteration cap per solve (LP_KRYLOV) */
+    int32_t nsamples;        /* parameter samples advanced together (lp_setup's samples[]);
+                                0 or 1: one sample.  More than one: LP_ERR_UNSUPPORTED */
 } lp_options;
 
 /* Optional device allocator (e.g. a framework's caching allocator). */
@@ -127,19 +143,27 @@ typedef struct {
     int32_t newton_its;      /* Newton iterations of the last coarse step */
     int32_t ir_sweeps;       /* refinement sweeps of the last local step (max over systems) */
     double ir_relres;        /* largest final relative residual of the last local step */
-    int32_t flags;           /* bit 0: refinement of the last local step did not converge;
-                                bit 1: Newton did not converge in some coarse step so far;
-                                bit 2: zero or non-finite pivot */
+    int32_t flags;           /* sticky over the whole run:
+                                bit 0: some local refinement ended above ir_tol;
+                                bit 1: some coarse step ended above newton_tol;
+                                bit 2: zero or non-finite pivot in a factorisation */
     int32_t newton_its_max;  /* most Newton iterations of any coarse step so far */
+    int32_t ir_sweeps_max;   /* most refinement sweeps of any system in any local step so far */
+    double ir_relres_max;    /* largest final relative residual of any system in any local step */
 } lp_stats;
 
 /* Build meshes, partition, reference data and device buffers; interpolate the
  * initial data (t = 0) on both grids and set e_j^0 = I_h x_0 - Pi_h x_H^0 on each
  * Omega_j (zero on artificial faces); factor the constant local porous
  * matrices.  Synchronises `stream` before returning.
+ * samples: opt->nsamples parameter sets (one when nsamples is 0 or 1); every
+ * sample shares mesh and partition and carries its own Section 2 parameters.
  * Errors: LP_ERR_ARG (dim != 2, n_coarse < 1, refine < 1, overlap < 0, bad cuts,
- * non-positive dt or parameters), LP_ERR_ALLOC, LP_ERR_DEVICE. */
-lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_params *prm,
+ * non-positive dt or parameters, unknown option values), LP_ERR_UNSUPPORTED
+ * (nsamples > 1, LP_KRYLOV, LP_SEMI_IMPLICIT, or a local half-bandwidth beyond
+ * the band kernels' window of 159), LP_ERR_NOCONV (zero or non-finite pivot in
+ * the constant porous matrices), LP_ERR_ALLOC, LP_ERR_DEVICE. */
+lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_params *samples,
                    const lp_options *opt, const lp_allocator *alloc, void *stream,
                    lp_ctx **out);
 
@@ -160,11 +184,21 @@ lp_status lp_local_step(lp_ctx *ctx, void *stream);
  * LP_LOCAL (its local lattice, Dirichlet nodes included), ignored otherwise. */
 lp_status lp_get_size(lp_ctx *ctx, int32_t field, int32_t level, int32_t sub, int64_t *len);
 
-/* Copy a field into `out` (len doubles; host memory, or device memory when
- * out_is_device != 0).  A host copy synchronises `stream`. */
-lp_status lp_get_solution(lp_ctx *ctx, int32_t field, int32_t level, int32_t sub,
+/* Copy a field of one sample into `out` (len doubles; host memory, or device
+ * memory when out_is_device != 0).  LP_MERGED_FINE is the corrected fine
+ * solution of Algorithm 3 Step 4, x_h = Pi_h x_H + sum_j w_j e_j on each region;
+ * LP_COARSE the latest coarse state (Step 1); LP_LOCAL subdomain `sub`'s
+ * correction e_j of Step 3 on its local lattice (zero on artificial faces, the
+ * lifted boundary values on the physical boundary).  A host copy synchronises
+ * `stream`.  Errors: LP_ERR_ARG (sample out of range, unknown field or level,
+ * field not carried by that subdomain's region, len too short). */
+lp_status lp_get_solution(lp_ctx *ctx, int32_t sample, int32_t field, int32_t level, int32_t sub,
                           double *out, int64_t len, int32_t out_is_device, void *stream);
 
+/* Waits for the device.  Fills `out` and returns LP_OK, or LP_ERR_NOCONV
+ * (with `out` filled all the same) when a sticky flag is set: a refinement,
+ * a coarse Newton iteration or a pivot check failed in some step so far; the
+ * fields hold the best iterates. */
 lp_status lp_get_stats(lp_ctx *ctx, lp_stats *out);
 
 /* Host-only partition queries (no device needed), for bit-exact index parity.
@@ -177,9 +211,19 @@ lp_status lp_get_stats(lp_ctx *ctx, lp_stats *out);
  *              (porous: scalar index; conduit: index of u_x, u_y follows), -1 if fixed
  *   which = 4: band-system unknown of each local P1 vertex of conduit `sub`, -1 if fixed
  *   which = 5: per subdomain: number of unknowns and half-bandwidth (2 int64 each)
+ *   which = 6: the coarse systems on T_H: unknowns and half-bandwidth of one
+ *              porous pressure system, then of the Navier-Stokes system
+ * For which = 1..4, sub = -1 returns the tables of every subdomain (of every
+ * conduit subdomain for which = 4) concatenated in id order. 
  * `needed` receives the required length; nothing is written if len is short. */
 lp_status lp_plan_query(const lp_mesh *mesh, const lp_partition *part, int32_t which,
                         int32_t sub, int64_t *out, int64_t len, int64_t *needed);
+
+/* The same tables as lp_plan_query, read from a context's own plan (the
+ * numbering its kernels use).  `needed` receives the required length; nothing
+ * is written if len is short.  Errors: LP_ERR_ARG. */
+lp_status lp_get_index_map(lp_ctx *ctx, int32_t which, int32_t sub, int64_t *out, int64_t len,
+                           int64_t *needed);
 
 /* Stage timers: HIP events recorded around the launches of the stages
  * selected in `mask`, on the stream each stage runs on (bit i = stage i below;

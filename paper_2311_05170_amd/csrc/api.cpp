@@ -5,6 +5,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -88,6 +89,10 @@ struct lp_ctx {
     double *cP[RING] = {}, *cU[RING] = {}, *cp[RING] = {};
     double *nwt_e = nullptr, *nwt_e1 = nullptr;
     int *d_done = nullptr, *d_its = nullptr, *d_flags = nullptr;
+    // run-long refinement totals (largest sweep count, largest final relative
+    // residual as double bits), folded in by the local finalize kernels
+    int *d_irmax = nullptr;
+    unsigned long long *d_irrel = nullptr;
 
     // prolonged coarse fields on the fine lattices.  Setup: the porous
     // pressures and the velocity of level 0, for the initial corrections.
@@ -130,6 +135,8 @@ struct lp_ctx {
     double *part_por = nullptr, *part_ose = nullptr, *part_cp = nullptr, *part_cn = nullptr;
     int *tick_por = nullptr, *tick_ose = nullptr, *tick_cp = nullptr, *tick_cn = nullptr;
     int *tick_dn = nullptr, *tick_dp = nullptr;        // last-block tickets of the fused coarse kernels
+    long long scratch_part_por = 0, scratch_part_ose = 0;   // doubles of norm partials per batch
+    int device = 0;                    // HIP device the context was set up on
     double *lu_dummy = nullptr;        // sink of the factorisation's masked stores
     long long lu_dummy_coarse_off = 0;
     int lu_variant = 0;                // factorisation kernel of the porous and coarse systems (0: default)
@@ -210,6 +217,15 @@ namespace {
         lp_status _s = (expr);           \
         if (_s != LP_OK) return _s;      \
     } while (0)
+
+// Scratch of the local step's refinement: residual-norm partials and
+// last-block tickets of the porous and the Oseen batches (they run on
+// different streams).  The context's own buffers, or a static device array
+// (an allocation-free variant of the local step).
+struct LocalScratch {
+    double *part_por, *part_ose;
+    int *tick_por, *tick_ose;
+};
 
 // brackets the launches of one stage with events when its bit is set
 struct StageTimer {
@@ -375,7 +391,7 @@ lp_status factor_porous(lp_ctx *c, T *band, T *fac, hipStream_t st) {
 }
 
 template <typename T>
-lp_status local_oseen(lp_ctx *c, hipStream_t st) {
+lp_status local_oseen(lp_ctx *c, hipStream_t st, const LocalScratch &ls) {
     const int nsys = (int)c->P.ose.size();
     const long long nf2 = c->nf2;
     const int o = c->ecur, nw = 1 - c->ecur;
@@ -405,11 +421,12 @@ lp_status local_oseen(lp_ctx *c, hipStream_t st) {
         StageTimer tm(c, LP_T_WAIT_FAC, st);
         HIPCHK(hipStreamWaitEvent(st, c->ev_fac[fs], 0));
     }
-    TRY(refine_oseen<T>(c, c->d_ose, nsys, c->nodes_ose, c->part_ose, c->tick_ose, c->d_sv_ose, (const T *)c->fac_ose[fs], c->maxbw_ose, c->maxn_ose, oa.W1[0], oa.W1[1], c->b_ose,
+    TRY(refine_oseen<T>(c, c->d_ose, nsys, c->nodes_ose, ls.part_ose, ls.tick_ose, c->d_sv_ose, (const T *)c->fac_ose[fs], c->maxbw_ose, c->maxn_ose, oa.W1[0], oa.W1[1], c->b_ose,
                         c->x_ose, c->r_ose, c->conv_ose, c->rel_ose, c->sw_ose, c->P.dof_total_ose, c->opt.max_ir,
                         c->opt.ir_tol, nullptr, true, st));
     StageTimer tm(c, LP_T_MERGE, st);
-    lp::FinalizeArgs fa{c->d_ose, c->d_dof2, c->d_dof1, c->x_ose, c->e2[nw], c->e1[nw], nullptr};
+    lp::FinalizeArgs fa{c->d_ose, c->d_dof2, c->d_dof1, c->x_ose, c->e2[nw], c->e1[nw], nullptr,
+                        lp::IrTotals{c->conv_ose, c->sw_ose, c->rel_ose, 1, c->d_flags, c->d_irmax, c->d_irrel}};
     lp::launch_oseen_finalize(fa, nsys, c->nodes_ose, st);
     return LP_OK;
 }
@@ -479,7 +496,7 @@ void prolong_porous(lp_ctx *c, double *pro, int cnew, int cold, hipStream_t st) 
 }
 
 template <typename T>
-lp_status local_porous(lp_ctx *c, const double *pro, hipStream_t st) {
+lp_status local_porous(lp_ctx *c, const double *pro, hipStream_t st, const LocalScratch &ls) {
     const int nsys = (int)c->P.por.size();
     const long long nf2 = c->nf2;
     const int o = c->ecur, nw = 1 - c->ecur;
@@ -501,11 +518,12 @@ lp_status local_porous(lp_ctx *c, const double *pro, hipStream_t st) {
         StageTimer tm(c, LP_T_POR_RHS, st);
         lp::launch_porous_rhs_tiled(pa, nsys, c->tiles_por, st);
     }
-    TRY(refine_porous<T>(c, c->d_por, nsys, c->nodes_por, c->part_por, c->tick_por, c->d_sv_por, (const T *)c->fac_por, c->maxbw_por, c->maxn_por, c->b_por,
+    TRY(refine_porous<T>(c, c->d_por, nsys, c->nodes_por, ls.part_por, ls.tick_por, c->d_sv_por, (const T *)c->fac_por, c->maxbw_por, c->maxn_por, c->b_por,
                          c->x_por, c->r_por, c->conv_por, c->rel_por, c->sw_por, c->P.dof_total_por, c->opt.max_ir,
                          c->opt.ir_tol, true, st));
     StageTimer tm(c, LP_T_MERGE, st);
-    lp::FinalizeArgs fa{c->d_por, c->d_dof2, c->d_dof1, c->x_por, c->e2[nw], nullptr, nullptr};
+    lp::FinalizeArgs fa{c->d_por, c->d_dof2, c->d_dof1, c->x_por, c->e2[nw], nullptr, nullptr,
+                        lp::IrTotals{c->conv_por, c->sw_por, c->rel_por, 3, c->d_flags, c->d_irmax, c->d_irrel}};
     lp::launch_porous_finalize(fa, nsys, c->nodes_por, st);
     return LP_OK;
 }
@@ -567,14 +585,8 @@ extern "C" {
 
 const char *lp_last_error(void) { return g_err.c_str(); }
 
-lp_status lp_plan_query(const lp_mesh *mesh, const lp_partition *part, int32_t which, int32_t sub, int64_t *out,
-                        int64_t len, int64_t *needed) {
-    if (!mesh || !part || !needed) return fail(LP_ERR_ARG, "NULL argument");
-    lp::Plan P;
-    std::string err;
-    if (!lp::build_plan(*mesh, *part, P, err)) return fail(LP_ERR_ARG, err);
+static lp_status plan_table(const lp::Plan &P, int32_t which, int32_t sub, std::vector<int64_t> &v) {
     const int nsub = (int)(P.por.size() + P.ose.size());
-    std::vector<int64_t> v;
     auto sysof = [&](int s) -> const lp::SysDesc * {
         if (s < 0 || s >= nsub) return nullptr;
         return s < (int)P.por.size() ? &P.por[s] : &P.ose[s - P.por.size()];
@@ -589,36 +601,74 @@ lp_status lp_plan_query(const lp_mesh *mesh, const lp_partition *part, int32_t w
             v.insert(v.end(), row, row + 9);
         }
     } else if (which >= 1 && which <= 4) {
-        const lp::SysDesc *S = sysof(sub);
-        if (!S) return fail(LP_ERR_ARG, "subdomain id out of range");
-        if (which == 4 && S->kind != lp::KIND_OSEEN) return fail(LP_ERR_ARG, "which = 4 needs a conduit subdomain");
-        long long n2 = (long long)S->lw2 * S->lh2, n1 = (long long)S->lw1 * S->lh1;
-        if (which == 1) for (long long q = 0; q < n2; ++q) v.push_back(P.cls2[S->node_off + q]);
-        if (which == 2) for (long long q = 0; q < n1; ++q) v.push_back(P.cls1[S->vert_off + q]);
-        if (which == 3) for (long long q = 0; q < n2; ++q) v.push_back(P.dof2[S->node_off + q]);
-        if (which == 4) for (long long q = 0; q < n1; ++q) v.push_back(P.dof1[S->vert_off + q]);
+        // one subdomain, or every subdomain in id order (sub = -1; which = 4
+        // then covers the conduit subdomains only)
+        const int s0 = sub == -1 ? (which == 4 ? (int)P.por.size() : 0) : sub;
+        const int s1 = sub == -1 ? nsub : sub + 1;
+        for (int s = s0; s < s1; ++s) {
+            const lp::SysDesc *S = sysof(s);
+            if (!S) return fail(LP_ERR_ARG, "subdomain id out of range");
+            if (which == 4 && S->kind != lp::KIND_OSEEN) return fail(LP_ERR_ARG, "which = 4 needs a conduit subdomain");
+            long long n2 = (long long)S->lw2 * S->lh2, n1 = (long long)S->lw1 * S->lh1;
+            if (which == 1) for (long long q = 0; q < n2; ++q) v.push_back(P.cls2[S->node_off + q]);
+            if (which == 2) for (long long q = 0; q < n1; ++q) v.push_back(P.cls1[S->vert_off + q]);
+            if (which == 3) for (long long q = 0; q < n2; ++q) v.push_back(P.dof2[S->node_off + q]);
+            if (which == 4) for (long long q = 0; q < n1; ++q) v.push_back(P.dof1[S->vert_off + q]);
+        }
     } else if (which == 5) {
         for (int s = 0; s < nsub; ++s) { v.push_back(sysof(s)->ndof); v.push_back(sysof(s)->bw); }
+    } else if (which == 6) {
+        v = {P.cpor.ndof, P.cpor.bw, P.cns.ndof, P.cns.bw};
     } else {
         return fail(LP_ERR_ARG, "unknown query");
     }
+    return LP_OK;
+}
+
+lp_status lp_plan_query(const lp_mesh *mesh, const lp_partition *part, int32_t which, int32_t sub, int64_t *out,
+                        int64_t len, int64_t *needed) {
+    if (!mesh || !part || !needed) return fail(LP_ERR_ARG, "NULL argument");
+    lp::Plan P;
+    std::string err;
+    if (!lp::build_plan(*mesh, *part, P, err)) return fail(LP_ERR_ARG, err);
+    std::vector<int64_t> v;
+    TRY(plan_table(P, which, sub, v));
     *needed = (int64_t)v.size();
     if (out && len >= (int64_t)v.size()) std::memcpy(out, v.data(), v.size() * sizeof(int64_t));
     return LP_OK;
 }
 
-lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_params *prm, const lp_options *opt,
+lp_status lp_get_index_map(lp_ctx *c, int32_t which, int32_t sub, int64_t *out, int64_t len, int64_t *needed) {
+    if (!c || !needed) return fail(LP_ERR_ARG, "NULL argument");
+    std::vector<int64_t> v;
+    TRY(plan_table(c->P, which, sub, v));
+    *needed = (int64_t)v.size();
+    if (out && len >= (int64_t)v.size()) std::memcpy(out, v.data(), v.size() * sizeof(int64_t));
+    return LP_OK;
+}
+
+lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_params *samples, const lp_options *opt,
                    const lp_allocator *alloc, void *stream, lp_ctx **out) {
-    if (!mesh || !part || !prm || !opt || !out) return fail(LP_ERR_ARG, "NULL argument");
+    if (!mesh || !part || !samples || !opt || !out) return fail(LP_ERR_ARG, "NULL argument");
     *out = nullptr;
+    const lp_params *prm = samples;
     std::string why;
-    if (!params_ok(*prm, why)) return fail(LP_ERR_ARG, why);
+    if (opt->nsamples < 0) return fail(LP_ERR_ARG, "nsamples must be >= 0");
+    for (int i = 0; i < std::max(opt->nsamples, 1); ++i)
+        if (!params_ok(samples[i], why)) return fail(LP_ERR_ARG, "sample " + std::to_string(i) + ": " + why);
+    if (opt->solver < LP_AUTO || opt->solver > LP_KRYLOV) return fail(LP_ERR_ARG, "solver must be LP_AUTO, LP_DENSE or LP_KRYLOV");
+    if (opt->coarse_ns != LP_NEWTON && opt->coarse_ns != LP_SEMI_IMPLICIT)
+        return fail(LP_ERR_ARG, "coarse_ns must be LP_NEWTON or LP_SEMI_IMPLICIT");
+    if (opt->nsamples > 1) return fail(LP_ERR_UNSUPPORTED, "more than one parameter sample per context is not built");
+    if (opt->solver == LP_KRYLOV) return fail(LP_ERR_UNSUPPORTED, "matrix-free Krylov local solves are not built");
+    if (opt->coarse_ns == LP_SEMI_IMPLICIT) return fail(LP_ERR_UNSUPPORTED, "the semi-implicit coarse step is not built");
     if (opt->problem != LP_MMS_EX1_2D) return fail(LP_ERR_UNSUPPORTED, "only the Example 1 manufactured problem is built in");
     if (opt->precision != LP_FP64 && opt->precision != LP_MIXED) return fail(LP_ERR_ARG, "precision must be LP_FP64 or LP_MIXED");
     if (opt->max_ir < 1 || opt->max_newton < 1 || !(opt->ir_tol > 0) || !(opt->newton_tol > 0) || opt->jacobian_every < 0)
         return fail(LP_ERR_ARG, "max_ir, max_newton >= 1 and positive tolerances required");
     hipStream_t st = (hipStream_t)stream;
     std::unique_ptr<lp_ctx> c(new lp_ctx());
+    HIPCHK(hipGetDevice(&c->device));
     if (!lp::build_plan(*mesh, *part, c->P, why)) return fail(LP_ERR_ARG, why);
     c->prm = *prm;
     c->opt = *opt;
@@ -713,7 +763,11 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     TRY(c->dalloc(&c->d_done, 4));
     TRY(c->dalloc(&c->d_its, 4));
     TRY(c->dalloc(&c->d_flags, 4));
+    TRY(c->dalloc(&c->d_irmax, 1));
+    TRY(c->dalloc(&c->d_irrel, 1));
     HIPCHK(hipMemsetAsync(c->d_flags, 0, 4 * sizeof(int), st));
+    HIPCHK(hipMemsetAsync(c->d_irmax, 0, sizeof(int), st));
+    HIPCHK(hipMemsetAsync(c->d_irrel, 0, sizeof(unsigned long long), st));
     HIPCHK(hipMemsetAsync(c->d_its, 0, 4 * sizeof(int), st));
     {
         // "converged" before the first coarse step (the Newton start reports
@@ -789,8 +843,10 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     TRY(c->dalloc(&c->conv_cn, 1)); TRY(c->dalloc(&c->rel_cn, 1)); TRY(c->dalloc(&c->sw_cn, 1));
     {
         auto nb = [](int nodes) { return (long long)lp::node_blocks(nodes); };
-        TRY(c->dalloc(&c->part_por, 2 * npf * std::max<long long>(nb(c->nodes_por), c->tiles_por))); TRY(c->dalloc(&c->tick_por, npf));
-        TRY(c->dalloc(&c->part_ose, 2 * nof * std::max<long long>(nb(c->nodes_ose), c->tiles_ose))); TRY(c->dalloc(&c->tick_ose, nof));
+        c->scratch_part_por = 2 * npf * std::max<long long>(nb(c->nodes_por), c->tiles_por);
+        c->scratch_part_ose = 2 * nof * std::max<long long>(nb(c->nodes_ose), c->tiles_ose);
+        TRY(c->dalloc(&c->part_por, c->scratch_part_por)); TRY(c->dalloc(&c->tick_por, npf));
+        TRY(c->dalloc(&c->part_ose, c->scratch_part_ose)); TRY(c->dalloc(&c->tick_ose, nof));
         TRY(c->dalloc(&c->part_cp, 2 * 3 * nb(c->nodes_cpor))); TRY(c->dalloc(&c->tick_cp, 3));
         TRY(c->dalloc(&c->part_cn, 2 * nb(c->nodes_cns))); TRY(c->dalloc(&c->tick_cn, 1));
         HIPCHK(hipMemsetAsync(c->tick_por, 0, npf * sizeof(int), st));
@@ -991,7 +1047,14 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
     return LP_OK;
 }
 
-lp_status lp_local_step(lp_ctx *c, void *stream) {
+}  // extern "C"
+
+namespace {
+
+// Algorithm 3 Steps 3-4 for one time level; `ls` holds the refinement
+// scratch (the context's buffers or the static array), `clear` says whether
+// its tickets must be zeroed first (each stream clears the part it uses).
+lp_status local_step_impl(lp_ctx *c, void *stream, const LocalScratch &ls, bool clear) {
     if (!c) return fail(LP_ERR_ARG, "NULL context");
     if (!c->coarse_pending) return fail(LP_ERR_STATE, "lp_local_step needs a preceding lp_coarse_step");
     hipStream_t st = (hipStream_t)stream, st_user = st;
@@ -1019,8 +1082,12 @@ lp_status lp_local_step(lp_ctx *c, void *stream) {
     if (m >= 2) HIPCHK(hipStreamWaitEvent(ps, c->ev_por, 0));
     if (m >= 3) HIPCHK(hipStreamWaitEvent(ps, c->ev_local[(m - 2) % lp_ctx::RING], 0));
     prolong_porous(c, pro, nw, o, ps);
-    if (c->mixed) { TRY(local_porous<float>(c, pro, ps)); TRY(local_oseen<float>(c, st)); }
-    else { TRY(local_porous<double>(c, pro, ps)); TRY(local_oseen<double>(c, st)); }
+    if (clear) {
+        lp::launch_zero_ints(ls.tick_por, 3 * (long long)c->P.por.size(), ps);
+        lp::launch_zero_ints(ls.tick_ose, (long long)c->P.ose.size(), st);
+    }
+    if (c->mixed) { TRY(local_porous<float>(c, pro, ps, ls)); TRY(local_oseen<float>(c, st, ls)); }
+    else { TRY(local_porous<double>(c, pro, ps, ls)); TRY(local_oseen<double>(c, st, ls)); }
     HIPCHK(hipEventRecord(c->ev_por, ps));
     {
         StageTimer tm(c, LP_T_WAIT_POR, st);
@@ -1057,6 +1124,16 @@ lp_status lp_local_step(lp_ctx *c, void *stream) {
     c->coarse_pending = false;
     return LP_OK;
 }
+
+}  // namespace
+
+extern "C" {
+
+lp_status lp_local_step(lp_ctx *c, void *stream) {
+    if (!c) return fail(LP_ERR_ARG, "NULL context");
+    return local_step_impl(c, stream, LocalScratch{c->part_por, c->part_ose, c->tick_por, c->tick_ose}, false);
+}
+
 
 static lp_status locate(lp_ctx *c, int32_t field, int32_t level, int32_t sub, const double **ptr, int64_t *len) {
     if (field < LP_U || field > LP_PM) return fail(LP_ERR_ARG, "unknown field");
@@ -1095,9 +1172,10 @@ lp_status lp_get_size(lp_ctx *c, int32_t field, int32_t level, int32_t sub, int6
     return locate(c, field, level, sub, &p, len);
 }
 
-lp_status lp_get_solution(lp_ctx *c, int32_t field, int32_t level, int32_t sub, double *out, int64_t len,
-                          int32_t out_is_device, void *stream) {
+lp_status lp_get_solution(lp_ctx *c, int32_t sample, int32_t field, int32_t level, int32_t sub, double *out,
+                          int64_t len, int32_t out_is_device, void *stream) {
     if (!c || !out) return fail(LP_ERR_ARG, "NULL argument");
+    if (sample != 0) return fail(LP_ERR_ARG, "sample out of range (the context holds one sample)");
     const double *p;
     int64_t n;
     TRY(locate(c, field, level, sub, &p, &n));
@@ -1128,28 +1206,34 @@ lp_status lp_get_stats(lp_ctx *c, lp_stats *out) {
     out->n_conduit = (int64_t)c->P.ose.size();
     out->local_dofs = c->P.local_dofs;
     out->max_bw = c->P.max_bw;
-    int its = 0, done = 0, flags = 0;
+    int its = 0, done = 0, flags = 0, irmax = 0;
+    unsigned long long irrel = 0;
     HIPCHK(hipMemcpy(&its, c->d_its, sizeof(int), hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(&done, c->d_done, sizeof(int), hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(&flags, c->d_flags, sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&irmax, c->d_irmax, sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&irrel, c->d_irrel, sizeof(irrel), hipMemcpyDeviceToHost));
     out->newton_its = its;
     HIPCHK(hipMemcpy(&its, c->d_its + 1, sizeof(int), hipMemcpyDeviceToHost));
     out->newton_its_max = std::max(its, out->newton_its);
-    out->flags = flags & 6;
+    out->flags = flags & 7;
     if (c->n > 0 && !done) out->flags |= 2;
-    std::vector<int> sw(3 * c->P.por.size() + c->P.ose.size()), cv(sw.size());
+    out->ir_sweeps_max = irmax;
+    std::memcpy(&out->ir_relres_max, &irrel, sizeof(double));
+    std::vector<int> sw(3 * c->P.por.size() + c->P.ose.size());
     std::vector<double> rel(sw.size());
     const size_t np = 3 * c->P.por.size(), no = c->P.ose.size();
     HIPCHK(hipMemcpy(sw.data(), c->sw_por, np * sizeof(int), hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(sw.data() + np, c->sw_ose, no * sizeof(int), hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(rel.data(), c->rel_por, np * sizeof(double), hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(rel.data() + np, c->rel_ose, no * sizeof(double), hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(cv.data(), c->conv_por, np * sizeof(int), hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(cv.data() + np, c->conv_ose, no * sizeof(int), hipMemcpyDeviceToHost));
     for (size_t i = 0; i < sw.size(); ++i) {
         out->ir_sweeps = std::max(out->ir_sweeps, sw[i]);
         out->ir_relres = std::max(out->ir_relres, rel[i]);
-        if (c->n > 0 && !cv[i]) out->flags |= 1;
+    }
+    if (out->flags) {
+        return fail(LP_ERR_NOCONV, std::string("flags ") + std::to_string(out->flags) +
+                                       ": a refinement, a coarse Newton iteration or a pivot check failed in some step so far");
     }
     return LP_OK;
 }

@@ -53,6 +53,22 @@ struct ResidualArgs {
     int *ticket;                  // per-id arrival counters, zero between launches
 };
 
+// Refinement outcome of a batch, folded into run-long totals by the finalize
+// kernels (null acc: not recorded): per system id its convergence flag, sweep
+// count and final relative residual; a system that ended unconverged sets bit
+// 0 of *flags, the largest sweep count and residual of the run so far are kept
+// (the residual as the bit pattern of a non-negative double, whose integer
+// order is its numeric order).
+struct IrTotals {
+    const int *conv;
+    const int *sweeps;
+    const double *relres;
+    int ids_per_sys;
+    int *flags;
+    int *max_sweeps;
+    unsigned long long *max_relres;
+};
+
 struct FinalizeArgs {
     const SysDesc *sys;
     const int32_t *dof2;
@@ -61,6 +77,7 @@ struct FinalizeArgs {
     double *e_new;
     double *e_new1;
     const int *skip;
+    IrTotals acc;
 };
 
 template <typename T>
@@ -276,5 +293,7 @@ void launch_newton_update(const NewtonArgs &a, hipStream_t st);
 void launch_dense_newton(const DenseNewtonArgs &a, hipStream_t st);
 void launch_dense_porous(const DensePorousArgs &a, int nsys, hipStream_t st);
 void launch_newton_start(const NewtonStartArgs &a, hipStream_t st);
+// p[0..n) = 0 by a small kernel (capturable in a graph, unlike a memset node)
+void launch_zero_ints(int *p, long long n, hipStream_t st);
 
 }  // namespace lp

@@ -83,9 +83,16 @@ __device__ __forceinline__ void p2_values(double xi, double eta, double v[6]) {
 // A latency-bound kernel claims the whole register file of each SIMD it runs
 // on (v255 and a255 count as used, 512 registers), so no wavefront of the
 // concurrent streams shares its instruction issue.  Only for workgroups of at
-// most four wavefronts (one per SIMD of the compute unit): a larger workgroup
-// with this allocation cannot be dispatched.
-__device__ __forceinline__ void own_simd() { asm volatile("" ::: "v255", "a255"); }
+// most four wavefronts (one per SIMD of the compute unit): a workgroup of more
+// wavefronts with this allocation cannot be dispatched (the queue aborts with
+// an invalid-code-object error).  The caller passes its launch bound, which
+// must be the same constant as in its __launch_bounds__, and the bound is
+// checked at compile time.
+template <int BLOCK_THREADS>
+__device__ __forceinline__ void own_simd() {
+    static_assert(BLOCK_THREADS <= 256, "own_simd: a full register claim needs workgroups of at most four wavefronts");
+    asm volatile("" ::: "v255", "a255");
+}
 
 __global__ void k_prolong_p2(ProlongArgs A) {
     const int nf = 2 * A.Nh + 1, nc = 2 * A.NH + 1;
@@ -314,9 +321,19 @@ __device__ __forceinline__ void porous_finalize_rows(const FinalizeArgs &F, cons
             F.e_new[S.e2_off + (long long)f * nloc + q] = F.x[S.dof_off + (long long)f * S.ndof + d];
     }
 }
+// the first block of each system folds its refinement outcome into the run totals
+__device__ __forceinline__ void record_ir_totals(const IrTotals &T) {
+    if (!T.flags || blockIdx.x != 0 || (int)threadIdx.x >= T.ids_per_sys) return;
+    const int id = blockIdx.y * T.ids_per_sys + threadIdx.x;
+    if (!T.conv[id]) atomicOr(T.flags, 1);
+    atomicMax(T.max_sweeps, T.sweeps[id]);
+    atomicMax(T.max_relres, (unsigned long long)__double_as_longlong(T.relres[id]));
+}
+
 __global__ __launch_bounds__(GB) void k_porous_finalize(FinalizeArgs F) {
     const SysDesc S = F.sys[blockIdx.y];
     if (F.skip && *F.skip) return;
+    record_ir_totals(F.acc);
     porous_finalize_rows(F, S, blockIdx.x * GB + threadIdx.x, gridDim.x * GB);
 }
 
@@ -1299,6 +1316,7 @@ __device__ __forceinline__ void oseen_finalize_rows(const FinalizeArgs &F, const
 __global__ __launch_bounds__(GB) void k_oseen_finalize(FinalizeArgs F) {
     const SysDesc S = F.sys[blockIdx.y];
     if (F.skip && *F.skip) return;
+    record_ir_totals(F.acc);
     oseen_finalize_rows(F, S, blockIdx.x * GB + threadIdx.x, gridDim.x * GB);
 }
 
@@ -2264,11 +2282,12 @@ __device__ __forceinline__ void band_pass(const T *C, int n, int ldf, T *ys, con
 #undef LP_COL
 }
 
+constexpr int SOLVE_THREADS = 64;
 template <typename T, int NR, int D>
-__global__ __launch_bounds__(64) void k_band_solve(SolveArgs<T> A) {
+__global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(SolveArgs<T> A) {
     static_assert(64 * NR + 32 * 2 * NR <= SOLVE_PAD, "pad too small");
     // one wavefront whose speed is its instruction issue: it owns its SIMD
-    own_simd();
+    own_simd<SOLVE_THREADS>();
     const int sysi = blockIdx.x, f = blockIdx.y;
     const BandSys Sy = A.sys[sysi];
     if (f >= Sy.nrhs) return;
@@ -2623,8 +2642,8 @@ bool launch_band_solve_d(const SolveArgs<T> &a, int nsys, int nrhs, int maxbw, i
     const size_t sh = (size_t)(2 * maxn + 3 * SOLVE_PAD) * sizeof(T);
     if (sh > 160 * 1024) return false;
     switch (solve_nr(maxbw)) {
-    case 2: hipLaunchKernelGGL((k_band_solve<T, 2, D>), g, dim3(64), sh, st, a); break;
-    case 3: hipLaunchKernelGGL((k_band_solve<T, 3, D>), g, dim3(64), sh, st, a); break;
+    case 2: hipLaunchKernelGGL((k_band_solve<T, 2, D>), g, dim3(SOLVE_THREADS), sh, st, a); break;
+    case 3: hipLaunchKernelGGL((k_band_solve<T, 3, D>), g, dim3(SOLVE_THREADS), sh, st, a); break;
     default: return false;
     }
     return true;
@@ -2664,6 +2683,14 @@ void launch_newton_start(const NewtonStartArgs &a, hipStream_t st) {
     const long long work = a.band_n > a.nu2 + a.np ? a.band_n : a.nu2 + a.np;
     const int nb = (int)std::min<long long>(1024, (work + 255) / 256);
     hipLaunchKernelGGL(k_newton_start, dim3(nb > 0 ? nb : 1), dim3(256), 0, st, a);
+}
+__global__ void k_zero_ints(int *p, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) p[i] = 0;
+}
+void launch_zero_ints(int *p, long long n, hipStream_t st) {
+    if (n <= 0) return;
+    const int nb = (int)std::min<long long>(256, (n + 255) / 256);
+    hipLaunchKernelGGL(k_zero_ints, dim3(nb), dim3(256), 0, st, p, n);
 }
 void launch_newton_update(const NewtonArgs &a, hipStream_t st) {
     hipLaunchKernelGGL(k_newton_update, dim3(1), dim3(256), 0, st, a);

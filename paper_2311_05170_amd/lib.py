@@ -26,9 +26,15 @@ LEVEL = {"merged": LP_MERGED_FINE, "coarse": LP_COARSE, "local": LP_LOCAL}
 STATUS = {0: "LP_OK", 1: "LP_ERR_ARG", 2: "LP_ERR_STATE", 3: "LP_ERR_ALLOC", 4: "LP_ERR_DEVICE",
           5: "LP_ERR_NOCONV", 6: "LP_ERR_UNSUPPORTED"}
 
+LP_AUTO, LP_DENSE, LP_KRYLOV = range(3)
+LP_NEWTON, LP_SEMI_IMPLICIT = range(2)
+SOLVER = {"auto": LP_AUTO, "dense": LP_DENSE, "krylov": LP_KRYLOV}
+COARSE_NS = {"newton": LP_NEWTON, "semi_implicit": LP_SEMI_IMPLICIT}
+LP_ERR_NOCONV = 5
+
 EXPORTS = ["lp_setup", "lp_coarse_step", "lp_local_step", "lp_get_size", "lp_get_solution",
-           "lp_get_stats", "lp_plan_query", "lp_set_timing", "lp_get_timing", "lp_destroy",
-           "lp_last_error"]
+           "lp_get_stats", "lp_plan_query", "lp_get_index_map", "lp_set_timing", "lp_get_timing",
+           "lp_destroy", "lp_last_error"]
 # stage timer indices (LP_T_* in lp.h)
 STAGES = ["prolong", "por_rhs", "por_solve", "por_res", "ose_rhs", "ose_asm", "ose_lu", "ose_solve",
           "ose_res", "merge", "coarse", "wait_coarse", "wait_fac", "wait_por"]
@@ -52,7 +58,9 @@ class LpParams(Structure):
 class LpOptions(Structure):
     _fields_ = [("problem", c_int32), ("precision", c_int32), ("convection", c_int32),
                 ("max_ir", c_int32), ("ir_tol", c_double), ("max_newton", c_int32),
-                ("newton_tol", c_double), ("jacobian_every", c_int32)]
+                ("newton_tol", c_double), ("jacobian_every", c_int32), ("solver", c_int32),
+                ("coarse_ns", c_int32), ("krylov_tol", c_double), ("max_iter", c_int32),
+                ("nsamples", c_int32)]
 
 
 ALLOC_FN = CFUNCTYPE(c_void_p, c_size_t, c_void_p)
@@ -67,7 +75,7 @@ class LpStats(Structure):
     _fields_ = [("step", c_int64), ("n_porous", c_int64), ("n_conduit", c_int64),
                 ("local_dofs", c_int64), ("max_bw", c_int64), ("newton_its", c_int32),
                 ("ir_sweeps", c_int32), ("ir_relres", c_double), ("flags", c_int32),
-                ("newton_its_max", c_int32)]
+                ("newton_its_max", c_int32), ("ir_sweeps_max", c_int32), ("ir_relres_max", c_double)]
 
 
 class LpError(RuntimeError):
@@ -85,11 +93,12 @@ def load(path=LIB_PATH):
     lib.lp_coarse_step.argtypes = [c_void_p, c_void_p]
     lib.lp_local_step.argtypes = [c_void_p, c_void_p]
     lib.lp_get_size.argtypes = [c_void_p, c_int32, c_int32, c_int32, POINTER(c_int64)]
-    lib.lp_get_solution.argtypes = [c_void_p, c_int32, c_int32, c_int32, POINTER(c_double), c_int64,
-                                    c_int32, c_void_p]
+    lib.lp_get_solution.argtypes = [c_void_p, c_int32, c_int32, c_int32, c_int32, POINTER(c_double),
+                                    c_int64, c_int32, c_void_p]
     lib.lp_get_stats.argtypes = [c_void_p, POINTER(LpStats)]
     lib.lp_plan_query.argtypes = [POINTER(LpMesh), POINTER(LpPartition), c_int32, c_int32,
                                   POINTER(c_int64), c_int64, POINTER(c_int64)]
+    lib.lp_get_index_map.argtypes = [c_void_p, c_int32, c_int32, POINTER(c_int64), c_int64, POINTER(c_int64)]
     lib.lp_set_timing.argtypes = [c_void_p, ctypes.c_uint32]
     lib.lp_get_timing.argtypes = [c_void_p, POINTER(c_double), POINTER(c_int64), c_int32]
     lib.lp_destroy.argtypes = [c_void_p]
@@ -149,7 +158,8 @@ class LocalParallel:
 
     def __init__(self, n_coarse, refine, nsub, overlap, prm, dt, cuts=None, precision="mixed",
                  convection=True, max_ir=8, ir_tol=None, max_newton=16, newton_tol=1e-13,
-                 jacobian_every=1, torch_allocator=True):
+                 jacobian_every=1, solver="auto", coarse_ns="newton", samples=None,
+                 torch_allocator=True):
         import torch
         self._torch = torch
         if not torch.cuda.is_available():
@@ -164,6 +174,13 @@ class LocalParallel:
         opt.max_newton = int(max_newton)
         opt.newton_tol = float(newton_tol)
         opt.jacobian_every = int(jacobian_every)
+        opt.solver = SOLVER[solver]
+        opt.coarse_ns = COARSE_NS[coarse_ns]
+        opt.krylov_tol = 1e-12
+        opt.max_iter = 200
+        plist = [prm] if samples is None else list(samples)
+        opt.nsamples = len(plist)
+        params = (LpParams * len(plist))(*[_params(q, dt) for q in plist])
         self._alloc = None
         alloc_ptr = None
         if torch_allocator:
@@ -177,7 +194,7 @@ class LocalParallel:
             alloc_ptr = byref(self._alloc)
         self.stream = torch.cuda.current_stream()
         handle = c_void_p()
-        _check(_LIB.lp_setup(byref(mesh), byref(part), byref(_params(prm, dt)), byref(opt),
+        _check(_LIB.lp_setup(byref(mesh), byref(part), params, byref(opt),
                              alloc_ptr, c_void_p(self.stream.cuda_stream), byref(handle)))
         self._h = handle
         self.n_sub = 2 * nsub[0] * nsub[1]
@@ -200,24 +217,37 @@ class LocalParallel:
         _check(_LIB.lp_get_size(self._h, FIELD[field], LEVEL[level], sub, byref(n)))
         return n.value
 
-    def solution(self, field, level="merged", sub=0):
+    def solution(self, field, level="merged", sub=0, sample=0):
         n = self.size(field, level, sub)
         out = np.zeros(n, dtype=np.float64)
-        _check(_LIB.lp_get_solution(self._h, FIELD[field], LEVEL[level], sub,
+        _check(_LIB.lp_get_solution(self._h, sample, FIELD[field], LEVEL[level], sub,
                                     out.ctypes.data_as(POINTER(c_double)), n, 0, self._s()))
         return out
 
-    def solution_device(self, field, level="merged", sub=0):
+    def solution_device(self, field, level="merged", sub=0, sample=0):
         torch = self._torch
         n = self.size(field, level, sub)
         out = torch.empty(n, dtype=torch.float64, device="cuda")
-        _check(_LIB.lp_get_solution(self._h, FIELD[field], LEVEL[level], sub,
+        _check(_LIB.lp_get_solution(self._h, sample, FIELD[field], LEVEL[level], sub,
                                     ctypes.cast(out.data_ptr(), POINTER(c_double)), n, 1, self._s()))
         return out
 
+    def index_map(self, which, sub=0):
+        """The context's own partition and numbering tables (see lp_plan_query)."""
+        need = c_int64(0)
+        _check(_LIB.lp_get_index_map(self._h, which, sub, None, 0, byref(need)))
+        out = np.zeros(max(need.value, 1), dtype=np.int64)
+        _check(_LIB.lp_get_index_map(self._h, which, sub, out.ctypes.data_as(POINTER(c_int64)),
+                                     need.value, byref(need)))
+        return out[:need.value]
+
     def stats(self):
+        """Run statistics; flags are sticky.  A set flag (lp_get_stats returns
+        LP_ERR_NOCONV) is reported in the dict, not raised."""
         s = LpStats()
-        _check(_LIB.lp_get_stats(self._h, byref(s)))
+        st = _LIB.lp_get_stats(self._h, byref(s))
+        if st not in (0, LP_ERR_NOCONV):
+            _check(st)
         return {k: getattr(s, k) for k, _ in LpStats._fields_}
 
     def set_timing(self, stages):

@@ -88,6 +88,25 @@ def config(name):
                 cuts=cuts, prm=prm, dt=dt, steps=steps)
 
 
+def shifted_small(seed=7):
+    """Uneven cores at a size the oracle finishes in seconds: H = 1/4, h = 1/16,
+    4 x 4 subdomains per region, overlap 2 fine cells, every interior cut of
+    each (region, axis) shifted by (x mod 3) - 1 fine cells (SplitMix64, draw
+    order porous x, porous y, conduit x, conduit y), non-unit parameters."""
+    NH, k, ns, ov = 4, 4, 4, 2
+    N = NH * k
+    rng = SplitMix64(seed)
+    cuts = {}
+    for key in ((0, 0), (0, 1), (1, 0), (1, 1)):
+        c = uniform_cuts(N, ns)
+        for i in range(1, ns):
+            c[i] += (rng.next() % 3) - 1
+        cuts[key] = c
+    prm = dict(unit_params(), nu=0.1, k=[0.5, 0.05, 0.01], sigma=3.0, sigma_star=0.3)
+    return dict(name="shifted_small", dim=2, supported=True, NH=NH, refine=k, Nh=N, nsub=(ns, ns),
+                overlap=ov, cuts=cuts, prm=prm, dt=0.02, steps=3)
+
+
 def small(NH=2, refine=4, nsub=2, overlap=1, dt=0.05, prm=None):
     """A small custom 2D case for parity tests."""
     N = NH * refine

@@ -19,12 +19,77 @@ def header_functions():
     return sorted(set(re.findall(r"\b(lp_[a-z_]+)\s*\(", txt)))
 
 
+def header_prototypes():
+    """{function name: parameter count} of every prototype in lp.h."""
+    txt = re.sub(r"/\*.*?\*/", "", open(HDR).read(), flags=re.S)
+    out = {}
+    for m in re.finditer(r"\b(lp_[a-z_]+)\s*\(([^)]*)\)\s*;", txt):
+        args = m.group(2).strip()
+        out[m.group(1)] = 0 if args in ("", "void") else len(args.split(","))
+    return out
+
+
 def test_library_exports_header_symbols():
     names = header_functions()
     assert set(names) == set(lib.EXPORTS)
     so = ctypes.CDLL(lib.LIB_PATH)
     for n in names:
         assert hasattr(so, n), n
+
+
+def test_binding_signatures_match_header():
+    """Every prototype of lp.h has as many parameters as the binding passes
+    (lp_setup takes the samples array, lp_get_solution the sample index)."""
+    protos = header_prototypes()
+    assert set(protos) == set(lib.EXPORTS)
+    for name, nargs in protos.items():
+        fn = getattr(lib._LIB, name)
+        if fn.argtypes is not None:
+            assert len(fn.argtypes) == nargs, (name, len(fn.argtypes), nargs)
+    assert protos["lp_get_solution"] == 9 and protos["lp_get_index_map"] == 6
+    txt = open(HDR).read()
+    assert "const lp_params *samples" in txt
+    for field in ("solver", "coarse_ns", "krylov_tol", "max_iter", "nsamples"):
+        assert field in dict(lib.LpOptions._fields_), field
+    for field in ("ir_sweeps_max", "ir_relres_max"):
+        assert field in dict(lib.LpStats._fields_), field
+
+
+def _setup_status(opt_kw=None, samples=None, prm_kw=None):
+    """Call lp_setup with options that it rejects before touching a device."""
+    from ctypes import byref, c_void_p
+    mesh, part, keep = lib._structs(2, 4, (2, 2), 1, None)
+    opt = lib.LpOptions()
+    opt.problem, opt.precision, opt.convection, opt.max_ir, opt.ir_tol = 0, lib.LP_MIXED, 1, 4, 1e-10
+    opt.max_newton, opt.newton_tol, opt.jacobian_every = 8, 1e-13, 1
+    opt.solver, opt.coarse_ns, opt.krylov_tol, opt.max_iter, opt.nsamples = 0, 0, 1e-12, 100, 1
+    for k, v in (opt_kw or {}).items():
+        setattr(opt, k, v)
+    plist = samples or [dict(W.unit_params(), **(prm_kw or {}))]
+    arr = (lib.LpParams * len(plist))(*[lib._params(q, 0.05) for q in plist])
+    h = c_void_p()
+    st = lib._LIB.lp_setup(byref(mesh), byref(part), arr, byref(opt), None, None, byref(h))
+    assert not h.value
+    return st, lib._LIB.lp_last_error().decode()
+
+
+def test_setup_rejects_bad_options_without_a_device():
+    """Argument checks run before any device call: unknown option values and
+    invalid parameters are LP_ERR_ARG, requests this build does not implement
+    (more than one sample, Krylov local solves, the semi-implicit coarse step)
+    LP_ERR_UNSUPPORTED."""
+    assert _setup_status({"solver": 7})[0] == 1
+    assert _setup_status({"coarse_ns": 3})[0] == 1
+    assert _setup_status({"nsamples": -1})[0] == 1
+    assert _setup_status({"precision": 5})[0] == 1
+    assert _setup_status({"max_ir": 0})[0] == 1
+    st, msg = _setup_status(prm_kw={"nu": -1.0})
+    assert st == 1 and "sample 0" in msg
+    st, msg = _setup_status({"nsamples": 2}, samples=[W.unit_params(), dict(W.unit_params(), k=[0.0, 1, 1])])
+    assert st == 1 and "sample 1" in msg          # every sample is validated
+    assert _setup_status({"nsamples": 2}, samples=[W.unit_params()] * 2)[0] == 6
+    assert _setup_status({"solver": lib.LP_KRYLOV})[0] == 6
+    assert _setup_status({"coarse_ns": lib.LP_SEMI_IMPLICIT})[0] == 6
 
 
 @pytest.mark.parametrize("name", ["cfg1", "cfg2", "cfg3"])
@@ -37,26 +102,37 @@ def test_partition_tables_match_oracle(name):
     mp, mc = RegionMesh(cfg["Nh"], 0), RegionMesh(cfg["Nh"], 1)
     assert len(tab) == len(subs)
     sizes = lib.plan_query(*args, 5, cuts=flat).reshape(-1, 2)
-    for sd in subs[:: max(1, len(subs) // 24)]:
+    # every subdomain's tables, in id order (one query each)
+    all_cls2, all_cls1, all_dof2, all_dof1 = (lib.plan_query(*args, w, -1, cuts=flat) for w in (1, 2, 3, 4))
+    o2 = o1 = o1c = 0
+    for sd in subs:
         row = tab[sd.sid]
         assert tuple(row[:5]) == (sd.region, sd.x0, sd.x1, sd.y0, sd.y1)
         assert tuple(row[5:]) == tuple(sd.d)
         mesh = mp if sd.region == POROUS else mc
         cls = sd.classify_p2(mesh)
-        assert np.array_equal(lib.plan_query(*args, 1, sd.sid, cuts=flat), cls)
         _, I, J = sd.p1_nodes(mesh)
         art = sd.artificial_p1(I, J)
-        assert np.array_equal(lib.plan_query(*args, 2, sd.sid, cuts=flat), 2 * art)
-        dof = lib.plan_query(*args, 3, sd.sid, cuts=flat)
+        n2, n1 = len(cls), len(art)
+        assert np.array_equal(all_cls2[o2:o2 + n2], cls), sd.sid
+        assert np.array_equal(all_cls1[o1:o1 + n1], 2 * art), sd.sid
+        dof = all_dof2[o2:o2 + n2]
+        o2 += n2
+        o1 += n1
         nfree = (cls == 0).sum()
         if sd.region == POROUS:
             assert sizes[sd.sid, 0] == nfree
             assert np.array_equal(np.sort(dof[dof >= 0]), np.arange(nfree))
         else:
-            dp = lib.plan_query(*args, 4, sd.sid, cuts=flat)
+            dp = all_dof1[o1c:o1c + n1]
+            o1c += n1
             assert sizes[sd.sid, 0] == 2 * nfree + (~art).sum()
             allu = np.concatenate([dof[dof >= 0], dof[dof >= 0] + 1, dp[dp >= 0]])
             assert np.array_equal(np.sort(allu), np.arange(sizes[sd.sid, 0]))
+    assert o2 == len(all_cls2) and o1 == len(all_cls1) and o1c == len(all_dof1)
+    # the single-subdomain queries return the same slices
+    for sd in subs[:: max(1, len(subs) // 8)]:
+        assert np.array_equal(lib.plan_query(*args, 1, sd.sid, cuts=flat), sd.classify_p2(mp if sd.region == POROUS else mc))
 
 
 def test_plan_query_rejects_bad_input():
