@@ -254,6 +254,18 @@ enum {
 lp_status lp_set_timing(lp_ctx *ctx, uint32_t mask);
 lp_status lp_get_timing(lp_ctx *ctx, double *ms, int64_t *launches, int32_t n);
 
+/* lp_local_step for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and results, with the refinement scratch (residual-norm
+ * partials and last-block tickets of the porous and Oseen batches) in a
+ * file-scope device array of LP_NOALLOC_SCRATCH_BYTES (8 MiB) that each
+ * device holds until the process ends, instead of context buffers.  Calls no
+ * allocator; its tickets are cleared by a small kernel on each call.  Every
+ * call on one device shares that array: calls of different contexts that
+ * overlap on one device race.  Errors: as lp_local_step, and
+ * LP_ERR_UNSUPPORTED when the problem's scratch exceeds the array. */
+lp_status lp_local_step_noalloc(lp_ctx *ctx, void *stream);
+
 void lp_destroy(lp_ctx *ctx);
 
 const char *lp_last_error(void);

@@ -30,6 +30,42 @@ lp_status fail(lp_status s, const std::string &msg) {
 
 }  // namespace
 
+// Scratch of lp_local_step_noalloc: one array per device, held until the
+// process ends.  In host code `scratch` only names the symbol; its device
+// address comes from hipGetSymbolAddress, taken once per device at lp_setup
+// with that device current, and only that address is handed to kernels.
+#define LP_NOALLOC_SCRATCH_BYTES (8LL << 20)
+static __device__ __align__(256) unsigned char scratch[LP_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[MAX_DEVICES] = {};
+
+// device address of `scratch` on the current device (first call per device)
+lp_status init_static_scratch(int device) {
+    if (device < 0 || device >= MAX_DEVICES) return fail(LP_ERR_DEVICE, "device id out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return LP_OK;
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(LP_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = (unsigned char *)ptr;
+    return LP_OK;
+}
+
+lp_status static_scratch(int device, unsigned char **out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (device < 0 || device >= MAX_DEVICES || !g_scratch_ptr[device])
+        return fail(LP_ERR_STATE, "static scratch of this device was not set up (lp_setup on it first)");
+    *out = g_scratch_ptr[device];
+    return LP_OK;
+}
+
+}  // namespace
+
 struct lp_ctx {
     lp::Plan P;
     lp::Coef co{};
@@ -221,7 +257,7 @@ namespace {
 // Scratch of the local step's refinement: residual-norm partials and
 // last-block tickets of the porous and the Oseen batches (they run on
 // different streams).  The context's own buffers, or a static device array
-// (an allocation-free variant of the local step).
+// (lp_local_step_noalloc).
 struct LocalScratch {
     double *part_por, *part_ose;
     int *tick_por, *tick_ose;
@@ -669,6 +705,7 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     hipStream_t st = (hipStream_t)stream;
     std::unique_ptr<lp_ctx> c(new lp_ctx());
     HIPCHK(hipGetDevice(&c->device));
+    TRY(init_static_scratch(c->device));
     if (!lp::build_plan(*mesh, *part, c->P, why)) return fail(LP_ERR_ARG, why);
     c->prm = *prm;
     c->opt = *opt;
@@ -1134,6 +1171,22 @@ lp_status lp_local_step(lp_ctx *c, void *stream) {
     return local_step_impl(c, stream, LocalScratch{c->part_por, c->part_ose, c->tick_por, c->tick_ose}, false);
 }
 
+lp_status lp_local_step_noalloc(lp_ctx *c, void *stream) {
+    if (!c) return fail(LP_ERR_ARG, "NULL context");
+    const long long need = c->scratch_part_por + c->scratch_part_ose;     // doubles
+    const long long need_t = 3LL * (long long)c->P.por.size() + (long long)c->P.ose.size();
+    const long long bytes = need * (long long)sizeof(double) + need_t * (long long)sizeof(int);
+    if (bytes > LP_NOALLOC_SCRATCH_BYTES)
+        return fail(LP_ERR_UNSUPPORTED, "lp_local_step_noalloc needs " + std::to_string(bytes) +
+                                            " bytes of scratch; the static array holds " +
+                                            std::to_string((long long)LP_NOALLOC_SCRATCH_BYTES));
+    unsigned char *base = nullptr;
+    TRY(static_scratch(c->device, &base));
+    double *d = (double *)base;
+    int *t = (int *)(d + need);
+    LocalScratch ls{d, d + c->scratch_part_por, t, t + 3 * c->P.por.size()};
+    return local_step_impl(c, stream, ls, true);
+}
 
 static lp_status locate(lp_ctx *c, int32_t field, int32_t level, int32_t sub, const double **ptr, int64_t *len) {
     if (field < LP_U || field > LP_PM) return fail(LP_ERR_ARG, "unknown field");

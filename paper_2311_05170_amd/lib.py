@@ -34,7 +34,7 @@ LP_ERR_NOCONV = 5
 
 EXPORTS = ["lp_setup", "lp_coarse_step", "lp_local_step", "lp_get_size", "lp_get_solution",
            "lp_get_stats", "lp_plan_query", "lp_get_index_map", "lp_set_timing", "lp_get_timing",
-           "lp_destroy", "lp_last_error"]
+           "lp_local_step_noalloc", "lp_destroy", "lp_last_error"]
 # stage timer indices (LP_T_* in lp.h)
 STAGES = ["prolong", "por_rhs", "por_solve", "por_res", "ose_rhs", "ose_asm", "ose_lu", "ose_solve",
           "ose_res", "merge", "coarse", "wait_coarse", "wait_fac", "wait_por"]
@@ -92,6 +92,7 @@ def load(path=LIB_PATH):
                              POINTER(LpAllocator), c_void_p, POINTER(c_void_p)]
     lib.lp_coarse_step.argtypes = [c_void_p, c_void_p]
     lib.lp_local_step.argtypes = [c_void_p, c_void_p]
+    lib.lp_local_step_noalloc.argtypes = [c_void_p, c_void_p]
     lib.lp_get_size.argtypes = [c_void_p, c_int32, c_int32, c_int32, POINTER(c_int64)]
     lib.lp_get_solution.argtypes = [c_void_p, c_int32, c_int32, c_int32, c_int32, POINTER(c_double),
                                     c_int64, c_int32, c_void_p]
