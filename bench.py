@@ -65,6 +65,11 @@ JACOBIAN_EVERY = 3
 # refinement sweeps launched per local step in the mixed path (each skips once
 # its system has converged; two reach the 1e-10 tolerance on this workload)
 MAX_IR_MIXED = 2
+# refinement sweeps launched on the uneven h = 1/256 workload: each sweep of
+# its Krylov path is one GMRES cycle (restart 30), one of which usually
+# reaches the tolerance; a second is launched and skips itself if not needed
+UNEVEN_MAX_IR = 2
+UNEVEN_STEPS, UNEVEN_WARMUP = 5, 2
 
 
 def make(cfg, precision, max_ir):
@@ -105,6 +110,42 @@ def timed_run(cfg, precision, steps, warmup, max_ir):
     res["stages_ms"] = {k: round(v[0] / nd, 4) for k, v in tm.items()}
     g.close()
     return res
+
+
+def uneven_run(precision, steps, warmup):
+    """The uneven h = 1/256 workload (16 x 16 + 16 x 16 subdomains, shifted
+    cuts, dt = 1e-3): the local Oseen systems (half-bandwidths to 399) go to
+    the Krylov path, the porous ones to the band factorisation.  Returns its
+    throughput, the run-long statistics and the stage split of a few
+    instrumented steps."""
+    import torch
+    from paper_2311_05170_amd import workloads as W
+    from paper_2311_05170_amd.lib import LocalParallel
+    from paper_2311_05170_amd import lib
+    cfg = W.config("cfg3")
+    t0 = time.perf_counter()
+    g = LocalParallel(cfg["NH"], cfg["refine"], cfg["nsub"], cfg["overlap"], cfg["prm"], cfg["dt"],
+                      cuts=W.flat_cuts(cfg["cuts"]), precision=precision, max_ir=UNEVEN_MAX_IR,
+                      max_newton=MAX_NEWTON, jacobian_every=JACOBIAN_EVERY)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    for _ in range(warmup):
+        g.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    st = g.stats()
+    g.set_timing(lib.STAGES)
+    nd = 2
+    for _ in range(nd):
+        g.step()
+    tm = g.timing()
+    g.close()
+    return dict(ms_per_step=ms, stats=st, setup_s=setup_s,
+                stages_ms={k: round(v[0] / nd, 3) for k, v in tm.items() if v[1]})
 
 
 def serial_lu_time(cfg, precision, max_ir, steps=SERIAL_STEPS):
@@ -302,6 +343,33 @@ def traffic_for(kernel, workload):
     return None
 
 
+def summarize_trace(path, last=SERIAL_STEPS):
+    """Per-kernel launch counts and average durations from a rocprofv3
+    kernel-trace CSV, and for the roofline kernel the average of its last
+    `last` launches (the uncontended pass that bench.py times with events)
+    beside that of its earlier, overlapped ones."""
+    import csv
+    import re
+    rows = list(csv.DictReader(open(path)))
+    by = {}
+    for r in rows:
+        by.setdefault(r["Kernel_Name"], []).append((int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+    print("| kernel | launches | avg us | total ms |")
+    print("|---|---:|---:|---:|")
+    tot = {k: sum(e - b for b, e in v) for k, v in by.items()}
+    for k in sorted(by, key=lambda k: -tot[k]):
+        v = by[k]
+        print("| %s | %d | %.1f | %.3f |" % (k.replace("|", "/")[:110], len(v), tot[k] / len(v) / 1e3, tot[k] / 1e6))
+    pat = re.compile(r"k_band_lu_la<float, ?11>")
+    for k, v in by.items():
+        if pat.search(k):
+            v = sorted(v)
+            d = [(e - b) / 1e3 for b, e in v]
+            print("\nroofline kernel %s: last %d launches (LP_SERIAL pass) avg %.1f us; earlier %d launches "
+                  "(overlapped schedule) avg %.1f us" % (k, last, sum(d[-last:]) / last, len(d) - last,
+                                                         sum(d[:-last]) / max(len(d) - last, 1)))
+
+
 def host_cores():
     try:
         avail = len(os.sched_getaffinity(0))
@@ -335,8 +403,11 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the h = 1/256 uneven-batch line")
     ap.add_argument("--cpu-leg", default=None, help=argparse.SUPPRESS)
     ap.add_argument("--cpu-pool", type=int, default=1, help=argparse.SUPPRESS)
+    ap.add_argument("--summarize-trace", default=None, metavar="KERNEL_TRACE_CSV",
+                    help="print per-kernel averages of a rocprofv3 kernel trace of this script and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (HBM counter calibration)")
     args = ap.parse_args()
@@ -345,6 +416,9 @@ def main():
         return
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the local stage needs no communication while "
@@ -371,6 +445,27 @@ def main():
     mixed = timed_run(cfg, "mixed", args.steps, args.warmup, MAX_IR_MIXED)
     fp64 = timed_run(cfg, "fp64", args.steps, args.warmup, 2)
     lu_ms, lu_n = serial_lu_time(cfg, "mixed", MAX_IR_MIXED)
+    uneven = None
+    if not args.no_uneven:
+        cfg3 = W.config("cfg3")
+        q3 = (cfg3["NH"], cfg3["refine"], cfg3["nsub"], cfg3["overlap"])
+        s3 = lib.plan_query(*q3, 5, cuts=W.flat_cuts(cfg3["cuts"])).reshape(-1, 2)
+        n3 = cfg3["nsub"][0] * cfg3["nsub"][1]
+        L3 = int(3 * s3[:n3, 0].sum() + s3[n3:, 0].sum())
+        um = uneven_run("mixed", UNEVEN_STEPS, UNEVEN_WARMUP)
+        uf = uneven_run("fp64", UNEVEN_STEPS, UNEVEN_WARMUP)
+        uneven = {"workload": "2D Example-1 MMS, H=1/16, h=1/256, 16x16 porous + 16x16 conduit subdomains, "
+                              "SplitMix64-shifted cuts (+-4 fine cells), overlap 8h, dt=1e-3, seed 3 parameters (cfg3)",
+                  "local_dofs_per_step": L3, "steps": UNEVEN_STEPS, "warmup": UNEVEN_WARMUP,
+                  "max_halfbandwidth": int(s3[:, 1].max()), "oseen_solver": "krylov",
+                  "mixed": {"value": L3 / (um["ms_per_step"] * 1e-3), "ms_per_step": um["ms_per_step"],
+                            "setup_s": um["setup_s"], "krylov_its": um["stats"]["krylov_its"],
+                            "sweeps_max": um["stats"]["ir_sweeps_max"], "relres_max": um["stats"]["ir_relres_max"],
+                            "flags": um["stats"]["flags"], "stages_ms": um["stages_ms"]},
+                  "fp64": {"value": L3 / (uf["ms_per_step"] * 1e-3), "ms_per_step": uf["ms_per_step"],
+                           "setup_s": uf["setup_s"], "krylov_its": uf["stats"]["krylov_its"],
+                           "sweeps_max": uf["stats"]["ir_sweeps_max"], "relres_max": uf["stats"]["ir_relres_max"],
+                           "flags": uf["stats"]["flags"], "stages_ms": uf["stages_ms"]}}
 
     def rate(ms):
         return L / (ms * 1e-3)
@@ -386,6 +481,8 @@ def main():
     roof_ms_mixed, stages_mixed = step_roofline(cfg, sizes, tab, coarse, mixed["stats"], 4, JACOBIAN_EVERY)
     roof_ms_fp64, stages_fp64 = step_roofline(cfg, sizes, tab, coarse, fp64["stats"], 8, JACOBIAN_EVERY)
     flags = [mixed["stats"]["flags"], fp64["stats"]["flags"]]
+    if uneven:
+        flags += [uneven["mixed"]["flags"], uneven["fp64"]["flags"]]
     line = {
         "metric": METRIC,
         "value": rate(mixed["ms_per_step"]),
@@ -425,6 +522,8 @@ def main():
                               "fp64": {"roofline_ms": roof_ms_fp64, "measured_ms": fp64["ms_per_step"],
                                        "frac": roof_ms_fp64 / fp64["ms_per_step"], "stages": stages_fp64}}},
     }
+    if uneven:
+        line["uneven_batch"] = uneven
     if not args.no_cpu:
         cores, model = host_cores()
         pool = max(1, min(CPU_POOL_MAX, cores))

@@ -115,15 +115,23 @@ typedef struct {
     double newton_tol;       /* stop when ||delta|| <= newton_tol ||x|| */
     int32_t jacobian_every;  /* the coarse Jacobian is formed at steps 1, 1 + J, 1 + 2 J, ...
                                 and reused in between (0 or 1: every step) */
-    int32_t solver;          /* LP_AUTO (the band factorisation wherever the half-bandwidth
-                                fits its window), LP_DENSE (band factorisation only) or
-                                LP_KRYLOV (matrix-free Krylov local solves: LP_ERR_UNSUPPORTED
-                                in this build) */
+    int32_t solver;          /* local Oseen solves (Eq. (5.8)): LP_DENSE, the per-step band
+                                factorisation (half-bandwidth <= 159); LP_KRYLOV, restarted
+                                flexible GMRES(max_iter) in FP64 with the FP64 matrix-free
+                                operator, right-preconditioned by restricted additive Schwarz
+                                over strips of each box (at most 16 cells wide, 2 cells of
+                                overlap) whose Stokes-part band matrices (the operator without
+                                b_N) are factored once at setup in the precision of the run;
+                                each refinement sweep is one GMRES cycle; LP_AUTO: dense where
+                                the half-bandwidth fits, else Krylov.  The porous systems
+                                always use the band factorisation. */
     int32_t coarse_ns;       /* LP_NEWTON: the fully implicit coarse step of Algorithm 3
                                 Step 1 (2) solved to newton_tol; LP_SEMI_IMPLICIT (convection
                                 lagged to u^n, one linear solve): LP_ERR_UNSUPPORTED */
-    double krylov_tol;       /* relative residual target of Krylov solves (LP_KRYLOV) */
-    int32_t max_iter;        /* Krylov iteration cap per solve (LP_KRYLOV) */
+    double krylov_tol;       /* a GMRES cycle stops when its residual estimate is
+                                <= krylov_tol ||b|| (the refinement test on the true residual
+                                follows) */
+    int32_t max_iter;        /* GMRES restart length, 1..64 (the Arnoldi steps of one cycle) */
     int32_t nsamples;        /* parameter samples advanced together (lp_setup's samples[]);
                                 0 or 1: one sample.  More than one: LP_ERR_UNSUPPORTED */
 } lp_options;
@@ -150,6 +158,9 @@ typedef struct {
     int32_t newton_its_max;  /* most Newton iterations of any coarse step so far */
     int32_t ir_sweeps_max;   /* most refinement sweeps of any system in any local step so far */
     double ir_relres_max;    /* largest final relative residual of any system in any local step */
+    int32_t solver;          /* local Oseen solver in use: LP_DENSE or LP_KRYLOV */
+    int32_t krylov_its;      /* LP_KRYLOV: most GMRES (Arnoldi) steps of any local Oseen
+                                system in the last local step, over its cycles */
 } lp_stats;
 
 /* Build meshes, partition, reference data and device buffers; interpolate the
@@ -160,8 +171,9 @@ typedef struct {
  * sample shares mesh and partition and carries its own Section 2 parameters.
  * Errors: LP_ERR_ARG (dim != 2, n_coarse < 1, refine < 1, overlap < 0, bad cuts,
  * non-positive dt or parameters, unknown option values), LP_ERR_UNSUPPORTED
- * (nsamples > 1, LP_KRYLOV, LP_SEMI_IMPLICIT, or a local half-bandwidth beyond
- * the band kernels' window of 159), LP_ERR_NOCONV (zero or non-finite pivot in
+ * (nsamples > 1, LP_SEMI_IMPLICIT, a porous, coarse or (LP_DENSE) Oseen
+ * half-bandwidth beyond the band kernels' window of 159, or a Krylov strip or
+ * system beyond its kernels' limits), LP_ERR_NOCONV (zero or non-finite pivot in
  * the constant porous matrices), LP_ERR_ALLOC, LP_ERR_DEVICE. */
 lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_params *samples,
                    const lp_options *opt, const lp_allocator *alloc, void *stream,
@@ -213,6 +225,10 @@ lp_status lp_get_stats(lp_ctx *ctx, lp_stats *out);
  *   which = 5: per subdomain: number of unknowns and half-bandwidth (2 int64 each)
  *   which = 6: the coarse systems on T_H: unknowns and half-bandwidth of one
  *              porous pressure system, then of the Navier-Stokes system
+ *   which = 7: the strips of the Krylov path's preconditioner for a strip
+ *              width of `sub` cells, 7 int64 per strip: parent conduit
+ *              system (0-based among the conduit subdomains), x0, x1, y0, y1,
+ *              unknowns, half-bandwidth
  * For which = 1..4, sub = -1 returns the tables of every subdomain (of every
  * conduit subdomain for which = 4) concatenated in id order. 
  * `needed` receives the required length; nothing is written if len is short. */

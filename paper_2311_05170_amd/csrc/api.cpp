@@ -163,6 +163,21 @@ struct lp_ctx {
     int *sw_por = nullptr, *sw_ose = nullptr, *sw_cp = nullptr, *sw_cn = nullptr;
 
     int maxbw_por = 0, maxbw_ose = 0, maxn_por = 0, maxn_ose = 0;
+    // Krylov path of the local Oseen systems (boxes too wide for the band
+    // factorisation, or LP_KRYLOV): FGMRES(m) preconditioned by restricted
+    // additive Schwarz over strips whose Stokes-part band matrices are
+    // factored once at setup
+    bool krylov = false;
+    int gm_m = 0;
+    lp::SysDesc *d_strip = nullptr;
+    int32_t *d_strip_parent = nullptr, *d_smap = nullptr;
+    int8_t *d_sown = nullptr;
+    lp::BandSys *d_lu_strip = nullptr, *d_sv_strip = nullptr;
+    void *band_strip = nullptr, *fac_strip = nullptr;
+    int maxbw_strip = 0, maxn_strip = 0;
+    double *gm_V = nullptr, *gm_Z = nullptr, *gm_H = nullptr, *gm_cs = nullptr, *gm_sn = nullptr, *gm_g = nullptr;
+    double *gm_bn = nullptr, *gm_w = nullptr, *s_rs = nullptr, *s_zs = nullptr;
+    int *gm_done = nullptr, *gm_kd = nullptr, *gm_tot = nullptr, *s_done = nullptr;
     // largest local P2 lattice per batch (node blocks of the gather kernels)
     int nodes_por = 0, nodes_ose = 0, nodes_cpor = 0, nodes_cns = 0;
     int tiles_ose = 0, tiles_por = 0;  // most residual tiles of a local Oseen / porous box
@@ -416,6 +431,51 @@ lp_status refine_oseen(lp_ctx *c, const lp::SysDesc *d_sys, int nsys, int maxnod
     return LP_OK;
 }
 
+// Krylov sweeps on the local Oseen batch: each sweep is one FGMRES(m) cycle
+// for the correction d of K d = r (right preconditioning by the strip
+// solves), x += d, then the FP64 residual with the convergence test.
+template <typename T>
+lp_status refine_oseen_krylov(lp_ctx *c, double *part, int *ticket, const double *W1x, const double *W1y, int sweeps,
+                              bool timed, hipStream_t st) {
+    const int nsys = (int)c->P.ose.size(), nstrip = (int)c->P.strip.size();
+    lp::GmresArgs ga{c->d_ose, c->gm_m, c->P.dof_total_ose, c->gm_V, c->gm_Z, c->gm_H, c->gm_cs, c->gm_sn, c->gm_g,
+                     c->gm_bn, c->gm_done, c->gm_kd, c->opt.krylov_tol, c->conv_ose, c->gm_tot};
+    lp::StripArgs sa{c->d_strip, c->d_strip_parent, c->d_ose, c->d_smap, c->d_sown, c->gm_done, c->s_done, c->s_rs, c->s_zs};
+    lp::OseenApplyArgs<double> mv{};
+    mv.sys = c->d_ose; mv.cls2 = c->d_cls2; mv.dof2 = c->d_dof2; mv.dof1 = c->d_dof1;
+    mv.W1[0] = W1x; mv.W1[1] = W1y;
+    mv.b = nullptr; mv.r = c->gm_w; mv.conv = c->gm_done;
+    const long long nt = c->P.dof_total_ose;
+    for (int sw = 0; sw < sweeps; ++sw) {
+        {
+            StageTimer tm(c, timed ? LP_T_OSE_SOLVE : -1, st);
+            lp::launch_gm_init(ga, nsys, c->r_ose, c->b_ose, sw == 0, st);
+            for (int k = 0; k < c->gm_m; ++k) {
+                lp::launch_strip_gather(sa, nstrip, c->gm_V + k * nt, st);
+                lp::SolveArgs<T> so{c->d_sv_strip, (const T *)c->fac_strip, c->s_rs, c->s_zs, c->s_done, 1, nullptr,
+                                    (const T *)c->consts, c->const_one<T>(), (const double *)c->consts, 1};
+                if (!lp::launch_band_solve<T>(so, nstrip, 1, c->maxbw_strip, c->maxn_strip, c->solve_depth, st))
+                    return fail(LP_ERR_UNSUPPORTED, "strip bandwidth too large for the solve kernels");
+                lp::launch_strip_scatter(sa, nstrip, c->gm_Z + k * nt, st);
+                mv.x = c->gm_Z + k * nt;
+                lp::launch_oseen_residual_tiled(mv, nsys, c->tiles_ose, st);
+                if (!lp::launch_gm_arnoldi(ga, nsys, c->maxn_ose, k, c->gm_w, st))
+                    return fail(LP_ERR_UNSUPPORTED, "local Oseen system too large for the Arnoldi kernel");
+            }
+            lp::launch_gm_update(ga, nsys, c->x_ose, st);
+        }
+        StageTimer tm(c, timed ? LP_T_OSE_RES : -1, st);
+        lp::OseenApplyArgs<double> ra{};
+        ra.sys = c->d_ose; ra.cls2 = c->d_cls2; ra.dof2 = c->d_dof2; ra.dof1 = c->d_dof1;
+        ra.W1[0] = W1x; ra.W1[1] = W1y;
+        ra.x = c->x_ose; ra.b = c->b_ose; ra.r = c->r_ose; ra.band = nullptr;
+        ra.conv = c->conv_ose; ra.relres = c->rel_ose; ra.sweeps = c->sw_ose; ra.tol = c->opt.ir_tol; ra.skip = nullptr;
+        ra.part = part; ra.ticket = ticket;
+        lp::launch_oseen_residual_tiled(ra, nsys, c->tiles_ose, st);
+    }
+    return LP_OK;
+}
+
 template <typename T>
 lp_status factor_porous(lp_ctx *c, T *band, T *fac, hipStream_t st) {
     lp::AssembleArgs<T> aa{c->d_por, c->d_dof2, band};
@@ -457,9 +517,12 @@ lp_status local_oseen(lp_ctx *c, hipStream_t st, const LocalScratch &ls) {
         StageTimer tm(c, LP_T_WAIT_FAC, st);
         HIPCHK(hipStreamWaitEvent(st, c->ev_fac[fs], 0));
     }
-    TRY(refine_oseen<T>(c, c->d_ose, nsys, c->nodes_ose, ls.part_ose, ls.tick_ose, c->d_sv_ose, (const T *)c->fac_ose[fs], c->maxbw_ose, c->maxn_ose, oa.W1[0], oa.W1[1], c->b_ose,
-                        c->x_ose, c->r_ose, c->conv_ose, c->rel_ose, c->sw_ose, c->P.dof_total_ose, c->opt.max_ir,
-                        c->opt.ir_tol, nullptr, true, st));
+    if (c->krylov)
+        TRY(refine_oseen_krylov<T>(c, ls.part_ose, ls.tick_ose, oa.W1[0], oa.W1[1], c->opt.max_ir, true, st));
+    else
+        TRY(refine_oseen<T>(c, c->d_ose, nsys, c->nodes_ose, ls.part_ose, ls.tick_ose, c->d_sv_ose, (const T *)c->fac_ose[fs], c->maxbw_ose, c->maxn_ose, oa.W1[0], oa.W1[1], c->b_ose,
+                            c->x_ose, c->r_ose, c->conv_ose, c->rel_ose, c->sw_ose, c->P.dof_total_ose, c->opt.max_ir,
+                            c->opt.ir_tol, nullptr, true, st));
     StageTimer tm(c, LP_T_MERGE, st);
     lp::FinalizeArgs fa{c->d_ose, c->d_dof2, c->d_dof1, c->x_ose, c->e2[nw], c->e1[nw], nullptr,
                         lp::IrTotals{c->conv_ose, c->sw_ose, c->rel_ose, 1, c->d_flags, c->d_irmax, c->d_irrel}};
@@ -491,6 +554,11 @@ lp_status factor_oseen(lp_ctx *c, int64_t m) {
         prolong_step(c, nw, (int)((m - 1) % lp_ctx::RING), nw, st);
     }
     HIPCHK(hipEventRecord(c->ev_pro[nw], st));
+    if (c->krylov) {
+        // the Krylov path has no per-step factorisation (its strip factors are constant)
+        HIPCHK(hipEventRecord(c->ev_fac[fs], st));
+        return LP_OK;
+    }
     const double *pro_Uf = c->pro_slot(nw);
     {
         StageTimer tm(c, LP_T_OSE_ASM, st);
@@ -607,6 +675,58 @@ void prolong_setup(lp_ctx *c, hipStream_t st) {
     lp::launch_prolong_p2(pa, st);
 }
 
+// Krylov path: strip tables, the strips' Stokes-part band matrices (the
+// local Oseen operator without b_N, constant in time) factored once, and the
+// FGMRES work space.
+template <typename T>
+lp_status setup_strips(lp_ctx *c, hipStream_t st) {
+    const lp::Plan &P = c->P;
+    const int nstrip = (int)P.strip.size(), nsys = (int)P.ose.size();
+    TRY(c->upload(&c->d_strip, P.strip, st));
+    TRY(c->upload(&c->d_strip_parent, P.strip_parent, st));
+    TRY(c->upload(&c->d_smap, P.smap, st));
+    TRY(c->upload(&c->d_sown, P.sown, st));
+    const FacLayout fl = fac_layout(P.strip, 1, c->maxbw_strip);
+    TRY(c->upload(&c->d_lu_strip, lu_list(P.strip, 1, fl), st));
+    TRY(c->upload(&c->d_sv_strip, solve_list(P.strip, 1, fl), st));
+    T *band = nullptr, *fac = nullptr;
+    TRY(c->dalloc(&band, P.band_total_strip + 64));
+    TRY(c->dalloc(&fac, fl.total + 64));
+    c->band_strip = band;
+    c->fac_strip = fac;
+    HIPCHK(hipMemsetAsync(band, 0, (size_t)P.band_total_strip * sizeof(T), st));
+    HIPCHK(hipMemsetAsync(fac, 0, (size_t)fl.total * sizeof(T), st));
+    lp::OseenApplyArgs<T> aa{};
+    aa.sys = c->d_strip; aa.cls2 = c->d_cls2; aa.dof2 = c->d_dof2; aa.dof1 = c->d_dof1;
+    aa.W1[0] = c->pro_U1; aa.W1[1] = c->pro_U1 + c->nf2;   // not read: no convection
+    aa.band = band;
+    aa.no_convection = 1;
+    int nodes = 0;
+    for (const auto &s : P.strip) nodes = std::max(nodes, s.lw2 * s.lh2);
+    lp::launch_oseen_assemble<T>(aa, nstrip, nodes, st);
+    lp::BandArgs<T> ba{c->d_lu_strip, band, fac, c->d_flags, nullptr, (T *)c->lu_dummy, (const T *)c->consts, c->const_one<T>()};
+    if (!lp::launch_band_lu<T>(ba, nstrip, c->maxbw_strip, c->lu_variant_ose, st))
+        return fail(LP_ERR_UNSUPPORTED, "strip bandwidth exceeds the factorisation kernels");
+    const long long nt = P.dof_total_ose, m = c->gm_m;
+    TRY(c->dalloc(&c->gm_V, (m + 1) * nt));
+    TRY(c->dalloc(&c->gm_Z, m * nt));
+    TRY(c->dalloc(&c->gm_w, nt));
+    TRY(c->dalloc(&c->gm_H, nsys * (m + 1) * m));
+    TRY(c->dalloc(&c->gm_cs, nsys * m));
+    TRY(c->dalloc(&c->gm_sn, nsys * m));
+    TRY(c->dalloc(&c->gm_g, nsys * (m + 1)));
+    TRY(c->dalloc(&c->gm_bn, nsys));
+    TRY(c->dalloc(&c->gm_done, nsys));
+    TRY(c->dalloc(&c->gm_kd, nsys));
+    TRY(c->dalloc(&c->gm_tot, nsys));
+    HIPCHK(hipMemsetAsync(c->gm_tot, 0, nsys * sizeof(int), st));
+    HIPCHK(hipMemsetAsync(c->gm_Z, 0, (size_t)(m * nt) * sizeof(double), st));
+    TRY(c->dalloc(&c->s_rs, P.dof_total_strip));
+    TRY(c->dalloc(&c->s_zs, P.dof_total_strip));
+    TRY(c->dalloc(&c->s_done, nstrip));
+    return LP_OK;
+}
+
 bool params_ok(const lp_params &p, std::string &why) {
     for (int i = 0; i < 3; ++i)
         if (!(p.phi[i] > 0 && p.C[i] > 0 && p.k[i] > 0)) { why = "phi, C and k must be positive"; return false; }
@@ -621,7 +741,22 @@ extern "C" {
 
 const char *lp_last_error(void) { return g_err.c_str(); }
 
-static lp_status plan_table(const lp::Plan &P, int32_t which, int32_t sub, std::vector<int64_t> &v) {
+static lp_status plan_table(const lp::Plan &P0, int32_t which, int32_t sub, std::vector<int64_t> &v) {
+    lp::Plan strips;
+    const lp::Plan *pp = &P0;
+    if (which == 7) {
+        // the Krylov path's strips for a strip width of `sub` cells
+        strips = P0;
+        std::string why;
+        if (!lp::build_strips(strips, sub, 2, 159, why)) return fail(LP_ERR_ARG, why);
+        for (size_t i = 0; i < strips.strip.size(); ++i) {
+            const lp::SysDesc &S = strips.strip[i];
+            const int64_t row[7] = {strips.strip_parent[i], S.x0, S.x0 + S.cx, S.y0, S.y0 + S.cy, S.ndof, S.bw};
+            v.insert(v.end(), row, row + 7);
+        }
+        return LP_OK;
+    }
+    const lp::Plan &P = *pp;
     const int nsub = (int)(P.por.size() + P.ose.size());
     auto sysof = [&](int s) -> const lp::SysDesc * {
         if (s < 0 || s >= nsub) return nullptr;
@@ -696,7 +831,8 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     if (opt->coarse_ns != LP_NEWTON && opt->coarse_ns != LP_SEMI_IMPLICIT)
         return fail(LP_ERR_ARG, "coarse_ns must be LP_NEWTON or LP_SEMI_IMPLICIT");
     if (opt->nsamples > 1) return fail(LP_ERR_UNSUPPORTED, "more than one parameter sample per context is not built");
-    if (opt->solver == LP_KRYLOV) return fail(LP_ERR_UNSUPPORTED, "matrix-free Krylov local solves are not built");
+    if (opt->solver != LP_DENSE && (opt->max_iter < 1 || opt->max_iter > lp::GM_MAX || !(opt->krylov_tol > 0)))
+        return fail(LP_ERR_ARG, "Krylov solves need 1 <= max_iter <= " + std::to_string(lp::GM_MAX) + " and krylov_tol > 0");
     if (opt->coarse_ns == LP_SEMI_IMPLICIT) return fail(LP_ERR_UNSUPPORTED, "the semi-implicit coarse step is not built");
     if (opt->problem != LP_MMS_EX1_2D) return fail(LP_ERR_UNSUPPORTED, "only the Example 1 manufactured problem is built in");
     if (opt->precision != LP_FP64 && opt->precision != LP_MIXED) return fail(LP_ERR_ARG, "precision must be LP_FP64 or LP_MIXED");
@@ -729,9 +865,24 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     for (const auto &s : P.ose) c->nodes_ose = std::max(c->nodes_ose, s.lw2 * s.lh2);
     c->nodes_cpor = P.cpor.lw2 * P.cpor.lh2;
     c->nodes_cns = P.cns.lw2 * P.cns.lh2;
-    if (std::max(c->maxbw_por, c->maxbw_ose) >= 160 || std::max(P.cpor.bw, P.cns.bw) >= 160)
-        return fail(LP_ERR_UNSUPPORTED, "local half-bandwidth " + std::to_string(std::max(c->maxbw_por, c->maxbw_ose)) +
-                                            " exceeds the 159 supported by the band kernels");
+    // local Oseen solver: the band factorisation where the half-bandwidth fits
+    // its window, else (or on request) the Krylov path
+    c->krylov = opt->solver == LP_KRYLOV || (opt->solver == LP_AUTO && c->maxbw_ose >= 160);
+    // local systems: window 160 (every factorisation kernel); the coarse
+    // ones, factored by the vector-unit kernel when wider, up to LU_MAX_BW
+    if (std::max(c->maxbw_por, c->krylov ? 0 : c->maxbw_ose) >= 160 || std::max(P.cpor.bw, P.cns.bw) > lp::LU_MAX_BW)
+        return fail(LP_ERR_UNSUPPORTED, "half-bandwidth " +
+                                            std::to_string(std::max({c->maxbw_por, c->krylov ? 0 : c->maxbw_ose, P.cpor.bw, P.cns.bw})) +
+                                            " exceeds the band kernels' window (159 local, " + std::to_string(lp::LU_MAX_BW) + " coarse)");
+    if (c->krylov) {
+        int width = 16;
+        if (const char *v = std::getenv("LP_KRYLOV_STRIP")) width = std::atoi(v);
+        if (!lp::build_strips(P, width, 2, 159, why)) return fail(LP_ERR_UNSUPPORTED, "Krylov strips: " + why);
+        for (const auto &s : P.strip) { c->maxbw_strip = std::max(c->maxbw_strip, s.bw); c->maxn_strip = std::max(c->maxn_strip, s.ndof); }
+        if (lp::gm_arnoldi_lds(c->maxn_ose) > lp::GM_LDS_MAX)
+            return fail(LP_ERR_UNSUPPORTED, "local Oseen system of " + std::to_string(c->maxn_ose) + " unknowns exceeds the Arnoldi kernel's LDS");
+        c->gm_m = opt->max_iter;
+    }
     // coefficients (Section 3.1 / Algorithm 3)
     lp::Coef &co = c->co;
     for (int i = 0; i < 3; ++i) { co.tau[i] = prm->phi[i] * prm->C[i] / prm->dt; co.kap[i] = prm->k[i] / prm->mu_tilde; }
@@ -829,7 +980,7 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
         else if (hipMalloc(&p, P.band_total_por * tb + 256) != hipSuccess) p = nullptr;
         if (!p) return fail(LP_ERR_ALLOC, "porous band allocation failed");
         c->owned.push_back(p); c->band_por = p;
-        for (int l = 0; l < 2; ++l) {
+        for (int l = 0; l < (c->krylov ? 0 : 2); ++l) {
             if (c->has_alloc) { p = c->alloc.alloc(P.band_total_ose * tb + 256, c->alloc.user); }
             else if (hipMalloc(&p, P.band_total_ose * tb + 256) != hipSuccess) p = nullptr;
             if (!p) return fail(LP_ERR_ALLOC, "conduit band allocation failed");
@@ -840,7 +991,7 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
         if (!p) return fail(LP_ERR_ALLOC, "porous factor allocation failed");
         c->owned.push_back(p); c->fac_por = p;
         HIPCHK(hipMemsetAsync(p, 0, fl_por.total * tb, st));
-        for (int l = 0; l < lp_ctx::FSLOTS; ++l) {
+        for (int l = 0; l < (c->krylov ? 0 : lp_ctx::FSLOTS); ++l) {
             if (c->has_alloc) { p = c->alloc.alloc(fl_ose.total * tb + 256, c->alloc.user); }
             else if (hipMalloc(&p, fl_ose.total * tb + 256) != hipSuccess) p = nullptr;
             if (!p) return fail(LP_ERR_ALLOC, "conduit factor allocation failed");
@@ -849,7 +1000,8 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
         }
     }
     {
-        const long long nlu = std::max<long long>(std::max<long long>(3LL * P.por.size(), (long long)P.ose.size()), 3);
+        const long long nlu = std::max<long long>(std::max<long long>(std::max<long long>(3LL * P.por.size(), (long long)P.ose.size()),
+                                                                      (long long)P.strip.size()), 3);
         // local factorisations use the first nlu sinks, the coarse ones (on the
         // coarse stream) the next three
         c->lu_dummy_coarse_off = nlu * lp::LU_DUMMY_PER_SYS;
@@ -936,6 +1088,10 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     } else {
         HIPCHK(hipMemsetAsync(c->band_por, 0, P.band_total_por * sizeof(double), st));
         TRY(factor_porous<double>(c.get(), (double *)c->band_por, (double *)c->fac_por, st));
+    }
+    if (c->krylov) {
+        if (c->mixed) TRY(setup_strips<float>(c.get(), st));
+        else TRY(setup_strips<double>(c.get(), st));
     }
     HIPCHK(hipMemsetAsync(c->band_cpor, 0, P.cband_por * sizeof(double), st));
     {
@@ -1283,6 +1439,12 @@ lp_status lp_get_stats(lp_ctx *c, lp_stats *out) {
     for (size_t i = 0; i < sw.size(); ++i) {
         out->ir_sweeps = std::max(out->ir_sweeps, sw[i]);
         out->ir_relres = std::max(out->ir_relres, rel[i]);
+    }
+    out->solver = c->krylov ? LP_KRYLOV : LP_DENSE;
+    if (c->krylov) {
+        std::vector<int> tot(no);
+        HIPCHK(hipMemcpy(tot.data(), c->gm_tot, no * sizeof(int), hipMemcpyDeviceToHost));
+        for (int v : tot) out->krylov_its = std::max(out->krylov_its, v);
     }
     if (out->flags) {
         return fail(LP_ERR_NOCONV, std::string("flags ") + std::to_string(out->flags) +

@@ -126,6 +126,7 @@ struct OseenApplyArgs {
     const int *skip;
     double *part;                 // residual mode: partial norms and counters as in ResidualArgs
     int *ticket;
+    int no_convection;            // assembly: leave out b_N (the Stokes part of the operator)
 };
 
 struct BandSys {
@@ -150,8 +151,14 @@ struct BandSys {
 // and zero at every other position of a column (buffers cleared at setup).
 // NR covers the bandwidth class of the factorisation window plus one block
 // of 32 rows: R >= bw + 32.
-constexpr int lu_window_bw(int bw) { return bw <= 64 ? 64 : bw <= 96 ? 96 : bw <= 128 ? 128 : bw <= 160 ? 160 : bw; }
-constexpr int solve_nr(int maxbw) { return lu_window_bw(maxbw) <= 160 ? (lu_window_bw(maxbw) + 32 + 63) / 64 : 0; }
+// Window classes: up to 160 for every factorisation; 161..175 for the
+// vector-unit one only (the blocked ones need 16 more than the bandwidth in a
+// workgroup of at most 1024 threads).
+constexpr int LU_MAX_BW = 175;
+constexpr int lu_window_bw(int bw) {
+    return bw <= 64 ? 64 : bw <= 96 ? 96 : bw <= 128 ? 128 : bw <= 160 ? 160 : bw <= LU_MAX_BW ? 176 : bw;
+}
+constexpr int solve_nr(int maxbw) { return lu_window_bw(maxbw) <= 176 ? (lu_window_bw(maxbw) + 32 + 63) / 64 : 0; }
 __host__ __device__ inline int fac_pos(int s, int nr) {
     const int h = s >> 5;
     return ((s & 31) | ((h & 1) << 5)) * nr + (h >> 1);
@@ -250,6 +257,47 @@ struct NewtonStartArgs {
     long long band_n;
     int *flags;                   // bit 1 set if the previous coarse step ended unconverged
 };
+
+// Restarted flexible GMRES over a batch of systems (krylov.hip).  Vectors are
+// in the batch's vector space (system s at sys[s].dof_off, ntot entries per
+// vector): V holds m + 1 basis vectors, Z the m preconditioned ones.  Per
+// system: the Hessenberg matrix (m + 1) x m column-major, the Givens
+// rotations, g, ||b||, a done flag and the steps taken.
+constexpr int GM_MAX = 64;                          // largest restart length
+constexpr size_t GM_LDS_MAX = 144 * 1024;           // Arnoldi work vector in LDS
+struct GmresArgs {
+    const SysDesc *sys;
+    int m;
+    long long ntot;
+    double *V, *Z;
+    double *H, *cs, *sn, *g, *bnorm;
+    int *done, *kdone;
+    double tol;                   // stop when |g_{k+1}| <= tol ||b||
+    const int *conv;              // systems already converged (skipped), or null
+    int *tot;                     // Arnoldi steps per system over the cycles of a local step
+};
+
+// Restricted additive Schwarz over strips: strip vectors rs (right-hand
+// sides) and zs (solutions) in the strip vector space.
+struct StripArgs {
+    const SysDesc *strip;
+    const int32_t *parent;
+    const SysDesc *sys;           // parent systems
+    const int32_t *smap;
+    const int8_t *sown;
+    const int *done;              // parent done flags
+    int *sdone;                   // per strip: skip (set by the gather)
+    double *rs, *zs;
+};
+
+// first: the first cycle of a local step (clears the step's Arnoldi count)
+bool launch_gm_init(const GmresArgs &a, int nsys, const double *r, const double *b, bool first, hipStream_t st);
+// false if a system does not fit the LDS work vector or k is out of range
+bool launch_gm_arnoldi(const GmresArgs &a, int nsys, int maxn, int k, const double *wneg, hipStream_t st);
+void launch_gm_update(const GmresArgs &a, int nsys, double *x, hipStream_t st);
+void launch_strip_gather(const StripArgs &a, int nstrip, const double *v, hipStream_t st);
+void launch_strip_scatter(const StripArgs &a, int nstrip, double *z, hipStream_t st);
+size_t gm_arnoldi_lds(int maxn);
 
 hipError_t upload_constants(const RefData &r, const Coef &c, hipStream_t st);
 void launch_prolong_p2(const ProlongArgs &a, hipStream_t st);

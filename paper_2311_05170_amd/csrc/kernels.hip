@@ -578,7 +578,7 @@ __global__ __launch_bounds__(GB) void k_oseen_assemble(OseenApplyArgs<T> A) {
                     // entries of rows (la, c) against columns (k, d) and pressure v
                     double Nw[2][2][6];     // [c][d][k]
                     for (int c = 0; c < 2; ++c) for (int d = 0; d < 2; ++d) for (int k = 0; k < 6; ++k) Nw[c][d][k] = 0.0;
-                    if (c_co.convection) {
+                    if (c_co.convection && !A.no_convection) {
                         for (int qq = 0; qq < NQ; ++qq) {
                             double wv[2] = {0, 0}, gw[2][2] = {{0, 0}, {0, 0}};
                             for (int k = 0; k < 6; ++k) {
@@ -705,10 +705,12 @@ constexpr int RT = 8;
 constexpr int RT_TRI = 2 * (RT + 1) * (RT + 1);
 int residual_tiles(int cx, int cy) { return ((cx + RT - 1) / RT) * ((cy + RT - 1) / RT); }
 
+// Apply mode (b null): r = -K x without norms or flags (part null), systems
+// whose conv flag is set skipped.
 __global__ __launch_bounds__(256) void k_oseen_residual_tiled(OseenApplyArgs<double> A) {
     const SysDesc S = A.sys[blockIdx.y];
     if (A.skip && *A.skip) return;
-    if (A.conv[blockIdx.y]) return;
+    if (A.conv && A.conv[blockIdx.y]) return;
     const int ntx = (S.cx + RT - 1) / RT, nty = (S.cy + RT - 1) / RT;
     const bool has = (int)blockIdx.x < ntx * nty;
     const int tx = has ? (int)blockIdx.x % ntx : 0, ty = has ? (int)blockIdx.x / ntx : 0;
@@ -826,20 +828,20 @@ __global__ __launch_bounds__(256) void k_oseen_residual_tiled(OseenApplyArgs<dou
             }
             if (dv >= 0)
                 for (int c = 0; c < 2; ++c) {
-                    const double bv = A.b[S.dof_off + dv + c], rv = bv - yv[c];
+                    const double bv = A.b ? A.b[S.dof_off + dv + c] : 0.0, rv = bv - yv[c];
                     A.r[S.dof_off + dv + c] = rv;
                     rr += rv * rv;
                     bb += bv * bv;
                 }
             if (dp >= 0) {
-                const double bv = A.b[S.dof_off + dp], rv = bv - yq;
+                const double bv = A.b ? A.b[S.dof_off + dp] : 0.0, rv = bv - yq;
                 A.r[S.dof_off + dp] = rv;
                 rr += rv * rv;
                 bb += bv * bv;
             }
         }
     }
-    grid_norms_and_flag(rr, bb, A.part, A.ticket, A.conv, A.relres, A.sweeps, A.tol, blockIdx.y);
+    if (A.part) grid_norms_and_flag(rr, bb, A.part, A.ticket, A.conv, A.relres, A.sweeps, A.tol, blockIdx.y);
 }
 
 // Local Oseen right-hand sides by the same tiles as the residual: each
@@ -2213,8 +2215,12 @@ __device__ __forceinline__ void col_load(__amdgpu_buffer_rsrc_t rs, int voff, in
     } else if constexpr (NB == 16) {
         const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0);
         w[0] = v[0]; w[1] = v[1]; w[2] = v[2]; w[3] = v[3];
+    } else if constexpr (NB == 32) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0);
+        const auto u = __builtin_amdgcn_raw_buffer_load_b128(rs, voff + 16, soff, 0);
+        w[0] = v[0]; w[1] = v[1]; w[2] = v[2]; w[3] = v[3]; w[4] = u[0]; w[5] = u[1]; w[6] = u[2]; w[7] = u[3];
     } else {
-        static_assert(NB == 24, "two or three values per lane");
+        static_assert(NB == 24, "two to four values per lane");
         const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, 0);
         const auto u = __builtin_amdgcn_raw_buffer_load_b64(rs, voff + 16, soff, 0);
         w[0] = v[0]; w[1] = v[1]; w[2] = v[2]; w[3] = v[3]; w[4] = u[0]; w[5] = u[1];
@@ -2604,7 +2610,7 @@ void launch_oseen_finalize(const FinalizeArgs &a, int nsys, int maxnodes, hipStr
 
 template <typename T>
 bool launch_band_lu(const BandArgs<T> &a, int nsys, int maxbw, int variant, hipStream_t st) {
-    if (variant == 9) {
+    if (variant == 9 && maxbw <= 160) {
         // the same with a one-panel lookahead
         if (maxbw <= 64) { hipLaunchKernelGGL((k_band_lu_la<T, 5>), dim3(nsys), dim3(64 * (5 + LU_NS)), 0, st, a); return true; }
         if (maxbw <= 96) { hipLaunchKernelGGL((k_band_lu_la<T, 7>), dim3(nsys), dim3(64 * (7 + LU_NS)), 0, st, a); return true; }
@@ -2612,7 +2618,7 @@ bool launch_band_lu(const BandArgs<T> &a, int nsys, int maxbw, int variant, hipS
         if (maxbw <= 160) { hipLaunchKernelGGL((k_band_lu_la<T, 11>), dim3(nsys), dim3(64 * (11 + LU_NS)), 0, st, a); return true; }
         return false;
     }
-    if (variant == 8) {
+    if (variant == 8 && maxbw <= 160) {
         // blocked factorisation on the matrix cores: window 16 TT >= bw + 16
         constexpr int X = 64 * LU_NS;
         if (maxbw <= 64) { hipLaunchKernelGGL((k_band_lu_mfma<T, 5, 4>), dim3(nsys), dim3(256 + X), 0, st, a); return true; }
@@ -2633,6 +2639,8 @@ bool launch_band_lu(const BandArgs<T> &a, int nsys, int maxbw, int variant, hipS
         else hipLaunchKernelGGL((k_band_lu<T, 20, 8>), dim3(nsys), dim3(400), 0, st, a);
         return true;
     }
+    // wider than the blocked kernels' windows (every variant lands here)
+    if (maxbw <= LU_MAX_BW) { hipLaunchKernelGGL((k_band_lu<T, 22, 8>), dim3(nsys), dim3(484), 0, st, a); return true; }
     return false;
 }
 
@@ -2644,6 +2652,7 @@ bool launch_band_solve_d(const SolveArgs<T> &a, int nsys, int nrhs, int maxbw, i
     switch (solve_nr(maxbw)) {
     case 2: hipLaunchKernelGGL((k_band_solve<T, 2, D>), g, dim3(SOLVE_THREADS), sh, st, a); break;
     case 3: hipLaunchKernelGGL((k_band_solve<T, 3, D>), g, dim3(SOLVE_THREADS), sh, st, a); break;
+    case 4: hipLaunchKernelGGL((k_band_solve<T, 4, D>), g, dim3(SOLVE_THREADS), sh, st, a); break;
     default: return false;
     }
     return true;

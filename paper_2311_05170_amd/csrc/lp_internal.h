@@ -100,10 +100,26 @@ struct Plan {
     std::vector<int32_t> own2_lo[2][2], own2_n[2][2], own1_lo[2][2], own1_n[2][2];
     int64_t local_dofs = 0;
     int max_bw = 0;
+    // Strips of the local Oseen boxes for the Krylov path's preconditioner:
+    // each conduit box cut along x into strips of at most strip_width cells
+    // (cores of equal width, extended by strip_overlap cells into their
+    // neighbours).  A strip is a box with the standard node classes, so its
+    // faces inside the box are artificial (zero).  Per strip unknown, the
+    // parent system's unknown (smap) and whether this strip owns it (sown:
+    // its x lies in the strip's core; every parent unknown has one owner).
+    std::vector<SysDesc> strip;
+    std::vector<int32_t> strip_parent;      // index into ose
+    std::vector<int32_t> smap;              // strip vector space -> parent unknown
+    std::vector<int8_t> sown;
+    long long band_total_strip = 0, dof_total_strip = 0;
+    int strip_width = 0, strip_overlap = 0;
 };
 
 // plan.cpp
 bool build_plan(const lp_mesh &m, const lp_partition &p, Plan &out, std::string &err);
+// strips of every local Oseen box (appends their node tables); false if a
+// strip's half-bandwidth exceeds max_bw
+bool build_strips(Plan &P, int width, int overlap, int max_bw, std::string &err);
 
 // fe.cpp: reference data and manufactured-solution data on a region lattice
 void build_refdata(RefData &r);

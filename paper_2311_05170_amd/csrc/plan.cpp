@@ -223,4 +223,79 @@ bool build_plan(const lp_mesh &m, const lp_partition &p, Plan &P, std::string &e
     return true;
 }
 
+bool build_strips(Plan &P, int width, int overlap, int max_bw, std::string &err) {
+    if (width < 2 * overlap + 1 || overlap < 1) { err = "strip width must exceed twice the strip overlap (>= 1)"; return false; }
+    P.strip.clear(); P.strip_parent.clear(); P.smap.clear(); P.sown.clear();
+    P.strip_width = width;
+    P.strip_overlap = overlap;
+    long long band = 0, dof = 0;
+    for (int j = 0; j < (int)P.ose.size(); ++j) {
+        const SysDesc &par = P.ose[j];
+        const int w = par.cx;
+        const int ns = w <= width ? 1 : (w + (width - 2 * overlap) - 1) / (width - 2 * overlap);
+        for (int k = 0; k < ns; ++k) {
+            // core [c0, c1) in box cells, equal widths (remainder to the first cores)
+            const int c0 = par.x0 + (int)((long long)w * k / ns), c1 = par.x0 + (int)((long long)w * (k + 1) / ns);
+            const int s0 = std::max(par.x0, c0 - (ns > 1 ? overlap : 0));
+            const int s1 = std::min(par.x0 + par.cx, c1 + (ns > 1 ? overlap : 0));
+            SysDesc s = par;
+            s.x0 = s0;
+            s.cx = s1 - s0;
+            s.sub = j;
+            number_system(s, P.cls2, P.dof2, P.cls1, P.dof1);
+            if (s.bw > max_bw) {
+                std::ostringstream e;
+                e << "strip half-bandwidth " << s.bw << " exceeds " << max_bw;
+                err = e.str();
+                return false;
+            }
+            s.band_off = band; band += s.band_size;
+            s.dof_off = dof; dof += s.ndof;
+            s.e2_off = 0; s.e1_off = 0;
+            // unknown maps: strip node (a, b) sits at parent lattice (a + 2 (s0 - x0), b)
+            P.smap.resize(dof, -1);
+            P.sown.resize(dof, 0);
+            const int da = 2 * (s0 - par.x0);
+            const bool last = k == ns - 1;
+            auto owned = [&](int A) { return A >= 2 * c0 && (last ? A <= 2 * c1 : A < 2 * c1); };
+            for (int b = 0; b < s.lh2; ++b)
+                for (int a = 0; a < s.lw2; ++a) {
+                    const int ds = P.dof2[s.node_off + a + s.lw2 * b];
+                    if (ds < 0) continue;
+                    const int dp = P.dof2[par.node_off + (a + da) + par.lw2 * b];
+                    if (dp < 0) { err = "strip unknown without a parent unknown"; return false; }
+                    const bool own = owned(2 * s0 + a);
+                    for (int c = 0; c < 2; ++c) {
+                        P.smap[s.dof_off + ds + c] = dp + c;
+                        P.sown[s.dof_off + ds + c] = own;
+                    }
+                }
+            for (int jj = 0; jj < s.lh1; ++jj)
+                for (int i = 0; i < s.lw1; ++i) {
+                    const int ds = P.dof1[s.vert_off + i + s.lw1 * jj];
+                    if (ds < 0) continue;
+                    const int dp = P.dof1[par.vert_off + (i + da / 2) + par.lw1 * jj];
+                    if (dp < 0) { err = "strip unknown without a parent unknown"; return false; }
+                    P.smap[s.dof_off + ds] = dp;
+                    P.sown[s.dof_off + ds] = owned(2 * (s0 + i));
+                }
+            P.strip.push_back(s);
+            P.strip_parent.push_back(j);
+        }
+    }
+    P.band_total_strip = band;
+    P.dof_total_strip = dof;
+    // every parent unknown has exactly one owning strip
+    std::vector<int> owners(P.dof_total_ose, 0);
+    for (size_t si = 0; si < P.strip.size(); ++si) {
+        const SysDesc &s = P.strip[si];
+        const long long base = P.ose[P.strip_parent[si]].dof_off;
+        for (int d = 0; d < s.ndof; ++d)
+            if (P.sown[s.dof_off + d]) owners[base + P.smap[s.dof_off + d]]++;
+    }
+    for (long long i = 0; i < P.dof_total_ose; ++i)
+        if (owners[i] != 1) { err = "strip ownership is not a partition of the local unknowns"; return false; }
+    return true;
+}
+
 }  // namespace lp

@@ -75,7 +75,8 @@ class LpStats(Structure):
     _fields_ = [("step", c_int64), ("n_porous", c_int64), ("n_conduit", c_int64),
                 ("local_dofs", c_int64), ("max_bw", c_int64), ("newton_its", c_int32),
                 ("ir_sweeps", c_int32), ("ir_relres", c_double), ("flags", c_int32),
-                ("newton_its_max", c_int32), ("ir_sweeps_max", c_int32), ("ir_relres_max", c_double)]
+                ("newton_its_max", c_int32), ("ir_sweeps_max", c_int32), ("ir_relres_max", c_double),
+                ("solver", c_int32), ("krylov_its", c_int32)]
 
 
 class LpError(RuntimeError):
@@ -160,7 +161,7 @@ class LocalParallel:
     def __init__(self, n_coarse, refine, nsub, overlap, prm, dt, cuts=None, precision="mixed",
                  convection=True, max_ir=8, ir_tol=None, max_newton=16, newton_tol=1e-13,
                  jacobian_every=1, solver="auto", coarse_ns="newton", samples=None,
-                 torch_allocator=True):
+                 krylov_restart=30, krylov_tol=None, torch_allocator=True):
         import torch
         self._torch = torch
         if not torch.cuda.is_available():
@@ -177,8 +178,8 @@ class LocalParallel:
         opt.jacobian_every = int(jacobian_every)
         opt.solver = SOLVER[solver]
         opt.coarse_ns = COARSE_NS[coarse_ns]
-        opt.krylov_tol = 1e-12
-        opt.max_iter = 200
+        opt.krylov_tol = float(krylov_tol if krylov_tol is not None else opt.ir_tol)
+        opt.max_iter = int(krylov_restart)
         plist = [prm] if samples is None else list(samples)
         opt.nsamples = len(plist)
         params = (LpParams * len(plist))(*[_params(q, dt) for q in plist])

@@ -62,7 +62,7 @@ def _setup_status(opt_kw=None, samples=None, prm_kw=None):
     opt = lib.LpOptions()
     opt.problem, opt.precision, opt.convection, opt.max_ir, opt.ir_tol = 0, lib.LP_MIXED, 1, 4, 1e-10
     opt.max_newton, opt.newton_tol, opt.jacobian_every = 8, 1e-13, 1
-    opt.solver, opt.coarse_ns, opt.krylov_tol, opt.max_iter, opt.nsamples = 0, 0, 1e-12, 100, 1
+    opt.solver, opt.coarse_ns, opt.krylov_tol, opt.max_iter, opt.nsamples = 0, 0, 1e-12, 30, 1
     for k, v in (opt_kw or {}).items():
         setattr(opt, k, v)
     plist = samples or [dict(W.unit_params(), **(prm_kw or {}))]
@@ -88,8 +88,34 @@ def test_setup_rejects_bad_options_without_a_device():
     st, msg = _setup_status({"nsamples": 2}, samples=[W.unit_params(), dict(W.unit_params(), k=[0.0, 1, 1])])
     assert st == 1 and "sample 1" in msg          # every sample is validated
     assert _setup_status({"nsamples": 2}, samples=[W.unit_params()] * 2)[0] == 6
-    assert _setup_status({"solver": lib.LP_KRYLOV})[0] == 6
+    assert _setup_status({"solver": lib.LP_KRYLOV, "max_iter": 65})[0] == 1
+    assert _setup_status({"solver": lib.LP_KRYLOV, "krylov_tol": 0.0})[0] == 1
     assert _setup_status({"coarse_ns": lib.LP_SEMI_IMPLICIT})[0] == 6
+
+
+@pytest.mark.parametrize("name,width", [("cfg3", 16), ("cfg2", 6), ("cfg1", 5)])
+def test_krylov_strips_cover_each_box(name, width):
+    """The Krylov path's preconditioner strips (one query): every conduit box
+    is cut along x into strips of at most `width` cells with 2 cells of
+    overlap, strips span the box's height, consecutive strips overlap, and
+    every strip's band fits the 159 window (the library also checks that the
+    strips' owned unknowns partition each box's unknowns)."""
+    cfg = W.config(name)
+    flat = W.flat_cuts(cfg["cuts"])
+    args = (cfg["NH"], cfg["refine"], cfg["nsub"], cfg["overlap"])
+    tab = lib.plan_query(*args, 0, cuts=flat).reshape(-1, 9)
+    st = lib.plan_query(*args, 7, width, cuts=flat).reshape(-1, 7)
+    npor = cfg["nsub"][0] * cfg["nsub"][1]
+    assert (st[:, 6] <= 159).all() and (st[:, 2] - st[:, 1] <= width).all()
+    for j in range(len(tab) - npor):
+        box = tab[npor + j]
+        mine = st[st[:, 0] == j]
+        assert len(mine) >= 1
+        assert mine[0, 1] == box[1] and mine[-1, 2] == box[2]
+        assert (mine[:, 3] == box[3]).all() and (mine[:, 4] == box[4]).all()
+        assert (mine[1:, 1] < mine[:-1, 2]).all()          # neighbours overlap
+        if box[2] - box[1] <= width:
+            assert len(mine) == 1
 
 
 @pytest.mark.parametrize("name", ["cfg1", "cfg2", "cfg3"])

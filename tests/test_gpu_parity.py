@@ -84,7 +84,7 @@ def local_corrections(o, g):
     return {f: diff[f] / max(scale[f], 1e-300) for f in diff}
 
 
-def run_parity(cfg, precision, steps, locals_every_step=True, **kw):
+def run_parity(cfg, precision, steps, locals_every_step=True, keep=False, **kw):
     o = _oracle(cfg, **{k: v for k, v in kw.items() if k == "convection"})
     g = _gpu(cfg, precision, **kw)
     worst = 0.0
@@ -110,6 +110,8 @@ def run_parity(cfg, precision, steps, locals_every_step=True, **kw):
     # no refinement or coarse step ended unconverged, no bad pivot (sticky flags)
     st = g.stats()
     assert st["flags"] == 0, st
+    if keep:
+        return g
     g.close()
     return worst
 
@@ -207,6 +209,66 @@ def test_cfg2_bench_window_matches_stored_oracle(precision):
     g.close()
     assert st["flags"] == 0 and st["ir_sweeps_max"] <= 2, st
     assert st["ir_relres_max"] <= (1e-10 if precision == "mixed" else 1e-12), st
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("width", ["6", "16"])
+def test_parity_krylov_cfg1(precision, width, monkeypatch):
+    """The Krylov path of the local Oseen solves (Eq. (5.8)): FGMRES in FP64
+    with the matrix-free operator, preconditioned by restricted additive
+    Schwarz over strips whose Stokes-part band matrices were factored at
+    setup.  Strips of at most 6 cells cut every 6-8 cell box of cfg1 into 2-4
+    overlapping strips; 16 leaves one strip per box (the whole box's Stokes
+    part).  All five steps against the oracle."""
+    monkeypatch.setenv("LP_KRYLOV_STRIP", width)
+    cfg = W.config("cfg1")
+    g = run_parity(cfg, precision, cfg["steps"], solver="krylov", max_ir=4, keep=True)
+    st = g.stats()
+    g.close()
+    assert st["solver"] == 2 and 1 <= st["krylov_its"] <= 4 * 30, st
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_parity_krylov_shifted_cuts(precision, monkeypatch):
+    """The Krylov path on uneven cores (explicit shifted cuts), strips of at
+    most 6 cells."""
+    monkeypatch.setenv("LP_KRYLOV_STRIP", "6")
+    run_parity(W.shifted_small(), precision, 3, solver="krylov", max_ir=4)
+
+
+FIXTURE3 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cfg3_oracle_sampled.npz")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_cfg3_uneven_batch_matches_stored_oracle(precision):
+    """The uneven h = 1/256 workload (16 x 16 + 16 x 16 subdomains with
+    SplitMix64-shifted cuts, local systems of 1.6k-5.9k porous and 4.4k-12.9k
+    Oseen unknowns, half-bandwidths to 399): the local Oseen systems go to the
+    Krylov path (too wide for the band window) and the porous ones to the band
+    factorisation, all in one launch per stage.  Two steps against the
+    oracle's record (tests/golden/make_cfg3_fixture.py): the full coarse
+    fields, and every 29th entry of each merged field element by element (the
+    record holds each field's largest magnitude), plus each field's sum of
+    squares."""
+    ref = np.load(FIXTURE3)
+    stride = int(ref["stride"])
+    cfg = W.config("cfg3")
+    g = _gpu(cfg, precision, max_ir=3)
+    assert g.stats()["solver"] == 2
+    for n in (1, 2):
+        g.step()
+        for f in ("pF", "pf", "pm", "u", "p"):
+            c = g.solution(f, "coarse")
+            assert np.max(np.abs(c - ref["coarse_%d_%s" % (n, f)])) <= 1e-10 * np.max(np.abs(c)), (n, f)
+            a = g.solution(f)
+            ee = np.max(np.abs(a[::stride] - ref["merged_%d_%s_val" % (n, f)])) / float(ref["merged_%d_%s_max" % (n, f)])
+            ss = abs(float(np.dot(a, a)) / float(ref["merged_%d_%s_ss" % (n, f)]) - 1.0)
+            print("step", n, f, "sampled elementwise %.1e, sum of squares %.1e" % (ee, ss), flush=True)
+            assert ee < ELEM_TOL[precision] and ss < 10 * ELEM_TOL[precision], (n, f, ee, ss)
+    st = g.stats()
+    g.close()
+    print(st, flush=True)
+    assert st["flags"] == 0, st
 
 
 def test_refinement_failure_is_sticky_and_reported():
@@ -437,11 +499,12 @@ def test_h_equals_H_gives_zero_corrections():
 
 
 def test_unsupported_bandwidth_is_reported():
-    """The uneven h = 1/256 workload needs half-bandwidths up to 399: lp_setup
-    refuses it with LP_ERR_UNSUPPORTED instead of running out of the kernels'
-    window."""
+    """The h = 1/256 workload's local Oseen systems (half-bandwidths to 399)
+    do not fit the band window: with the band factorisation requested
+    (LP_DENSE) lp_setup refuses them with LP_ERR_UNSUPPORTED instead of
+    running out of the kernels' window."""
     from paper_2311_05170_amd.lib import LpError
     with pytest.raises(LpError) as e:
-        _gpu(W.config("cfg3"), "mixed")
+        _gpu(W.config("cfg3"), "mixed", solver="dense")
     assert e.value.status == 6
     assert "bandwidth" in str(e.value)
