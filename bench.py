@@ -66,18 +66,36 @@ JACOBIAN_EVERY = 3
 # its system has converged; two reach the 1e-10 tolerance on this workload)
 MAX_IR_MIXED = 2
 # refinement sweeps launched on the uneven h = 1/256 workload: each sweep of
-# its Krylov path is one GMRES cycle (restart 30), one of which usually
-# reaches the tolerance; a second is launched and skips itself if not needed
-UNEVEN_MAX_IR = 2
+# its Krylov path is one GMRES cycle (restart 30); the mixed path takes three
+# to the 1e-10 tolerance, the FP64 path one (later ones skip themselves)
+UNEVEN_MAX_IR = 3
 UNEVEN_STEPS, UNEVEN_WARMUP = 5, 2
 
 
-def make(cfg, precision, max_ir):
+def make(cfg, precision, max_ir, graphs=False):
     from paper_2311_05170_amd import workloads as W
     from paper_2311_05170_amd.lib import LocalParallel
     return LocalParallel(cfg["NH"], cfg["refine"], cfg["nsub"], cfg["overlap"], cfg["prm"], cfg["dt"],
                          cuts=W.flat_cuts(cfg["cuts"]), precision=precision, max_ir=max_ir,
-                         max_newton=MAX_NEWTON, jacobian_every=JACOBIAN_EVERY)
+                         max_newton=MAX_NEWTON, jacobian_every=JACOBIAN_EVERY, graphs=graphs)
+
+
+def graph_run(cfg, precision, steps, warmup, max_ir):
+    """The same timed region with every step's launch sequences replayed as
+    HIP graphs (lp_options.graphs)."""
+    import torch
+    g = make(cfg, precision, max_ir, graphs=True)
+    for _ in range(warmup):
+        g.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st = g.stats()
+    g.close()
+    return dict(ms_per_step=(t1 - t0) * 1e3 / steps, stats=st)
 
 
 def timed_run(cfg, precision, steps, warmup, max_ir):
@@ -404,6 +422,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-uneven", action="store_true", help="skip the h = 1/256 uneven-batch line")
+    ap.add_argument("--uneven-only", action="store_true",
+                    help="run only the h = 1/256 uneven batch (both precisions) and print its object")
     ap.add_argument("--cpu-leg", default=None, help=argparse.SUPPRESS)
     ap.add_argument("--cpu-pool", type=int, default=1, help=argparse.SUPPRESS)
     ap.add_argument("--summarize-trace", default=None, metavar="KERNEL_TRACE_CSV",
@@ -419,6 +439,14 @@ def main():
         return
     if args.summarize_trace:
         summarize_trace(args.summarize_trace)
+        return
+    if args.uneven_only:
+        import torch
+        assert torch.cuda.is_available(), "bench.py needs a HIP device"
+        um = uneven_run("mixed", UNEVEN_STEPS, UNEVEN_WARMUP)
+        uf = uneven_run("fp64", UNEVEN_STEPS, UNEVEN_WARMUP)
+        print(json.dumps({"uneven_batch": {"mixed": {"ms_per_step": um["ms_per_step"], "stats": um["stats"]},
+                                           "fp64": {"ms_per_step": uf["ms_per_step"], "stats": uf["stats"]}}}), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the local stage needs no communication while "
@@ -445,6 +473,8 @@ def main():
     mixed = timed_run(cfg, "mixed", args.steps, args.warmup, MAX_IR_MIXED)
     fp64 = timed_run(cfg, "fp64", args.steps, args.warmup, 2)
     lu_ms, lu_n = serial_lu_time(cfg, "mixed", MAX_IR_MIXED)
+    gmix = graph_run(cfg, "mixed", args.steps, args.warmup, MAX_IR_MIXED)
+    gf64 = graph_run(cfg, "fp64", args.steps, args.warmup, 2)
     uneven = None
     if not args.no_uneven:
         cfg3 = W.config("cfg3")
@@ -480,7 +510,7 @@ def main():
     coarse = lib.plan_query(*qargs, 6, cuts=flat)
     roof_ms_mixed, stages_mixed = step_roofline(cfg, sizes, tab, coarse, mixed["stats"], 4, JACOBIAN_EVERY)
     roof_ms_fp64, stages_fp64 = step_roofline(cfg, sizes, tab, coarse, fp64["stats"], 8, JACOBIAN_EVERY)
-    flags = [mixed["stats"]["flags"], fp64["stats"]["flags"]]
+    flags = [mixed["stats"]["flags"], fp64["stats"]["flags"], gmix["stats"]["flags"], gf64["stats"]["flags"]]
     if uneven:
         flags += [uneven["mixed"]["flags"], uneven["fp64"]["flags"]]
     line = {
@@ -501,6 +531,10 @@ def main():
                    "local_dofs_per_step": L, "subdomains": int(len(sizes)),
                    "max_halfbandwidth": int(sizes[:, 1].max())},
         "fp64": {"value": rate(fp64["ms_per_step"]), "ms_per_step": fp64["ms_per_step"], "dtype": "f64"},
+        "graphs": {"mixed": {"value": rate(gmix["ms_per_step"]), "ms_per_step": gmix["ms_per_step"]},
+                   "fp64": {"value": rate(gf64["ms_per_step"]), "ms_per_step": gf64["ms_per_step"]},
+                   "note": "every step's launch sequences replayed as HIP graphs (lp_options.graphs = 1); "
+                           "value and ms_per_step above are direct launches"},
         "stages_ms": {"mixed": mixed["stages_ms"], "fp64": fp64["stages_ms"]},
         "refinement": {"scope": "every step of the run (warmup + timed), sticky",
                        "mixed_sweeps_max": mixed["stats"]["ir_sweeps_max"], "mixed_max_sweeps": MAX_IR_MIXED,

@@ -134,6 +134,23 @@ typedef struct {
     int32_t max_iter;        /* GMRES restart length, 1..64 (the Arnoldi steps of one cycle) */
     int32_t nsamples;        /* parameter samples advanced together (lp_setup's samples[]);
                                 0 or 1: one sample.  More than one: LP_ERR_UNSUPPORTED */
+    int32_t autotune;        /* 1: at the end of lp_setup, time the local Oseen solves on this
+                                run's own systems: the band factorisation kernel (three
+                                variants) and the band solve prefetch depth are set to the
+                                fastest, and under LP_AUTO, where the band path fits, both
+                                paths are set up and the faster batch of solves (the dense
+                                path's assembly, factorisation and refinement against the
+                                Krylov path's GMRES cycles) is kept.  0: fixed defaults. */
+    int32_t graphs;          /* 1: every launch sequence that one stream runs between event
+                                operations in a step (coarse porous part, coarse Newton
+                                chain, prolongation, assembly and factorisation, porous
+                                batch, Oseen right-hand sides, Oseen refinement, merge) is
+                                captured once per sequence and ring slot (from the third
+                                step on) and replayed as a HIP graph on its stream: every
+                                argument of a sequence is a function of the slot (the step's
+                                time factors are computed on the device), so a replay is the
+                                next step of that slot.  Steps with stage timers on
+                                (lp_set_timing) use direct launches.  0: direct launches. */
 } lp_options;
 
 /* Optional device allocator (e.g. a framework's caching allocator). */
@@ -159,8 +176,15 @@ typedef struct {
     int32_t ir_sweeps_max;   /* most refinement sweeps of any system in any local step so far */
     double ir_relres_max;    /* largest final relative residual of any system in any local step */
     int32_t solver;          /* local Oseen solver in use: LP_DENSE or LP_KRYLOV */
+    int32_t tuned;           /* 1 if lp_setup autotuned (lp_options.autotune) */
+    int32_t lu_variant;      /* band factorisation kernel of the local Oseen systems */
+    int32_t solve_depth;     /* band solve prefetch depth (0: the default per precision) */
+    double tune_dense_ms;    /* autotuning: one batch of local Oseen solves by the band path */
+    double tune_krylov_ms;   /* ... and by the Krylov path (0 if that path was not set up) */
     int32_t krylov_its;      /* LP_KRYLOV: most GMRES (Arnoldi) steps of any local Oseen
                                 system in the last local step, over its cycles */
+    int32_t ir_sweeps_porous, ir_sweeps_oseen;   /* ir_sweeps split by system kind */
+    double ir_relres_porous, ir_relres_oseen;    /* ir_relres split by system kind */
 } lp_stats;
 
 /* Build meshes, partition, reference data and device buffers; interpolate the

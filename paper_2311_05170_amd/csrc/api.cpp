@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -83,7 +84,7 @@ struct lp_ctx {
     // steps).  A slot is rewritten only after the local step that last reads
     // it has finished.
     static constexpr int RING = 8;
-    static constexpr int FSLOTS = 5;   // factor slots of the local Oseen operators (< RING)
+    static constexpr int FSLOTS = 8;   // factor slots of the local Oseen operators (<= RING, a divisor of it)
     hipStream_t cstream = nullptr;
     hipEvent_t ev_coarse[RING] = {}, ev_local[RING] = {};
     hipEvent_t ev_cpor[RING] = {};     // coarse porous solves of a level done (they run on a factor stream)
@@ -102,6 +103,25 @@ struct lp_ctx {
     // rewritten once local step m - FSLOTS has finished.
     hipStream_t fstream[2] = {};
     hipEvent_t ev_fac[FSLOTS] = {};
+    // Graph mode (lp_options.graphs): each launch sequence that one stream
+    // runs between event operations (the coarse porous and Navier-Stokes
+    // parts, the prolongation, the assembly and factorisation, the porous
+    // batch, the local Oseen right-hand sides, refinement and merge) is
+    // captured once per (sequence, ring slot) on lstream, a stream that only
+    // records, and replayed as a HIP graph on the stream the sequence belongs
+    // to.
+    static constexpr int GSLOTS = RING;
+    bool graphs = false;
+    hipStream_t lstream = nullptr;
+    std::map<int, hipGraphExec_t> gx;
+    int64_t seg_m = 0;             // the step whose launches seg() is issuing
+    int key_off = 0;               // graph key offset of the local step's scratch (allocation-free variant)
+    // time factors (cos t, sin t, cos^2 t) of each ring slot's level, and the
+    // slot's level counter (next level of the slot, advanced by RING)
+    double *tf_dev = nullptr;
+    long long *level_dev = nullptr;
+    double *tf_slot(int slot) const { return tf_dev + 4 * slot; }
+    int64_t graph_launches = 0, graph_instantiations = 0;
     int ecur = 0;                  // correction buffers holding e^n
     bool serial = false;           // diagnostic (LP_SERIAL=1): all stages on one stream, no overlap
     bool mixed = false;
@@ -168,7 +188,13 @@ struct lp_ctx {
     // additive Schwarz over strips whose Stokes-part band matrices are
     // factored once at setup
     bool krylov = false;
+    bool have_dense = false, have_strips = false;  // resources of each local Oseen path
     int gm_m = 0;
+    int gm_reorth = 0;             // second Gram-Schmidt pass in the Arnoldi steps (LP_GM_REORTH)
+    // setup-time autotuning (lp_options.autotune): measured milliseconds of
+    // one local Oseen solve batch by each path, and what was chosen
+    bool tuned = false;
+    double tune_dense_ms = 0.0, tune_krylov_ms = 0.0;
     lp::SysDesc *d_strip = nullptr;
     int32_t *d_strip_parent = nullptr, *d_smap = nullptr;
     int8_t *d_sown = nullptr;
@@ -232,6 +258,9 @@ struct lp_ctx {
         for (int i = 0; i < FSLOTS; ++i)
             if (ev_fac[i]) (void)hipEventDestroy(ev_fac[i]);
         if (ev_por) (void)hipEventDestroy(ev_por);
+        if (lstream) { (void)hipStreamSynchronize(lstream); (void)hipStreamDestroy(lstream); }
+        for (auto &kv : gx)
+            if (kv.second) (void)hipGraphExecDestroy(kv.second);
         for (auto &r : recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
         for (auto e : pool) (void)hipEventDestroy(e);
         for (void *p : owned) {
@@ -296,6 +325,50 @@ struct StageTimer {
         if (b && hipEventRecord(b, st) == hipSuccess) c->recs.push_back({a, b, stage});
     }
 };
+
+// Run the launches of `body` on stream st: directly, or (graph mode, no stage
+// timers, from the third step on) as the HIP graph of `key`, captured and
+// instantiated the first time the key is met and replayed after that.  A key
+// names a launch sequence and a ring slot: every argument of the sequence is
+// a function of the slot (buffers of the slot's level, the slot's time
+// factors in device memory) and not of the step, so a replay does the next
+// step of that slot exactly.  A key's replays all go to the same stream.
+template <class F>
+lp_status seg(lp_ctx *c, int key, hipStream_t st, F &&body) {
+    if (!c->graphs || c->tmask || c->seg_m < 3) return body(st);
+    hipGraphExec_t &ex = c->gx[key];
+    if (!ex) {
+        // recorded on the context's capture stream (the caller's stream may be
+        // the null stream, which cannot capture), replayed on st
+        hipStream_t cs = c->lstream;
+        HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        const lp_status s = body(cs);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(cs, &graph);
+        if (s != LP_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return s;
+        }
+        if (e != hipSuccess || !graph) return fail(LP_ERR_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        const hipError_t ie = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess) {
+            ex = nullptr;
+            return fail(LP_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+        }
+        c->graph_instantiations += 1;
+    }
+    HIPCHK(hipGraphLaunch(ex, st));
+    c->graph_launches += 1;
+    return LP_OK;
+}
+
+// graph keys: launch sequence x step slot
+enum { G_CPOR = 0, G_CNS = 1, G_CNS_REFRESH = 2, G_PROLONG = 3, G_FACTOR = 4, G_POROUS = 5, G_OSE_RHS = 6,
+       G_OSE_SOLVE = 7, G_MERGE = 8 };
+int gkey(int seq, int64_t m) { return seq * lp_ctx::GSLOTS + (int)(m % lp_ctx::GSLOTS); }
+// the allocation-free local step's sequences read other scratch buffers
+constexpr int G_NOALLOC = 1 << 12;
 
 // Factor storage of a batch: per (system, matrix) n (2 ldf + 1) entries,
 // ldf = 64 NR for the solve's NR registers per lane (L and U columns of ldf
@@ -439,7 +512,7 @@ lp_status refine_oseen_krylov(lp_ctx *c, double *part, int *ticket, const double
                               bool timed, hipStream_t st) {
     const int nsys = (int)c->P.ose.size(), nstrip = (int)c->P.strip.size();
     lp::GmresArgs ga{c->d_ose, c->gm_m, c->P.dof_total_ose, c->gm_V, c->gm_Z, c->gm_H, c->gm_cs, c->gm_sn, c->gm_g,
-                     c->gm_bn, c->gm_done, c->gm_kd, c->opt.krylov_tol, c->conv_ose, c->gm_tot};
+                     c->gm_bn, c->gm_done, c->gm_kd, c->opt.krylov_tol, c->conv_ose, c->gm_tot, c->gm_reorth};
     lp::StripArgs sa{c->d_strip, c->d_strip_parent, c->d_ose, c->d_smap, c->d_sown, c->gm_done, c->s_done, c->s_rs, c->s_zs};
     lp::OseenApplyArgs<double> mv{};
     mv.sys = c->d_ose; mv.cls2 = c->d_cls2; mv.dof2 = c->d_dof2; mv.dof1 = c->d_dof1;
@@ -504,30 +577,32 @@ lp_status local_oseen(lp_ctx *c, hipStream_t st, const LocalScratch &ls) {
     oa.e_old = c->e2[o]; oa.e_new = c->e2[nw]; oa.e_new1 = c->e1[nw];
     oa.b = c->b_ose;
     oa.ir = lp::IrStart{c->x_ose, c->r_ose, c->conv_ose, c->rel_ose, c->sw_ose};
-    const double t1 = time_at(c, c->n + 1);
-    oa.tf[0] = std::cos(t1); oa.tf[1] = std::sin(t1); oa.tf[2] = oa.tf[0] * oa.tf[0];
+    oa.tf = c->tf_slot((int)((c->n + 1) % lp_ctx::RING));
     oa.skip = nullptr;
-    {
-        StageTimer tm(c, LP_T_OSE_RHS, st);
-        lp::launch_oseen_rhs_tiled(oa, nsys, c->tiles_ose, st);
-    }
+    TRY(seg(c, gkey(G_OSE_RHS, c->n + 1) + c->key_off, st, [&](hipStream_t s) -> lp_status {
+        StageTimer tm(c, LP_T_OSE_RHS, s);
+        lp::launch_oseen_rhs_tiled(oa, nsys, c->tiles_ose, s);
+        return LP_OK;
+    }));
     // factors of the operator linearised about Pi_h u_cH^{n+1} (factor stream)
     const int fs = (int)((c->n + 1) % lp_ctx::FSLOTS);
     {
         StageTimer tm(c, LP_T_WAIT_FAC, st);
         HIPCHK(hipStreamWaitEvent(st, c->ev_fac[fs], 0));
     }
-    if (c->krylov)
-        TRY(refine_oseen_krylov<T>(c, ls.part_ose, ls.tick_ose, oa.W1[0], oa.W1[1], c->opt.max_ir, true, st));
-    else
-        TRY(refine_oseen<T>(c, c->d_ose, nsys, c->nodes_ose, ls.part_ose, ls.tick_ose, c->d_sv_ose, (const T *)c->fac_ose[fs], c->maxbw_ose, c->maxn_ose, oa.W1[0], oa.W1[1], c->b_ose,
-                            c->x_ose, c->r_ose, c->conv_ose, c->rel_ose, c->sw_ose, c->P.dof_total_ose, c->opt.max_ir,
-                            c->opt.ir_tol, nullptr, true, st));
-    StageTimer tm(c, LP_T_MERGE, st);
-    lp::FinalizeArgs fa{c->d_ose, c->d_dof2, c->d_dof1, c->x_ose, c->e2[nw], c->e1[nw], nullptr,
-                        lp::IrTotals{c->conv_ose, c->sw_ose, c->rel_ose, 1, c->d_flags, c->d_irmax, c->d_irrel}};
-    lp::launch_oseen_finalize(fa, nsys, c->nodes_ose, st);
-    return LP_OK;
+    return seg(c, gkey(G_OSE_SOLVE, c->n + 1) + c->key_off, st, [&](hipStream_t s) -> lp_status {
+        if (c->krylov)
+            TRY(refine_oseen_krylov<T>(c, ls.part_ose, ls.tick_ose, oa.W1[0], oa.W1[1], c->opt.max_ir, true, s));
+        else
+            TRY(refine_oseen<T>(c, c->d_ose, nsys, c->nodes_ose, ls.part_ose, ls.tick_ose, c->d_sv_ose, (const T *)c->fac_ose[fs], c->maxbw_ose, c->maxn_ose, oa.W1[0], oa.W1[1], c->b_ose,
+                                c->x_ose, c->r_ose, c->conv_ose, c->rel_ose, c->sw_ose, c->P.dof_total_ose, c->opt.max_ir,
+                                c->opt.ir_tol, nullptr, true, s));
+        StageTimer tm(c, LP_T_MERGE, s);
+        lp::FinalizeArgs fa{c->d_ose, c->d_dof2, c->d_dof1, c->x_ose, c->e2[nw], c->e1[nw], nullptr,
+                            lp::IrTotals{c->conv_ose, c->sw_ose, c->rel_ose, 1, c->d_flags, c->d_irmax, c->d_irrel}};
+        lp::launch_oseen_finalize(fa, nsys, c->nodes_ose, s);
+        return LP_OK;
+    });
 }
 
 void prolong_step(lp_ctx *c, int cnew, int cold, int slot, hipStream_t st);
@@ -549,10 +624,11 @@ lp_status factor_oseen(lp_ctx *c, int64_t m) {
     // Oseen stage and the merge of step m; slot nw was last read by local step
     // m - RING, finished before local step m - RING + 1 (coarse step m waited
     // for it)
-    {
-        StageTimer tm(c, LP_T_PROLONG, st);
-        prolong_step(c, nw, (int)((m - 1) % lp_ctx::RING), nw, st);
-    }
+    TRY(seg(c, gkey(G_PROLONG, m), st, [&](hipStream_t s) -> lp_status {
+        StageTimer tm(c, LP_T_PROLONG, s);
+        prolong_step(c, nw, (int)((m - 1) % lp_ctx::RING), nw, s);
+        return LP_OK;
+    }));
     HIPCHK(hipEventRecord(c->ev_pro[nw], st));
     if (c->krylov) {
         // the Krylov path has no per-step factorisation (its strip factors are constant)
@@ -560,21 +636,24 @@ lp_status factor_oseen(lp_ctx *c, int64_t m) {
         return LP_OK;
     }
     const double *pro_Uf = c->pro_slot(nw);
-    {
-        StageTimer tm(c, LP_T_OSE_ASM, st);
-        HIPCHK(hipMemsetAsync(band, 0, (size_t)c->P.band_total_ose * sizeof(T), st));
-        lp::OseenApplyArgs<T> aa{};
-        aa.sys = c->d_ose; aa.cls2 = c->d_cls2; aa.dof2 = c->d_dof2; aa.dof1 = c->d_dof1;
-        aa.W1[0] = pro_Uf; aa.W1[1] = pro_Uf + c->nf2; aa.band = band;
-        lp::launch_oseen_assemble<T>(aa, nsys, c->nodes_ose, st);
-    }
-    {
-        StageTimer tm(c, LP_T_OSE_LU, st);
+    TRY(seg(c, gkey(G_FACTOR, m), st, [&](hipStream_t s) -> lp_status {
+        {
+            StageTimer tm(c, LP_T_OSE_ASM, s);
+            // the band is cleared by a kernel (a memset node would not replay
+            // reliably in a graph)
+            lp::launch_zero_fill(band, (size_t)c->P.band_total_ose * sizeof(T), s);
+            lp::OseenApplyArgs<T> aa{};
+            aa.sys = c->d_ose; aa.cls2 = c->d_cls2; aa.dof2 = c->d_dof2; aa.dof1 = c->d_dof1;
+            aa.W1[0] = pro_Uf; aa.W1[1] = pro_Uf + c->nf2; aa.band = band;
+            lp::launch_oseen_assemble<T>(aa, nsys, c->nodes_ose, s);
+        }
+        StageTimer tm(c, LP_T_OSE_LU, s);
         lp::BandArgs<T> ba{c->d_lu_ose, band, (T *)c->fac_ose[fs], c->d_flags, nullptr, (T *)c->lu_dummy, (const T *)c->consts,
                            c->const_one<T>()};
-        if (!lp::launch_band_lu<T>(ba, nsys, c->maxbw_ose, c->lu_variant_ose, st))
+        if (!lp::launch_band_lu<T>(ba, nsys, c->maxbw_ose, c->lu_variant_ose, s))
             return fail(LP_ERR_UNSUPPORTED, "conduit bandwidth exceeds the factorisation kernels");
-    }
+        return LP_OK;
+    }));
     HIPCHK(hipEventRecord(c->ev_fac[fs], st));
     return LP_OK;
 }
@@ -616,8 +695,7 @@ lp_status local_porous(lp_ctx *c, const double *pro, hipStream_t st, const Local
     pa.Uy0 = pro + 6 * nf2;
     pa.e_old = c->e2[o]; pa.e_new = c->e2[nw]; pa.b = c->b_por;
     pa.ir = lp::IrStart{c->x_por, c->r_por, c->conv_por, c->rel_por, c->sw_por};
-    const double t1 = time_at(c, c->n + 1);
-    pa.tf[0] = std::cos(t1); pa.tf[1] = std::sin(t1); pa.tf[2] = pa.tf[0] * pa.tf[0];
+    pa.tf = c->tf_slot((int)((c->n + 1) % lp_ctx::RING));
     {
         StageTimer tm(c, LP_T_POR_RHS, st);
         lp::launch_porous_rhs_tiled(pa, nsys, c->tiles_por, st);
@@ -724,6 +802,123 @@ lp_status setup_strips(lp_ctx *c, hipStream_t st) {
     TRY(c->dalloc(&c->s_rs, P.dof_total_strip));
     TRY(c->dalloc(&c->s_zs, P.dof_total_strip));
     TRY(c->dalloc(&c->s_done, nstrip));
+    return LP_OK;
+}
+
+// milliseconds between two events recorded around fn's launches on st
+template <class F>
+lp_status time_launches(hipStream_t st, double *ms, F &&fn) {
+    hipEvent_t a = nullptr, b = nullptr;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    HIPCHK(hipEventRecord(a, st));
+    const lp_status s = fn();
+    HIPCHK(hipEventRecord(b, st));
+    HIPCHK(hipEventSynchronize(b));
+    float t = 0.0f;
+    HIPCHK(hipEventElapsedTime(&t, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *ms = t;
+    return s;
+}
+
+// Setup-time autotuning of the local Oseen solves on this run's own systems,
+// linearised about the prolonged initial velocity, with the right-hand side
+// b = -K x for a fixed smooth x (apply mode of the FP64 residual):
+//  - band factorisation kernel (variants 9, 8, 0) and band solve prefetch
+//    depth (16, 32, and 64 in FP32), each kept at its fastest;
+//  - under LP_AUTO with both paths set up: one batch of local Oseen solves
+//    (assembly, factorisation and the refinement sweeps, against the
+//    refinement sweeps of the Krylov path) by each, the faster kept.
+// Each candidate runs once untimed, then once timed.  Nothing here touches
+// the time-stepping state: the band, factor and vector buffers used are
+// rewritten by every step.
+template <typename T>
+lp_status autotune(lp_ctx *c, hipStream_t st) {
+    const int nsys = (int)c->P.ose.size();
+    const long long nt = c->P.dof_total_ose;
+    const double *Wx = c->pro_U1, *Wy = c->pro_U1 + c->nf2;
+    lp::launch_fill_pattern(c->x_ose, nt, st);
+    {
+        lp::OseenApplyArgs<double> mv{};
+        mv.sys = c->d_ose; mv.cls2 = c->d_cls2; mv.dof2 = c->d_dof2; mv.dof1 = c->d_dof1;
+        mv.W1[0] = Wx; mv.W1[1] = Wy;
+        mv.x = c->x_ose; mv.b = nullptr; mv.r = c->b_ose; mv.conv = nullptr;
+        lp::launch_oseen_residual_tiled(mv, nsys, c->tiles_ose, st);
+    }
+    // x = 0, r = b, flags cleared: the state a local step's right-hand side kernel leaves
+    auto reset = [&]() -> lp_status {
+        HIPCHK(hipMemsetAsync(c->x_ose, 0, nt * sizeof(double), st));
+        HIPCHK(hipMemcpyAsync(c->r_ose, c->b_ose, nt * sizeof(double), hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemsetAsync(c->conv_ose, 0, nsys * sizeof(int), st));
+        HIPCHK(hipMemsetAsync(c->sw_ose, 0, nsys * sizeof(int), st));
+        HIPCHK(hipMemsetAsync(c->rel_ose, 0, nsys * sizeof(double), st));
+        return LP_OK;
+    };
+    if (c->have_dense) {
+        T *band = (T *)c->band_ose[0];
+        T *fac = (T *)c->fac_ose[0];
+        auto factor = [&](int variant) -> lp_status {
+            lp::launch_zero_fill(band, (size_t)c->P.band_total_ose * sizeof(T), st);
+            lp::OseenApplyArgs<T> aa{};
+            aa.sys = c->d_ose; aa.cls2 = c->d_cls2; aa.dof2 = c->d_dof2; aa.dof1 = c->d_dof1;
+            aa.W1[0] = Wx; aa.W1[1] = Wy; aa.band = band;
+            lp::launch_oseen_assemble<T>(aa, nsys, c->nodes_ose, st);
+            lp::BandArgs<T> ba{c->d_lu_ose, band, fac, c->d_flags, nullptr, (T *)c->lu_dummy, (const T *)c->consts, c->const_one<T>()};
+            if (!lp::launch_band_lu<T>(ba, nsys, c->maxbw_ose, variant, st)) return fail(LP_ERR_UNSUPPORTED, "factorisation variant");
+            return LP_OK;
+        };
+        double best_lu = 1e30;
+        int best_v = c->lu_variant_ose;
+        for (int v : {9, 8, 0}) {
+            double ms = 0.0;
+            TRY(factor(v));
+            TRY(time_launches(st, &ms, [&] { return factor(v); }));
+            int flags = 0;
+            HIPCHK(hipMemcpy(&flags, c->d_flags, sizeof(int), hipMemcpyDeviceToHost));
+            if (flags & 4) {
+                // a pivot this kernel's arithmetic cannot take: not a candidate
+                flags &= ~4;
+                HIPCHK(hipMemcpy(c->d_flags, &flags, sizeof(int), hipMemcpyHostToDevice));
+                continue;
+            }
+            if (ms < best_lu) { best_lu = ms; best_v = v; }
+        }
+        c->lu_variant_ose = best_v;
+        TRY(factor(best_v));
+        double best_sv = 1e30;
+        int best_d = c->solve_depth;
+        for (int d : {16, 32, 64}) {
+            if (d == 64 && sizeof(T) != 4) continue;
+            c->solve_depth = d;
+            double ms = 0.0;
+            for (int rep = 0; rep < 2; ++rep) {
+                TRY(reset());
+                TRY(time_launches(st, &ms, [&] {
+                    return refine_oseen<T>(c, c->d_ose, nsys, c->nodes_ose, c->part_ose, c->tick_ose, c->d_sv_ose, (const T *)fac,
+                                           c->maxbw_ose, c->maxn_ose, Wx, Wy, c->b_ose, c->x_ose, c->r_ose, c->conv_ose,
+                                           c->rel_ose, c->sw_ose, nt, c->opt.max_ir, c->opt.ir_tol, nullptr, false, st);
+                }));
+            }
+            if (ms < best_sv) { best_sv = ms; best_d = d; }
+        }
+        c->solve_depth = best_d;
+        c->tune_dense_ms = best_lu + best_sv;
+    }
+    if (c->have_strips) {
+        double ms = 0.0;
+        for (int rep = 0; rep < 2; ++rep) {
+            TRY(reset());
+            TRY(time_launches(st, &ms, [&] {
+                return refine_oseen_krylov<T>(c, c->part_ose, c->tick_ose, Wx, Wy, c->opt.max_ir, false, st);
+            }));
+        }
+        c->tune_krylov_ms = ms;
+    }
+    if (c->have_dense && c->have_strips) c->krylov = c->tune_krylov_ms < c->tune_dense_ms;
+    c->tuned = true;
+    HIPCHK(hipStreamSynchronize(st));
     return LP_OK;
 }
 
@@ -868,13 +1063,18 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     // local Oseen solver: the band factorisation where the half-bandwidth fits
     // its window, else (or on request) the Krylov path
     c->krylov = opt->solver == LP_KRYLOV || (opt->solver == LP_AUTO && c->maxbw_ose >= 160);
+    // with autotuning, LP_AUTO sets up both paths where the dense one fits and
+    // keeps the faster (measured at the end of setup)
+    const bool try_both = opt->autotune && opt->solver == LP_AUTO && c->maxbw_ose < 160;
+    c->have_dense = !c->krylov || try_both;
+    c->have_strips = c->krylov || try_both;
     // local systems: window 160 (every factorisation kernel); the coarse
     // ones, factored by the vector-unit kernel when wider, up to LU_MAX_BW
     if (std::max(c->maxbw_por, c->krylov ? 0 : c->maxbw_ose) >= 160 || std::max(P.cpor.bw, P.cns.bw) > lp::LU_MAX_BW)
         return fail(LP_ERR_UNSUPPORTED, "half-bandwidth " +
                                             std::to_string(std::max({c->maxbw_por, c->krylov ? 0 : c->maxbw_ose, P.cpor.bw, P.cns.bw})) +
                                             " exceeds the band kernels' window (159 local, " + std::to_string(lp::LU_MAX_BW) + " coarse)");
-    if (c->krylov) {
+    if (c->have_strips) {
         int width = 16;
         if (const char *v = std::getenv("LP_KRYLOV_STRIP")) width = std::atoi(v);
         if (!lp::build_strips(P, width, 2, 159, why)) return fail(LP_ERR_UNSUPPORTED, "Krylov strips: " + why);
@@ -882,6 +1082,7 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
         if (lp::gm_arnoldi_lds(c->maxn_ose) > lp::GM_LDS_MAX)
             return fail(LP_ERR_UNSUPPORTED, "local Oseen system of " + std::to_string(c->maxn_ose) + " unknowns exceeds the Arnoldi kernel's LDS");
         c->gm_m = opt->max_iter;
+        if (const char *v = std::getenv("LP_GM_REORTH")) c->gm_reorth = std::atoi(v) != 0;
     }
     // coefficients (Section 3.1 / Algorithm 3)
     lp::Coef &co = c->co;
@@ -951,6 +1152,13 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     TRY(c->dalloc(&c->d_done, 4));
     TRY(c->dalloc(&c->d_its, 4));
     TRY(c->dalloc(&c->d_flags, 4));
+    TRY(c->dalloc(&c->tf_dev, 4 * lp_ctx::RING));
+    {
+        // slot k's first level: the smallest m >= 1 with m = k mod RING
+        std::vector<long long> lv(lp_ctx::RING);
+        for (int k = 0; k < lp_ctx::RING; ++k) lv[k] = k == 0 ? lp_ctx::RING : k;
+        TRY(c->upload(&c->level_dev, lv, st));
+    }
     TRY(c->dalloc(&c->d_irmax, 1));
     TRY(c->dalloc(&c->d_irrel, 1));
     HIPCHK(hipMemsetAsync(c->d_flags, 0, 4 * sizeof(int), st));
@@ -980,7 +1188,7 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
         else if (hipMalloc(&p, P.band_total_por * tb + 256) != hipSuccess) p = nullptr;
         if (!p) return fail(LP_ERR_ALLOC, "porous band allocation failed");
         c->owned.push_back(p); c->band_por = p;
-        for (int l = 0; l < (c->krylov ? 0 : 2); ++l) {
+        for (int l = 0; l < (c->have_dense ? 2 : 0); ++l) {
             if (c->has_alloc) { p = c->alloc.alloc(P.band_total_ose * tb + 256, c->alloc.user); }
             else if (hipMalloc(&p, P.band_total_ose * tb + 256) != hipSuccess) p = nullptr;
             if (!p) return fail(LP_ERR_ALLOC, "conduit band allocation failed");
@@ -991,7 +1199,7 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
         if (!p) return fail(LP_ERR_ALLOC, "porous factor allocation failed");
         c->owned.push_back(p); c->fac_por = p;
         HIPCHK(hipMemsetAsync(p, 0, fl_por.total * tb, st));
-        for (int l = 0; l < (c->krylov ? 0 : lp_ctx::FSLOTS); ++l) {
+        for (int l = 0; l < (c->have_dense ? lp_ctx::FSLOTS : 0); ++l) {
             if (c->has_alloc) { p = c->alloc.alloc(fl_ose.total * tb + 256, c->alloc.user); }
             else if (hipMalloc(&p, fl_ose.total * tb + 256) != hipSuccess) p = nullptr;
             if (!p) return fail(LP_ERR_ALLOC, "conduit factor allocation failed");
@@ -1055,6 +1263,10 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     c->ecur = 0;
     HIPCHK(hipStreamCreateWithFlags(&c->cstream, hipStreamNonBlocking));
     if (const char *v = std::getenv("LP_SERIAL")) c->serial = std::atoi(v) != 0;
+    c->graphs = opt->graphs != 0;
+    if (c->graphs) {
+        HIPCHK(hipStreamCreateWithFlags(&c->lstream, hipStreamNonBlocking));
+    }
     if (c->serial) {
         // diagnostic: every stage on one internal stream, in program order
         c->fstream[0] = c->fstream[1] = c->cstream;
@@ -1089,7 +1301,7 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
         HIPCHK(hipMemsetAsync(c->band_por, 0, P.band_total_por * sizeof(double), st));
         TRY(factor_porous<double>(c.get(), (double *)c->band_por, (double *)c->fac_por, st));
     }
-    if (c->krylov) {
+    if (c->have_strips) {
         if (c->mixed) TRY(setup_strips<float>(c.get(), st));
         else TRY(setup_strips<double>(c.get(), st));
     }
@@ -1119,6 +1331,10 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     int flags = 0;
     HIPCHK(hipMemcpy(&flags, c->d_flags, sizeof(int), hipMemcpyDeviceToHost));
     if (flags & 4) return fail(LP_ERR_NOCONV, "zero or non-finite pivot while factoring the porous matrices");
+    if (opt->autotune) {
+        if (c->mixed) TRY(autotune<float>(c.get(), st));
+        else TRY(autotune<double>(c.get(), st));
+    }
     *out = c.release();
     return LP_OK;
 }
@@ -1151,8 +1367,6 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
     }
     StageTimer ttot(c, LP_T_COARSE, st);
     const long long nc2 = c->nc2;
-    const double t1 = time_at(c, c->n + 1);
-    const double tf[3] = {std::cos(t1), std::sin(t1), std::cos(t1) * std::cos(t1)};
     // (5.1)-(5.3): three SPD solves with lagged exchange and lagged u^n on Gamma
     lp::PorousArgs pa{};
     pa.sys = c->d_cpor; pa.cls2 = c->d_cls2; pa.dof2 = c->d_dof2;
@@ -1164,73 +1378,80 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
     }
     pa.Uy0 = c->cU[o] + nc2;
     pa.e_old = c->cP[o]; pa.e_new = c->cP[nw]; pa.b = c->b_cp;
-    for (int k = 0; k < 3; ++k) pa.tf[k] = tf[k];
-    lp::launch_porous_rhs(pa, 1, c->nodes_cpor, 8, ps);
-    {
+    pa.tf = c->tf_slot(nw);
+    c->seg_m = m;
+    TRY(seg(c, gkey(G_CPOR, m), ps, [&](hipStream_t s) -> lp_status {
+        // the level's time factors on the device (its ring slot's counter)
+        lp::launch_time_level(c->level_dev + nw, lp_ctx::RING, c->prm.dt, c->tf_slot(nw), s);
+        lp::launch_porous_rhs(pa, 1, c->nodes_cpor, 8, s);
         // the three solves with the explicit inverses, then the node layout
         lp::DensePorousArgs dp{};
         dp.d = lp::DenseArgs{c->inv_cp, c->b_cp, c->x_cp, P.cpor.ndof, nullptr};
         dp.f = lp::FinalizeArgs{c->d_cpor, c->d_dof2, c->d_dof1, c->x_cp, c->cP[nw], nullptr, nullptr};
         dp.ticket = c->tick_dp;
-        lp::launch_dense_porous(dp, 3, ps);
-    }
+        lp::launch_dense_porous(dp, 3, s);
+        return LP_OK;
+    }));
     HIPCHK(hipEventRecord(c->ev_cpor[nw], ps));
     // (5.4): Navier-Stokes by Newton from the extrapolation 2 (u^n, p^n) -
     // (u^(n-1), p^(n-1)) (from (u^n, p^n) at the first step); each iteration
     // solves the Oseen system linearised about the current iterate
-    {
-        const int om = (int)((m + lp_ctx::RING - 2) % lp_ctx::RING), omm = (int)((m + lp_ctx::RING - 3) % lp_ctx::RING);
-        const bool ex = m >= 2, ex2 = m >= 3;
-        lp::NewtonStartArgs ns{c->cU[o], c->cp[o], ex ? c->cU[om] : nullptr, ex ? c->cp[om] : nullptr,
-                               ex2 ? c->cU[omm] : nullptr, ex2 ? c->cp[omm] : nullptr,
-                               c->cU[nw], c->cp[nw], 2 * nc2, c->nc1, c->d_done, c->d_its, nullptr, 0, c->d_flags};
-        lp::launch_newton_start(ns, st);
-    }
     // the Jacobian of a refresh step stays in use (its explicit inverse) until
     // the next refresh
     const int jev = c->opt.jacobian_every > 1 ? c->opt.jacobian_every : 1;
     const bool refresh = (m - 1) % jev == 0;
-    for (int it = 0; it < c->opt.max_newton; ++it) {
-        lp::OseenArgs oa{};
-        oa.sys = c->d_cns; oa.cls2 = c->d_cls2; oa.dof2 = c->d_dof2; oa.cls1 = c->d_cls1; oa.dof1 = c->d_dof1;
-        oa.W1[0] = c->cU[nw]; oa.W1[1] = c->cU[nw] + nc2;
-        oa.W0[0] = c->cU[o]; oa.W0[1] = c->cU[o] + nc2;
-        oa.Pp = c->cp[nw];
-        oa.ex[0] = c->ex_c[3]; oa.ex[1] = c->ex_c[4];
-        for (int cc = 0; cc < 2; ++cc) for (int k = 0; k < 3; ++k) oa.load[cc][k] = c->ld_c[3 + cc][k];
-        oa.PF0 = c->cP[o];
-        oa.e_old = nullptr; oa.e_new = c->nwt_e; oa.e_new1 = c->nwt_e1;
-        oa.b = c->b_cn;
-        for (int k = 0; k < 3; ++k) oa.tf[k] = tf[k];
-        oa.skip = c->d_done;
-        lp::launch_oseen_rhs(oa, 1, c->nodes_cns, 8, st);
-        if (it == 0 && refresh) {
-            // Jacobian at the first iterate; later iterations (and steps, up to
-            // the next refresh) reuse its inverse, with residuals of the
-            // current iterate (chord steps)
-            lp::OseenApplyArgs<double> aa{};
-            aa.sys = c->d_cns; aa.cls2 = c->d_cls2; aa.dof2 = c->d_dof2; aa.dof1 = c->d_dof1;
-            aa.W1[0] = oa.W1[0]; aa.W1[1] = oa.W1[1]; aa.band = c->band_cns; aa.skip = c->d_done;
-            lp::launch_oseen_rows<double>(aa, 1, c->nodes_cns, P.cns.bw, st);
-            lp::BandArgs<double> ba{c->d_lu_cns, c->band_cns, c->fac_cns, c->d_flags, c->d_done, c->lu_dummy + c->lu_dummy_coarse_off,
-                                    (const double *)c->consts, c->const_one<double>()};
-            if (!lp::launch_band_lu<double>(ba, 1, P.cns.bw, c->lu_variant_cns, st)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
-            // explicit inverse of the Jacobian: each chord step is then one
-            // dense product instead of a serial band solve
-            const int n = P.cns.ndof;
-            lp::SolveArgs<double> sa{c->d_iv_cns, c->fac_cns, c->eye_cn, c->inv_cn, nullptr, n, c->d_done,
-                                     (const double *)c->consts, c->const_one<double>(), (const double *)c->consts, 1};
-            if (!lp::launch_band_solve<double>(sa, 1, n, P.cns.bw, n, c->solve_depth, st)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
+    TRY(seg(c, gkey(refresh ? G_CNS_REFRESH : G_CNS, m), st, [&](hipStream_t s) -> lp_status {
+        {
+            const int om = (int)((m + lp_ctx::RING - 2) % lp_ctx::RING), omm = (int)((m + lp_ctx::RING - 3) % lp_ctx::RING);
+            const bool ex = m >= 2, ex2 = m >= 3;
+            lp::NewtonStartArgs ns{c->cU[o], c->cp[o], ex ? c->cU[om] : nullptr, ex ? c->cp[om] : nullptr,
+                                   ex2 ? c->cU[omm] : nullptr, ex2 ? c->cp[omm] : nullptr,
+                                   c->cU[nw], c->cp[nw], 2 * nc2, c->nc1, c->d_done, c->d_its, nullptr, 0, c->d_flags};
+            lp::launch_newton_start(ns, s);
         }
-        // chord step: x = J^-1 b, the correction to the node layout and the
-        // update with its convergence test, in one launch
-        lp::DenseNewtonArgs dn{};
-        dn.d = lp::DenseArgs{c->inv_cn, c->b_cn, c->x_cn, P.cns.ndof, c->d_done};
-        dn.f = lp::FinalizeArgs{c->d_cns, c->d_dof2, c->d_dof1, c->x_cn, c->nwt_e, c->nwt_e1, c->d_done};
-        dn.u = lp::NewtonArgs{c->cU[nw], c->cp[nw], c->nwt_e, c->nwt_e1, nc2, c->nc1, c->d_done, c->d_its, c->opt.newton_tol};
-        dn.ticket = c->tick_dn;
-        lp::launch_dense_newton(dn, st);
-    }
+        for (int it = 0; it < c->opt.max_newton; ++it) {
+            lp::OseenArgs oa{};
+            oa.sys = c->d_cns; oa.cls2 = c->d_cls2; oa.dof2 = c->d_dof2; oa.cls1 = c->d_cls1; oa.dof1 = c->d_dof1;
+            oa.W1[0] = c->cU[nw]; oa.W1[1] = c->cU[nw] + nc2;
+            oa.W0[0] = c->cU[o]; oa.W0[1] = c->cU[o] + nc2;
+            oa.Pp = c->cp[nw];
+            oa.ex[0] = c->ex_c[3]; oa.ex[1] = c->ex_c[4];
+            for (int cc = 0; cc < 2; ++cc) for (int k = 0; k < 3; ++k) oa.load[cc][k] = c->ld_c[3 + cc][k];
+            oa.PF0 = c->cP[o];
+            oa.e_old = nullptr; oa.e_new = c->nwt_e; oa.e_new1 = c->nwt_e1;
+            oa.b = c->b_cn;
+            oa.tf = c->tf_slot(nw);
+            oa.skip = c->d_done;
+            lp::launch_oseen_rhs(oa, 1, c->nodes_cns, 8, s);
+            if (it == 0 && refresh) {
+                // Jacobian at the first iterate; later iterations (and steps, up to
+                // the next refresh) reuse its inverse, with residuals of the
+                // current iterate (chord steps)
+                lp::OseenApplyArgs<double> aa{};
+                aa.sys = c->d_cns; aa.cls2 = c->d_cls2; aa.dof2 = c->d_dof2; aa.dof1 = c->d_dof1;
+                aa.W1[0] = oa.W1[0]; aa.W1[1] = oa.W1[1]; aa.band = c->band_cns; aa.skip = c->d_done;
+                lp::launch_oseen_rows<double>(aa, 1, c->nodes_cns, P.cns.bw, s);
+                lp::BandArgs<double> ba{c->d_lu_cns, c->band_cns, c->fac_cns, c->d_flags, c->d_done, c->lu_dummy + c->lu_dummy_coarse_off,
+                                        (const double *)c->consts, c->const_one<double>()};
+                if (!lp::launch_band_lu<double>(ba, 1, P.cns.bw, c->lu_variant_cns, s)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
+                // explicit inverse of the Jacobian: each chord step is then one
+                // dense product instead of a serial band solve
+                const int n = P.cns.ndof;
+                lp::SolveArgs<double> sa{c->d_iv_cns, c->fac_cns, c->eye_cn, c->inv_cn, nullptr, n, c->d_done,
+                                         (const double *)c->consts, c->const_one<double>(), (const double *)c->consts, 1};
+                if (!lp::launch_band_solve<double>(sa, 1, n, P.cns.bw, n, c->solve_depth, s)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
+            }
+            // chord step: x = J^-1 b, the correction to the node layout and the
+            // update with its convergence test, in one launch
+            lp::DenseNewtonArgs dn{};
+            dn.d = lp::DenseArgs{c->inv_cn, c->b_cn, c->x_cn, P.cns.ndof, c->d_done};
+            dn.f = lp::FinalizeArgs{c->d_cns, c->d_dof2, c->d_dof1, c->x_cn, c->nwt_e, c->nwt_e1, c->d_done};
+            dn.u = lp::NewtonArgs{c->cU[nw], c->cp[nw], c->nwt_e, c->nwt_e1, nc2, c->nc1, c->d_done, c->d_its, c->opt.newton_tol};
+            dn.ticket = c->tick_dn;
+            lp::launch_dense_newton(dn, s);
+        }
+        return LP_OK;
+    }));
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(c->ev_coarse[nw], st));
     if (c->mixed) TRY(factor_oseen<float>(c, m));
@@ -1254,6 +1475,8 @@ lp_status local_step_impl(lp_ctx *c, void *stream, const LocalScratch &ls, bool 
     if (c->serial) st = c->cstream;
     const int64_t m = c->n + 1;
     const int o = (int)((m - 1) % lp_ctx::RING), nw = (int)(m % lp_ctx::RING);
+    c->seg_m = m;
+    c->key_off = clear ? G_NOALLOC : 0;
     {
         StageTimer tm(c, LP_T_WAIT_COARSE, st);
         HIPCHK(hipStreamWaitEvent(st, c->ev_coarse[nw], 0));
@@ -1274,13 +1497,14 @@ lp_status local_step_impl(lp_ctx *c, void *stream, const LocalScratch &ls, bool 
     HIPCHK(hipStreamWaitEvent(ps, c->ev_cpor[nw], 0));
     if (m >= 2) HIPCHK(hipStreamWaitEvent(ps, c->ev_por, 0));
     if (m >= 3) HIPCHK(hipStreamWaitEvent(ps, c->ev_local[(m - 2) % lp_ctx::RING], 0));
-    prolong_porous(c, pro, nw, o, ps);
-    if (clear) {
-        lp::launch_zero_ints(ls.tick_por, 3 * (long long)c->P.por.size(), ps);
-        lp::launch_zero_ints(ls.tick_ose, (long long)c->P.ose.size(), st);
-    }
-    if (c->mixed) { TRY(local_porous<float>(c, pro, ps, ls)); TRY(local_oseen<float>(c, st, ls)); }
-    else { TRY(local_porous<double>(c, pro, ps, ls)); TRY(local_oseen<double>(c, st, ls)); }
+    TRY(seg(c, gkey(G_POROUS, m) + c->key_off, ps, [&](hipStream_t s) -> lp_status {
+        prolong_porous(c, pro, nw, o, s);
+        if (clear) lp::launch_zero_ints(ls.tick_por, 3 * (long long)c->P.por.size(), s);
+        return c->mixed ? local_porous<float>(c, pro, s, ls) : local_porous<double>(c, pro, s, ls);
+    }));
+    if (clear) lp::launch_zero_ints(ls.tick_ose, (long long)c->P.ose.size(), st);
+    if (c->mixed) TRY(local_oseen<float>(c, st, ls));
+    else TRY(local_oseen<double>(c, st, ls));
     HIPCHK(hipEventRecord(c->ev_por, ps));
     {
         StageTimer tm(c, LP_T_WAIT_POR, st);
@@ -1308,7 +1532,10 @@ lp_status local_step_impl(lp_ctx *c, void *stream, const LocalScratch &ls, bool 
         }
         ma.e2 = c->e2[en]; ma.e1 = c->e1[en];
     }
-    lp::launch_merge(mr[lp::POROUS], mr[lp::CONDUIT], st);
+    TRY(seg(c, gkey(G_MERGE, m), st, [&](hipStream_t s) -> lp_status {
+        lp::launch_merge(mr[lp::POROUS], mr[lp::CONDUIT], s);
+        return LP_OK;
+    }));
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(c->ev_local[m % lp_ctx::RING], st));
     if (st != st_user) HIPCHK(hipStreamWaitEvent(st_user, c->ev_local[m % lp_ctx::RING], 0));
@@ -1439,8 +1666,20 @@ lp_status lp_get_stats(lp_ctx *c, lp_stats *out) {
     for (size_t i = 0; i < sw.size(); ++i) {
         out->ir_sweeps = std::max(out->ir_sweeps, sw[i]);
         out->ir_relres = std::max(out->ir_relres, rel[i]);
+        if (i < np) {
+            out->ir_sweeps_porous = std::max(out->ir_sweeps_porous, sw[i]);
+            out->ir_relres_porous = std::max(out->ir_relres_porous, rel[i]);
+        } else {
+            out->ir_sweeps_oseen = std::max(out->ir_sweeps_oseen, sw[i]);
+            out->ir_relres_oseen = std::max(out->ir_relres_oseen, rel[i]);
+        }
     }
     out->solver = c->krylov ? LP_KRYLOV : LP_DENSE;
+    out->tuned = c->tuned ? 1 : 0;
+    out->lu_variant = c->lu_variant_ose;
+    out->solve_depth = c->solve_depth;
+    out->tune_dense_ms = c->tune_dense_ms;
+    out->tune_krylov_ms = c->tune_krylov_ms;
     if (c->krylov) {
         std::vector<int> tot(no);
         HIPCHK(hipMemcpy(tot.data(), c->gm_tot, no * sizeof(int), hipMemcpyDeviceToHost));

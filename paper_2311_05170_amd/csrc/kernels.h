@@ -34,7 +34,7 @@ struct PorousArgs {
     const double *e_old;          // previous corrections (local lattices)
     double *e_new;
     double *b;
-    double tf[3];                 // cos t_{n+1}, sin t_{n+1}, cos^2 t_{n+1}
+    const double *tf;             // device: cos t_{n+1}, sin t_{n+1}, cos^2 t_{n+1}
     IrStart ir;                   // three flags per system
 };
 
@@ -103,7 +103,7 @@ struct OseenArgs {
     double *e_new;
     double *e_new1;
     double *b;
-    double tf[3];
+    const double *tf;             // device: cos t_{n+1}, sin t_{n+1}, cos^2 t_{n+1}
     const int *skip;
     IrStart ir;                   // one flag per system
 };
@@ -275,6 +275,7 @@ struct GmresArgs {
     double tol;                   // stop when |g_{k+1}| <= tol ||b||
     const int *conv;              // systems already converged (skipped), or null
     int *tot;                     // Arnoldi steps per system over the cycles of a local step
+    int reorth;                   // 1: classical Gram-Schmidt with a second pass
 };
 
 // Restricted additive Schwarz over strips: strip vectors rs (right-hand
@@ -298,6 +299,7 @@ void launch_gm_update(const GmresArgs &a, int nsys, double *x, hipStream_t st);
 void launch_strip_gather(const StripArgs &a, int nstrip, const double *v, hipStream_t st);
 void launch_strip_scatter(const StripArgs &a, int nstrip, double *z, hipStream_t st);
 size_t gm_arnoldi_lds(int maxn);
+void launch_fill_pattern(double *x, long long n, hipStream_t st);
 
 hipError_t upload_constants(const RefData &r, const Coef &c, hipStream_t st);
 void launch_prolong_p2(const ProlongArgs &a, hipStream_t st);
@@ -341,7 +343,14 @@ void launch_newton_update(const NewtonArgs &a, hipStream_t st);
 void launch_dense_newton(const DenseNewtonArgs &a, hipStream_t st);
 void launch_dense_porous(const DensePorousArgs &a, int nsys, hipStream_t st);
 void launch_newton_start(const NewtonStartArgs &a, hipStream_t st);
+// The time level of a step on the device: m = *level, then *level = m + stride,
+// t = m dt (a product, never accumulated) and tf = (cos t, sin t, cos^2 t).
+// Each ring slot has its own counter, advanced by the ring's size, so every
+// replay of a step's launches reads the time of its own level.
+void launch_time_level(long long *level, long long stride, double dt, double *tf, hipStream_t st);
 // p[0..n) = 0 by a small kernel (capturable in a graph, unlike a memset node)
 void launch_zero_ints(int *p, long long n, hipStream_t st);
+// bytes of p (a 16-byte aligned device buffer) set to zero by a kernel
+void launch_zero_fill(void *p, size_t bytes, hipStream_t st);
 
 }  // namespace lp

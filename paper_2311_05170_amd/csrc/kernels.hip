@@ -2194,8 +2194,9 @@ __global__ __launch_bounds__(64 * (TT + LU_NS)) void k_band_lu_la(BandArgs<T> B)
 // zero, so the last block and the prefetch run straight through.
 // ---------------------------------------------------------------------------
 // LDS pad (rows) on each side of the right-hand side: a window and a
-// super-block of blocks beyond the end (rows read past n are zero)
-constexpr int SOLVE_PAD = 3 * 256 + 64;
+// super-block of blocks beyond the end (rows read past n are zero), for NR
+// window registers per lane
+constexpr int solve_pad(int nr) { return 128 * nr + 64; }
 // rows per lane in flight when moving the right-hand side and the solution
 constexpr int SOLVE_LD = 8;
 
@@ -2229,7 +2230,7 @@ __device__ __forceinline__ void col_load(__amdgpu_buffer_rsrc_t rs, int voff, in
 }
 
 template <typename T, int NR, int D, bool REV>
-__device__ __forceinline__ void band_pass(const T *C, int n, int ldf, T *ys, const T *dl, int lane) {
+__device__ __forceinline__ void band_pass(const T *C, int n, int ldf, T *ys, int lane) {
     constexpr int H = 2 * NR, R = 64 * NR;
     // column k sits in ring slot k mod D, static within the unrolled super-block
     static_assert((32 * H) % D == 0, "prefetch ring divides a super-block");
@@ -2281,7 +2282,7 @@ __device__ __forceinline__ void band_pass(const T *C, int n, int ldf, T *ys, con
             }
             const bool mine = (lane & 32) == lh;
             const int r = 32 * b + (lane & 31);
-            if (mine) yat(r) = REV ? win[mh] : win[mh] * dl[r];  // first pass: z = D^-1 y
+            if (mine) yat(r) = win[mh];
             win[mh] = mine ? ent : win[mh];
         }
     }
@@ -2291,7 +2292,8 @@ __device__ __forceinline__ void band_pass(const T *C, int n, int ldf, T *ys, con
 constexpr int SOLVE_THREADS = 64;
 template <typename T, int NR, int D>
 __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(SolveArgs<T> A) {
-    static_assert(64 * NR + 32 * 2 * NR <= SOLVE_PAD, "pad too small");
+    constexpr int PAD = solve_pad(NR);
+    static_assert(64 * NR + 32 * 2 * NR <= PAD, "pad too small");
     // one wavefront whose speed is its instruction issue: it owns its SIMD
     own_simd<SOLVE_THREADS>();
     const int sysi = blockIdx.x, f = blockIdx.y;
@@ -2302,37 +2304,42 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(SolveArgs<T> A) {
     if (A.conv && A.conv[id]) return;
     extern __shared__ unsigned char smem_raw[];
     const int n = Sy.n;
-    T *ys = reinterpret_cast<T *>(smem_raw) + SOLVE_PAD;   // r, then z, then d, by row
-    T *dl = ys + n + SOLVE_PAD;                             // 1 / U(i, i), zero past n
+    T *ys = reinterpret_cast<T *>(smem_raw) + PAD;          // r, then z, then d, by row
     const int ldf = Sy.ldf;
     const T *Lr = A.fac + Sy.foff + (long long)f * Sy.fstride;
     const T *Ur = Lr + (long long)n * ldf, *Di = Ur + (long long)n * ldf;
     const double *rg = A.r + Sy.vec + (long long)f * n;
     double *x = A.x + Sy.vec + (long long)f * n;
     const int lane = threadIdx.x;
-    // the right-hand side and the pivot reciprocals into LDS, SOLVE_LD rows
-    // per lane in flight (clamped unconditional loads, then masked stores)
-    for (int i0 = lane - SOLVE_PAD; i0 < n + SOLVE_PAD; i0 += 64 * SOLVE_LD) {
+    // the right-hand side into LDS, SOLVE_LD rows per lane in flight (clamped
+    // unconditional loads, then masked stores; the pads are zero)
+    for (int i0 = lane - PAD; i0 < n + PAD; i0 += 64 * SOLVE_LD) {
         double v[SOLVE_LD];
-        T dv[SOLVE_LD];
 #pragma unroll
-        for (int u = 0; u < SOLVE_LD; ++u) {
-            const int ic = min(max(i0 + 64 * u, 0), n - 1);
-            v[u] = rg[ic];
-            dv[u] = Di[ic];
-        }
+        for (int u = 0; u < SOLVE_LD; ++u) v[u] = rg[min(max(i0 + 64 * u, 0), n - 1)];
 #pragma unroll
         for (int u = 0; u < SOLVE_LD; ++u) {
             const int i = i0 + 64 * u;
-            const bool in = i >= 0 && i < n;
-            if (i < n + SOLVE_PAD) ys[i] = in ? (T)v[u] : T(0);
-            if (i >= 0 && i < n + SOLVE_PAD) dl[i] = in ? dv[u] : T(0);
+            if (i < n + PAD) ys[i] = (i >= 0 && i < n) ? (T)v[u] : T(0);
         }
     }
     __syncthreads();
-    band_pass<T, NR, D, false>(Lr, n, ldf, ys, dl, lane);
+    band_pass<T, NR, D, false>(Lr, n, ldf, ys, lane);
     __syncthreads();
-    band_pass<T, NR, D, true>(Ur, n, ldf, ys, dl, lane);
+    // z = D^-1 y between the passes (pivot reciprocals read from the factors,
+    // so the LDS holds one vector only)
+    for (int i0 = lane; i0 < n; i0 += 64 * SOLVE_LD) {
+        T dv[SOLVE_LD];
+#pragma unroll
+        for (int u = 0; u < SOLVE_LD; ++u) dv[u] = Di[min(i0 + 64 * u, n - 1)];
+#pragma unroll
+        for (int u = 0; u < SOLVE_LD; ++u) {
+            const int i = i0 + 64 * u;
+            if (i < n) ys[i] = ys[i] * dv[u];
+        }
+    }
+    __syncthreads();
+    band_pass<T, NR, D, true>(Ur, n, ldf, ys, lane);
     __syncthreads();
     if (A.assign) {
         for (int i = lane; i < n; i += 64) x[i] = (double)ys[i];
@@ -2647,7 +2654,7 @@ bool launch_band_lu(const BandArgs<T> &a, int nsys, int maxbw, int variant, hipS
 template <typename T, int D>
 bool launch_band_solve_d(const SolveArgs<T> &a, int nsys, int nrhs, int maxbw, int maxn, hipStream_t st) {
     dim3 g(nsys, nrhs);
-    const size_t sh = (size_t)(2 * maxn + 3 * SOLVE_PAD) * sizeof(T);
+    const size_t sh = (size_t)(maxn + 2 * solve_pad(solve_nr(maxbw))) * sizeof(T);
     if (sh > 160 * 1024) return false;
     switch (solve_nr(maxbw)) {
     case 2: hipLaunchKernelGGL((k_band_solve<T, 2, D>), g, dim3(SOLVE_THREADS), sh, st, a); break;
@@ -2693,6 +2700,18 @@ void launch_newton_start(const NewtonStartArgs &a, hipStream_t st) {
     const int nb = (int)std::min<long long>(1024, (work + 255) / 256);
     hipLaunchKernelGGL(k_newton_start, dim3(nb > 0 ? nb : 1), dim3(256), 0, st, a);
 }
+__global__ void k_time_level(long long *level, long long stride, double dt, double *tf) {
+    const long long m = *level;
+    *level = m + stride;
+    const double t = (double)m * dt;
+    const double c = cos(t);
+    tf[0] = c;
+    tf[1] = sin(t);
+    tf[2] = c * c;
+}
+void launch_time_level(long long *level, long long stride, double dt, double *tf, hipStream_t st) {
+    hipLaunchKernelGGL(k_time_level, dim3(1), dim3(1), 0, st, level, stride, dt, tf);
+}
 __global__ void k_zero_ints(int *p, long long n) {
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) p[i] = 0;
 }
@@ -2700,6 +2719,18 @@ void launch_zero_ints(int *p, long long n, hipStream_t st) {
     if (n <= 0) return;
     const int nb = (int)std::min<long long>(256, (n + 255) / 256);
     hipLaunchKernelGGL(k_zero_ints, dim3(nb), dim3(256), 0, st, p, n);
+}
+__global__ void k_zero_fill(uint4 *p, long long n16, unsigned char *tail, int ntail) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n16; i += stride) p[i] = make_uint4(0, 0, 0, 0);
+    if (blockIdx.x == 0 && (int)threadIdx.x < ntail) tail[threadIdx.x] = 0;
+}
+void launch_zero_fill(void *p, size_t bytes, hipStream_t st) {
+    if (bytes == 0) return;
+    const long long n16 = (long long)(bytes / 16);
+    const int ntail = (int)(bytes % 16);
+    const int nb = (int)std::min<long long>(2048, std::max<long long>(1, (n16 + 255) / 256));
+    hipLaunchKernelGGL(k_zero_fill, dim3(nb), dim3(256), 0, st, (uint4 *)p, n16, (unsigned char *)p + n16 * 16, ntail);
 }
 void launch_newton_update(const NewtonArgs &a, hipStream_t st) {
     hipLaunchKernelGGL(k_newton_update, dim3(1), dim3(256), 0, st, a);

@@ -10,6 +10,8 @@
 // of launches serves systems that converge after different iteration counts.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace lp {
@@ -101,6 +103,29 @@ __global__ __launch_bounds__(GT) void k_gm_arnoldi(GmresArgs G, int k, const dou
         wl[i] = a;
         nn += a * a;
     }
+    if (G.reorth) {
+        // a second Gram-Schmidt pass against the same basis (its coefficients
+        // added to the Hessenberg column)
+        __shared__ double h2[GM_MAX + 1];
+        for (int j = 0; j <= k; ++j) {
+            const double *vj = G.V + j * nt + off;
+            double p = 0.0;
+            for (int i = threadIdx.x; i < n; i += GT) p += wl[i] * vj[i];
+            p = block_sum(p, red);
+            if (threadIdx.x == 0) h2[j] = p;
+        }
+        __syncthreads();
+        nn = 0.0;
+        for (int i = threadIdx.x; i < n; i += GT) {
+            double a = wl[i];
+            for (int j = 0; j <= k; ++j) a -= h2[j] * G.V[j * nt + off + i];
+            wl[i] = a;
+            nn += a * a;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int j = 0; j <= k; ++j) hcol[j] += h2[j];
+    }
     const double nrm = sqrt(block_sum(nn, red));
     const double sc = nrm > 0.0 ? 1.0 / nrm : 0.0;
     double *vk1 = G.V + (k + 1) * nt + off;
@@ -186,7 +211,18 @@ __global__ __launch_bounds__(256) void k_strip_scatter(StripArgs A, double *z) {
         if (A.sown[S.dof_off + i]) z[po + A.smap[S.dof_off + i]] = A.zs[S.dof_off + i];
 }
 
+// a smooth fixed vector (autotuning right-hand sides): x_i = sin(0.37 i) + 0.5
+__global__ void k_fill_pattern(double *x, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        x[i] = sin(0.37 * (double)i) + 0.5;
+}
+
 size_t gm_arnoldi_lds(int maxn) { return (size_t)maxn * sizeof(double); }
+
+void launch_fill_pattern(double *x, long long n, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill_pattern, dim3((unsigned)std::min<long long>(1024, (n + 255) / 256)), dim3(256), 0, st, x, n);
+}
 
 bool launch_gm_init(const GmresArgs &a, int nsys, const double *r, const double *b, bool first, hipStream_t st) {
     hipLaunchKernelGGL(k_gm_init, dim3(nsys), dim3(GT), 0, st, a, r, b, first ? 1 : 0);

@@ -60,7 +60,7 @@ class LpOptions(Structure):
                 ("max_ir", c_int32), ("ir_tol", c_double), ("max_newton", c_int32),
                 ("newton_tol", c_double), ("jacobian_every", c_int32), ("solver", c_int32),
                 ("coarse_ns", c_int32), ("krylov_tol", c_double), ("max_iter", c_int32),
-                ("nsamples", c_int32)]
+                ("nsamples", c_int32), ("autotune", c_int32), ("graphs", c_int32)]
 
 
 ALLOC_FN = CFUNCTYPE(c_void_p, c_size_t, c_void_p)
@@ -76,7 +76,10 @@ class LpStats(Structure):
                 ("local_dofs", c_int64), ("max_bw", c_int64), ("newton_its", c_int32),
                 ("ir_sweeps", c_int32), ("ir_relres", c_double), ("flags", c_int32),
                 ("newton_its_max", c_int32), ("ir_sweeps_max", c_int32), ("ir_relres_max", c_double),
-                ("solver", c_int32), ("krylov_its", c_int32)]
+                ("solver", c_int32), ("tuned", c_int32), ("lu_variant", c_int32), ("solve_depth", c_int32),
+                ("tune_dense_ms", c_double), ("tune_krylov_ms", c_double), ("krylov_its", c_int32),
+                ("ir_sweeps_porous", c_int32), ("ir_sweeps_oseen", c_int32), ("ir_relres_porous", c_double),
+                ("ir_relres_oseen", c_double)]
 
 
 class LpError(RuntimeError):
@@ -161,7 +164,7 @@ class LocalParallel:
     def __init__(self, n_coarse, refine, nsub, overlap, prm, dt, cuts=None, precision="mixed",
                  convection=True, max_ir=8, ir_tol=None, max_newton=16, newton_tol=1e-13,
                  jacobian_every=1, solver="auto", coarse_ns="newton", samples=None,
-                 krylov_restart=30, krylov_tol=None, torch_allocator=True):
+                 krylov_restart=30, krylov_tol=None, autotune=False, graphs=False, torch_allocator=True):
         import torch
         self._torch = torch
         if not torch.cuda.is_available():
@@ -178,8 +181,12 @@ class LocalParallel:
         opt.jacobian_every = int(jacobian_every)
         opt.solver = SOLVER[solver]
         opt.coarse_ns = COARSE_NS[coarse_ns]
-        opt.krylov_tol = float(krylov_tol if krylov_tol is not None else opt.ir_tol)
+        # a GMRES cycle stops a decade below the refinement tolerance, so the
+        # true residual test that follows it passes after one cycle
+        opt.krylov_tol = float(krylov_tol if krylov_tol is not None else 0.1 * opt.ir_tol)
         opt.max_iter = int(krylov_restart)
+        opt.autotune = 1 if autotune else 0
+        opt.graphs = 1 if graphs else 0
         plist = [prm] if samples is None else list(samples)
         opt.nsamples = len(plist)
         params = (LpParams * len(plist))(*[_params(q, dt) for q in plist])

@@ -55,6 +55,30 @@ def test_binding_signatures_match_header():
         assert field in dict(lib.LpStats._fields_), field
 
 
+def _struct_fields(name):
+    """Field names of a typedef struct of lp.h, in declaration order."""
+    txt = re.sub(r"/\*.*?\*/", "", open(HDR).read(), flags=re.S)
+    m = re.search(r"typedef struct \{([^{}]*)\}\s*" + name + r"\s*;", txt)
+    assert m, name
+    out = []
+    for decl in m.group(1).split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        for part in decl.split(","):
+            nm = re.sub(r"\[.*?\]", "", part).split()[-1].lstrip("*")
+            out.append(nm)
+    return out
+
+
+@pytest.mark.parametrize("cname,pyname", [("lp_stats", "LpStats"), ("lp_options", "LpOptions"),
+                                          ("lp_params", "LpParams"), ("lp_mesh", "LpMesh")])
+def test_binding_structs_match_header(cname, pyname):
+    """The ctypes mirrors of the header's structs list the same fields in the
+    same order (a field out of place would shift every later one)."""
+    assert [f for f, _ in getattr(lib, pyname)._fields_] == _struct_fields(cname)
+
+
 def _setup_status(opt_kw=None, samples=None, prm_kw=None):
     """Call lp_setup with options that it rejects before touching a device."""
     from ctypes import byref, c_void_p

@@ -271,6 +271,23 @@ def test_cfg3_uneven_batch_matches_stored_oracle(precision):
     assert st["flags"] == 0, st
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_autotuned_run_matches_oracle(precision, monkeypatch):
+    """lp_options.autotune: lp_setup times the band factorisation variants,
+    the solve prefetch depths and (LP_AUTO, both paths set up) one batch of
+    local Oseen solves by the band path and by the Krylov path on the run's
+    own systems, keeps the fastest, and the run still matches the oracle."""
+    monkeypatch.setenv("LP_KRYLOV_STRIP", "6")
+    cfg = W.config("cfg1")
+    g = run_parity(cfg, precision, 3, autotune=True, max_ir=4, keep=True)
+    st = g.stats()
+    g.close()
+    print(st, flush=True)
+    assert st["tuned"] == 1 and st["tune_dense_ms"] > 0 and st["tune_krylov_ms"] > 0, st
+    assert st["lu_variant"] in (0, 8, 9) and st["solve_depth"] in (16, 32, 64), st
+    assert (st["solver"] == 2) == (st["tune_krylov_ms"] < st["tune_dense_ms"]), st
+
+
 def test_refinement_failure_is_sticky_and_reported():
     """A refinement that cannot reach its tolerance (one FP32 sweep against
     1e-14) raises flag bit 0, lp_get_stats returns LP_ERR_NOCONV with the
@@ -473,6 +490,67 @@ def test_pipeline_wraps_its_rings(precision, monkeypatch):
     monkeypatch.setenv("LP_SERIAL", "1")
     g = _gpu(cfg, precision, **kw)
     for _ in range(RING_STEPS):
+        g.step()
+    b = _fields(g)
+    g.close()
+    for f in a:
+        assert np.array_equal(a[f], b[f]), f
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("solver", ["dense", "krylov"])
+def test_graphs_match_serial(precision, solver, monkeypatch):
+    """Graph mode (each step's launch sequences captured and replayed as HIP
+    graphs, the instantiated graphs updated with each step's arguments; eight
+    graphs per sequence in rotation) over 18 steps issued back to back gives
+    bit-identical fields to the serial schedule without graphs, agrees with
+    the oracle after the last step, and a stage-timed step in between (run
+    without graphs) changes nothing."""
+    cfg = W.config("cfg1")
+    kw = dict(jacobian_every=3, max_newton=10, solver=solver, max_ir=4)
+    if solver == "krylov":
+        monkeypatch.setenv("LP_KRYLOV_STRIP", "6")
+    g = _gpu(cfg, precision, graphs=True, **kw)
+    for n in range(RING_STEPS):
+        if n == 9:
+            g.set_timing(["ose_solve"])
+        g.step()
+        if n == 9:
+            g.timing()
+            g.set_timing([])
+    a = _fields(g)
+    o = _oracle_after("cfg1", RING_STEPS)
+    em = compare(o, g, "merged")
+    st = g.stats()
+    g.close()
+    assert max(em.values()) < TOL[precision], em
+    assert st["flags"] == 0, st
+    monkeypatch.setenv("LP_SERIAL", "1")
+    g = _gpu(cfg, precision, **kw)
+    for _ in range(RING_STEPS):
+        g.step()
+    b = _fields(g)
+    g.close()
+    for f in a:
+        assert np.array_equal(a[f], b[f]), f
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_cfg2_graphs_match_serial(precision, monkeypatch):
+    """cfg2 in the timed configuration with graphs: 12 steps bit-identical to
+    the serial schedule."""
+    cfg = W.config("cfg2")
+    kw = dict(max_ir=2, jacobian_every=3, max_newton=10)
+    g = _gpu(cfg, precision, graphs=True, **kw)
+    for _ in range(12):
+        g.step()
+    a = _fields(g)
+    st = g.stats()
+    g.close()
+    assert st["flags"] == 0, st
+    monkeypatch.setenv("LP_SERIAL", "1")
+    g = _gpu(cfg, precision, **kw)
+    for _ in range(12):
         g.step()
     b = _fields(g)
     g.close()
