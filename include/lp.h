@@ -132,6 +132,8 @@ typedef struct {
                                 <= krylov_tol ||b|| (the refinement test on the true residual
                                 follows) */
     int32_t max_iter;        /* GMRES restart length, 1..64 (the Arnoldi steps of one cycle) */
+    int32_t krylov_cycles;   /* GMRES cycles (refinement sweeps) of the Krylov path per local
+                                step, 1..max_ir; 0: max_ir */
     int32_t nsamples;        /* parameter samples advanced together (lp_setup's samples[]);
                                 0 or 1: one sample.  More than one: LP_ERR_UNSUPPORTED */
     int32_t autotune;        /* 1: at the end of lp_setup, time the local Oseen solves on this

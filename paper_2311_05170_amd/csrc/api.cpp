@@ -190,6 +190,7 @@ struct lp_ctx {
     bool krylov = false;
     bool have_dense = false, have_strips = false;  // resources of each local Oseen path
     int gm_m = 0;
+    int krylov_cycles() const { return opt.krylov_cycles > 0 ? opt.krylov_cycles : opt.max_ir; }
     int gm_reorth = 0;             // second Gram-Schmidt pass in the Arnoldi steps (LP_GM_REORTH)
     // setup-time autotuning (lp_options.autotune): measured milliseconds of
     // one local Oseen solve batch by each path, and what was chosen
@@ -592,7 +593,7 @@ lp_status local_oseen(lp_ctx *c, hipStream_t st, const LocalScratch &ls) {
     }
     return seg(c, gkey(G_OSE_SOLVE, c->n + 1) + c->key_off, st, [&](hipStream_t s) -> lp_status {
         if (c->krylov)
-            TRY(refine_oseen_krylov<T>(c, ls.part_ose, ls.tick_ose, oa.W1[0], oa.W1[1], c->opt.max_ir, true, s));
+            TRY(refine_oseen_krylov<T>(c, ls.part_ose, ls.tick_ose, oa.W1[0], oa.W1[1], c->krylov_cycles(), true, s));
         else
             TRY(refine_oseen<T>(c, c->d_ose, nsys, c->nodes_ose, ls.part_ose, ls.tick_ose, c->d_sv_ose, (const T *)c->fac_ose[fs], c->maxbw_ose, c->maxn_ose, oa.W1[0], oa.W1[1], c->b_ose,
                                 c->x_ose, c->r_ose, c->conv_ose, c->rel_ose, c->sw_ose, c->P.dof_total_ose, c->opt.max_ir,
@@ -911,7 +912,7 @@ lp_status autotune(lp_ctx *c, hipStream_t st) {
         for (int rep = 0; rep < 2; ++rep) {
             TRY(reset());
             TRY(time_launches(st, &ms, [&] {
-                return refine_oseen_krylov<T>(c, c->part_ose, c->tick_ose, Wx, Wy, c->opt.max_ir, false, st);
+                return refine_oseen_krylov<T>(c, c->part_ose, c->tick_ose, Wx, Wy, c->krylov_cycles(), false, st);
             }));
         }
         c->tune_krylov_ms = ms;
@@ -1033,6 +1034,8 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     if (opt->precision != LP_FP64 && opt->precision != LP_MIXED) return fail(LP_ERR_ARG, "precision must be LP_FP64 or LP_MIXED");
     if (opt->max_ir < 1 || opt->max_newton < 1 || !(opt->ir_tol > 0) || !(opt->newton_tol > 0) || opt->jacobian_every < 0)
         return fail(LP_ERR_ARG, "max_ir, max_newton >= 1 and positive tolerances required");
+    if (opt->krylov_cycles < 0 || opt->krylov_cycles > opt->max_ir)
+        return fail(LP_ERR_ARG, "krylov_cycles must lie in 0..max_ir");
     hipStream_t st = (hipStream_t)stream;
     std::unique_ptr<lp_ctx> c(new lp_ctx());
     HIPCHK(hipGetDevice(&c->device));

@@ -60,7 +60,7 @@ class LpOptions(Structure):
                 ("max_ir", c_int32), ("ir_tol", c_double), ("max_newton", c_int32),
                 ("newton_tol", c_double), ("jacobian_every", c_int32), ("solver", c_int32),
                 ("coarse_ns", c_int32), ("krylov_tol", c_double), ("max_iter", c_int32),
-                ("nsamples", c_int32), ("autotune", c_int32), ("graphs", c_int32)]
+                ("krylov_cycles", c_int32), ("nsamples", c_int32), ("autotune", c_int32), ("graphs", c_int32)]
 
 
 ALLOC_FN = CFUNCTYPE(c_void_p, c_size_t, c_void_p)
@@ -164,7 +164,8 @@ class LocalParallel:
     def __init__(self, n_coarse, refine, nsub, overlap, prm, dt, cuts=None, precision="mixed",
                  convection=True, max_ir=8, ir_tol=None, max_newton=16, newton_tol=1e-13,
                  jacobian_every=1, solver="auto", coarse_ns="newton", samples=None,
-                 krylov_restart=30, krylov_tol=None, autotune=False, graphs=False, torch_allocator=True):
+                 krylov_restart=30, krylov_tol=None, krylov_cycles=0, autotune=False, graphs=False,
+                 torch_allocator=True):
         import torch
         self._torch = torch
         if not torch.cuda.is_available():
@@ -185,6 +186,7 @@ class LocalParallel:
         # true residual test that follows it passes after one cycle
         opt.krylov_tol = float(krylov_tol if krylov_tol is not None else 0.1 * opt.ir_tol)
         opt.max_iter = int(krylov_restart)
+        opt.krylov_cycles = int(krylov_cycles)
         opt.autotune = 1 if autotune else 0
         opt.graphs = 1 if graphs else 0
         plist = [prm] if samples is None else list(samples)

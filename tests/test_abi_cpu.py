@@ -114,6 +114,7 @@ def test_setup_rejects_bad_options_without_a_device():
     assert _setup_status({"nsamples": 2}, samples=[W.unit_params()] * 2)[0] == 6
     assert _setup_status({"solver": lib.LP_KRYLOV, "max_iter": 65})[0] == 1
     assert _setup_status({"solver": lib.LP_KRYLOV, "krylov_tol": 0.0})[0] == 1
+    assert _setup_status({"krylov_cycles": 5})[0] == 1            # more cycles than refinement sweeps
     assert _setup_status({"coarse_ns": lib.LP_SEMI_IMPLICIT})[0] == 6
 
 
