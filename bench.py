@@ -544,6 +544,13 @@ def main():
                        "mixed_relres_max": mixed["stats"]["ir_relres_max"],
                        "fp64_sweeps_max": fp64["stats"]["ir_sweeps_max"],
                        "fp64_relres_max": fp64["stats"]["ir_relres_max"], "flags": flags,
+                       # band factorisations without pivoting: largest growth
+                       # factor and smallest pivot relative to the largest entry
+                       "lu_monitor": {k: {"growth_local": r["stats"]["lu_growth_local"],
+                                          "pivot_local": r["stats"]["lu_pivot_local"],
+                                          "growth_coarse": r["stats"]["lu_growth_coarse"],
+                                          "pivot_coarse": r["stats"]["lu_pivot_coarse"]}
+                                      for k, r in (("mixed", mixed), ("fp64", fp64))},
                        "newton_its_max": [mixed["stats"]["newton_its_max"], fp64["stats"]["newton_its_max"]],
                        "max_newton": MAX_NEWTON, "jacobian_every": JACOBIAN_EVERY},
         "roofline": {"kernel": LU_KERNEL,

@@ -173,7 +173,10 @@ typedef struct {
     int32_t flags;           /* sticky over the whole run:
                                 bit 0: some local refinement ended above ir_tol;
                                 bit 1: some coarse step ended above newton_tol;
-                                bit 2: zero or non-finite pivot in a factorisation */
+                                bit 2: a factorisation met a zero or non-finite pivot, a
+                                pivot below one rounding unit of the system's largest
+                                entry (|u_kk| <= 2^-23 max|a_ij| in FP32, 2^-52 in FP64)
+                                or a growth factor above 2^16 (FP32) / 2^45 (FP64) */
     int32_t newton_its_max;  /* most Newton iterations of any coarse step so far */
     int32_t ir_sweeps_max;   /* most refinement sweeps of any system in any local step so far */
     double ir_relres_max;    /* largest final relative residual of any system in any local step */
@@ -187,6 +190,12 @@ typedef struct {
                                 system in the last local step, over its cycles */
     int32_t ir_sweeps_porous, ir_sweeps_oseen;   /* ir_sweeps split by system kind */
     double ir_relres_porous, ir_relres_oseen;    /* ir_relres split by system kind */
+    /* Band factorisations without pivoting, run-long, over the local systems
+     * (Step 3) and the coarse ones (Step 1): the largest growth factor
+     * max|u_ij| / max|a_ij| of a system, and the smallest pivot relative to the
+     * largest entry of its system, min|u_kk| / max|a_ij| (1 before any). */
+    double lu_growth_local, lu_pivot_local;
+    double lu_growth_coarse, lu_pivot_coarse;
 } lp_stats;
 
 /* Build meshes, partition, reference data and device buffers; interpolate the
@@ -238,6 +247,22 @@ lp_status lp_get_solution(lp_ctx *ctx, int32_t sample, int32_t field, int32_t le
  * a coarse Newton iteration or a pivot check failed in some step so far; the
  * fields hold the best iterates. */
 lp_status lp_get_stats(lp_ctx *ctx, lp_stats *out);
+
+/* Diagnostic entry for the band kernels of Steps 1 and 3: factor nsys
+ * caller-provided band systems without pivoting and solve one right-hand side
+ * each, with the library's factorisation (variant as for the local systems:
+ * 0 vector units, 8 blocked on MFMA, 9 blocked with lookahead) and band solve.
+ * Host arrays, all FP64: band[nsys * n * (2 bw + 1)], system s's entry (i, j)
+ * at s n (2 bw + 1) + j (2 bw + 1) + i - j + bw; rhs and x[nsys * n].
+ * precision LP_FP64 factors and solves in FP64, LP_MIXED in FP32 (no
+ * refinement: x is the plain FP32 solve).  Outputs: *flags (bit 2 as in
+ * lp_stats), *growth and *pivot_min over the systems (as the lu_* fields of
+ * lp_stats).  Allocates and frees device memory; synchronous.
+ * Errors: LP_ERR_ARG (sizes, precision, variant), LP_ERR_UNSUPPORTED (bw beyond
+ * the kernels' window of 175 for variant 0, 160 for 8 and 9), LP_ERR_DEVICE. */
+lp_status lp_band_factor_solve(int32_t nsys, int32_t n, int32_t bw, const double *band, const double *rhs,
+                               double *x, int32_t precision, int32_t variant, int32_t *flags,
+                               double *growth, double *pivot_min);
 
 /* Host-only partition queries (no device needed), for bit-exact index parity.
  *   which = 0: subdomain table, 9 int64 per subdomain:

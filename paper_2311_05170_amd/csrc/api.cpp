@@ -145,6 +145,9 @@ struct lp_ctx {
     double *cP[RING] = {}, *cU[RING] = {}, *cp[RING] = {};
     double *nwt_e = nullptr, *nwt_e1 = nullptr;
     int *d_done = nullptr, *d_its = nullptr, *d_flags = nullptr;
+    // factorisation monitor, run-long maxima (float bits): growth and
+    // inverse smallest relative pivot of the local systems, then the coarse ones
+    float *d_lustat = nullptr;
     // run-long refinement totals (largest sweep count, largest final relative
     // residual as double bits), folded in by the local finalize kernels
     int *d_irmax = nullptr;
@@ -554,7 +557,8 @@ template <typename T>
 lp_status factor_porous(lp_ctx *c, T *band, T *fac, hipStream_t st) {
     lp::AssembleArgs<T> aa{c->d_por, c->d_dof2, band};
     lp::launch_porous_assemble<T>(aa, (int)c->P.por.size(), st);
-    lp::BandArgs<T> ba{c->d_lu_por, band, fac, c->d_flags, nullptr, (T *)c->lu_dummy, (const T *)c->consts, c->const_one<T>()};
+    lp::BandArgs<T> ba{c->d_lu_por, band, fac, c->d_flags, nullptr, (T *)c->lu_dummy, (const T *)c->consts, c->const_one<T>(),
+                       c->d_lustat};
     if (!lp::launch_band_lu<T>(ba, 3 * (int)c->P.por.size(), c->maxbw_por, c->lu_variant, st))
         return fail(LP_ERR_UNSUPPORTED, "porous bandwidth exceeds the factorisation kernels");
     return LP_OK;
@@ -650,7 +654,7 @@ lp_status factor_oseen(lp_ctx *c, int64_t m) {
         }
         StageTimer tm(c, LP_T_OSE_LU, s);
         lp::BandArgs<T> ba{c->d_lu_ose, band, (T *)c->fac_ose[fs], c->d_flags, nullptr, (T *)c->lu_dummy, (const T *)c->consts,
-                           c->const_one<T>()};
+                           c->const_one<T>(), c->d_lustat};
         if (!lp::launch_band_lu<T>(ba, nsys, c->maxbw_ose, c->lu_variant_ose, s))
             return fail(LP_ERR_UNSUPPORTED, "conduit bandwidth exceeds the factorisation kernels");
         return LP_OK;
@@ -783,7 +787,8 @@ lp_status setup_strips(lp_ctx *c, hipStream_t st) {
     int nodes = 0;
     for (const auto &s : P.strip) nodes = std::max(nodes, s.lw2 * s.lh2);
     lp::launch_oseen_assemble<T>(aa, nstrip, nodes, st);
-    lp::BandArgs<T> ba{c->d_lu_strip, band, fac, c->d_flags, nullptr, (T *)c->lu_dummy, (const T *)c->consts, c->const_one<T>()};
+    lp::BandArgs<T> ba{c->d_lu_strip, band, fac, c->d_flags, nullptr, (T *)c->lu_dummy, (const T *)c->consts, c->const_one<T>(),
+                       c->d_lustat};
     if (!lp::launch_band_lu<T>(ba, nstrip, c->maxbw_strip, c->lu_variant_ose, st))
         return fail(LP_ERR_UNSUPPORTED, "strip bandwidth exceeds the factorisation kernels");
     const long long nt = P.dof_total_ose, m = c->gm_m;
@@ -866,12 +871,15 @@ lp_status autotune(lp_ctx *c, hipStream_t st) {
             aa.sys = c->d_ose; aa.cls2 = c->d_cls2; aa.dof2 = c->d_dof2; aa.dof1 = c->d_dof1;
             aa.W1[0] = Wx; aa.W1[1] = Wy; aa.band = band;
             lp::launch_oseen_assemble<T>(aa, nsys, c->nodes_ose, st);
-            lp::BandArgs<T> ba{c->d_lu_ose, band, fac, c->d_flags, nullptr, (T *)c->lu_dummy, (const T *)c->consts, c->const_one<T>()};
+            lp::BandArgs<T> ba{c->d_lu_ose, band, fac, c->d_flags, nullptr, (T *)c->lu_dummy, (const T *)c->consts, c->const_one<T>(),
+                               c->d_lustat};
             if (!lp::launch_band_lu<T>(ba, nsys, c->maxbw_ose, variant, st)) return fail(LP_ERR_UNSUPPORTED, "factorisation variant");
             return LP_OK;
         };
         double best_lu = 1e30;
         int best_v = c->lu_variant_ose;
+        float lustat[4];
+        HIPCHK(hipMemcpy(lustat, c->d_lustat, sizeof(lustat), hipMemcpyDeviceToHost));
         for (int v : {9, 8, 0}) {
             double ms = 0.0;
             TRY(factor(v));
@@ -887,6 +895,7 @@ lp_status autotune(lp_ctx *c, hipStream_t st) {
             if (ms < best_lu) { best_lu = ms; best_v = v; }
         }
         c->lu_variant_ose = best_v;
+        HIPCHK(hipMemcpy(c->d_lustat, lustat, sizeof(lustat), hipMemcpyHostToDevice));
         TRY(factor(best_v));
         double best_sv = 1e30;
         int best_d = c->solve_depth;
@@ -1155,6 +1164,7 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     TRY(c->dalloc(&c->d_done, 4));
     TRY(c->dalloc(&c->d_its, 4));
     TRY(c->dalloc(&c->d_flags, 4));
+    TRY(c->dalloc(&c->d_lustat, 4));
     TRY(c->dalloc(&c->tf_dev, 4 * lp_ctx::RING));
     {
         // slot k's first level: the smallest m >= 1 with m = k mod RING
@@ -1165,6 +1175,7 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     TRY(c->dalloc(&c->d_irmax, 1));
     TRY(c->dalloc(&c->d_irrel, 1));
     HIPCHK(hipMemsetAsync(c->d_flags, 0, 4 * sizeof(int), st));
+    HIPCHK(hipMemsetAsync(c->d_lustat, 0, 4 * sizeof(float), st));
     HIPCHK(hipMemsetAsync(c->d_irmax, 0, sizeof(int), st));
     HIPCHK(hipMemsetAsync(c->d_irrel, 0, sizeof(unsigned long long), st));
     HIPCHK(hipMemsetAsync(c->d_its, 0, 4 * sizeof(int), st));
@@ -1313,7 +1324,7 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
         lp::AssembleArgs<double> aa{c->d_cpor, c->d_dof2, c->band_cpor};
         lp::launch_porous_assemble<double>(aa, 1, st);
         lp::BandArgs<double> ba{c->d_lu_cpor, c->band_cpor, c->fac_cpor, c->d_flags, nullptr, c->lu_dummy + c->lu_dummy_coarse_off,
-                                (const double *)c->consts, c->const_one<double>()};
+                                (const double *)c->consts, c->const_one<double>(), c->d_lustat + 2};
         if (!lp::launch_band_lu<double>(ba, 3, P.cpor.bw, c->lu_variant, st)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
         // the coarse porous matrices are constant: invert them once
         const long long n = P.cpor.ndof;
@@ -1435,7 +1446,7 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
                 aa.W1[0] = oa.W1[0]; aa.W1[1] = oa.W1[1]; aa.band = c->band_cns; aa.skip = c->d_done;
                 lp::launch_oseen_rows<double>(aa, 1, c->nodes_cns, P.cns.bw, s);
                 lp::BandArgs<double> ba{c->d_lu_cns, c->band_cns, c->fac_cns, c->d_flags, c->d_done, c->lu_dummy + c->lu_dummy_coarse_off,
-                                        (const double *)c->consts, c->const_one<double>()};
+                                        (const double *)c->consts, c->const_one<double>(), c->d_lustat + 2};
                 if (!lp::launch_band_lu<double>(ba, 1, P.cns.bw, c->lu_variant_cns, s)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
                 // explicit inverse of the Jacobian: each chord step is then one
                 // dense product instead of a serial band solve
@@ -1548,6 +1559,72 @@ lp_status local_step_impl(lp_ctx *c, void *stream, const LocalScratch &ls, bool 
     return LP_OK;
 }
 
+}  // namespace
+
+namespace {
+// device buffers of one diagnostic call, freed on every return path
+struct DiagBuffers {
+    std::vector<void *> p;
+    template <typename T>
+    bool get(T **q, size_t count) {
+        void *v = nullptr;
+        if (hipMalloc(&v, (count > 0 ? count : 1) * sizeof(T)) != hipSuccess) return false;
+        p.push_back(v);
+        *q = (T *)v;
+        return true;
+    }
+    ~DiagBuffers() {
+        for (void *v : p) (void)hipFree(v);
+    }
+};
+
+template <typename T>
+lp_status band_factor_solve(int nsys, int n, int bw, const double *band, const double *rhs, double *x, int variant,
+                            int *flags, double *growth, double *pivot_min) {
+    const int ld = 2 * bw + 1, nr = lp::solve_nr(bw);
+    if (nr == 0 || bw > lp::LU_MAX_BW || ((variant == 8 || variant == 9) && bw > 160))
+        return fail(LP_ERR_UNSUPPORTED, "half-bandwidth beyond the factorisation kernels' window");
+    const int ldf = 64 * nr;
+    const long long nb = (long long)nsys * n * ld, nfac = (long long)nsys * (2LL * n * ldf + n);
+    std::vector<lp::BandSys> sys(nsys);
+    for (int s = 0; s < nsys; ++s)
+        sys[s] = lp::BandSys{(long long)s * n * ld, 0, (long long)s * n, (long long)s * (2LL * n * ldf + n), 0, n, bw, 1, ldf};
+    std::vector<T> bt(band, band + nb);
+    const T consts[2] = {T(0), T(1)};
+    const double zero64 = 0.0;
+    DiagBuffers db;
+    lp::BandSys *dsys;
+    T *dband, *dfac, *ddummy, *dconst;
+    double *dr, *dx, *dz;
+    int *dflags;
+    float *dstat;
+    if (!db.get(&dsys, nsys) || !db.get(&dband, nb) || !db.get(&dfac, nfac) ||
+        !db.get(&ddummy, (size_t)nsys * lp::LU_DUMMY_PER_SYS) || !db.get(&dconst, 2) || !db.get(&dr, (size_t)nsys * n) ||
+        !db.get(&dx, (size_t)nsys * n) || !db.get(&dz, 1) || !db.get(&dflags, 1) || !db.get(&dstat, 2))
+        return fail(LP_ERR_ALLOC, "device allocation failed");
+    HIPCHK(hipMemcpy(dsys, sys.data(), sys.size() * sizeof(lp::BandSys), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dband, bt.data(), nb * sizeof(T), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dconst, consts, sizeof(consts), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dz, &zero64, sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(dr, rhs, (size_t)nsys * n * sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(dfac, 0, nfac * sizeof(T)));
+    HIPCHK(hipMemset(dflags, 0, sizeof(int)));
+    HIPCHK(hipMemset(dstat, 0, 2 * sizeof(float)));
+    lp::BandArgs<T> ba{dsys, dband, dfac, dflags, nullptr, ddummy, dconst, dconst + 1, dstat};
+    if (!lp::launch_band_lu<T>(ba, nsys, bw, variant, nullptr)) return fail(LP_ERR_UNSUPPORTED, "factorisation variant");
+    lp::SolveArgs<T> sa{dsys, dfac, dr, dx, nullptr, 1, nullptr, dconst, dconst + 1, dz};
+    sa.assign = 1;
+    if (!lp::launch_band_solve<T>(sa, nsys, 1, bw, n, 0, nullptr)) return fail(LP_ERR_UNSUPPORTED, "band solve size");
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipDeviceSynchronize());
+    float st[2];
+    HIPCHK(hipMemcpy(x, dx, (size_t)nsys * n * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(flags, dflags, sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(st, dstat, sizeof(st), hipMemcpyDeviceToHost));
+    *growth = st[0];
+    *pivot_min = st[1] > 0.f ? 1.0 / st[1] : 1.0;
+    return LP_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -1688,11 +1765,29 @@ lp_status lp_get_stats(lp_ctx *c, lp_stats *out) {
         HIPCHK(hipMemcpy(tot.data(), c->gm_tot, no * sizeof(int), hipMemcpyDeviceToHost));
         for (int v : tot) out->krylov_its = std::max(out->krylov_its, v);
     }
+    {
+        float st[4];
+        HIPCHK(hipMemcpy(st, c->d_lustat, sizeof(st), hipMemcpyDeviceToHost));
+        out->lu_growth_local = st[0];
+        out->lu_pivot_local = st[1] > 0.f ? 1.0 / st[1] : 1.0;
+        out->lu_growth_coarse = st[2];
+        out->lu_pivot_coarse = st[3] > 0.f ? 1.0 / st[3] : 1.0;
+    }
     if (out->flags) {
         return fail(LP_ERR_NOCONV, std::string("flags ") + std::to_string(out->flags) +
                                        ": a refinement, a coarse Newton iteration or a pivot check failed in some step so far");
     }
     return LP_OK;
+}
+
+lp_status lp_band_factor_solve(int32_t nsys, int32_t n, int32_t bw, const double *band, const double *rhs, double *x,
+                               int32_t precision, int32_t variant, int32_t *flags, double *growth, double *pivot_min) {
+    if (nsys < 1 || n < 1 || bw < 0 || bw >= n || !band || !rhs || !x || !flags || !growth || !pivot_min)
+        return fail(LP_ERR_ARG, "sizes or NULL arguments");
+    if (variant != 0 && variant != 8 && variant != 9) return fail(LP_ERR_ARG, "variant must be 0, 8 or 9");
+    if (precision == LP_FP64) return band_factor_solve<double>(nsys, n, bw, band, rhs, x, variant, flags, growth, pivot_min);
+    if (precision == LP_MIXED) return band_factor_solve<float>(nsys, n, bw, band, rhs, x, variant, flags, growth, pivot_min);
+    return fail(LP_ERR_ARG, "precision must be LP_FP64 or LP_MIXED");
 }
 
 lp_status lp_set_timing(lp_ctx *c, uint32_t mask) {

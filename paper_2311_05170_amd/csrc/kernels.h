@@ -174,9 +174,23 @@ struct BandArgs {
     T *dummy;                     // LU_DUMMY_PER_SYS elements per system: sink for masked stores
     const T *zero;                // a device zero, read by masked prefetches
     const T *one;                 // a device one (identity padding beyond n)
+    // pivot and growth monitor (may be null): run-long maxima, as float bits,
+    // of the growth factor max|u_ij| / max|a_ij| of a system and of
+    // max|a_ij| / min|u_kk| (the inverse of its smallest relative pivot)
+    float *stat = nullptr;
 };
 
 constexpr long long LU_DUMMY_PER_SYS = 1024;
+// A pivot is too small when |u_kk| <= lu_tiny(T) * max|a_ij| of its system:
+// below one rounding unit of the largest entry, where a pivot formed by
+// cancellation keeps no correct digit.  (Pivots well below max|a_ij| are
+// normal here: the pressure rows of the saddle-point systems eliminate to a
+// Schur complement on a smaller scale.)  The growth is too large when
+// max|u_ij| / max|a_ij| > lu_growth_limit(T): the factor's rounding, eps
+// times the growth, would leave the refinement less than 2^-7 per sweep.
+// Either raises flag bit 2.
+template <typename T> constexpr float lu_tiny() { return sizeof(T) == 4 ? 0x1p-23f : 0x1p-52f; }
+template <typename T> constexpr float lu_growth_limit() { return sizeof(T) == 4 ? 0x1p16f : 0x1p45f; }
 
 template <typename T>
 struct SolveArgs {

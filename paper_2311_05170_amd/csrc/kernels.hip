@@ -1323,6 +1323,48 @@ __global__ __launch_bounds__(GB) void k_oseen_finalize(FinalizeArgs F) {
 }
 
 // ---------------------------------------------------------------------------
+// Pivot and growth monitor of one band factorisation.  Each thread keeps the
+// largest magnitude it has seen of a matrix entry (amax), of an entry of U
+// (umax) and of a pivot reciprocal (dmax); the workgroup reduces them once at
+// the end of the kernel.  The smallest pivot relative to the largest entry is
+// 1 / (dmax amax) and the growth factor umax / amax; the thresholds of
+// lu_tiny and lu_growth_limit raise flag bit 2, and both values go to the
+// run-long maxima of B.stat.
+struct LuMon {
+    float amax = 0.f, umax = 0.f, dmax = 0.f;
+    template <typename T> __device__ __forceinline__ void a(T v) { amax = fmaxf(amax, (float)fabs(v)); }
+    template <typename T> __device__ __forceinline__ void u(T v) { umax = fmaxf(umax, (float)fabs(v)); }
+    template <typename T> __device__ __forceinline__ void d(T v) { dmax = fmaxf(dmax, (float)fabs(v)); }
+};
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+// every thread of the workgroup calls this once, after its last barrier
+template <typename T, int NWAVES>
+__device__ void lu_monitor_finish(const LuMon &m, const BandArgs<T> &B) {
+    __shared__ float red[3][NWAVES];
+    const float a = wave_max(m.amax), u = wave_max(m.umax), d = wave_max(m.dmax);
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { red[0][wv] = a; red[1][wv] = u; red[2][wv] = d; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float A = 0.f, U = 0.f, D = 0.f;
+        for (int w = 0; w < NWAVES; ++w) { A = fmaxf(A, red[0][w]); U = fmaxf(U, red[1][w]); D = fmaxf(D, red[2][w]); }
+        if (A > 0.f) {
+            const float growth = U / A, invpiv = D * A;      // invpiv: max|a| / min|u_kk|
+            const bool bad = !(invpiv * lu_tiny<T>() < 1.f) || !(growth <= lu_growth_limit<T>());
+            if (bad) atomicOr(B.flags, 4);
+            if (B.stat) {
+                // non-negative floats order like their bit patterns
+                atomicMax(reinterpret_cast<unsigned *>(B.stat), __float_as_uint(isfinite(growth) ? growth : INFINITY));
+                atomicMax(reinterpret_cast<unsigned *>(B.stat) + 1, __float_as_uint(isfinite(invpiv) ? invpiv : INFINITY));
+            }
+        }
+    }
+}
+
 // Band LU without pivoting.  One workgroup per system; the active window of
 // WR x WC entries (rows k..k+WR-1, columns k..k+WC-1 relative to the current
 // pivot k) lives in registers, thread (tr, tc) holding an RB x CB block.
@@ -1367,6 +1409,7 @@ __global__ __launch_bounds__(TP *TP) void k_band_lu(BandArgs<T> B) {
     __shared__ T lbuf[2][W];       // pivot column by row slot
     __shared__ T ent[2][NE];       // entering row by column slot, then entering column by row slot
     const int tid = threadIdx.x, tr = tid / TP, tc = tid % TP;
+    LuMon mon;
     T a[RB][RB];
 #pragma unroll
     for (int i = 0; i < RB; ++i)
@@ -1376,6 +1419,7 @@ __global__ __launch_bounds__(TP *TP) void k_band_lu(BandArgs<T> B) {
             const bool ok = gi < n && gj < n && d <= bw && d >= -bw;
             const T v = M[ok ? gj * ld + d + bw : 0];
             a[i][jj] = ok ? v : T(0);
+            mon.a(a[i][jj]);
         }
     // Per-thread items q = tid + it*NT (q < 2W).  Fetch (for step kk): q < W is
     // A(kk+W, kk+1+q), W <= q is A(kk+1+e, kk+W) with e = q - W; both at a fixed
@@ -1410,7 +1454,10 @@ __global__ __launch_bounds__(TP *TP) void k_band_lu(BandArgs<T> B) {
 #pragma unroll
     for (int s = 0; s < U; ++s)
 #pragma unroll
-        for (int it = 0; it < NI; ++it) fifo[s][it] = *(s < fend[it] ? M + (foff[it] + s * ld) : B.zero);
+        for (int it = 0; it < NI; ++it) {
+            fifo[s][it] = *(s < fend[it] ? M + (foff[it] + s * ld) : B.zero);
+            mon.a(fifo[s][it]);
+        }
     int bad = 0;
     int kw = 0;                                     // k0 mod W (a multiple of U)
     int rk = (n - 1) % R;                           // (n-1-k) mod R
@@ -1447,6 +1494,7 @@ __global__ __launch_bounds__(TP *TP) void k_band_lu(BandArgs<T> B) {
             T piv = ubuf[buf][kmod];
             if (!(fabs((double)piv) > 0.0) || !isfinite((double)piv)) { bad = 1; piv = T(1); }
             const T inv = T(1) / piv;
+            if (tid == 0) { mon.d(inv); mon.u(piv); }
             const int kl = k * ldf, rl = (n - 1 - k) * ldf + fac_pos(rk, nrf);
 #pragma unroll
             for (int it = 0; it < NI; ++it) {
@@ -1460,6 +1508,7 @@ __global__ __launch_bounds__(TP *TP) void k_band_lu(BandArgs<T> B) {
                 T *udst = o == 0 ? Di + k : Ur + (rl + soff[it]);
                 T *dst = k < send[it] ? (isl ? ldst : udst) : dummy + it;
                 *dst = isl ? lv : uv;
+                mon.u(!isl && o != 0 && k < send[it] ? ubuf[buf][sl] : T(0));
                 srot[it] = srot[it] + 1 == R ? 0 : srot[it] + 1;
             }
             rk = rk == 0 ? R - 1 : rk - 1;
@@ -1488,12 +1537,16 @@ __global__ __launch_bounds__(TP *TP) void k_band_lu(BandArgs<T> B) {
                 }
             const int kf = k + U, kfl = kf * ld;
 #pragma unroll
-            for (int it = 0; it < NI; ++it) fifo[s][it] = *(kf < fend[it] ? M + (kfl + foff[it]) : B.zero);
+            for (int it = 0; it < NI; ++it) {
+                fifo[s][it] = *(kf < fend[it] ? M + (kfl + foff[it]) : B.zero);
+                mon.a(fifo[s][it]);
+            }
         }
         kw += U;
         kw = kw == W ? 0 : kw;
     }
     if (bad && tid == 0) atomicOr(B.flags, 4);
+    lu_monitor_finish<T, (NT + 63) / 64>(mon, B);
 }
 
 // value of v in lane `lane` of the wavefront (uniform lane index)
@@ -1613,6 +1666,7 @@ __global__ __launch_bounds__(64 * (NW + LU_NS)) void k_band_lu_mfma(BandArgs<T> 
     // the wavefront index is uniform: keep tile coordinates and branches scalar
     const int tid = threadIdx.x, wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63, lc = lane & 15;
     const int npan = (n + 15) / 16;
+    LuMon mon;
     if (wv < NW) {
         // ---- tile wavefronts: hold the window, refill it, apply the trailing updates
         v4 acc[MT];
@@ -1627,6 +1681,7 @@ __global__ __launch_bounds__(64 * (NW + LU_NS)) void k_band_lu_mfma(BandArgs<T> 
                 const bool in = gi < n && gj < n && d <= bw && d >= -bw;                       \
                 const T *src = in ? M + ((long long)gj * ld + d + bw) : (gi == gj ? B.one : B.zero); \
                 DST_[r] = *src;                                                               \
+                mon.a(in ? DST_[r] : T(0));     /* the identity padding is not the matrix's */ \
             }                                                                                 \
         } while (0)
 #pragma unroll
@@ -1708,6 +1763,7 @@ __global__ __launch_bounds__(64 * (NW + LU_NS)) void k_band_lu_mfma(BandArgs<T> 
                     T piv = wave_bcast(d[j], j);
                     if (!(fabs((double)piv) > 0.0) || !isfinite((double)piv)) { bad = 1; piv = T(1); }
                     const T inv = T(1) / piv;
+                    if (k0 + j < n) { mon.d(inv); mon.u(piv); }
                     if (lane == j) dinv[j] = inv;
                     const T l = d[j] * inv;
 #pragma unroll
@@ -1821,7 +1877,9 @@ __global__ __launch_bounds__(64 * (NW + LU_NS)) void k_band_lu_mfma(BandArgs<T> 
                     int jw = 16 * P + 1 + jo;
                     jw = jw >= W ? jw - W : jw;
                     jw = jw >= W ? jw - W : jw;
-                    uvv[u] = ok ? (j < k0 + 16 ? Pc[16 * P + c][(j - k0) & 15] : Pr[c][jw]) * dk : T(0);
+                    const T uval = ok ? (j < k0 + 16 ? Pc[16 * P + c][(j - k0) & 15] : Pr[c][jw]) : T(0);
+                    mon.u(uval);
+                    uvv[u] = uval * dk;
                     ua[u] = ok ? (long long)(n - 1 - j) * ldf + pk : -1;
                 }
 #pragma unroll
@@ -1833,6 +1891,7 @@ __global__ __launch_bounds__(64 * (NW + LU_NS)) void k_band_lu_mfma(BandArgs<T> 
         }
         if (bad && lane == 0) atomicOr(B.flags, 4);
     }
+    lu_monitor_finish<T, NW + LU_NS>(mon, B);
 }
 
 // ---------------------------------------------------------------------------
@@ -1891,6 +1950,7 @@ __global__ __launch_bounds__(64 * (TT + LU_NS)) void k_band_lu_la(BandArgs<T> B)
     T (*DgS)[16][16] = reinterpret_cast<T (*)[16][16]>(&DgSQ[0][0][0]);
     const int tid = threadIdx.x, wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63, lc = lane & 15, lg = lane >> 4;
     const int npan = (n + 15) / 16;
+    LuMon mon;
     T *Lr = B.fac + Sy.foff, *Ur = Lr + (long long)n * ldf, *Di = Ur + (long long)n * ldf;
     // L and U of panel ps from buffer bb in the solves' layout (fac_pos, R
     // slots per column), by worker w of NWK (its share of the columns and rows)
@@ -1947,6 +2007,7 @@ __global__ __launch_bounds__(64 * (TT + LU_NS)) void k_band_lu_la(BandArgs<T> B)
                 const int dj = j - k0;
                 const T *src = dj < 16 ? &DgS[q][c][dj & 15] : &Pr[bb][jw][lu_perm(c)];
                 const T v = *src;
+                mon.u(ok ? v : T(0));
                 if (ok) Ur[(long long)(n - 1 - j) * ldf + pk] = v * dk;
             }
         }
@@ -1970,6 +2031,7 @@ __global__ __launch_bounds__(64 * (TT + LU_NS)) void k_band_lu_la(BandArgs<T> B)
                 const bool in = gi < n && gj < n && d <= bw && d >= -bw;                       \
                 const T *src = in ? M + ((long long)gj * ld + d + bw) : (gi == gj ? B.one : B.zero); \
                 DST_[r] = *src;                                                               \
+                mon.a(in ? DST_[r] : T(0));     /* the identity padding is not the matrix's */ \
             }                                                                                 \
         } while (0)
         // entering tiles in flight: staging registers, filled by loads from
@@ -2028,7 +2090,10 @@ __global__ __launch_bounds__(64 * (TT + LU_NS)) void k_band_lu_la(BandArgs<T> B)
                             const int gi = gi0 + Mfma<T>::crow(lane, r), d = gi - gj;          \
                             const bool in = gi < n && gj < n && d <= bw && d >= -bw;           \
                             acc[t][r] = in ? acc[t][r] : (gi == gj ? T(1) : T(0));            \
+                            mon.a(in ? acc[t][r] : T(0));                                     \
                         }                                                                     \
+                    } else {                                                                  \
+                        _Pragma("unroll") for (int r = 0; r < 4; ++r) mon.a(acc[t][r]);        \
                     }                                                                         \
                 }                                                                             \
             }                                                                                 \
@@ -2100,8 +2165,10 @@ __global__ __launch_bounds__(64 * (TT + LU_NS)) void k_band_lu_la(BandArgs<T> B)
                     for (int kk = 0; kk < 4; ++kk) d[4 * kk + g] = x.v[kk];
                 }
                 tile_lu(d, lc, lane, dinv, std::make_integer_sequence<int, 16>());
-                // a zero, tiny or non-finite pivot leaves a zero or non-finite reciprocal
+                // a zero or non-finite pivot leaves a zero or non-finite reciprocal; a
+                // merely small one is judged against the matrix scale at the end
                 if (lane < 16 && !(fabs((double)dinv) > 0.0 && isfinite((double)dinv))) bad = 1;
+                if (lane < 16 && 16 * pf + lane < n) { mon.d(dinv); mon.u(T(1) / dinv); }
                 if (lane < 16) {
                     Dv[wr][lane] = dinv;
                     if (wr == 0) DvS[pf & 1][lane] = dinv;
@@ -2174,6 +2241,7 @@ __global__ __launch_bounds__(64 * (TT + LU_NS)) void k_band_lu_la(BandArgs<T> B)
         }
         if (bad && lane == 0) atomicOr(B.flags, 4);
     }
+    lu_monitor_finish<T, TT + LU_NS>(mon, B);
 }
 
 // ---------------------------------------------------------------------------

@@ -34,7 +34,7 @@ LP_ERR_NOCONV = 5
 
 EXPORTS = ["lp_setup", "lp_coarse_step", "lp_local_step", "lp_get_size", "lp_get_solution",
            "lp_get_stats", "lp_plan_query", "lp_get_index_map", "lp_set_timing", "lp_get_timing",
-           "lp_local_step_noalloc", "lp_destroy", "lp_last_error"]
+           "lp_local_step_noalloc", "lp_band_factor_solve", "lp_destroy", "lp_last_error"]
 # stage timer indices (LP_T_* in lp.h)
 STAGES = ["prolong", "por_rhs", "por_solve", "por_res", "ose_rhs", "ose_asm", "ose_lu", "ose_solve",
           "ose_res", "merge", "coarse", "wait_coarse", "wait_fac", "wait_por"]
@@ -79,7 +79,8 @@ class LpStats(Structure):
                 ("solver", c_int32), ("tuned", c_int32), ("lu_variant", c_int32), ("solve_depth", c_int32),
                 ("tune_dense_ms", c_double), ("tune_krylov_ms", c_double), ("krylov_its", c_int32),
                 ("ir_sweeps_porous", c_int32), ("ir_sweeps_oseen", c_int32), ("ir_relres_porous", c_double),
-                ("ir_relres_oseen", c_double)]
+                ("ir_relres_oseen", c_double), ("lu_growth_local", c_double), ("lu_pivot_local", c_double),
+                ("lu_growth_coarse", c_double), ("lu_pivot_coarse", c_double)]
 
 
 class LpError(RuntimeError):
@@ -106,6 +107,9 @@ def load(path=LIB_PATH):
     lib.lp_get_index_map.argtypes = [c_void_p, c_int32, c_int32, POINTER(c_int64), c_int64, POINTER(c_int64)]
     lib.lp_set_timing.argtypes = [c_void_p, ctypes.c_uint32]
     lib.lp_get_timing.argtypes = [c_void_p, POINTER(c_double), POINTER(c_int64), c_int32]
+    lib.lp_band_factor_solve.argtypes = [c_int32, c_int32, c_int32, POINTER(c_double), POINTER(c_double),
+                                         POINTER(c_double), c_int32, c_int32, POINTER(c_int32), POINTER(c_double),
+                                         POINTER(c_double)]
     lib.lp_destroy.argtypes = [c_void_p]
     lib.lp_destroy.restype = None
     lib.lp_last_error.restype = c_char_p
@@ -132,6 +136,22 @@ def _structs(n_coarse, refine, nsub, overlap, cuts):
         keep = (c_int32 * len(cuts))(*[int(v) for v in cuts])
         part.cuts = ctypes.cast(keep, POINTER(c_int32))
     return mesh, part, keep
+
+
+def band_factor_solve(band, rhs, precision="fp64", variant=9):
+    """Factor and solve caller-provided band systems with the library's band
+    kernels (lp_band_factor_solve).  band: (nsys, n, 2 bw + 1) FP64, entry
+    (i, j) of system s at band[s, j, i - j + bw]; rhs: (nsys, n).  Returns
+    (x, flags, growth, pivot_min)."""
+    band = np.ascontiguousarray(band, dtype=np.float64)
+    rhs = np.ascontiguousarray(rhs, dtype=np.float64)
+    nsys, n, ld = band.shape
+    x = np.zeros((nsys, n))
+    flags, growth, pivot = c_int32(0), c_double(0.0), c_double(0.0)
+    dp = lambda a: a.ctypes.data_as(POINTER(c_double))  # noqa: E731
+    _check(_LIB.lp_band_factor_solve(nsys, n, (ld - 1) // 2, dp(band), dp(rhs), dp(x), LP_MIXED if precision == "mixed" else LP_FP64,
+                                     int(variant), byref(flags), byref(growth), byref(pivot)))
+    return x, flags.value, growth.value, pivot.value
 
 
 def plan_query(n_coarse, refine, nsub, overlap, which, sub=0, cuts=None):
