@@ -169,6 +169,48 @@ def uneven_run(precision, steps, warmup):
                 stages_ms={k: round(v[0] / nd, 3) for k, v in tm.items() if v[1]})
 
 
+def scheme_comparison(steps=20, warmup=3):
+    """Algorithm 1 (one grid, lp_options.scheme = LP_ONE_GRID) against
+    Algorithm 3 on the same fine grid h = 1/16 (cfg1: H = 1/4, 4 x 4 + 4 x 4
+    subdomains, overlap 2h, unit parameters, dt = 0.1): wall time per step of
+    each, the comparison of the paper's Tables 2 and 4 on this GPU.  Algorithm
+    1 solves the global fine systems in FP64 (decoupled porous solves, then the
+    Navier-Stokes step by chord iterations to newton_tol)."""
+    import torch
+    from paper_2311_05170_amd import workloads as W
+    from paper_2311_05170_amd.lib import LocalParallel
+    cfg = W.config("cfg1")
+    out = {}
+
+    def clock(g):
+        for _ in range(warmup):
+            g.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            g.step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        st = g.stats()
+        g.close()
+        return ms, st
+
+    # both schemes with the library's default nonlinear iteration (Jacobian
+    # formed every step, at most 16 iterations)
+    ms, st = clock(LocalParallel(cfg["Nh"], 1, cfg["nsub"], 1, cfg["prm"], cfg["dt"], precision="fp64",
+                                 scheme="one_grid"))
+    out["algorithm1_fp64"] = {"ms_per_step": ms, "newton_its_max": st["newton_its_max"], "flags": st["flags"]}
+    for prec, max_ir in (("mixed", MAX_IR_MIXED), ("fp64", 2)):
+        ms, st = clock(LocalParallel(cfg["NH"], cfg["refine"], cfg["nsub"], cfg["overlap"], cfg["prm"], cfg["dt"],
+                                     cuts=W.flat_cuts(cfg["cuts"]), precision=prec, max_ir=max_ir))
+        out["algorithm3_" + prec] = {"ms_per_step": ms, "newton_its_max": st["newton_its_max"], "flags": st["flags"]}
+    out["workload"] = ("2D Example-1 MMS, fine h=1/16 (cfg1): Algorithm 1 on T_h against Algorithm 3 with H=1/4, "
+                       "4x4 porous + 4x4 conduit subdomains, overlap 2h, unit parameters, dt=0.1")
+    out["steps"], out["warmup"] = steps, warmup
+    out["time_ratio_alg3_mixed_to_alg1"] = out["algorithm3_mixed"]["ms_per_step"] / out["algorithm1_fp64"]["ms_per_step"]
+    return out
+
+
 def serial_lu_time(cfg, precision, max_ir, steps=SERIAL_STEPS):
     """Average duration of the local Oseen factorisation with nothing beside it:
     every stage on one stream in program order (LP_SERIAL=1), HIP events
@@ -478,6 +520,7 @@ def main():
     lu_ms, lu_n = serial_lu_time(cfg, "mixed", MAX_IR_MIXED)
     gmix = graph_run(cfg, "mixed", args.steps, args.warmup, MAX_IR_MIXED)
     gf64 = graph_run(cfg, "fp64", args.steps, args.warmup, 2)
+    schemes = scheme_comparison()
     uneven = None
     if not args.no_uneven:
         cfg3 = W.config("cfg3")
@@ -514,6 +557,7 @@ def main():
     roof_ms_mixed, stages_mixed = step_roofline(cfg, sizes, tab, coarse, mixed["stats"], 4, JACOBIAN_EVERY)
     roof_ms_fp64, stages_fp64 = step_roofline(cfg, sizes, tab, coarse, fp64["stats"], 8, JACOBIAN_EVERY)
     flags = [mixed["stats"]["flags"], fp64["stats"]["flags"], gmix["stats"]["flags"], gf64["stats"]["flags"]]
+    flags += [v["flags"] for k, v in schemes.items() if k.startswith("algorithm")]
     if uneven:
         flags += [uneven["mixed"]["flags"], uneven["fp64"]["flags"]]
     line = {
@@ -566,6 +610,7 @@ def main():
                               "fp64": {"roofline_ms": roof_ms_fp64, "measured_ms": fp64["ms_per_step"],
                                        "frac": roof_ms_fp64 / fp64["ms_per_step"], "stages": stages_fp64}}},
     }
+    line["algorithm1_vs_3"] = schemes
     if uneven:
         line["uneven_batch"] = uneven
     if not args.no_cpu:

@@ -100,6 +100,9 @@ typedef struct {
 enum { LP_AUTO = 0, LP_DENSE = 1, LP_KRYLOV = 2 };
 /* coarse Navier-Stokes step (Algorithm 3 Step 1 (2)) */
 enum { LP_NEWTON = 0, LP_SEMI_IMPLICIT = 1 };
+/* scheme: the two-grid local parallel method (Algorithm 3) or the one-grid
+ * partitioned time stepping it is compared with (Algorithm 1, Section 3.3) */
+enum { LP_TWO_GRID = 0, LP_ONE_GRID = 1 };
 
 typedef struct {
     int32_t problem;         /* LP_MMS_EX1_2D */
@@ -153,6 +156,15 @@ typedef struct {
                                 time factors are computed on the device), so a replay is the
                                 next step of that slot.  Steps with stage timers on
                                 (lp_set_timing) use direct launches.  0: direct launches. */
+    int32_t scheme;          /* LP_TWO_GRID (default): Algorithm 3.  LP_ONE_GRID: Algorithm 1
+                                on the mesh of n_coarse cells (refine must be 1, so T_H = T_h):
+                                lp_coarse_step takes its step (the decoupled porous solves
+                                and the Navier-Stokes step solved by chord iterations to
+                                newton_tol, in FP64), lp_local_step has no work and only
+                                completes the step, and LP_MERGED_FINE reads the one grid's
+                                fields.  The partition is set up but not used; LP_LOCAL is
+                                an LP_ERR_STATE.  The band kernels bound the grid: coarse
+                                half-bandwidth 10 n_coarse + 2 <= 175, so n_coarse <= 17. */
 } lp_options;
 
 /* Optional device allocator (e.g. a framework's caching allocator). */

@@ -78,6 +78,7 @@ struct lp_ctx {
     std::vector<void *> owned;
     int64_t n = 0;                 // completed local steps
     bool coarse_pending = false;
+    bool one_grid = false;             // Algorithm 1: the coarse step is the whole step
     // Coarse states live in a ring of RING slots (time m in slot m % RING).
     // The coarse step runs on an internal stream: it never reads local
     // results, so coarse steps run ahead of the local stage (up to RING - 2
@@ -1045,6 +1046,9 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
         return fail(LP_ERR_ARG, "max_ir, max_newton >= 1 and positive tolerances required");
     if (opt->krylov_cycles < 0 || opt->krylov_cycles > opt->max_ir)
         return fail(LP_ERR_ARG, "krylov_cycles must lie in 0..max_ir");
+    if (opt->scheme != LP_TWO_GRID && opt->scheme != LP_ONE_GRID) return fail(LP_ERR_ARG, "scheme must be LP_TWO_GRID or LP_ONE_GRID");
+    if (opt->scheme == LP_ONE_GRID && mesh->refine != 1)
+        return fail(LP_ERR_ARG, "LP_ONE_GRID (Algorithm 1) runs on one grid: refine must be 1");
     hipStream_t st = (hipStream_t)stream;
     std::unique_ptr<lp_ctx> c(new lp_ctx());
     HIPCHK(hipGetDevice(&c->device));
@@ -1053,6 +1057,7 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     c->prm = *prm;
     c->opt = *opt;
     c->mixed = opt->precision == LP_MIXED;
+    c->one_grid = opt->scheme == LP_ONE_GRID;
     c->lu_variant_ose = 9;
     if (const char *v = std::getenv("LP_LU_VARIANT")) c->lu_variant = c->lu_variant_ose = c->lu_variant_cns = std::atoi(v);
     if (const char *v = std::getenv("LP_LU_VARIANT_COARSE")) c->lu_variant_cns = std::atoi(v);
@@ -1468,8 +1473,10 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
     }));
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(c->ev_coarse[nw], st));
-    if (c->mixed) TRY(factor_oseen<float>(c, m));
-    else TRY(factor_oseen<double>(c, m));
+    if (!c->one_grid) {
+        if (c->mixed) TRY(factor_oseen<float>(c, m));
+        else TRY(factor_oseen<double>(c, m));
+    }
     HIPCHK(hipGetLastError());
     c->coarse_pending = true;
     return LP_OK;
@@ -1491,6 +1498,16 @@ lp_status local_step_impl(lp_ctx *c, void *stream, const LocalScratch &ls, bool 
     const int o = (int)((m - 1) % lp_ctx::RING), nw = (int)(m % lp_ctx::RING);
     c->seg_m = m;
     c->key_off = clear ? G_NOALLOC : 0;
+    if (c->one_grid) {
+        // Algorithm 1: the step is complete once the coarse (= fine) step is
+        HIPCHK(hipStreamWaitEvent(st, c->ev_coarse[nw], 0));
+        HIPCHK(hipStreamWaitEvent(st, c->ev_cpor[nw], 0));
+        HIPCHK(hipEventRecord(c->ev_local[m % lp_ctx::RING], st));
+        if (st != st_user) HIPCHK(hipStreamWaitEvent(st_user, c->ev_local[m % lp_ctx::RING], 0));
+        c->n += 1;
+        c->coarse_pending = false;
+        return LP_OK;
+    }
     {
         StageTimer tm(c, LP_T_WAIT_COARSE, st);
         HIPCHK(hipStreamWaitEvent(st, c->ev_coarse[nw], 0));
@@ -1684,6 +1701,8 @@ static lp_status locate(lp_ctx *c, int32_t field, int32_t level, int32_t sub, co
 
 lp_status lp_get_size(lp_ctx *c, int32_t field, int32_t level, int32_t sub, int64_t *len) {
     if (!c || !len) return fail(LP_ERR_ARG, "NULL argument");
+    if (c->one_grid && level == LP_LOCAL) return fail(LP_ERR_STATE, "the one-grid scheme has no local corrections");
+    if (c->one_grid && level == LP_MERGED_FINE) level = LP_COARSE;
     const double *p;
     return locate(c, field, level, sub, &p, len);
 }
@@ -1692,6 +1711,8 @@ lp_status lp_get_solution(lp_ctx *c, int32_t sample, int32_t field, int32_t leve
                           int64_t len, int32_t out_is_device, void *stream) {
     if (!c || !out) return fail(LP_ERR_ARG, "NULL argument");
     if (sample != 0) return fail(LP_ERR_ARG, "sample out of range (the context holds one sample)");
+    if (c->one_grid && level == LP_LOCAL) return fail(LP_ERR_STATE, "the one-grid scheme has no local corrections");
+    if (c->one_grid && level == LP_MERGED_FINE) level = LP_COARSE;
     const double *p;
     int64_t n;
     TRY(locate(c, field, level, sub, &p, &n));

@@ -30,6 +30,8 @@ LP_AUTO, LP_DENSE, LP_KRYLOV = range(3)
 LP_NEWTON, LP_SEMI_IMPLICIT = range(2)
 SOLVER = {"auto": LP_AUTO, "dense": LP_DENSE, "krylov": LP_KRYLOV}
 COARSE_NS = {"newton": LP_NEWTON, "semi_implicit": LP_SEMI_IMPLICIT}
+LP_TWO_GRID, LP_ONE_GRID = range(2)
+SCHEME = {"two_grid": LP_TWO_GRID, "one_grid": LP_ONE_GRID}
 LP_ERR_NOCONV = 5
 
 EXPORTS = ["lp_setup", "lp_coarse_step", "lp_local_step", "lp_get_size", "lp_get_solution",
@@ -60,7 +62,8 @@ class LpOptions(Structure):
                 ("max_ir", c_int32), ("ir_tol", c_double), ("max_newton", c_int32),
                 ("newton_tol", c_double), ("jacobian_every", c_int32), ("solver", c_int32),
                 ("coarse_ns", c_int32), ("krylov_tol", c_double), ("max_iter", c_int32),
-                ("krylov_cycles", c_int32), ("nsamples", c_int32), ("autotune", c_int32), ("graphs", c_int32)]
+                ("krylov_cycles", c_int32), ("nsamples", c_int32), ("autotune", c_int32), ("graphs", c_int32),
+                ("scheme", c_int32)]
 
 
 ALLOC_FN = CFUNCTYPE(c_void_p, c_size_t, c_void_p)
@@ -185,7 +188,7 @@ class LocalParallel:
                  convection=True, max_ir=8, ir_tol=None, max_newton=16, newton_tol=1e-13,
                  jacobian_every=1, solver="auto", coarse_ns="newton", samples=None,
                  krylov_restart=30, krylov_tol=None, krylov_cycles=0, autotune=False, graphs=False,
-                 torch_allocator=True):
+                 scheme="two_grid", torch_allocator=True):
         import torch
         self._torch = torch
         if not torch.cuda.is_available():
@@ -209,6 +212,7 @@ class LocalParallel:
         opt.krylov_cycles = int(krylov_cycles)
         opt.autotune = 1 if autotune else 0
         opt.graphs = 1 if graphs else 0
+        opt.scheme = SCHEME[scheme]
         plist = [prm] if samples is None else list(samples)
         opt.nsamples = len(plist)
         params = (LpParams * len(plist))(*[_params(q, dt) for q in plist])
