@@ -149,6 +149,7 @@ struct lp_ctx {
     // factorisation monitor, run-long maxima (float bits): growth and
     // inverse smallest relative pivot of the local systems, then the coarse ones
     float *d_lustat = nullptr;
+    lp::Coef *d_co = nullptr;          // the coefficients every assembly and residual kernel reads
     // run-long refinement totals (largest sweep count, largest final relative
     // residual as double bits), folded in by the local finalize kernels
     int *d_irmax = nullptr;
@@ -480,6 +481,7 @@ lp_status refine_porous(lp_ctx *c, const lp::SysDesc *d_sys, int nsys, int maxno
         }
         StageTimer tm(c, timed ? LP_T_POR_RES : -1, st);
         lp::ResidualArgs ra{d_sys, c->d_dof2, x, b, r, conv, rel, sw, tol, nullptr, part, ticket};
+        ra.co = c->d_co;
         lp::launch_porous_residual_tiled(ra, nsys, c->tiles_por, st);
     }
     return LP_OK;
@@ -499,6 +501,7 @@ lp_status refine_oseen(lp_ctx *c, const lp::SysDesc *d_sys, int nsys, int maxnod
         }
         StageTimer tm(c, timed ? LP_T_OSE_RES : -1, st);
         lp::OseenApplyArgs<double> ra{};
+        ra.co = c->d_co;
         ra.sys = d_sys; ra.cls2 = c->d_cls2; ra.dof2 = c->d_dof2; ra.dof1 = c->d_dof1;
         ra.W1[0] = W1x; ra.W1[1] = W1y;
         ra.x = x; ra.b = b; ra.r = r; ra.band = nullptr;
@@ -520,6 +523,7 @@ lp_status refine_oseen_krylov(lp_ctx *c, double *part, int *ticket, const double
                      c->gm_bn, c->gm_done, c->gm_kd, c->opt.krylov_tol, c->conv_ose, c->gm_tot, c->gm_reorth};
     lp::StripArgs sa{c->d_strip, c->d_strip_parent, c->d_ose, c->d_smap, c->d_sown, c->gm_done, c->s_done, c->s_rs, c->s_zs};
     lp::OseenApplyArgs<double> mv{};
+    mv.co = c->d_co;
     mv.sys = c->d_ose; mv.cls2 = c->d_cls2; mv.dof2 = c->d_dof2; mv.dof1 = c->d_dof1;
     mv.W1[0] = W1x; mv.W1[1] = W1y;
     mv.b = nullptr; mv.r = c->gm_w; mv.conv = c->gm_done;
@@ -544,6 +548,7 @@ lp_status refine_oseen_krylov(lp_ctx *c, double *part, int *ticket, const double
         }
         StageTimer tm(c, timed ? LP_T_OSE_RES : -1, st);
         lp::OseenApplyArgs<double> ra{};
+        ra.co = c->d_co;
         ra.sys = c->d_ose; ra.cls2 = c->d_cls2; ra.dof2 = c->d_dof2; ra.dof1 = c->d_dof1;
         ra.W1[0] = W1x; ra.W1[1] = W1y;
         ra.x = c->x_ose; ra.b = c->b_ose; ra.r = c->r_ose; ra.band = nullptr;
@@ -557,6 +562,7 @@ lp_status refine_oseen_krylov(lp_ctx *c, double *part, int *ticket, const double
 template <typename T>
 lp_status factor_porous(lp_ctx *c, T *band, T *fac, hipStream_t st) {
     lp::AssembleArgs<T> aa{c->d_por, c->d_dof2, band};
+    aa.co = c->d_co;
     lp::launch_porous_assemble<T>(aa, (int)c->P.por.size(), st);
     lp::BandArgs<T> ba{c->d_lu_por, band, fac, c->d_flags, nullptr, (T *)c->lu_dummy, (const T *)c->consts, c->const_one<T>(),
                        c->d_lustat};
@@ -572,6 +578,7 @@ lp_status local_oseen(lp_ctx *c, hipStream_t st, const LocalScratch &ls) {
     const int o = c->ecur, nw = 1 - c->ecur;
     // right-hand sides of (5.8) and Dirichlet values of the new corrections
     lp::OseenArgs oa{};
+    oa.co = c->d_co;
     oa.sys = c->d_ose; oa.cls2 = c->d_cls2; oa.dof2 = c->d_dof2; oa.cls1 = c->d_cls1; oa.dof1 = c->d_dof1;
     const double *pro = c->pro_slot((int)((c->n + 1) % lp_ctx::RING));
     oa.W1[0] = pro; oa.W1[1] = pro + nf2;
@@ -649,6 +656,7 @@ lp_status factor_oseen(lp_ctx *c, int64_t m) {
             // reliably in a graph)
             lp::launch_zero_fill(band, (size_t)c->P.band_total_ose * sizeof(T), s);
             lp::OseenApplyArgs<T> aa{};
+            aa.co = c->d_co;
             aa.sys = c->d_ose; aa.cls2 = c->d_cls2; aa.dof2 = c->d_dof2; aa.dof1 = c->d_dof1;
             aa.W1[0] = pro_Uf; aa.W1[1] = pro_Uf + c->nf2; aa.band = band;
             lp::launch_oseen_assemble<T>(aa, nsys, c->nodes_ose, s);
@@ -690,6 +698,7 @@ lp_status local_porous(lp_ctx *c, const double *pro, hipStream_t st, const Local
     const long long nf2 = c->nf2;
     const int o = c->ecur, nw = 1 - c->ecur;
     lp::PorousArgs pa{};
+    pa.co = c->d_co;
     pa.sys = c->d_por; pa.cls2 = c->d_cls2; pa.dof2 = c->d_dof2;
     for (int f = 0; f < 3; ++f) {
         pa.P1[f] = pro + f * nf2;
@@ -781,6 +790,7 @@ lp_status setup_strips(lp_ctx *c, hipStream_t st) {
     HIPCHK(hipMemsetAsync(band, 0, (size_t)P.band_total_strip * sizeof(T), st));
     HIPCHK(hipMemsetAsync(fac, 0, (size_t)fl.total * sizeof(T), st));
     lp::OseenApplyArgs<T> aa{};
+    aa.co = c->d_co;
     aa.sys = c->d_strip; aa.cls2 = c->d_cls2; aa.dof2 = c->d_dof2; aa.dof1 = c->d_dof1;
     aa.W1[0] = c->pro_U1; aa.W1[1] = c->pro_U1 + c->nf2;   // not read: no convection
     aa.band = band;
@@ -849,6 +859,7 @@ lp_status autotune(lp_ctx *c, hipStream_t st) {
     lp::launch_fill_pattern(c->x_ose, nt, st);
     {
         lp::OseenApplyArgs<double> mv{};
+        mv.co = c->d_co;
         mv.sys = c->d_ose; mv.cls2 = c->d_cls2; mv.dof2 = c->d_dof2; mv.dof1 = c->d_dof1;
         mv.W1[0] = Wx; mv.W1[1] = Wy;
         mv.x = c->x_ose; mv.b = nullptr; mv.r = c->b_ose; mv.conv = nullptr;
@@ -869,6 +880,7 @@ lp_status autotune(lp_ctx *c, hipStream_t st) {
         auto factor = [&](int variant) -> lp_status {
             lp::launch_zero_fill(band, (size_t)c->P.band_total_ose * sizeof(T), st);
             lp::OseenApplyArgs<T> aa{};
+            aa.co = c->d_co;
             aa.sys = c->d_ose; aa.cls2 = c->d_cls2; aa.dof2 = c->d_dof2; aa.dof1 = c->d_dof1;
             aa.W1[0] = Wx; aa.W1[1] = Wy; aa.band = band;
             lp::launch_oseen_assemble<T>(aa, nsys, c->nodes_ose, st);
@@ -1111,7 +1123,8 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     co.ctau = prm->eta * prm->nu * prm->alpha * std::sqrt(prm->k[0]) / prm->mu_tilde;
     co.convection = opt->convection ? 1 : 0;
     lp::build_refdata(c->ref);
-    HIPCHK(lp::upload_constants(c->ref, co, st));
+    HIPCHK(lp::upload_constants(c->ref, st));
+    TRY(c->upload(&c->d_co, std::vector<lp::Coef>{co}, st));
 
     c->nf2 = (long long)(2 * P.Nh + 1) * (2 * P.Nh + 1);
     c->nf1 = (long long)(P.Nh + 1) * (P.Nh + 1);
@@ -1327,6 +1340,7 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     HIPCHK(hipMemsetAsync(c->band_cpor, 0, P.cband_por * sizeof(double), st));
     {
         lp::AssembleArgs<double> aa{c->d_cpor, c->d_dof2, c->band_cpor};
+        aa.co = c->d_co;
         lp::launch_porous_assemble<double>(aa, 1, st);
         lp::BandArgs<double> ba{c->d_lu_cpor, c->band_cpor, c->fac_cpor, c->d_flags, nullptr, c->lu_dummy + c->lu_dummy_coarse_off,
                                 (const double *)c->consts, c->const_one<double>(), c->d_lustat + 2};
@@ -1388,6 +1402,7 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
     const long long nc2 = c->nc2;
     // (5.1)-(5.3): three SPD solves with lagged exchange and lagged u^n on Gamma
     lp::PorousArgs pa{};
+    pa.co = c->d_co;
     pa.sys = c->d_cpor; pa.cls2 = c->d_cls2; pa.dof2 = c->d_dof2;
     for (int f = 0; f < 3; ++f) {
         pa.P1[f] = nullptr; pa.P0[f] = nullptr;
@@ -1430,6 +1445,7 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
         }
         for (int it = 0; it < c->opt.max_newton; ++it) {
             lp::OseenArgs oa{};
+            oa.co = c->d_co;
             oa.sys = c->d_cns; oa.cls2 = c->d_cls2; oa.dof2 = c->d_dof2; oa.cls1 = c->d_cls1; oa.dof1 = c->d_dof1;
             oa.W1[0] = c->cU[nw]; oa.W1[1] = c->cU[nw] + nc2;
             oa.W0[0] = c->cU[o]; oa.W0[1] = c->cU[o] + nc2;
@@ -1447,6 +1463,7 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
                 // the next refresh) reuse its inverse, with residuals of the
                 // current iterate (chord steps)
                 lp::OseenApplyArgs<double> aa{};
+                aa.co = c->d_co;
                 aa.sys = c->d_cns; aa.cls2 = c->d_cls2; aa.dof2 = c->d_dof2; aa.dof1 = c->d_dof1;
                 aa.W1[0] = oa.W1[0]; aa.W1[1] = oa.W1[1]; aa.band = c->band_cns; aa.skip = c->d_done;
                 lp::launch_oseen_rows<double>(aa, 1, c->nodes_cns, P.cns.bw, s);

@@ -36,6 +36,7 @@ struct PorousArgs {
     double *b;
     const double *tf;             // device: cos t_{n+1}, sin t_{n+1}, cos^2 t_{n+1}
     IrStart ir;                   // three flags per system
+    const Coef *co = nullptr;     // the context's coefficients (device)
 };
 
 struct ResidualArgs {
@@ -51,6 +52,7 @@ struct ResidualArgs {
     const int *skip;
     double *part;                 // per-(system, node block) partial norms: 2 * nblocks doubles per id
     int *ticket;                  // per-id arrival counters, zero between launches
+    const Coef *co = nullptr;     // the context's coefficients (device)
 };
 
 // Refinement outcome of a batch, folded into run-long totals by the finalize
@@ -85,6 +87,7 @@ struct AssembleArgs {
     const SysDesc *sys;
     const int32_t *dof2;
     T *band;
+    const Coef *co = nullptr;     // the context's coefficients (device)
 };
 
 struct OseenArgs {
@@ -106,6 +109,7 @@ struct OseenArgs {
     const double *tf;             // device: cos t_{n+1}, sin t_{n+1}, cos^2 t_{n+1}
     const int *skip;
     IrStart ir;                   // one flag per system
+    const Coef *co = nullptr;     // the context's coefficients (device)
 };
 
 template <typename T>
@@ -127,6 +131,7 @@ struct OseenApplyArgs {
     double *part;                 // residual mode: partial norms and counters as in ResidualArgs
     int *ticket;
     int no_convection;            // assembly: leave out b_N (the Stokes part of the operator)
+    const Coef *co = nullptr;     // the context's coefficients (device)
 };
 
 struct BandSys {
@@ -315,7 +320,7 @@ void launch_strip_scatter(const StripArgs &a, int nstrip, double *z, hipStream_t
 size_t gm_arnoldi_lds(int maxn);
 void launch_fill_pattern(double *x, long long n, hipStream_t st);
 
-hipError_t upload_constants(const RefData &r, const Coef &c, hipStream_t st);
+hipError_t upload_constants(const RefData &r, hipStream_t st);
 void launch_prolong_p2(const ProlongArgs &a, hipStream_t st);
 void launch_prolong_p1(const ProlongArgs &a, hipStream_t st);
 // Node-gather kernels run gridDim = (node blocks of GB threads, systems);

@@ -21,12 +21,9 @@
 namespace lp {
 
 __constant__ RefData c_ref;
-__constant__ Coef c_co;
 
-hipError_t upload_constants(const RefData &r, const Coef &c, hipStream_t st) {
-    hipError_t e = hipMemcpyToSymbolAsync(HIP_SYMBOL(c_ref), &r, sizeof(RefData), 0, hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return e;
-    return hipMemcpyToSymbolAsync(HIP_SYMBOL(c_co), &c, sizeof(Coef), 0, hipMemcpyHostToDevice, st);
+hipError_t upload_constants(const RefData &r, hipStream_t st) {
+    return hipMemcpyToSymbolAsync(HIP_SYMBOL(c_ref), &r, sizeof(RefData), 0, hipMemcpyHostToDevice, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -148,7 +145,7 @@ __global__ void k_prolong_p1(ProlongArgs A) {
 //   X_f = P_f^{n+1} + z_f (background at n+1 plus Dirichlet values of the correction),
 //   O_f = P_f^n + e_f^n (background at n plus the previous correction).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double porous_x(int f) { return f == 0 ? c_co.sst : f == 1 ? c_co.s + c_co.sst : c_co.s; }
+__device__ __forceinline__ double porous_x(const Coef &cf, int f) { return f == 0 ? cf.sst : f == 1 ? cf.s + cf.sst : cf.s; }
 
 // Dirichlet value of field f of the correction at local P2 node q of system S
 __device__ __forceinline__ double porous_z(const SysDesc &S, const PorousArgs &A, int f, int q, long long G) {
@@ -195,6 +192,7 @@ __device__ __forceinline__ double group_sum(double v) {
 // single coarse system, where a thread per node leaves the chip idle).
 template <int SPLIT>
 __global__ __launch_bounds__(GB) void k_porous_rhs(PorousArgs A) {
+    const Coef &cf = *A.co;           // this context's coefficients
     static_assert(GB % SPLIT == 0, "node groups within a block");
     const SysDesc S = A.sys[blockIdx.y];
     const int nloc = S.lw2 * S.lh2;
@@ -229,15 +227,15 @@ __global__ __launch_bounds__(GB) void k_porous_rhs(PorousArgs A) {
                     X[g] = p1 + (dir ? A.ex[g][Gk] * A.tf[0] - p1 : 0.0);
                 }
                 for (int f = 0; f < 3; ++f) {
-                    double m = c_co.tau[f] * (O[f] - X[f]) - porous_x(f) * X[f];
-                    if (f == 0) m += c_co.sst * O[1];
-                    if (f == 1) m += c_co.s * O[2] + c_co.sst * O[0];
-                    if (f == 2) m += c_co.s * O[1];
+                    double m = cf.tau[f] * (O[f] - X[f]) - porous_x(cf, f) * X[f];
+                    if (f == 0) m += cf.sst * O[1];
+                    if (f == 1) m += cf.s * O[2] + cf.sst * O[0];
+                    if (f == 2) m += cf.s * O[1];
                     mv[f] += c_ref.Me[t][la][k] * m;
                     kv[f] += c_ref.Ke[t][la][k] * X[f];
                 }
             }
-            for (int f = 0; f < 3; ++f) r[f] += h2 * mv[f] - c_co.kap[f] * kv[f];
+            for (int f = 0; f < 3; ++f) r[f] += h2 * mv[f] - cf.kap[f] * kv[f];
         };
         if (SPLIT == 1) {
             for_elements(a, b, S.cx, S.cy, elem);
@@ -340,6 +338,7 @@ __global__ __launch_bounds__(GB) void k_porous_finalize(FinalizeArgs F) {
 // band assembly of the constant porous matrices (setup)
 template <typename T>
 __global__ __launch_bounds__(256) void k_porous_assemble(AssembleArgs<T> A) {
+    const Coef &cf = *A.co;           // this context's coefficients
     const SysDesc S = A.sys[blockIdx.x];
     const int nloc = S.lw2 * S.lh2;
     const int ld = 2 * S.bw + 1;
@@ -350,7 +349,7 @@ __global__ __launch_bounds__(256) void k_porous_assemble(AssembleArgs<T> A) {
         const int a = q % S.lw2, bq = q / S.lw2;
         for (int f = 0; f < 3; ++f) {
             T *band = A.band + S.band_off + (long long)f * S.band_size;
-            const double tau = c_co.tau[f], xf = porous_x(f), kap = c_co.kap[f];
+            const double tau = cf.tau[f], xf = porous_x(cf, f), kap = cf.kap[f];
             for_elements(a, bq, S.cx, S.cy, [&](int t, int ci, int cj, int la) {
                 for (int k = 0; k < 6; ++k) {
                     const int qk = (2 * ci + off2a(t, k)) + S.lw2 * (2 * cj + off2b(t, k));
@@ -426,13 +425,14 @@ __device__ __forceinline__ void conv_rows(int t, int la, double h, const double 
 // the per-node work is the latency).
 template <int SPLIT>
 __global__ __launch_bounds__(GB) void k_oseen_rhs(OseenArgs A) {
+    const Coef &cf = *A.co;           // this context's coefficients
     static_assert(GB % SPLIT == 0, "node groups within a block");
     const SysDesc S = A.sys[blockIdx.y];
     if (A.skip && *A.skip) return;
     const int nloc = S.lw2 * S.lh2;
     const int ng = 2 * S.N + 1, ng1 = S.N + 1;
     const double h = S.h, h2 = h * h;
-    const double eta = c_co.eta, edt = c_co.eta / c_co.dt, nue = c_co.nu * c_co.eta;
+    const double eta = cf.eta, edt = cf.eta / cf.dt, nue = cf.nu * cf.eta;
     const int sub = SPLIT > 1 ? (int)(threadIdx.x % SPLIT) : 0;
     for (int qq = blockIdx.x * GB + threadIdx.x; qq < nloc * SPLIT; qq += gridDim.x * GB) {
         const int q = qq / SPLIT;
@@ -471,7 +471,7 @@ __global__ __launch_bounds__(GB) void k_oseen_rhs(OseenArgs A) {
                 P[k] = A.Pp[(S.x0 + ci + off1a(t, k)) + (long long)ng1 * (S.y0 + cj + off1b(t, k))];
             if (cls == 0) {
                 double cW[2], Nz[2];
-                if (c_co.convection) conv_rows(t, la, h, W, Z, true, cW, Nz);
+                if (cf.convection) conv_rows(t, la, h, W, Z, true, cW, Nz);
                 else cW[0] = cW[1] = Nz[0] = Nz[1] = 0.0;
                 for (int c = 0; c < 2; ++c) {
                     double m = 0.0, sv = 0.0, bt = 0.0;
@@ -524,8 +524,8 @@ __global__ __launch_bounds__(GB) void k_oseen_rhs(OseenArgs A) {
                     pg += c_ref.Ge[la][k] * pf;
                     pgx += c_ref.Gxe[la][k] * pf;
                 }
-                rv[0] -= eta * c_co.beta * h * bj + c_co.ctau * pgx;
-                rv[1] += eta / c_co.rho * h * pg;
+                rv[0] -= eta * cf.beta * h * bj + cf.ctau * pgx;
+                rv[1] += eta / cf.rho * h * pg;
             }
         }
         if (cls == 0) {
@@ -541,12 +541,13 @@ __global__ __launch_bounds__(GB) void k_oseen_rhs(OseenArgs A) {
 // rows, added element by element into the cleared band.
 template <typename T>
 __global__ __launch_bounds__(GB) void k_oseen_assemble(OseenApplyArgs<T> A) {
+    const Coef &cf = *A.co;           // this context's coefficients
     const SysDesc S = A.sys[blockIdx.y];
     if (A.skip && *A.skip) return;
     const int nloc = S.lw2 * S.lh2;
     const int ng = 2 * S.N + 1;
     const double h = S.h, h2 = h * h;
-    const double eta = c_co.eta, edt = c_co.eta / c_co.dt, nue = c_co.nu * c_co.eta;
+    const double eta = cf.eta, edt = cf.eta / cf.dt, nue = cf.nu * cf.eta;
     const int ld = 2 * S.bw + 1;
     T *band = A.band + S.band_off;
     auto put = [&](int row, int col, double v) {
@@ -578,7 +579,7 @@ __global__ __launch_bounds__(GB) void k_oseen_assemble(OseenApplyArgs<T> A) {
                     // entries of rows (la, c) against columns (k, d) and pressure v
                     double Nw[2][2][6];     // [c][d][k]
                     for (int c = 0; c < 2; ++c) for (int d = 0; d < 2; ++d) for (int k = 0; k < 6; ++k) Nw[c][d][k] = 0.0;
-                    if (c_co.convection && !A.no_convection) {
+                    if (cf.convection && !A.no_convection) {
                         for (int qq = 0; qq < NQ; ++qq) {
                             double wv[2] = {0, 0}, gw[2][2] = {{0, 0}, {0, 0}};
                             for (int k = 0; k < 6; ++k) {
@@ -686,7 +687,7 @@ __global__ __launch_bounds__(GB) void k_oseen_assemble(OseenApplyArgs<T> A) {
                     const int qk = 2 * ie + k - 2 * S.x0;
                     const int dk = A.dof2[S.node_off + qk];
                     if (dk < 0) continue;
-                    const double v = eta * c_co.beta * h * c_ref.Ge[la][k];
+                    const double v = eta * cf.beta * h * c_ref.Ge[la][k];
                     put(dv, dk, v);
                 }
             }
@@ -708,6 +709,7 @@ int residual_tiles(int cx, int cy) { return ((cx + RT - 1) / RT) * ((cy + RT - 1
 // Apply mode (b null): r = -K x without norms or flags (part null), systems
 // whose conv flag is set skipped.
 __global__ __launch_bounds__(256) void k_oseen_residual_tiled(OseenApplyArgs<double> A) {
+    const Coef &cf = *A.co;           // this context's coefficients
     const SysDesc S = A.sys[blockIdx.y];
     if (A.skip && *A.skip) return;
     if (A.conv && A.conv[blockIdx.y]) return;
@@ -717,7 +719,7 @@ __global__ __launch_bounds__(256) void k_oseen_residual_tiled(OseenApplyArgs<dou
     const int ci_lo = tx * RT - 1, cj_lo = ty * RT - 1;    // first (halo) cell of the tile's triangles
     const int ng = 2 * S.N + 1;
     const double h = S.h, h2 = h * h;
-    const double eta = c_co.eta, edt = c_co.eta / c_co.dt, nue = c_co.nu * c_co.eta;
+    const double eta = cf.eta, edt = cf.eta / cf.dt, nue = cf.nu * cf.eta;
     const double *x = A.x + S.dof_off;
     __shared__ double cv[RT_TRI][6][2];     // velocity rows: (triangle, its node la, component)
     __shared__ double cp[RT_TRI][3];        // pressure rows: (triangle, its vertex)
@@ -744,7 +746,7 @@ __global__ __launch_bounds__(256) void k_oseen_residual_tiled(OseenApplyArgs<dou
             // int (N(W) X)_c phi_la for the six test nodes at once
             double Nz[6][2];
             for (int l = 0; l < 6; ++l) Nz[l][0] = Nz[l][1] = 0.0;
-            if (c_co.convection) {
+            if (cf.convection) {
                 for (int q = 0; q < NQ; ++q) {
                     double wv[2] = {0, 0}, gw[2][2] = {{0, 0}, {0, 0}}, zv[2] = {0, 0}, gz[2][2] = {{0, 0}, {0, 0}};
 #pragma unroll
@@ -822,7 +824,7 @@ __global__ __launch_bounds__(256) void k_oseen_residual_tiled(OseenApplyArgs<dou
                     for (int k = 0; k < 3; ++k) {
                         const int dk = A.dof2[S.node_off + (2 * ie + k - 2 * S.x0)];
                         if (dk < 0) continue;
-                        yv[0] += eta * c_co.beta * h * c_ref.Ge[lg][k] * x[dk];
+                        yv[0] += eta * cf.beta * h * c_ref.Ge[lg][k] * x[dk];
                     }
                 }
             }
@@ -849,6 +851,7 @@ __global__ __launch_bounds__(256) void k_oseen_residual_tiled(OseenApplyArgs<dou
 // once into LDS, then the node threads (Dirichlet values, sources, Gamma
 // terms) add their triangles in the node-thread order.
 __global__ __launch_bounds__(256) void k_oseen_rhs_tiled(OseenArgs A) {
+    const Coef &cf = *A.co;           // this context's coefficients
     const SysDesc S = A.sys[blockIdx.y];
     if (A.skip && *A.skip) return;
     const int ntx = (S.cx + RT - 1) / RT, nty = (S.cy + RT - 1) / RT;
@@ -858,7 +861,7 @@ __global__ __launch_bounds__(256) void k_oseen_rhs_tiled(OseenArgs A) {
     const int nloc = S.lw2 * S.lh2;
     const int ng = 2 * S.N + 1, ng1 = S.N + 1;
     const double h = S.h, h2 = h * h;
-    const double eta = c_co.eta, edt = c_co.eta / c_co.dt, nue = c_co.nu * c_co.eta;
+    const double eta = cf.eta, edt = cf.eta / cf.dt, nue = cf.nu * cf.eta;
     __shared__ double cv[RT_TRI][6][2];
     __shared__ double cp[RT_TRI][3];
     const int tid = threadIdx.x;
@@ -889,7 +892,7 @@ __global__ __launch_bounds__(256) void k_oseen_rhs_tiled(OseenArgs A) {
         // int ((W.grad)W + N(W) Z)_c phi_la for the six test nodes at once
         double CN[6][2];
         for (int l = 0; l < 6; ++l) CN[l][0] = CN[l][1] = 0.0;
-        if (c_co.convection) {
+        if (cf.convection) {
             for (int q = 0; q < NQ; ++q) {
                 double wv[2] = {0, 0}, gw[2][2] = {{0, 0}, {0, 0}}, zv[2] = {0, 0}, gz[2][2] = {{0, 0}, {0, 0}};
 #pragma unroll
@@ -979,8 +982,8 @@ __global__ __launch_bounds__(256) void k_oseen_rhs_tiled(OseenArgs A) {
                     pg += c_ref.Ge[lg][k] * pf;
                     pgx += c_ref.Gxe[lg][k] * pf;
                 }
-                rv[0] -= eta * c_co.beta * h * bj + c_co.ctau * pgx;
-                rv[1] += eta / c_co.rho * h * pg;
+                rv[0] -= eta * cf.beta * h * bj + cf.ctau * pgx;
+                rv[1] += eta / cf.rho * h * pg;
             }
         }
         auto put = [&](long long row, double v) {
@@ -1001,6 +1004,7 @@ __global__ __launch_bounds__(256) void k_oseen_rhs_tiled(OseenArgs A) {
 // add their triangles in the node-thread order.  A converged field is left
 // alone; blocks past a box's tile count only take part in the reductions.
 __global__ __launch_bounds__(256) void k_porous_residual_tiled(ResidualArgs R) {
+    const Coef &cf = *R.co;           // this context's coefficients
     const SysDesc S = R.sys[blockIdx.y];
     if (R.skip && *R.skip) return;
     const int id0 = blockIdx.y * 3;
@@ -1013,7 +1017,7 @@ __global__ __launch_bounds__(256) void k_porous_residual_tiled(ResidualArgs R) {
     const int ci_lo = tx * RT - 1, cj_lo = ty * RT - 1;
     const double h2 = S.h * S.h;
     double cm[3], ck[3];
-    for (int f = 0; f < 3; ++f) { cm[f] = (c_co.tau[f] + porous_x(f)) * h2; ck[f] = c_co.kap[f]; }
+    for (int f = 0; f < 3; ++f) { cm[f] = (cf.tau[f] + porous_x(cf, f)) * h2; ck[f] = cf.kap[f]; }
     const double *x = R.x + S.dof_off, *b = R.b + S.dof_off;
     double *r = R.r + S.dof_off;
     const long long nd = S.ndof;
@@ -1072,6 +1076,7 @@ __global__ __launch_bounds__(256) void k_porous_residual_tiled(ResidualArgs R) {
 // the node threads (Dirichlet values, sources, the Gamma term) add their
 // triangles in the node-thread order.
 __global__ __launch_bounds__(256) void k_porous_rhs_tiled(PorousArgs A) {
+    const Coef &cf = *A.co;           // this context's coefficients
     const SysDesc S = A.sys[blockIdx.y];
     const int ntx = (S.cx + RT - 1) / RT, nty = (S.cy + RT - 1) / RT;
     if ((int)blockIdx.x >= ntx * nty) return;
@@ -1104,10 +1109,10 @@ __global__ __launch_bounds__(256) void k_porous_rhs_tiled(PorousArgs A) {
                 X[g] = p1 + (dir ? A.ex[g][Gk] * A.tf[0] - p1 : 0.0);
             }
             for (int f = 0; f < 3; ++f) {
-                double m = c_co.tau[f] * (O[f] - X[f]) - porous_x(f) * X[f];
-                if (f == 0) m += c_co.sst * O[1];
-                if (f == 1) m += c_co.s * O[2] + c_co.sst * O[0];
-                if (f == 2) m += c_co.s * O[1];
+                double m = cf.tau[f] * (O[f] - X[f]) - porous_x(cf, f) * X[f];
+                if (f == 0) m += cf.sst * O[1];
+                if (f == 1) m += cf.s * O[2] + cf.sst * O[0];
+                if (f == 2) m += cf.s * O[1];
                 M3[f][k] = m;
                 X3[f][k] = X[f];
             }
@@ -1118,7 +1123,7 @@ __global__ __launch_bounds__(256) void k_porous_rhs_tiled(PorousArgs A) {
                 const double me = c_ref.Me[t][l][k], ke = c_ref.Ke[t][l][k];
                 for (int f = 0; f < 3; ++f) { mv[f] += me * M3[f][k]; kv[f] += ke * X3[f][k]; }
             }
-            for (int f = 0; f < 3; ++f) cr[e][l][f] = h2 * mv[f] - c_co.kap[f] * kv[f];
+            for (int f = 0; f < 3; ++f) cr[e][l][f] = h2 * mv[f] - cf.kap[f] * kv[f];
         }
     }
     __syncthreads();
@@ -1175,6 +1180,7 @@ __global__ __launch_bounds__(256) void k_porous_rhs_tiled(PorousArgs A) {
 // kernel's assembly mode.
 template <typename T>
 __global__ __launch_bounds__(64) void k_oseen_rows(OseenApplyArgs<T> A) {
+    const Coef &cf = *A.co;           // this context's coefficients
     const SysDesc S = A.sys[blockIdx.y];
     if (A.skip && *A.skip) return;
     const int q = blockIdx.x;
@@ -1189,7 +1195,7 @@ __global__ __launch_bounds__(64) void k_oseen_rows(OseenApplyArgs<T> A) {
     if (dv < 0 && dp < 0) return;
     const int ng = 2 * S.N + 1, ld = 2 * S.bw + 1;
     const double h = S.h, h2 = h * h;
-    const double eta = c_co.eta, edt = c_co.eta / c_co.dt, nue = c_co.nu * c_co.eta;
+    const double eta = cf.eta, edt = cf.eta / cf.dt, nue = cf.nu * cf.eta;
     extern __shared__ double rows_dyn[];
     T *row = reinterpret_cast<T *>(rows_dyn);            // [3][ld]: rows dv, dv + 1, dp
     for (int j = lane; j < 3 * ld; j += 64) row[j] = (T)0;
@@ -1214,7 +1220,7 @@ __global__ __launch_bounds__(64) void k_oseen_rows(OseenApplyArgs<T> A) {
         if (k < 3) pks = A.dof1[S.vert_off + (ci + off1a(t, k)) + S.lw1 * (cj + off1b(t, k))];
         if (dv >= 0) {
             double Nw[2][2] = {{0, 0}, {0, 0}};
-            if (c_co.convection) {
+            if (cf.convection) {
                 double W[2][6];
                 for (int kk = 0; kk < 6; ++kk) {
                     const long long Gk = (2 * S.x0 + 2 * ci + off2a(t, kk)) + (long long)ng * (2 * S.y0 + 2 * cj + off2b(t, kk));
@@ -1285,7 +1291,7 @@ __global__ __launch_bounds__(64) void k_oseen_rows(OseenApplyArgs<T> A) {
             for (int k = 0; k < 3; ++k) {
                 const int dk = A.dof2[S.node_off + 2 * ie + k - 2 * S.x0];
                 if (dk < 0) continue;
-                add(0, dk, dv, eta * c_co.beta * h * c_ref.Ge[lg][k]);
+                add(0, dk, dv, eta * cf.beta * h * c_ref.Ge[lg][k]);
             }
         }
     }
