@@ -467,6 +467,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-uneven", action="store_true", help="skip the h = 1/256 uneven-batch line")
+    ap.add_argument("--lean", action="store_true",
+                    help="profiling runs: only the timed cfg2 passes and the roofline pass (no graphs, no scheme "
+                         "comparison, no uneven line, no CPU leg)")
     ap.add_argument("--uneven-only", action="store_true",
                     help="run only the h = 1/256 uneven batch (both precisions) and print its object")
     ap.add_argument("--cpu-leg", default=None, help=argparse.SUPPRESS)
@@ -515,14 +518,30 @@ def main():
     ose = sizes[npor:].astype(float)
     lu_bytes = float((ose[:, 0] * (2 * ose[:, 1] + 1) * 4 + (2 * ose[:, 0] * ose[:, 1] + ose[:, 0]) * 4).sum())
 
+    t_start = time.perf_counter()
+
+    def progress(what):
+        print("[bench] %s done, %.1f s" % (what, time.perf_counter() - t_start), file=sys.stderr, flush=True)
+
     mixed = timed_run(cfg, "mixed", args.steps, args.warmup, MAX_IR_MIXED)
+    progress("cfg2 mixed")
     fp64 = timed_run(cfg, "fp64", args.steps, args.warmup, 2)
+    progress("cfg2 fp64")
+    if args.lean:
+        gmix = gf64 = None
+    else:
+        gmix = graph_run(cfg, "mixed", args.steps, args.warmup, MAX_IR_MIXED)
+        gf64 = graph_run(cfg, "fp64", args.steps, args.warmup, 2)
+        progress("cfg2 graphs")
+    # the last cfg2 pass, so that its factorisations are the last launches of
+    # that kernel in a kernel trace of this run (summarize_trace relies on it)
     lu_ms, lu_n = serial_lu_time(cfg, "mixed", MAX_IR_MIXED)
-    gmix = graph_run(cfg, "mixed", args.steps, args.warmup, MAX_IR_MIXED)
-    gf64 = graph_run(cfg, "fp64", args.steps, args.warmup, 2)
-    schemes = scheme_comparison()
+    progress("roofline pass")
+    schemes = None if args.lean else scheme_comparison()
+    if schemes:
+        progress("Algorithm 1 vs 3")
     uneven = None
-    if not args.no_uneven:
+    if not (args.no_uneven or args.lean):
         cfg3 = W.config("cfg3")
         q3 = (cfg3["NH"], cfg3["refine"], cfg3["nsub"], cfg3["overlap"])
         s3 = lib.plan_query(*q3, 5, cuts=W.flat_cuts(cfg3["cuts"])).reshape(-1, 2)
@@ -556,8 +575,9 @@ def main():
     coarse = lib.plan_query(*qargs, 6, cuts=flat)
     roof_ms_mixed, stages_mixed = step_roofline(cfg, sizes, tab, coarse, mixed["stats"], 4, JACOBIAN_EVERY)
     roof_ms_fp64, stages_fp64 = step_roofline(cfg, sizes, tab, coarse, fp64["stats"], 8, JACOBIAN_EVERY)
-    flags = [mixed["stats"]["flags"], fp64["stats"]["flags"], gmix["stats"]["flags"], gf64["stats"]["flags"]]
-    flags += [v["flags"] for k, v in schemes.items() if k.startswith("algorithm")]
+    flags = [r["stats"]["flags"] for r in (mixed, fp64, gmix, gf64) if r]
+    if schemes:
+        flags += [v["flags"] for k, v in schemes.items() if k.startswith("algorithm")]
     if uneven:
         flags += [uneven["mixed"]["flags"], uneven["fp64"]["flags"]]
     line = {
@@ -578,10 +598,11 @@ def main():
                    "local_dofs_per_step": L, "subdomains": int(len(sizes)),
                    "max_halfbandwidth": int(sizes[:, 1].max())},
         "fp64": {"value": rate(fp64["ms_per_step"]), "ms_per_step": fp64["ms_per_step"], "dtype": "f64"},
-        "graphs": {"mixed": {"value": rate(gmix["ms_per_step"]), "ms_per_step": gmix["ms_per_step"]},
-                   "fp64": {"value": rate(gf64["ms_per_step"]), "ms_per_step": gf64["ms_per_step"]},
-                   "note": "every step's launch sequences replayed as HIP graphs (lp_options.graphs = 1); "
-                           "value and ms_per_step above are direct launches"},
+        "graphs": None if gmix is None else {
+            "mixed": {"value": rate(gmix["ms_per_step"]), "ms_per_step": gmix["ms_per_step"]},
+            "fp64": {"value": rate(gf64["ms_per_step"]), "ms_per_step": gf64["ms_per_step"]},
+            "note": "every step's launch sequences replayed as HIP graphs (lp_options.graphs = 1); "
+                    "value and ms_per_step above are direct launches"},
         "stages_ms": {"mixed": mixed["stages_ms"], "fp64": fp64["stages_ms"]},
         "refinement": {"scope": "every step of the run (warmup + timed), sticky",
                        "mixed_sweeps_max": mixed["stats"]["ir_sweeps_max"], "mixed_max_sweeps": MAX_IR_MIXED,
@@ -610,10 +631,11 @@ def main():
                               "fp64": {"roofline_ms": roof_ms_fp64, "measured_ms": fp64["ms_per_step"],
                                        "frac": roof_ms_fp64 / fp64["ms_per_step"], "stages": stages_fp64}}},
     }
-    line["algorithm1_vs_3"] = schemes
+    if schemes:
+        line["algorithm1_vs_3"] = schemes
     if uneven:
         line["uneven_batch"] = uneven
-    if not args.no_cpu:
+    if not (args.no_cpu or args.lean):
         cores, model = host_cores()
         pool = max(1, min(CPU_POOL_MAX, cores))
         secs1, ref = run_cpu_leg(1)
