@@ -16,8 +16,8 @@ Layout
   scheme   Algorithm 3: coarse decoupled step (Step 1), local corrections
            (Step 3), partition-of-unity correction (Step 4); Algorithm 1 on T_h
   fe3, mesh3, forms3, mms3, scheme3
-           the same in 3D (Kuhn tetrahedra, Example 2 reflected): Algorithm 1,
-           exact prolongation, the Step 2 extension rule
+           the same in 3D (Kuhn tetrahedra, Example 2 reflected): Algorithms 1
+           and 3, exact prolongation, the Step 2 extension rule
 
 Readings of points where the paper is silent are listed in ``scheme.py``'s
 docstring; every oracle function cites the passage it follows.

@@ -151,6 +151,16 @@ class Subdomain3:
         A, B, C = A.ravel(), B.ravel(), C.ravel()
         return A + mesh.n1 * (B + mesh.n1 * C), A, B, C
 
+    def artificial_p1(self, I, J, K):
+        """Mask of P1 vertices (region coordinates I, J, K) on an artificial face."""
+        art = np.zeros(I.shape, dtype=bool)
+        for lo, hi, X in ((self.x0, self.x1, I), (self.y0, self.y1, J), (self.z0, self.z1, K)):
+            if lo > 0:
+                art |= X == lo
+            if hi < self.N:
+                art |= X == hi
+        return art
+
     def classify_p2(self, mesh):
         """Per local P2 node: 0 free, 1 physical Dirichlet, 2 artificial.
         Physical boundary = region boundary minus Gamma; artificial = the

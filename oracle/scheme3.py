@@ -1,4 +1,5 @@
-"""Algorithm 1 (Section 3.3, partitioned time stepping) in 3D, plain FP64 with
+"""Algorithm 1 (Section 3.3, partitioned time stepping) and Algorithm 3 (the
+two-grid local parallel method, Section 5) in 3D, plain FP64 with
 scipy.sparse direct solves, on the unit-cube regions of mesh3 (porous
 (0,1)^3 below the conduit (0,1)^2 x (1,2), Gamma at z = 1, n_c = (0,0,-1)).
 
@@ -15,7 +16,8 @@ import scipy.sparse as sps
 
 from . import forms3
 from .fe3 import p1_basis3, p2_basis3
-from .mesh3 import RegionMesh3, POROUS, CONDUIT, PERMS
+from .mesh import owner_counts
+from .mesh3 import RegionMesh3, POROUS, CONDUIT, PERMS, make_subdomains3
 from .mms3 import MMS3
 from .scheme import Coefs, _solve_dirichlet
 
@@ -175,3 +177,235 @@ def prolong_p1_3d(coarse, fine, vec):
     eid, ref = _locate3(coarse, X)
     val, _ = p1_basis3(ref)
     return np.einsum("na,na->n", val, vec[coarse.el_p1[eid]])
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 3, Steps 2-4, in 3D
+# ---------------------------------------------------------------------------
+def prolong_u_3d(coarse, fine, vec):
+    """Component-blocked P2 velocity from the coarse to the fine lattice."""
+    n2c = coarse.n2 ** 3
+    return np.concatenate([prolong_p2_3d(coarse, fine, vec[c * n2c:(c + 1) * n2c]) for c in range(3)])
+
+
+def conduit_gamma_rhs3_box(gp, PF_n, co, G, Gx, Gy):
+    """conduit_gamma_rhs3 with the Gamma forms of one box's interface triangles."""
+    n2 = gp.mc.n2 ** 3
+    pg = gp.T_pc @ PF_n
+    r = np.zeros(3 * n2)
+    r[2 * n2:] = co.eta / co.rho * (G @ pg)
+    r[:n2] = -co.ctau * (Gx @ pg)
+    r[n2:2 * n2] = -co.ctau * (Gy @ pg)
+    return r
+
+
+class Oracle3D:
+    """Algorithm 3 in 3D, the same steps and readings as the 2D oracle
+    (Oracle2D) on the Kuhn meshes: init() once, then per time step
+    coarse_step() and local_step(); merged() and coarse() read results.
+    cuts: {(region, axis): [0, ..., Nh]} for axes 0, 1, 2 (x, y, vertical),
+    overlap in fine cells (an int or a per-axis triple)."""
+
+    def __init__(self, NH, Nh, cuts, overlap, prm, dt, convection=True):
+        assert Nh % NH == 0
+        self.co = Coefs(prm, dt)
+        self.mms = MMS3(prm)
+        self.cg = GridProblem3(NH, self.co)
+        self.fg = GridProblem3(Nh, self.co)
+        self.subs = make_subdomains3(Nh, cuts, overlap)
+        self.cuts = cuts
+        self.convection = convection
+        self.n = 0
+        self._cache = {}
+
+    def t(self, n):
+        return n * self.co.dt
+
+    def _fine_mesh(self, region):
+        return self.fg.mp if region == POROUS else self.fg.mc
+
+    def init(self):
+        """Nodal interpolants at t = 0 on both grids; e_j^0 = I_h x_0 - Pi_h x_H^0
+        on each Omega_j, zero on artificial faces (pressure corrections zero)."""
+        cg, fg, mms = self.cg, self.fg, self.mms
+        self.P = [interp(cg.mp, mms, nm, 0.0) for nm in ("pF", "pf", "pm")]
+        self.U = np.concatenate([interp(cg.mc, mms, "u%d" % (c + 1), 0.0) for c in range(3)])
+        self.Pc = interp(cg.mc, mms, "p", 0.0, p1=True)
+        self.P_old, self.U_old = [p.copy() for p in self.P], self.U.copy()
+        fineP = [interp(fg.mp, mms, nm, 0.0) for nm in ("pF", "pf", "pm")]
+        fineU = np.concatenate([interp(fg.mc, mms, "u%d" % (c + 1), 0.0) for c in range(3)])
+        ProlP = [prolong_p2_3d(cg.mp, fg.mp, p) for p in self.P]
+        ProlU = prolong_u_3d(cg.mc, fg.mc, self.U)
+        n2f = fg.mc.n2 ** 3
+        self.e = {}
+        for sd in self.subs:
+            mesh = self._fine_mesh(sd.region)
+            nodes = sd.p2_nodes(mesh)[0]
+            cls = sd.classify_p2(mesh)
+            if sd.region == POROUS:
+                vals = [np.where(cls == 2, 0.0, fineP[i][nodes] - ProlP[i][nodes]) for i in range(3)]
+            else:
+                vals = [np.where(cls == 2, 0.0, fineU[c * n2f + nodes] - ProlU[c * n2f + nodes]) for c in range(3)]
+                vals.append(np.zeros(len(sd.p1_nodes(mesh)[0])))
+            self.e[sd.sid] = vals
+        self.n = 0
+
+    # -- Step 1
+    def coarse_step(self):
+        t1 = self.t(self.n + 1)
+        self.P_old, self.U_old = [p.copy() for p in self.P], self.U.copy()
+        P_new = porous_step3(self.cg, self.mms, self.P, self.U, t1)
+        U_new, P_c, self.newton_its = ns_step3(self.cg, self.mms, self.U, self.Pc, self.P[0], t1,
+                                               convection=self.convection)
+        self.P, self.U, self.Pc = P_new, U_new, P_c
+
+    def _box_elements(self, mesh, sd):
+        return mesh.elements_in_box(sd.x0, sd.x1, sd.y0, sd.y1, sd.z0, sd.z1)
+
+    # -- Step 3 (1): Eqs. (5.5)-(5.7)
+    def local_porous(self, sd, pro):
+        co, mesh, mms = self.co, self.fg.mp, self.mms
+        t1 = self.t(self.n + 1)
+        key = ("p", sd.sid)
+        if key not in self._cache:
+            E = self._box_elements(mesh, sd)
+            M, K = forms3.p2_mass_stiff(mesh, E)
+            G = forms3.gamma_forms(mesh, sd.x0, sd.x1, sd.y0, sd.y1)[0] if sd.touches_gamma else None
+            self._cache[key] = (E, M, K, G)
+        E, M, K, G = self._cache[key]
+        nodes = sd.p2_nodes(mesh)[0]
+        cls = sd.classify_p2(mesh)
+        nn = mesh.n2 ** 3
+        PF1, Pf1, Pm1 = pro["P1"]
+        PF0, Pf0, Pm0 = pro["P0"]
+        Q = [forms3.load_p2(mesh, E, lambda X, nm=nm: mms(nm, X, t1)) for nm in ("qF", "qf", "qm")]
+
+        def full(loc):
+            v = np.zeros(nn)
+            v[nodes] = loc
+            return v
+        eF, ef, em = [full(v) for v in self.e[sd.sid]]
+        gam = np.zeros(nn)
+        if G is not None:
+            n2c = self.fg.mc.n2 ** 3
+            gam = -G @ (self.fg.T_cp @ pro["U0"][2 * n2c:])     # + <u_cH^n . n_c, v_F>, v . n_c = -v_z
+        rhs = [Q[0] - (co.tau[0] * (M @ (PF1 - PF0)) + co.kap[0] * (K @ PF1) + co.sst * (M @ (PF1 - Pf0)))
+               + gam + co.tau[0] * (M @ eF) + co.sst * (M @ ef),
+               Q[1] - (co.tau[1] * (M @ (Pf1 - Pf0)) + co.kap[1] * (K @ Pf1) + co.s * (M @ (Pf1 - Pm0))
+                       + co.sst * (M @ (Pf1 - PF0)))
+               + co.tau[1] * (M @ ef) + co.s * (M @ em) + co.sst * (M @ eF),
+               Q[2] - (co.tau[2] * (M @ (Pm1 - Pm0)) + co.kap[2] * (K @ Pm1) + co.s * (M @ (Pm1 - Pf0)))
+               + co.tau[2] * (M @ em) + co.s * (M @ ef)]
+        A = [(co.tau[0] + co.sst) * M + co.kap[0] * K,
+             (co.tau[1] + co.s + co.sst) * M + co.kap[1] * K,
+             (co.tau[2] + co.s) * M + co.kap[2] * K]
+        xyz = mesh.p2_coords()[nodes]
+        out = []
+        for i, nm in enumerate(("pF", "pf", "pm")):
+            dvals = np.where(cls == 1, mms(nm, xyz, t1) - pro["P1"][i][nodes], 0.0)
+            out.append(_solve_dirichlet(A[i][nodes][:, nodes].tocsr(), rhs[i][nodes], cls != 0, dvals))
+        return out
+
+    # -- Step 3 (2): Eq. (5.8)
+    def local_conduit(self, sd, pro):
+        co, mesh, mms = self.co, self.fg.mc, self.mms
+        t1 = self.t(self.n + 1)
+        E = self._box_elements(mesh, sd)
+        Mv, S, Bq = forms3.stokes_blocks(mesh, E)
+        n2 = mesh.n2 ** 3
+        W1, W0, Pp = pro["U1"], pro["U0"], pro["Pc1"]
+        if self.convection:
+            cv, Nm = forms3.convection(mesh, E, W1)
+        else:
+            cv, Nm = np.zeros(3 * n2), sps.csr_matrix((3 * n2, 3 * n2))
+        if sd.touches_gamma:
+            G, Gx, Gy = forms3.gamma_forms(mesh, sd.x0, sd.x1, sd.y0, sd.y1)
+            Gblk = sps.block_diag([G, G, sps.csr_matrix((n2, n2))]).tocsr()
+            gam = conduit_gamma_rhs3_box(self.fg, pro["P0"][0], co, G, Gx, Gy)
+        else:
+            Gblk = sps.csr_matrix((3 * n2, 3 * n2))
+            gam = np.zeros(3 * n2)
+        F = np.concatenate([forms3.load_p2(mesh, E, lambda X, c=c: mms("f%d" % (c + 1), X, t1)) for c in range(3)])
+        Avis = co.nu * co.eta * S + co.eta * co.beta * Gblk
+        A = (co.eta / co.dt) * Mv + Avis + co.eta * Nm
+        nodes = sd.p2_nodes(mesh)[0]
+        pn, I, J, K = sd.p1_nodes(mesh)
+        cls = sd.classify_p2(mesh)
+        pfix = sd.artificial_p1(I, J, K)
+        en = np.zeros(3 * n2)
+        for c in range(3):
+            en[c * n2 + nodes] = self.e[sd.sid][c]
+        rv = co.eta * F - ((co.eta / co.dt) * (Mv @ (W1 - W0)) + Avis @ W1
+                           - co.eta * (Bq.T @ Pp) + co.eta * cv) + gam + (co.eta / co.dt) * (Mv @ en)
+        rq = -co.eta * (Bq @ W1)
+        vi = np.concatenate([c * n2 + nodes for c in range(3)])
+        Kmat = sps.bmat([[A[vi][:, vi], -co.eta * Bq.T[vi][:, pn]],
+                         [co.eta * Bq[pn][:, vi], None]]).tocsr()
+        rhs = np.concatenate([rv[vi], rq[pn]])
+        xyz = mesh.p2_coords()[nodes]
+        dv = [np.where(cls == 1, mms("u%d" % (c + 1), xyz, t1) - W1[c * n2 + nodes], 0.0) for c in range(3)]
+        dmask = np.concatenate([cls != 0, cls != 0, cls != 0, pfix])
+        dvals = np.concatenate(dv + [np.zeros(len(pn))])
+        z = _solve_dirichlet(Kmat, rhs, dmask, dvals)
+        nv = len(nodes)
+        return [z[:nv], z[nv:2 * nv], z[2 * nv:3 * nv], z[3 * nv:]]
+
+    # -- Steps 3 and 4
+    def prolonged(self):
+        cg, fg = self.cg, self.fg
+        return dict(P1=[prolong_p2_3d(cg.mp, fg.mp, p) for p in self.P],
+                    P0=[prolong_p2_3d(cg.mp, fg.mp, p) for p in self.P_old],
+                    U1=prolong_u_3d(cg.mc, fg.mc, self.U),
+                    U0=prolong_u_3d(cg.mc, fg.mc, self.U_old),
+                    Pc1=prolong_p1_3d(cg.mc, fg.mc, self.Pc))
+
+    def local_step(self):
+        pro = self.prolonged()
+        self.e = {sd.sid: (self.local_porous(sd, pro) if sd.region == POROUS else self.local_conduit(sd, pro))
+                  for sd in self.subs}
+        self.n += 1
+        self._pro = pro
+        return pro
+
+    def merged(self):
+        """Step 4 with the partition-of-unity weights of the 2D oracle, one
+        factor per axis: w = 1 / (owners along x) (owners along y) (owners
+        along the vertical) of the closed cores."""
+        pro = self._pro
+        out = {}
+        for region in (POROUS, CONDUIT):
+            mesh = self._fine_mesh(region)
+            a = np.arange(mesh.n2)
+            i1 = np.arange(mesh.n1)
+            w2 = [1.0 / owner_counts(self.cuts[(region, ax)], a) for ax in range(3)]
+            w1 = [1.0 / owner_counts(self.cuts[(region, ax)], 2 * i1) for ax in range(3)]
+            n2 = mesh.n2 ** 3
+            if region == POROUS:
+                acc = [p.copy() for p in pro["P1"]]
+            else:
+                acc = [pro["U1"][c * n2:(c + 1) * n2].copy() for c in range(3)] + [pro["Pc1"].copy()]
+            for sd in self.subs:
+                if sd.region != region:
+                    continue
+                d = sd.d
+                nodes, A, B, C = sd.p2_nodes(mesh)
+                inD = ((A >= 2 * d[0]) & (A <= 2 * d[1]) & (B >= 2 * d[2]) & (B <= 2 * d[3])
+                       & (C >= 2 * d[4]) & (C <= 2 * d[5]))
+                w = w2[0][A] * w2[1][B] * w2[2][C]
+                nv = 3
+                for k in range(nv):
+                    acc[k][nodes[inD]] += w[inD] * self.e[sd.sid][k][inD]
+                if region == CONDUIT:
+                    pn, I, J, K = sd.p1_nodes(mesh)
+                    inDp = ((I >= d[0]) & (I <= d[1]) & (J >= d[2]) & (J <= d[3]) & (K >= d[4]) & (K <= d[5]))
+                    wp = w1[0][I] * w1[1][J] * w1[2][K]
+                    acc[3][pn[inDp]] += wp[inDp] * self.e[sd.sid][3][inDp]
+            if region == POROUS:
+                out["pF"], out["pf"], out["pm"] = acc
+            else:
+                out["u"] = np.concatenate(acc[:3])
+                out["p"] = acc[3]
+        return out
+
+    def coarse(self):
+        return dict(pF=self.P[0], pf=self.P[1], pm=self.P[2], u=self.U, p=self.Pc)

@@ -363,3 +363,107 @@ def test_algorithm1_3d_rates():
         r1 = np.log2(errs[0][nm][1] / errs[1][nm][1])
         assert r0 > 2.5 and r1 > 1.8, (nm, r0, r1, errs)
     assert np.log2(errs[0]["p"][0] / errs[1]["p"][0]) > 2.0, errs
+
+
+# --------------------------------------------------------------------------
+# Algorithm 3 in 3D (Steps 1-4 on the Kuhn meshes)
+# --------------------------------------------------------------------------
+def _cuts3(N, n):
+    from oracle.mesh3 import uniform_cuts
+    return {(r, a): uniform_cuts(N, n) for r in (POROUS, CONDUIT) for a in range(3)}
+
+
+def test_algorithm3_3d_h_equals_H_gives_zero_corrections():
+    """H = h: the coarse solution already solves the fine residual equations
+    of Step 3, so every correction vanishes and the merged field is
+    Algorithm 1 on that grid."""
+    from oracle.scheme3 import Oracle3D
+    prm = example2_params()
+    o = Oracle3D(2, 2, _cuts3(2, 2), 1, prm, 0.05)
+    o.init()
+    for _ in range(2):
+        o.coarse_step()
+        o.local_step()
+    assert max(np.abs(v).max() for vs in o.e.values() for v in vs) < 1e-11
+    _, f = algorithm1_3d(2, prm, 0.05, 2)
+    m = o.merged()
+    for k in f:
+        assert np.abs(m[k] - f[k]).max() < 1e-11, k
+
+
+def test_algorithm3_3d_merge_reproduces_a_fine_field():
+    """Step 4 in 3D: with every correction set to I_h x - Pi_h x_H on its
+    box, the merged field is x at every fine P2 and P1 node (uneven cores, a
+    different overlap per axis, seams and corners where up to 8 cores meet)."""
+    from oracle.scheme3 import Oracle3D
+    cuts = {(r, a): [0, 1, 4] for r in (POROUS, CONDUIT) for a in range(3)}
+    o = Oracle3D(1, 4, cuts, (1, 0, 2), example2_params(), 0.05)
+    o.init()
+    o._pro = pro = o.prolonged()
+    rng = np.random.default_rng(3)
+    mp, mc = o.fg.mp, o.fg.mc
+    n2 = mc.n2 ** 3
+    X = {"pF": rng.standard_normal(n2), "pf": rng.standard_normal(n2), "pm": rng.standard_normal(n2),
+         "u": rng.standard_normal(3 * n2), "p": rng.standard_normal(mc.n1 ** 3)}
+    for sd in o.subs:
+        if sd.region == POROUS:
+            nodes = sd.p2_nodes(mp)[0]
+            o.e[sd.sid] = [X[nm][nodes] - pro["P1"][i][nodes] for i, nm in enumerate(("pF", "pf", "pm"))]
+        else:
+            nodes, pn = sd.p2_nodes(mc)[0], sd.p1_nodes(mc)[0]
+            o.e[sd.sid] = ([X["u"][c * n2 + nodes] - pro["U1"][c * n2 + nodes] for c in range(3)]
+                           + [X["p"][pn] - pro["Pc1"][pn]])
+    m = o.merged()
+    for k in X:
+        assert np.abs(m[k] - X[k]).max() < 1e-12, k
+
+
+def test_algorithm3_3d_single_subdomain_equals_global_fine_solve():
+    """One subdomain per region (BF2) in 3D: the merged result equals an
+    independently written global fine solve: the porous step of Algorithm 1
+    on T_h fed by the prolonged coarse u_cH^n on Gamma, and the Oseen problem
+    linearised about the prolonged u_cH^{n+1} (one Newton step of the fine
+    Navier-Stokes equations) with the coarse p_FH^n on Gamma."""
+    import scipy.sparse as sps
+    from oracle.scheme import _solve_dirichlet
+    from oracle.scheme3 import Oracle3D, conduit_gamma_rhs3, interp
+    NH, Nh, dt = 2, 4, 0.05
+    prm = dict(example2_params(), nu=0.1, k=[0.5, 0.2, 0.01], sigma=3.0)
+    cuts = {(r, a): [0, Nh] for r in (POROUS, CONDUIT) for a in range(3)}
+    o = Oracle3D(NH, Nh, cuts, 0, prm, dt)
+    o.init()
+    mms, fg, co = o.mms, o.fg, o.co
+    mp, mc = fg.mp, fg.mc
+    n2 = mc.n2 ** 3
+    E = np.arange(6 * Nh ** 3)
+    xp, xc = mp.p2_coords(), mc.p2_coords()
+    X = [interp(mp, mms, nm, 0.0) for nm in ("pF", "pf", "pm")]
+    u = np.concatenate([interp(mc, mms, "u%d" % (c + 1), 0.0) for c in range(3)])
+    Gblk = sps.block_diag([fg.Gc, fg.Gc, sps.csr_matrix((n2, n2))]).tocsr()
+    for n in range(2):
+        t1 = (n + 1) * dt
+        o.coarse_step()
+        o.local_step()
+        pro = o._pro
+        M, K = fg.M, fg.K
+        Q = [forms3.load_p2(mp, E, lambda Y, nm=nm: mms(nm, Y, t1)) for nm in ("qF", "qf", "qm")]
+        gam = -fg.Gp @ (fg.T_cp @ pro["U0"][2 * n2:])
+        A = [(co.tau[0] + co.sst) * M + co.kap[0] * K, (co.tau[1] + co.s + co.sst) * M + co.kap[1] * K,
+             (co.tau[2] + co.s) * M + co.kap[2] * K]
+        rhs = [Q[0] + co.tau[0] * (M @ X[0]) + co.sst * (M @ X[1]) + gam,
+               Q[1] + co.tau[1] * (M @ X[1]) + co.s * (M @ X[2]) + co.sst * (M @ X[0]),
+               Q[2] + co.tau[2] * (M @ X[2]) + co.s * (M @ X[1])]
+        X = [_solve_dirichlet(A[i], rhs[i], fg.dir_p, mms(nm, xp, t1)) for i, nm in enumerate(("pF", "pf", "pm"))]
+        cv, Nm = forms3.convection(mc, E, pro["U1"])
+        F = np.concatenate([forms3.load_p2(mc, E, lambda Y, c=c: mms("f%d" % (c + 1), Y, t1)) for c in range(3)])
+        Aop = (co.eta / co.dt) * fg.Mv + co.nu * co.eta * fg.S + co.eta * co.beta * Gblk + co.eta * Nm
+        J = sps.bmat([[Aop, -co.eta * fg.Bq.T], [co.eta * fg.Bq, None]]).tocsr()
+        rv = co.eta * F + (co.eta / co.dt) * (fg.Mv @ u) + co.eta * cv + conduit_gamma_rhs3(fg, pro["P0"][0], co)
+        rq = np.zeros(fg.Bq.shape[0])
+        g = np.concatenate([mms("u%d" % (c + 1), xc, t1) for c in range(3)] + [np.zeros(len(rq))])
+        dm = np.concatenate([fg.dir_c] * 3 + [np.zeros(len(rq), bool)])
+        z = _solve_dirichlet(J, np.concatenate([rv, rq]), dm, g)
+        u, p = z[:3 * n2], z[3 * n2:]
+        m = o.merged()
+        for k, ref in dict(pF=X[0], pf=X[1], pm=X[2], u=u, p=p).items():
+            assert np.abs(m[k] - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max()), (n, k)
