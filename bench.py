@@ -19,6 +19,9 @@ Prints ONE JSON line.  Fields beyond the driver's contract:
                   mixed and FP64 paths
   cpu_baseline    the CPU oracle on the host: a process pool over subdomains
                   on the host cores (and one thread), 2 steps of the workload
+  ensemble        32 seeded parameter samples on the same geometry, all
+                  samples' systems in every launch (lp_options.nsamples),
+                  against the same samples run one context after another
 """
 import argparse
 import hashlib
@@ -39,6 +42,12 @@ PEAK_HBM_GBS = 8000.0           # MI355X HBM3E
 CPU_STEPS = 2
 CPU_POOL_MAX = 16               # host cores given to one GPU's share
 SERIAL_STEPS = 8                # roofline pass: LU launches timed on an uncontended stream
+ENSEMBLE_SAMPLES, ENSEMBLE_WARMUP, ENSEMBLE_STEPS = 32, 2, 8
+# the ensemble's parameters span decades (viscosity to 1e-3, permeabilities to
+# 1e-5): it runs with the library's default iteration limits, a Jacobian every
+# Newton iteration
+ENSEMBLE_MAX_IR = {"mixed": 8, "fp64": 4}
+ENSEMBLE_MAX_NEWTON, ENSEMBLE_JACOBIAN_EVERY = 16, 1
 # the instantiation the launcher picks for half-bandwidths 129..160 in FP32
 LU_KERNEL = "k_band_lu_la<float,11> (local Oseen blocked band LU with one-panel lookahead, FP32, MFMA 16x16x4)"
 LU_NAME = "k_band_lu_la<float,11>"
@@ -232,6 +241,85 @@ def serial_lu_time(cfg, precision, max_ir, steps=SERIAL_STEPS):
     ms, n = g.timing()["ose_lu"]
     g.close()
     return ms / max(n, 1), n
+
+
+def ensemble_run(L, lu_bytes):
+    """The parameter ensemble (ENSEMBLE_SAMPLES seeded samples on the cfg2
+    geometry, dt = 0.01, 10 steps): one context holding every sample, so that
+    each launch covers all samples' systems, against the same samples stepped
+    one context after another (each context's setup outside its timed steps).
+    Also the ensemble's local Oseen factorisation timed on an uncontended
+    stream, as the roofline pass does for one sample."""
+    import torch
+    from paper_2311_05170_amd import workloads as W
+    from paper_2311_05170_amd.lib import LocalParallel
+    cfg = W.ensemble(ENSEMBLE_SAMPLES)
+    samples = cfg["samples"]
+    S = len(samples)
+
+    def build(plist, prec):
+        return LocalParallel(cfg["NH"], cfg["refine"], cfg["nsub"], cfg["overlap"], plist[0], cfg["dt"],
+                             cuts=W.flat_cuts(cfg["cuts"]), precision=prec, max_ir=ENSEMBLE_MAX_IR[prec],
+                             max_newton=ENSEMBLE_MAX_NEWTON, jacobian_every=ENSEMBLE_JACOBIAN_EVERY, samples=plist)
+
+    def clock(g):
+        for _ in range(ENSEMBLE_WARMUP):
+            g.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(ENSEMBLE_STEPS):
+            g.step()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / ENSEMBLE_STEPS
+
+    out = {"workload": "2D Example-1 MMS on the cfg2 geometry (H=1/8, h=1/64, 8x8 porous + 8x8 conduit "
+                       "subdomains, overlap 1/16), dt=0.01, %d SplitMix64 seed-5 samples: nu logU[1e-3,1], "
+                       "k_F, k_f, k_m logU[1e-5,1], sigma*, sigma logU[0.01,10]" % S,
+           "samples": S, "steps": ENSEMBLE_STEPS, "warmup": ENSEMBLE_WARMUP,
+           "max_ir": ENSEMBLE_MAX_IR, "max_newton": ENSEMBLE_MAX_NEWTON, "jacobian_every": ENSEMBLE_JACOBIAN_EVERY,
+           "local_dofs_per_step": S * L}
+    for prec in ("mixed", "fp64"):
+        t0 = time.perf_counter()
+        g = build(samples, prec)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        ms = clock(g)
+        st = g.stats()
+        g.close()
+        seq = 0.0
+        for q in samples:
+            h = build([q], prec)
+            seq += clock(h)
+            h.close()
+        out[prec] = {"value": S * L / (ms * 1e-3), "ms_per_step": ms, "setup_s": setup_s,
+                     "sequential_value": S * L / (seq * 1e-3), "sequential_ms_per_step": seq,
+                     "speedup_vs_sequential": seq / ms,
+                     "flags": st["flags"], "newton_its_max": st["newton_its_max"],
+                     "sweeps_max": st["ir_sweeps_max"], "relres_max": st["ir_relres_max"],
+                     "lu_growth_local": st["lu_growth_local"], "lu_pivot_local": st["lu_pivot_local"]}
+    os.environ["LP_SERIAL"] = "1"
+    try:
+        g = build(samples, "mixed")
+    finally:
+        del os.environ["LP_SERIAL"]
+    for _ in range(2):
+        g.step()
+    torch.cuda.synchronize()
+    g.set_timing(["ose_lu"])
+    for _ in range(4):
+        g.step()
+    lms, n = g.timing()["ose_lu"]
+    g.close()
+    lms /= max(n, 1)
+    gbs = S * lu_bytes / (lms * 1e-3) / 1e9
+    out["lu_roofline"] = {"kernel": LU_NAME, "bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                          "frac": gbs / PEAK_HBM_GBS, "bytes_per_launch": S * lu_bytes, "avg_launch_ms": lms,
+                          "launches": n, "systems_per_launch": S * cfg["nsub"][0] * cfg["nsub"][1],
+                          "timing": "HIP events around each launch, every stage on one stream (LP_SERIAL=1)"}
+    out["flags_meaning"] = ("bit 0 refinement above ir_tol, bit 1 coarse Newton above newton_tol, "
+                            "bit 2 pivot monitor: a factorisation without pivoting exceeded its growth or "
+                            "small-pivot limit (the refinement test still decides the result)")
+    return out
 
 
 def step_roofline(cfg, sizes, tab, coarse, stats, T, jacobian_every):
@@ -467,6 +555,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-uneven", action="store_true", help="skip the h = 1/256 uneven-batch line")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the parameter-ensemble object")
+    ap.add_argument("--ensemble-only", action="store_true",
+                    help="run only the parameter ensemble and print its object")
     ap.add_argument("--lean", action="store_true",
                     help="profiling runs: only the timed cfg2 passes and the roofline pass (no graphs, no scheme "
                          "comparison, no uneven line, no CPU leg)")
@@ -518,6 +609,9 @@ def main():
     ose = sizes[npor:].astype(float)
     lu_bytes = float((ose[:, 0] * (2 * ose[:, 1] + 1) * 4 + (2 * ose[:, 0] * ose[:, 1] + ose[:, 0]) * 4).sum())
 
+    if args.ensemble_only:
+        print(json.dumps({"ensemble": ensemble_run(L, lu_bytes)}), flush=True)
+        return
     t_start = time.perf_counter()
 
     def progress(what):
@@ -540,6 +634,9 @@ def main():
     schemes = None if args.lean else scheme_comparison()
     if schemes:
         progress("Algorithm 1 vs 3")
+    ens = None if (args.lean or args.no_ensemble) else ensemble_run(L, lu_bytes)
+    if ens:
+        progress("ensemble")
     uneven = None
     if not (args.no_uneven or args.lean):
         cfg3 = W.config("cfg3")
@@ -635,6 +732,8 @@ def main():
         line["algorithm1_vs_3"] = schemes
     if uneven:
         line["uneven_batch"] = uneven
+    if ens:
+        line["ensemble"] = ens
     if not (args.no_cpu or args.lean):
         cores, model = host_cores()
         pool = max(1, min(CPU_POOL_MAX, cores))

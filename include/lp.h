@@ -138,7 +138,12 @@ typedef struct {
     int32_t krylov_cycles;   /* GMRES cycles (refinement sweeps) of the Krylov path per local
                                 step, 1..max_ir; 0: max_ir */
     int32_t nsamples;        /* parameter samples advanced together (lp_setup's samples[]);
-                                0 or 1: one sample.  More than one: LP_ERR_UNSUPPORTED */
+                                0 or 1: one sample.  Several share mesh, partition and dt;
+                                every launch then covers all samples' systems, and each
+                                sample's fields are what a context of that sample alone
+                                computes, bit for bit.  They need the dense local path
+                                (LP_DENSE, or LP_AUTO where the band fits), LP_TWO_GRID,
+                                graphs = 0 and autotune = 0 (else LP_ERR_UNSUPPORTED) */
     int32_t autotune;        /* 1: at the end of lp_setup, time the local Oseen solves on this
                                 run's own systems: the band factorisation kernel (three
                                 variants) and the band solve prefetch depth are set to the
@@ -176,10 +181,10 @@ typedef struct {
 
 typedef struct {
     int64_t step;            /* completed local steps */
-    int64_t n_porous, n_conduit;      /* subdomains */
-    int64_t local_dofs;      /* unknowns solved per local step (all systems) */
+    int64_t n_porous, n_conduit;      /* subdomains (of one sample) */
+    int64_t local_dofs;      /* unknowns solved per local step (all systems of all samples) */
     int64_t max_bw;          /* largest half-bandwidth of a local system */
-    int32_t newton_its;      /* Newton iterations of the last coarse step */
+    int32_t newton_its;      /* Newton iterations of the last coarse step (most over samples) */
     int32_t ir_sweeps;       /* refinement sweeps of the last local step (max over systems) */
     double ir_relres;        /* largest final relative residual of the last local step */
     int32_t flags;           /* sticky over the whole run:
@@ -215,10 +220,12 @@ typedef struct {
  * Omega_j (zero on artificial faces); factor the constant local porous
  * matrices.  Synchronises `stream` before returning.
  * samples: opt->nsamples parameter sets (one when nsamples is 0 or 1); every
- * sample shares mesh and partition and carries its own Section 2 parameters.
+ * sample shares mesh, partition and dt and carries its own Section 2
+ * parameters.
  * Errors: LP_ERR_ARG (dim != 2, n_coarse < 1, refine < 1, overlap < 0, bad cuts,
- * non-positive dt or parameters, unknown option values), LP_ERR_UNSUPPORTED
- * (nsamples > 1, LP_SEMI_IMPLICIT, a porous, coarse or (LP_DENSE) Oseen
+ * non-positive dt or parameters, samples with different dt, unknown option
+ * values), LP_ERR_UNSUPPORTED (nsamples > 1 with the Krylov path, graphs,
+ * autotuning or LP_ONE_GRID, LP_SEMI_IMPLICIT, a porous, coarse or (LP_DENSE) Oseen
  * half-bandwidth beyond the band kernels' window of 159, or a Krylov strip or
  * system beyond its kernels' limits), LP_ERR_NOCONV (zero or non-finite pivot in
  * the constant porous matrices), LP_ERR_ALLOC, LP_ERR_DEVICE. */
@@ -342,7 +349,8 @@ lp_status lp_get_timing(lp_ctx *ctx, double *ms, int64_t *launches, int32_t n);
  * allocator; its tickets are cleared by a small kernel on each call.  Every
  * call on one device shares that array: calls of different contexts that
  * overlap on one device race.  Errors: as lp_local_step, and
- * LP_ERR_UNSUPPORTED when the problem's scratch exceeds the array. */
+ * LP_ERR_UNSUPPORTED when the problem's scratch exceeds the array or the
+ * context holds more than one sample. */
 lp_status lp_local_step_noalloc(lp_ctx *ctx, void *stream);
 
 void lp_destroy(lp_ctx *ctx);

@@ -79,6 +79,15 @@ struct lp_ctx {
     int64_t n = 0;                 // completed local steps
     bool coarse_pending = false;
     bool one_grid = false;             // Algorithm 1: the coarse step is the whole step
+    // Parameter samples advanced together (lp_options.nsamples): every system
+    // list holds the systems of sample 0, then of sample 1, ...; the fields
+    // read by position on a lattice (coarse states, prolongations, loads,
+    // merged output, Newton iterates) live in one arena block per sample,
+    // zs doubles apart (SysDesc::zo = sample * zs).
+    int ns = 1;
+    int np1 = 0, no1 = 0;              // porous / conduit subdomains per sample
+    long long zs = 0;
+    double *arena = nullptr;
     // Coarse states live in a ring of RING slots (time m in slot m % RING).
     // The coarse step runs on an internal stream: it never reads local
     // results, so coarse steps run ahead of the local stage (up to RING - 2
@@ -440,21 +449,24 @@ double time_at(const lp_ctx *c, int64_t step) { return (double)step * c->prm.dt;
 // solve list that turns nmat factored band matrices of system s into their
 // inverses: every right-hand side of matrix f shares its factors (stride 0)
 // and column j of the inverse is the solution for the j-th unit vector
-std::vector<lp::BandSys> inverse_list(const lp::SysDesc &s, int nmat, const FacLayout &L) {
+std::vector<lp::BandSys> inverse_list(const std::vector<lp::SysDesc> &v, int nmat, const FacLayout &L) {
     std::vector<lp::BandSys> out;
-    const long long n = s.ndof;
-    for (int f = 0; f < nmat; ++f) {
-        lp::BandSys b{};
-        b.off = s.band_off + (long long)f * s.band_size;
-        b.stride = 0;
-        b.vec = (long long)f * n * n;
-        b.foff = L.off[f];
-        b.fstride = 0;
-        b.n = s.ndof;
-        b.bw = s.bw;
-        b.nrhs = s.ndof;
-        b.ldf = L.ldf;
-        out.push_back(b);
+    size_t i = 0;
+    for (const auto &s : v) {
+        const long long n = s.ndof;
+        for (int f = 0; f < nmat; ++f, ++i) {
+            lp::BandSys b{};
+            b.off = s.band_off + (long long)f * s.band_size;
+            b.stride = 0;
+            b.vec = (long long)i * n * n;
+            b.foff = L.off[i];
+            b.fstride = 0;
+            b.n = s.ndof;
+            b.bw = s.bw;
+            b.nrhs = s.ndof;
+            b.ldf = L.ldf;
+            out.push_back(b);
+        }
     }
     return out;
 }
@@ -678,6 +690,7 @@ void prolong_porous(lp_ctx *c, double *pro, int cnew, int cold, hipStream_t st) 
     const long long nc2 = c->nc2, nf2 = c->nf2;
     lp::ProlongArgs pa{};
     pa.NH = c->P.NH; pa.Nh = c->P.Nh; pa.k = c->P.k;
+    pa.zs = c->zs;
     pa.nfields = 6;
     for (int f = 0; f < 3; ++f) {
         pa.src[f] = c->cP[cnew] + f * nc2;
@@ -685,11 +698,11 @@ void prolong_porous(lp_ctx *c, double *pro, int cnew, int cold, hipStream_t st) 
         pa.src[3 + f] = c->cP[cold] + f * nc2;
         pa.dst[3 + f] = pro + (3 + f) * nf2;
     }
-    lp::launch_prolong_p2(pa, st);
+    lp::launch_prolong_p2(pa, c->ns, st);
     pa.nfields = 1;
     pa.src[0] = c->cU[cold] + nc2;
     pa.dst[0] = pro + 6 * nf2;
-    lp::launch_prolong_p2(pa, st);
+    lp::launch_prolong_p2(pa, c->ns, st);
 }
 
 template <typename T>
@@ -734,6 +747,7 @@ void prolong_step(lp_ctx *c, int cnew, int cold, int slot, hipStream_t st) {
     double *d = c->pro_slot(slot);
     lp::ProlongArgs pa{};
     pa.NH = c->P.NH; pa.Nh = c->P.Nh; pa.k = c->P.k;
+    pa.zs = c->zs;
     pa.nfields = 5;
     for (int cc = 0; cc < 2; ++cc) {
         pa.src[cc] = c->cU[cnew] + cc * nc2;
@@ -743,11 +757,11 @@ void prolong_step(lp_ctx *c, int cnew, int cold, int slot, hipStream_t st) {
     }
     pa.src[4] = c->cP[cold];
     pa.dst[4] = d + 4 * nf2;
-    lp::launch_prolong_p2(pa, st);
+    lp::launch_prolong_p2(pa, c->ns, st);
     pa.nfields = 1;
     pa.src[0] = c->cp[cnew];
     pa.dst[0] = d + 5 * nf2;
-    lp::launch_prolong_p1(pa, st);
+    lp::launch_prolong_p1(pa, c->ns, st);
 }
 
 // level 0 prolonged for the initial corrections: the three porous pressures
@@ -756,6 +770,7 @@ void prolong_setup(lp_ctx *c, hipStream_t st) {
     const long long nc2 = c->nc2, nf2 = c->nf2;
     lp::ProlongArgs pa{};
     pa.NH = c->P.NH; pa.Nh = c->P.Nh; pa.k = c->P.k;
+    pa.zs = c->zs;
     pa.nfields = 5;
     for (int f = 0; f < 3; ++f) {
         pa.src[f] = c->cP[0] + f * nc2;
@@ -765,7 +780,7 @@ void prolong_setup(lp_ctx *c, hipStream_t st) {
         pa.src[3 + cc] = c->cU[0] + cc * nc2;
         pa.dst[3 + cc] = c->pro_U1 + cc * nf2;
     }
-    lp::launch_prolong_p2(pa, st);
+    lp::launch_prolong_p2(pa, c->ns, st);
 }
 
 // Krylov path: strip tables, the strips' Stokes-part band matrices (the
@@ -955,6 +970,64 @@ bool params_ok(const lp_params &p, std::string &why) {
 
 }  // namespace
 
+namespace {
+// The per-sample field arena: the offsets (doubles) of every field that kernels
+// read by lattice position, in one sample's block.
+struct ArenaLayout {
+    long long cP[lp_ctx::RING], cU[lp_ctx::RING], cp[lp_ctx::RING];
+    long long nwt_e, nwt_e1, pro_P1, pro_U1, pro_ring, pro_Pb[2], m_P, m_U, m_p;
+    long long ld_f[5][3], ld_c[5][3];
+    long long total;
+};
+ArenaLayout arena_layout(long long nf2, long long nf1, long long nc2, long long nc1, long long pro_stride) {
+    ArenaLayout L{};
+    long long o = 0;
+    auto take = [&](long long n) { const long long at = o; o += (n + 63) / 64 * 64; return at; };
+    for (int l = 0; l < lp_ctx::RING; ++l) { L.cP[l] = take(3 * nc2); L.cU[l] = take(2 * nc2); L.cp[l] = take(nc1); }
+    L.nwt_e = take(2 * nc2); L.nwt_e1 = take(nc1);
+    L.pro_P1 = take(3 * nf2); L.pro_U1 = take(2 * nf2);
+    L.pro_ring = take(lp_ctx::RING * pro_stride);
+    for (int l = 0; l < 2; ++l) L.pro_Pb[l] = take(7 * nf2);
+    L.m_P = take(3 * nf2); L.m_U = take(2 * nf2); L.m_p = take(nf1);
+    for (int f = 0; f < 5; ++f)
+        for (int k = 0; k < 3; ++k) { L.ld_f[f][k] = take(nf2); L.ld_c[f][k] = take(nc2); }
+    L.total = o;
+    return L;
+}
+
+// S copies of a system list (sample s's systems after sample s-1's), their
+// per-system buffers laid out sample after sample and their lattice fields in
+// sample s's arena block
+void replicate_samples(std::vector<lp::SysDesc> &v, int S, long long band_total, long long dof_total,
+                       long long e2_total, long long e1_total, long long zs) {
+    const size_t n = v.size();
+    for (int smp = 1; smp < S; ++smp)
+        for (size_t i = 0; i < n; ++i) {
+            lp::SysDesc d = v[i];
+            d.sample = smp;
+            d.zo = smp * zs;
+            d.band_off += smp * band_total;
+            d.dof_off += smp * dof_total;
+            d.e2_off += smp * e2_total;
+            d.e1_off += smp * e1_total;
+            v.push_back(d);
+        }
+}
+
+// the coefficients of one parameter sample (Section 3.1 / Algorithm 3)
+lp::Coef coefficients(const lp_params &q, int convection) {
+    lp::Coef co{};
+    for (int i = 0; i < 3; ++i) { co.tau[i] = q.phi[i] * q.C[i] / q.dt; co.kap[i] = q.k[i] / q.mu_tilde; }
+    co.sst = q.sigma_star * q.k[1] / q.mu_tilde;
+    co.s = q.sigma * q.k[2] / q.mu_tilde;
+    co.eta = q.eta; co.nu = q.nu; co.rho = q.rho; co.dt = q.dt;
+    co.beta = q.alpha * q.nu / std::sqrt(q.k[0]);
+    co.ctau = q.eta * q.nu * q.alpha * std::sqrt(q.k[0]) / q.mu_tilde;
+    co.convection = convection;
+    return co;
+}
+}  // namespace
+
 extern "C" {
 
 const char *lp_last_error(void) { return g_err.c_str(); }
@@ -1030,7 +1103,15 @@ lp_status lp_plan_query(const lp_mesh *mesh, const lp_partition *part, int32_t w
 lp_status lp_get_index_map(lp_ctx *c, int32_t which, int32_t sub, int64_t *out, int64_t len, int64_t *needed) {
     if (!c || !needed) return fail(LP_ERR_ARG, "NULL argument");
     std::vector<int64_t> v;
-    TRY(plan_table(c->P, which, sub, v));
+    if (c->ns > 1) {
+        // the tables of one sample: every sample shares the partition
+        lp::Plan one = c->P;
+        one.por.resize(c->np1);
+        one.ose.resize(c->no1);
+        TRY(plan_table(one, which, sub, v));
+    } else {
+        TRY(plan_table(c->P, which, sub, v));
+    }
     *needed = (int64_t)v.size();
     if (out && len >= (int64_t)v.size()) std::memcpy(out, v.data(), v.size() * sizeof(int64_t));
     return LP_OK;
@@ -1048,7 +1129,12 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     if (opt->solver < LP_AUTO || opt->solver > LP_KRYLOV) return fail(LP_ERR_ARG, "solver must be LP_AUTO, LP_DENSE or LP_KRYLOV");
     if (opt->coarse_ns != LP_NEWTON && opt->coarse_ns != LP_SEMI_IMPLICIT)
         return fail(LP_ERR_ARG, "coarse_ns must be LP_NEWTON or LP_SEMI_IMPLICIT");
-    if (opt->nsamples > 1) return fail(LP_ERR_UNSUPPORTED, "more than one parameter sample per context is not built");
+    const int nsam = std::max(opt->nsamples, 1);
+    for (int i = 1; i < nsam; ++i)
+        if (samples[i].dt != samples[0].dt) return fail(LP_ERR_ARG, "every sample must share dt (one time grid)");
+    if (nsam > 1 && (opt->solver == LP_KRYLOV || opt->graphs || opt->autotune || opt->scheme == LP_ONE_GRID))
+        return fail(LP_ERR_UNSUPPORTED, "several samples run the dense local path with direct launches and no autotuning, "
+                                        "under the two-grid scheme");
     if (opt->solver != LP_DENSE && (opt->max_iter < 1 || opt->max_iter > lp::GM_MAX || !(opt->krylov_tol > 0)))
         return fail(LP_ERR_ARG, "Krylov solves need 1 <= max_iter <= " + std::to_string(lp::GM_MAX) + " and krylov_tol > 0");
     if (opt->coarse_ns == LP_SEMI_IMPLICIT) return fail(LP_ERR_UNSUPPORTED, "the semi-implicit coarse step is not built");
@@ -1096,6 +1182,26 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     // keeps the faster (measured at the end of setup)
     const bool try_both = opt->autotune && opt->solver == LP_AUTO && c->maxbw_ose < 160;
     c->have_dense = !c->krylov || try_both;
+    if (nsam > 1 && c->krylov)
+        return fail(LP_ERR_UNSUPPORTED, "several samples need the dense local Oseen path (half-bandwidth <= 159)");
+    c->ns = nsam;
+    c->np1 = (int)P.por.size();
+    c->no1 = (int)P.ose.size();
+    c->nf2 = (long long)(2 * P.Nh + 1) * (2 * P.Nh + 1);
+    c->nf1 = (long long)(P.Nh + 1) * (P.Nh + 1);
+    c->nc2 = (long long)(2 * P.NH + 1) * (2 * P.NH + 1);
+    c->nc1 = (long long)(P.NH + 1) * (P.NH + 1);
+    c->pro_stride = (5 * c->nf2 + c->nf1 + 63) / 64 * 64;
+    const ArenaLayout AL = arena_layout(c->nf2, c->nf1, c->nc2, c->nc1, c->pro_stride);
+    c->zs = AL.total;
+    if (nsam > 1) {
+        replicate_samples(P.por, nsam, P.band_total_por, P.dof_total_por, P.e2_total, P.e1_total, c->zs);
+        replicate_samples(P.ose, nsam, P.band_total_ose, P.dof_total_ose, P.e2_total, P.e1_total, c->zs);
+        P.band_total_por *= nsam; P.band_total_ose *= nsam;
+        P.dof_total_por *= nsam; P.dof_total_ose *= nsam;
+        P.e2_total *= nsam; P.e1_total *= nsam;
+        P.local_dofs *= nsam;
+    }
     c->have_strips = c->krylov || try_both;
     // local systems: window 160 (every factorisation kernel); the coarse
     // ones, factored by the vector-unit kernel when wider, up to LU_MAX_BW
@@ -1113,25 +1219,26 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
         c->gm_m = opt->max_iter;
         if (const char *v = std::getenv("LP_GM_REORTH")) c->gm_reorth = std::atoi(v) != 0;
     }
-    // coefficients (Section 3.1 / Algorithm 3)
-    lp::Coef &co = c->co;
-    for (int i = 0; i < 3; ++i) { co.tau[i] = prm->phi[i] * prm->C[i] / prm->dt; co.kap[i] = prm->k[i] / prm->mu_tilde; }
-    co.sst = prm->sigma_star * prm->k[1] / prm->mu_tilde;
-    co.s = prm->sigma * prm->k[2] / prm->mu_tilde;
-    co.eta = prm->eta; co.nu = prm->nu; co.rho = prm->rho; co.dt = prm->dt;
-    co.beta = prm->alpha * prm->nu / std::sqrt(prm->k[0]);
-    co.ctau = prm->eta * prm->nu * prm->alpha * std::sqrt(prm->k[0]) / prm->mu_tilde;
-    co.convection = opt->convection ? 1 : 0;
+    // coefficients (Section 3.1 / Algorithm 3), one set per sample
+    std::vector<lp::Coef> cos(nsam);
+    for (int i = 0; i < nsam; ++i) cos[i] = coefficients(samples[i], opt->convection ? 1 : 0);
+    c->co = cos[0];
     lp::build_refdata(c->ref);
     HIPCHK(lp::upload_constants(c->ref, st));
-    TRY(c->upload(&c->d_co, std::vector<lp::Coef>{co}, st));
-
-    c->nf2 = (long long)(2 * P.Nh + 1) * (2 * P.Nh + 1);
-    c->nf1 = (long long)(P.Nh + 1) * (P.Nh + 1);
-    c->nc2 = (long long)(2 * P.NH + 1) * (2 * P.NH + 1);
-    c->nc1 = (long long)(P.NH + 1) * (P.NH + 1);
-    // tables
-    std::vector<lp::SysDesc> cp{P.cpor}, cn{P.cns};
+    TRY(c->upload(&c->d_co, cos, st));
+    // tables: the coarse systems of every sample (their states and Newton
+    // iterates in the sample's arena block)
+    std::vector<lp::SysDesc> cp, cn;
+    for (int smp = 0; smp < nsam; ++smp) {
+        lp::SysDesc a = P.cpor, b = P.cns;
+        a.sample = b.sample = smp;
+        a.zo = b.zo = smp * c->zs;
+        a.band_off += smp * P.cband_por; b.band_off += smp * P.cband_ns;
+        a.dof_off += smp * 3LL * P.cpor.ndof; b.dof_off += smp * (long long)P.cns.ndof;
+        a.e2_off += smp * c->zs; b.e2_off += smp * c->zs; b.e1_off += smp * c->zs;
+        cp.push_back(a);
+        cn.push_back(b);
+    }
     TRY(c->upload(&c->d_por, P.por, st));
     TRY(c->upload(&c->d_ose, P.ose, st));
     TRY(c->upload(&c->d_cpor, cp, st));
@@ -1158,29 +1265,48 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
             TRY(c->upload(&c->d_own[r][ax][3], P.own1_n[r][ax], st));
         }
     // manufactured data
+    TRY(c->dalloc(&c->arena, (long long)nsam * c->zs));
     {
-        std::vector<double> exf[6], exc[6], lf[5][3], lc[5][3];
+        double *A0 = c->arena;
+        for (int l = 0; l < lp_ctx::RING; ++l) { c->cP[l] = A0 + AL.cP[l]; c->cU[l] = A0 + AL.cU[l]; c->cp[l] = A0 + AL.cp[l]; }
+        c->nwt_e = A0 + AL.nwt_e; c->nwt_e1 = A0 + AL.nwt_e1;
+        c->pro_P1 = A0 + AL.pro_P1; c->pro_U1 = A0 + AL.pro_U1; c->pro_ring = A0 + AL.pro_ring;
+        for (int l = 0; l < 2; ++l) c->pro_Pb[l] = A0 + AL.pro_Pb[l];
+        c->m_P = A0 + AL.m_P; c->m_U = A0 + AL.m_U; c->m_p = A0 + AL.m_p;
+        for (int f = 0; f < 5; ++f)
+            for (int k = 0; k < 3; ++k) { c->ld_f[f][k] = A0 + AL.ld_f[f][k]; c->ld_c[f][k] = A0 + AL.ld_c[f][k]; }
+    }
+    auto put = [&](double *dst0, int smp, const std::vector<double> &v) -> lp_status {
+        HIPCHK(hipMemcpyAsync(dst0 + (long long)smp * c->zs, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice, st));
+        return LP_OK;
+    };
+    {
+        std::vector<double> exf[6], exc[6];
         lp::exact_spatial(P.Nh, exf);
         lp::exact_spatial(P.NH, exc);
-        lp::source_loads(P.Nh, *prm, lf);
-        lp::source_loads(P.NH, *prm, lc);
         for (int f = 0; f < 6; ++f) { TRY(c->upload(&c->ex_f[f], exf[f], st)); TRY(c->upload(&c->ex_c[f], exc[f], st)); }
-        for (int f = 0; f < 5; ++f)
-            for (int k = 0; k < 3; ++k) { TRY(c->upload(&c->ld_f[f][k], lf[f][k], st)); TRY(c->upload(&c->ld_c[f][k], lc[f][k], st)); }
-        // coarse initial data: nodal interpolants at t = 0 (cos 0 = 1)
+        // coarse initial data: nodal interpolants at t = 0 (cos 0 = 1), the
+        // same for every sample (the exact solution does not depend on the
+        // parameters; the sources do)
         std::vector<double> P0(3 * c->nc2), U0(2 * c->nc2);
         for (int f = 0; f < 3; ++f) std::copy(exc[f].begin(), exc[f].end(), P0.begin() + f * c->nc2);
         for (int cc = 0; cc < 2; ++cc) std::copy(exc[3 + cc].begin(), exc[3 + cc].end(), U0.begin() + cc * c->nc2);
-        for (int l = 0; l < lp_ctx::RING; ++l) {
-            TRY(c->upload(&c->cP[l], P0, st));
-            TRY(c->upload(&c->cU[l], U0, st));
-            TRY(c->upload(&c->cp[l], exc[5], st));
+        for (int smp = 0; smp < nsam; ++smp) {
+            std::vector<double> lf[5][3], lc[5][3];
+            lp::source_loads(P.Nh, samples[smp], lf);
+            lp::source_loads(P.NH, samples[smp], lc);
+            for (int f = 0; f < 5; ++f)
+                for (int k = 0; k < 3; ++k) { TRY(put(c->ld_f[f][k], smp, lf[f][k])); TRY(put(c->ld_c[f][k], smp, lc[f][k])); }
+            for (int l = 0; l < lp_ctx::RING; ++l) {
+                TRY(put(c->cP[l], smp, P0));
+                TRY(put(c->cU[l], smp, U0));
+                TRY(put(c->cp[l], smp, exc[5]));
+            }
         }
+        HIPCHK(hipStreamSynchronize(st));
     }
-    TRY(c->dalloc(&c->nwt_e, 2 * c->nc2));
-    TRY(c->dalloc(&c->nwt_e1, c->nc1));
-    TRY(c->dalloc(&c->d_done, 4));
-    TRY(c->dalloc(&c->d_its, 4));
+    TRY(c->dalloc(&c->d_done, nsam));
+    TRY(c->dalloc(&c->d_its, 2 * nsam));
     TRY(c->dalloc(&c->d_flags, 4));
     TRY(c->dalloc(&c->d_lustat, 4));
     TRY(c->dalloc(&c->tf_dev, 4 * lp_ctx::RING));
@@ -1196,23 +1322,15 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     HIPCHK(hipMemsetAsync(c->d_lustat, 0, 4 * sizeof(float), st));
     HIPCHK(hipMemsetAsync(c->d_irmax, 0, sizeof(int), st));
     HIPCHK(hipMemsetAsync(c->d_irrel, 0, sizeof(unsigned long long), st));
-    HIPCHK(hipMemsetAsync(c->d_its, 0, 4 * sizeof(int), st));
+    HIPCHK(hipMemsetAsync(c->d_its, 0, 2 * nsam * sizeof(int), st));
     {
         // "converged" before the first coarse step (the Newton start reports
         // an unconverged previous step into the flags)
-        const std::vector<int> one{1, 0, 0, 0};
-        HIPCHK(hipMemcpyAsync(c->d_done, one.data(), 4 * sizeof(int), hipMemcpyHostToDevice, st));
+        const std::vector<int> one(nsam, 1);
+        HIPCHK(hipMemcpyAsync(c->d_done, one.data(), nsam * sizeof(int), hipMemcpyHostToDevice, st));
         HIPCHK(hipStreamSynchronize(st));
     }
-    TRY(c->dalloc(&c->pro_P1, 3 * c->nf2));
-    TRY(c->dalloc(&c->pro_U1, 2 * c->nf2));
-    c->pro_stride = (5 * c->nf2 + c->nf1 + 63) / 64 * 64;
-    TRY(c->dalloc(&c->pro_ring, lp_ctx::RING * c->pro_stride));
-    for (int l = 0; l < 2; ++l) TRY(c->dalloc(&c->pro_Pb[l], 7 * c->nf2));
     for (int l = 0; l < 2; ++l) { TRY(c->dalloc(&c->e2[l], P.e2_total)); TRY(c->dalloc(&c->e1[l], P.e1_total)); }
-    TRY(c->dalloc(&c->m_P, 3 * c->nf2));
-    TRY(c->dalloc(&c->m_U, 2 * c->nf2));
-    TRY(c->dalloc(&c->m_p, c->nf1));
     const size_t tb = c->mixed ? sizeof(float) : sizeof(double);
     {
         void *p;
@@ -1245,46 +1363,46 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
         // local factorisations use the first nlu sinks, the coarse ones (on the
         // coarse stream) the next three
         c->lu_dummy_coarse_off = nlu * lp::LU_DUMMY_PER_SYS;
-        TRY(c->dalloc(&c->lu_dummy, (nlu + 3) * lp::LU_DUMMY_PER_SYS));
+        TRY(c->dalloc(&c->lu_dummy, (nlu + 3LL * nsam) * lp::LU_DUMMY_PER_SYS));
         std::vector<double> k3(514, 0.0);
         k3[512] = 1.0;
         const float onef = 1.0f;
         std::memcpy(&k3[513], &onef, sizeof(float));
         TRY(c->upload(&c->consts, k3, st));
     }
-    TRY(c->dalloc(&c->band_cpor, P.cband_por));
-    TRY(c->dalloc(&c->band_cns, P.cband_ns));
+    TRY(c->dalloc(&c->band_cpor, nsam * P.cband_por));
+    TRY(c->dalloc(&c->band_cns, nsam * P.cband_ns));
     // the Jacobian assembly stores whole rows; entries outside the matrix stay zero
-    HIPCHK(hipMemsetAsync(c->band_cns, 0, P.cband_ns * sizeof(double), st));
+    HIPCHK(hipMemsetAsync(c->band_cns, 0, nsam * P.cband_ns * sizeof(double), st));
     TRY(c->dalloc(&c->fac_cpor, fl_cpor.total + 32));
     TRY(c->dalloc(&c->fac_cns, fl_cns.total + 32));
     HIPCHK(hipMemsetAsync(c->fac_cpor, 0, fl_cpor.total * sizeof(double), st));
     HIPCHK(hipMemsetAsync(c->fac_cns, 0, fl_cns.total * sizeof(double), st));
     TRY(c->dalloc(&c->b_por, P.dof_total_por)); TRY(c->dalloc(&c->x_por, P.dof_total_por)); TRY(c->dalloc(&c->r_por, P.dof_total_por));
     TRY(c->dalloc(&c->b_ose, P.dof_total_ose)); TRY(c->dalloc(&c->x_ose, P.dof_total_ose)); TRY(c->dalloc(&c->r_ose, P.dof_total_ose));
-    const long long ncp = 3LL * P.cpor.ndof, ncn = P.cns.ndof;
+    const long long ncp = 3LL * P.cpor.ndof * nsam, ncn = (long long)P.cns.ndof * nsam;
     TRY(c->dalloc(&c->b_cp, ncp)); TRY(c->dalloc(&c->x_cp, ncp)); TRY(c->dalloc(&c->r_cp, ncp));
     TRY(c->dalloc(&c->b_cn, ncn)); TRY(c->dalloc(&c->x_cn, ncn)); TRY(c->dalloc(&c->r_cn, ncn));
     const long long npf = 3LL * P.por.size(), nof = (long long)P.ose.size();
     TRY(c->dalloc(&c->conv_por, npf)); TRY(c->dalloc(&c->rel_por, npf)); TRY(c->dalloc(&c->sw_por, npf));
     TRY(c->dalloc(&c->conv_ose, nof)); TRY(c->dalloc(&c->rel_ose, nof)); TRY(c->dalloc(&c->sw_ose, nof));
-    TRY(c->dalloc(&c->conv_cp, 3)); TRY(c->dalloc(&c->rel_cp, 3)); TRY(c->dalloc(&c->sw_cp, 3));
-    TRY(c->dalloc(&c->conv_cn, 1)); TRY(c->dalloc(&c->rel_cn, 1)); TRY(c->dalloc(&c->sw_cn, 1));
+    TRY(c->dalloc(&c->conv_cp, 3 * nsam)); TRY(c->dalloc(&c->rel_cp, 3 * nsam)); TRY(c->dalloc(&c->sw_cp, 3 * nsam));
+    TRY(c->dalloc(&c->conv_cn, nsam)); TRY(c->dalloc(&c->rel_cn, nsam)); TRY(c->dalloc(&c->sw_cn, nsam));
     {
         auto nb = [](int nodes) { return (long long)lp::node_blocks(nodes); };
         c->scratch_part_por = 2 * npf * std::max<long long>(nb(c->nodes_por), c->tiles_por);
         c->scratch_part_ose = 2 * nof * std::max<long long>(nb(c->nodes_ose), c->tiles_ose);
         TRY(c->dalloc(&c->part_por, c->scratch_part_por)); TRY(c->dalloc(&c->tick_por, npf));
         TRY(c->dalloc(&c->part_ose, c->scratch_part_ose)); TRY(c->dalloc(&c->tick_ose, nof));
-        TRY(c->dalloc(&c->part_cp, 2 * 3 * nb(c->nodes_cpor))); TRY(c->dalloc(&c->tick_cp, 3));
-        TRY(c->dalloc(&c->part_cn, 2 * nb(c->nodes_cns))); TRY(c->dalloc(&c->tick_cn, 1));
+        TRY(c->dalloc(&c->part_cp, 2 * 3 * nsam * nb(c->nodes_cpor))); TRY(c->dalloc(&c->tick_cp, 3 * nsam));
+        TRY(c->dalloc(&c->part_cn, 2 * nsam * nb(c->nodes_cns))); TRY(c->dalloc(&c->tick_cn, nsam));
         HIPCHK(hipMemsetAsync(c->tick_por, 0, npf * sizeof(int), st));
         HIPCHK(hipMemsetAsync(c->tick_ose, 0, nof * sizeof(int), st));
-        HIPCHK(hipMemsetAsync(c->tick_cp, 0, 3 * sizeof(int), st));
-        HIPCHK(hipMemsetAsync(c->tick_cn, 0, sizeof(int), st));
-        TRY(c->dalloc(&c->tick_dn, 1)); TRY(c->dalloc(&c->tick_dp, 1));
-        HIPCHK(hipMemsetAsync(c->tick_dn, 0, sizeof(int), st));
-        HIPCHK(hipMemsetAsync(c->tick_dp, 0, sizeof(int), st));
+        HIPCHK(hipMemsetAsync(c->tick_cp, 0, 3 * nsam * sizeof(int), st));
+        HIPCHK(hipMemsetAsync(c->tick_cn, 0, nsam * sizeof(int), st));
+        TRY(c->dalloc(&c->tick_dn, nsam)); TRY(c->dalloc(&c->tick_dp, nsam));
+        HIPCHK(hipMemsetAsync(c->tick_dn, 0, nsam * sizeof(int), st));
+        HIPCHK(hipMemsetAsync(c->tick_dp, 0, nsam * sizeof(int), st));
     }
     HIPCHK(hipMemsetAsync(c->sw_ose, 0, nof * sizeof(int), st));
     HIPCHK(hipMemsetAsync(c->sw_por, 0, npf * sizeof(int), st));
@@ -1337,27 +1455,28 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
         if (c->mixed) TRY(setup_strips<float>(c.get(), st));
         else TRY(setup_strips<double>(c.get(), st));
     }
-    HIPCHK(hipMemsetAsync(c->band_cpor, 0, P.cband_por * sizeof(double), st));
+    HIPCHK(hipMemsetAsync(c->band_cpor, 0, c->ns * P.cband_por * sizeof(double), st));
     {
+        const int S = c->ns;
         lp::AssembleArgs<double> aa{c->d_cpor, c->d_dof2, c->band_cpor};
         aa.co = c->d_co;
-        lp::launch_porous_assemble<double>(aa, 1, st);
+        lp::launch_porous_assemble<double>(aa, S, st);
         lp::BandArgs<double> ba{c->d_lu_cpor, c->band_cpor, c->fac_cpor, c->d_flags, nullptr, c->lu_dummy + c->lu_dummy_coarse_off,
                                 (const double *)c->consts, c->const_one<double>(), c->d_lustat + 2};
-        if (!lp::launch_band_lu<double>(ba, 3, P.cpor.bw, c->lu_variant, st)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
+        if (!lp::launch_band_lu<double>(ba, 3 * S, P.cpor.bw, c->lu_variant, st)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
         // the coarse porous matrices are constant: invert them once
         const long long n = P.cpor.ndof;
-        TRY(c->upload(&c->eye_cp, identities(n, 3), st));
-        TRY(c->upload(&c->d_iv_cpor, inverse_list(P.cpor, 3, fl_cpor), st));
-        TRY(c->dalloc(&c->inv_cp, 3 * n * n));
-        HIPCHK(hipMemsetAsync(c->inv_cp, 0, 3 * n * n * sizeof(double), st));
+        TRY(c->upload(&c->eye_cp, identities(n, 3 * S), st));
+        TRY(c->upload(&c->d_iv_cpor, inverse_list(cp, 3, fl_cpor), st));
+        TRY(c->dalloc(&c->inv_cp, 3LL * S * n * n));
+        HIPCHK(hipMemsetAsync(c->inv_cp, 0, 3LL * S * n * n * sizeof(double), st));
         lp::SolveArgs<double> sa{c->d_iv_cpor, c->fac_cpor, c->eye_cp, c->inv_cp, nullptr, (int)n, nullptr,
                                  (const double *)c->consts, c->const_one<double>(), (const double *)c->consts};
-        if (!lp::launch_band_solve<double>(sa, 3, (int)n, P.cpor.bw, (int)n, c->solve_depth, st)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
+        if (!lp::launch_band_solve<double>(sa, 3 * S, (int)n, P.cpor.bw, (int)n, c->solve_depth, st)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
         const long long m = P.cns.ndof;
-        TRY(c->upload(&c->eye_cn, identities(m, 1), st));
-        TRY(c->upload(&c->d_iv_cns, inverse_list(P.cns, 1, fl_cns), st));
-        TRY(c->dalloc(&c->inv_cn, m * m));
+        TRY(c->upload(&c->eye_cn, identities(m, S), st));
+        TRY(c->upload(&c->d_iv_cns, inverse_list(cn, 1, fl_cns), st));
+        TRY(c->dalloc(&c->inv_cn, (long long)S * m * m));
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));
@@ -1417,13 +1536,13 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
     TRY(seg(c, gkey(G_CPOR, m), ps, [&](hipStream_t s) -> lp_status {
         // the level's time factors on the device (its ring slot's counter)
         lp::launch_time_level(c->level_dev + nw, lp_ctx::RING, c->prm.dt, c->tf_slot(nw), s);
-        lp::launch_porous_rhs(pa, 1, c->nodes_cpor, 8, s);
+        lp::launch_porous_rhs(pa, c->ns, c->nodes_cpor, 8, s);
         // the three solves with the explicit inverses, then the node layout
         lp::DensePorousArgs dp{};
         dp.d = lp::DenseArgs{c->inv_cp, c->b_cp, c->x_cp, P.cpor.ndof, nullptr};
         dp.f = lp::FinalizeArgs{c->d_cpor, c->d_dof2, c->d_dof1, c->x_cp, c->cP[nw], nullptr, nullptr};
         dp.ticket = c->tick_dp;
-        lp::launch_dense_porous(dp, 3, s);
+        lp::launch_dense_porous(dp, 3 * c->ns, s);
         return LP_OK;
     }));
     HIPCHK(hipEventRecord(c->ev_cpor[nw], ps));
@@ -1441,7 +1560,8 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
             lp::NewtonStartArgs ns{c->cU[o], c->cp[o], ex ? c->cU[om] : nullptr, ex ? c->cp[om] : nullptr,
                                    ex2 ? c->cU[omm] : nullptr, ex2 ? c->cp[omm] : nullptr,
                                    c->cU[nw], c->cp[nw], 2 * nc2, c->nc1, c->d_done, c->d_its, nullptr, 0, c->d_flags};
-            lp::launch_newton_start(ns, s);
+            ns.zs = c->zs;
+            lp::launch_newton_start(ns, c->ns, s);
         }
         for (int it = 0; it < c->opt.max_newton; ++it) {
             lp::OseenArgs oa{};
@@ -1457,7 +1577,7 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
             oa.b = c->b_cn;
             oa.tf = c->tf_slot(nw);
             oa.skip = c->d_done;
-            lp::launch_oseen_rhs(oa, 1, c->nodes_cns, 8, s);
+            lp::launch_oseen_rhs(oa, c->ns, c->nodes_cns, 8, s);
             if (it == 0 && refresh) {
                 // Jacobian at the first iterate; later iterations (and steps, up to
                 // the next refresh) reuse its inverse, with residuals of the
@@ -1466,25 +1586,25 @@ lp_status lp_coarse_step(lp_ctx *c, void *stream) {
                 aa.co = c->d_co;
                 aa.sys = c->d_cns; aa.cls2 = c->d_cls2; aa.dof2 = c->d_dof2; aa.dof1 = c->d_dof1;
                 aa.W1[0] = oa.W1[0]; aa.W1[1] = oa.W1[1]; aa.band = c->band_cns; aa.skip = c->d_done;
-                lp::launch_oseen_rows<double>(aa, 1, c->nodes_cns, P.cns.bw, s);
+                lp::launch_oseen_rows<double>(aa, c->ns, c->nodes_cns, P.cns.bw, s);
                 lp::BandArgs<double> ba{c->d_lu_cns, c->band_cns, c->fac_cns, c->d_flags, c->d_done, c->lu_dummy + c->lu_dummy_coarse_off,
                                         (const double *)c->consts, c->const_one<double>(), c->d_lustat + 2};
-                if (!lp::launch_band_lu<double>(ba, 1, P.cns.bw, c->lu_variant_cns, s)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
+                if (!lp::launch_band_lu<double>(ba, c->ns, P.cns.bw, c->lu_variant_cns, s)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
                 // explicit inverse of the Jacobian: each chord step is then one
                 // dense product instead of a serial band solve
                 const int n = P.cns.ndof;
                 lp::SolveArgs<double> sa{c->d_iv_cns, c->fac_cns, c->eye_cn, c->inv_cn, nullptr, n, c->d_done,
                                          (const double *)c->consts, c->const_one<double>(), (const double *)c->consts, 1};
-                if (!lp::launch_band_solve<double>(sa, 1, n, P.cns.bw, n, c->solve_depth, s)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
+                if (!lp::launch_band_solve<double>(sa, c->ns, n, P.cns.bw, n, c->solve_depth, s)) return fail(LP_ERR_UNSUPPORTED, "coarse bandwidth too large");
             }
             // chord step: x = J^-1 b, the correction to the node layout and the
             // update with its convergence test, in one launch
             lp::DenseNewtonArgs dn{};
             dn.d = lp::DenseArgs{c->inv_cn, c->b_cn, c->x_cn, P.cns.ndof, c->d_done};
             dn.f = lp::FinalizeArgs{c->d_cns, c->d_dof2, c->d_dof1, c->x_cn, c->nwt_e, c->nwt_e1, c->d_done};
-            dn.u = lp::NewtonArgs{c->cU[nw], c->cp[nw], c->nwt_e, c->nwt_e1, nc2, c->nc1, c->d_done, c->d_its, c->opt.newton_tol};
+            dn.u = lp::NewtonArgs{c->cU[nw], c->cp[nw], c->nwt_e, c->nwt_e1, nc2, c->nc1, c->d_done, c->d_its, c->opt.newton_tol, c->zs};
             dn.ticket = c->tick_dn;
-            lp::launch_dense_newton(dn, s);
+            lp::launch_dense_newton(dn, c->ns, s);
         }
         return LP_OK;
     }));
@@ -1579,9 +1699,11 @@ lp_status local_step_impl(lp_ctx *c, void *stream, const LocalScratch &ls, bool 
             ma.base1 = pu + 5 * c->nf2; ma.out1 = c->m_p;
         }
         ma.e2 = c->e2[en]; ma.e1 = c->e1[en];
+        ma.nper = r == lp::POROUS ? c->np1 : c->no1;
+        ma.zs = c->zs;
     }
     TRY(seg(c, gkey(G_MERGE, m), st, [&](hipStream_t s) -> lp_status {
-        lp::launch_merge(mr[lp::POROUS], mr[lp::CONDUIT], s);
+        lp::launch_merge(mr[lp::POROUS], mr[lp::CONDUIT], c->ns, s);
         return LP_OK;
     }));
     HIPCHK(hipGetLastError());
@@ -1670,6 +1792,7 @@ lp_status lp_local_step(lp_ctx *c, void *stream) {
 
 lp_status lp_local_step_noalloc(lp_ctx *c, void *stream) {
     if (!c) return fail(LP_ERR_ARG, "NULL context");
+    if (c->ns > 1) return fail(LP_ERR_UNSUPPORTED, "lp_local_step_noalloc takes one sample per context");
     const long long need = c->scratch_part_por + c->scratch_part_ose;     // doubles
     const long long need_t = 3LL * (long long)c->P.por.size() + (long long)c->P.ose.size();
     const long long bytes = need * (long long)sizeof(double) + need_t * (long long)sizeof(int);
@@ -1685,21 +1808,25 @@ lp_status lp_local_step_noalloc(lp_ctx *c, void *stream) {
     return local_step_impl(c, stream, ls, true);
 }
 
-static lp_status locate(lp_ctx *c, int32_t field, int32_t level, int32_t sub, const double **ptr, int64_t *len) {
+static lp_status locate(lp_ctx *c, int32_t sample, int32_t field, int32_t level, int32_t sub, const double **ptr,
+                        int64_t *len) {
     if (field < LP_U || field > LP_PM) return fail(LP_ERR_ARG, "unknown field");
+    if (sample < 0 || sample >= c->ns) return fail(LP_ERR_ARG, "sample out of range (the context holds " + std::to_string(c->ns) + ")");
     const int latest = (int)((c->coarse_pending ? c->n + 1 : c->n) % lp_ctx::RING);
+    const long long zo = (long long)sample * c->zs;       // the sample's arena block
     if (level == LP_MERGED_FINE) {
-        if (field == LP_U) { *ptr = c->m_U; *len = 2 * c->nf2; }
-        else if (field == LP_P) { *ptr = c->m_p; *len = c->nf1; }
-        else { *ptr = c->m_P + (field - LP_PF) * c->nf2; *len = c->nf2; }
+        if (field == LP_U) { *ptr = c->m_U + zo; *len = 2 * c->nf2; }
+        else if (field == LP_P) { *ptr = c->m_p + zo; *len = c->nf1; }
+        else { *ptr = c->m_P + zo + (field - LP_PF) * c->nf2; *len = c->nf2; }
     } else if (level == LP_COARSE) {
-        if (field == LP_U) { *ptr = c->cU[latest]; *len = 2 * c->nc2; }
-        else if (field == LP_P) { *ptr = c->cp[latest]; *len = c->nc1; }
-        else { *ptr = c->cP[latest] + (field - LP_PF) * c->nc2; *len = c->nc2; }
+        if (field == LP_U) { *ptr = c->cU[latest] + zo; *len = 2 * c->nc2; }
+        else if (field == LP_P) { *ptr = c->cp[latest] + zo; *len = c->nc1; }
+        else { *ptr = c->cP[latest] + zo + (field - LP_PF) * c->nc2; *len = c->nc2; }
     } else if (level == LP_LOCAL) {
-        const int np = (int)c->P.por.size(), nsub = np + (int)c->P.ose.size();
+        // sub: a subdomain id of one sample (porous first)
+        const int np = c->np1, nsub = np + c->no1;
         if (sub < 0 || sub >= nsub) return fail(LP_ERR_ARG, "subdomain id out of range");
-        const lp::SysDesc &S = sub < np ? c->P.por[sub] : c->P.ose[sub - np];
+        const lp::SysDesc &S = sub < np ? c->P.por[sample * c->np1 + sub] : c->P.ose[sample * c->no1 + sub - np];
         const long long nl = (long long)S.lw2 * S.lh2;
         const double *e2 = c->e2[c->ecur], *e1 = c->e1[c->ecur];
         if (S.region == lp::POROUS) {
@@ -1721,18 +1848,17 @@ lp_status lp_get_size(lp_ctx *c, int32_t field, int32_t level, int32_t sub, int6
     if (c->one_grid && level == LP_LOCAL) return fail(LP_ERR_STATE, "the one-grid scheme has no local corrections");
     if (c->one_grid && level == LP_MERGED_FINE) level = LP_COARSE;
     const double *p;
-    return locate(c, field, level, sub, &p, len);
+    return locate(c, 0, field, level, sub, &p, len);
 }
 
 lp_status lp_get_solution(lp_ctx *c, int32_t sample, int32_t field, int32_t level, int32_t sub, double *out,
                           int64_t len, int32_t out_is_device, void *stream) {
     if (!c || !out) return fail(LP_ERR_ARG, "NULL argument");
-    if (sample != 0) return fail(LP_ERR_ARG, "sample out of range (the context holds one sample)");
     if (c->one_grid && level == LP_LOCAL) return fail(LP_ERR_STATE, "the one-grid scheme has no local corrections");
     if (c->one_grid && level == LP_MERGED_FINE) level = LP_COARSE;
     const double *p;
     int64_t n;
-    TRY(locate(c, field, level, sub, &p, &n));
+    TRY(locate(c, sample, field, level, sub, &p, &n));
     if (len < n) return fail(LP_ERR_ARG, "output buffer too short: need " + std::to_string(n));
     hipStream_t st = (hipStream_t)stream;
     if (level == LP_COARSE) {
@@ -1756,22 +1882,25 @@ lp_status lp_get_stats(lp_ctx *c, lp_stats *out) {
     HIPCHK(hipDeviceSynchronize());
     std::memset(out, 0, sizeof(*out));
     out->step = c->n;
-    out->n_porous = (int64_t)c->P.por.size();
-    out->n_conduit = (int64_t)c->P.ose.size();
+    out->n_porous = c->np1;
+    out->n_conduit = c->no1;
     out->local_dofs = c->P.local_dofs;
     out->max_bw = c->P.max_bw;
-    int its = 0, done = 0, flags = 0, irmax = 0;
+    int flags = 0, irmax = 0;
     unsigned long long irrel = 0;
-    HIPCHK(hipMemcpy(&its, c->d_its, sizeof(int), hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(&done, c->d_done, sizeof(int), hipMemcpyDeviceToHost));
+    std::vector<int> its(2 * c->ns), done(c->ns);
+    HIPCHK(hipMemcpy(its.data(), c->d_its, its.size() * sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(done.data(), c->d_done, done.size() * sizeof(int), hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(&flags, c->d_flags, sizeof(int), hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(&irmax, c->d_irmax, sizeof(int), hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(&irrel, c->d_irrel, sizeof(irrel), hipMemcpyDeviceToHost));
-    out->newton_its = its;
-    HIPCHK(hipMemcpy(&its, c->d_its + 1, sizeof(int), hipMemcpyDeviceToHost));
-    out->newton_its_max = std::max(its, out->newton_its);
+    // over every sample: the last step's most Newton iterations, the run's most
     out->flags = flags & 7;
-    if (c->n > 0 && !done) out->flags |= 2;
+    for (int smp = 0; smp < c->ns; ++smp) {
+        out->newton_its = std::max(out->newton_its, its[2 * smp]);
+        out->newton_its_max = std::max({out->newton_its_max, its[2 * smp], its[2 * smp + 1]});
+        if (c->n > 0 && !done[smp]) out->flags |= 2;
+    }
     out->ir_sweeps_max = irmax;
     std::memcpy(&out->ir_relres_max, &irrel, sizeof(double));
     std::vector<int> sw(3 * c->P.por.size() + c->P.ose.size());

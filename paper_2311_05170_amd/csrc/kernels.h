@@ -6,10 +6,11 @@
 namespace lp {
 
 struct ProlongArgs {
-    const double *src[6];
+    const double *src[6];         // sample 0's fields in the per-sample arena
     double *dst[6];
     int nfields;
     int NH, Nh, k;
+    long long zs = 0;             // arena stride between samples (doubles); grid row = sample
 };
 
 // Start of a refinement, written by the local right-hand side kernels beside
@@ -230,6 +231,8 @@ struct MergeArgs {
     const double *e1;
     double *out[3];
     double *out1;
+    int nper = 0;                 // systems of the region per sample
+    long long zs = 0;             // arena stride of base / out between samples (grid z = sample)
 };
 
 struct InitArgs {
@@ -242,27 +245,28 @@ struct InitArgs {
 };
 
 struct NewtonArgs {
-    double *U;
+    double *U;                    // U, P, e, e1: sample 0's in the per-sample arena
     double *P;
     const double *e;
     const double *e1;
     long long nu, np;
-    int *done;
-    int *its;
+    int *done;                    // per sample
+    int *its;                     // two per sample
     double tol;
+    long long zs = 0;             // arena stride between samples
 };
 
 struct DenseNewtonArgs {
-    DenseArgs d;                  // one system: x = J^-1 b
+    DenseArgs d;                  // one system per sample: x = J^-1 b
     FinalizeArgs f;               // x to e_new, e_new1
     NewtonArgs u;                 // the update and its convergence test
-    int *ticket;                  // blocks finished (reset by the last)
+    int *ticket;                  // blocks finished, per sample (reset by the last)
 };
 
 struct DensePorousArgs {
-    DenseArgs d;                  // the three porous fields of one system
+    DenseArgs d;                  // the three porous fields of one system per sample
     FinalizeArgs f;
-    int *ticket;
+    int *ticket;                  // per sample
 };
 
 struct NewtonStartArgs {
@@ -271,10 +275,11 @@ struct NewtonStartArgs {
     const double *Umm, *Pmm;      // level n-2 (null at the first two steps)
     double *U1, *P1;              // first iterate for level n+1
     long long nu2, np;
-    int *done, *its;
+    int *done, *its;              // per sample (one, two)
     double *band;                 // the Jacobian band, cleared for its assembly (or null)
     long long band_n;
     int *flags;                   // bit 1 set if the previous coarse step ended unconverged
+    long long zs = 0;             // arena stride between samples (grid row = sample)
 };
 
 // Restarted flexible GMRES over a batch of systems (krylov.hip).  Vectors are
@@ -321,8 +326,8 @@ size_t gm_arnoldi_lds(int maxn);
 void launch_fill_pattern(double *x, long long n, hipStream_t st);
 
 hipError_t upload_constants(const RefData &r, hipStream_t st);
-void launch_prolong_p2(const ProlongArgs &a, hipStream_t st);
-void launch_prolong_p1(const ProlongArgs &a, hipStream_t st);
+void launch_prolong_p2(const ProlongArgs &a, int nsamples, hipStream_t st);
+void launch_prolong_p1(const ProlongArgs &a, int nsamples, hipStream_t st);
 // Node-gather kernels run gridDim = (node blocks of GB threads, systems);
 // maxnodes is the largest local P2 lattice of the batch.
 constexpr int GB = 128;
@@ -356,12 +361,12 @@ bool launch_band_lu(const BandArgs<T> &a, int nsys, int maxbw, int variant, hipS
 template <typename T>
 bool launch_band_solve(const SolveArgs<T> &a, int nsys, int nrhs, int maxbw, int maxn, int depth, hipStream_t st);
 void launch_dense_apply(const DenseArgs &a, int nsys, hipStream_t st);
-void launch_merge(const MergeArgs &porous, const MergeArgs &conduit, hipStream_t st);   // both regions, one launch
+void launch_merge(const MergeArgs &porous, const MergeArgs &conduit, int nsamples, hipStream_t st);   // both regions, every sample, one launch
 void launch_init_corrections(const InitArgs &a, int nsys, hipStream_t st);
-void launch_newton_update(const NewtonArgs &a, hipStream_t st);
-void launch_dense_newton(const DenseNewtonArgs &a, hipStream_t st);
-void launch_dense_porous(const DensePorousArgs &a, int nsys, hipStream_t st);
-void launch_newton_start(const NewtonStartArgs &a, hipStream_t st);
+void launch_newton_update(const NewtonArgs &a, int nsamples, hipStream_t st);
+void launch_dense_newton(const DenseNewtonArgs &a, int nsamples, hipStream_t st);
+void launch_dense_porous(const DensePorousArgs &a, int nsys, hipStream_t st);   // nsys = 3 per sample
+void launch_newton_start(const NewtonStartArgs &a, int nsamples, hipStream_t st);
 // The time level of a step on the device: m = *level, then *level = m + stride,
 // t = m dt (a product, never accumulated) and tf = (cos t, sin t, cos^2 t).
 // Each ring slot has its own counter, advanced by the ring's size, so every

@@ -92,6 +92,7 @@ __device__ __forceinline__ void own_simd() {
 }
 
 __global__ void k_prolong_p2(ProlongArgs A) {
+    const long long zo = blockIdx.y * A.zs;
     const int nf = 2 * A.Nh + 1, nc = 2 * A.NH + 1;
     const long long tot = (long long)nf * nf;
     for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < tot; g += (long long)gridDim.x * blockDim.x) {
@@ -108,16 +109,17 @@ __global__ void k_prolong_p2(ProlongArgs A) {
         double v[6];
         p2_values(xi, eta, v);
         for (int f = 0; f < A.nfields; ++f) {
-            const double *src = A.src[f];
+            const double *src = A.src[f] + zo;
             double s = 0.0;
             for (int q = 0; q < 6; ++q)
                 s += v[q] * src[(2 * ci + off2a(t, q)) + (long long)nc * (2 * cj + off2b(t, q))];
-            A.dst[f][g] = s;
+            A.dst[f][zo + g] = s;
         }
     }
 }
 
 __global__ void k_prolong_p1(ProlongArgs A) {
+    const long long zo = blockIdx.y * A.zs;
     const int nf = A.Nh + 1, nc = A.NH + 1;
     const long long tot = (long long)nf * nf;
     for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < tot; g += (long long)gridDim.x * blockDim.x) {
@@ -132,8 +134,8 @@ __global__ void k_prolong_p1(ProlongArgs A) {
         l[0] = 1.0 - l[1] - l[2];
         for (int f = 0; f < A.nfields; ++f) {
             double s = 0.0;
-            for (int q = 0; q < 3; ++q) s += l[q] * A.src[f][(ci + off1a(t, q)) + (long long)nc * (cj + off1b(t, q))];
-            A.dst[f][g] = s;
+            for (int q = 0; q < 3; ++q) s += l[q] * A.src[f][zo + (ci + off1a(t, q)) + (long long)nc * (cj + off1b(t, q))];
+            A.dst[f][zo + g] = s;
         }
     }
 }
@@ -151,7 +153,7 @@ __device__ __forceinline__ double porous_x(const Coef &cf, int f) { return f == 
 __device__ __forceinline__ double porous_z(const SysDesc &S, const PorousArgs &A, int f, int q, long long G) {
     const int c = A.cls2[S.node_off + q];
     if (c != 1) return 0.0;
-    const double bg = A.P1[f] ? A.P1[f][G] : 0.0;
+    const double bg = A.P1[f] ? A.P1[f][S.zo + G] : 0.0;
     return A.ex[f][G] * A.tf[0] - bg;
 }
 
@@ -192,9 +194,9 @@ __device__ __forceinline__ double group_sum(double v) {
 // single coarse system, where a thread per node leaves the chip idle).
 template <int SPLIT>
 __global__ __launch_bounds__(GB) void k_porous_rhs(PorousArgs A) {
-    const Coef &cf = *A.co;           // this context's coefficients
     static_assert(GB % SPLIT == 0, "node groups within a block");
     const SysDesc S = A.sys[blockIdx.y];
+    const Coef &cf = A.co[S.sample];   // the coefficients of the system's sample
     const int nloc = S.lw2 * S.lh2;
     const int ng = 2 * S.N + 1;
     const double h = S.h, h2 = h * h;
@@ -212,7 +214,7 @@ __global__ __launch_bounds__(GB) void k_porous_rhs(PorousArgs A) {
         // sources at t_{n+1}; the three fields together, so each node of a
         // triangle is read once for all of them
         double r[3];
-        for (int f = 0; f < 3; ++f) r[f] = sub == 0 ? A.load[f][0][G] * A.tf[0] + A.load[f][1][G] * A.tf[1] : 0.0;
+        for (int f = 0; f < 3; ++f) r[f] = sub == 0 ? A.load[f][0][S.zo + G] * A.tf[0] + A.load[f][1][S.zo + G] * A.tf[1] : 0.0;
         auto elem = [&](int t, int ci, int cj, int la) {
             double mv[3] = {0.0, 0.0, 0.0}, kv[3] = {0.0, 0.0, 0.0};
             for (int k = 0; k < 6; ++k) {
@@ -222,8 +224,8 @@ __global__ __launch_bounds__(GB) void k_porous_rhs(PorousArgs A) {
                 const bool dir = A.cls2[S.node_off + qk] == 1;
                 double O[3], X[3];
                 for (int g = 0; g < 3; ++g) {
-                    const double p1 = A.P1[g] ? A.P1[g][Gk] : 0.0;
-                    O[g] = (A.P0[g] ? A.P0[g][Gk] : 0.0) + A.e_old[S.e2_off + (long long)g * nloc + qk];
+                    const double p1 = A.P1[g] ? A.P1[g][S.zo + Gk] : 0.0;
+                    O[g] = (A.P0[g] ? A.P0[g][S.zo + Gk] : 0.0) + A.e_old[S.e2_off + (long long)g * nloc + qk];
                     X[g] = p1 + (dir ? A.ex[g][Gk] * A.tf[0] - p1 : 0.0);
                 }
                 for (int f = 0; f < 3; ++f) {
@@ -255,7 +257,7 @@ __global__ __launch_bounds__(GB) void k_porous_rhs(PorousArgs A) {
                 if (ie < S.x0 || ie >= S.x0 + S.cx) continue;
                 const int la = A0 - 2 * ie;
                 double sg = 0.0;
-                for (int k = 0; k < 3; ++k) sg += c_ref.Ge[la][k] * A.Uy0[2 * ie + k];   // conduit Gamma row b = 0
+                for (int k = 0; k < 3; ++k) sg += c_ref.Ge[la][k] * A.Uy0[S.zo + 2 * ie + k];   // conduit Gamma row b = 0
                 r[0] -= h * sg;
             }
         }
@@ -330,7 +332,7 @@ __device__ __forceinline__ void record_ir_totals(const IrTotals &T) {
 
 __global__ __launch_bounds__(GB) void k_porous_finalize(FinalizeArgs F) {
     const SysDesc S = F.sys[blockIdx.y];
-    if (F.skip && *F.skip) return;
+    if (F.skip && F.skip[S.sample]) return;
     record_ir_totals(F.acc);
     porous_finalize_rows(F, S, blockIdx.x * GB + threadIdx.x, gridDim.x * GB);
 }
@@ -338,8 +340,8 @@ __global__ __launch_bounds__(GB) void k_porous_finalize(FinalizeArgs F) {
 // band assembly of the constant porous matrices (setup)
 template <typename T>
 __global__ __launch_bounds__(256) void k_porous_assemble(AssembleArgs<T> A) {
-    const Coef &cf = *A.co;           // this context's coefficients
     const SysDesc S = A.sys[blockIdx.x];
+    const Coef &cf = A.co[S.sample];   // the coefficients of the system's sample
     const int nloc = S.lw2 * S.lh2;
     const int ld = 2 * S.bw + 1;
     const double h2 = S.h * S.h;
@@ -377,7 +379,7 @@ struct ElemVel {
 // velocity Dirichlet value of the correction at local node q
 __device__ __forceinline__ double oseen_z(const SysDesc &S, const OseenArgs &A, int c, int q, long long G) {
     if (A.cls2[S.node_off + q] != 1) return 0.0;
-    return A.ex[c][G] * A.tf[0] - A.W1[c][G];
+    return A.ex[c][G] * A.tf[0] - A.W1[c][S.zo + G];
 }
 
 // convection rows at test node la of triangle t (unit-cell reference data,
@@ -425,10 +427,10 @@ __device__ __forceinline__ void conv_rows(int t, int la, double h, const double 
 // the per-node work is the latency).
 template <int SPLIT>
 __global__ __launch_bounds__(GB) void k_oseen_rhs(OseenArgs A) {
-    const Coef &cf = *A.co;           // this context's coefficients
     static_assert(GB % SPLIT == 0, "node groups within a block");
     const SysDesc S = A.sys[blockIdx.y];
-    if (A.skip && *A.skip) return;
+    const Coef &cf = A.co[S.sample];   // the coefficients of the system's sample
+    if (A.skip && A.skip[S.sample]) return;
     const int nloc = S.lw2 * S.lh2;
     const int ng = 2 * S.N + 1, ng1 = S.N + 1;
     const double h = S.h, h2 = h * h;
@@ -452,7 +454,7 @@ __global__ __launch_bounds__(GB) void k_oseen_rhs(OseenArgs A) {
         double rv[2] = {0.0, 0.0}, rq = 0.0;
         if (active && cls == 0 && sub == 0)
             for (int c = 0; c < 2; ++c)
-                rv[c] = eta * (A.load[c][0][G] * A.tf[0] + A.load[c][1][G] * A.tf[1] + A.load[c][2][G] * A.tf[2]);
+                rv[c] = eta * (A.load[c][0][S.zo + G] * A.tf[0] + A.load[c][1][S.zo + G] * A.tf[1] + A.load[c][2][S.zo + G] * A.tf[2]);
         auto elem = [&](int t, int ci, int cj, int la) {
             double W[2][6], Z[2][6], Y[2][6], O[2][6], P[3];
             for (int k = 0; k < 6; ++k) {
@@ -460,15 +462,15 @@ __global__ __launch_bounds__(GB) void k_oseen_rhs(OseenArgs A) {
                 const int qk = qa + S.lw2 * qb;
                 const long long Gk = (2 * S.x0 + qa) + (long long)ng * (2 * S.y0 + qb);
                 for (int c = 0; c < 2; ++c) {
-                    W[c][k] = A.W1[c][Gk];
+                    W[c][k] = A.W1[c][S.zo + Gk];
                     Z[c][k] = oseen_z(S, A, c, qk, Gk);
                     Y[c][k] = W[c][k] + Z[c][k];
-                    O[c][k] = (A.W0[c] ? A.W0[c][Gk] : 0.0) + (A.e_old ? A.e_old[S.e2_off + (long long)c * nloc + qk] : 0.0)
+                    O[c][k] = (A.W0[c] ? A.W0[c][S.zo + Gk] : 0.0) + (A.e_old ? A.e_old[S.e2_off + (long long)c * nloc + qk] : 0.0)
                               - W[c][k] - Z[c][k];
                 }
             }
             for (int k = 0; k < 3; ++k)
-                P[k] = A.Pp[(S.x0 + ci + off1a(t, k)) + (long long)ng1 * (S.y0 + cj + off1b(t, k))];
+                P[k] = A.Pp[S.zo + (S.x0 + ci + off1a(t, k)) + (long long)ng1 * (S.y0 + cj + off1b(t, k))];
             if (cls == 0) {
                 double cW[2], Nz[2];
                 if (cf.convection) conv_rows(t, la, h, W, Z, true, cW, Nz);
@@ -519,8 +521,8 @@ __global__ __launch_bounds__(GB) void k_oseen_rhs(OseenArgs A) {
                 for (int k = 0; k < 3; ++k) {
                     const int qk = (2 * ie + k - 2 * S.x0);     // box-local, row 0
                     const long long Gk = 2 * ie + k;           // grid conduit row 0
-                    bj += c_ref.Ge[la][k] * (A.W1[0][Gk] + oseen_z(S, A, 0, qk, Gk));
-                    const double pf = A.PF0[(2 * ie + k) + (long long)ng * (2 * S.N)];   // porous top row
+                    bj += c_ref.Ge[la][k] * (A.W1[0][S.zo + Gk] + oseen_z(S, A, 0, qk, Gk));
+                    const double pf = A.PF0[S.zo + (2 * ie + k) + (long long)ng * (2 * S.N)];   // porous top row
                     pg += c_ref.Ge[la][k] * pf;
                     pgx += c_ref.Gxe[la][k] * pf;
                 }
@@ -541,9 +543,9 @@ __global__ __launch_bounds__(GB) void k_oseen_rhs(OseenArgs A) {
 // rows, added element by element into the cleared band.
 template <typename T>
 __global__ __launch_bounds__(GB) void k_oseen_assemble(OseenApplyArgs<T> A) {
-    const Coef &cf = *A.co;           // this context's coefficients
     const SysDesc S = A.sys[blockIdx.y];
-    if (A.skip && *A.skip) return;
+    const Coef &cf = A.co[S.sample];   // the coefficients of the system's sample
+    if (A.skip && A.skip[S.sample]) return;
     const int nloc = S.lw2 * S.lh2;
     const int ng = 2 * S.N + 1;
     const double h = S.h, h2 = h * h;
@@ -570,7 +572,7 @@ __global__ __launch_bounds__(GB) void k_oseen_assemble(OseenApplyArgs<T> A) {
                 const int qk = qa + S.lw2 * qb;
                 const long long Gk = (2 * S.x0 + qa) + (long long)ng * (2 * S.y0 + qb);
                 dk[k] = A.dof2[S.node_off + qk];
-                for (int c = 0; c < 2; ++c) W[c][k] = A.W1[c][Gk];
+                for (int c = 0; c < 2; ++c) W[c][k] = A.W1[c][S.zo + Gk];
             }
             for (int k = 0; k < 3; ++k)
                 pk[k] = A.dof1[S.vert_off + (ci + off1a(t, k)) + S.lw1 * (cj + off1b(t, k))];
@@ -709,9 +711,9 @@ int residual_tiles(int cx, int cy) { return ((cx + RT - 1) / RT) * ((cy + RT - 1
 // Apply mode (b null): r = -K x without norms or flags (part null), systems
 // whose conv flag is set skipped.
 __global__ __launch_bounds__(256) void k_oseen_residual_tiled(OseenApplyArgs<double> A) {
-    const Coef &cf = *A.co;           // this context's coefficients
     const SysDesc S = A.sys[blockIdx.y];
-    if (A.skip && *A.skip) return;
+    const Coef &cf = A.co[S.sample];   // the coefficients of the system's sample
+    if (A.skip && A.skip[S.sample]) return;
     if (A.conv && A.conv[blockIdx.y]) return;
     const int ntx = (S.cx + RT - 1) / RT, nty = (S.cy + RT - 1) / RT;
     const bool has = (int)blockIdx.x < ntx * nty;
@@ -735,7 +737,7 @@ __global__ __launch_bounds__(256) void k_oseen_residual_tiled(OseenApplyArgs<dou
                 const long long Gk = (2 * S.x0 + qa) + (long long)ng * (2 * S.y0 + qb);
                 const int dk = A.dof2[S.node_off + qa + S.lw2 * qb];
                 for (int c = 0; c < 2; ++c) {
-                    W[c][k] = A.W1[c][Gk];
+                    W[c][k] = A.W1[c][S.zo + Gk];
                     X[c][k] = dk >= 0 ? x[dk + c] : 0.0;
                 }
             }
@@ -851,9 +853,9 @@ __global__ __launch_bounds__(256) void k_oseen_residual_tiled(OseenApplyArgs<dou
 // once into LDS, then the node threads (Dirichlet values, sources, Gamma
 // terms) add their triangles in the node-thread order.
 __global__ __launch_bounds__(256) void k_oseen_rhs_tiled(OseenArgs A) {
-    const Coef &cf = *A.co;           // this context's coefficients
     const SysDesc S = A.sys[blockIdx.y];
-    if (A.skip && *A.skip) return;
+    const Coef &cf = A.co[S.sample];   // the coefficients of the system's sample
+    if (A.skip && A.skip[S.sample]) return;
     const int ntx = (S.cx + RT - 1) / RT, nty = (S.cy + RT - 1) / RT;
     if ((int)blockIdx.x >= ntx * nty) return;
     const int tx = (int)blockIdx.x % ntx, ty = (int)blockIdx.x / ntx;
@@ -880,15 +882,15 @@ __global__ __launch_bounds__(256) void k_oseen_rhs_tiled(OseenArgs A) {
             const int qk = qa + S.lw2 * qb;
             const long long Gk = (2 * S.x0 + qa) + (long long)ng * (2 * S.y0 + qb);
             for (int c = 0; c < 2; ++c) {
-                W[c][k] = A.W1[c][Gk];
+                W[c][k] = A.W1[c][S.zo + Gk];
                 Z[c][k] = oseen_z(S, A, c, qk, Gk);
                 Y[c][k] = W[c][k] + Z[c][k];
-                O[c][k] = (A.W0[c] ? A.W0[c][Gk] : 0.0) + (A.e_old ? A.e_old[S.e2_off + (long long)c * nloc + qk] : 0.0)
+                O[c][k] = (A.W0[c] ? A.W0[c][S.zo + Gk] : 0.0) + (A.e_old ? A.e_old[S.e2_off + (long long)c * nloc + qk] : 0.0)
                           - W[c][k] - Z[c][k];
             }
         }
         for (int k = 0; k < 3; ++k)
-            P[k] = A.Pp[(S.x0 + ci + off1a(t, k)) + (long long)ng1 * (S.y0 + cj + off1b(t, k))];
+            P[k] = A.Pp[S.zo + (S.x0 + ci + off1a(t, k)) + (long long)ng1 * (S.y0 + cj + off1b(t, k))];
         // int ((W.grad)W + N(W) Z)_c phi_la for the six test nodes at once
         double CN[6][2];
         for (int l = 0; l < 6; ++l) CN[l][0] = CN[l][1] = 0.0;
@@ -958,7 +960,7 @@ __global__ __launch_bounds__(256) void k_oseen_rhs_tiled(OseenArgs A) {
         double rv[2] = {0.0, 0.0}, rq = 0.0;
         if (cls == 0)
             for (int c = 0; c < 2; ++c)
-                rv[c] = eta * (A.load[c][0][G] * A.tf[0] + A.load[c][1][G] * A.tf[1] + A.load[c][2][G] * A.tf[2]);
+                rv[c] = eta * (A.load[c][0][S.zo + G] * A.tf[0] + A.load[c][1][S.zo + G] * A.tf[1] + A.load[c][2][S.zo + G] * A.tf[2]);
         for_elements(a, b, S.cx, S.cy, [&](int t, int ci, int cj, int la) {
             const int e = 2 * ((ci - ci_lo) + (RT + 1) * (cj - cj_lo)) + t;
             if (cls == 0) { rv[0] += cv[e][la][0]; rv[1] += cv[e][la][1]; }
@@ -977,8 +979,8 @@ __global__ __launch_bounds__(256) void k_oseen_rhs_tiled(OseenArgs A) {
                 for (int k = 0; k < 3; ++k) {
                     const int qk = (2 * ie + k - 2 * S.x0);     // box-local, row 0
                     const long long Gk = 2 * ie + k;           // grid conduit row 0
-                    bj += c_ref.Ge[lg][k] * (A.W1[0][Gk] + oseen_z(S, A, 0, qk, Gk));
-                    const double pf = A.PF0[(2 * ie + k) + (long long)ng * (2 * S.N)];   // porous top row
+                    bj += c_ref.Ge[lg][k] * (A.W1[0][S.zo + Gk] + oseen_z(S, A, 0, qk, Gk));
+                    const double pf = A.PF0[S.zo + (2 * ie + k) + (long long)ng * (2 * S.N)];   // porous top row
                     pg += c_ref.Ge[lg][k] * pf;
                     pgx += c_ref.Gxe[lg][k] * pf;
                 }
@@ -1004,9 +1006,9 @@ __global__ __launch_bounds__(256) void k_oseen_rhs_tiled(OseenArgs A) {
 // add their triangles in the node-thread order.  A converged field is left
 // alone; blocks past a box's tile count only take part in the reductions.
 __global__ __launch_bounds__(256) void k_porous_residual_tiled(ResidualArgs R) {
-    const Coef &cf = *R.co;           // this context's coefficients
     const SysDesc S = R.sys[blockIdx.y];
-    if (R.skip && *R.skip) return;
+    const Coef &cf = R.co[S.sample];   // the coefficients of the system's sample
+    if (R.skip && R.skip[S.sample]) return;
     const int id0 = blockIdx.y * 3;
     bool act[3];
     for (int f = 0; f < 3; ++f) act[f] = !R.conv[id0 + f];
@@ -1076,8 +1078,8 @@ __global__ __launch_bounds__(256) void k_porous_residual_tiled(ResidualArgs R) {
 // the node threads (Dirichlet values, sources, the Gamma term) add their
 // triangles in the node-thread order.
 __global__ __launch_bounds__(256) void k_porous_rhs_tiled(PorousArgs A) {
-    const Coef &cf = *A.co;           // this context's coefficients
     const SysDesc S = A.sys[blockIdx.y];
+    const Coef &cf = A.co[S.sample];   // the coefficients of the system's sample
     const int ntx = (S.cx + RT - 1) / RT, nty = (S.cy + RT - 1) / RT;
     if ((int)blockIdx.x >= ntx * nty) return;
     const int tx = (int)blockIdx.x % ntx, ty = (int)blockIdx.x / ntx;
@@ -1104,8 +1106,8 @@ __global__ __launch_bounds__(256) void k_porous_rhs_tiled(PorousArgs A) {
             const bool dir = A.cls2[S.node_off + qk] == 1;
             double O[3], X[3];
             for (int g = 0; g < 3; ++g) {
-                const double p1 = A.P1[g] ? A.P1[g][Gk] : 0.0;
-                O[g] = (A.P0[g] ? A.P0[g][Gk] : 0.0) + A.e_old[S.e2_off + (long long)g * nloc + qk];
+                const double p1 = A.P1[g] ? A.P1[g][S.zo + Gk] : 0.0;
+                O[g] = (A.P0[g] ? A.P0[g][S.zo + Gk] : 0.0) + A.e_old[S.e2_off + (long long)g * nloc + qk];
                 X[g] = p1 + (dir ? A.ex[g][Gk] * A.tf[0] - p1 : 0.0);
             }
             for (int f = 0; f < 3; ++f) {
@@ -1141,7 +1143,7 @@ __global__ __launch_bounds__(256) void k_porous_rhs_tiled(PorousArgs A) {
         }
         // sources at t_{n+1}
         double r[3];
-        for (int f = 0; f < 3; ++f) r[f] = A.load[f][0][G] * A.tf[0] + A.load[f][1][G] * A.tf[1];
+        for (int f = 0; f < 3; ++f) r[f] = A.load[f][0][S.zo + G] * A.tf[0] + A.load[f][1][S.zo + G] * A.tf[1];
         for_elements(a, b, S.cx, S.cy, [&](int t, int ci, int cj, int la) {
             const int e = 2 * ((ci - ci_lo) + (RT + 1) * (cj - cj_lo)) + t;
             for (int f = 0; f < 3; ++f) r[f] += cr[e][la][f];
@@ -1155,7 +1157,7 @@ __global__ __launch_bounds__(256) void k_porous_rhs_tiled(PorousArgs A) {
                 if (ie < S.x0 || ie >= S.x0 + S.cx) continue;
                 const int lg = A0 - 2 * ie;
                 double sg = 0.0;
-                for (int k = 0; k < 3; ++k) sg += c_ref.Ge[lg][k] * A.Uy0[2 * ie + k];   // conduit Gamma row b = 0
+                for (int k = 0; k < 3; ++k) sg += c_ref.Ge[lg][k] * A.Uy0[S.zo + 2 * ie + k];   // conduit Gamma row b = 0
                 r[0] -= h * sg;
             }
         }
@@ -1180,9 +1182,9 @@ __global__ __launch_bounds__(256) void k_porous_rhs_tiled(PorousArgs A) {
 // kernel's assembly mode.
 template <typename T>
 __global__ __launch_bounds__(64) void k_oseen_rows(OseenApplyArgs<T> A) {
-    const Coef &cf = *A.co;           // this context's coefficients
     const SysDesc S = A.sys[blockIdx.y];
-    if (A.skip && *A.skip) return;
+    const Coef &cf = A.co[S.sample];   // the coefficients of the system's sample
+    if (A.skip && A.skip[S.sample]) return;
     const int q = blockIdx.x;
     const int nloc = S.lw2 * S.lh2;
     if (q >= nloc) return;
@@ -1224,7 +1226,7 @@ __global__ __launch_bounds__(64) void k_oseen_rows(OseenApplyArgs<T> A) {
                 double W[2][6];
                 for (int kk = 0; kk < 6; ++kk) {
                     const long long Gk = (2 * S.x0 + 2 * ci + off2a(t, kk)) + (long long)ng * (2 * S.y0 + 2 * cj + off2b(t, kk));
-                    for (int c = 0; c < 2; ++c) W[c][kk] = A.W1[c][Gk];
+                    for (int c = 0; c < 2; ++c) W[c][kk] = A.W1[c][S.zo + Gk];
                 }
                 for (int qq = 0; qq < NQ; ++qq) {
                     double wv[2] = {0, 0}, gw[2][2] = {{0, 0}, {0, 0}};
@@ -1323,7 +1325,7 @@ __device__ __forceinline__ void oseen_finalize_rows(const FinalizeArgs &F, const
 }
 __global__ __launch_bounds__(GB) void k_oseen_finalize(FinalizeArgs F) {
     const SysDesc S = F.sys[blockIdx.y];
-    if (F.skip && *F.skip) return;
+    if (F.skip && F.skip[S.sample]) return;
     record_ir_totals(F.acc);
     oseen_finalize_rows(F, S, blockIdx.x * GB + threadIdx.x, gridDim.x * GB);
 }
@@ -1403,7 +1405,7 @@ template <typename T, int TP, int RB>
 __global__ __launch_bounds__(TP *TP) void k_band_lu(BandArgs<T> B) {
     constexpr int NT = TP * TP, W = TP * RB, U = RB, NE = 2 * W, NI = (NE + NT - 1) / NT;
     const BandSys Sy = B.sys[blockIdx.x];
-    if (B.skip && *B.skip) return;
+    if (B.skip && B.skip[blockIdx.x]) return;
     const int n = Sy.n, bw = Sy.bw, ld = 2 * bw + 1;
     const T *M = B.band + Sy.off;
     // factors in the solves' layout (fac_pos): R = ldf slots per column,
@@ -1662,7 +1664,7 @@ __global__ __launch_bounds__(64 * (NW + LU_NS)) void k_band_lu_mfma(BandArgs<T> 
     constexpr int W = 16 * TT, NTILE = TT * TT, MT = (NTILE + NW - 1) / NW;
     static_assert(2 * (W - 16) <= 64 * LU_NS, "one writer thread per panel row and column");
     const BandSys Sy = B.sys[blockIdx.x];
-    if (B.skip && *B.skip) return;
+    if (B.skip && B.skip[blockIdx.x]) return;
     const int n = Sy.n, bw = Sy.bw, ld = 2 * bw + 1;
     const int ws = bw > 0 ? bw : 1, ldf = Sy.ldf, nrf = ldf >> 6, R = ldf;
     const T *M = B.band + Sy.off;
@@ -1933,7 +1935,7 @@ __global__ __launch_bounds__(64 * (TT + LU_NS)) void k_band_lu_la(BandArgs<T> B)
     constexpr int NRF = solve_nr(W - 16);         // solve registers per lane of this window's bandwidths
     static_assert(2 * (W - 16) <= 64 * LU_NS, "one writer thread per panel row and column");
     const BandSys Sy = B.sys[blockIdx.x];
-    if (B.skip && *B.skip) return;
+    if (B.skip && B.skip[blockIdx.x]) return;
     const int n = Sy.n, bw = Sy.bw, ld = 2 * bw + 1;
     const int ws = bw > 0 ? bw : 1, ldf = Sy.ldf;
     if (n <= 0) return;
@@ -2374,7 +2376,7 @@ __global__ __launch_bounds__(SOLVE_THREADS) void k_band_solve(SolveArgs<T> A) {
     const BandSys Sy = A.sys[sysi];
     if (f >= Sy.nrhs) return;
     const int id = sysi * A.rhs_per_sys + f;
-    if (A.skip && *A.skip) return;
+    if (A.skip && A.skip[sysi]) return;
     if (A.conv && A.conv[id]) return;
     extern __shared__ unsigned char smem_raw[];
     const int n = Sy.n;
@@ -2465,18 +2467,17 @@ __device__ __forceinline__ void dense_rows(const DenseArgs &A, int s, int bx) {
     }
 }
 __global__ __launch_bounds__(1024) void k_dense_apply(DenseArgs A) {
-    if (A.skip && *A.skip) return;
+    if (A.skip && A.skip[blockIdx.y]) return;
     dense_rows(A, blockIdx.y, blockIdx.x);
 }
 
 // true in the one block that finishes last (all blocks' global writes are
 // then visible to it); the ticket is reset for the next launch
-__device__ __forceinline__ bool last_block(int *ticket) {
+__device__ __forceinline__ bool last_block(int *ticket, int nb) {
     __shared__ int last;
     __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) {
-        const int nb = (int)(gridDim.x * gridDim.y);
         last = atomicAdd(ticket, 1) == nb - 1;
         if (last) *ticket = 0;
     }
@@ -2492,6 +2493,8 @@ __device__ __forceinline__ bool last_block(int *ticket) {
 // both regions in one launch (grid row = region)
 __global__ void k_merge(MergeArgs Ap, MergeArgs Ac) {
     const MergeArgs &A = blockIdx.y == 0 ? Ap : Ac;
+    const long long zo = blockIdx.z * A.zs;          // the sample's base and output fields
+    const int sys0 = blockIdx.z * A.nper;            // and its systems
     const int n2 = 2 * A.N + 1, n1 = A.N + 1;
     const long long tot2 = (long long)n2 * n2, tot1 = (long long)n1 * n1;
     for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < tot2 + tot1; g += (long long)gridDim.x * blockDim.x) {
@@ -2505,10 +2508,10 @@ __global__ void k_merge(MergeArgs Ap, MergeArgs Ac) {
         const double w = 1.0 / (double)(cnx[a] * cny[b]);
         const int nf = p1 ? 1 : (A.region == POROUS ? 3 : 2);
         double acc[3];
-        for (int f = 0; f < nf; ++f) acc[f] = p1 ? A.base1[gg] : A.base[f][gg];
+        for (int f = 0; f < nf; ++f) acc[f] = p1 ? A.base1[zo + gg] : A.base[f][zo + gg];
         for (int ky = loy[b]; ky < loy[b] + cny[b]; ++ky)
             for (int kx = lox[a]; kx < lox[a] + cnx[a]; ++kx) {
-                const SysDesc &S = A.sys[kx + A.nsx * ky];
+                const SysDesc &S = A.sys[sys0 + kx + A.nsx * ky];
                 if (p1) {
                     const int li = (a - S.x0) + S.lw1 * (b - S.y0);
                     acc[0] += w * A.e1[S.e1_off + li];
@@ -2518,8 +2521,8 @@ __global__ void k_merge(MergeArgs Ap, MergeArgs Ac) {
                     for (int f = 0; f < nf; ++f) acc[f] += w * A.e2[S.e2_off + f * nloc + li];
                 }
             }
-        if (p1) A.out1[gg] = acc[0];
-        else for (int f = 0; f < nf; ++f) A.out[f][gg] = acc[f];
+        if (p1) A.out1[zo + gg] = acc[0];
+        else for (int f = 0; f < nf; ++f) A.out[f][zo + gg] = acc[f];
     }
 }
 
@@ -2534,7 +2537,7 @@ __global__ void k_init_corrections(InitArgs A) {
         const long long G = (2 * S.x0 + a) + (long long)ng * (2 * S.y0 + b);
         const int cls = A.cls2[S.node_off + q];
         for (int f = 0; f < nf; ++f)
-            A.e[S.e2_off + (long long)f * nloc + q] = cls == 2 ? 0.0 : A.ex[f][G] - A.pro[f][G];
+            A.e[S.e2_off + (long long)f * nloc + q] = cls == 2 ? 0.0 : A.ex[f][G] - A.pro[f][S.zo + G];
     }
     if (S.kind == KIND_OSEEN)
         for (int v = threadIdx.x; v < S.lw1 * S.lh1; v += blockDim.x) A.e1[S.e1_off + v] = 0.0;
@@ -2543,10 +2546,16 @@ __global__ void k_init_corrections(InitArgs A) {
 // Newton update of the coarse Navier-Stokes iterate: U += e, P += d, and the
 // convergence test ||(e, d)|| <= tol ||(U, P)||, by the first 256 threads of
 // a block (every thread of the block takes the barriers)
-__device__ void newton_update_block(const NewtonArgs &A) {
+__device__ void newton_update_block(const NewtonArgs &A0, int smp) {
     constexpr int NT = 256;
     const int tid = threadIdx.x;
-    const long long nu = A.nu, np = A.np;
+    const long long nu = A0.nu, np = A0.np, zo = smp * A0.zs;
+    struct {
+        double *U, *P;
+        const double *e, *e1;
+        int *done, *its;
+        double tol;
+    } A{A0.U + zo, A0.P + zo, A0.e + zo, A0.e1 + zo, A0.done + smp, A0.its + 2 * smp, A0.tol};
     double dd = 0.0, xx = 0.0;
     if (tid < NT) {
         for (long long i = tid; i < 2 * nu; i += NT) {
@@ -2578,28 +2587,30 @@ __device__ void newton_update_block(const NewtonArgs &A) {
     }
 }
 __global__ __launch_bounds__(256) void k_newton_update(NewtonArgs A) {
-    if (*A.done) return;
-    newton_update_block(A);
+    if (A.done[blockIdx.x]) return;
+    newton_update_block(A, blockIdx.x);
 }
 
 // One chord step of the coarse Navier-Stokes solve after its right-hand side:
 // x = J^-1 b by row blocks, then (last block) the correction to the node
 // layout and the Newton update with its convergence test
 __global__ __launch_bounds__(1024) void k_dense_newton(DenseNewtonArgs A) {
-    if (*A.u.done) return;
-    dense_rows(A.d, 0, blockIdx.x);
-    if (!last_block(A.ticket)) return;
-    oseen_finalize_rows(A.f, A.f.sys[0], threadIdx.x, blockDim.x);
+    const int smp = blockIdx.y;                   // one system per sample
+    if (A.u.done[smp]) return;
+    dense_rows(A.d, smp, blockIdx.x);
+    if (!last_block(A.ticket + smp, gridDim.x)) return;
+    oseen_finalize_rows(A.f, A.f.sys[smp], threadIdx.x, blockDim.x);
     __syncthreads();
-    newton_update_block(A.u);
+    newton_update_block(A.u, smp);
 }
 
 // The three coarse porous solves: x_f = A_f^-1 b_f, then (last block) the
 // solution to the node layout
 __global__ __launch_bounds__(1024) void k_dense_porous(DensePorousArgs A) {
+    const int smp = blockIdx.y / 3;               // three fields per sample
     dense_rows(A.d, blockIdx.y, blockIdx.x);
-    if (!last_block(A.ticket)) return;
-    porous_finalize_rows(A.f, A.f.sys[0], threadIdx.x, blockDim.x);
+    if (!last_block(A.ticket + smp, gridDim.x * 3)) return;
+    porous_finalize_rows(A.f, A.f.sys[smp], threadIdx.x, blockDim.x);
 }
 
 // start of the coarse Newton solve: the first iterate is the extrapolation
@@ -2608,24 +2619,28 @@ __global__ __launch_bounds__(1024) void k_dense_porous(DensePorousArgs A) {
 // reported), and optionally a band cleared
 __global__ void k_newton_start(NewtonStartArgs A) {
     const long long tot = A.nu2 + A.np;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < A.band_n; i += (long long)gridDim.x * blockDim.x)
+    const int smp = blockIdx.y;
+    const long long zo = smp * A.zs;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; blockIdx.y == 0 && i < A.band_n; i += (long long)gridDim.x * blockDim.x)
         A.band[i] = 0.0;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < tot; i += (long long)gridDim.x * blockDim.x) {
         const bool u = i < A.nu2;
         const long long j = u ? i : i - A.nu2;
         // extrapolation through the last three levels (two at the second step)
-        const double x0 = u ? A.U0[j] : A.P0[j];
-        const double xm = A.Um ? (u ? A.Um[j] : A.Pm[j]) : x0;
-        const double x1 = A.Umm ? 3.0 * (x0 - xm) + (u ? A.Umm[j] : A.Pmm[j]) : 2.0 * x0 - xm;
-        if (u) A.U1[j] = x1;
-        else A.P1[j] = x1;
+        const long long jz = j + zo;
+        const double x0 = u ? A.U0[jz] : A.P0[jz];
+        const double xm = A.Um ? (u ? A.Um[jz] : A.Pm[jz]) : x0;
+        const double x1 = A.Umm ? 3.0 * (x0 - xm) + (u ? A.Umm[jz] : A.Pmm[jz]) : 2.0 * x0 - xm;
+        if (u) A.U1[jz] = x1;
+        else A.P1[jz] = x1;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         // done starts at 1 (setup), so this reports the previous step only
-        if (*A.done == 0) atomicOr(A.flags, 2);
-        A.its[1] = max(A.its[1], A.its[0]);
-        *A.done = 0;
-        *A.its = 0;
+        int *done = A.done + smp, *its = A.its + 2 * smp;
+        if (*done == 0) atomicOr(A.flags, 2);
+        its[1] = max(its[1], its[0]);
+        *done = 0;
+        *its = 0;
     }
 }
 
@@ -2640,13 +2655,13 @@ static inline int grid_for(long long n, int block) {
     return (int)g;
 }
 
-void launch_prolong_p2(const ProlongArgs &a, hipStream_t st) {
+void launch_prolong_p2(const ProlongArgs &a, int nsamples, hipStream_t st) {
     long long n = (long long)(2 * a.Nh + 1) * (2 * a.Nh + 1);
-    hipLaunchKernelGGL(k_prolong_p2, dim3(grid_for(n, 256)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_prolong_p2, dim3(grid_for(n, 256), nsamples), dim3(256), 0, st, a);
 }
-void launch_prolong_p1(const ProlongArgs &a, hipStream_t st) {
+void launch_prolong_p1(const ProlongArgs &a, int nsamples, hipStream_t st) {
     long long n = (long long)(a.Nh + 1) * (a.Nh + 1);
-    hipLaunchKernelGGL(k_prolong_p1, dim3(grid_for(n, 256)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_prolong_p1, dim3(grid_for(n, 256), nsamples), dim3(256), 0, st, a);
 }
 int node_blocks(int maxnodes) { return maxnodes > 0 ? (maxnodes + GB - 1) / GB : 1; }
 
@@ -2756,23 +2771,23 @@ void launch_dense_apply(const DenseArgs &a, int nsys, hipStream_t st) {
     hipLaunchKernelGGL(k_dense_apply, dim3((a.n + 63) / 64, nsys), dim3(1024), 0, st, a);
 }
 
-void launch_merge(const MergeArgs &porous, const MergeArgs &conduit, hipStream_t st) {
+void launch_merge(const MergeArgs &porous, const MergeArgs &conduit, int nsamples, hipStream_t st) {
     long long n = (long long)(2 * porous.N + 1) * (2 * porous.N + 1) + (long long)(porous.N + 1) * (porous.N + 1);
-    hipLaunchKernelGGL(k_merge, dim3(grid_for(n, 256), 2), dim3(256), 0, st, porous, conduit);
+    hipLaunchKernelGGL(k_merge, dim3(grid_for(n, 256), 2, nsamples), dim3(256), 0, st, porous, conduit);
 }
 void launch_init_corrections(const InitArgs &a, int nsys, hipStream_t st) {
     hipLaunchKernelGGL(k_init_corrections, dim3(nsys), dim3(256), 0, st, a);
 }
-void launch_dense_newton(const DenseNewtonArgs &a, hipStream_t st) {
-    hipLaunchKernelGGL(k_dense_newton, dim3((a.d.n + 63) / 64), dim3(1024), 0, st, a);
+void launch_dense_newton(const DenseNewtonArgs &a, int nsamples, hipStream_t st) {
+    hipLaunchKernelGGL(k_dense_newton, dim3((a.d.n + 63) / 64, nsamples), dim3(1024), 0, st, a);
 }
 void launch_dense_porous(const DensePorousArgs &a, int nsys, hipStream_t st) {
     hipLaunchKernelGGL(k_dense_porous, dim3((a.d.n + 63) / 64, nsys), dim3(1024), 0, st, a);
 }
-void launch_newton_start(const NewtonStartArgs &a, hipStream_t st) {
+void launch_newton_start(const NewtonStartArgs &a, int nsamples, hipStream_t st) {
     const long long work = a.band_n > a.nu2 + a.np ? a.band_n : a.nu2 + a.np;
     const int nb = (int)std::min<long long>(1024, (work + 255) / 256);
-    hipLaunchKernelGGL(k_newton_start, dim3(nb > 0 ? nb : 1), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(k_newton_start, dim3(nb > 0 ? nb : 1, nsamples), dim3(256), 0, st, a);
 }
 __global__ void k_time_level(long long *level, long long stride, double dt, double *tf) {
     const long long m = *level;
@@ -2806,8 +2821,8 @@ void launch_zero_fill(void *p, size_t bytes, hipStream_t st) {
     const int nb = (int)std::min<long long>(2048, std::max<long long>(1, (n16 + 255) / 256));
     hipLaunchKernelGGL(k_zero_fill, dim3(nb), dim3(256), 0, st, (uint4 *)p, n16, (unsigned char *)p + n16 * 16, ntail);
 }
-void launch_newton_update(const NewtonArgs &a, hipStream_t st) {
-    hipLaunchKernelGGL(k_newton_update, dim3(1), dim3(256), 0, st, a);
+void launch_newton_update(const NewtonArgs &a, int nsamples, hipStream_t st) {
+    hipLaunchKernelGGL(k_newton_update, dim3(nsamples), dim3(256), 0, st, a);
 }
 template void launch_porous_assemble<float>(const AssembleArgs<float> &, int, hipStream_t);
 template void launch_porous_assemble<double>(const AssembleArgs<double> &, int, hipStream_t);

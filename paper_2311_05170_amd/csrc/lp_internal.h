@@ -72,7 +72,7 @@ struct SysDesc {
     int lw2, lh2, lw1, lh1;     // local lattice sizes
     int ndof, bw;               // unknowns and half-bandwidth of one band system
     int sub;                    // subdomain id, -1 for a coarse system
-    int pad;
+    int sample;                 // parameter sample of the system (coefficients, background fields)
     double h;
     long long band_off;         // band offset of field 0 (porous field f at + f*band_size)
     long long band_size;        // ndof * (2 bw + 1)
@@ -81,6 +81,7 @@ struct SysDesc {
     long long vert_off;         // offset of the local P1 lattice in cls1/dof1
     long long e2_off;           // state offset (local P2 lattice); porous field f / velocity comp c at + f*lw2*lh2
     long long e1_off;           // state offset (local P1 lattice), conduit only
+    long long zo;               // offset of the sample's block in the per-sample field arena (doubles)
 };
 
 // Host plan of a run: meshes, partition, per-system tables.

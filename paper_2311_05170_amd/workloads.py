@@ -88,6 +88,30 @@ def config(name):
                 cuts=cuts, prm=prm, dt=dt, steps=steps)
 
 
+def ensemble_samples(n, seed=5):
+    """n seeded parameter samples with the ensemble's ranges: nu logU[1e-3, 1],
+    permeabilities k_F, k_f, k_m logU[1e-5, 1], exchange coefficients sigma*,
+    sigma logU[0.01, 10] (draw order nu, k_F, k_f, k_m, sigma*, sigma per
+    sample); the other parameters are 1."""
+    rng = SplitMix64(seed)
+    out = []
+    for _ in range(n):
+        nu = rng.log_uniform(1e-3, 1.0)
+        k = [rng.log_uniform(1e-5, 1.0) for _ in range(3)]
+        sst = rng.log_uniform(0.01, 10.0)
+        s = rng.log_uniform(0.01, 10.0)
+        out.append(dict(unit_params(), nu=nu, k=k, sigma_star=sst, sigma=s))
+    return out
+
+
+def ensemble(nsamples=32, seed=5):
+    """The parameter ensemble on the 2D geometry of cfg2 (H = 1/8, h = 1/64,
+    8 x 8 subdomains per region, overlap 4 fine cells): nsamples seeded samples
+    (ensemble_samples), dt = 0.01, 10 steps."""
+    cfg = config("cfg2")
+    return dict(cfg, name="ensemble", prm=None, samples=ensemble_samples(nsamples, seed), steps=10)
+
+
 def shifted_small(seed=7):
     """Uneven cores at a size the oracle finishes in seconds: H = 1/4, h = 1/16,
     4 x 4 subdomains per region, overlap 2 fine cells, every interior cut of

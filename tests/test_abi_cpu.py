@@ -79,7 +79,7 @@ def test_binding_structs_match_header(cname, pyname):
     assert [f for f, _ in getattr(lib, pyname)._fields_] == _struct_fields(cname)
 
 
-def _setup_status(opt_kw=None, samples=None, prm_kw=None):
+def _setup_status(opt_kw=None, samples=None, prm_kw=None, dts=None):
     """Call lp_setup with options that it rejects before touching a device."""
     from ctypes import byref, c_void_p
     mesh, part, keep = lib._structs(2, 4, (2, 2), 1, None)
@@ -90,7 +90,8 @@ def _setup_status(opt_kw=None, samples=None, prm_kw=None):
     for k, v in (opt_kw or {}).items():
         setattr(opt, k, v)
     plist = samples or [dict(W.unit_params(), **(prm_kw or {}))]
-    arr = (lib.LpParams * len(plist))(*[lib._params(q, 0.05) for q in plist])
+    dts = dts or [0.05] * len(plist)
+    arr = (lib.LpParams * len(plist))(*[lib._params(q, t) for q, t in zip(plist, dts)])
     h = c_void_p()
     st = lib._LIB.lp_setup(byref(mesh), byref(part), arr, byref(opt), None, None, byref(h))
     assert not h.value
@@ -99,8 +100,9 @@ def _setup_status(opt_kw=None, samples=None, prm_kw=None):
 
 def test_setup_rejects_bad_options_without_a_device():
     """Argument checks run before any device call: unknown option values and
-    invalid parameters are LP_ERR_ARG, requests this build does not implement
-    (more than one sample, Krylov local solves, the semi-implicit coarse step)
+    invalid parameters (and samples with different dt) are LP_ERR_ARG, requests
+    this build does not implement (several samples with the Krylov path,
+    graphs, autotuning or Algorithm 1; the semi-implicit coarse step)
     LP_ERR_UNSUPPORTED."""
     assert _setup_status({"solver": 7})[0] == 1
     assert _setup_status({"coarse_ns": 3})[0] == 1
@@ -111,7 +113,10 @@ def test_setup_rejects_bad_options_without_a_device():
     assert st == 1 and "sample 0" in msg
     st, msg = _setup_status({"nsamples": 2}, samples=[W.unit_params(), dict(W.unit_params(), k=[0.0, 1, 1])])
     assert st == 1 and "sample 1" in msg          # every sample is validated
-    assert _setup_status({"nsamples": 2}, samples=[W.unit_params()] * 2)[0] == 6
+    st, msg = _setup_status({"nsamples": 2}, samples=[W.unit_params(), W.unit_params()], dts=[0.05, 0.02])
+    assert st == 1 and "dt" in msg                # samples share one time grid
+    for kw in ({"solver": lib.LP_KRYLOV}, {"graphs": 1}, {"autotune": 1}, {"scheme": lib.LP_ONE_GRID}):
+        assert _setup_status(dict(kw, nsamples=2), samples=[W.unit_params()] * 2)[0] == 6, kw
     assert _setup_status({"solver": lib.LP_KRYLOV, "max_iter": 65})[0] == 1
     assert _setup_status({"solver": lib.LP_KRYLOV, "krylov_tol": 0.0})[0] == 1
     assert _setup_status({"krylov_cycles": 5})[0] == 1            # more cycles than refinement sweeps
