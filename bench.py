@@ -243,13 +243,14 @@ def serial_lu_time(cfg, precision, max_ir, steps=SERIAL_STEPS):
     return ms / max(n, 1), n
 
 
-def ensemble_run(L, lu_bytes):
+def ensemble_run(L, lu_bytes, lean=False):
     """The parameter ensemble (ENSEMBLE_SAMPLES seeded samples on the cfg2
     geometry, dt = 0.01, 10 steps): one context holding every sample, so that
     each launch covers all samples' systems, against the same samples stepped
     one context after another (each context's setup outside its timed steps).
     Also the ensemble's local Oseen factorisation timed on an uncontended
-    stream, as the roofline pass does for one sample."""
+    stream, as the roofline pass does for one sample.  lean: the mixed
+    ensemble pass and the factorisation pass only (profiling runs)."""
     import torch
     from paper_2311_05170_amd import workloads as W
     from paper_2311_05170_amd.lib import LocalParallel
@@ -278,7 +279,7 @@ def ensemble_run(L, lu_bytes):
            "samples": S, "steps": ENSEMBLE_STEPS, "warmup": ENSEMBLE_WARMUP,
            "max_ir": ENSEMBLE_MAX_IR, "max_newton": ENSEMBLE_MAX_NEWTON, "jacobian_every": ENSEMBLE_JACOBIAN_EVERY,
            "local_dofs_per_step": S * L}
-    for prec in ("mixed", "fp64"):
+    for prec in ("mixed",) if lean else ("mixed", "fp64"):
         t0 = time.perf_counter()
         g = build(samples, prec)
         torch.cuda.synchronize()
@@ -286,11 +287,13 @@ def ensemble_run(L, lu_bytes):
         ms = clock(g)
         st = g.stats()
         g.close()
-        seq = 0.0
-        for q in samples:
-            h = build([q], prec)
-            seq += clock(h)
-            h.close()
+        seq = float("nan")
+        if not lean:
+            seq = 0.0
+            for q in samples:
+                h = build([q], prec)
+                seq += clock(h)
+                h.close()
         out[prec] = {"value": S * L / (ms * 1e-3), "ms_per_step": ms, "setup_s": setup_s,
                      "sequential_value": S * L / (seq * 1e-3), "sequential_ms_per_step": seq,
                      "speedup_vs_sequential": seq / ms,
@@ -567,6 +570,8 @@ def main():
     ap.add_argument("--cpu-pool", type=int, default=1, help=argparse.SUPPRESS)
     ap.add_argument("--summarize-trace", default=None, metavar="KERNEL_TRACE_CSV",
                     help="print per-kernel averages of a rocprofv3 kernel trace of this script and exit")
+    ap.add_argument("--trace-last", type=int, default=SERIAL_STEPS,
+                    help="with --summarize-trace: launches of the roofline kernel in the final uncontended pass")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (HBM counter calibration)")
     args = ap.parse_args()
@@ -577,7 +582,7 @@ def main():
         calibrate_copy()
         return
     if args.summarize_trace:
-        summarize_trace(args.summarize_trace)
+        summarize_trace(args.summarize_trace, args.trace_last)
         return
     if args.uneven_only:
         import torch
@@ -610,7 +615,7 @@ def main():
     lu_bytes = float((ose[:, 0] * (2 * ose[:, 1] + 1) * 4 + (2 * ose[:, 0] * ose[:, 1] + ose[:, 0]) * 4).sum())
 
     if args.ensemble_only:
-        print(json.dumps({"ensemble": ensemble_run(L, lu_bytes)}), flush=True)
+        print(json.dumps({"ensemble": ensemble_run(L, lu_bytes, lean=args.lean)}), flush=True)
         return
     t_start = time.perf_counter()
 

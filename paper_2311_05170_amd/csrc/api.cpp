@@ -222,6 +222,7 @@ struct lp_ctx {
     // largest local P2 lattice per batch (node blocks of the gather kernels)
     int nodes_por = 0, nodes_ose = 0, nodes_cpor = 0, nodes_cns = 0;
     int tiles_ose = 0, tiles_por = 0;  // most residual tiles of a local Oseen / porous box
+    int rblk_ose = 0, rblk_por = 0;    // residual blocks per box (each takes every rblk-th tile)
     // residual norm partials and arrival counters, one set per batch (the
     // batches run on different streams)
     double *part_por = nullptr, *part_ose = nullptr, *part_cp = nullptr, *part_cn = nullptr;
@@ -494,7 +495,7 @@ lp_status refine_porous(lp_ctx *c, const lp::SysDesc *d_sys, int nsys, int maxno
         StageTimer tm(c, timed ? LP_T_POR_RES : -1, st);
         lp::ResidualArgs ra{d_sys, c->d_dof2, x, b, r, conv, rel, sw, tol, nullptr, part, ticket};
         ra.co = c->d_co;
-        lp::launch_porous_residual_tiled(ra, nsys, c->tiles_por, st);
+        lp::launch_porous_residual_tiled(ra, nsys, c->rblk_por, st);
     }
     return LP_OK;
 }
@@ -519,7 +520,7 @@ lp_status refine_oseen(lp_ctx *c, const lp::SysDesc *d_sys, int nsys, int maxnod
         ra.x = x; ra.b = b; ra.r = r; ra.band = nullptr;
         ra.conv = conv; ra.relres = rel; ra.sweeps = sw; ra.tol = tol; ra.skip = skip;
         ra.part = part; ra.ticket = ticket;
-        lp::launch_oseen_residual_tiled(ra, nsys, c->tiles_ose, st);
+        lp::launch_oseen_residual_tiled(ra, nsys, c->rblk_ose, st);
     }
     return LP_OK;
 }
@@ -552,7 +553,7 @@ lp_status refine_oseen_krylov(lp_ctx *c, double *part, int *ticket, const double
                     return fail(LP_ERR_UNSUPPORTED, "strip bandwidth too large for the solve kernels");
                 lp::launch_strip_scatter(sa, nstrip, c->gm_Z + k * nt, st);
                 mv.x = c->gm_Z + k * nt;
-                lp::launch_oseen_residual_tiled(mv, nsys, c->tiles_ose, st);
+                lp::launch_oseen_residual_tiled(mv, nsys, c->rblk_ose, st);
                 if (!lp::launch_gm_arnoldi(ga, nsys, c->maxn_ose, k, c->gm_w, st))
                     return fail(LP_ERR_UNSUPPORTED, "local Oseen system too large for the Arnoldi kernel");
             }
@@ -566,7 +567,7 @@ lp_status refine_oseen_krylov(lp_ctx *c, double *part, int *ticket, const double
         ra.x = c->x_ose; ra.b = c->b_ose; ra.r = c->r_ose; ra.band = nullptr;
         ra.conv = c->conv_ose; ra.relres = c->rel_ose; ra.sweeps = c->sw_ose; ra.tol = c->opt.ir_tol; ra.skip = nullptr;
         ra.part = part; ra.ticket = ticket;
-        lp::launch_oseen_residual_tiled(ra, nsys, c->tiles_ose, st);
+        lp::launch_oseen_residual_tiled(ra, nsys, c->rblk_ose, st);
     }
     return LP_OK;
 }
@@ -878,7 +879,7 @@ lp_status autotune(lp_ctx *c, hipStream_t st) {
         mv.sys = c->d_ose; mv.cls2 = c->d_cls2; mv.dof2 = c->d_dof2; mv.dof1 = c->d_dof1;
         mv.W1[0] = Wx; mv.W1[1] = Wy;
         mv.x = c->x_ose; mv.b = nullptr; mv.r = c->b_ose; mv.conv = nullptr;
-        lp::launch_oseen_residual_tiled(mv, nsys, c->tiles_ose, st);
+        lp::launch_oseen_residual_tiled(mv, nsys, c->rblk_ose, st);
     }
     // x = 0, r = b, flags cleared: the state a local step's right-hand side kernel leaves
     auto reset = [&]() -> lp_status {
@@ -1173,6 +1174,24 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
         c->tiles_por = std::max(c->tiles_por, lp::residual_tiles(s.cx, s.cy));
     }
     for (const auto &s : P.ose) c->nodes_ose = std::max(c->nodes_ose, s.lw2 * s.lh2);
+    // residual blocks per box: enough for about two blocks per compute unit,
+    // and no more, since every block beyond the first of a box ends with a
+    // device-scope fence and ticket for the box's norm (costly when
+    // thousands of blocks do it at once)
+    {
+        const long long nbox_por = (long long)P.por.size() * std::max(nsam, 1), nbox_ose = (long long)P.ose.size() * std::max(nsam, 1);
+        auto per_box = [](long long nbox, int tiles) {
+            const long long want = (lp::RESIDUAL_BLOCKS_TARGET + nbox - 1) / std::max(nbox, 1LL);
+            return (int)std::max(1LL, std::min<long long>(tiles, want));
+        };
+        c->rblk_por = per_box(nbox_por, c->tiles_por);
+        c->rblk_ose = per_box(nbox_ose, c->tiles_ose);
+    }
+    if (const char *v = std::getenv("LP_RES_BLOCKS")) {
+        const int k = std::max(1, std::atoi(v));
+        c->rblk_por = std::min(c->rblk_por, k);
+        c->rblk_ose = std::min(c->rblk_ose, k);
+    }
     c->nodes_cpor = P.cpor.lw2 * P.cpor.lh2;
     c->nodes_cns = P.cns.lw2 * P.cns.lh2;
     // local Oseen solver: the band factorisation where the half-bandwidth fits

@@ -286,6 +286,19 @@ __device__ void grid_norms_and_flag(double rr, double bb, double *part, int *tic
     const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
     if ((threadIdx.x & 63) == 0) { s1[w] = rr; s2[w] = bb; }
     __syncthreads();
+    if (gridDim.x == 1) {
+        // the whole system in this block: no partials, ticket or fence
+        if (threadIdx.x == 0) {
+            double a = 0.0, b = 0.0;
+            for (int i = 0; i < nw; ++i) { a += s1[i]; b += s2[i]; }
+            const double rel = b > 0.0 ? sqrt(a / b) : 0.0;
+            relres[id] = rel;
+            sweeps[id] += 1;
+            if (rel <= tol) conv[id] = 1;
+        }
+        __syncthreads();                    // s1, s2 free for the next call
+        return;
+    }
     const long long base = 2LL * id * gridDim.x;
     if (threadIdx.x == 0) {
         double a = 0.0, b = 0.0;
@@ -703,7 +716,9 @@ __global__ __launch_bounds__(GB) void k_oseen_assemble(OseenApplyArgs<T> A) {
 // convection term shared by them) into LDS; then every node of the tile adds
 // the contributions of its triangles in the node-thread order, so a node's
 // sum does not depend on the tiling.  Blocks past a box's tile count only
-// take part in the norm reduction.
+// take part in the norm reduction.  A block takes tiles blockIdx.x,
+// blockIdx.x + gridDim.x, ... of its box; with one block per box the norms
+// are finished in the block.
 constexpr int RT = 8;
 constexpr int RT_TRI = 2 * (RT + 1) * (RT + 1);
 int residual_tiles(int cx, int cy) { return ((cx + RT - 1) / RT) * ((cy + RT - 1) / RT); }
@@ -716,9 +731,6 @@ __global__ __launch_bounds__(256) void k_oseen_residual_tiled(OseenApplyArgs<dou
     if (A.skip && A.skip[S.sample]) return;
     if (A.conv && A.conv[blockIdx.y]) return;
     const int ntx = (S.cx + RT - 1) / RT, nty = (S.cy + RT - 1) / RT;
-    const bool has = (int)blockIdx.x < ntx * nty;
-    const int tx = has ? (int)blockIdx.x % ntx : 0, ty = has ? (int)blockIdx.x / ntx : 0;
-    const int ci_lo = tx * RT - 1, cj_lo = ty * RT - 1;    // first (halo) cell of the tile's triangles
     const int ng = 2 * S.N + 1;
     const double h = S.h, h2 = h * h;
     const double eta = cf.eta, edt = cf.eta / cf.dt, nue = cf.nu * cf.eta;
@@ -726,7 +738,11 @@ __global__ __launch_bounds__(256) void k_oseen_residual_tiled(OseenApplyArgs<dou
     __shared__ double cv[RT_TRI][6][2];     // velocity rows: (triangle, its node la, component)
     __shared__ double cp[RT_TRI][3];        // pressure rows: (triangle, its vertex)
     const int tid = threadIdx.x;
-    if (has) {
+    double rr = 0.0, bb = 0.0;
+    for (int tile = blockIdx.x; tile < ntx * nty; tile += gridDim.x) {
+        const int tx = tile % ntx, ty = tile / ntx;
+        const int ci_lo = tx * RT - 1, cj_lo = ty * RT - 1;    // first (halo) cell of the tile's triangles
+        if (tile != (int)blockIdx.x) __syncthreads();          // the previous tile's node pass is done with LDS
         for (int e = tid; e < RT_TRI; e += blockDim.x) {
             const int t = e & 1, cc = e >> 1;
             const int ci = ci_lo + cc % (RT + 1), cj = cj_lo + cc / (RT + 1);
@@ -793,10 +809,7 @@ __global__ __launch_bounds__(256) void k_oseen_residual_tiled(OseenApplyArgs<dou
                 cp[e][v] = eta * h * sv;
             }
         }
-    }
-    __syncthreads();
-    double rr = 0.0, bb = 0.0;
-    if (has) {
+        __syncthreads();
         // nodes of the tile: lattice columns 2 RT tx .. (the last tile to the box's edge)
         const int a0 = 2 * RT * tx, a1 = tx == ntx - 1 ? 2 * S.cx : 2 * RT * (tx + 1) - 1;
         const int b0 = 2 * RT * ty, b1 = ty == nty - 1 ? 2 * S.cy : 2 * RT * (ty + 1) - 1;
@@ -1014,9 +1027,6 @@ __global__ __launch_bounds__(256) void k_porous_residual_tiled(ResidualArgs R) {
     for (int f = 0; f < 3; ++f) act[f] = !R.conv[id0 + f];
     if (!act[0] && !act[1] && !act[2]) return;
     const int ntx = (S.cx + RT - 1) / RT, nty = (S.cy + RT - 1) / RT;
-    const bool has = (int)blockIdx.x < ntx * nty;
-    const int tx = has ? (int)blockIdx.x % ntx : 0, ty = has ? (int)blockIdx.x / ntx : 0;
-    const int ci_lo = tx * RT - 1, cj_lo = ty * RT - 1;
     const double h2 = S.h * S.h;
     double cm[3], ck[3];
     for (int f = 0; f < 3; ++f) { cm[f] = (cf.tau[f] + porous_x(cf, f)) * h2; ck[f] = cf.kap[f]; }
@@ -1025,7 +1035,11 @@ __global__ __launch_bounds__(256) void k_porous_residual_tiled(ResidualArgs R) {
     const long long nd = S.ndof;
     __shared__ double cy[RT_TRI][6][3];     // (triangle, its node la, field)
     const int tid = threadIdx.x;
-    if (has) {
+    double rr[3] = {0.0, 0.0, 0.0}, bb[3] = {0.0, 0.0, 0.0};
+    for (int tile = blockIdx.x; tile < ntx * nty; tile += gridDim.x) {
+        const int tx = tile % ntx, ty = tile / ntx;
+        const int ci_lo = tx * RT - 1, cj_lo = ty * RT - 1;
+        if (tile != (int)blockIdx.x) __syncthreads();          // the previous tile's node pass is done with LDS
         for (int e = tid; e < RT_TRI; e += blockDim.x) {
             const int t = e & 1, cc = e >> 1;
             const int ci = ci_lo + cc % (RT + 1), cj = cj_lo + cc / (RT + 1);
@@ -1044,10 +1058,7 @@ __global__ __launch_bounds__(256) void k_porous_residual_tiled(ResidualArgs R) {
                 for (int f = 0; f < 3; ++f) cy[e][l][f] = y[f];
             }
         }
-    }
-    __syncthreads();
-    double rr[3] = {0.0, 0.0, 0.0}, bb[3] = {0.0, 0.0, 0.0};
-    if (has) {
+        __syncthreads();
         const int a0 = 2 * RT * tx, a1 = tx == ntx - 1 ? 2 * S.cx : 2 * RT * (tx + 1) - 1;
         const int b0 = 2 * RT * ty, b1 = ty == nty - 1 ? 2 * S.cy : 2 * RT * (ty + 1) - 1;
         const int wa = a1 - a0 + 1, cnt = wa * (b1 - b0 + 1);
@@ -2672,8 +2683,8 @@ void launch_porous_rhs(const PorousArgs &a, int nsys, int maxnodes, int split, h
 void launch_porous_rhs_tiled(const PorousArgs &a, int nsys, int maxtiles, hipStream_t st) {
     hipLaunchKernelGGL(k_porous_rhs_tiled, dim3(maxtiles > 0 ? maxtiles : 1, nsys), dim3(256), 0, st, a);
 }
-void launch_porous_residual_tiled(const ResidualArgs &a, int nsys, int maxtiles, hipStream_t st) {
-    hipLaunchKernelGGL(k_porous_residual_tiled, dim3(maxtiles > 0 ? maxtiles : 1, nsys), dim3(256), 0, st, a);
+void launch_porous_residual_tiled(const ResidualArgs &a, int nsys, int blocks, hipStream_t st) {
+    hipLaunchKernelGGL(k_porous_residual_tiled, dim3(blocks > 0 ? blocks : 1, nsys), dim3(256), 0, st, a);
 }
 void launch_porous_finalize(const FinalizeArgs &a, int nsys, int maxnodes, hipStream_t st) {
     hipLaunchKernelGGL(k_porous_finalize, dim3(node_blocks(maxnodes), nsys), dim3(GB), 0, st, a);
@@ -2697,8 +2708,8 @@ void launch_oseen_rows(const OseenApplyArgs<T> &a, int nsys, int maxnodes, int m
 void launch_oseen_rhs_tiled(const OseenArgs &a, int nsys, int maxtiles, hipStream_t st) {
     hipLaunchKernelGGL(k_oseen_rhs_tiled, dim3(maxtiles > 0 ? maxtiles : 1, nsys), dim3(256), 0, st, a);
 }
-void launch_oseen_residual_tiled(const OseenApplyArgs<double> &a, int nsys, int maxtiles, hipStream_t st) {
-    hipLaunchKernelGGL(k_oseen_residual_tiled, dim3(maxtiles > 0 ? maxtiles : 1, nsys), dim3(256), 0, st, a);
+void launch_oseen_residual_tiled(const OseenApplyArgs<double> &a, int nsys, int blocks, hipStream_t st) {
+    hipLaunchKernelGGL(k_oseen_residual_tiled, dim3(blocks > 0 ? blocks : 1, nsys), dim3(256), 0, st, a);
 }
 void launch_oseen_finalize(const FinalizeArgs &a, int nsys, int maxnodes, hipStream_t st) {
     hipLaunchKernelGGL(k_oseen_finalize, dim3(node_blocks(maxnodes), nsys), dim3(GB), 0, st, a);
