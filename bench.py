@@ -497,11 +497,14 @@ def traffic_for(kernel, workload):
     return None
 
 
-def summarize_trace(path, last=SERIAL_STEPS):
+def summarize_trace(path, last=SERIAL_STEPS, split=False):
     """Per-kernel launch counts and average durations from a rocprofv3
     kernel-trace CSV, and for the roofline kernel the average of its last
     `last` launches (the uncontended pass that bench.py times with events)
-    beside that of its earlier, overlapped ones."""
+    beside that of its earlier, overlapped ones.  split: also every kernel's
+    time per step over the steps of those last launches (from the end of the
+    launch before them to the end of the trace; meaningful when that pass is
+    the run's last, as with --lean)."""
     import csv
     import re
     rows = list(csv.DictReader(open(path)))
@@ -522,6 +525,19 @@ def summarize_trace(path, last=SERIAL_STEPS):
             print("\nroofline kernel %s: last %d launches (LP_SERIAL pass) avg %.1f us; earlier %d launches "
                   "(overlapped schedule) avg %.1f us" % (k, last, sum(d[-last:]) / last, len(d) - last,
                                                          sum(d[:-last]) / max(len(d) - last, 1)))
+            if split and len(v) > last:
+                t0 = v[-last - 1][1]
+                win = [(b, e, name) for name, lst in by.items() for b, e in lst if b > t0]
+                tw = {}
+                for b, e, name in win:
+                    tw[name] = tw.get(name, 0) + (e - b)
+                span = (max(e for _, e, _ in win) - min(b for b, _, _ in win)) / 1e6
+                print("\nUncontended pass, per step (%d steps, %.2f ms span, %.2f ms of kernels):\n"
+                      % (last, span, sum(tw.values()) / 1e6))
+                print("| kernel | ms per step |")
+                print("|---|---:|")
+                for name in sorted(tw, key=lambda n: -tw[n]):
+                    print("| %s | %.3f |" % (name.replace("|", "/")[:110], tw[name] / 1e6 / last))
 
 
 def host_cores():
@@ -572,6 +588,8 @@ def main():
                     help="print per-kernel averages of a rocprofv3 kernel trace of this script and exit")
     ap.add_argument("--trace-last", type=int, default=SERIAL_STEPS,
                     help="with --summarize-trace: launches of the roofline kernel in the final uncontended pass")
+    ap.add_argument("--trace-split", action="store_true",
+                    help="with --summarize-trace: per-step kernel times of that final pass")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (HBM counter calibration)")
     args = ap.parse_args()
@@ -582,7 +600,7 @@ def main():
         calibrate_copy()
         return
     if args.summarize_trace:
-        summarize_trace(args.summarize_trace, args.trace_last)
+        summarize_trace(args.summarize_trace, args.trace_last, args.trace_split)
         return
     if args.uneven_only:
         import torch
