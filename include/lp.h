@@ -353,6 +353,31 @@ lp_status lp_get_timing(lp_ctx *ctx, double *ms, int64_t *launches, int32_t n);
  * context holds more than one sample. */
 lp_status lp_local_step_noalloc(lp_ctx *ctx, void *stream);
 
+/* Checkpoint and resume of a run between steps (no coarse step pending).
+ * The state is what the next steps read: the coarse states of the last
+ * levels (Algorithm 3 Step 1 lags them and starts Newton from them), the
+ * local corrections e_j^n that Step 3 reads back (Eqs. (5.5)-(5.8)), the
+ * merged fields of Step 4, the coarse Jacobian inverse in use when
+ * jacobian_every > 1, the time-level counters, the coarse Newton status and
+ * the sticky flags and run-long maxima of lp_get_stats; prolongations,
+ * factorisations and right-hand sides are rebuilt by the next step.  A
+ * context set up with the same mesh, partition, samples (parameters and dt)
+ * and options continues from it exactly where the saving one would have:
+ * the same fields, bit for bit, when the same kernel variants run (the
+ * autotuner may choose others on another run).
+ *   lp_state_size: bytes of the state of `ctx` (no device call).
+ *   lp_save_state: writes it into `buf` (host memory, `len` bytes, owned by
+ *     the caller); waits for `stream` and the device.
+ *   lp_load_state: replaces the state of `ctx` by `buf`'s; the step count
+ *     continues from the saved one.
+ * Errors: LP_ERR_ARG (NULL, `len` too short, a buffer that is not a saved
+ * state or was saved by a context of another mesh, partition, sample set,
+ * precision, scheme or jacobian_every), LP_ERR_STATE (a coarse step is
+ * pending), LP_ERR_DEVICE. */
+lp_status lp_state_size(lp_ctx *ctx, int64_t *bytes);
+lp_status lp_save_state(lp_ctx *ctx, void *buf, int64_t len, void *stream);
+lp_status lp_load_state(lp_ctx *ctx, const void *buf, int64_t len, void *stream);
+
 void lp_destroy(lp_ctx *ctx);
 
 const char *lp_last_error(void);

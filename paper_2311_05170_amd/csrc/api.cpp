@@ -72,6 +72,7 @@ struct lp_ctx {
     lp::Coef co{};
     lp::RefData ref{};
     lp_params prm{};
+    std::vector<lp_params> samples_h;  // every sample's parameters, as given to lp_setup
     lp_options opt{};
     lp_allocator alloc{};
     bool has_alloc = false;
@@ -1154,6 +1155,7 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     TRY(init_static_scratch(c->device));
     if (!lp::build_plan(*mesh, *part, c->P, why)) return fail(LP_ERR_ARG, why);
     c->prm = *prm;
+    c->samples_h.assign(samples, samples + nsam);
     c->opt = *opt;
     c->mixed = opt->precision == LP_MIXED;
     c->one_grid = opt->scheme == LP_ONE_GRID;
@@ -2010,6 +2012,126 @@ lp_status lp_get_timing(lp_ctx *c, double *ms, int64_t *launches, int32_t n) {
     }
     c->recs.clear();
     for (int i = 0; i < n; ++i) { ms[i] = c->tms[i]; launches[i] = c->tcnt[i]; }
+    return LP_OK;
+}
+
+namespace {
+// A run's state between steps, in the order it is written: a header, every
+// sample's parameters, then the device segments below.  The prolonged fields,
+// factors and right-hand sides are rebuilt by the next step and not kept.
+struct StateHeader {
+    char magic[8];
+    int64_t n;                         // completed steps
+    int32_t ecur, ns, mixed, scheme, jev, pad;
+    int64_t Nh, NH, np1, no1, zs, e2_total, e1_total, inv_len, local_dofs;
+};
+struct Seg { void *dev; size_t bytes; };
+
+std::vector<Seg> state_segments(lp_ctx *c) {
+    const int jev = c->opt.jacobian_every > 1 ? c->opt.jacobian_every : 1;
+    std::vector<Seg> v;
+    v.push_back({c->arena, (size_t)(c->ns * c->zs) * sizeof(double)});      // coarse ring, merged fields, ...
+    v.push_back({c->e2[c->ecur], (size_t)c->P.e2_total * sizeof(double)});  // e_j^n (P2 lattices)
+    v.push_back({c->e1[c->ecur], (size_t)c->P.e1_total * sizeof(double)});  // e_j^n (pressure, P1)
+    if (jev > 1)                                                             // the Jacobian inverse in use
+        v.push_back({c->inv_cn, (size_t)(c->ns * c->P.cns.ndof * c->P.cns.ndof) * sizeof(double)});
+    v.push_back({c->level_dev, lp_ctx::RING * sizeof(long long)});
+    v.push_back({c->tf_dev, 4 * lp_ctx::RING * sizeof(double)});
+    v.push_back({c->d_done, (size_t)c->ns * sizeof(int)});
+    v.push_back({c->d_its, (size_t)(2 * c->ns) * sizeof(int)});
+    v.push_back({c->d_flags, 4 * sizeof(int)});
+    v.push_back({c->d_lustat, 4 * sizeof(float)});
+    v.push_back({c->d_irmax, sizeof(int)});
+    v.push_back({c->d_irrel, sizeof(unsigned long long)});
+    return v;
+}
+
+size_t pad8(size_t b) { return (b + 7) / 8 * 8; }
+
+StateHeader state_header(lp_ctx *c) {
+    StateHeader h{};
+    std::memcpy(h.magic, "LPSTATE1", 8);
+    h.n = c->n;
+    h.ecur = c->ecur;
+    h.ns = c->ns;
+    h.mixed = c->mixed ? 1 : 0;
+    h.scheme = c->one_grid ? LP_ONE_GRID : LP_TWO_GRID;
+    h.jev = c->opt.jacobian_every > 1 ? c->opt.jacobian_every : 1;
+    h.Nh = c->P.Nh; h.NH = c->P.NH;
+    h.np1 = c->np1; h.no1 = c->no1;
+    h.zs = c->zs;
+    h.e2_total = c->P.e2_total; h.e1_total = c->P.e1_total;
+    h.inv_len = h.jev > 1 ? (int64_t)c->ns * c->P.cns.ndof * c->P.cns.ndof : 0;
+    h.local_dofs = c->P.local_dofs;
+    return h;
+}
+
+size_t state_bytes(lp_ctx *c) {
+    size_t b = pad8(sizeof(StateHeader)) + pad8(c->samples_h.size() * sizeof(lp_params));
+    for (const Seg &g : state_segments(c)) b += pad8(g.bytes);
+    return b;
+}
+}  // namespace
+
+lp_status lp_state_size(lp_ctx *c, int64_t *bytes) {
+    if (!c || !bytes) return fail(LP_ERR_ARG, "NULL argument");
+    *bytes = (int64_t)state_bytes(c);
+    return LP_OK;
+}
+
+lp_status lp_save_state(lp_ctx *c, void *buf, int64_t len, void *stream) {
+    if (!c || !buf) return fail(LP_ERR_ARG, "NULL argument");
+    if (c->coarse_pending) return fail(LP_ERR_STATE, "a coarse step is pending: save between steps");
+    const size_t need = state_bytes(c);
+    if (len < (int64_t)need) return fail(LP_ERR_ARG, "state buffer too short (" + std::to_string(need) + " bytes needed)");
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    HIPCHK(hipDeviceSynchronize());                 // every internal stream's work of the last step
+    char *p = (char *)buf;
+    std::memset(p, 0, need);
+    const StateHeader h = state_header(c);
+    std::memcpy(p, &h, sizeof(h));
+    p += pad8(sizeof(StateHeader));
+    std::memcpy(p, c->samples_h.data(), c->samples_h.size() * sizeof(lp_params));
+    p += pad8(c->samples_h.size() * sizeof(lp_params));
+    for (const Seg &g : state_segments(c)) {
+        if (g.bytes) HIPCHK(hipMemcpy(p, g.dev, g.bytes, hipMemcpyDeviceToHost));
+        p += pad8(g.bytes);
+    }
+    return LP_OK;
+}
+
+lp_status lp_load_state(lp_ctx *c, const void *buf, int64_t len, void *stream) {
+    if (!c || !buf) return fail(LP_ERR_ARG, "NULL argument");
+    if (c->coarse_pending) return fail(LP_ERR_STATE, "a coarse step is pending: load between steps");
+    if (len < (int64_t)sizeof(StateHeader)) return fail(LP_ERR_ARG, "state buffer too short");
+    StateHeader h;
+    std::memcpy(&h, buf, sizeof(h));
+    if (std::memcmp(h.magic, "LPSTATE1", 8) != 0) return fail(LP_ERR_ARG, "not a saved state");
+    StateHeader mine = state_header(c);
+    mine.n = h.n;
+    mine.ecur = h.ecur;
+    if (std::memcmp(&h, &mine, sizeof(h)) != 0)
+        return fail(LP_ERR_ARG, "the state was saved by a context of another mesh, partition, sample count, "
+                                "precision, scheme or jacobian_every");
+    const char *p = (const char *)buf + pad8(sizeof(StateHeader));
+    if (len < (int64_t)(pad8(sizeof(StateHeader)) + c->samples_h.size() * sizeof(lp_params)))
+        return fail(LP_ERR_ARG, "state buffer too short");
+    if (std::memcmp(p, c->samples_h.data(), c->samples_h.size() * sizeof(lp_params)) != 0)
+        return fail(LP_ERR_ARG, "the state was saved with other parameters");
+    if (h.n < 0 || (h.ecur != 0 && h.ecur != 1)) return fail(LP_ERR_ARG, "corrupt state header");
+    if (len < (int64_t)state_bytes(c)) return fail(LP_ERR_ARG, "state buffer too short");
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+    HIPCHK(hipDeviceSynchronize());
+    c->ecur = h.ecur;                               // the segments name e2/e1[ecur]
+    p += pad8(c->samples_h.size() * sizeof(lp_params));
+    for (const Seg &g : state_segments(c)) {
+        if (g.bytes) HIPCHK(hipMemcpy(g.dev, p, g.bytes, hipMemcpyHostToDevice));
+        p += pad8(g.bytes);
+    }
+    HIPCHK(hipDeviceSynchronize());
+    c->n = h.n;
     return LP_OK;
 }
 

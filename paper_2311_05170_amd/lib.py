@@ -36,7 +36,8 @@ LP_ERR_NOCONV = 5
 
 EXPORTS = ["lp_setup", "lp_coarse_step", "lp_local_step", "lp_get_size", "lp_get_solution",
            "lp_get_stats", "lp_plan_query", "lp_get_index_map", "lp_set_timing", "lp_get_timing",
-           "lp_local_step_noalloc", "lp_band_factor_solve", "lp_destroy", "lp_last_error"]
+           "lp_local_step_noalloc", "lp_band_factor_solve", "lp_state_size", "lp_save_state",
+           "lp_load_state", "lp_destroy", "lp_last_error"]
 # stage timer indices (LP_T_* in lp.h)
 STAGES = ["prolong", "por_rhs", "por_solve", "por_res", "ose_rhs", "ose_asm", "ose_lu", "ose_solve",
           "ose_res", "merge", "coarse", "wait_coarse", "wait_fac", "wait_por"]
@@ -113,6 +114,9 @@ def load(path=LIB_PATH):
     lib.lp_band_factor_solve.argtypes = [c_int32, c_int32, c_int32, POINTER(c_double), POINTER(c_double),
                                          POINTER(c_double), c_int32, c_int32, POINTER(c_int32), POINTER(c_double),
                                          POINTER(c_double)]
+    lib.lp_state_size.argtypes = [c_void_p, POINTER(c_int64)]
+    lib.lp_save_state.argtypes = [c_void_p, c_void_p, c_int64, c_void_p]
+    lib.lp_load_state.argtypes = [c_void_p, c_void_p, c_int64, c_void_p]
     lib.lp_destroy.argtypes = [c_void_p]
     lib.lp_destroy.restype = None
     lib.lp_last_error.restype = c_char_p
@@ -266,6 +270,20 @@ class LocalParallel:
         _check(_LIB.lp_get_solution(self._h, sample, FIELD[field], LEVEL[level], sub,
                                     ctypes.cast(out.data_ptr(), POINTER(c_double)), n, 1, self._s()))
         return out
+
+    def save_state(self):
+        """The run's state between steps (lp_save_state) as bytes."""
+        n = c_int64(0)
+        _check(_LIB.lp_state_size(self._h, byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        _check(_LIB.lp_save_state(self._h, buf, n.value, self._s()))
+        return buf.raw
+
+    def load_state(self, state):
+        """Continue from a state saved by a context built with the same
+        arguments (lp_load_state)."""
+        buf = ctypes.create_string_buffer(bytes(state), len(state))
+        _check(_LIB.lp_load_state(self._h, buf, len(state), self._s()))
 
     def index_map(self, which, sub=0):
         """The context's own partition and numbering tables (see lp_plan_query)."""
