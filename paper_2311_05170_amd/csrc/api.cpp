@@ -223,6 +223,10 @@ struct lp_ctx {
     // largest local P2 lattice per batch (node blocks of the gather kernels)
     int nodes_por = 0, nodes_ose = 0, nodes_cpor = 0, nodes_cns = 0;
     int tiles_ose = 0, tiles_por = 0;  // most residual tiles of a local Oseen / porous box
+    // local Oseen assembly into bands cleared once at setup, each entry's
+    // first element storing instead of adding (LP_OSEEN_ASM=0: cleared and
+    // read back every step)
+    bool asm_first_write = true;
     int rblk_ose = 0, rblk_por = 0;    // residual blocks per box (each takes every rblk-th tile)
     // residual norm partials and arrival counters, one set per batch (the
     // batches run on different streams)
@@ -666,11 +670,12 @@ lp_status factor_oseen(lp_ctx *c, int64_t m) {
     TRY(seg(c, gkey(G_FACTOR, m), st, [&](hipStream_t s) -> lp_status {
         {
             StageTimer tm(c, LP_T_OSE_ASM, s);
-            // the band is cleared by a kernel (a memset node would not replay
-            // reliably in a graph)
-            lp::launch_zero_fill(band, (size_t)c->P.band_total_ose * sizeof(T), s);
+            // without first writes the band is cleared by a kernel (a memset
+            // node would not replay reliably in a graph)
+            if (!c->asm_first_write) lp::launch_zero_fill(band, (size_t)c->P.band_total_ose * sizeof(T), s);
             lp::OseenApplyArgs<T> aa{};
             aa.co = c->d_co;
+            aa.first_write = c->asm_first_write ? 1 : 0;
             aa.sys = c->d_ose; aa.cls2 = c->d_cls2; aa.dof2 = c->d_dof2; aa.dof1 = c->d_dof1;
             aa.W1[0] = pro_Uf; aa.W1[1] = pro_Uf + c->nf2; aa.band = band;
             lp::launch_oseen_assemble<T>(aa, nsys, c->nodes_ose, s);
@@ -895,9 +900,10 @@ lp_status autotune(lp_ctx *c, hipStream_t st) {
         T *band = (T *)c->band_ose[0];
         T *fac = (T *)c->fac_ose[0];
         auto factor = [&](int variant) -> lp_status {
-            lp::launch_zero_fill(band, (size_t)c->P.band_total_ose * sizeof(T), st);
+            if (!c->asm_first_write) lp::launch_zero_fill(band, (size_t)c->P.band_total_ose * sizeof(T), st);
             lp::OseenApplyArgs<T> aa{};
             aa.co = c->d_co;
+            aa.first_write = c->asm_first_write ? 1 : 0;
             aa.sys = c->d_ose; aa.cls2 = c->d_cls2; aa.dof2 = c->d_dof2; aa.dof1 = c->d_dof1;
             aa.W1[0] = Wx; aa.W1[1] = Wy; aa.band = band;
             lp::launch_oseen_assemble<T>(aa, nsys, c->nodes_ose, st);
@@ -1160,6 +1166,7 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     c->mixed = opt->precision == LP_MIXED;
     c->one_grid = opt->scheme == LP_ONE_GRID;
     c->lu_variant_ose = 9;
+    if (const char *v = std::getenv("LP_OSEEN_ASM")) c->asm_first_write = std::atoi(v) != 0;
     if (const char *v = std::getenv("LP_LU_VARIANT")) c->lu_variant = c->lu_variant_ose = c->lu_variant_cns = std::atoi(v);
     if (const char *v = std::getenv("LP_LU_VARIANT_COARSE")) c->lu_variant_cns = std::atoi(v);
     if (const char *v = std::getenv("LP_SOLVE_DEPTH")) c->solve_depth = std::atoi(v);
@@ -1364,6 +1371,8 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
             else if (hipMalloc(&p, P.band_total_ose * tb + 256) != hipSuccess) p = nullptr;
             if (!p) return fail(LP_ERR_ALLOC, "conduit band allocation failed");
             c->owned.push_back(p); c->band_ose[l] = p;
+            // once: entries outside the matrices' pattern stay zero
+            HIPCHK(hipMemsetAsync(p, 0, P.band_total_ose * tb, st));
         }
         if (c->has_alloc) { p = c->alloc.alloc(fl_por.total * tb + 256, c->alloc.user); }
         else if (hipMalloc(&p, fl_por.total * tb + 256) != hipSuccess) p = nullptr;

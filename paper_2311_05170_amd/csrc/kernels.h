@@ -133,6 +133,7 @@ struct OseenApplyArgs {
     int *ticket;
     int no_convection;            // assembly: leave out b_N (the Stokes part of the operator)
     const Coef *co = nullptr;     // the context's coefficients (device)
+    int first_write = 0;          // assembly: the band was cleared once and its pattern is fixed (see k_oseen_assemble)
 };
 
 struct BandSys {

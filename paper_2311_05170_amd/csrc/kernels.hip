@@ -553,7 +553,13 @@ __global__ __launch_bounds__(GB) void k_oseen_rhs(OseenArgs A) {
 }
 
 // Band assembly of the local Oseen operators (T), one thread per node: its
-// rows, added element by element into the cleared band.
+// rows, added element by element.  With first_write the band was cleared
+// once, at setup: the matrices' pattern is the same every step, so entries
+// outside it are still zero, and an entry's first element stores its value
+// (0 + v, the same rounding as adding to the cleared entry) instead of
+// reading the entry back; masks over the node's 5 x 5 lattice neighbourhood
+// record the column nodes earlier elements have touched.  Without it the
+// band is cleared before every assembly and every entry is read back.
 template <typename T>
 __global__ __launch_bounds__(GB) void k_oseen_assemble(OseenApplyArgs<T> A) {
     const SysDesc S = A.sys[blockIdx.y];
@@ -569,6 +575,7 @@ __global__ __launch_bounds__(GB) void k_oseen_assemble(OseenApplyArgs<T> A) {
         T *p = band + (long long)col * ld + (row - col + S.bw);
         *p = (T)((double)*p + v);
     };
+    const bool fw = A.first_write != 0;
     for (int q = blockIdx.x * GB + threadIdx.x; q < nloc; q += gridDim.x * GB) {
         const int a = q % S.lw2, b = q / S.lw2;
         const int cls = A.cls2[S.node_off + q];
@@ -577,7 +584,25 @@ __global__ __launch_bounds__(GB) void k_oseen_assemble(OseenApplyArgs<T> A) {
         const int dv = cls == 0 ? A.dof2[S.node_off + q] : -1;
         const int dp = vertex ? A.dof1[S.vert_off + vq] : -1;
         if (dv < 0 && dp < 0) continue;
+        // column nodes (velocity) and vertices (pressure) touched so far, bit
+        // (qa - a + 2) + 5 (qb - b + 2) of lattice node (qa, qb)
+        unsigned seen_v = 0u, seen_p = 0u;
+        auto nbit = [&](int qa, int qb) { return 1u << ((qa - a + 2) + 5 * (qb - b + 2)); };
         for_elements(a, b, S.cx, S.cy, [&](int t, int ci, int cj, int la) {
+            // bit k of fv / fp: column node / vertex k first met in this element
+            unsigned fv = 0u, fp = 0u;
+            if (fw) {
+                for (int k = 0; k < 6; ++k) {
+                    const unsigned bit = nbit(2 * ci + off2a(t, k), 2 * cj + off2b(t, k));
+                    if (!(seen_v & bit)) fv |= 1u << k;
+                    seen_v |= bit;
+                }
+                for (int k = 0; k < 3; ++k) {
+                    const unsigned bit = nbit(2 * (ci + off1a(t, k)), 2 * (cj + off1b(t, k)));
+                    if (!(seen_p & bit)) fp |= 1u << k;
+                    seen_p |= bit;
+                }
+            }
             double W[2][6];
             int dk[6], pk[3];
             for (int k = 0; k < 6; ++k) {
@@ -633,7 +658,7 @@ __global__ __launch_bounds__(GB) void k_oseen_assemble(OseenApplyArgs<T> A) {
                                     off[4 * k + 2 * c + d] = dk[k] >= 0 ? col * ld + (dv + c - col + S.bw) : 0;
                                 }
 #pragma unroll
-                        for (int i = 0; i < 24; ++i) old[i] = band[off[i]];
+                        for (int i = 0; i < 24; ++i) old[i] = (fv >> (i >> 2)) & 1u ? (T)0 : band[off[i]];
 #pragma unroll
                         for (int k = 0; k < 6; ++k) {
                             if (dk[k] < 0) continue;
@@ -657,7 +682,7 @@ __global__ __launch_bounds__(GB) void k_oseen_assemble(OseenApplyArgs<T> A) {
                             for (int c = 0; c < 2; ++c)
                                 off[2 * v + c] = pk[v] >= 0 ? pk[v] * ld + (dv + c - pk[v] + S.bw) : 0;
 #pragma unroll
-                        for (int i = 0; i < 6; ++i) old[i] = band[off[i]];
+                        for (int i = 0; i < 6; ++i) old[i] = (fp >> (i >> 1)) & 1u ? (T)0 : band[off[i]];
 #pragma unroll
                         for (int v = 0; v < 3; ++v)
                             if (pk[v] >= 0)
@@ -680,7 +705,7 @@ __global__ __launch_bounds__(GB) void k_oseen_assemble(OseenApplyArgs<T> A) {
                             off[2 * k + d] = dk[k] >= 0 ? col * ld + (dp - col + S.bw) : 0;
                         }
 #pragma unroll
-                    for (int i = 0; i < 12; ++i) old[i] = band[off[i]];
+                    for (int i = 0; i < 12; ++i) old[i] = (fv >> (i >> 1)) & 1u ? (T)0 : band[off[i]];
 #pragma unroll
                     for (int k = 0; k < 6; ++k)
                         if (dk[k] >= 0)
@@ -690,7 +715,8 @@ __global__ __launch_bounds__(GB) void k_oseen_assemble(OseenApplyArgs<T> A) {
                 }
             }
         });
-        // Beavers-Joseph term on Gamma edges (x rows, x columns)
+        // Beavers-Joseph term on Gamma edges (x rows, x columns; entries an
+        // element has written)
         if (dv >= 0 && S.gamma && 2 * S.y0 + b == 0) {
             const int A0 = 2 * S.x0 + a;
             const int ne = (A0 & 1) ? 1 : 2;
