@@ -13,12 +13,12 @@ Prints ONE JSON line.  Fields beyond the driver's contract:
   stages_ms       per-step stage split from a separate instrumented pass
   refinement      run-long refinement and Newton statistics of the timed runs
                   (sticky flags: the run exits non-zero if any is raised)
-  accuracy        relative mass-norm error vs the CPU oracle after 2 steps
+  accuracy        relative mass-norm error vs the CPU oracle after CPU_STEPS (6) steps
   roofline        dominant kernel (the local Oseen band factorisation) against
                   its binding roof, plus whole-step roofline fractions of the
                   mixed and FP64 paths
   cpu_baseline    the CPU oracle on the host: a process pool over subdomains
-                  on the host cores (and one thread), 2 steps of the workload
+                  on the host cores (and one thread), 6 steps of the workload
   ensemble        32 seeded parameter samples on the same geometry, all
                   samples' systems in every launch (lp_options.nsamples),
                   against the same samples run one context after another
@@ -39,7 +39,7 @@ WORKLOAD = "cfg2"
 PEAK_MFMA_FP32_TFLOPS = 157.3   # MI355X dense FP32 matrix peak (the factorisation's trailing updates run on MFMA)
 PEAK_FP64_TFLOPS = 78.6         # MI355X FP64 vector and matrix peak
 PEAK_HBM_GBS = 8000.0           # MI355X HBM3E
-CPU_STEPS = 2
+CPU_STEPS = 6                   # oracle steps of the CPU baseline (about 13 s on one host core)
 CPU_POOL_MAX = 16               # host cores given to one GPU's share
 SERIAL_STEPS = 8                # roofline pass: LU launches timed on an uncontended stream
 ENSEMBLE_SAMPLES, ENSEMBLE_WARMUP, ENSEMBLE_STEPS = 32, 2, 8
