@@ -258,10 +258,11 @@ def ensemble_run(L, lu_bytes, lean=False):
     samples = cfg["samples"]
     S = len(samples)
 
-    def build(plist, prec):
+    def build(plist, prec, graphs=False):
         return LocalParallel(cfg["NH"], cfg["refine"], cfg["nsub"], cfg["overlap"], plist[0], cfg["dt"],
                              cuts=W.flat_cuts(cfg["cuts"]), precision=prec, max_ir=ENSEMBLE_MAX_IR[prec],
-                             max_newton=ENSEMBLE_MAX_NEWTON, jacobian_every=ENSEMBLE_JACOBIAN_EVERY, samples=plist)
+                             max_newton=ENSEMBLE_MAX_NEWTON, jacobian_every=ENSEMBLE_JACOBIAN_EVERY, samples=plist,
+                             graphs=graphs)
 
     def clock(g):
         for _ in range(ENSEMBLE_WARMUP):
@@ -300,6 +301,13 @@ def ensemble_run(L, lu_bytes, lean=False):
                      "flags": st["flags"], "newton_its_max": st["newton_its_max"],
                      "sweeps_max": st["ir_sweeps_max"], "relres_max": st["ir_relres_max"],
                      "lu_growth_local": st["lu_growth_local"], "lu_pivot_local": st["lu_pivot_local"]}
+    if not lean:
+        # the same timed steps with every launch sequence replayed as a HIP graph
+        g = build(samples, "mixed", graphs=True)
+        ms = clock(g)
+        st = g.stats()
+        g.close()
+        out["mixed"]["graphs"] = {"value": S * L / (ms * 1e-3), "ms_per_step": ms, "flags": st["flags"]}
     os.environ["LP_SERIAL"] = "1"
     try:
         g = build(samples, "mixed")

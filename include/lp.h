@@ -142,8 +142,9 @@ typedef struct {
                                 every launch then covers all samples' systems, and each
                                 sample's fields are what a context of that sample alone
                                 computes, bit for bit.  They need the dense local path
-                                (LP_DENSE, or LP_AUTO where the band fits), LP_TWO_GRID,
-                                graphs = 0 and autotune = 0 (else LP_ERR_UNSUPPORTED) */
+                                (LP_DENSE, or LP_AUTO where the band fits) and LP_TWO_GRID
+                                (else LP_ERR_UNSUPPORTED); the autotuner then tunes the
+                                dense path only */
     int32_t autotune;        /* 1: at the end of lp_setup, time the local Oseen solves on this
                                 run's own systems: the band factorisation kernel (three
                                 variants) and the band solve prefetch depth are set to the
@@ -224,8 +225,8 @@ typedef struct {
  * parameters.
  * Errors: LP_ERR_ARG (dim != 2, n_coarse < 1, refine < 1, overlap < 0, bad cuts,
  * non-positive dt or parameters, samples with different dt, unknown option
- * values), LP_ERR_UNSUPPORTED (nsamples > 1 with the Krylov path, graphs,
- * autotuning or LP_ONE_GRID, LP_SEMI_IMPLICIT, a porous, coarse or (LP_DENSE) Oseen
+ * values), LP_ERR_UNSUPPORTED (nsamples > 1 with the Krylov path or
+ * LP_ONE_GRID, LP_SEMI_IMPLICIT, a porous, coarse or (LP_DENSE) Oseen
  * half-bandwidth beyond the band kernels' window of 159, or a Krylov strip or
  * system beyond its kernels' limits), LP_ERR_NOCONV (zero or non-finite pivot in
  * the constant porous matrices), LP_ERR_ALLOC, LP_ERR_DEVICE. */

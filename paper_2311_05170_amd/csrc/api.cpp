@@ -1140,9 +1140,9 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     const int nsam = std::max(opt->nsamples, 1);
     for (int i = 1; i < nsam; ++i)
         if (samples[i].dt != samples[0].dt) return fail(LP_ERR_ARG, "every sample must share dt (one time grid)");
-    if (nsam > 1 && (opt->solver == LP_KRYLOV || opt->graphs || opt->autotune || opt->scheme == LP_ONE_GRID))
-        return fail(LP_ERR_UNSUPPORTED, "several samples run the dense local path with direct launches and no autotuning, "
-                                        "under the two-grid scheme");
+    if (nsam > 1 && (opt->solver == LP_KRYLOV || opt->scheme == LP_ONE_GRID))
+        return fail(LP_ERR_UNSUPPORTED, "several samples run the dense local path under Algorithm 3 "
+                                        "(LP_KRYLOV and LP_ONE_GRID take one sample)");
     if (opt->solver != LP_DENSE && (opt->max_iter < 1 || opt->max_iter > lp::GM_MAX || !(opt->krylov_tol > 0)))
         return fail(LP_ERR_ARG, "Krylov solves need 1 <= max_iter <= " + std::to_string(lp::GM_MAX) + " and krylov_tol > 0");
     if (opt->coarse_ns == LP_SEMI_IMPLICIT) return fail(LP_ERR_UNSUPPORTED, "the semi-implicit coarse step is not built");
@@ -1208,7 +1208,7 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     c->krylov = opt->solver == LP_KRYLOV || (opt->solver == LP_AUTO && c->maxbw_ose >= 160);
     // with autotuning, LP_AUTO sets up both paths where the dense one fits and
     // keeps the faster (measured at the end of setup)
-    const bool try_both = opt->autotune && opt->solver == LP_AUTO && c->maxbw_ose < 160;
+    const bool try_both = opt->autotune && opt->solver == LP_AUTO && c->maxbw_ose < 160 && nsam == 1;
     c->have_dense = !c->krylov || try_both;
     if (nsam > 1 && c->krylov)
         return fail(LP_ERR_UNSUPPORTED, "several samples need the dense local Oseen path (half-bandwidth <= 159)");

@@ -101,8 +101,8 @@ def _setup_status(opt_kw=None, samples=None, prm_kw=None, dts=None):
 def test_setup_rejects_bad_options_without_a_device():
     """Argument checks run before any device call: unknown option values and
     invalid parameters (and samples with different dt) are LP_ERR_ARG, requests
-    this build does not implement (several samples with the Krylov path,
-    graphs, autotuning or Algorithm 1; the semi-implicit coarse step)
+    this build does not implement (several samples with the Krylov path or
+    Algorithm 1; the semi-implicit coarse step)
     LP_ERR_UNSUPPORTED."""
     assert _setup_status({"solver": 7})[0] == 1
     assert _setup_status({"coarse_ns": 3})[0] == 1
@@ -115,7 +115,7 @@ def test_setup_rejects_bad_options_without_a_device():
     assert st == 1 and "sample 1" in msg          # every sample is validated
     st, msg = _setup_status({"nsamples": 2}, samples=[W.unit_params(), W.unit_params()], dts=[0.05, 0.02])
     assert st == 1 and "dt" in msg                # samples share one time grid
-    for kw in ({"solver": lib.LP_KRYLOV}, {"graphs": 1}, {"autotune": 1}, {"scheme": lib.LP_ONE_GRID}):
+    for kw in ({"solver": lib.LP_KRYLOV}, {"scheme": lib.LP_ONE_GRID}):
         assert _setup_status(dict(kw, nsamples=2), samples=[W.unit_params()] * 2)[0] == 6, kw
     assert _setup_status({"solver": lib.LP_KRYLOV, "max_iter": 65})[0] == 1
     assert _setup_status({"solver": lib.LP_KRYLOV, "krylov_tol": 0.0})[0] == 1

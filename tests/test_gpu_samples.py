@@ -14,10 +14,10 @@ pytestmark = pytest.mark.gpu
 FIELDS = ("pF", "pf", "pm", "u", "p")
 
 
-def _make(cfg, samples, precision):
+def _make(cfg, samples, precision, **kw):
     from paper_2311_05170_amd.lib import LocalParallel
     return LocalParallel(cfg["NH"], cfg["refine"], cfg["nsub"], cfg["overlap"], samples[0], cfg["dt"],
-                         cuts=W.flat_cuts(cfg["cuts"]), precision=precision, samples=samples)
+                         cuts=W.flat_cuts(cfg["cuts"]), precision=precision, samples=samples, **kw)
 
 
 def _fields(g, sample, subs):
@@ -111,3 +111,54 @@ def test_samples_match_oracle_small():
             err = np.abs(got[i][f] - ref[f]).max() / np.abs(ref[f]).max()
             print("sample", i, f, "%.1e" % err, flush=True)
             assert err < 1e-9, (i, f, err)
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_samples_under_hip_graphs(precision):
+    """Several samples with every step's launch sequences replayed as HIP
+    graphs: the same fields, bit for bit, as direct launches (graphs start at
+    the third step; eight steps replay every ring slot's graphs at least once)."""
+    cfg = dict(W.config("cfg1"), dt=0.01)
+    samples = W.ensemble_samples(4, seed=3)
+    a, b = _make(cfg, samples, precision), _make(cfg, samples, precision, graphs=True)
+    try:
+        for k in range(10):
+            a.step()
+            b.step()
+            for i in range(len(samples)):
+                for f in FIELDS:
+                    x, y = a.solution(f, sample=i), b.solution(f, sample=i)
+                    assert np.array_equal(x, y), (precision, k, i, f, np.abs(x - y).max())
+        assert a.stats()["flags"] == 0 and b.stats()["flags"] == 0
+    finally:
+        a.close()
+        b.close()
+
+
+def test_samples_with_autotuning():
+    """The autotuner on a context of several samples tunes the dense path (the
+    factorisation variant and solve depth over all samples' systems); the
+    fields stay at oracle parity, as the small case's fixed variants are."""
+    from oracle.scheme import Oracle2D
+    cfg = W.small(dt=0.05)
+    samples = W.ensemble_samples(3)
+    steps = 3
+    g = _make(cfg, samples, "mixed", autotune=True)
+    try:
+        for _ in range(steps):
+            g.step()
+        st = g.stats()
+        assert st["tuned"] == 1 and st["solver"] == 1 and st["flags"] == 0, st
+        got = {i: {f: g.solution(f, sample=i) for f in FIELDS} for i in range(len(samples))}
+    finally:
+        g.close()
+    for i, prm in enumerate(samples):
+        o = Oracle2D(cfg["NH"], cfg["Nh"], cfg["cuts"], cfg["overlap"], prm, cfg["dt"])
+        o.init()
+        for _ in range(steps):
+            o.coarse_step()
+            o.local_step()
+        ref = o.merged()
+        for f in FIELDS:
+            err = np.abs(got[i][f] - ref[f]).max() / np.abs(ref[f]).max()
+            assert err < 1e-7, (i, f, err)
