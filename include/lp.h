@@ -350,8 +350,8 @@ lp_status lp_get_timing(lp_ctx *ctx, double *ms, int64_t *launches, int32_t n);
  * allocator; its tickets are cleared by a small kernel on each call.  Every
  * call on one device shares that array: calls of different contexts that
  * overlap on one device race.  Errors: as lp_local_step, and
- * LP_ERR_UNSUPPORTED when the problem's scratch exceeds the array or the
- * context holds more than one sample. */
+ * LP_ERR_UNSUPPORTED when the problem's scratch (all samples' systems)
+ * exceeds the array. */
 lp_status lp_local_step_noalloc(lp_ctx *ctx, void *stream);
 
 /* Checkpoint and resume of a run between steps (no coarse step pending).

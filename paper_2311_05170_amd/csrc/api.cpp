@@ -1822,7 +1822,6 @@ lp_status lp_local_step(lp_ctx *c, void *stream) {
 
 lp_status lp_local_step_noalloc(lp_ctx *c, void *stream) {
     if (!c) return fail(LP_ERR_ARG, "NULL context");
-    if (c->ns > 1) return fail(LP_ERR_UNSUPPORTED, "lp_local_step_noalloc takes one sample per context");
     const long long need = c->scratch_part_por + c->scratch_part_ose;     // doubles
     const long long need_t = 3LL * (long long)c->P.por.size() + (long long)c->P.ose.size();
     const long long bytes = need * (long long)sizeof(double) + need_t * (long long)sizeof(int);
