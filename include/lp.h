@@ -268,6 +268,16 @@ lp_status lp_get_solution(lp_ctx *ctx, int32_t sample, int32_t field, int32_t le
  * fields hold the best iterates. */
 lp_status lp_get_stats(lp_ctx *ctx, lp_stats *out);
 
+/* lp_get_stats restricted to one parameter sample's systems (0 <= sample <
+ * nsamples): the coarse Newton iterations of that sample's last step and of
+ * its run (newton_its, newton_its_max), flag bit 1 when its last coarse step
+ * ended above newton_tol, its last local step's refinement sweeps and final
+ * relative residuals (ir_sweeps*, ir_relres*), and local_dofs per sample.
+ * Flag bits 0 and 2, the run-long refinement maxima, the factorisation
+ * monitor and the solver choice are the context's.  Errors: as lp_get_stats,
+ * and LP_ERR_ARG for a sample out of range. */
+lp_status lp_get_sample_stats(lp_ctx *ctx, int32_t sample, lp_stats *out);
+
 /* Diagnostic entry for the band kernels of Steps 1 and 3: factor nsys
  * caller-provided band systems without pivoting and solve one right-hand side
  * each, with the library's factorisation (variant as for the local systems:

@@ -499,6 +499,7 @@ lp_status refine_porous(lp_ctx *c, const lp::SysDesc *d_sys, int nsys, int maxno
         }
         StageTimer tm(c, timed ? LP_T_POR_RES : -1, st);
         lp::ResidualArgs ra{d_sys, c->d_dof2, x, b, r, conv, rel, sw, tol, nullptr, part, ticket};
+        ra.tstride = c->tiles_por;
         ra.co = c->d_co;
         lp::launch_porous_residual_tiled(ra, nsys, c->rblk_por, st);
     }
@@ -524,7 +525,7 @@ lp_status refine_oseen(lp_ctx *c, const lp::SysDesc *d_sys, int nsys, int maxnod
         ra.W1[0] = W1x; ra.W1[1] = W1y;
         ra.x = x; ra.b = b; ra.r = r; ra.band = nullptr;
         ra.conv = conv; ra.relres = rel; ra.sweeps = sw; ra.tol = tol; ra.skip = skip;
-        ra.part = part; ra.ticket = ticket;
+        ra.part = part; ra.ticket = ticket; ra.tstride = c->tiles_ose;
         lp::launch_oseen_residual_tiled(ra, nsys, c->rblk_ose, st);
     }
     return LP_OK;
@@ -571,7 +572,7 @@ lp_status refine_oseen_krylov(lp_ctx *c, double *part, int *ticket, const double
         ra.W1[0] = W1x; ra.W1[1] = W1y;
         ra.x = c->x_ose; ra.b = c->b_ose; ra.r = c->r_ose; ra.band = nullptr;
         ra.conv = c->conv_ose; ra.relres = c->rel_ose; ra.sweeps = c->sw_ose; ra.tol = c->opt.ir_tol; ra.skip = nullptr;
-        ra.part = part; ra.ticket = ticket;
+        ra.part = part; ra.ticket = ticket; ra.tstride = c->tiles_ose;
         lp::launch_oseen_residual_tiled(ra, nsys, c->rblk_ose, st);
     }
     return LP_OK;
@@ -1906,14 +1907,17 @@ lp_status lp_get_solution(lp_ctx *c, int32_t sample, int32_t field, int32_t leve
     return LP_OK;
 }
 
-lp_status lp_get_stats(lp_ctx *c, lp_stats *out) {
-    if (!c || !out) return fail(LP_ERR_ARG, "NULL argument");
+// Statistics of the whole context (sample < 0) or of one sample's systems:
+// its Newton iterations and convergence, its last-step refinement sweeps and
+// residuals; the sticky flag bits 0 and 2, the run-long maxima and the
+// factorisation monitor are the context's.
+static lp_status stats_impl(lp_ctx *c, int sample, lp_stats *out) {
     HIPCHK(hipDeviceSynchronize());
     std::memset(out, 0, sizeof(*out));
     out->step = c->n;
     out->n_porous = c->np1;
     out->n_conduit = c->no1;
-    out->local_dofs = c->P.local_dofs;
+    out->local_dofs = sample < 0 ? c->P.local_dofs : c->P.local_dofs / c->ns;
     out->max_bw = c->P.max_bw;
     int flags = 0, irmax = 0;
     unsigned long long irrel = 0;
@@ -1923,9 +1927,10 @@ lp_status lp_get_stats(lp_ctx *c, lp_stats *out) {
     HIPCHK(hipMemcpy(&flags, c->d_flags, sizeof(int), hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(&irmax, c->d_irmax, sizeof(int), hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(&irrel, c->d_irrel, sizeof(irrel), hipMemcpyDeviceToHost));
-    // over every sample: the last step's most Newton iterations, the run's most
+    // over the samples asked for: the last step's most Newton iterations, the run's most
     out->flags = flags & 7;
-    for (int smp = 0; smp < c->ns; ++smp) {
+    if (sample >= 0) out->flags &= ~2;             // bit 1 from this sample's Newton status below
+    for (int smp = sample < 0 ? 0 : sample; smp < (sample < 0 ? c->ns : sample + 1); ++smp) {
         out->newton_its = std::max(out->newton_its, its[2 * smp]);
         out->newton_its_max = std::max({out->newton_its_max, its[2 * smp], its[2 * smp + 1]});
         if (c->n > 0 && !done[smp]) out->flags |= 2;
@@ -1939,7 +1944,11 @@ lp_status lp_get_stats(lp_ctx *c, lp_stats *out) {
     HIPCHK(hipMemcpy(sw.data() + np, c->sw_ose, no * sizeof(int), hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(rel.data(), c->rel_por, np * sizeof(double), hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(rel.data() + np, c->rel_ose, no * sizeof(double), hipMemcpyDeviceToHost));
+    // the systems of one sample: its porous fields, then its conduit boxes
+    const size_t pp0 = sample < 0 ? 0 : 3 * (size_t)sample * c->np1, pp1 = sample < 0 ? np : pp0 + 3 * (size_t)c->np1;
+    const size_t oo0 = sample < 0 ? 0 : (size_t)sample * c->no1, oo1 = sample < 0 ? no : oo0 + c->no1;
     for (size_t i = 0; i < sw.size(); ++i) {
+        if (i < np ? (i < pp0 || i >= pp1) : (i - np < oo0 || i - np >= oo1)) continue;
         out->ir_sweeps = std::max(out->ir_sweeps, sw[i]);
         out->ir_relres = std::max(out->ir_relres, rel[i]);
         if (i < np) {
@@ -1974,6 +1983,17 @@ lp_status lp_get_stats(lp_ctx *c, lp_stats *out) {
                                        ": a refinement, a coarse Newton iteration or a pivot check failed in some step so far");
     }
     return LP_OK;
+}
+
+lp_status lp_get_stats(lp_ctx *c, lp_stats *out) {
+    if (!c || !out) return fail(LP_ERR_ARG, "NULL argument");
+    return stats_impl(c, -1, out);
+}
+
+lp_status lp_get_sample_stats(lp_ctx *c, int32_t sample, lp_stats *out) {
+    if (!c || !out) return fail(LP_ERR_ARG, "NULL argument");
+    if (sample < 0 || sample >= c->ns) return fail(LP_ERR_ARG, "sample out of range (the context holds " + std::to_string(c->ns) + ")");
+    return stats_impl(c, sample, out);
 }
 
 lp_status lp_band_factor_solve(int32_t nsys, int32_t n, int32_t bw, const double *band, const double *rhs, double *x,

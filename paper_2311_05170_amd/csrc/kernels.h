@@ -51,9 +51,10 @@ struct ResidualArgs {
     int *sweeps;
     double tol;
     const int *skip;
-    double *part;                 // per-(system, node block) partial norms: 2 * nblocks doubles per id
-    int *ticket;                  // per-id arrival counters, zero between launches
+    double *part;                 // per-(system, tile) partial norms: 2 * tstride doubles per id
+    int *ticket;                  // per-box arrival counters (at the box's first id), zero between launches
     const Coef *co = nullptr;     // the context's coefficients (device)
+    int tstride = 0;              // tiles per id in part (at least any box's tile count)
 };
 
 // Refinement outcome of a batch, folded into run-long totals by the finalize
@@ -131,6 +132,7 @@ struct OseenApplyArgs {
     const int *skip;
     double *part;                 // residual mode: partial norms and counters as in ResidualArgs
     int *ticket;
+    int tstride = 0;              // residual mode: tiles per system in part
     int no_convection;            // assembly: leave out b_N (the Stokes part of the operator)
     const Coef *co = nullptr;     // the context's coefficients (device)
     int first_write = 0;          // assembly: the band was cleared once and its pattern is fixed (see k_oseen_assemble)

@@ -324,6 +324,77 @@ __device__ void grid_norms_and_flag(double rr, double bb, double *part, int *tic
     }
 }
 
+// Norms of the tiled residual kernels, in an order that does not depend on
+// how many blocks share a box: each tile's sums of r^2 and b^2 are reduced in
+// the block (wavefront sums, then the wavefronts in order), and the tiles'
+// sums are added in tile order, by a running total when one block takes the
+// whole box, else by the last of the box's blocks from the tiles' partials
+// (part[2 ((id0 + f) tstride + tile)]).  tile_norms: after each tile;
+// tile_norms_finish: after the last, by every thread of every block.
+template <int F>
+__device__ __forceinline__ void tile_norms(double (&r)[F], double (&b)[F], const bool (&act)[F], double (&tr)[F],
+                                           double (&tb)[F], double *part, int tstride, int id0, int tile) {
+    __shared__ double s[2 * F][16];
+    const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+        const double x = wave_sum(r[f]), y = wave_sum(b[f]);
+        if ((threadIdx.x & 63) == 0) { s[2 * f][w] = x; s[2 * f + 1][w] = y; }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+        double x = 0.0, y = 0.0;
+        for (int i = 0; i < nw; ++i) { x += s[2 * f][i]; y += s[2 * f + 1][i]; }
+        if (gridDim.x == 1) {
+            tr[f] += x;
+            tb[f] += y;
+        } else if (threadIdx.x == 0 && act[f]) {
+            const long long at = 2 * ((long long)(id0 + f) * tstride + tile);
+            part[at] = x;
+            part[at + 1] = y;
+        }
+    }
+    __syncthreads();                        // s free for the next tile
+}
+template <int F>
+__device__ void tile_norms_finish(const double (&tr)[F], const double (&tb)[F], const bool (&act)[F], double *part,
+                                  int *ticket, int *conv, double *relres, int *sweeps, double tol, int id0, int tstride,
+                                  int ntile) {
+    auto done = [&](int f, double a, double b) {
+        const double rel = b > 0.0 ? sqrt(a / b) : 0.0;
+        relres[id0 + f] = rel;
+        sweeps[id0 + f] += 1;
+        if (rel <= tol) conv[id0 + f] = 1;
+    };
+    if (gridDim.x == 1) {
+        if (threadIdx.x == 0)
+            for (int f = 0; f < F; ++f)
+                if (act[f]) done(f, tr[f], tb[f]);
+        return;
+    }
+    __shared__ int last;
+    if (threadIdx.x == 0) {
+        __threadfence();
+        last = atomicAdd(ticket + id0, 1) == (int)gridDim.x - 1;
+    }
+    __syncthreads();
+    if (last && threadIdx.x == 0) {
+        __threadfence();
+        ticket[id0] = 0;
+        for (int f = 0; f < F; ++f) {
+            if (!act[f]) continue;
+            double a = 0.0, b = 0.0;
+            const long long base = 2LL * (id0 + f) * tstride;
+            for (int t = 0; t < ntile; ++t) {
+                a += part[base + 2 * t];
+                b += part[base + 2 * t + 1];
+            }
+            done(f, a, b);
+        }
+    }
+}
+
 // y = A_f x restricted to free rows (FP64, matrix-free); r = b - y; norms
 __device__ __forceinline__ void porous_finalize_rows(const FinalizeArgs &F, const SysDesc &S, int start, int stride) {
     const int nloc = S.lw2 * S.lh2;
@@ -764,8 +835,10 @@ __global__ __launch_bounds__(256) void k_oseen_residual_tiled(OseenApplyArgs<dou
     __shared__ double cv[RT_TRI][6][2];     // velocity rows: (triangle, its node la, component)
     __shared__ double cp[RT_TRI][3];        // pressure rows: (triangle, its vertex)
     const int tid = threadIdx.x;
-    double rr = 0.0, bb = 0.0;
+    double tr[1] = {0.0}, tb[1] = {0.0};                       // the box's norms so far (one block per box)
+    const bool act1[1] = {true};
     for (int tile = blockIdx.x; tile < ntx * nty; tile += gridDim.x) {
+        double rr = 0.0, bb = 0.0;
         const int tx = tile % ntx, ty = tile / ntx;
         const int ci_lo = tx * RT - 1, cj_lo = ty * RT - 1;    // first (halo) cell of the tile's triangles
         if (tile != (int)blockIdx.x) __syncthreads();          // the previous tile's node pass is done with LDS
@@ -883,8 +956,13 @@ __global__ __launch_bounds__(256) void k_oseen_residual_tiled(OseenApplyArgs<dou
                 bb += bv * bv;
             }
         }
+        if (A.part) {
+            double pr[1] = {rr}, pb[1] = {bb};
+            tile_norms(pr, pb, act1, tr, tb, A.part, A.tstride, blockIdx.y, tile);
+        }
     }
-    if (A.part) grid_norms_and_flag(rr, bb, A.part, A.ticket, A.conv, A.relres, A.sweeps, A.tol, blockIdx.y);
+    if (A.part)
+        tile_norms_finish(tr, tb, act1, A.part, A.ticket, A.conv, A.relres, A.sweeps, A.tol, blockIdx.y, A.tstride, ntx * nty);
 }
 
 // Local Oseen right-hand sides by the same tiles as the residual: each
@@ -1061,8 +1139,9 @@ __global__ __launch_bounds__(256) void k_porous_residual_tiled(ResidualArgs R) {
     const long long nd = S.ndof;
     __shared__ double cy[RT_TRI][6][3];     // (triangle, its node la, field)
     const int tid = threadIdx.x;
-    double rr[3] = {0.0, 0.0, 0.0}, bb[3] = {0.0, 0.0, 0.0};
+    double tr[3] = {0.0, 0.0, 0.0}, tb[3] = {0.0, 0.0, 0.0};   // the box's norms so far (one block per box)
     for (int tile = blockIdx.x; tile < ntx * nty; tile += gridDim.x) {
+        double rr[3] = {0.0, 0.0, 0.0}, bb[3] = {0.0, 0.0, 0.0};
         const int tx = tile % ntx, ty = tile / ntx;
         const int ci_lo = tx * RT - 1, cj_lo = ty * RT - 1;
         if (tile != (int)blockIdx.x) __syncthreads();          // the previous tile's node pass is done with LDS
@@ -1105,9 +1184,9 @@ __global__ __launch_bounds__(256) void k_porous_residual_tiled(ResidualArgs R) {
                 bb[f] += bv * bv;
             }
         }
+        tile_norms(rr, bb, act, tr, tb, R.part, R.tstride, id0, tile);
     }
-    for (int f = 0; f < 3; ++f)
-        if (act[f]) grid_norms_and_flag(rr[f], bb[f], R.part, R.ticket, R.conv, R.relres, R.sweeps, R.tol, id0 + f);
+    tile_norms_finish(tr, tb, act, R.part, R.ticket, R.conv, R.relres, R.sweeps, R.tol, id0, R.tstride, ntx * nty);
 }
 
 // Local porous right-hand sides by the same tiles: each triangle's mass and

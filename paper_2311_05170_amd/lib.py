@@ -35,7 +35,7 @@ SCHEME = {"two_grid": LP_TWO_GRID, "one_grid": LP_ONE_GRID}
 LP_ERR_NOCONV = 5
 
 EXPORTS = ["lp_setup", "lp_coarse_step", "lp_local_step", "lp_get_size", "lp_get_solution",
-           "lp_get_stats", "lp_plan_query", "lp_get_index_map", "lp_set_timing", "lp_get_timing",
+           "lp_get_stats", "lp_get_sample_stats", "lp_plan_query", "lp_get_index_map", "lp_set_timing", "lp_get_timing",
            "lp_local_step_noalloc", "lp_band_factor_solve", "lp_state_size", "lp_save_state",
            "lp_load_state", "lp_destroy", "lp_last_error"]
 # stage timer indices (LP_T_* in lp.h)
@@ -106,6 +106,7 @@ def load(path=LIB_PATH):
     lib.lp_get_solution.argtypes = [c_void_p, c_int32, c_int32, c_int32, c_int32, POINTER(c_double),
                                     c_int64, c_int32, c_void_p]
     lib.lp_get_stats.argtypes = [c_void_p, POINTER(LpStats)]
+    lib.lp_get_sample_stats.argtypes = [c_void_p, c_int32, POINTER(LpStats)]
     lib.lp_plan_query.argtypes = [POINTER(LpMesh), POINTER(LpPartition), c_int32, c_int32,
                                   POINTER(c_int64), c_int64, POINTER(c_int64)]
     lib.lp_get_index_map.argtypes = [c_void_p, c_int32, c_int32, POINTER(c_int64), c_int64, POINTER(c_int64)]
@@ -294,11 +295,16 @@ class LocalParallel:
                                      need.value, byref(need)))
         return out[:need.value]
 
-    def stats(self):
+    def stats(self, sample=None):
         """Run statistics; flags are sticky.  A set flag (lp_get_stats returns
-        LP_ERR_NOCONV) is reported in the dict, not raised."""
+        LP_ERR_NOCONV) is reported in the dict, not raised.  With a sample
+        index, that sample's Newton and refinement statistics
+        (lp_get_sample_stats)."""
         s = LpStats()
-        st = _LIB.lp_get_stats(self._h, byref(s))
+        if sample is None:
+            st = _LIB.lp_get_stats(self._h, byref(s))
+        else:
+            st = _LIB.lp_get_sample_stats(self._h, int(sample), byref(s))
         if st not in (0, LP_ERR_NOCONV):
             _check(st)
         return {k: getattr(s, k) for k, _ in LpStats._fields_}

@@ -51,6 +51,13 @@ def _compare(cfg, samples, precision, steps, check):
                                                             np.abs(a[key] - b[key]).max())
         st = ens.stats()
         one = next(iter(solo.values())).stats()
+        # per-sample statistics: those of the sample's own context
+        for i, g in solo.items():
+            a, b = ens.stats(sample=i), g.stats()
+            for key in ("newton_its", "newton_its_max", "ir_sweeps", "ir_relres", "ir_sweeps_porous",
+                        "ir_relres_porous", "ir_sweeps_oseen", "ir_relres_oseen", "local_dofs"):
+                assert a[key] == b[key], (i, key, a[key], b[key])
+            assert (a["flags"] & 2) == (b["flags"] & 2), (i, a["flags"], b["flags"])
         assert st["flags"] == 0, st
         assert st["n_porous"] == one["n_porous"] and st["n_conduit"] == one["n_conduit"]
         assert st["local_dofs"] == len(samples) * one["local_dofs"]
@@ -60,6 +67,8 @@ def _compare(cfg, samples, precision, steps, check):
             assert np.array_equal(ens.index_map(which, sub), g0.index_map(which, sub)), which
         with pytest.raises(Exception, match="sample out of range"):
             ens.solution("u", sample=len(samples))
+        with pytest.raises(Exception, match="sample out of range"):
+            ens.stats(sample=len(samples))
     finally:
         ens.close()
         for g in solo.values():
