@@ -559,7 +559,7 @@ lp_status refine_oseen_krylov(lp_ctx *c, double *part, int *ticket, const double
                     return fail(LP_ERR_UNSUPPORTED, "strip bandwidth too large for the solve kernels");
                 lp::launch_strip_scatter(sa, nstrip, c->gm_Z + k * nt, st);
                 mv.x = c->gm_Z + k * nt;
-                lp::launch_oseen_residual_tiled(mv, nsys, c->rblk_ose, st);
+                lp::launch_oseen_residual_tiled(mv, nsys, c->tiles_ose, st);   // apply mode: no norms, a block per tile
                 if (!lp::launch_gm_arnoldi(ga, nsys, c->maxn_ose, k, c->gm_w, st))
                     return fail(LP_ERR_UNSUPPORTED, "local Oseen system too large for the Arnoldi kernel");
             }
@@ -886,7 +886,7 @@ lp_status autotune(lp_ctx *c, hipStream_t st) {
         mv.sys = c->d_ose; mv.cls2 = c->d_cls2; mv.dof2 = c->d_dof2; mv.dof1 = c->d_dof1;
         mv.W1[0] = Wx; mv.W1[1] = Wy;
         mv.x = c->x_ose; mv.b = nullptr; mv.r = c->b_ose; mv.conv = nullptr;
-        lp::launch_oseen_residual_tiled(mv, nsys, c->rblk_ose, st);
+        lp::launch_oseen_residual_tiled(mv, nsys, c->tiles_ose, st);   // apply mode: no norms, a block per tile
     }
     // x = 0, r = b, flags cleared: the state a local step's right-hand side kernel leaves
     auto reset = [&]() -> lp_status {
@@ -1184,10 +1184,9 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
         c->tiles_por = std::max(c->tiles_por, lp::residual_tiles(s.cx, s.cy));
     }
     for (const auto &s : P.ose) c->nodes_ose = std::max(c->nodes_ose, s.lw2 * s.lh2);
-    // residual blocks per box: enough for about two blocks per compute unit,
-    // and no more, since every block beyond the first of a box ends with a
-    // device-scope fence and ticket for the box's norm (costly when
-    // thousands of blocks do it at once)
+    // residual blocks per box: RESIDUAL_BLOCKS_TARGET in all, no more than
+    // the box's tiles, since every block beyond the first of a box ends with
+    // a device-scope fence and ticket for the box's norms
     {
         const long long nbox_por = (long long)P.por.size() * std::max(nsam, 1), nbox_ose = (long long)P.ose.size() * std::max(nsam, 1);
         auto per_box = [](long long nbox, int tiles) {

@@ -351,8 +351,11 @@ void launch_oseen_rows(const OseenApplyArgs<T> &a, int nsys, int maxnodes, int m
 // maxtiles = max over the systems of residual_tiles(cx, cy); its norm partials
 // take 2 maxtiles doubles per system
 int residual_tiles(int cx, int cy);
-// blocks the residual launches aim for (two per compute unit of a 256-CU chip)
-constexpr long long RESIDUAL_BLOCKS_TARGET = 512;
+// blocks the residual launches aim for: each block beyond a box's first ends
+// with a device-scope fence and ticket, so fewer, fuller blocks (measured at
+// cfg2: 0.813 ms per step with two blocks per box, 0.826 with one, 0.87 with
+// four)
+constexpr long long RESIDUAL_BLOCKS_TARGET = 128;
 void launch_oseen_residual_tiled(const OseenApplyArgs<double> &a, int nsys, int maxtiles, hipStream_t st);
 // local Oseen right-hand sides by the same tiles
 void launch_oseen_rhs_tiled(const OseenArgs &a, int nsys, int maxtiles, hipStream_t st);
