@@ -18,7 +18,10 @@ Layout
   fe3, mesh3, forms3, mms3, scheme3
            the same in 3D (Kuhn tetrahedra, Example 2 reflected): Algorithms 1
            and 3, exact prolongation, the Step 2 extension rule
+  mini     the paper's own elements (MINI conduit, P1 porous; Section 6) with
+           Algorithm 1 on one grid
 
-Readings of points where the paper is silent are listed in ``scheme.py``'s
-docstring; every oracle function cites the passage it follows.
+Readings of points where the paper is silent are listed in the docstrings of
+``scheme.py`` and, for the MINI element, ``mini.py``; every oracle function
+cites the passage it follows.
 """
