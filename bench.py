@@ -575,6 +575,50 @@ def run_cpu_leg(pool):
     return float(np.load(ref)["seconds"]), ref
 
 
+# Algorithm 1 with the paper's own elements (lp_mini_*): Example 1 at h = 1/16,
+# dt = h^2, T = 1, the workload of Table 2's second row
+PAPER_N = 16
+PAPER_CPU_STEPS = 24
+
+
+def paper_elements_run():
+    """Algorithm 1 with MINI in the conduit and P1 porous pressures on the
+    device: wall time per step (every Newton iteration waits for its
+    convergence test on the host), the paper's Table 2 workload at h = 1/16."""
+    from paper_2311_05170_amd import workloads as W
+    from paper_2311_05170_amd.lib import MiniAlgorithm1
+    N = PAPER_N
+    dt, nsteps, warm = 1.0 / N ** 2, N ** 2, 4
+    g = MiniAlgorithm1(N, W.unit_params(), dt)
+    try:
+        g.step(warm)
+        t0 = time.perf_counter()
+        g.step(nsteps - warm)
+        ms = (time.perf_counter() - t0) * 1e3 / (nsteps - warm)
+        st = g.stats()
+    finally:
+        g.close()
+    n1 = N + 1
+    return {"workload": "2D Example-1 MMS with the paper's elements (MINI conduit, P1 porous), Algorithm 1 on "
+                        "h=1/%d, dt=h^2=1/%d, T=1, unit parameters (Table 2, second row)" % (N, N * N),
+            "ms_per_step": ms, "steps": nsteps - warm, "warmup": warm, "newton_its_max": st["newton_its_max"],
+            "flags": st["flags"],
+            "unknowns": {"navier_stokes": 3 * n1 * n1 + 4 * N * N, "porous": 3 * n1 * n1,
+                         "ns_half_bandwidth": 7 * N + 16}}
+
+
+def paper_elements_cpu():
+    """The oracle's Algorithm 1 with the same elements on a bounded sample of
+    the same workload (its first PAPER_CPU_STEPS steps), ms per step."""
+    from paper_2311_05170_amd import workloads as W
+    from oracle.mini import algorithm1_mini
+    N = PAPER_N
+    t0 = time.perf_counter()
+    algorithm1_mini(N, W.unit_params(), 1.0 / N ** 2, PAPER_CPU_STEPS)
+    return {"ms_per_step": (time.perf_counter() - t0) * 1e3 / PAPER_CPU_STEPS, "steps": PAPER_CPU_STEPS,
+            "kind": "oracle", "cores": 1}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -668,6 +712,9 @@ def main():
     ens = None if (args.lean or args.no_ensemble) else ensemble_run(L, lu_bytes)
     if ens:
         progress("ensemble")
+    paper = None if args.lean else paper_elements_run()
+    if paper:
+        progress("paper's elements")
     uneven = None
     if not (args.no_uneven or args.lean):
         cfg3 = W.config("cfg3")
@@ -765,6 +812,8 @@ def main():
         line["uneven_batch"] = uneven
     if ens:
         line["ensemble"] = ens
+    if paper:
+        line["paper_elements"] = paper
     if not (args.no_cpu or args.lean):
         cores, model = host_cores()
         pool = max(1, min(CPU_POOL_MAX, cores))
@@ -778,6 +827,8 @@ def main():
                                 "single_thread_value": L * CPU_STEPS / secs1,
                                 "single_thread_seconds": secs1}
         line["accuracy"] = accuracy(cfg, ref)
+        if paper:
+            line["paper_elements"]["cpu_baseline"] = paper_elements_cpu()
     print(json.dumps(line), flush=True)
     if any(flags):
         print("a refinement, coarse Newton iteration or pivot check failed during the run: flags %s" % flags,

@@ -391,6 +391,50 @@ lp_status lp_load_state(lp_ctx *ctx, const void *buf, int64_t len, void *stream)
 
 void lp_destroy(lp_ctx *ctx);
 
+/* The paper's own discretisation on the device (Section 6, first paragraph:
+ * MINI elements, P1b-P1, in the conduit and P1 elements for the porous
+ * pressures) with Algorithm 1 (partitioned time stepping, Section 3.3) on one
+ * grid of n cells per unit length, for Example 1's manufactured solution
+ * (Section 6), FP64 throughout.  Per step t_n -> t_{n+1} = (n+1) dt:
+ *   1. the three porous P1 systems with the lagged exchange terms and the
+ *      lagged Gamma flux u^n . n_c (their matrices are constant: factored
+ *      once at setup);
+ *   2. backward-Euler Navier-Stokes on the MINI space with the lagged p_F^n
+ *      on Gamma, by Newton's method from (u^n, p^n) with the boundary values
+ *      of t_{n+1}, to a relative update <= 1e-13 (at most 30 iterations).
+ * The same model, coefficients and time levels as lp_setup's (sources and
+ * Dirichlet data at t_{n+1}); initial data: vertex values of the exact
+ * fields, and each element's bubble coefficient chosen so that the
+ * element's value at its centroid is exact.  The bubble is 27 l0 l1 l2
+ * (value 1 at the centroid); elements are numbered 2 (i + n j) + t in cell
+ * (i, j), t = 0 the triangle (0,0),(1,0),(1,1) of the cell, t = 1 the
+ * triangle (0,0),(1,1),(0,1).
+ * Fields read back by lp_mini_get (host arrays owned by the caller):
+ *   LP_PF, LP_PFMI, LP_PM: (n+1)^2 porous vertex values, index i + (n+1) j;
+ *   LP_P: (n+1)^2 conduit vertex values (j counted up from Gamma);
+ *   LP_U: u_x then u_y, each (n+1)^2 vertex values then one bubble
+ *         coefficient per element: 2 ((n+1)^2 + 2 n^2) values.
+ * lp_mini_setup: `device` is a HIP device id; `prm` holds the parameters and
+ *   dt.  Errors: LP_ERR_ARG (NULL, dt <= 0, n < 2: with n = 1 every conduit
+ *   vertex has Dirichlet velocity and the pressure keeps a free constant),
+ *   LP_ERR_DEVICE,
+ *   LP_ERR_UNSUPPORTED (the Navier-Stokes half-bandwidth, 7 n + 16 for n >= 2,
+ *   beyond the band kernels' window of 175: n <= 22), LP_ERR_ALLOC.
+ * lp_mini_step: advances nsteps steps, synchronously.  LP_ERR_NOCONV when a
+ *   Newton solve reached its cap (flags bit 1) or a factorisation met a
+ *   pivot below the rounding of its matrix (bit 2); the flags are sticky and
+ *   the state advances all the same.
+ * lp_mini_get: copies `field` into out[len]; *needed (if not NULL) receives
+ *   its length; out = NULL only queries it.  LP_ERR_ARG for an unknown field
+ *   or a short buffer.
+ * lp_mini_stats: steps taken, the most Newton iterations of any step, flags. */
+typedef struct lp_mini lp_mini;
+lp_status lp_mini_setup(int32_t n, const lp_params *prm, int32_t device, lp_mini **out);
+lp_status lp_mini_step(lp_mini *ctx, int32_t nsteps);
+lp_status lp_mini_get(lp_mini *ctx, int32_t field, double *out, int64_t len, int64_t *needed);
+lp_status lp_mini_stats(lp_mini *ctx, int32_t *steps, int32_t *newton_its_max, int32_t *flags);
+void lp_mini_destroy(lp_mini *ctx);
+
 const char *lp_last_error(void);
 
 #ifdef __cplusplus

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblp.so")
-SOURCES = ["kernels.hip", "krylov.hip", "plan.cpp", "fe.cpp", "api.cpp"]
+SOURCES = ["kernels.hip", "krylov.hip", "mini.hip", "plan.cpp", "fe.cpp", "api.cpp"]
 # Packed FP32 instructions are disabled for all device code.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

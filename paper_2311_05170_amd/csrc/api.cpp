@@ -31,6 +31,8 @@ lp_status fail(lp_status s, const std::string &msg) {
 
 }  // namespace
 
+lp_status lp::set_error(lp_status s, const std::string &msg) { return fail(s, msg); }
+
 // Scratch of lp_local_step_noalloc: one array per device, held until the
 // process ends.  In host code `scratch` only names the symbol; its device
 // address comes from hipGetSymbolAddress, taken once per device at lp_setup

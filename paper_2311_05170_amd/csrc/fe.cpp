@@ -97,6 +97,49 @@ void yprof(int i, double y, double &Y, double &Y2) {
     }
 }
 
+
+// Time-separable parts of the Example 1 sources at a point of a region
+// (region-relative y): val[f][k] for f = F, f, m (porous: k = cos t, sin t) or
+// f = 3 + c (conduit u_c: k = cos t, sin t, cos^2 t); unused parts stay 0.
+void source_point(int region, double x, double yl, const lp_params &prm, double val[5][3]) {
+    const double mu = prm.mu_tilde;
+    const double kap[3] = {prm.k[0] / mu, prm.k[1] / mu, prm.k[2] / mu};
+    const double sst = prm.sigma_star * prm.k[1] / mu, s = prm.sigma * prm.k[2] / mu;
+    const double nu = prm.nu;
+    for (int f = 0; f < 5; ++f)
+        for (int k = 0; k < 3; ++k) val[f][k] = 0.0;
+    if (region == POROUS) {
+        double y = yl, a[3], lap[3];
+        for (int f = 0; f < 3; ++f) {
+            double Y, Y2;
+            yprof(f, y, Y, Y2);
+            a[f] = gfun(x) * Y;
+            lap[f] = gfun2(x) * Y + gfun(x) * Y2;
+        }
+        // cos t parts (diffusion + exchange), sin t parts (-phi C a)
+        val[0][0] = -kap[0] * lap[0] + sst * (a[0] - a[1]);
+        val[1][0] = -kap[1] * lap[1] + sst * (a[1] - a[0]) + s * (a[1] - a[2]);
+        val[2][0] = -kap[2] * lap[2] + s * (a[2] - a[1]);
+        for (int f = 0; f < 3; ++f) val[f][1] = -prm.phi[f] * prm.C[f] * a[f];
+    } else {
+        double y = 1.0 + yl, ym = y - 1.0;
+        double U1 = x * x * ym * ym + y;
+        double U2 = -2.0 / 3.0 * x * ym * ym * ym + gfun(x);
+        double U1x = 2 * x * ym * ym, U1y = 2 * x * x * ym + 1.0;
+        double U2x = -2.0 / 3.0 * ym * ym * ym + gfun1(x), U2y = -2 * x * ym * ym;
+        double L1 = 2 * ym * ym + 2 * x * x;
+        double L2 = -4 * x * ym + gfun2(x);
+        double Px = gfun1(x) * std::sin(0.5 * PI * y);
+        double Py = gfun(x) * 0.5 * PI * std::cos(0.5 * PI * y);
+        val[3][0] = -nu * L1 + Px;
+        val[4][0] = -nu * L2 + Py;
+        val[3][1] = -U1;
+        val[4][1] = -U2;
+        val[3][2] = U1 * U1x + U2 * U1y;
+        val[4][2] = U1 * U2x + U2 * U2y;
+    }
+}
+
 }  // namespace
 
 void build_refdata(RefData &r) {
@@ -200,10 +243,6 @@ void source_loads(int N, const lp_params &prm, std::vector<double> loads[5][3]) 
         p2_eval(xi[q], eta[q], v, g);
         for (int a = 0; a < 6; ++a) phi[q * 6 + a] = v[a];
     }
-    const double mu = prm.mu_tilde;
-    const double kap[3] = {prm.k[0] / mu, prm.k[1] / mu, prm.k[2] / mu};
-    const double sst = prm.sigma_star * prm.k[1] / mu, s = prm.sigma * prm.k[2] / mu;
-    const double nu = prm.nu;
     for (int region = 0; region < 2; ++region)
         for (int cj = 0; cj < N; ++cj)
             for (int ci = 0; ci < N; ++ci)
@@ -213,37 +252,8 @@ void source_loads(int N, const lp_params &prm, std::vector<double> loads[5][3]) 
                         double x, yl;
                         to_xy(t, ci * h, cj * h, h, xi[q], eta[q], x, yl);
                         const double w = wt[q] * h * h;
-                        double val[5][3] = {};
-                        if (region == POROUS) {
-                            double y = yl, a[3], lap[3];
-                            for (int f = 0; f < 3; ++f) {
-                                double Y, Y2;
-                                yprof(f, y, Y, Y2);
-                                a[f] = gfun(x) * Y;
-                                lap[f] = gfun2(x) * Y + gfun(x) * Y2;
-                            }
-                            // cos t parts (diffusion + exchange), sin t parts (-phi C a)
-                            val[0][0] = -kap[0] * lap[0] + sst * (a[0] - a[1]);
-                            val[1][0] = -kap[1] * lap[1] + sst * (a[1] - a[0]) + s * (a[1] - a[2]);
-                            val[2][0] = -kap[2] * lap[2] + s * (a[2] - a[1]);
-                            for (int f = 0; f < 3; ++f) val[f][1] = -prm.phi[f] * prm.C[f] * a[f];
-                        } else {
-                            double y = 1.0 + yl, ym = y - 1.0;
-                            double U1 = x * x * ym * ym + y;
-                            double U2 = -2.0 / 3.0 * x * ym * ym * ym + gfun(x);
-                            double U1x = 2 * x * ym * ym, U1y = 2 * x * x * ym + 1.0;
-                            double U2x = -2.0 / 3.0 * ym * ym * ym + gfun1(x), U2y = -2 * x * ym * ym;
-                            double L1 = 2 * ym * ym + 2 * x * x;
-                            double L2 = -4 * x * ym + gfun2(x);
-                            double Px = gfun1(x) * std::sin(0.5 * PI * y);
-                            double Py = gfun(x) * 0.5 * PI * std::cos(0.5 * PI * y);
-                            val[3][0] = -nu * L1 + Px;
-                            val[4][0] = -nu * L2 + Py;
-                            val[3][1] = -U1;
-                            val[4][1] = -U2;
-                            val[3][2] = U1 * U1x + U2 * U1y;
-                            val[4][2] = U1 * U2x + U2 * U2y;
-                        }
+                        double val[5][3];
+                        source_point(region, x, yl, prm, val);
                         for (int f = 0; f < 5; ++f)
                             for (int k = 0; k < 3; ++k)
                                 if (val[f][k] != 0.0)
@@ -256,6 +266,100 @@ void source_loads(int N, const lp_params &prm, std::vector<double> loads[5][3]) 
                             for (int k = 0; k < 3; ++k) loads[f][k][node] += acc[f][k][a2];
                     }
                 }
+}
+
+// ---------------------------------------------------------------------------
+// The paper's own elements (Section 6): MINI (P1 plus the cubic bubble
+// 27 l0 l1 l2) in the conduit, P1 for the porous pressures.
+
+void build_mini_refdata(MiniRef &r) {
+    std::vector<double> xi, eta, wt;
+    triangle_rule(5, xi, eta, wt);   // 25 points, exact to degree 8
+    const double dl[3][2] = {{-1, -1}, {1, 0}, {0, 1}};
+    for (int q = 0; q < MINI_NQ; ++q) {
+        const double l[3] = {1.0 - xi[q] - eta[q], xi[q], eta[q]};
+        r.w[q] = wt[q];
+        double g[4][2];
+        for (int a = 0; a < 3; ++a) {
+            r.phi[q][a] = l[a];
+            g[a][0] = dl[a][0];
+            g[a][1] = dl[a][1];
+        }
+        r.phi[q][3] = 27.0 * l[0] * l[1] * l[2];
+        for (int d = 0; d < 2; ++d)
+            g[3][d] = 27.0 * (l[1] * l[2] * dl[0][d] + l[0] * l[2] * dl[1][d] + l[0] * l[1] * dl[2][d]);
+        for (int t = 0; t < 2; ++t)
+            for (int a = 0; a < 4; ++a) to_physical(t, g[a], r.dphi[t][q][a]);
+    }
+}
+
+void mini_source_loads(int N, const lp_params &prm, std::vector<double> loads[5][3]) {
+    const int n1 = N + 1;
+    const size_t nv = (size_t)n1 * n1, ne = 2 * (size_t)N * N;
+    const double h = 1.0 / N;
+    for (int f = 0; f < 5; ++f)
+        for (int k = 0; k < 3; ++k) loads[f][k].assign(f < 3 ? nv : nv + ne, 0.0);
+    std::vector<double> xi, eta, wt;
+    triangle_rule(6, xi, eta, wt);   // 36 points, exact to degree 10
+    const int nq = (int)xi.size();
+    for (int region = 0; region < 2; ++region)
+        for (int cj = 0; cj < N; ++cj)
+            for (int ci = 0; ci < N; ++ci)
+                for (int t = 0; t < 2; ++t) {
+                    double acc[5][3][4] = {};
+                    for (int q = 0; q < nq; ++q) {
+                        const double l[3] = {1.0 - xi[q] - eta[q], xi[q], eta[q]};
+                        const double phi[4] = {l[0], l[1], l[2], 27.0 * l[0] * l[1] * l[2]};
+                        double x, yl;
+                        to_xy(t, ci * h, cj * h, h, xi[q], eta[q], x, yl);
+                        const double w = wt[q] * h * h;
+                        double val[5][3];
+                        source_point(region, x, yl, prm, val);
+                        for (int f = 0; f < 5; ++f)
+                            for (int k = 0; k < 3; ++k)
+                                if (val[f][k] != 0.0)
+                                    for (int a = 0; a < 4; ++a) acc[f][k][a] += w * val[f][k] * phi[a];
+                    }
+                    const int f0 = region == POROUS ? 0 : 3, f1 = region == POROUS ? 3 : 5;
+                    const size_t e = 2 * ((size_t)ci + (size_t)N * cj) + t;
+                    for (int f = f0; f < f1; ++f)
+                        for (int k = 0; k < 3; ++k) {
+                            for (int a = 0; a < 3; ++a)
+                                loads[f][k][(ci + off1a(t, a)) + (size_t)n1 * (cj + off1b(t, a))] += acc[f][k][a];
+                            if (region == CONDUIT) loads[f][k][nv + e] += acc[f][k][3];
+                        }
+                }
+}
+
+void mini_exact_spatial(int N, std::vector<double> out[8]) {
+    const int n1 = N + 1;
+    const double h = 1.0 / N;
+    for (int f = 0; f < 6; ++f) out[f].assign((size_t)n1 * n1, 0.0);
+    for (int f = 6; f < 8; ++f) out[f].assign(2 * (size_t)N * N, 0.0);
+    auto u = [](double x, double y, double &u1, double &u2) {
+        const double ym = y - 1.0;
+        u1 = x * x * ym * ym + y;
+        u2 = -2.0 / 3.0 * x * ym * ym * ym + gfun(x);
+    };
+    for (int j = 0; j < n1; ++j)
+        for (int i = 0; i < n1; ++i) {
+            const size_t v = i + (size_t)n1 * j;
+            const double x = i * h, y = j * h;
+            for (int f = 0; f < 3; ++f) {
+                double Y, Y2;
+                yprof(f, y, Y, Y2);
+                out[f][v] = gfun(x) * Y;
+            }
+            u(x, 1.0 + y, out[3][v], out[4][v]);
+            out[5][v] = gfun(x) * std::sin(0.5 * PI * (1.0 + y));
+        }
+    for (int cj = 0; cj < N; ++cj)
+        for (int ci = 0; ci < N; ++ci)
+            for (int t = 0; t < 2; ++t) {
+                double x, yl;
+                to_xy(t, ci * h, cj * h, h, 1.0 / 3.0, 1.0 / 3.0, x, yl);
+                u(x, 1.0 + yl, out[6][2 * (ci + (size_t)N * cj) + t], out[7][2 * (ci + (size_t)N * cj) + t]);
+            }
 }
 
 }  // namespace lp

@@ -134,4 +134,24 @@ void exact_spatial(int N, std::vector<double> out[6]);
 //                                           -> loads[3+c][0] (cos), [1] (sin), [2] (cos^2)
 void source_loads(int N, const lp_params &prm, std::vector<double> loads[5][3]);
 
+// The paper's own elements (Section 6): MINI in the conduit (P1 hats plus the
+// bubble 27 l0 l1 l2, index 3), P1 porous pressures.  Unit-cell data as RefData.
+constexpr int MINI_NQ = 25;  // collapsed Gauss 5 x 5, exact to degree 8
+struct MiniRef {
+    double w[MINI_NQ];               // weights times |det J| for h = 1 (sum 1/2)
+    double phi[MINI_NQ][4];          // P1 hats (= the P1 pressure basis), then the bubble
+    double dphi[2][MINI_NQ][4][2];   // unit-cell gradients per orientation
+};
+void build_mini_refdata(MiniRef &r);
+// Loads of the Example 1 sources (time-separable parts as in source_loads)
+// against P1 on the porous vertex lattice (loads[0..2][0..1], i + (N+1) j) and
+// against MINI on the conduit (loads[3+c][0..2]: vertices, then one bubble per
+// element id 2 (i + N j) + t).
+void mini_source_loads(int N, const lp_params &prm, std::vector<double> loads[5][3]);
+// Spatial parts of the Example 1 exact fields: pF, pf, pm, u1, u2, p at the
+// vertices of their region, then u1, u2 at the element centroids.
+void mini_exact_spatial(int N, std::vector<double> out[8]);
+// Error status with a message for lp_last_error (api.cpp).
+lp_status set_error(lp_status s, const std::string &msg);
+
 }  // namespace lp

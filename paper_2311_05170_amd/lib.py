@@ -37,7 +37,8 @@ LP_ERR_NOCONV = 5
 EXPORTS = ["lp_setup", "lp_coarse_step", "lp_local_step", "lp_get_size", "lp_get_solution",
            "lp_get_stats", "lp_get_sample_stats", "lp_plan_query", "lp_get_index_map", "lp_set_timing", "lp_get_timing",
            "lp_local_step_noalloc", "lp_band_factor_solve", "lp_state_size", "lp_save_state",
-           "lp_load_state", "lp_destroy", "lp_last_error"]
+           "lp_load_state", "lp_mini_setup", "lp_mini_step", "lp_mini_get", "lp_mini_stats", "lp_mini_destroy",
+           "lp_destroy", "lp_last_error"]
 # stage timer indices (LP_T_* in lp.h)
 STAGES = ["prolong", "por_rhs", "por_solve", "por_res", "ose_rhs", "ose_asm", "ose_lu", "ose_solve",
           "ose_res", "merge", "coarse", "wait_coarse", "wait_fac", "wait_por"]
@@ -121,8 +122,14 @@ def load(path=LIB_PATH):
     lib.lp_destroy.argtypes = [c_void_p]
     lib.lp_destroy.restype = None
     lib.lp_last_error.restype = c_char_p
+    lib.lp_mini_setup.argtypes = [c_int32, POINTER(LpParams), c_int32, POINTER(c_void_p)]
+    lib.lp_mini_step.argtypes = [c_void_p, c_int32]
+    lib.lp_mini_get.argtypes = [c_void_p, c_int32, POINTER(c_double), c_int64, POINTER(c_int64)]
+    lib.lp_mini_stats.argtypes = [c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32)]
+    lib.lp_mini_destroy.argtypes = [c_void_p]
     for name in EXPORTS[:-2]:
         getattr(lib, name).restype = c_int32
+    lib.lp_mini_destroy.restype = None
     return lib
 
 
@@ -326,6 +333,44 @@ class LocalParallel:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             _LIB.lp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MiniAlgorithm1:
+    """Algorithm 1 with the paper's MINI + P1 elements on one grid of n cells
+    per unit length, on the device (lp_mini_*).  Fields come back in the
+    layouts lp.h states (vertex values, then one bubble per element for u)."""
+
+    def __init__(self, n, prm, dt, device=0):
+        self._h = c_void_p()
+        p = _params(prm, dt)
+        _check(_LIB.lp_mini_setup(int(n), byref(p), int(device), byref(self._h)))
+        self.n = int(n)
+
+    def step(self, nsteps=1):
+        _check(_LIB.lp_mini_step(self._h, int(nsteps)))
+
+    def solution(self, field):
+        need = c_int64(0)
+        _check(_LIB.lp_mini_get(self._h, FIELD[field], None, 0, byref(need)))
+        out = np.zeros(need.value, dtype=np.float64)
+        _check(_LIB.lp_mini_get(self._h, FIELD[field], out.ctypes.data_as(POINTER(c_double)), need.value, None))
+        return out
+
+    def stats(self):
+        st, its, fl = c_int32(0), c_int32(0), c_int32(0)
+        _check(_LIB.lp_mini_stats(self._h, byref(st), byref(its), byref(fl)))
+        return dict(step=st.value, newton_its_max=its.value, flags=fl.value)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _LIB.lp_mini_destroy(self._h)
             self._h = None
 
     def __del__(self):
