@@ -599,12 +599,25 @@ def paper_elements_run():
     finally:
         g.close()
     n1 = N + 1
+    n, bw = 3 * n1 * n1 + 4 * N * N, 7 * N + 16
+    # the dominant kernel: the FP64 band factorisation of the Navier-Stokes
+    # system, once per step (chord iterations), timed by HIP events around
+    # each launch over the whole run
+    flops = band_lu_flops([(n, bw)])
+    nbytes = float(n * (2 * bw + 1) * 8 + (2 * n * bw + n) * 8)
+    lu_ms = st["lu_ms"] / max(st["lu_launches"], 1)
+    roof_ms = max(nbytes / (PEAK_HBM_GBS * 1e9), flops / (PEAK_FP64_TFLOPS * 1e12)) * 1e3
+    bound = "hbm" if nbytes / (PEAK_HBM_GBS * 1e9) >= flops / (PEAK_FP64_TFLOPS * 1e12) else "mfma"
     return {"workload": "2D Example-1 MMS with the paper's elements (MINI conduit, P1 porous), Algorithm 1 on "
                         "h=1/%d, dt=h^2=1/%d, T=1, unit parameters (Table 2, second row)" % (N, N * N),
-            "ms_per_step": ms, "steps": nsteps - warm, "warmup": warm, "newton_its_max": st["newton_its_max"],
+            "ms_per_step": ms, "steps": nsteps - warm, "warmup": warm, "iterations_max": st["newton_its_max"],
             "flags": st["flags"],
-            "unknowns": {"navier_stokes": 3 * n1 * n1 + 4 * N * N, "porous": 3 * n1 * n1,
-                         "ns_half_bandwidth": 7 * N + 16}}
+            "unknowns": {"navier_stokes": n, "porous": 3 * n1 * n1, "ns_half_bandwidth": bw},
+            "roofline": {"kernel": "k_band_lu_la<double,9> (Navier-Stokes band LU, one system)", "bound": bound,
+                         "achieved": nbytes / (lu_ms * 1e-3) / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": roof_ms / lu_ms, "traffic": None, "bytes_per_launch": nbytes,
+                         "flops_per_launch": flops, "avg_launch_ms": lu_ms, "launches": st["lu_launches"],
+                         "timing": "HIP events around each launch"}}
 
 
 def paper_elements_cpu():
@@ -632,6 +645,8 @@ def main():
     ap.add_argument("--lean", action="store_true",
                     help="profiling runs: only the timed cfg2 passes and the roofline pass (no graphs, no scheme "
                          "comparison, no uneven line, no CPU leg)")
+    ap.add_argument("--paper-only", action="store_true",
+                    help="run only Algorithm 1 with the paper's elements and print its object")
     ap.add_argument("--uneven-only", action="store_true",
                     help="run only the h = 1/256 uneven batch (both precisions) and print its object")
     ap.add_argument("--cpu-leg", default=None, help=argparse.SUPPRESS)
@@ -653,6 +668,11 @@ def main():
         return
     if args.summarize_trace:
         summarize_trace(args.summarize_trace, args.trace_last, args.trace_split)
+        return
+    if args.paper_only:
+        import torch
+        assert torch.cuda.is_available(), "bench.py needs a HIP device"
+        print(json.dumps({"paper_elements": paper_elements_run()}), flush=True)
         return
     if args.uneven_only:
         import torch

@@ -400,8 +400,10 @@ void lp_destroy(lp_ctx *ctx);
  *      lagged Gamma flux u^n . n_c (their matrices are constant: factored
  *      once at setup);
  *   2. backward-Euler Navier-Stokes on the MINI space with the lagged p_F^n
- *      on Gamma, by Newton's method from (u^n, p^n) with the boundary values
- *      of t_{n+1}, to a relative update <= 1e-13 (at most 30 iterations).
+ *      on Gamma, from (u^n, p^n) with the boundary values of t_{n+1}, by chord
+ *      iterations (the Jacobian of the step's first iterate, applied to the
+ *      exact residual of every iterate) to a relative update <= 1e-13 (at
+ *      most 30 iterations).
  * The same model, coefficients and time levels as lp_setup's (sources and
  * Dirichlet data at t_{n+1}); initial data: vertex values of the exact
  * fields, and each element's bubble coefficient chosen so that the
@@ -427,12 +429,15 @@ void lp_destroy(lp_ctx *ctx);
  * lp_mini_get: copies `field` into out[len]; *needed (if not NULL) receives
  *   its length; out = NULL only queries it.  LP_ERR_ARG for an unknown field
  *   or a short buffer.
- * lp_mini_stats: steps taken, the most Newton iterations of any step, flags. */
+ * lp_mini_stats: steps taken, the most iterations of any step, flags, and the
+ *   summed HIP-event time (ms) and count of the Navier-Stokes factorisations
+ *   (any output may be NULL). */
 typedef struct lp_mini lp_mini;
 lp_status lp_mini_setup(int32_t n, const lp_params *prm, int32_t device, lp_mini **out);
 lp_status lp_mini_step(lp_mini *ctx, int32_t nsteps);
 lp_status lp_mini_get(lp_mini *ctx, int32_t field, double *out, int64_t len, int64_t *needed);
-lp_status lp_mini_stats(lp_mini *ctx, int32_t *steps, int32_t *newton_its_max, int32_t *flags);
+lp_status lp_mini_stats(lp_mini *ctx, int32_t *steps, int32_t *newton_its_max, int32_t *flags, double *lu_ms,
+                        int64_t *lu_launches);
 void lp_mini_destroy(lp_mini *ctx);
 
 const char *lp_last_error(void);

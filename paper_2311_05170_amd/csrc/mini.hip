@@ -8,10 +8,10 @@
 //      constant and factored once), one node-gather right-hand side kernel and
 //      one band solve launch;
 //   2. backward-Euler Navier-Stokes on the MINI space with the lagged p_F^n on
-//      Gamma (Algorithm 1 Step 2), Newton's method: per iteration one
-//      row-gather kernel writes the Jacobian band and -F, the band LU and
-//      solve of the library give the update, and one block applies it and
-//      forms the norms of the convergence test.
+//      Gamma (Algorithm 1 Step 2) by chord iterations: one row-gather kernel
+//      writes -F (and, at the step's first iterate, the Jacobian band, which
+//      the library's band LU factors), the band solve gives the update, and
+//      one block applies it and forms the norms of the convergence test.
 //
 // Unknowns of the Navier-Stokes system, in band order: vertex by vertex (x
 // fastest), each vertex (i, j) with i, j < N holding [u_x, u_y, the bubbles
@@ -64,6 +64,7 @@ struct MiniNsArgs {
     double *band;                 // Jacobian, entry (r, c) at c (2 bw + 1) + bw + r - c (cleared)
     double *rhs;                  // -F
     Coef co;
+    int jac;                      // 1: also write the Jacobian rows (0: -F only)
 };
 
 __global__ void __launch_bounds__(128) k_mini_ns_rows(MiniNsArgs a) {
@@ -76,7 +77,7 @@ __global__ void __launch_bounds__(128) k_mini_ns_rows(MiniNsArgs a) {
     const long long ld = 2 * a.bw + 1;
     const int R = kind == 2 ? a.vp[v] : kind < 2 ? a.vu[v] + c : a.eb[e] + c;
     if (kind < 2 && a.dirv[v]) {
-        a.band[(long long)R * ld + a.bw] = 1.0;
+        if (a.jac) a.band[(long long)R * ld + a.bw] = 1.0;
         a.rhs[R] = 0.0;
         return;
     }
@@ -150,10 +151,12 @@ __global__ void __launch_bounds__(128) k_mini_ns_rows(MiniNsArgs a) {
                 for (int b = 0; b < 3; ++b) Jp[b] -= wq * eta * phi[b] * gac;
             }
         }
-        for (int b = 0; b < 4; ++b)
-            for (int d = 0; d < 2; ++d) put(iu[b] + d, Jv[b][d]);
-        if (kind != 2)
-            for (int b = 0; b < 3; ++b) put(ip[b], Jp[b]);
+        if (a.jac) {
+            for (int b = 0; b < 4; ++b)
+                for (int d = 0; d < 2; ++d) put(iu[b] + d, Jv[b][d]);
+            if (kind != 2)
+                for (int b = 0; b < 3; ++b) put(ip[b], Jp[b]);
+        }
     }
     if (kind != 2) {
         // sources (time-separable loads)
@@ -174,7 +177,7 @@ __global__ void __launch_bounds__(128) k_mini_ns_rows(MiniNsArgs a) {
                     const double pF = a.pF0[ib + n1 * N];
                     if (c == 0) {
                         const int col = a.vu[ib];
-                        put(col, eta * co.beta * G);
+                        if (a.jac) put(col, eta * co.beta * G);
                         F += eta * co.beta * G * a.x[col] + co.ctau * Gx * pF;
                     } else {
                         F -= eta / co.rho * G * pF;
@@ -311,6 +314,9 @@ struct lp_mini {
     hipStream_t st = nullptr;
     std::vector<int32_t> vu, vp, eb;
     int32_t steps = 0, its_max = 0, flags = 0;
+    double lu_ms = 0.0;           // HIP-event time of the Navier-Stokes factorisations
+    int64_t lu_launches = 0;
+    hipEvent_t ev[2] = {nullptr, nullptr};
     std::vector<void *> bufs;
     // device
     int32_t *d_vu = nullptr, *d_vp = nullptr, *d_eb = nullptr;
@@ -334,6 +340,8 @@ struct lp_mini {
     }
     ~lp_mini() {
         for (void *v : bufs) (void)hipFree(v);
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
         if (st) (void)hipStreamDestroy(st);
     }
 };
@@ -535,15 +543,23 @@ lp_status mini_step(lp_mini *c) {
     lp::BandArgs<double> ba{c->sys_ns, c->band, c->fac, c->lflags, nullptr, c->dummy, c->consts, c->consts + 1, c->lstat};
     lp::SolveArgs<double> sa{c->sys_ns, c->fac, c->rhs, c->d, nullptr, 1, nullptr, c->consts, c->consts + 1, c->consts};
     sa.assign = 1;
+    // chord iterations: the Jacobian is formed and factored at the first
+    // iterate of the step and applied to the exact residual of every iterate,
+    // so the step reaches the same fixed point at the same tolerance
     const int maxit = 30;
     int it = 0;
     bool conv = false;
     while (it < maxit && !conv) {
         ++it;
-        MCHK(hipMemsetAsync(c->band, 0, nband * sizeof(double), c->st));
+        na.jac = it == 1;
+        if (na.jac) MCHK(hipMemsetAsync(c->band, 0, nband * sizeof(double), c->st));
         hipLaunchKernelGGL(lp::k_mini_ns_rows, dim3(grid(nrows, 128)), dim3(128), 0, c->st, na);
-        if (!lp::launch_band_lu<double>(ba, 1, c->bw_ns, c->var_ns, c->st))
-            return lp::set_error(LP_ERR_UNSUPPORTED, "Navier-Stokes factorisation window");
+        if (na.jac) {
+            MCHK(hipEventRecord(c->ev[0], c->st));
+            if (!lp::launch_band_lu<double>(ba, 1, c->bw_ns, c->var_ns, c->st))
+                return lp::set_error(LP_ERR_UNSUPPORTED, "Navier-Stokes factorisation window");
+            MCHK(hipEventRecord(c->ev[1], c->st));
+        }
         if (!lp::launch_band_solve<double>(sa, 1, 1, c->bw_ns, nns, 0, c->st))
             return lp::set_error(LP_ERR_UNSUPPORTED, "Navier-Stokes band solve size");
         hipLaunchKernelGGL(lp::k_mini_update, dim3(1), dim3(1024), 0, c->st, nns, c->d, c->x, c->norms);
@@ -552,6 +568,12 @@ lp_status mini_step(lp_mini *c) {
         MCHK(hipStreamSynchronize(c->st));
         // relative update <= 1e-13 (||d|| <= tol ||x||, in squares)
         conv = nrm[0] <= 1e-26 * nrm[1];
+        if (na.jac) {
+            float ms = 0.f;
+            MCHK(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+            c->lu_ms += ms;
+            c->lu_launches += 1;
+        }
     }
     MCHK(hipGetLastError());
     std::swap(c->P, c->Pn);
@@ -597,9 +619,10 @@ lp_status lp_mini_setup(int32_t n, const lp_params *prm, int32_t device, lp_mini
     c->co.beta = prm->alpha * prm->nu / std::sqrt(prm->k[0]);
     c->co.ctau = prm->eta * prm->nu * prm->alpha * std::sqrt(prm->k[0]) / mu;
     c->co.convection = 1;
-    if (hipStreamCreate(&c->st) != hipSuccess) {
+    if (hipStreamCreate(&c->st) != hipSuccess || hipEventCreate(&c->ev[0]) != hipSuccess ||
+        hipEventCreate(&c->ev[1]) != hipSuccess) {
         delete c;
-        return lp::set_error(LP_ERR_DEVICE, "hipStreamCreate failed");
+        return lp::set_error(LP_ERR_DEVICE, "stream or event creation failed");
     }
     const lp_status s = mini_init(c);
     if (s != LP_OK) {
@@ -656,8 +679,11 @@ lp_status lp_mini_get(lp_mini *c, int32_t field, double *out, int64_t len, int64
     return LP_OK;
 }
 
-lp_status lp_mini_stats(lp_mini *c, int32_t *steps, int32_t *newton_its_max, int32_t *flags) {
+lp_status lp_mini_stats(lp_mini *c, int32_t *steps, int32_t *newton_its_max, int32_t *flags, double *lu_ms,
+                        int64_t *lu_launches) {
     if (!c) return lp::set_error(LP_ERR_ARG, "NULL context");
+    if (lu_ms) *lu_ms = c->lu_ms;
+    if (lu_launches) *lu_launches = c->lu_launches;
     if (steps) *steps = c->steps;
     if (newton_its_max) *newton_its_max = c->its_max;
     if (flags) *flags = c->flags;

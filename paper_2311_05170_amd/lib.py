@@ -125,7 +125,8 @@ def load(path=LIB_PATH):
     lib.lp_mini_setup.argtypes = [c_int32, POINTER(LpParams), c_int32, POINTER(c_void_p)]
     lib.lp_mini_step.argtypes = [c_void_p, c_int32]
     lib.lp_mini_get.argtypes = [c_void_p, c_int32, POINTER(c_double), c_int64, POINTER(c_int64)]
-    lib.lp_mini_stats.argtypes = [c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32)]
+    lib.lp_mini_stats.argtypes = [c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32), POINTER(c_double),
+                                  POINTER(c_int64)]
     lib.lp_mini_destroy.argtypes = [c_void_p]
     for name in EXPORTS[:-2]:
         getattr(lib, name).restype = c_int32
@@ -364,9 +365,9 @@ class MiniAlgorithm1:
         return out
 
     def stats(self):
-        st, its, fl = c_int32(0), c_int32(0), c_int32(0)
-        _check(_LIB.lp_mini_stats(self._h, byref(st), byref(its), byref(fl)))
-        return dict(step=st.value, newton_its_max=its.value, flags=fl.value)
+        st, its, fl, lms, lun = c_int32(0), c_int32(0), c_int32(0), c_double(0.0), c_int64(0)
+        _check(_LIB.lp_mini_stats(self._h, byref(st), byref(its), byref(fl), byref(lms), byref(lun)))
+        return dict(step=st.value, newton_its_max=its.value, flags=fl.value, lu_ms=lms.value, lu_launches=lun.value)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
