@@ -19,7 +19,7 @@ Layout
            the same in 3D (Kuhn tetrahedra, Example 2 reflected): Algorithms 1
            and 3, exact prolongation, the Step 2 extension rule
   mini     the paper's own elements (MINI conduit, P1 porous; Section 6) with
-           Algorithm 1 on one grid
+           Algorithm 1 on one grid and Algorithm 3 (Steps 1-4)
 
 Readings of points where the paper is silent are listed in the docstrings of
 ``scheme.py`` and, for the MINI element, ``mini.py``; every oracle function

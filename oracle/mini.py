@@ -23,14 +23,27 @@ Readings
       centroid exact (b(centroid) = 1, the P1 part there is the vertex mean).
   M2  Dirichlet data at the boundary vertices; bubbles are interior unknowns.
   M3  Gamma terms act on traces, where the bubbles vanish: the P1 edge forms.
+  M5  Algorithm 3: the MINI spaces of T_H and T_h are not nested (a coarse
+      bubble is not a fine MINI function), so Pi_h is the fine MINI
+      interpolant of the coarse function (its values at the fine vertices,
+      bubbles exact at the fine centroids, as M1); the P1 parts are nested
+      and prolonged exactly.  The local spaces are the fine functions
+      supported in Omega_j: vertices off the artificial faces (velocity and
+      pressure, as R1 and R1p) and the bubbles of the elements inside.  The
+      merge weights vertices as R4 and takes a bubble from the core holding
+      its element.
+  M6  the lagged e^n of Eqs. (5.5)-(5.8): the subdomain's own e_j^n, as the
+      equations write it ("own", the default and the library's reading), or
+      the merged correction of Step 4 restricted to Omega_j and zero on its
+      artificial faces ("merged"), offered to compare with Table 1.
 """
 import numpy as np
 import scipy.sparse as sps
 
 from .fe import triangle_rule, p1_basis, gauss_legendre_01
-from .mesh import RegionMesh, POROUS, CONDUIT
+from .mesh import RegionMesh, POROUS, CONDUIT, make_subdomains, owner_counts
 from .mms import MMS
-from .scheme import Coefs, _solve_dirichlet
+from .scheme import Coefs, _solve_dirichlet, _locate
 
 _PTS, _WTS = triangle_rule(6)              # exact to degree 10
 _P1V, _P1G = p1_basis(_PTS)                # (nq, 3), (3, 2)
@@ -172,12 +185,13 @@ def load(mesh, E, func, space):
     return out
 
 
-def gamma_p1(mesh):
-    """P1 edge forms on Gamma (y = 1): G[a,b] = int phi_a phi_b and
-    Gx[a,b] = int phi_a d_x phi_b, on the region's P1 lattice."""
+def gamma_p1(mesh, x0=0, x1=None):
+    """P1 edge forms on the Gamma edges (y = 1) of cells x0 <= i < x1:
+    G[a,b] = int phi_a phi_b and Gx[a,b] = int phi_a d_x phi_b, on the
+    region's P1 lattice."""
     n, N, h = mesh.n1 ** 2, mesh.N, mesh.h
     j = N if mesh.region == POROUS else 0
-    i = np.arange(N)
+    i = np.arange(x0, N if x1 is None else x1)
     nodes = np.stack([i + mesh.n1 * j, i + 1 + mesh.n1 * j], 1)
     s, ws = gauss_legendre_01(4)
     val = np.stack([1 - s, s], 1)
@@ -333,3 +347,273 @@ def errors(mesh, vec, exact, space):
         e2 += np.sum(w[None] * (uh - ux.reshape(uh.shape)) ** 2)
         g2 += np.sum(w[None, :, None] * (gh - gx.reshape(gh.shape)) ** 2)
     return np.sqrt(e2), np.sqrt(g2)
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 3 with the paper's elements (Table 1)
+# ---------------------------------------------------------------------------
+def eval_mini(coarse, vec, X):
+    """Values at points X (n, 2) of a MINI (vertices + bubbles) or, with a
+    vector of vertex values only, P1 function on the mesh `coarse`."""
+    eid, ref = _locate(coarse, X[:, 0], X[:, 1] - coarse.y0)
+    val, _ = mini_basis(ref)
+    nv = coarse.n1 ** 2
+    out = np.einsum("na,na->n", val[:, :3], vec[coarse.el_p1[eid]])
+    if len(vec) > nv:
+        out += val[:, 3] * vec[nv + eid]
+    return out
+
+
+def prolong_mini(coarse, fine, vec):
+    """Reading M5: the fine MINI interpolant of a coarse MINI function."""
+    vert = eval_mini(coarse, vec, fine.p1_coords())
+    E = np.arange(2 * fine.N ** 2)
+    cen = fine.p1_coords()[fine.el_p1[E]].mean(axis=1)
+    return np.concatenate([vert, eval_mini(coarse, vec, cen) - vert[fine.el_p1[E]].mean(axis=1)])
+
+
+def _classify_p1(sd, mesh):
+    """Per local vertex of Omega_j: 0 free, 1 physical Dirichlet, 2 artificial."""
+    pn, I, J = sd.p1_nodes(mesh)
+    phys = (I == 0) | (I == mesh.N) | ((J == 0) if mesh.region == POROUS else (J == mesh.N))
+    cls = np.where(sd.artificial_p1(I, J), 2, 0)
+    cls[phys] = 1
+    return pn, I, J, cls
+
+
+class MiniOracle2D:
+    """Algorithm 3 (Section 5) with MINI + P1: init(), then per step
+    coarse_step() and local_step(); merged() reads the corrected fields."""
+
+    def __init__(self, NH, Nh, cuts, overlap, prm, dt, previous="own"):
+        assert Nh % NH == 0 and previous in ("own", "merged")
+        self.previous = previous
+        self.co = Coefs(prm, dt)
+        self.mms = MMS(prm)
+        self.cg = MiniProblem(NH, self.co)
+        self.fg = MiniProblem(Nh, self.co)
+        self.subs = make_subdomains(Nh, cuts, overlap)
+        self.cuts = cuts
+        self.n = 0
+        self._cache = {}
+
+    def t(self, n):
+        return n * self.co.dt
+
+    def _mesh(self, region):
+        return self.fg.mp if region == POROUS else self.fg.mc
+
+    def _pro_u(self, U):
+        cm, fm = self.cg.mc, self.fg.mc
+        nb = n_vel(cm)
+        return np.concatenate([prolong_mini(cm, fm, U[:nb]), prolong_mini(cm, fm, U[nb:])])
+
+    def _pro_p1(self, mesh_c, mesh_f, v):
+        return eval_mini(mesh_c, v, mesh_f.p1_coords())
+
+    def init(self):
+        cg, fg, mms = self.cg, self.fg, self.mms
+        self.P = [interp_p1(cg.mp, mms, nm, 0.0) for nm in ("pF", "pf", "pm")]
+        self.U = np.concatenate([interp_mini(cg.mc, mms, "u1", 0.0), interp_mini(cg.mc, mms, "u2", 0.0)])
+        self.Pc = interp_p1(cg.mc, mms, "p", 0.0)
+        self.P_old, self.U_old = [p.copy() for p in self.P], self.U.copy()
+        fineP = [interp_p1(fg.mp, mms, nm, 0.0) for nm in ("pF", "pf", "pm")]
+        fineU = np.concatenate([interp_mini(fg.mc, mms, "u1", 0.0), interp_mini(fg.mc, mms, "u2", 0.0)])
+        ProlP = [self._pro_p1(cg.mp, fg.mp, p) for p in self.P]
+        ProlU = self._pro_u(self.U)
+        nb = n_vel(fg.mc)
+        self.e = {}
+        for sd in self.subs:
+            mesh = self._mesh(sd.region)
+            pn, _, _, cls = _classify_p1(sd, mesh)
+            if sd.region == POROUS:
+                self.e[sd.sid] = [np.where(cls == 2, 0.0, fineP[i][pn] - ProlP[i][pn]) for i in range(3)]
+            else:
+                vi = self._vel_index(sd)
+                d = fineU - ProlU
+                ev = d[vi]
+                ev[self._vel_fixed(sd) == 2] = 0.0
+                self.e[sd.sid] = [ev, np.zeros(len(pn))]
+        self.n = 0
+
+    def coarse_step(self):
+        """Step 1: Algorithm 1's step on T_H."""
+        t1 = self.t(self.n + 1)
+        self.P_old, self.U_old = [p.copy() for p in self.P], self.U.copy()
+        P_new = mini_porous_step(self.cg, self.mms, self.P, self.U, t1)
+        U_new, P_c, _ = mini_ns_step(self.cg, self.mms, self.U, self.Pc, self.P[0], t1)
+        self.P, self.U, self.Pc = P_new, U_new, P_c
+
+    # local velocity unknowns of a conduit subdomain: both components of the
+    # box's vertices, then of the bubbles of its elements (MINI vector indices)
+    def _vel_index(self, sd):
+        mesh = self.fg.mc
+        nb = n_vel(mesh)
+        pn = sd.p1_nodes(mesh)[0]
+        E = mesh.elements_in_box(sd.x0, sd.x1, sd.y0, sd.y1)
+        one = np.concatenate([pn, mesh.n1 ** 2 + E])
+        return np.concatenate([one, nb + one])
+
+    def _vel_fixed(self, sd):
+        mesh = self.fg.mc
+        _, _, _, cls = _classify_p1(sd, mesh)
+        nE = len(mesh.elements_in_box(sd.x0, sd.x1, sd.y0, sd.y1))
+        one = np.concatenate([cls, np.zeros(nE, dtype=cls.dtype)])
+        return np.concatenate([one, one])
+
+    def local_porous(self, sd, pro):
+        """Step 3 (1), Eqs. (5.5)-(5.7) on the P1 space of Omega_j."""
+        co, mesh, mms = self.co, self.fg.mp, self.mms
+        t1 = self.t(self.n + 1)
+        key = ("p", sd.sid)
+        if key not in self._cache:
+            E = mesh.elements_in_box(sd.x0, sd.x1, sd.y0, sd.y1)
+            M, K = p1_mass_stiff(mesh, E)
+            G = gamma_p1(mesh, sd.x0, sd.x1)[0] if sd.touches_gamma else None
+            self._cache[key] = (E, M, K, G)
+        E, M, K, G = self._cache[key]
+        pn, _, _, cls = _classify_p1(sd, mesh)
+        nn = mesh.n1 ** 2
+        PF1, Pf1, Pm1 = pro["P1"]
+        PF0, Pf0, Pm0 = pro["P0"]
+        Q = [load(mesh, E, lambda X, nm=nm: mms(nm, X, t1), "p1") for nm in ("qF", "qf", "qm")]
+
+        def full(loc):
+            v = np.zeros(nn)
+            v[pn] = loc
+            return v
+        eF, ef, em = [full(v) for v in self.e[sd.sid]]
+        gam = np.zeros(nn)
+        if G is not None:
+            nbc, n1c = n_vel(self.fg.mc), self.fg.mc.n1 ** 2
+            gam = -G @ (self.fg.T_cp @ pro["U0"][nbc:nbc + n1c])
+        rhs = [Q[0] - (co.tau[0] * (M @ (PF1 - PF0)) + co.kap[0] * (K @ PF1) + co.sst * (M @ (PF1 - Pf0)))
+               + gam + co.tau[0] * (M @ eF) + co.sst * (M @ ef),
+               Q[1] - (co.tau[1] * (M @ (Pf1 - Pf0)) + co.kap[1] * (K @ Pf1) + co.s * (M @ (Pf1 - Pm0))
+                       + co.sst * (M @ (Pf1 - PF0)))
+               + co.tau[1] * (M @ ef) + co.s * (M @ em) + co.sst * (M @ eF),
+               Q[2] - (co.tau[2] * (M @ (Pm1 - Pm0)) + co.kap[2] * (K @ Pm1) + co.s * (M @ (Pm1 - Pf0)))
+               + co.tau[2] * (M @ em) + co.s * (M @ ef)]
+        A = [(co.tau[0] + co.sst) * M + co.kap[0] * K,
+             (co.tau[1] + co.s + co.sst) * M + co.kap[1] * K,
+             (co.tau[2] + co.s) * M + co.kap[2] * K]
+        xy = mesh.p1_coords()[pn]
+        out = []
+        for i, nm in enumerate(("pF", "pf", "pm")):
+            dvals = np.where(cls == 1, mms(nm, xy, t1) - pro["P1"][i][pn], 0.0)
+            out.append(_solve_dirichlet(A[i][pn][:, pn].tocsr(), rhs[i][pn], cls != 0, dvals))
+        return out
+
+    def local_conduit(self, sd, pro):
+        """Step 3 (2), Eq. (5.8): the Oseen correction on the MINI space of
+        Omega_j, linearised about Pi_h u_H^{n+1}."""
+        co, mesh, mms = self.co, self.fg.mc, self.mms
+        t1 = self.t(self.n + 1)
+        E = mesh.elements_in_box(sd.x0, sd.x1, sd.y0, sd.y1)
+        key = ("c", sd.sid)
+        if key not in self._cache:
+            self._cache[key] = mini_stokes(mesh, E)
+        Mv, S, Bq = self._cache[key]
+        nb, n1 = n_vel(mesh), mesh.n1 ** 2
+        W1, W0, Pp = pro["U1"], pro["U0"], pro["Pc1"]
+        cv, Nm = mini_convection(mesh, E, W1)
+        Gblk = sps.csr_matrix((2 * nb, 2 * nb))
+        gam = np.zeros(2 * nb)
+        if sd.touches_gamma:
+            G, Gx = gamma_p1(mesh, sd.x0, sd.x1)
+            Gblk = sps.block_diag([G, sps.csr_matrix((nb - n1, nb - n1)), sps.csr_matrix((nb, nb))]).tocsr()
+            pg = self.fg.T_pc @ pro["P0"][0]
+            gam[nb:nb + n1] = co.eta / co.rho * (G @ pg)
+            gam[:n1] = -co.ctau * (Gx @ pg)
+        F = np.concatenate([load(mesh, E, lambda X: mms("f1", X, t1), "mini"),
+                            load(mesh, E, lambda X: mms("f2", X, t1), "mini")])
+        Avis = co.nu * co.eta * S + co.eta * co.beta * Gblk
+        A = (co.eta / co.dt) * Mv + Avis + co.eta * Nm
+        vi = self._vel_index(sd)
+        fixed = self._vel_fixed(sd)
+        pn, I, J, cls = _classify_p1(sd, mesh)
+        pfix = sd.artificial_p1(I, J)          # R1p: every artificial vertex, physical ones too
+        en = np.zeros(2 * nb)
+        en[vi] = self.e[sd.sid][0]
+        rv = co.eta * F - ((co.eta / co.dt) * (Mv @ (W1 - W0)) + Avis @ W1
+                           - co.eta * (Bq.T @ Pp) + co.eta * cv) + gam + (co.eta / co.dt) * (Mv @ en)
+        rq = -co.eta * (Bq @ W1)
+        K = sps.bmat([[A[vi][:, vi], -co.eta * Bq.T[vi][:, pn]],
+                      [co.eta * Bq[pn][:, vi], None]]).tocsr()
+        rhs = np.concatenate([rv[vi], rq[pn]])
+        # physical Dirichlet vertices: g(t_{n+1}) - Pi_h u_H^{n+1}
+        xyv = mesh.p1_coords()
+        nE = len(E)
+        g = np.concatenate([mms("u1", xyv[pn], t1), np.zeros(nE), mms("u2", xyv[pn], t1), np.zeros(nE)])
+        dv = np.where(fixed == 1, g - W1[vi], 0.0)
+        z = _solve_dirichlet(K, rhs, np.concatenate([fixed != 0, pfix]), np.concatenate([dv, np.zeros(len(pn))]))
+        return [z[:len(vi)], z[len(vi):]]
+
+    def prolonged(self):
+        cg, fg = self.cg, self.fg
+        return dict(P1=[self._pro_p1(cg.mp, fg.mp, p) for p in self.P],
+                    P0=[self._pro_p1(cg.mp, fg.mp, p) for p in self.P_old],
+                    U1=self._pro_u(self.U), U0=self._pro_u(self.U_old),
+                    Pc1=self._pro_p1(cg.mc, fg.mc, self.Pc))
+
+    def local_step(self):
+        pro = self.prolonged()
+        self.e = {sd.sid: (self.local_porous(sd, pro) if sd.region == POROUS else self.local_conduit(sd, pro))
+                  for sd in self.subs}
+        self.n += 1
+        self._pro = pro
+        if self.previous == "merged":
+            # reading M6: the next step lags the merged correction
+            f = self.merged()
+            for sd in self.subs:
+                mesh = self._mesh(sd.region)
+                pn, _, _, cls = _classify_p1(sd, mesh)
+                if sd.region == POROUS:
+                    self.e[sd.sid] = [np.where(cls == 2, 0.0, (f[k] - pro["P1"][i])[pn])
+                                      for i, k in enumerate(("pF", "pf", "pm"))]
+                else:
+                    vi = self._vel_index(sd)
+                    ev = (f["u"] - pro["U1"])[vi]
+                    ev[self._vel_fixed(sd) == 2] = 0.0
+                    self.e[sd.sid] = [ev, self.e[sd.sid][1]]
+
+    def merged(self):
+        """Step 4 (readings R4 and M5): pF, pf, pm (P1), u (MINI), p (P1)."""
+        pro = self._pro
+        out = {}
+        for region in (POROUS, CONDUIT):
+            mesh = self._mesh(region)
+            i1 = np.arange(mesh.n1)
+            vx = 1.0 / owner_counts(self.cuts[(region, 0)], 2 * i1)
+            vy = 1.0 / owner_counts(self.cuts[(region, 1)], 2 * i1)
+            if region == POROUS:
+                acc = [p.copy() for p in pro["P1"]]
+            else:
+                acc = [pro["U1"].copy(), pro["Pc1"].copy()]
+            nb, n1v = n_vel(mesh), mesh.n1 ** 2
+            for sd in self.subs:
+                if sd.region != region:
+                    continue
+                dx0, dx1, dy0, dy1 = sd.d
+                pn, I, J, _ = _classify_p1(sd, mesh)
+                inD = (I >= dx0) & (I <= dx1) & (J >= dy0) & (J <= dy1)
+                w = vx[I] * vy[J]
+                if region == POROUS:
+                    for k in range(3):
+                        acc[k][pn[inD]] += w[inD] * self.e[sd.sid][k][inD]
+                    continue
+                E = mesh.elements_in_box(sd.x0, sd.x1, sd.y0, sd.y1)
+                cell = mesh.el_cell[E]
+                inDe = (cell[:, 0] >= dx0) & (cell[:, 0] < dx1) & (cell[:, 1] >= dy0) & (cell[:, 1] < dy1)
+                ev = self.e[sd.sid][0]
+                nloc = len(pn) + len(E)
+                for c in range(2):
+                    part = ev[c * nloc:(c + 1) * nloc]
+                    acc[0][c * nb + pn[inD]] += w[inD] * part[:len(pn)][inD]
+                    acc[0][c * nb + n1v + E[inDe]] += part[len(pn):][inDe]
+                acc[1][pn[inD]] += w[inD] * self.e[sd.sid][1][inD]
+            if region == POROUS:
+                out["pF"], out["pf"], out["pm"] = acc
+            else:
+                out["u"], out["p"] = acc
+        return out
