@@ -84,12 +84,12 @@ UNEVEN_KRYLOV_CYCLES = 2
 UNEVEN_STEPS, UNEVEN_WARMUP = 5, 2
 
 
-def make(cfg, precision, max_ir, graphs=False):
+def make(cfg, precision, max_ir, graphs=False, lagged="own"):
     from paper_2311_05170_amd import workloads as W
     from paper_2311_05170_amd.lib import LocalParallel
     return LocalParallel(cfg["NH"], cfg["refine"], cfg["nsub"], cfg["overlap"], cfg["prm"], cfg["dt"],
                          cuts=W.flat_cuts(cfg["cuts"]), precision=precision, max_ir=max_ir,
-                         max_newton=MAX_NEWTON, jacobian_every=JACOBIAN_EVERY, graphs=graphs)
+                         max_newton=MAX_NEWTON, jacobian_every=JACOBIAN_EVERY, graphs=graphs, lagged=lagged)
 
 
 def graph_run(cfg, precision, steps, warmup, max_ir):
@@ -110,10 +110,10 @@ def graph_run(cfg, precision, steps, warmup, max_ir):
     return dict(ms_per_step=(t1 - t0) * 1e3 / steps, stats=st)
 
 
-def timed_run(cfg, precision, steps, warmup, max_ir):
+def timed_run(cfg, precision, steps, warmup, max_ir, lagged="own"):
     import torch
     from paper_2311_05170_amd import lib
-    g = make(cfg, precision, max_ir)
+    g = make(cfg, precision, max_ir, lagged=lagged)
     for _ in range(warmup):
         g.step()
     torch.cuda.synchronize()
@@ -732,6 +732,11 @@ def main():
     ens = None if (args.lean or args.no_ensemble) else ensemble_run(L, lu_bytes)
     if ens:
         progress("ensemble")
+    # the same timed region with the lagged correction taken from the merged
+    # field (lp_options.lagged = LP_LAG_MERGED): one more kernel per step
+    lagm = None if args.lean else timed_run(cfg, "mixed", args.steps, args.warmup, MAX_IR_MIXED, lagged="merged")
+    if lagm:
+        progress("cfg2 mixed, merged lagged correction")
     paper = None if args.lean else paper_elements_run()
     if paper:
         progress("paper's elements")
@@ -770,7 +775,7 @@ def main():
     coarse = lib.plan_query(*qargs, 6, cuts=flat)
     roof_ms_mixed, stages_mixed = step_roofline(cfg, sizes, tab, coarse, mixed["stats"], 4, JACOBIAN_EVERY)
     roof_ms_fp64, stages_fp64 = step_roofline(cfg, sizes, tab, coarse, fp64["stats"], 8, JACOBIAN_EVERY)
-    flags = [r["stats"]["flags"] for r in (mixed, fp64, gmix, gf64) if r]
+    flags = [r["stats"]["flags"] for r in (mixed, fp64, gmix, gf64, lagm) if r]
     if schemes:
         flags += [v["flags"] for k, v in schemes.items() if k.startswith("algorithm")]
     if uneven:
@@ -832,6 +837,9 @@ def main():
         line["uneven_batch"] = uneven
     if ens:
         line["ensemble"] = ens
+    if lagm:
+        line["lagged_merged"] = {"ms_per_step": lagm["ms_per_step"], "flags": lagm["stats"]["flags"],
+                                 "merge_stage_ms": lagm["stages_ms"].get("merge")}
     if paper:
         line["paper_elements"] = paper
     if not (args.no_cpu or args.lean):

@@ -103,6 +103,10 @@ enum { LP_NEWTON = 0, LP_SEMI_IMPLICIT = 1 };
 /* scheme: the two-grid local parallel method (Algorithm 3) or the one-grid
  * partitioned time stepping it is compared with (Algorithm 1, Section 3.3) */
 enum { LP_TWO_GRID = 0, LP_ONE_GRID = 1 };
+/* the lagged correction e^n of Eqs. (5.5)-(5.8): the subdomain's own e_j^n,
+ * as the equations write it, or the merged correction of Step 4 restricted to
+ * the subdomain */
+enum { LP_LAG_OWN = 0, LP_LAG_MERGED = 1 };
 
 typedef struct {
     int32_t problem;         /* LP_MMS_EX1_2D */
@@ -171,6 +175,17 @@ typedef struct {
                                 fields.  The partition is set up but not used; LP_LOCAL is
                                 an LP_ERR_STATE.  The band kernels bound the grid: coarse
                                 half-bandwidth 10 n_coarse + 2 <= 175, so n_coarse <= 17. */
+    int32_t lagged;          /* LP_LAG_OWN (default): the lagged e^n terms of Eqs. (5.5)-(5.8)
+                                (time derivative and exchange) take the subdomain's own
+                                correction e_j^n.  LP_LAG_MERGED: after each step's merge
+                                (Step 4), every subdomain's porous and velocity corrections
+                                are replaced by the merged correction x_h^{n+1} - Pi_h
+                                x_H^{n+1} on its lattice (zero on its artificial faces; the
+                                conduit pressure correction is not lagged), so the next step
+                                starts each subdomain from its neighbours' cores.  The
+                                paper's printed Algorithm 3 errors (Table 1, porous columns)
+                                are reproduced under this reading with its own elements.
+                                No effect with LP_ONE_GRID. */
 } lp_options;
 
 /* Optional device allocator (e.g. a framework's caching allocator). */

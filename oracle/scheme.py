@@ -30,6 +30,12 @@ Readings of points the paper leaves open (kept identical in the HIP library):
       e_{fh,j}^n in (5.7); p_cH -> p_H in (5.8).
   R17 time levels as written: porous Gamma flux uses u_cH^n, conduit uses p_FH^n;
       sources and Dirichlet data at t_{n+1} = (n+1) dt.
+  R18 the lagged e^n of Eqs. (5.5)-(5.8) is the subdomain's own e_j^n, as the
+      equations write it (previous="own"); previous="merged" lags instead the
+      merged correction of Step 4 restricted to Omega_j (zero on its
+      artificial faces; the pressure correction is not lagged), the reading
+      under which the paper's Table 1 porous errors are reproduced with its
+      own elements.
 """
 import numpy as np
 import scipy.sparse as sps
@@ -235,8 +241,9 @@ class Oracle2D:
     overlap: enlargement of D_j in fine cells.  prm: model parameters.
     """
 
-    def __init__(self, NH, Nh, cuts, overlap, prm, dt, convection=True):
-        assert Nh % NH == 0
+    def __init__(self, NH, Nh, cuts, overlap, prm, dt, convection=True, previous="own"):
+        assert Nh % NH == 0 and previous in ("own", "merged")
+        self.previous = previous
         self.co = Coefs(prm, dt)
         self.mms = MMS(prm)
         self.cg = GridProblem(NH, self.co)
@@ -406,6 +413,21 @@ class Oracle2D:
         self.e = enew
         self.n += 1
         self._pro = pro
+        if self.previous == "merged":
+            # reading R18: the next step lags the merged correction
+            f = self.merged()
+            n2 = self.fg.mc.n2 ** 2
+            for sd in self.subs:
+                mesh = self._fine_mesh(sd.region)
+                nodes, _, _ = sd.p2_nodes(mesh)
+                cls = sd.classify_p2(mesh)
+                if sd.region == POROUS:
+                    self.e[sd.sid] = [np.where(cls == 2, 0.0, (f[k] - pro["P1"][i])[nodes])
+                                      for i, k in enumerate(("pF", "pf", "pm"))]
+                else:
+                    d = f["u"] - pro["U1"]
+                    self.e[sd.sid] = [np.where(cls == 2, 0.0, d[c * n2 + nodes]) for c in range(2)] + \
+                                     [self.e[sd.sid][2]]
         return pro
 
     def merged(self):

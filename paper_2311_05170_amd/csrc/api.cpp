@@ -82,6 +82,7 @@ struct lp_ctx {
     int64_t n = 0;                 // completed local steps
     bool coarse_pending = false;
     bool one_grid = false;             // Algorithm 1: the coarse step is the whole step
+    bool lag_merged = false;           // lagged e^n from the merged correction (LP_LAG_MERGED)
     // Parameter samples advanced together (lp_options.nsamples): every system
     // list holds the systems of sample 0, then of sample 1, ...; the fields
     // read by position on a lattice (coarse states, prolongations, loads,
@@ -1156,6 +1157,8 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     if (opt->krylov_cycles < 0 || opt->krylov_cycles > opt->max_ir)
         return fail(LP_ERR_ARG, "krylov_cycles must lie in 0..max_ir");
     if (opt->scheme != LP_TWO_GRID && opt->scheme != LP_ONE_GRID) return fail(LP_ERR_ARG, "scheme must be LP_TWO_GRID or LP_ONE_GRID");
+    if (opt->lagged != LP_LAG_OWN && opt->lagged != LP_LAG_MERGED)
+        return fail(LP_ERR_ARG, "lagged must be LP_LAG_OWN or LP_LAG_MERGED");
     if (opt->scheme == LP_ONE_GRID && mesh->refine != 1)
         return fail(LP_ERR_ARG, "LP_ONE_GRID (Algorithm 1) runs on one grid: refine must be 1");
     hipStream_t st = (hipStream_t)stream;
@@ -1168,6 +1171,7 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     c->opt = *opt;
     c->mixed = opt->precision == LP_MIXED;
     c->one_grid = opt->scheme == LP_ONE_GRID;
+    c->lag_merged = opt->lagged == LP_LAG_MERGED;
     c->lu_variant_ose = 9;
     if (const char *v = std::getenv("LP_OSEEN_ASM")) c->asm_first_write = std::atoi(v) != 0;
     if (const char *v = std::getenv("LP_LU_VARIANT")) c->lu_variant = c->lu_variant_ose = c->lu_variant_cns = std::atoi(v);
@@ -1731,11 +1735,14 @@ lp_status local_step_impl(lp_ctx *c, void *stream, const LocalScratch &ls, bool 
             ma.base1 = pu + 5 * c->nf2; ma.out1 = c->m_p;
         }
         ma.e2 = c->e2[en]; ma.e1 = c->e1[en];
+        ma.cls2 = c->d_cls2;
+        ma.e2w = c->e2[en];
         ma.nper = r == lp::POROUS ? c->np1 : c->no1;
         ma.zs = c->zs;
     }
     TRY(seg(c, gkey(G_MERGE, m), st, [&](hipStream_t s) -> lp_status {
         lp::launch_merge(mr[lp::POROUS], mr[lp::CONDUIT], c->ns, s);
+        if (c->lag_merged) lp::launch_lag_merged(mr[lp::POROUS], mr[lp::CONDUIT], c->ns, s);
         return LP_OK;
     }));
     HIPCHK(hipGetLastError());
@@ -2051,7 +2058,7 @@ namespace {
 struct StateHeader {
     char magic[8];
     int64_t n;                         // completed steps
-    int32_t ecur, ns, mixed, scheme, jev, pad;
+    int32_t ecur, ns, mixed, scheme, jev, lag;
     int64_t Nh, NH, np1, no1, zs, e2_total, e1_total, inv_len, local_dofs;
 };
 struct Seg { void *dev; size_t bytes; };
@@ -2086,6 +2093,7 @@ StateHeader state_header(lp_ctx *c) {
     h.mixed = c->mixed ? 1 : 0;
     h.scheme = c->one_grid ? LP_ONE_GRID : LP_TWO_GRID;
     h.jev = c->opt.jacobian_every > 1 ? c->opt.jacobian_every : 1;
+    h.lag = c->lag_merged ? LP_LAG_MERGED : LP_LAG_OWN;
     h.Nh = c->P.Nh; h.NH = c->P.NH;
     h.np1 = c->np1; h.no1 = c->no1;
     h.zs = c->zs;
@@ -2142,7 +2150,7 @@ lp_status lp_load_state(lp_ctx *c, const void *buf, int64_t len, void *stream) {
     mine.ecur = h.ecur;
     if (std::memcmp(&h, &mine, sizeof(h)) != 0)
         return fail(LP_ERR_ARG, "the state was saved by a context of another mesh, partition, sample count, "
-                                "precision, scheme or jacobian_every");
+                                "precision, scheme, jacobian_every or lagged reading");
     const char *p = (const char *)buf + pad8(sizeof(StateHeader));
     if (len < (int64_t)(pad8(sizeof(StateHeader)) + c->samples_h.size() * sizeof(lp_params)))
         return fail(LP_ERR_ARG, "state buffer too short");

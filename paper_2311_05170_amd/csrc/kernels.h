@@ -236,6 +236,8 @@ struct MergeArgs {
     double *out1;
     int nper = 0;                 // systems of the region per sample
     long long zs = 0;             // arena stride of base / out between samples (grid z = sample)
+    const int8_t *cls2 = nullptr; // launch_lag_merged: local P2 node classes
+    double *e2w = nullptr;        // launch_lag_merged: the corrections it rewrites (e2's buffer)
 };
 
 struct InitArgs {
@@ -370,6 +372,10 @@ template <typename T>
 bool launch_band_solve(const SolveArgs<T> &a, int nsys, int nrhs, int maxbw, int maxn, int depth, hipStream_t st);
 void launch_dense_apply(const DenseArgs &a, int nsys, hipStream_t st);
 void launch_merge(const MergeArgs &porous, const MergeArgs &conduit, int nsamples, hipStream_t st);   // both regions, every sample, one launch
+// after launch_merge: every subdomain's porous and velocity corrections
+// replaced by the merged correction out - base on its local lattice (zero on
+// artificial nodes), the lagged e^n of LP_LAG_MERGED
+void launch_lag_merged(const MergeArgs &porous, const MergeArgs &conduit, int nsamples, hipStream_t st);
 void launch_init_corrections(const InitArgs &a, int nsys, hipStream_t st);
 void launch_newton_update(const NewtonArgs &a, int nsamples, hipStream_t st);
 void launch_dense_newton(const DenseNewtonArgs &a, int nsamples, hipStream_t st);

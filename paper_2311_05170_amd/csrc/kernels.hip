@@ -2642,6 +2642,26 @@ __global__ void k_merge(MergeArgs Ap, MergeArgs Ac) {
     }
 }
 
+// lagged corrections from the merged field (LP_LAG_MERGED): block (system,
+// region, sample) rewrites its local P2 lattice's corrections as the merged
+// correction out - base of Step 4, zero on artificial nodes; on physical nodes
+// every owner's correction is the same g - Pi_h x_H, so their merge is too
+__global__ void k_lag_merged(MergeArgs Ap, MergeArgs Ac) {
+    const MergeArgs &A = blockIdx.y == 0 ? Ap : Ac;
+    if ((int)blockIdx.x >= A.nper) return;
+    const long long zo = blockIdx.z * A.zs;
+    const SysDesc &S = A.sys[blockIdx.z * A.nper + blockIdx.x];
+    const int n2 = 2 * A.N + 1, nloc = S.lw2 * S.lh2;
+    const int nf = A.region == POROUS ? 3 : 2;
+    for (int q = threadIdx.x; q < nloc; q += blockDim.x) {
+        const int a = q % S.lw2, b = q / S.lw2;
+        const long long G = (2 * S.x0 + a) + (long long)n2 * (2 * S.y0 + b);
+        const bool art = A.cls2[S.node_off + q] == 2;
+        for (int f = 0; f < nf; ++f)
+            A.e2w[S.e2_off + (long long)f * nloc + q] = art ? 0.0 : A.out[f][zo + G] - A.base[f][zo + G];
+    }
+}
+
 // initial corrections e_j^0 = I_h x_0 - Pi_h x_H^0 on each local lattice, zero
 // on artificial faces (the exact data is a(x) cos t, cos 0 = 1)
 __global__ void k_init_corrections(InitArgs A) {
@@ -2890,6 +2910,10 @@ void launch_dense_apply(const DenseArgs &a, int nsys, hipStream_t st) {
 void launch_merge(const MergeArgs &porous, const MergeArgs &conduit, int nsamples, hipStream_t st) {
     long long n = (long long)(2 * porous.N + 1) * (2 * porous.N + 1) + (long long)(porous.N + 1) * (porous.N + 1);
     hipLaunchKernelGGL(k_merge, dim3(grid_for(n, 256), 2, nsamples), dim3(256), 0, st, porous, conduit);
+}
+void launch_lag_merged(const MergeArgs &porous, const MergeArgs &conduit, int nsamples, hipStream_t st) {
+    const int nb = porous.nper > conduit.nper ? porous.nper : conduit.nper;
+    hipLaunchKernelGGL(k_lag_merged, dim3(nb, 2, nsamples), dim3(256), 0, st, porous, conduit);
 }
 void launch_init_corrections(const InitArgs &a, int nsys, hipStream_t st) {
     hipLaunchKernelGGL(k_init_corrections, dim3(nsys), dim3(256), 0, st, a);

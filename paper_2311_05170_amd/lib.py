@@ -32,6 +32,7 @@ SOLVER = {"auto": LP_AUTO, "dense": LP_DENSE, "krylov": LP_KRYLOV}
 COARSE_NS = {"newton": LP_NEWTON, "semi_implicit": LP_SEMI_IMPLICIT}
 LP_TWO_GRID, LP_ONE_GRID = range(2)
 SCHEME = {"two_grid": LP_TWO_GRID, "one_grid": LP_ONE_GRID}
+LAGGED = {"own": 0, "merged": 1}
 LP_ERR_NOCONV = 5
 
 EXPORTS = ["lp_setup", "lp_coarse_step", "lp_local_step", "lp_get_size", "lp_get_solution",
@@ -65,7 +66,7 @@ class LpOptions(Structure):
                 ("newton_tol", c_double), ("jacobian_every", c_int32), ("solver", c_int32),
                 ("coarse_ns", c_int32), ("krylov_tol", c_double), ("max_iter", c_int32),
                 ("krylov_cycles", c_int32), ("nsamples", c_int32), ("autotune", c_int32), ("graphs", c_int32),
-                ("scheme", c_int32)]
+                ("scheme", c_int32), ("lagged", c_int32)]
 
 
 ALLOC_FN = CFUNCTYPE(c_void_p, c_size_t, c_void_p)
@@ -201,7 +202,7 @@ class LocalParallel:
                  convection=True, max_ir=8, ir_tol=None, max_newton=16, newton_tol=1e-13,
                  jacobian_every=1, solver="auto", coarse_ns="newton", samples=None,
                  krylov_restart=30, krylov_tol=None, krylov_cycles=0, autotune=False, graphs=False,
-                 scheme="two_grid", torch_allocator=True):
+                 scheme="two_grid", torch_allocator=True, lagged="own"):
         import torch
         self._torch = torch
         if not torch.cuda.is_available():
@@ -226,6 +227,7 @@ class LocalParallel:
         opt.autotune = 1 if autotune else 0
         opt.graphs = 1 if graphs else 0
         opt.scheme = SCHEME[scheme]
+        opt.lagged = LAGGED[lagged] if lagged in LAGGED else int(lagged)
         plist = [prm] if samples is None else list(samples)
         opt.nsamples = len(plist)
         params = (LpParams * len(plist))(*[_params(q, dt) for q in plist])

@@ -122,6 +122,7 @@ def test_setup_rejects_bad_options_without_a_device():
     assert _setup_status({"krylov_cycles": 5})[0] == 1            # more cycles than refinement sweeps
     assert _setup_status({"coarse_ns": lib.LP_SEMI_IMPLICIT})[0] == 6
     assert _setup_status({"scheme": 2})[0] == 1
+    assert _setup_status({"lagged": 2})[0] == 1
     st, msg = _setup_status({"scheme": lib.LP_ONE_GRID})          # Algorithm 1 needs refine = 1
     assert st == 1 and "refine" in msg
 
