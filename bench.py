@@ -620,6 +620,37 @@ def paper_elements_run():
                          "timing": "HIP events around each launch"}}
 
 
+EX3_N, EX3_STEPS, EX3_DT = 9, 200, 0.05
+EX3_KF = [2e-2, 4e-2, 6e-2, 8e-2, 2e-1, 4e-1, 6e-1, 8e-1]
+
+
+def example3_run():
+    """The Example-3-type variant (lp_mini_setup with LP_EX3_2D) over the
+    paper's k_F sweep: h = 1/9, dt = 0.05, T = 10 as Example 3, on the
+    two-square geometry; the outflow rate through the conduit top (the P1
+    trace of u_y, trapezoid) and the wall time per step."""
+    from paper_2311_05170_amd.lib import MiniAlgorithm1
+    N = EX3_N
+    nb = (N + 1) ** 2 + 2 * N * N
+    rates, ms = [], []
+    for kF in EX3_KF:
+        p = dict(phi=[1e-4, 1e-3, 1e-2], C=[1e-4] * 3, k=[kF, 1e-6, 1e-8], mu_tilde=1e-2, sigma=0.5,
+                 sigma_star=0.5, rho=10.0, alpha=1.0, eta=1.0, nu=1e-2)
+        g = MiniAlgorithm1(N, p, EX3_DT, problem="ex3")
+        try:
+            t0 = time.perf_counter()
+            g.step(EX3_STEPS)
+            ms.append((time.perf_counter() - t0) * 1e3 / EX3_STEPS)
+            uy = g.solution("u")[nb + N * (N + 1):nb + (N + 1) ** 2]
+        finally:
+            g.close()
+        rates.append(float((uy[:-1] + uy[1:]).sum() / (2 * N)))
+    return {"workload": "Example-3-type variant with the paper's elements: Gamma_in pressures 1.0e3/1.6e3/4.0e3, "
+                        "Stokes conduit with cased walls and an outflow top, Example 3 parameters, h=1/%d, "
+                        "dt=%g, T=%g" % (N, EX3_DT, EX3_STEPS * EX3_DT),
+            "k_F": EX3_KF, "outflow_rate": rates, "ms_per_step": sum(ms) / len(ms)}
+
+
 def paper_elements_cpu():
     """The oracle's Algorithm 1 with the same elements on a bounded sample of
     the same workload (its first PAPER_CPU_STEPS steps), ms per step."""
@@ -672,7 +703,9 @@ def main():
     if args.paper_only:
         import torch
         assert torch.cuda.is_available(), "bench.py needs a HIP device"
-        print(json.dumps({"paper_elements": paper_elements_run()}), flush=True)
+        out = paper_elements_run()
+        out["example3"] = example3_run()
+        print(json.dumps({"paper_elements": out}), flush=True)
         return
     if args.uneven_only:
         import torch
@@ -739,6 +772,7 @@ def main():
         progress("cfg2 mixed, merged lagged correction")
     paper = None if args.lean else paper_elements_run()
     if paper:
+        paper["example3"] = example3_run()
         progress("paper's elements")
     uneven = None
     if not (args.no_uneven or args.lean):

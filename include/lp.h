@@ -65,7 +65,7 @@ enum { LP_MERGED_FINE = 0, LP_COARSE = 1, LP_LOCAL = 2 };
 /* arithmetic of the local solves */
 enum { LP_FP64 = 0, LP_MIXED = 1 };
 /* manufactured problems */
-enum { LP_MMS_EX1_2D = 0 };
+enum { LP_MMS_EX1_2D = 0, LP_EX3_2D = 1 };
 
 /* Nested meshes (Section 4: T_h is a uniform refinement of T_H).
  *   n_coarse = 1/H cells per unit length, refine = H/h (integer >= 1). */
@@ -109,7 +109,8 @@ enum { LP_TWO_GRID = 0, LP_ONE_GRID = 1 };
 enum { LP_LAG_OWN = 0, LP_LAG_MERGED = 1 };
 
 typedef struct {
-    int32_t problem;         /* LP_MMS_EX1_2D */
+    int32_t problem;         /* LP_MMS_EX1_2D (LP_EX3_2D runs through lp_mini_setup only:
+                                LP_ERR_UNSUPPORTED here) */
     int32_t precision;       /* LP_FP64 (FP64 factorisation and solves) or
                                 LP_MIXED (FP32 factorisation and solves, FP64
                                 residuals, iterative refinement) */
@@ -431,8 +432,16 @@ void lp_destroy(lp_ctx *ctx);
  *   LP_P: (n+1)^2 conduit vertex values (j counted up from Gamma);
  *   LP_U: u_x then u_y, each (n+1)^2 vertex values then one bubble
  *         coefficient per element: 2 ((n+1)^2 + 2 n^2) values.
- * lp_mini_setup: `device` is a HIP device id; `prm` holds the parameters and
- *   dt.  Errors: LP_ERR_ARG (NULL, dt <= 0, n < 2: with n = 1 every conduit
+ * problem LP_EX3_2D is an Example-3-type variant (Section 6, Example 3) on
+ * the same two squares: the porous region's outer boundary is Gamma_in with
+ * fixed p_F = 1.0e3, p_f = 1.6e3, p_m = 4.0e3 (also the initial porous state);
+ * there are no sources; the conduit is Stokes (no convection) and starts at
+ * rest; its side walls x = 0, 1 are cased (u = 0, end points included); the
+ * rest of its top y = 2 is the outflow boundary (T(u, p) n = 0, natural).
+ * Fluid enters the conduit only through Gamma.  Boundary data are constant
+ * in time.
+ * lp_mini_setup: `problem` is LP_MMS_EX1_2D or LP_EX3_2D; `device` is a HIP
+ *   device id; `prm` holds the parameters and dt.  Errors: LP_ERR_ARG (NULL, dt <= 0, n < 2: with n = 1 every conduit
  *   vertex has Dirichlet velocity and the pressure keeps a free constant),
  *   LP_ERR_DEVICE,
  *   LP_ERR_UNSUPPORTED (the Navier-Stokes half-bandwidth, 7 n + 16 for n >= 2,
@@ -448,7 +457,7 @@ void lp_destroy(lp_ctx *ctx);
  *   summed HIP-event time (ms) and count of the Navier-Stokes factorisations
  *   (any output may be NULL). */
 typedef struct lp_mini lp_mini;
-lp_status lp_mini_setup(int32_t n, const lp_params *prm, int32_t device, lp_mini **out);
+lp_status lp_mini_setup(int32_t n, int32_t problem, const lp_params *prm, int32_t device, lp_mini **out);
 lp_status lp_mini_step(lp_mini *ctx, int32_t nsteps);
 lp_status lp_mini_get(lp_mini *ctx, int32_t field, double *out, int64_t len, int64_t *needed);
 lp_status lp_mini_stats(lp_mini *ctx, int32_t *steps, int32_t *newton_its_max, int32_t *flags, double *lu_ms,

@@ -240,7 +240,8 @@ def interp_mini(mesh, mms, name, tt):
 class MiniProblem:
     """Constant operators of one grid of N cells per unit length."""
 
-    def __init__(self, N, co):
+    def __init__(self, N, co, outflow_top=False):
+        self.outflow_top = outflow_top
         self.mp = RegionMesh(N, POROUS)
         self.mc = RegionMesh(N, CONDUIT)
         self.co = co
@@ -255,6 +256,11 @@ class MiniProblem:
         nb, n1 = n_vel(self.mc), self.mc.n1 ** 2
         dv = np.zeros(nb, bool)
         dv[:n1] = dirichlet_p1(self.mc)
+        if outflow_top:
+            # the side walls x = 0, 1 (their end points included) keep u = 0;
+            # the rest of the top y = 2 is an outflow boundary (natural)
+            i = np.arange(n1) % self.mc.n1
+            dv[:n1] = (i == 0) | (i == N)
         self.dir_u = dv
 
 
@@ -280,7 +286,7 @@ def mini_porous_step(mp_, mms, P_n, U_n, t1):
             for i, nm in enumerate(("pF", "pf", "pm"))]
 
 
-def mini_ns_step(mp_, mms, U_n, P_n, PF_n, t1, tol=1e-13, maxit=30):
+def mini_ns_step(mp_, mms, U_n, P_n, PF_n, t1, tol=1e-13, maxit=30, convection=True):
     """Algorithm 1 Step 2: backward Euler Navier-Stokes on the MINI space with
     the lagged p_F on Gamma, solved by Newton's method."""
     co, mc = mp_.co, mp_.mc
@@ -301,7 +307,10 @@ def mini_ns_step(mp_, mms, U_n, P_n, PF_n, t1, tol=1e-13, maxit=30):
     P = P_n.copy()
     dmask = np.concatenate([dmask_u, np.zeros(n1, bool)])
     for it in range(maxit):
-        cv, Nm = mini_convection(mc, E, U)
+        if convection:
+            cv, Nm = mini_convection(mc, E, U)
+        else:
+            cv, Nm = np.zeros(2 * nb), sps.csr_matrix((2 * nb, 2 * nb))
         Fv = Alin @ U - (co.eta / co.dt) * (mp_.Mv @ U_n) + co.eta * cv \
             - co.eta * (mp_.Bq.T @ P) - gam - co.eta * F
         Fq = co.eta * (mp_.Bq @ U)
@@ -314,22 +323,51 @@ def mini_ns_step(mp_, mms, U_n, P_n, PF_n, t1, tol=1e-13, maxit=30):
     return U, P, it + 1
 
 
-def algorithm1_mini(N, prm, dt, nsteps):
+def algorithm1_mini(N, prm, dt, nsteps, problem="ex1"):
     """Algorithm 1 on one grid of N cells per unit length with MINI + P1;
-    returns the problem and the final fields."""
+    returns the problem and the final fields.  problem "ex1": Example 1's
+    manufactured solution; "ex3": the Example-3-type variant (Example3)."""
     co = Coefs(prm, dt)
-    mms = MMS(prm)
-    mp_ = MiniProblem(N, co)
+    ex3 = problem == "ex3"
+    mms = Example3() if ex3 else MMS(prm)
+    mp_ = MiniProblem(N, co, outflow_top=ex3)
     P = [interp_p1(mp_.mp, mms, nm, 0.0) for nm in ("pF", "pf", "pm")]
     U = np.concatenate([interp_mini(mp_.mc, mms, "u1", 0.0), interp_mini(mp_.mc, mms, "u2", 0.0)])
     Pc = interp_p1(mp_.mc, mms, "p", 0.0)
     for n in range(nsteps):
         t1 = (n + 1) * dt
         Pn = mini_porous_step(mp_, mms, P, U, t1)
-        U, Pc, _ = mini_ns_step(mp_, mms, U, Pc, P[0], t1)
+        U, Pc, _ = mini_ns_step(mp_, mms, U, Pc, P[0], t1, convection=not ex3)
         P = Pn
     return mp_, dict(pF=P[0], pf=P[1], pm=P[2], u=U, p=Pc)
 
+
+class Example3:
+    """Data of the Example-3-type variant (Section 6, Example 3) on the
+    two-square geometry: fixed pressures p_F = 1.0e3, p_f = 1.6e3,
+    p_m = 4.0e3 on the porous region's outer boundary (Gamma_in, also the
+    initial porous state), no sources, a Stokes conduit (no convection)
+    whose side walls are cased (no-slip, u = 0) and whose top y = 2 is the
+    outflow boundary (T(u, p) n = 0), starting from rest."""
+    VALUES = dict(pF=1.0e3, pf=1.6e3, pm=4.0e3)
+
+    def __call__(self, name, xy, tt):
+        return np.full(xy.shape[0], self.VALUES.get(name, 0.0))
+
+
+def example3_params(kF):
+    """Section 6, Example 3's parameters (sigma* not given: taken equal to
+    sigma) with macro-fracture permeability kF."""
+    return dict(phi=[1e-4, 1e-3, 1e-2], C=[1e-4] * 3, k=[kF, 1e-6, 1e-8], mu_tilde=1e-2, sigma=0.5,
+                sigma_star=0.5, rho=10.0, alpha=1.0, eta=1.0, nu=1e-2)
+
+
+def boundary_flux(mesh, U, j):
+    """int u_y dx over the conduit lattice row j (a horizontal line; bubbles
+    vanish there): the P1 trace integrated exactly (trapezoid)."""
+    nb, n1 = n_vel(mesh), mesh.n1
+    uy = U[nb + j * n1: nb + (j + 1) * n1]
+    return float(mesh.h * (uy[:-1] + uy[1:]).sum() / 2)
 
 def errors(mesh, vec, exact, space):
     """(L2 error, H1-seminorm error) of a P1 ("p1") or MINI ("mini") scalar

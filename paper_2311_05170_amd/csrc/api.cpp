@@ -1150,7 +1150,9 @@ lp_status lp_setup(const lp_mesh *mesh, const lp_partition *part, const lp_param
     if (opt->solver != LP_DENSE && (opt->max_iter < 1 || opt->max_iter > lp::GM_MAX || !(opt->krylov_tol > 0)))
         return fail(LP_ERR_ARG, "Krylov solves need 1 <= max_iter <= " + std::to_string(lp::GM_MAX) + " and krylov_tol > 0");
     if (opt->coarse_ns == LP_SEMI_IMPLICIT) return fail(LP_ERR_UNSUPPORTED, "the semi-implicit coarse step is not built");
-    if (opt->problem != LP_MMS_EX1_2D) return fail(LP_ERR_UNSUPPORTED, "only the Example 1 manufactured problem is built in");
+    if (opt->problem != LP_MMS_EX1_2D)
+        return fail(LP_ERR_UNSUPPORTED, "lp_setup runs the Example 1 manufactured problem only (the Example-3-type "
+                                        "variant runs through lp_mini_setup)");
     if (opt->precision != LP_FP64 && opt->precision != LP_MIXED) return fail(LP_ERR_ARG, "precision must be LP_FP64 or LP_MIXED");
     if (opt->max_ir < 1 || opt->max_newton < 1 || !(opt->ir_tol > 0) || !(opt->newton_tol > 0) || opt->jacobian_every < 0)
         return fail(LP_ERR_ARG, "max_ir, max_newton >= 1 and positive tolerances required");

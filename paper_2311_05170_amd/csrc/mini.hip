@@ -84,6 +84,7 @@ __global__ void __launch_bounds__(128) k_mini_ns_rows(MiniNsArgs a) {
     const double h = 1.0 / N, ih = (double)N, h2 = h * h;
     const Coef &co = a.co;
     const double eta = co.eta, mdt = co.eta / co.dt, visc = co.nu * co.eta;
+    const double ceta = co.convection ? co.eta : 0.0;          // Stokes: no b_N
     int el[6][4];
     int nel;
     if (kind == 3) {
@@ -139,13 +140,13 @@ __global__ void __launch_bounds__(128) k_mini_ns_rows(MiniNsArgs a) {
                 // (eta/dt)(u - u^n) + 2 nu eta D(u) : D(v) + eta (u.grad)u . v - eta p div v
                 F += wq * (mdt * (w[c] - wold[c]) * fa +
                            visc * (ga0 * (gw[c][0] + gw[0][c]) + ga1 * (gw[c][1] + gw[1][c])) +
-                           eta * (w[0] * gw[c][0] + w[1] * gw[c][1]) * fa - eta * pq * gac);
+                           ceta * (w[0] * gw[c][0] + w[1] * gw[c][1]) * fa - eta * pq * gac);
                 for (int b = 0; b < 4; ++b) {
                     const double wgb = w[0] * g[b][0] + w[1] * g[b][1];
-                    const double diag = mdt * fa * phi[b] + visc * (ga0 * g[b][0] + ga1 * g[b][1]) + eta * wgb * fa;
+                    const double diag = mdt * fa * phi[b] + visc * (ga0 * g[b][0] + ga1 * g[b][1]) + ceta * wgb * fa;
                     for (int d = 0; d < 2; ++d) {
                         const double ga_d = d == 0 ? ga0 : ga1;
-                        Jv[b][d] += wq * ((c == d ? diag : 0.0) + visc * ga_d * g[b][c] + eta * phi[b] * gw[c][d] * fa);
+                        Jv[b][d] += wq * ((c == d ? diag : 0.0) + visc * ga_d * g[b][c] + ceta * phi[b] * gw[c][d] * fa);
                     }
                 }
                 for (int b = 0; b < 3; ++b) Jp[b] -= wq * eta * phi[b] * gac;
@@ -307,6 +308,7 @@ using lp::Coef;
 
 struct lp_mini {
     int device = 0;
+    int problem = LP_MMS_EX1_2D;
     int N = 0, n1 = 0, nv = 0, ne = 0;
     int nns = 0, bw_ns = 0, bw_p = 0, var_ns = 0, var_p = 0;
     lp_params prm{};
@@ -397,10 +399,14 @@ lp_status mini_init(lp_mini *c) {
         return lp::set_error(LP_ERR_UNSUPPORTED, "the MINI Navier-Stokes half-bandwidth " + std::to_string(bw) +
                                                      " exceeds the band kernels' window of " +
                                                      std::to_string(lp::LU_MAX_BW));
+    // conduit velocity fixed on the physical boundary: every side but Gamma
+    // for Example 1; for the Example-3-type variant only the cased side walls
+    // (their end points included), the rest of the top being the outflow
+    const bool ex3 = c->problem == LP_EX3_2D;
     std::vector<int8_t> dirv(nv);
     for (int v = 0; v < nv; ++v) {
         const int i = v % n1, j = v / n1;
-        dirv[v] = i == 0 || i == N || j == N;
+        dirv[v] = i == 0 || i == N || (!ex3 && j == N);
     }
     // reference data, loads, exact spatial parts
     lp::MiniRef ref;
@@ -409,8 +415,19 @@ lp_status mini_init(lp_mini *c) {
     MCHK(hipMemcpyToSymbol(HIP_SYMBOL(lp::c_mphi), ref.phi, sizeof(ref.phi)));
     MCHK(hipMemcpyToSymbol(HIP_SYMBOL(lp::c_mdphi), ref.dphi, sizeof(ref.dphi)));
     std::vector<double> loads[5][3], ex[8];
-    lp::mini_source_loads(N, c->prm, loads);
-    lp::mini_exact_spatial(N, ex);
+    if (ex3) {
+        // no sources; fixed porous pressures on Gamma_in (and as the initial
+        // state), a conduit at rest
+        const double pin[3] = {1.0e3, 1.6e3, 4.0e3};
+        for (int f = 0; f < 5; ++f)
+            for (int k = 0; k < 3; ++k) loads[f][k].assign(f < 3 ? nv : nv + ne, 0.0);
+        for (int f = 0; f < 3; ++f) ex[f].assign(nv, pin[f]);
+        for (int f = 3; f < 6; ++f) ex[f].assign(nv, 0.0);
+        for (int f = 6; f < 8; ++f) ex[f].assign(ne, 0.0);
+    } else {
+        lp::mini_source_loads(N, c->prm, loads);
+        lp::mini_exact_spatial(N, ex);
+    }
     // device buffers
     const int nns = c->nns;
     const long long ldn = 2LL * c->bw_ns + 1, ldp = 2LL * c->bw_p + 1;
@@ -495,7 +512,10 @@ lp_status mini_init(lp_mini *c) {
 lp_status mini_step(lp_mini *c) {
     const int N = c->N, nv = c->nv, nns = c->nns;
     const double t1 = (double)(c->steps + 1) * c->prm.dt;
-    const double ct = std::cos(t1), st = std::sin(t1);
+    // Example 1's data are a(x) cos t (sources also sin t, cos^2 t); the
+    // Example-3-type variant's boundary data are constant in time
+    const bool ex3 = c->problem == LP_EX3_2D;
+    const double ct = ex3 ? 1.0 : std::cos(t1), st = ex3 ? 0.0 : std::sin(t1);
     // Step 1: porous pressures at t_{n+1}
     lp::MiniPorArgs pa{};
     pa.N = N;
@@ -587,9 +607,11 @@ lp_status mini_step(lp_mini *c) {
 
 extern "C" {
 
-lp_status lp_mini_setup(int32_t n, const lp_params *prm, int32_t device, lp_mini **out) {
+lp_status lp_mini_setup(int32_t n, int32_t problem, const lp_params *prm, int32_t device, lp_mini **out) {
     if (!out || !prm) return lp::set_error(LP_ERR_ARG, "NULL argument");
     *out = nullptr;
+    if (problem != LP_MMS_EX1_2D && problem != LP_EX3_2D)
+        return lp::set_error(LP_ERR_ARG, "problem must be LP_MMS_EX1_2D or LP_EX3_2D");
     // with n = 1 every conduit vertex carries Dirichlet velocity: only the
     // bubbles test the pressure, which then keeps an undetermined constant
     if (n < 2) return lp::set_error(LP_ERR_ARG, "n must be >= 2");
@@ -600,6 +622,7 @@ lp_status lp_mini_setup(int32_t n, const lp_params *prm, int32_t device, lp_mini
     MCHK(hipSetDevice(device));
     lp_mini *c = new lp_mini();
     c->device = device;
+    c->problem = problem;
     c->N = n;
     c->n1 = n + 1;
     c->nv = c->n1 * c->n1;
@@ -618,7 +641,7 @@ lp_status lp_mini_setup(int32_t n, const lp_params *prm, int32_t device, lp_mini
     c->co.dt = prm->dt;
     c->co.beta = prm->alpha * prm->nu / std::sqrt(prm->k[0]);
     c->co.ctau = prm->eta * prm->nu * prm->alpha * std::sqrt(prm->k[0]) / mu;
-    c->co.convection = 1;
+    c->co.convection = problem == LP_EX3_2D ? 0 : 1;           // Example 3's conduit is Stokes
     if (hipStreamCreate(&c->st) != hipSuccess || hipEventCreate(&c->ev[0]) != hipSuccess ||
         hipEventCreate(&c->ev[1]) != hipSuccess) {
         delete c;

@@ -123,7 +123,7 @@ def load(path=LIB_PATH):
     lib.lp_destroy.argtypes = [c_void_p]
     lib.lp_destroy.restype = None
     lib.lp_last_error.restype = c_char_p
-    lib.lp_mini_setup.argtypes = [c_int32, POINTER(LpParams), c_int32, POINTER(c_void_p)]
+    lib.lp_mini_setup.argtypes = [c_int32, c_int32, POINTER(LpParams), c_int32, POINTER(c_void_p)]
     lib.lp_mini_step.argtypes = [c_void_p, c_int32]
     lib.lp_mini_get.argtypes = [c_void_p, c_int32, POINTER(c_double), c_int64, POINTER(c_int64)]
     lib.lp_mini_stats.argtypes = [c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32), POINTER(c_double),
@@ -350,10 +350,10 @@ class MiniAlgorithm1:
     per unit length, on the device (lp_mini_*).  Fields come back in the
     layouts lp.h states (vertex values, then one bubble per element for u)."""
 
-    def __init__(self, n, prm, dt, device=0):
+    def __init__(self, n, prm, dt, device=0, problem="ex1"):
         self._h = c_void_p()
         p = _params(prm, dt)
-        _check(_LIB.lp_mini_setup(int(n), byref(p), int(device), byref(self._h)))
+        _check(_LIB.lp_mini_setup(int(n), {"ex1": 0, "ex3": 1}[problem], byref(p), int(device), byref(self._h)))
         self.n = int(n)
 
     def step(self, nsteps=1):

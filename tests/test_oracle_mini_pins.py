@@ -12,7 +12,8 @@ from oracle.fe import triangle_rule
 from oracle.mesh import RegionMesh, CONDUIT, POROUS
 from oracle.mesh import uniform_cuts
 from oracle.mini import (mini_basis, mini_stokes, mini_convection, p1_mass_stiff, gamma_p1, n_vel,
-                         el_vel, interp_mini, algorithm1_mini, errors, MiniOracle2D, prolong_mini)
+                         el_vel, interp_mini, algorithm1_mini, errors, MiniOracle2D, prolong_mini,
+                         example3_params, boundary_flux)
 from oracle.mms import exact_ex1, MMS, x, y, t
 
 UNIT = dict(phi=[1.0] * 3, C=[1.0] * 3, k=[1.0] * 3, mu_tilde=1.0, sigma=1.0, sigma_star=1.0,
@@ -235,3 +236,29 @@ def test_mini_algorithm3_merged_reading_reproduces_table1_porous_columns():
     ref = np.array(rows[1], dtype=float)[[1, 3, 5]]     # Table 1, row h = 1/16: the porous H1 errors
     rel = np.abs(np.array(got) - ref) / ref
     assert rel.max() < 0.005, (got, rel)
+
+
+# the macro-fracture permeabilities of Example 3's sweep (Section 6, Example 3)
+KF_SWEEP = [2e-2, 4e-2, 6e-2, 8e-2, 2e-1, 4e-1, 6e-1, 8e-1]
+
+
+def test_example3_variant_conserves_mass_through_the_conduit():
+    """Example-3-type variant: the conduit's only inflow is Gamma and its only
+    outflow the top, so the discrete divergence constraint tested with the
+    constant pressure makes the two fluxes equal at every step (to the
+    Newton tolerance), and fluid does flow (the porous pressures drive it)."""
+    for kF in (1e-3, 0.2):
+        mp, f = algorithm1_mini(6, example3_params(kF), 0.05, 40, problem="ex3")
+        qin, qout = boundary_flux(mp.mc, f["u"], 0), boundary_flux(mp.mc, f["u"], 6)
+        assert qout > 1.0 and abs(qin - qout) <= 1e-9 * qout, (kF, qin, qout)
+
+
+def test_example3_variant_rate_rises_with_the_macro_fracture_permeability():
+    """Section 6, Example 3: over the paper's k_F sweep the oil production
+    rate (here the outflow through the conduit top at T = 10, dt = 0.05)
+    rises with k_F."""
+    q = []
+    for kF in KF_SWEEP:
+        mp, f = algorithm1_mini(6, example3_params(kF), 0.05, 200, problem="ex3")
+        q.append(boundary_flux(mp.mc, f["u"], 6))
+    assert all(b > a for a, b in zip(q, q[1:])), q
