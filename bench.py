@@ -632,23 +632,29 @@ def example3_run():
     from paper_2311_05170_amd.lib import MiniAlgorithm1
     N = EX3_N
     nb = (N + 1) ** 2 + 2 * N * N
-    rates, ms = [], []
-    for kF in EX3_KF:
-        p = dict(phi=[1e-4, 1e-3, 1e-2], C=[1e-4] * 3, k=[kF, 1e-6, 1e-8], mu_tilde=1e-2, sigma=0.5,
-                 sigma_star=0.5, rho=10.0, alpha=1.0, eta=1.0, nu=1e-2)
-        g = MiniAlgorithm1(N, p, EX3_DT, problem="ex3")
+    samples = [dict(phi=[1e-4, 1e-3, 1e-2], C=[1e-4] * 3, k=[kF, 1e-6, 1e-8], mu_tilde=1e-2, sigma=0.5,
+                    sigma_star=0.5, rho=10.0, alpha=1.0, eta=1.0, nu=1e-2) for kF in EX3_KF]
+
+    def run(plist):
+        g = MiniAlgorithm1(N, plist[0], EX3_DT, problem="ex3", samples=plist)
         try:
             t0 = time.perf_counter()
             g.step(EX3_STEPS)
-            ms.append((time.perf_counter() - t0) * 1e3 / EX3_STEPS)
-            uy = g.solution("u")[nb + N * (N + 1):nb + (N + 1) ** 2]
+            ms = (time.perf_counter() - t0) * 1e3 / EX3_STEPS
+            uys = [g.solution("u", sample=k)[nb + N * (N + 1):nb + (N + 1) ** 2] for k in range(len(plist))]
         finally:
             g.close()
-        rates.append(float((uy[:-1] + uy[1:]).sum() / (2 * N)))
+        return ms, [float((uy[:-1] + uy[1:]).sum() / (2 * N)) for uy in uys]
+
+    # the sweep as one ensemble (every launch covers the eight samples), and
+    # one context per k_F, one after another
+    ms_batch, rates = run(samples)
+    ms_seq = sum(run([q])[0] for q in samples)
     return {"workload": "Example-3-type variant with the paper's elements: Gamma_in pressures 1.0e3/1.6e3/4.0e3, "
                         "Stokes conduit with cased walls and an outflow top, Example 3 parameters, h=1/%d, "
                         "dt=%g, T=%g" % (N, EX3_DT, EX3_STEPS * EX3_DT),
-            "k_F": EX3_KF, "outflow_rate": rates, "ms_per_step": sum(ms) / len(ms)}
+            "k_F": EX3_KF, "outflow_rate": rates, "ms_per_step_ensemble": ms_batch,
+            "ms_per_step_sequential": ms_seq, "speedup": ms_seq / ms_batch}
 
 
 def paper_elements_cpu():

@@ -64,7 +64,8 @@ enum { LP_U = 0, LP_P = 1, LP_PF = 2, LP_PFMI = 3, LP_PM = 4 };
 enum { LP_MERGED_FINE = 0, LP_COARSE = 1, LP_LOCAL = 2 };
 /* arithmetic of the local solves */
 enum { LP_FP64 = 0, LP_MIXED = 1 };
-/* manufactured problems */
+/* problems: Example 1's manufactured solution (Section 6); the Example-3-type
+ * variant of lp_mini_setup */
 enum { LP_MMS_EX1_2D = 0, LP_EX3_2D = 1 };
 
 /* Nested meshes (Section 4: T_h is a uniform refinement of T_H).
@@ -441,7 +442,12 @@ void lp_destroy(lp_ctx *ctx);
  * Fluid enters the conduit only through Gamma.  Boundary data are constant
  * in time.
  * lp_mini_setup: `problem` is LP_MMS_EX1_2D or LP_EX3_2D; `device` is a HIP
- *   device id; `prm` holds the parameters and dt.  Errors: LP_ERR_ARG (NULL, dt <= 0, n < 2: with n = 1 every conduit
+ *   device id; samples[nsamples] (host, read during the call) hold the
+ *   parameters and dt of independent runs advanced together (a parameter
+ *   sweep: every launch covers all samples' systems, and each sample's fields
+ *   are bit for bit those of a one-sample context with its parameters); the
+ *   samples share dt.  Errors: LP_ERR_ARG (NULL, nsamples < 1, dt <= 0 or
+ *   differing, k_F, mu_tilde or rho <= 0, n < 2: with n = 1 every conduit
  *   vertex has Dirichlet velocity and the pressure keeps a free constant),
  *   LP_ERR_DEVICE,
  *   LP_ERR_UNSUPPORTED (the Navier-Stokes half-bandwidth, 7 n + 16 for n >= 2,
@@ -450,16 +456,18 @@ void lp_destroy(lp_ctx *ctx);
  *   Newton solve reached its cap (flags bit 1) or a factorisation met a
  *   pivot below the rounding of its matrix (bit 2); the flags are sticky and
  *   the state advances all the same.
- * lp_mini_get: copies `field` into out[len]; *needed (if not NULL) receives
- *   its length; out = NULL only queries it.  LP_ERR_ARG for an unknown field
- *   or a short buffer.
- * lp_mini_stats: steps taken, the most iterations of any step, flags, and the
+ * lp_mini_get: copies `field` of `sample` into out[len]; *needed (if not
+ *   NULL) receives its length; out = NULL only queries it.  LP_ERR_ARG for a
+ *   sample out of range, an unknown field or a short buffer.
+ * lp_mini_stats: steps taken, the most iterations of any step (any sample),
+ *   flags, and the
  *   summed HIP-event time (ms) and count of the Navier-Stokes factorisations
  *   (any output may be NULL). */
 typedef struct lp_mini lp_mini;
-lp_status lp_mini_setup(int32_t n, int32_t problem, const lp_params *prm, int32_t device, lp_mini **out);
+lp_status lp_mini_setup(int32_t n, int32_t problem, const lp_params *samples, int32_t nsamples, int32_t device,
+                        lp_mini **out);
 lp_status lp_mini_step(lp_mini *ctx, int32_t nsteps);
-lp_status lp_mini_get(lp_mini *ctx, int32_t field, double *out, int64_t len, int64_t *needed);
+lp_status lp_mini_get(lp_mini *ctx, int32_t sample, int32_t field, double *out, int64_t len, int64_t *needed);
 lp_status lp_mini_stats(lp_mini *ctx, int32_t *steps, int32_t *newton_its_max, int32_t *flags, double *lu_ms,
                         int64_t *lu_launches);
 void lp_mini_destroy(lp_mini *ctx);

@@ -123,9 +123,9 @@ def load(path=LIB_PATH):
     lib.lp_destroy.argtypes = [c_void_p]
     lib.lp_destroy.restype = None
     lib.lp_last_error.restype = c_char_p
-    lib.lp_mini_setup.argtypes = [c_int32, c_int32, POINTER(LpParams), c_int32, POINTER(c_void_p)]
+    lib.lp_mini_setup.argtypes = [c_int32, c_int32, POINTER(LpParams), c_int32, c_int32, POINTER(c_void_p)]
     lib.lp_mini_step.argtypes = [c_void_p, c_int32]
-    lib.lp_mini_get.argtypes = [c_void_p, c_int32, POINTER(c_double), c_int64, POINTER(c_int64)]
+    lib.lp_mini_get.argtypes = [c_void_p, c_int32, c_int32, POINTER(c_double), c_int64, POINTER(c_int64)]
     lib.lp_mini_stats.argtypes = [c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32), POINTER(c_double),
                                   POINTER(c_int64)]
     lib.lp_mini_destroy.argtypes = [c_void_p]
@@ -350,20 +350,24 @@ class MiniAlgorithm1:
     per unit length, on the device (lp_mini_*).  Fields come back in the
     layouts lp.h states (vertex values, then one bubble per element for u)."""
 
-    def __init__(self, n, prm, dt, device=0, problem="ex1"):
+    def __init__(self, n, prm, dt, device=0, problem="ex1", samples=None):
         self._h = c_void_p()
-        p = _params(prm, dt)
-        _check(_LIB.lp_mini_setup(int(n), {"ex1": 0, "ex3": 1}[problem], byref(p), int(device), byref(self._h)))
+        plist = samples if samples else [prm]
+        params = (LpParams * len(plist))(*[_params(q, dt) for q in plist])
+        _check(_LIB.lp_mini_setup(int(n), {"ex1": 0, "ex3": 1}[problem], params, len(plist), int(device),
+                                  byref(self._h)))
+        self.nsamples = len(plist)
         self.n = int(n)
 
     def step(self, nsteps=1):
         _check(_LIB.lp_mini_step(self._h, int(nsteps)))
 
-    def solution(self, field):
+    def solution(self, field, sample=0):
         need = c_int64(0)
-        _check(_LIB.lp_mini_get(self._h, FIELD[field], None, 0, byref(need)))
+        _check(_LIB.lp_mini_get(self._h, int(sample), FIELD[field], None, 0, byref(need)))
         out = np.zeros(need.value, dtype=np.float64)
-        _check(_LIB.lp_mini_get(self._h, FIELD[field], out.ctypes.data_as(POINTER(c_double)), need.value, None))
+        _check(_LIB.lp_mini_get(self._h, int(sample), FIELD[field], out.ctypes.data_as(POINTER(c_double)),
+                                need.value, None))
         return out
 
     def stats(self):

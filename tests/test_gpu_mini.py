@@ -134,20 +134,32 @@ def test_example3_variant_matches_oracle(N, kF, steps):
 
 
 def test_example3_variant_sweep_on_the_device():
-    """The paper's k_F sweep (Section 6, Example 3) on the device at h = 1/9,
-    dt = 0.05, T = 10: the outflow rises with k_F, and at every k_F it equals
-    the inflow through Gamma (the discrete divergence constraint)."""
+    """The paper's k_F sweep (Section 6, Example 3) as one ensemble on the
+    device (eight samples in one context) at h = 1/9, dt = 0.05, T = 10: the
+    outflow rises with k_F, and at every k_F it equals the inflow through
+    Gamma (the discrete divergence constraint); two samples equal one-sample
+    contexts bit for bit."""
     from paper_2311_05170_amd.lib import MiniAlgorithm1
     from oracle.mini import example3_params
     N = 9
-    q = []
-    for kF in (2e-2, 4e-2, 6e-2, 8e-2, 2e-1, 4e-1, 6e-1, 8e-1):
-        g = MiniAlgorithm1(N, example3_params(kF), 0.05, problem="ex3")
+    kfs = (2e-2, 4e-2, 6e-2, 8e-2, 2e-1, 4e-1, 6e-1, 8e-1)
+    samples = [example3_params(kF) for kF in kfs]
+    g = MiniAlgorithm1(N, samples[0], 0.05, problem="ex3", samples=samples)
+    try:
+        g.step(200)
+        us = [g.solution("u", sample=k) for k in range(len(kfs))]
+        assert g.stats()["flags"] == 0
+    finally:
+        g.close()
+    for k in (0, 5):
+        solo = MiniAlgorithm1(N, samples[k], 0.05, problem="ex3")
         try:
-            g.step(200)
-            u = g.solution("u")
+            solo.step(200)
+            assert np.array_equal(solo.solution("u"), us[k]), k
         finally:
-            g.close()
+            solo.close()
+    q = []
+    for kF, u in zip(kfs, us):
         nb = (N + 1) ** 2 + 2 * N * N
         uy = u[nb:nb + (N + 1) ** 2].reshape(N + 1, N + 1)
         qin = (uy[0, :-1] + uy[0, 1:]).sum() / (2 * N)
@@ -156,3 +168,27 @@ def test_example3_variant_sweep_on_the_device():
         assert abs(qin - qout) <= 1e-9 * abs(qout)
         q.append(qout)
     assert all(b > a for a, b in zip(q, q[1:])), q
+
+
+
+def test_mini_samples_match_one_sample_contexts():
+    """Three parameter samples of Example 1 in one context take, bit for bit,
+    the path of three one-sample contexts (every field), though they converge
+    in different iteration counts."""
+    from paper_2311_05170_amd.lib import MiniAlgorithm1
+    samples = [UNIT, _skewed(), dict(UNIT, nu=0.2, k=[0.5, 0.1, 0.05])]
+    g = MiniAlgorithm1(6, UNIT, 0.02, samples=samples)
+    solo = [MiniAlgorithm1(6, q, 0.02) for q in samples]
+    try:
+        g.step(5)
+        for s_ in solo:
+            s_.step(5)
+        for k, s_ in enumerate(solo):
+            for f in FIELDS:
+                assert np.array_equal(g.solution(f, sample=k), s_.solution(f)), (k, f)
+        with pytest.raises(Exception, match="sample out of range"):
+            g.solution("u", sample=3)
+    finally:
+        g.close()
+        for s_ in solo:
+            s_.close()
