@@ -76,40 +76,47 @@ __global__ void __launch_bounds__(128) k_mini_ns_rows(MiniNsArgs a) {
     const int smp = blockIdx.y;
     if (r >= 3 * nv + 2 * ne || a.done[smp]) return;
     const long long ld = 2 * a.bw + 1;
-    // this sample's vectors and band
-    a.x += smp * a.nx;
-    a.xo += smp * a.nx;
-    a.rhs += smp * a.nx;
-    a.band += smp * a.nx * ld;
-    a.pF0 += smp * a.np;
-    for (int cc = 0; cc < 2; ++cc)
-        for (int k = 0; k < 3; ++k) a.load[cc][k] += smp * a.nl;
+    // this sample's vectors and band (local pointers: the argument block is
+    // left as it is, so that no part of it needs a private copy)
+    const double *X = a.x + smp * a.nx, *XO = a.xo + smp * a.nx, *PF0 = a.pF0 + smp * a.np;
+    double *RHS = a.rhs + smp * a.nx, *BAND = a.band + smp * a.nx * ld;
+    const long long loff = smp * a.nl;
     int kind, c, v = -1, e = -1;
     if (r < 3 * nv) { v = r / 3; kind = r % 3; c = kind; }
     else { e = (r - 3 * nv) / 2; c = (r - 3 * nv) % 2; kind = 3; }
     const int R = kind == 2 ? a.vp[v] : kind < 2 ? a.vu[v] + c : a.eb[e] + c;
     if (kind < 2 && a.dirv[v]) {
-        if (a.jac) a.band[(long long)R * ld + a.bw] = 1.0;
-        a.rhs[R] = 0.0;
+        if (a.jac) BAND[(long long)R * ld + a.bw] = 1.0;
+        RHS[R] = 0.0;
         return;
     }
     const double h = 1.0 / N, ih = (double)N, h2 = h * h;
     const Coef &co = a.co[smp];
     const double eta = co.eta, mdt = co.eta / co.dt, visc = co.nu * co.eta;
     const double ceta = co.convection ? co.eta : 0.0;          // Stokes: no b_N
-    int el[6][4];
-    int nel;
-    if (kind == 3) {
-        const int cell = e >> 1;
-        el[0][0] = cell % N; el[0][1] = cell / N; el[0][2] = e & 1; el[0][3] = 3;
-        nel = 1;
-    } else {
-        nel = vertex_elements(v % n1, v / n1, N, el);
-    }
-    auto put = [&](int col, double val) { a.band[(long long)col * ld + a.bw + R - col] += val; };
+    // the elements touching the row's basis function, in a fixed order:
+    // for a vertex (i, j) the triangles (cell, orientation, local index)
+    // (i,j,0,0) (i,j,1,0) (i-1,j,0,1) (i-1,j-1,0,2) (i-1,j-1,1,1) (i,j-1,1,2),
+    // for a bubble its own element (indices computed, no local tables)
+    const int vi = kind == 3 ? 0 : v % n1, vj = kind == 3 ? 0 : v / n1;
+    auto put = [&](int col, double val) { BAND[(long long)col * ld + a.bw + R - col] += val; };
     double F = 0.0;
-    for (int k = 0; k < nel; ++k) {
-        const int ci = el[k][0], cj = el[k][1], t = el[k][2], ta = el[k][3];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        int ci, cj, t;
+        const int tv = k <= 1 ? 0 : (k == 2 || k == 4) ? 1 : 2;      // a vertex's local index there
+        if (kind == 3) {
+            if (k > 0) break;
+            const int cell = e >> 1;
+            ci = cell % N;
+            cj = cell / N;
+            t = e & 1;
+        } else {
+            ci = vi - ((k == 2 || k == 3 || k == 4) ? 1 : 0);
+            cj = vj - (k >= 3 ? 1 : 0);
+            t = (k == 1 || k == 4 || k == 5) ? 1 : 0;
+            if (ci < 0 || ci >= N || cj < 0 || cj >= N) continue;
+        }
         int iu[4], ip[3];
         for (int b = 0; b < 3; ++b) {
             const int vb = (ci + off1a(t, b)) + n1 * (cj + off1b(t, b));
@@ -119,16 +126,18 @@ __global__ void __launch_bounds__(128) k_mini_ns_rows(MiniNsArgs a) {
         iu[3] = a.eb[2 * (ci + N * cj) + t];
         double wv[2][4], wo[2][4], pv[3];
         for (int b = 0; b < 4; ++b)
-            for (int d = 0; d < 2; ++d) { wv[d][b] = a.x[iu[b] + d]; wo[d][b] = a.xo[iu[b] + d]; }
-        for (int b = 0; b < 3; ++b) pv[b] = a.x[ip[b]];
+            for (int d = 0; d < 2; ++d) { wv[d][b] = X[iu[b] + d]; wo[d][b] = XO[iu[b] + d]; }
+        for (int b = 0; b < 3; ++b) pv[b] = X[ip[b]];
         double Jv[4][2] = {}, Jp[3] = {};
         for (int q = 0; q < MINI_NQ; ++q) {
             const double wq = c_mw[q] * h2;
             double phi[4], g[4][2];
             for (int b = 0; b < 4; ++b) {
                 phi[b] = c_mphi[q][b];
-                g[b][0] = c_mdphi[t][q][b][0] * ih;
-                g[b][1] = c_mdphi[t][q][b][1] * ih;
+                // both orientations' tables at the wave-uniform point q (scalar
+                // loads), then this lane's orientation
+                g[b][0] = (t ? c_mdphi[1][q][b][0] : c_mdphi[0][q][b][0]) * ih;
+                g[b][1] = (t ? c_mdphi[1][q][b][1] : c_mdphi[0][q][b][1]) * ih;
             }
             double w[2], wold[2], gw[2][2];
             for (int d = 0; d < 2; ++d) {
@@ -141,24 +150,32 @@ __global__ void __launch_bounds__(128) k_mini_ns_rows(MiniNsArgs a) {
                 }
             }
             const double pq = pv[0] * phi[0] + pv[1] * phi[1] + pv[2] * phi[2];
+            // the row's test function and component by selects (no indexing
+            // of these small arrays by run-time values)
+            const double fa = kind == 3 ? phi[3] : phi[tv];
+            const double ga0 = kind == 3 ? g[3][0] : g[tv][0], ga1 = kind == 3 ? g[3][1] : g[tv][1];
             if (kind == 2) {
                 // eta int psi_a div u; Jacobian eta int psi_a d_d phi_b
-                const double fa = wq * eta * phi[ta];
-                F += fa * (gw[0][0] + gw[1][1]);
+                const double fe = wq * eta * fa;
+                F += fe * (gw[0][0] + gw[1][1]);
                 for (int b = 0; b < 4; ++b)
-                    for (int d = 0; d < 2; ++d) Jv[b][d] += fa * g[b][d];
+                    for (int d = 0; d < 2; ++d) Jv[b][d] += fe * g[b][d];
             } else {
-                const double fa = phi[ta], ga0 = g[ta][0], ga1 = g[ta][1], gac = g[ta][c];
+                const double gac = c ? ga1 : ga0;
+                const double wc = c ? w[1] : w[0], woc = c ? wold[1] : wold[0];
+                const double gwc0 = c ? gw[1][0] : gw[0][0], gwc1 = c ? gw[1][1] : gw[0][1];   // d_0 u_c, d_1 u_c
+                const double gw0c = c ? gw[0][1] : gw[0][0], gw1c = c ? gw[1][1] : gw[1][0];   // d_c u_0, d_c u_1
                 // (eta/dt)(u - u^n) + 2 nu eta D(u) : D(v) + eta (u.grad)u . v - eta p div v
-                F += wq * (mdt * (w[c] - wold[c]) * fa +
-                           visc * (ga0 * (gw[c][0] + gw[0][c]) + ga1 * (gw[c][1] + gw[1][c])) +
-                           ceta * (w[0] * gw[c][0] + w[1] * gw[c][1]) * fa - eta * pq * gac);
+                F += wq * (mdt * (wc - woc) * fa + visc * (ga0 * (gwc0 + gw0c) + ga1 * (gwc1 + gw1c)) +
+                           ceta * (w[0] * gwc0 + w[1] * gwc1) * fa - eta * pq * gac);
                 for (int b = 0; b < 4; ++b) {
                     const double wgb = w[0] * g[b][0] + w[1] * g[b][1];
                     const double diag = mdt * fa * phi[b] + visc * (ga0 * g[b][0] + ga1 * g[b][1]) + ceta * wgb * fa;
+                    const double gbc = c ? g[b][1] : g[b][0];
                     for (int d = 0; d < 2; ++d) {
                         const double ga_d = d == 0 ? ga0 : ga1;
-                        Jv[b][d] += wq * ((c == d ? diag : 0.0) + visc * ga_d * g[b][c] + ceta * phi[b] * gw[c][d] * fa);
+                        const double gwcd = d == 0 ? gwc0 : gwc1;
+                        Jv[b][d] += wq * ((c == d ? diag : 0.0) + visc * ga_d * gbc + ceta * phi[b] * gwcd * fa);
                     }
                 }
                 for (int b = 0; b < 3; ++b) Jp[b] -= wq * eta * phi[b] * gac;
@@ -174,7 +191,9 @@ __global__ void __launch_bounds__(128) k_mini_ns_rows(MiniNsArgs a) {
     if (kind != 2) {
         // sources (time-separable loads)
         const int pub = kind == 3 ? nv + e : v;
-        F -= eta * (a.load[c][0][pub] * a.ct + a.load[c][1][pub] * a.st + a.load[c][2][pub] * a.c2t);
+        const double *L0 = c ? a.load[1][0] : a.load[0][0], *L1 = c ? a.load[1][1] : a.load[0][1];
+        const double *L2 = c ? a.load[1][2] : a.load[0][2];
+        F -= eta * (L0[loff + pub] * a.ct + L1[loff + pub] * a.st + L2[loff + pub] * a.c2t);
         // Gamma (conduit row j = 0, n_c = (0, -1)): Beavers-Joseph eta beta int u_x v_x,
         // + c_tau int d_x p_F v_x and -(eta/rho) int p_F v_y with the lagged p_F^n
         if (kind < 2 && v / n1 == 0) {
@@ -187,11 +206,11 @@ __global__ void __launch_bounds__(128) k_mini_ns_rows(MiniNsArgs a) {
                     const int ib = i0 + lb;
                     const double G = h * (la == lb ? 1.0 / 3.0 : 1.0 / 6.0);
                     const double Gx = lb == 0 ? -0.5 : 0.5;
-                    const double pF = a.pF0[ib + n1 * N];
+                    const double pF = PF0[ib + n1 * N];
                     if (c == 0) {
                         const int col = a.vu[ib];
                         if (a.jac) put(col, eta * co.beta * G);
-                        F += eta * co.beta * G * a.x[col] + co.ctau * Gx * pF;
+                        F += eta * co.beta * G * X[col] + co.ctau * Gx * pF;
                     } else {
                         F -= eta / co.rho * G * pF;
                     }
@@ -199,7 +218,7 @@ __global__ void __launch_bounds__(128) k_mini_ns_rows(MiniNsArgs a) {
             }
         }
     }
-    a.rhs[R] = -F;
+    RHS[R] = -F;
 }
 
 // Velocity at t_{n+1} on the physical boundary (Newton start: the state of
@@ -270,9 +289,8 @@ __global__ void __launch_bounds__(128) k_mini_porous(MiniPorArgs a) {
         a.P += smp * a.np;
         a.rhs += smp * a.np;
         a.xo += smp * a.nx;
-        for (int f = 0; f < 3; ++f)
-            for (int k = 0; k < 2; ++k) a.load[f][k] += smp * nv;
     }
+    const long long loff = (long long)smp * nv;
     const int i = v % n1, j = v / n1;
     const bool dir = i == 0 || i == N || j == 0;
     const Coef &co = a.co[smp];
@@ -321,7 +339,7 @@ __global__ void __launch_bounds__(128) k_mini_porous(MiniPorArgs a) {
         }
     }
     double Q[3];
-    for (int f = 0; f < 3; ++f) Q[f] = a.load[f][0][v] * a.ct + a.load[f][1][v] * a.st;
+    for (int f = 0; f < 3; ++f) Q[f] = a.load[f][0][loff + v] * a.ct + a.load[f][1][loff + v] * a.st;
     a.rhs[v] = Q[0] + co.tau[0] * m[0] + co.sst * m[1] + gam;
     a.rhs[nv + v] = Q[1] + co.tau[1] * m[1] + co.s * m[2] + co.sst * m[0];
     a.rhs[2 * nv + v] = Q[2] + co.tau[2] * m[2] + co.s * m[1];
