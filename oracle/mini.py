@@ -410,10 +410,15 @@ def prolong_mini(coarse, fine, vec):
     return np.concatenate([vert, eval_mini(coarse, vec, cen) - vert[fine.el_p1[E]].mean(axis=1)])
 
 
-def _classify_p1(sd, mesh):
-    """Per local vertex of Omega_j: 0 free, 1 physical Dirichlet, 2 artificial."""
+def _classify_p1(sd, mesh, outflow_top=False):
+    """Per local vertex of Omega_j: 0 free, 1 physical Dirichlet, 2 artificial.
+    With outflow_top the conduit's top is natural (Example 3's outflow) and
+    only its side walls carry Dirichlet velocity."""
     pn, I, J = sd.p1_nodes(mesh)
-    phys = (I == 0) | (I == mesh.N) | ((J == 0) if mesh.region == POROUS else (J == mesh.N))
+    if mesh.region == CONDUIT and outflow_top:
+        phys = (I == 0) | (I == mesh.N)
+    else:
+        phys = (I == 0) | (I == mesh.N) | ((J == 0) if mesh.region == POROUS else (J == mesh.N))
     cls = np.where(sd.artificial_p1(I, J), 2, 0)
     cls[phys] = 1
     return pn, I, J, cls
@@ -423,13 +428,14 @@ class MiniOracle2D:
     """Algorithm 3 (Section 5) with MINI + P1: init(), then per step
     coarse_step() and local_step(); merged() reads the corrected fields."""
 
-    def __init__(self, NH, Nh, cuts, overlap, prm, dt, previous="own"):
+    def __init__(self, NH, Nh, cuts, overlap, prm, dt, previous="own", problem="ex1"):
         assert Nh % NH == 0 and previous in ("own", "merged")
         self.previous = previous
+        self.ex3 = problem == "ex3"
         self.co = Coefs(prm, dt)
-        self.mms = MMS(prm)
-        self.cg = MiniProblem(NH, self.co)
-        self.fg = MiniProblem(Nh, self.co)
+        self.mms = Example3() if self.ex3 else MMS(prm)
+        self.cg = MiniProblem(NH, self.co, outflow_top=self.ex3)
+        self.fg = MiniProblem(Nh, self.co, outflow_top=self.ex3)
         self.subs = make_subdomains(Nh, cuts, overlap)
         self.cuts = cuts
         self.n = 0
@@ -463,7 +469,7 @@ class MiniOracle2D:
         self.e = {}
         for sd in self.subs:
             mesh = self._mesh(sd.region)
-            pn, _, _, cls = _classify_p1(sd, mesh)
+            pn, _, _, cls = _classify_p1(sd, mesh, self.ex3)
             if sd.region == POROUS:
                 self.e[sd.sid] = [np.where(cls == 2, 0.0, fineP[i][pn] - ProlP[i][pn]) for i in range(3)]
             else:
@@ -479,7 +485,7 @@ class MiniOracle2D:
         t1 = self.t(self.n + 1)
         self.P_old, self.U_old = [p.copy() for p in self.P], self.U.copy()
         P_new = mini_porous_step(self.cg, self.mms, self.P, self.U, t1)
-        U_new, P_c, _ = mini_ns_step(self.cg, self.mms, self.U, self.Pc, self.P[0], t1)
+        U_new, P_c, _ = mini_ns_step(self.cg, self.mms, self.U, self.Pc, self.P[0], t1, convection=not self.ex3)
         self.P, self.U, self.Pc = P_new, U_new, P_c
 
     # local velocity unknowns of a conduit subdomain: both components of the
@@ -494,7 +500,7 @@ class MiniOracle2D:
 
     def _vel_fixed(self, sd):
         mesh = self.fg.mc
-        _, _, _, cls = _classify_p1(sd, mesh)
+        _, _, _, cls = _classify_p1(sd, mesh, self.ex3)
         nE = len(mesh.elements_in_box(sd.x0, sd.x1, sd.y0, sd.y1))
         one = np.concatenate([cls, np.zeros(nE, dtype=cls.dtype)])
         return np.concatenate([one, one])
@@ -510,7 +516,7 @@ class MiniOracle2D:
             G = gamma_p1(mesh, sd.x0, sd.x1)[0] if sd.touches_gamma else None
             self._cache[key] = (E, M, K, G)
         E, M, K, G = self._cache[key]
-        pn, _, _, cls = _classify_p1(sd, mesh)
+        pn, _, _, cls = _classify_p1(sd, mesh, self.ex3)
         nn = mesh.n1 ** 2
         PF1, Pf1, Pm1 = pro["P1"]
         PF0, Pf0, Pm0 = pro["P0"]
@@ -554,7 +560,10 @@ class MiniOracle2D:
         Mv, S, Bq = self._cache[key]
         nb, n1 = n_vel(mesh), mesh.n1 ** 2
         W1, W0, Pp = pro["U1"], pro["U0"], pro["Pc1"]
-        cv, Nm = mini_convection(mesh, E, W1)
+        if self.ex3:
+            cv, Nm = np.zeros(2 * nb), sps.csr_matrix((2 * nb, 2 * nb))
+        else:
+            cv, Nm = mini_convection(mesh, E, W1)
         Gblk = sps.csr_matrix((2 * nb, 2 * nb))
         gam = np.zeros(2 * nb)
         if sd.touches_gamma:
@@ -569,7 +578,7 @@ class MiniOracle2D:
         A = (co.eta / co.dt) * Mv + Avis + co.eta * Nm
         vi = self._vel_index(sd)
         fixed = self._vel_fixed(sd)
-        pn, I, J, cls = _classify_p1(sd, mesh)
+        pn, I, J, cls = _classify_p1(sd, mesh, self.ex3)
         pfix = sd.artificial_p1(I, J)          # R1p: every artificial vertex, physical ones too
         en = np.zeros(2 * nb)
         en[vi] = self.e[sd.sid][0]
@@ -605,7 +614,7 @@ class MiniOracle2D:
             f = self.merged()
             for sd in self.subs:
                 mesh = self._mesh(sd.region)
-                pn, _, _, cls = _classify_p1(sd, mesh)
+                pn, _, _, cls = _classify_p1(sd, mesh, self.ex3)
                 if sd.region == POROUS:
                     self.e[sd.sid] = [np.where(cls == 2, 0.0, (f[k] - pro["P1"][i])[pn])
                                       for i, k in enumerate(("pF", "pf", "pm"))]
@@ -633,7 +642,7 @@ class MiniOracle2D:
                 if sd.region != region:
                     continue
                 dx0, dx1, dy0, dy1 = sd.d
-                pn, I, J, _ = _classify_p1(sd, mesh)
+                pn, I, J, _ = _classify_p1(sd, mesh, self.ex3)
                 inD = (I >= dx0) & (I <= dx1) & (J >= dy0) & (J <= dy1)
                 w = vx[I] * vy[J]
                 if region == POROUS:
